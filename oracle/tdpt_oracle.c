@@ -1,0 +1,396 @@
+/*
+ * CPU oracle for two-dimensional parallel tempering (2D-PT).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, sequential, slow
+ * reference that the GPU library is checked against.  Nothing in the library
+ * links, includes or calls it; only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark load it.  It shares no code with the GPU
+ * path: its random generator, colour ranks, energies, swap rules and
+ * schedule are all written out here from the paper and from the published
+ * definition of the generator.
+ *
+ * What it computes (paper references are by section / equation / algorithm):
+ *   - energy of a replica in penalty column j: E_j = f + P_j g   (Eq. 1)
+ *     with f = -sum_{i<j} J_ij s_i s_j - sum_i b_i s_i and
+ *     g = sum over copy edges of (s_a - s_b)^2  (section on graph
+ *     sparsification with copy constraints; 4 per violated edge in +-1 form)
+ *   - Monte Carlo sweeps: heat-bath single-spin updates visiting colour
+ *     classes in ascending order, P(s_i = +1) = sigma(2 beta h_i) with
+ *     h_i = sum_j J_ij s_j + b_i + 2 P sum_{copies k of i} s_k
+ *     (Algorithm 1 only says "perform sweeps"; heat-bath is the reading
+ *     adopted, the copy term being the ferromagnetic coupling 2P that
+ *     P (s_a - s_b)^2 amounts to)
+ *   - P-swaps along a row: accept with min(1, exp(beta dP dg))    (Eq. 2)
+ *   - beta-swaps along a column: accept with min(1, exp(dbeta dE)) (Eq. 3)
+ *     (both are the axis cases of the two-replica rule of Appendix A)
+ *   - the round structure of Algorithm 1: every replica sweeps, E and g are
+ *     taken from the final state, then one swap direction with alternating
+ *     even/odd pairs, the direction flipping after every even round; the
+ *     bottom-right replica (largest beta, largest P) is recorded.
+ *
+ * Fixed-point: couplings, fields and penalties are Q12 integers, so h, f,
+ * g, dE and dP*dg are exact integers.  The two decisions that need real
+ * arithmetic are written as one canonical double-precision expression each.
+ *
+ * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel
+ * random numbers: as easy as 1, 2, 3", SC'11), key = (seed low, seed high):
+ *   Gibbs update of spin v at sweep t in grid position p:
+ *       counter (rho(v) >> 2, t, p, 0), output word rho(v) & 3
+ *   swap of pair (k, k+1) on line `line` in round n, direction d (0 = P, 1 = beta):
+ *       counter (k, n, line, 1 + d), u = ((x0 >> 5) 2^26 + (x1 >> 6)) 2^-53
+ *   initial spin v at position p when no initial state is given:
+ *       counter (v >> 2, 0, p, 3), output word v & 3, +1 iff its top bit is set
+ * rho(v) is v's rank after sorting spins by (colour, index), every colour's
+ * first rank being rounded up to a multiple of 4.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_OK 0
+#define ORACLE_EINVAL 1
+#define ORACLE_ENOMEM 2
+
+#define ORACLE_NO_PSWAP 1u
+
+/* ---------------------------------------------------------------- Philox */
+
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+        uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+        uint32_t y0 = hi1 ^ x1 ^ k0;
+        uint32_t y1 = lo1;
+        uint32_t y2 = hi0 ^ x3 ^ k1;
+        uint32_t y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+static uint32_t philox_word(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
+                            uint32_t c3, int which)
+{
+    uint32_t ctr[4] = {c0, c1, c2, c3};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    oracle_philox4x32_10(ctr, key, out);
+    return out[which];
+}
+
+static double philox_u53(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3)
+{
+    uint32_t ctr[4] = {c0, c1, c2, c3};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    oracle_philox4x32_10(ctr, key, out);
+    double hi = (double)(out[0] >> 5);
+    double lo = (double)(out[1] >> 6);
+    return (hi * 67108864.0 + lo) * (1.0 / 9007199254740992.0);
+}
+
+/* ---------------------------------------------------------- colour ranks */
+
+/* rank[v] for every spin; returns the padded total through n_pad. */
+int oracle_color_rank(int32_t n, const int32_t *color, int32_t *rank, int32_t *n_pad)
+{
+    int32_t n_colors = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        if (color[v] < 0) return ORACLE_EINVAL;
+        if (color[v] + 1 > n_colors) n_colors = color[v] + 1;
+    }
+    int64_t base = 0;
+    for (int32_t c = 0; c < n_colors; ++c) {
+        int64_t next = base;
+        for (int32_t v = 0; v < n; ++v) {
+            if (color[v] == c) rank[v] = (int32_t)next++;
+        }
+        int64_t size = next - base;
+        base += (size + 3) / 4 * 4;
+    }
+    *n_pad = (int32_t)base;
+    return ORACLE_OK;
+}
+
+/* ---------------------------------------------------------------- energy */
+
+typedef struct {
+    int32_t n;
+    const int32_t *row_ptr, *col, *J_q, *b_q;
+    int32_t m;
+    const int32_t *copy_a, *copy_b;
+    const int32_t *color;
+} oracle_instance;
+
+/* f = -sum_{i<j} J_ij s_i s_j - sum_i b_i s_i ; g = sum_copy (s_a - s_b)^2 */
+void oracle_energy(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                   const int32_t *J_q, const int32_t *b_q, int32_t m,
+                   const int32_t *copy_a, const int32_t *copy_b,
+                   const int8_t *s, int64_t *f_out, int64_t *g_out)
+{
+    int64_t f = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            int32_t j = col[e];
+            if (j > i) f -= (int64_t)J_q[e] * s[i] * s[j];
+        }
+        if (b_q) f -= (int64_t)b_q[i] * s[i];
+    }
+    int64_t g = 0;
+    for (int32_t e = 0; e < m; ++e) {
+        int64_t d = (int64_t)s[copy_a[e]] - s[copy_b[e]];
+        g += d * d;
+    }
+    *f_out = f;
+    *g_out = g;
+}
+
+/* ------------------------------------------------------------ swap rules */
+
+/* Eq. 2: exponent of a P-swap between penalty columns a (left) and b (right)
+ * of the same row: beta (P_b - P_a) (g_b - g_a), penalties in Q12. */
+double oracle_pswap_exponent(double beta, int32_t pq_a, int32_t pq_b, int64_t g_a, int64_t g_b)
+{
+    int64_t dpg = ((int64_t)pq_b - pq_a) * (g_b - g_a);
+    return ldexp(beta * (double)dpg, -12);
+}
+
+/* Eq. 3: exponent of a beta-swap between rows a (upper) and b (lower) of the
+ * same column: (beta_b - beta_a) (E_b - E_a), energies in Q12. */
+double oracle_bswap_exponent(double beta_a, double beta_b, int64_t e_a, int64_t e_b)
+{
+    double dbeta = beta_b - beta_a;
+    return ldexp(dbeta * (double)(e_b - e_a), -12);
+}
+
+/* Metropolis test "rand <= min(1, exp(x))" with rand in [0, 1). */
+int oracle_swap_accept(double x, double u)
+{
+    if (x >= 0.0) return 1;
+    return u <= exp(x);
+}
+
+/* Heat-bath decision for a spin with Q12 local field h at inverse
+ * temperature beta, given a 32-bit uniform: +1 with probability
+ * sigma(2 beta h) = 1 / (1 + exp(-2 beta h)). */
+int oracle_heat_bath(double beta, int64_t h_q, uint32_t u)
+{
+    double x = ldexp(beta * (double)h_q, -11);
+    double p = 1.0 / (1.0 + exp(-x));
+    return ((double)u < ldexp(p, 32)) ? 1 : -1;
+}
+
+/* Swap direction and pair parity of round n (1-based) under Algorithm 1:
+ * the direction starts on P and flips after every even round; the first
+ * left index is 1 on even rounds, 0 on odd ones (0-based). */
+void oracle_schedule(int64_t n, uint32_t flags, int32_t *dir_beta, int32_t *first)
+{
+    int even = (n % 2 == 0);
+    *first = even ? 1 : 0;
+    if (flags & ORACLE_NO_PSWAP) {
+        *dir_beta = 1;
+    } else {
+        *dir_beta = (((n - 1) / 2) % 2 == 1);
+    }
+}
+
+/* -------------------------------------------------------------- the run */
+
+typedef struct {
+    int8_t *states;      /* [R * n], position order, written at the end */
+    int64_t *f, *g;      /* [R], position order */
+    int8_t *best_state;  /* [n] */
+    int64_t best_f, best_sweep, first_hit;
+    int64_t *p_att, *p_acc; /* [I * (J-1)], row-major (row, left index) */
+    int64_t *b_att, *b_acc; /* [J * (I-1)], (column, left index) */
+    int64_t *trace_f, *trace_g; /* [trace_cap] bottom-right f, g per round */
+    int64_t trace_cap;
+} oracle_out;
+
+int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *J_q,
+               const int32_t *b_q, int32_t m, const int32_t *copy_a, const int32_t *copy_b,
+               const int32_t *color,
+               int32_t n_beta, const double *beta, int32_t n_p, const int32_t *p_q,
+               int32_t mcs_per_swap, int64_t n_rounds, uint64_t seed,
+               const int8_t *s0, int32_t has_target, int64_t f_target, uint32_t flags,
+               int8_t *states_out, int64_t *f_out, int64_t *g_out,
+               int8_t *best_state, int64_t *best_f, int64_t *best_sweep, int64_t *first_hit,
+               int64_t *p_att, int64_t *p_acc, int64_t *b_att, int64_t *b_acc,
+               int64_t *trace_f, int64_t *trace_g, int64_t trace_cap)
+{
+    if (n <= 0 || n_beta <= 0 || n_p <= 0 || mcs_per_swap <= 0 || n_rounds < 0)
+        return ORACLE_EINVAL;
+    const int32_t R = n_beta * n_p;
+    int32_t n_colors = 0;
+    for (int32_t v = 0; v < n; ++v)
+        if (color[v] + 1 > n_colors) n_colors = color[v] + 1;
+
+    int32_t *rank = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *order = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *class_start = (int32_t *)calloc((size_t)n_colors + 1, sizeof(int32_t));
+    int32_t *chain_ptr = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+    int32_t *chain_nbr = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * m + 1));
+    int8_t *pool = (int8_t *)malloc((size_t)R * (size_t)n);
+    int8_t **state = (int8_t **)malloc(sizeof(int8_t *) * (size_t)R);
+    int64_t *f = (int64_t *)malloc(sizeof(int64_t) * (size_t)R);
+    int64_t *g = (int64_t *)malloc(sizeof(int64_t) * (size_t)R);
+    if (!rank || !order || !class_start || !chain_ptr || !chain_nbr || !pool || !state || !f || !g) {
+        free(rank); free(order); free(class_start); free(chain_ptr); free(chain_nbr);
+        free(pool); free(state); free(f); free(g);
+        return ORACLE_ENOMEM;
+    }
+    int32_t n_pad;
+    oracle_color_rank(n, color, rank, &n_pad);
+    (void)n_pad;
+
+    /* spins of each colour class in ascending index */
+    {
+        int32_t k = 0;
+        for (int32_t c = 0; c < n_colors; ++c) {
+            class_start[c] = k;
+            for (int32_t v = 0; v < n; ++v)
+                if (color[v] == c) order[k++] = v;
+        }
+        class_start[n_colors] = k;
+    }
+    /* copy-edge neighbours of every spin */
+    for (int32_t e = 0; e < m; ++e) {
+        chain_ptr[copy_a[e] + 1]++;
+        chain_ptr[copy_b[e] + 1]++;
+    }
+    for (int32_t v = 0; v < n; ++v) chain_ptr[v + 1] += chain_ptr[v];
+    {
+        int32_t *fill = (int32_t *)calloc((size_t)n, sizeof(int32_t));
+        for (int32_t e = 0; e < m; ++e) {
+            int32_t a = copy_a[e], b = copy_b[e];
+            chain_nbr[chain_ptr[a] + fill[a]++] = b;
+            chain_nbr[chain_ptr[b] + fill[b]++] = a;
+        }
+        free(fill);
+    }
+
+    /* initial configurations, one per grid position */
+    for (int32_t p = 0; p < R; ++p) {
+        state[p] = pool + (size_t)p * (size_t)n;
+        for (int32_t v = 0; v < n; ++v) {
+            if (s0) {
+                state[p][v] = s0[(size_t)p * (size_t)n + (size_t)v];
+            } else {
+                uint32_t w = philox_word(seed, (uint32_t)v >> 2, 0u, (uint32_t)p, 3u, v & 3);
+                state[p][v] = (w >> 31) ? 1 : -1;
+            }
+        }
+    }
+
+    if (p_att) memset(p_att, 0, sizeof(int64_t) * (size_t)(n_beta * (n_p - 1 > 0 ? n_p - 1 : 0)));
+    if (p_acc) memset(p_acc, 0, sizeof(int64_t) * (size_t)(n_beta * (n_p - 1 > 0 ? n_p - 1 : 0)));
+    if (b_att) memset(b_att, 0, sizeof(int64_t) * (size_t)(n_p * (n_beta - 1 > 0 ? n_beta - 1 : 0)));
+    if (b_acc) memset(b_acc, 0, sizeof(int64_t) * (size_t)(n_p * (n_beta - 1 > 0 ? n_beta - 1 : 0)));
+    int64_t bf = INT64_MAX, bsweep = -1, fhit = -1;
+    const int32_t br = R - 1;
+
+    for (int32_t p = 0; p < R; ++p)
+        oracle_energy(n, row_ptr, col, J_q, b_q, m, copy_a, copy_b, state[p], &f[p], &g[p]);
+
+    for (int64_t rnd = 1; rnd <= n_rounds; ++rnd) {
+        /* every replica performs mcs_per_swap sweeps */
+        for (int32_t p = 0; p < R; ++p) {
+            const int32_t i = p / n_p, j = p % n_p;
+            int8_t *s = state[p];
+            for (int32_t k = 0; k < mcs_per_swap; ++k) {
+                const uint32_t t = (uint32_t)((rnd - 1) * mcs_per_swap + k);
+                for (int32_t c = 0; c < n_colors; ++c) {
+                    for (int32_t q = class_start[c]; q < class_start[c + 1]; ++q) {
+                        const int32_t v = order[q];
+                        int64_t h = b_q ? b_q[v] : 0;
+                        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e)
+                            h += (int64_t)J_q[e] * s[col[e]];
+                        int64_t cs = 0;
+                        for (int32_t e = chain_ptr[v]; e < chain_ptr[v + 1]; ++e)
+                            cs += s[chain_nbr[e]];
+                        h += 2 * (int64_t)p_q[j] * cs;
+                        uint32_t u = philox_word(seed, (uint32_t)rank[v] >> 2, t, (uint32_t)p,
+                                                 0u, rank[v] & 3);
+                        s[v] = (int8_t)oracle_heat_bath(beta[i], h, u);
+                    }
+                }
+            }
+            /* "for final sweep: compute energy E and constraint g" */
+            oracle_energy(n, row_ptr, col, J_q, b_q, m, copy_a, copy_b, s, &f[p], &g[p]);
+        }
+
+        int32_t dir_beta, first;
+        oracle_schedule(rnd, flags, &dir_beta, &first);
+        if (!dir_beta) {
+            for (int32_t i = 0; i < n_beta; ++i) {
+                for (int32_t k = first; k + 1 < n_p; k += 2) {
+                    const int32_t a = i * n_p + k, b = a + 1;
+                    double x = oracle_pswap_exponent(beta[i], p_q[k], p_q[k + 1], g[a], g[b]);
+                    double u = philox_u53(seed, (uint32_t)k, (uint32_t)rnd, (uint32_t)i, 1u);
+                    int acc = oracle_swap_accept(x, u);
+                    if (p_att) p_att[i * (n_p - 1) + k]++;
+                    if (acc) {
+                        if (p_acc) p_acc[i * (n_p - 1) + k]++;
+                        int8_t *ts = state[a]; state[a] = state[b]; state[b] = ts;
+                        int64_t tf = f[a]; f[a] = f[b]; f[b] = tf;
+                        int64_t tg = g[a]; g[a] = g[b]; g[b] = tg;
+                    }
+                }
+            }
+        } else {
+            for (int32_t j = 0; j < n_p; ++j) {
+                for (int32_t k = first; k + 1 < n_beta; k += 2) {
+                    const int32_t a = k * n_p + j, b = a + n_p;
+                    int64_t ea = f[a] + (int64_t)p_q[j] * g[a];
+                    int64_t eb = f[b] + (int64_t)p_q[j] * g[b];
+                    double x = oracle_bswap_exponent(beta[k], beta[k + 1], ea, eb);
+                    double u = philox_u53(seed, (uint32_t)k, (uint32_t)rnd, (uint32_t)j, 2u);
+                    int acc = oracle_swap_accept(x, u);
+                    if (b_att) b_att[j * (n_beta - 1) + k]++;
+                    if (acc) {
+                        if (b_acc) b_acc[j * (n_beta - 1) + k]++;
+                        int8_t *ts = state[a]; state[a] = state[b]; state[b] = ts;
+                        int64_t tf = f[a]; f[a] = f[b]; f[b] = tf;
+                        int64_t tg = g[a]; g[a] = g[b]; g[b] = tg;
+                    }
+                }
+            }
+        }
+
+        /* "store spins from the last replica": the bottom-right position */
+        const int64_t sweeps_done = rnd * mcs_per_swap;
+        if (trace_f && rnd - 1 < trace_cap) trace_f[rnd - 1] = f[br];
+        if (trace_g && rnd - 1 < trace_cap) trace_g[rnd - 1] = g[br];
+        if (g[br] == 0) {
+            if (has_target && fhit < 0 && f[br] <= f_target) fhit = sweeps_done;
+            if (f[br] < bf) {
+                bf = f[br];
+                bsweep = sweeps_done;
+                if (best_state) memcpy(best_state, state[br], (size_t)n);
+            }
+        }
+    }
+
+    if (states_out)
+        for (int32_t p = 0; p < R; ++p)
+            memcpy(states_out + (size_t)p * (size_t)n, state[p], (size_t)n);
+    if (f_out) memcpy(f_out, f, sizeof(int64_t) * (size_t)R);
+    if (g_out) memcpy(g_out, g, sizeof(int64_t) * (size_t)R);
+    if (best_f) *best_f = bf;
+    if (best_sweep) *best_sweep = bsweep;
+    if (first_hit) *first_hit = fhit;
+
+    free(rank); free(order); free(class_start); free(chain_ptr); free(chain_nbr);
+    free(pool); free(state); free(f); free(g);
+    return ORACLE_OK;
+}

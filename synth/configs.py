@@ -1,0 +1,111 @@
+"""Named synthetic workloads (sizes and schedules) and their seeded builders.
+
+Each workload is a planted Wishart problem family sparsified with copy chains
+under a degree cap, run on an I x J replica grid with geometric inverse
+temperatures and linear penalties.  The sweep-per-swap ratio is 50 (the
+ratio the paper uses for its Wishart study) unless the workload says
+otherwise.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+from .instances import (Instance, build_instance, geometric_betas,
+                        linear_penalties_q)
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    instance: Instance
+    beta: np.ndarray           # float64[I], ascending
+    p_q: np.ndarray            # int32[J], non-decreasing, Q12
+    mcs_per_swap: int
+    sweeps: int
+    seed: int
+
+    @property
+    def n_beta(self) -> int:
+        return int(self.beta.shape[0])
+
+    @property
+    def n_p(self) -> int:
+        return int(self.p_q.shape[0])
+
+    @property
+    def replicas(self) -> int:
+        return self.n_beta * self.n_p
+
+    @property
+    def rounds(self) -> int:
+        return self.sweeps // self.mcs_per_swap
+
+    @property
+    def updates_per_sweep(self) -> int:
+        return self.replicas * self.instance.n
+
+
+_CACHE: dict = {}
+
+
+def _inst(N, alpha, seed, D):
+    key = (N, alpha, seed, D)
+    if key not in _CACHE:
+        _CACHE[key] = build_instance(N, alpha, seed, degree_cap=D)
+    return _CACHE[key]
+
+
+def wishart_small(seed: int = 0) -> Workload:
+    """N=12, alpha=0.5, degree cap 4, 8x4 grid (beta 0.1..5, P 0..4), 1e4 sweeps."""
+    return Workload("wishart-N12-D4-8x4", _inst(12, 0.5, 0, 4),
+                    geometric_betas(0.1, 5.0, 8), linear_penalties_q(0, 4, 4),
+                    50, 10_000, seed)
+
+
+def wishart_n200(seed: int = 0) -> Workload:
+    """N=200, alpha=0.8, degree cap 8, 32x16 grid (beta 0.05..10, P 0..8), swap every sweep, 1e5 sweeps."""
+    return Workload("wishart-N200-D8-32x16", _inst(200, 0.8, 0, 8),
+                    geometric_betas(0.05, 10.0, 32), linear_penalties_q(0, 8, 16),
+                    1, 100_000, seed)
+
+
+def batched_sizes(count: int = 64, seed0: int = 0):
+    """(N, alpha) of the batched family: N ~ U{50..400}, alpha ~ U{0.5, 0.8}."""
+    out = []
+    for k in range(count):
+        rng = np.random.default_rng(10_000 + seed0 + k)
+        N = int(rng.integers(50, 401))
+        alpha = float(rng.choice([0.5, 0.8]))
+        out.append((N, alpha, seed0 + k))
+    return out
+
+
+def batched_member(N: int, alpha: float, seed: int) -> Workload:
+    """One member of the batched family: degree cap 6, 16x8 grid (beta 0.1..8, P 0..6), 5e4 sweeps."""
+    return Workload(f"wishart-N{N}-D6-16x8-s{seed}", _inst(N, alpha, seed, 6),
+                    geometric_betas(0.1, 8.0, 16), linear_penalties_q(0, 6, 8),
+                    50, 50_000, seed)
+
+
+def wishart_n1000(seed: int = 0) -> Workload:
+    """N=1000, alpha=0.6, degree cap 6, 64x32 grid (beta 0.02..12, P 0..10), 2e5-sweep cap."""
+    return Workload("wishart-N1000-D6-64x32", _inst(1000, 0.6, 0, 6),
+                    geometric_betas(0.02, 12.0, 64), linear_penalties_q(0, 10, 32),
+                    50, 200_000, seed)
+
+
+def serving_grid(N: int):
+    """Replica grid scaled with N: I = 8*2^round(0.75*(log2 N - 6)) in [8, 64], J = I/2."""
+    I = 8 * 2 ** int(round(0.75 * (math.log2(N) - 6)))
+    I = max(8, min(64, I))
+    return I, I // 2
+
+
+def serving_member(N: int, alpha: float, seed: int, sweeps: int) -> Workload:
+    I, J = serving_grid(N)
+    return Workload(f"serve-N{N}-D6-{I}x{J}-s{seed}", _inst(N, alpha, seed, 6),
+                    geometric_betas(0.1, 8.0, I), linear_penalties_q(0, 6, J),
+                    50, sweeps, seed)
