@@ -1,0 +1,197 @@
+/*
+ * tdpt.h -- C ABI of the MI355X (gfx950) two-dimensional parallel tempering
+ * library.
+ *
+ * The method (Delacour, Sajeeb, Hespanha, Camsari, "Two-dimensional
+ * Parallel Tempering for Constrained Optimization"):
+ *   - an I x J grid of replicas; row i has inverse temperature beta_i, column
+ *     j penalty strength P_j; the energy of a replica in column j is
+ *     E_j = f + P_j g  (Eq. 1), g >= 0 the constraint function;
+ *   - every replica performs Monte Carlo sweeps, then E and g are taken
+ *     from the final state and one swap direction is tried (Algorithm 1):
+ *     P-swaps between neighbouring columns of a row accept with
+ *     min(1, exp(beta dP dg)) (Eq. 2), beta-swaps between neighbouring rows
+ *     of a column with min(1, exp(dbeta dE)) (Eq. 3); pairs alternate
+ *     between odd and even left indices and the direction flips after every
+ *     even round; the bottom-right replica (largest beta and P) carries the
+ *     answer.
+ *   - the constraint handled here is the copy constraint of graph
+ *     sparsification: g = sum over copy edges (S_a - S_b)^2 (section on
+ *     graph sparsification with copy constraints).
+ *
+ * Conventions fixed by this library (the paper leaves them open):
+ *   - Q12 fixed point: couplings J_q, fields b_q and penalties P_q are int32
+ *     holding value * 2^12; f_q, E_q are int64 in the same scale, g is the
+ *     integer sum of (s_a - s_b)^2 (4 per violated copy edge).
+ *     f_q = -sum_{i<j} J_q[ij] s_i s_j - sum_i b_q[i] s_i.
+ *   - Sweep: heat-bath updates colour class by colour class (ascending),
+ *     P(s_i = +1) = 1 / (1 + exp(-2 beta h_i)) with
+ *     h_i = sum_j J_ij s_j + b_i + 2 P sum_{copy neighbours k} s_k.
+ *   - Random numbers: Philox4x32-10 keyed by the 64-bit seed; the counter of
+ *     every draw is a function of (spin, sweep, grid position) or (pair,
+ *     round, line, direction) only, so results do not depend on launch
+ *     shape, batching or checkpoints.  Decisions are the double-precision
+ *     expressions 2^32 u-threshold (heat bath) and u53 <= exp(x) (swaps).
+ *   - Grid positions are row-major: p = i * J + j.  Outputs are reported per
+ *     position; spins use the caller's original numbering.
+ *
+ * Errors: every int-returning call returns TDPT_OK or one of TDPT_E_*; the
+ * message of the last failure on the calling thread is tdpt_last_error().
+ * No call aborts or throws across the ABI.
+ *
+ * Threads and streams: an instance is immutable after creation and may be
+ * shared.  A problem is bound to the stream given at creation; run calls
+ * enqueue work on it and return without waiting; read/query calls wait for
+ * that stream.  A problem must not be used from two threads at once.
+ */
+#ifndef TDPT_H
+#define TDPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TDPT_OK 0
+#define TDPT_E_INVALID 1 /* malformed instance, schedule or argument */
+#define TDPT_E_RANGE 2   /* fixed-point bounds exceeded (see tdpt_problem_create) */
+#define TDPT_E_NOMEM 3   /* workspace too small / host allocation failed */
+#define TDPT_E_DEVICE 4  /* HIP runtime error (code in the message) */
+#define TDPT_E_STATE 5   /* call out of order (e.g. a problem inside a batch) */
+
+/* Flags of tdpt_run_cfg.flags */
+#define TDPT_NO_PSWAP 1u /* J-column PT: no P-swaps; every round tries beta-swaps,
+                            pair parity alternating every round */
+
+typedef struct tdpt_instance tdpt_instance;
+typedef struct tdpt_problem tdpt_problem;
+typedef struct tdpt_batch tdpt_batch;
+
+/* Run configuration (Algorithm 1 inputs). */
+typedef struct tdpt_run_cfg {
+    int32_t n_beta;          /* I >= 1 */
+    const double *beta;      /* [I], strictly ascending, > 0, finite */
+    int32_t n_p;             /* J >= 1 */
+    const int32_t *p_q;      /* [J], Q12, non-decreasing, >= 0 */
+    int32_t mcs_per_swap;    /* sweeps per swap round, >= 1 */
+    uint64_t seed;           /* Philox key */
+    const int8_t *s0;        /* nullable; [I*J*n] +-1, position-major, original spin
+                                order; NULL draws every spin uniformly from the seed */
+    int32_t has_target;      /* nonzero: record the first sweep at which the
+                                bottom-right replica has g == 0 and f_q <= f_target_q */
+    int64_t f_target_q;
+    uint32_t flags;          /* TDPT_NO_PSWAP */
+    int64_t trace_cap;       /* keep (f_q, g) of the bottom-right replica for the
+                                first trace_cap rounds; 0 keeps none */
+} tdpt_run_cfg;
+
+typedef struct tdpt_instance_info {
+    int32_t n;          /* physical spins */
+    int32_t n_pad;      /* colour-major padded length (classes rounded up to 4) */
+    int32_t n_colors;
+    int32_t max_degree; /* problem neighbours per spin (ELL width) */
+    int32_t max_copy_degree;
+    int32_t narrow;     /* 1 if indices and couplings fit 16 bits (packed layout) */
+    int64_t nnz;        /* directed problem couplings */
+    int32_t m;          /* copy edges */
+} tdpt_instance_info;
+
+typedef struct tdpt_status {
+    int64_t rounds_done;     /* swap rounds completed */
+    int64_t sweeps_done;     /* rounds_done * mcs_per_swap */
+    int64_t first_hit_sweep; /* -1 if the target was not reached (or no target) */
+    int64_t best_f_q;        /* best feasible f_q seen at the bottom-right, INT64_MAX if none */
+    int64_t best_sweep;      /* sweep count at which best_f_q was recorded, -1 if none */
+} tdpt_status;
+
+/* ---------------------------------------------------------------- instance */
+
+/* Validate an Ising instance with copy constraints and lay it out for the
+ * device (host memory only; nothing is allocated on the GPU).
+ *   n           physical spins (> 0)
+ *   row_ptr     [n+1] CSR offsets of the problem couplings, row_ptr[0] == 0
+ *   col, J_q    [row_ptr[n]] neighbour index and Q12 coupling; the matrix must
+ *               be symmetric (both directions present with equal values), with
+ *               no self loops and no repeated neighbour in a row
+ *   b_q         [n] Q12 fields, or NULL for zero
+ *   m, copy_a, copy_b   copy-constraint edges (a != b, no repeats, not also a
+ *               problem coupling); the constraint is g = sum (s_a - s_b)^2
+ *   color       [n] colour class of every spin (>= 0); must be proper over
+ *               problem and copy edges (a spin shares no class with any neighbour)
+ * All arrays are read during the call only.  On success *out owns a host
+ * object released by tdpt_instance_destroy.  Returns TDPT_E_INVALID with a
+ * message naming the first violation. */
+int tdpt_instance_create(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                         const int32_t *J_q, const int32_t *b_q, int32_t m,
+                         const int32_t *copy_a, const int32_t *copy_b,
+                         const int32_t *color, tdpt_instance **out);
+int tdpt_instance_info_get(const tdpt_instance *inst, tdpt_instance_info *out);
+void tdpt_instance_destroy(tdpt_instance *inst);
+
+/* ---------------------------------------------------------------- problem */
+
+/* Device bytes a problem needs (structure, all replica states, energies,
+ * counters, tracking and trace).  The caller allocates them (e.g. a torch
+ * uint8 tensor) and passes the pointer to tdpt_problem_create. */
+int tdpt_workspace_bytes(const tdpt_instance *inst, const tdpt_run_cfg *cfg, size_t *bytes);
+
+/* Create a problem in a caller-owned device workspace (>= tdpt_workspace_bytes,
+ * 256-byte aligned, on the current HIP device) and enqueue its
+ * initialisation on `stream` (a hipStream_t; NULL is the default stream).
+ * The instance may be destroyed afterwards.  The workspace must stay
+ * allocated until tdpt_problem_destroy.  Returns TDPT_E_RANGE if a local
+ * field could reach 2^31 in magnitude (sum |J_q| + |b_q| + 2 P_q * copy
+ * degree) or an energy difference 2^52. */
+int tdpt_problem_create(const tdpt_instance *inst, const tdpt_run_cfg *cfg, void *dev_ws,
+                        size_t ws_bytes, void *stream, tdpt_problem **out);
+
+/* Enqueue n_rounds swap rounds (each: mcs_per_swap sweeps of every replica,
+ * f/g of the final states, one swap step, bottom-right tracking).  Resumable:
+ * calling it twice with a and b rounds equals one call with a + b. */
+int tdpt_problem_run(tdpt_problem *prob, int64_t n_rounds);
+
+/* Wait for the problem's stream, then report counters and tracking. */
+int tdpt_problem_query(tdpt_problem *prob, tdpt_status *out);
+
+/* f_q[R], g[R] per grid position (R = I*J). */
+int tdpt_problem_read_energies(tdpt_problem *prob, int64_t *f_q, int64_t *g);
+/* s[R*n] per position, original spin order. */
+int tdpt_problem_read_states(tdpt_problem *prob, int8_t *s);
+/* pos_to_slot[R]: which internal replica slot sits at each position. */
+int tdpt_problem_read_perm(tdpt_problem *prob, int32_t *pos_to_slot);
+/* Best feasible bottom-right state (original order), its f_q and sweep. */
+int tdpt_problem_read_best(tdpt_problem *prob, int8_t *s, int64_t *f_q, int64_t *sweep);
+/* Swap attempts/accepts: P pairs [I*(J-1)] indexed (row, left column), beta
+ * pairs [J*(I-1)] indexed (column, upper row).  Any pointer may be NULL. */
+int tdpt_problem_read_counters(tdpt_problem *prob, int64_t *p_att, int64_t *p_acc,
+                               int64_t *b_att, int64_t *b_acc);
+/* Bottom-right (f_q, g) of rounds 1..min(rounds_done, trace_cap). */
+int tdpt_problem_read_trace(tdpt_problem *prob, int64_t *f_q, int64_t *g, int64_t *count);
+
+/* Checkpoint: copy the whole mutable device state to host memory.  With
+ * host == NULL only *bytes is set.  tdpt_problem_load restores it into a
+ * problem created from the same instance and configuration; a run resumed
+ * from it is bit-identical to an uninterrupted one. */
+int tdpt_problem_save(tdpt_problem *prob, void *host, size_t *bytes);
+int tdpt_problem_load(tdpt_problem *prob, const void *host, size_t bytes);
+
+void tdpt_problem_destroy(tdpt_problem *prob);
+
+/* Measurement hook: from now on record a pair of HIP events on the problem's
+ * stream around every `every`-th sweep-kernel launch (at most 4096 pairs;
+ * 0 switches it off and clears what was recorded). */
+int tdpt_problem_set_timing(tdpt_problem *prob, int32_t every);
+/* Wait for the stream and report the mean duration (ms) of the timed
+ * sweep-kernel launches and how many were timed. */
+int tdpt_problem_read_timing(tdpt_problem *prob, double *avg_ms, int64_t *launches);
+
+/* Thread-local message of the last failed call ("" if none). */
+const char *tdpt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDPT_H */

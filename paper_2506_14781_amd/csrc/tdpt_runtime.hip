@@ -1,0 +1,716 @@
+// Host runtime of the 2D parallel tempering library: instance validation
+// and colour-major re-layout, workspace layout, problem lifecycle, readback
+// and checkpoints.  All sampling work runs in the kernels of
+// tdpt_kernels.hip; this file only moves data and launches.
+#include "tdpt.h"
+#include "tdpt_internal.h"
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    char buf[256];
+    snprintf(buf, sizeof(buf), "%s: HIP error %d (%s)", what, (int)e, hipGetErrorString(e));
+    g_err = buf;
+    return TDPT_E_DEVICE;
+}
+
+#define HIP_TRY(expr, what)                         \
+    do {                                            \
+        hipError_t e_ = (expr);                     \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+constexpr size_t kMaxTimedLaunches = 4096;
+
+// ELL widths the sweep kernels are instantiated for.
+int ell_width(int deg)
+{
+    if (deg <= 8) return std::max(deg, 1);
+    if (deg <= 12) return 12;
+    if (deg <= 16) return 16;
+    return -1;
+}
+
+}  // namespace
+
+struct tdpt_instance {
+    int32_t n = 0, n_pad = 0, n_colors = 0, wd = 0, wc = 2, narrow = 0, m = 0;
+    int32_t max_deg = 0, max_copy_deg = 0;
+    int64_t nnz = 0;
+    std::vector<int32_t> rank;       // original -> colour-major
+    std::vector<int32_t> orig;       // colour-major -> original (-1 padding)
+    std::vector<int32_t> cls_start;  // [C+1]
+    std::vector<int32_t> cls_live;   // [C]
+    std::vector<int32_t> nb_idx, nb_J;  // [wd][n_pad]
+    std::vector<int32_t> ch_idx;        // [2][n_pad]
+    std::vector<int32_t> bias;          // [n_pad]
+    int64_t max_field = 0;   // max_i sum_j |J_ij| + |b_i|
+    int64_t abs_f_bound = 0; // sum_{i<j} |J_ij| + sum_i |b_i|
+    int32_t max_class_quads = 0;
+};
+
+struct tdpt_problem {
+    tdpt::DevProblem dp{};
+    hipStream_t stream = nullptr;
+    int rb = 1;
+    int32_t n = 0, I = 0, J = 0, R = 0, mcs = 1;
+    std::vector<int32_t> rank;
+    uint8_t *ws = nullptr;
+    size_t ws_bytes = 0, mut_off = 0, mut_bytes = 0;
+    int64_t trace_cap = 0;
+    uint64_t fingerprint = 0;
+    // optional sweep-kernel timing (HIP events on the problem's stream)
+    int32_t time_every = 0;
+    int64_t sweep_launches = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    ~tdpt_problem()
+    {
+        for (auto &e : events) {
+            hipEventDestroy(e.first);
+            hipEventDestroy(e.second);
+        }
+    }
+};
+
+namespace {
+
+struct Layout {
+    size_t hdr, states, f, g, slot_pos, pos_slot, p_att, p_acc, b_att, b_acc, best, trace_f,
+        trace_g, mut_end;
+    size_t beta, p_q, nbp, nb_idx, nb_J, chp, ch_idx, bias, orig, total;
+    int32_t stride;
+};
+
+Layout make_layout(const tdpt_instance *in, int32_t I, int32_t J, int64_t trace_cap)
+{
+    Layout L{};
+    const size_t R = (size_t)I * J;
+    L.stride = (int32_t)align_up((size_t)in->n_pad + 1, 16);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes, 256);
+        return at;
+    };
+    L.hdr = take(sizeof(int64_t) * tdpt::kHdrWords);
+    L.states = take(R * (size_t)L.stride);
+    L.f = take(R * 8);
+    L.g = take(R * 8);
+    L.slot_pos = take(R * 4);
+    L.pos_slot = take(R * 4);
+    const size_t np = (size_t)I * (J > 1 ? J - 1 : 0), nb = (size_t)J * (I > 1 ? I - 1 : 0);
+    L.p_att = take(np * 8 + 8);
+    L.p_acc = take(np * 8 + 8);
+    L.b_att = take(nb * 8 + 8);
+    L.b_acc = take(nb * 8 + 8);
+    L.best = take((size_t)L.stride);
+    L.trace_f = take((size_t)trace_cap * 8 + 8);
+    L.trace_g = take((size_t)trace_cap * 8 + 8);
+    L.mut_end = o;
+    L.beta = take((size_t)I * 8);
+    L.p_q = take((size_t)J * 4);
+    const size_t ell = (size_t)in->wd * in->n_pad * 4;
+    if (in->narrow) {
+        L.nbp = take(ell);
+        L.chp = take((size_t)in->n_pad * 4);
+        L.nb_idx = L.nb_J = L.ch_idx = 0;
+    } else {
+        L.nb_idx = take(ell);
+        L.nb_J = take(ell);
+        L.ch_idx = take((size_t)2 * in->n_pad * 4);
+        L.nbp = L.chp = 0;
+    }
+    L.bias = take((size_t)in->n_pad * 4);
+    L.orig = take((size_t)in->n_pad * 4);
+    L.total = o;
+    return L;
+}
+
+int check_cfg(const tdpt_run_cfg *c)
+{
+    if (!c) return fail(TDPT_E_INVALID, "cfg is NULL");
+    if (c->n_beta < 1 || !c->beta) return fail(TDPT_E_INVALID, "need n_beta >= 1 and a beta array");
+    if (c->n_p < 1 || !c->p_q) return fail(TDPT_E_INVALID, "need n_p >= 1 and a p_q array");
+    if ((int64_t)c->n_beta * c->n_p > (1 << 22)) return fail(TDPT_E_INVALID, "replica grid too large");
+    for (int i = 0; i < c->n_beta; ++i) {
+        if (!std::isfinite(c->beta[i]) || c->beta[i] <= 0.0)
+            return fail(TDPT_E_INVALID, "beta must be finite and > 0");
+        if (i && !(c->beta[i] > c->beta[i - 1]))
+            return fail(TDPT_E_INVALID, "beta must be strictly ascending");
+    }
+    for (int j = 0; j < c->n_p; ++j) {
+        if (c->p_q[j] < 0) return fail(TDPT_E_INVALID, "p_q must be >= 0");
+        if (j && c->p_q[j] < c->p_q[j - 1]) return fail(TDPT_E_INVALID, "p_q must be non-decreasing");
+    }
+    if (c->mcs_per_swap < 1) return fail(TDPT_E_INVALID, "mcs_per_swap must be >= 1");
+    if (c->trace_cap < 0) return fail(TDPT_E_INVALID, "trace_cap must be >= 0");
+    if (c->flags & ~TDPT_NO_PSWAP) return fail(TDPT_E_INVALID, "unknown flag bits");
+    return TDPT_OK;
+}
+
+int slots_per_block(const tdpt_instance *in, int32_t R, int32_t stride, size_t lds_max)
+{
+    int rb = (R >= 512) ? 2 : 1;
+    if (const char *e = getenv("TDPT_SLOTS_PER_BLOCK")) {
+        int v = atoi(e);
+        if (v == 1 || v == 2 || v == 4) rb = v;
+    }
+    while (rb > 1 && (size_t)rb * stride > lds_max) rb >>= 1;
+    (void)in;
+    return rb;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tdpt_last_error(void) { return g_err.c_str(); }
+
+int tdpt_instance_create(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *J_q,
+                         const int32_t *b_q, int32_t m, const int32_t *copy_a,
+                         const int32_t *copy_b, const int32_t *color, tdpt_instance **out)
+{
+    if (!out) return fail(TDPT_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n <= 0 || !row_ptr || !color) return fail(TDPT_E_INVALID, "need n > 0, row_ptr and color");
+    if (row_ptr[0] != 0) return fail(TDPT_E_INVALID, "row_ptr[0] must be 0");
+    for (int32_t i = 0; i < n; ++i)
+        if (row_ptr[i + 1] < row_ptr[i]) return fail(TDPT_E_INVALID, "row_ptr must be non-decreasing");
+    const int64_t nnz = row_ptr[n];
+    if (nnz > 0 && (!col || !J_q)) return fail(TDPT_E_INVALID, "col and J_q are required");
+    if (m < 0 || (m > 0 && (!copy_a || !copy_b))) return fail(TDPT_E_INVALID, "bad copy-edge arrays");
+
+    // sorted (col, J) per row for symmetry / duplicate checks
+    std::vector<std::pair<int32_t, int32_t>> ent((size_t)nnz);
+    for (int32_t i = 0; i < n; ++i) {
+        for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            const int32_t j = col[e];
+            if (j < 0 || j >= n) return fail(TDPT_E_INVALID, "col index out of range at row " + std::to_string(i));
+            if (j == i) return fail(TDPT_E_INVALID, "self loop at spin " + std::to_string(i));
+            ent[e] = {j, J_q[e]};
+        }
+        std::sort(ent.begin() + row_ptr[i], ent.begin() + row_ptr[i + 1]);
+        for (int32_t e = row_ptr[i] + 1; e < row_ptr[i + 1]; ++e)
+            if (ent[e].first == ent[e - 1].first)
+                return fail(TDPT_E_INVALID, "repeated neighbour in row " + std::to_string(i));
+    }
+    auto find = [&](int32_t i, int32_t j) -> const std::pair<int32_t, int32_t> * {
+        auto b = ent.begin() + row_ptr[i], e = ent.begin() + row_ptr[i + 1];
+        auto it = std::lower_bound(b, e, std::make_pair(j, INT32_MIN));
+        if (it != e && it->first == j) return &*it;
+        return nullptr;
+    };
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            const auto *rev = find(ent[e].first, i);
+            if (!rev || rev->second != ent[e].second)
+                return fail(TDPT_E_INVALID, "couplings are not symmetric at (" + std::to_string(i) + "," +
+                                                std::to_string(ent[e].first) + ")");
+        }
+    // copy edges
+    std::vector<int32_t> cdeg(n, 0);
+    std::vector<std::pair<int32_t, int32_t>> cpairs((size_t)m);
+    for (int32_t e = 0; e < m; ++e) {
+        const int32_t a = copy_a[e], b = copy_b[e];
+        if (a < 0 || a >= n || b < 0 || b >= n || a == b)
+            return fail(TDPT_E_INVALID, "bad copy edge " + std::to_string(e));
+        if (find(a, b)) return fail(TDPT_E_INVALID, "copy edge " + std::to_string(e) + " is also a coupling");
+        cpairs[e] = {std::min(a, b), std::max(a, b)};
+        if (++cdeg[a] > 2 || ++cdeg[b] > 2)
+            return fail(TDPT_E_INVALID, "copy constraints must form chains (at most 2 copy edges per spin)");
+    }
+    std::sort(cpairs.begin(), cpairs.end());
+    for (int32_t e = 1; e < m; ++e)
+        if (cpairs[e] == cpairs[e - 1]) return fail(TDPT_E_INVALID, "repeated copy edge");
+    // colouring
+    int32_t C = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        if (color[v] < 0) return fail(TDPT_E_INVALID, "negative colour");
+        C = std::max(C, color[v] + 1);
+    }
+    if (C > tdpt::kMaxColors) return fail(TDPT_E_INVALID, "more than 32 colour classes");
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+            if (color[i] == color[col[e]])
+                return fail(TDPT_E_INVALID, "colouring is not proper on coupling (" + std::to_string(i) + "," +
+                                                std::to_string(col[e]) + ")");
+    for (int32_t e = 0; e < m; ++e)
+        if (color[copy_a[e]] == color[copy_b[e]])
+            return fail(TDPT_E_INVALID, "colouring is not proper on copy edge " + std::to_string(e));
+
+    auto *in = new (std::nothrow) tdpt_instance();
+    if (!in) return fail(TDPT_E_NOMEM, "host allocation failed");
+    in->n = n;
+    in->nnz = nnz;
+    in->m = m;
+    in->n_colors = C;
+    // colour-major numbering, classes padded to multiples of 4
+    std::vector<int32_t> size(C, 0);
+    for (int32_t v = 0; v < n; ++v) size[color[v]]++;
+    in->cls_start.assign(C + 1, 0);
+    in->cls_live.assign(C, 0);
+    for (int32_t c = 0; c < C; ++c) {
+        in->cls_live[c] = in->cls_start[c] + size[c];
+        in->cls_start[c + 1] = in->cls_start[c] + (size[c] + 3) / 4 * 4;
+        in->max_class_quads = std::max(in->max_class_quads, (size[c] + 3) / 4);
+    }
+    const int32_t n_pad = in->cls_start[C];
+    in->n_pad = n_pad;
+    in->rank.assign(n, 0);
+    in->orig.assign(n_pad, -1);
+    {
+        std::vector<int32_t> next(in->cls_start.begin(), in->cls_start.end() - 1);
+        for (int32_t v = 0; v < n; ++v) {
+            const int32_t r = next[color[v]]++;
+            in->rank[v] = r;
+            in->orig[r] = v;
+        }
+    }
+    int32_t maxdeg = 0;
+    for (int32_t i = 0; i < n; ++i) maxdeg = std::max(maxdeg, row_ptr[i + 1] - row_ptr[i]);
+    in->max_deg = maxdeg;
+    in->wd = ell_width(maxdeg);
+    if (in->wd < 0) {
+        delete in;
+        return fail(TDPT_E_INVALID, "a spin has more than 16 problem neighbours");
+    }
+    in->max_copy_deg = 0;
+    for (int32_t v = 0; v < n; ++v) in->max_copy_deg = std::max(in->max_copy_deg, cdeg[v]);
+    const int32_t wd = in->wd;
+    in->nb_idx.assign((size_t)wd * n_pad, n_pad);
+    in->nb_J.assign((size_t)wd * n_pad, 0);
+    in->ch_idx.assign((size_t)2 * n_pad, n_pad);
+    in->bias.assign(n_pad, 0);
+    bool narrow = (n_pad + 1 <= 65536);
+    int64_t absf = 0;
+    for (int32_t r = 0; r < n_pad; ++r) {
+        const int32_t v = in->orig[r];
+        if (v < 0) continue;
+        int64_t field = b_q ? std::llabs((long long)b_q[v]) : 0;
+        int k = 0;
+        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e, ++k) {
+            in->nb_idx[(size_t)k * n_pad + r] = in->rank[col[e]];
+            in->nb_J[(size_t)k * n_pad + r] = J_q[e];
+            field += std::llabs((long long)J_q[e]);
+            if (J_q[e] < -32768 || J_q[e] > 32767) narrow = false;
+            if (col[e] > v) absf += std::llabs((long long)J_q[e]);
+        }
+        if (b_q) {
+            in->bias[r] = b_q[v];
+            absf += std::llabs((long long)b_q[v]);
+        }
+        in->max_field = std::max(in->max_field, field);
+    }
+    for (int32_t e = 0; e < m; ++e) {
+        const int32_t a = in->rank[copy_a[e]], b = in->rank[copy_b[e]];
+        int32_t *sa = (in->ch_idx[a] == n_pad) ? &in->ch_idx[a] : &in->ch_idx[(size_t)n_pad + a];
+        *sa = b;
+        int32_t *sb = (in->ch_idx[b] == n_pad) ? &in->ch_idx[b] : &in->ch_idx[(size_t)n_pad + b];
+        *sb = a;
+    }
+    in->abs_f_bound = absf;
+    in->narrow = narrow ? 1 : 0;
+    *out = in;
+    return TDPT_OK;
+}
+
+int tdpt_instance_info_get(const tdpt_instance *in, tdpt_instance_info *out)
+{
+    if (!in || !out) return fail(TDPT_E_INVALID, "NULL argument");
+    out->n = in->n;
+    out->n_pad = in->n_pad;
+    out->n_colors = in->n_colors;
+    out->max_degree = in->max_deg;
+    out->max_copy_degree = in->max_copy_deg;
+    out->narrow = in->narrow;
+    out->nnz = in->nnz;
+    out->m = in->m;
+    return TDPT_OK;
+}
+
+void tdpt_instance_destroy(tdpt_instance *in) { delete in; }
+
+int tdpt_workspace_bytes(const tdpt_instance *in, const tdpt_run_cfg *cfg, size_t *bytes)
+{
+    if (!in || !bytes) return fail(TDPT_E_INVALID, "NULL argument");
+    int rc = check_cfg(cfg);
+    if (rc) return rc;
+    *bytes = make_layout(in, cfg->n_beta, cfg->n_p, cfg->trace_cap).total;
+    return TDPT_OK;
+}
+
+int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *dev_ws,
+                        size_t ws_bytes, void *stream, tdpt_problem **out)
+{
+    if (!out) return fail(TDPT_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!in) return fail(TDPT_E_INVALID, "instance is NULL");
+    int rc = check_cfg(cfg);
+    if (rc) return rc;
+    if (!dev_ws) return fail(TDPT_E_INVALID, "workspace is NULL");
+    if (((uintptr_t)dev_ws) % 256) return fail(TDPT_E_INVALID, "workspace must be 256-byte aligned");
+    const int32_t I = cfg->n_beta, J = cfg->n_p, R = I * J;
+    const Layout L = make_layout(in, I, J, cfg->trace_cap);
+    if (ws_bytes < L.total)
+        return fail(TDPT_E_NOMEM, "workspace holds " + std::to_string(ws_bytes) + " bytes, needs " +
+                                      std::to_string(L.total));
+    // fixed-point bounds
+    const int64_t pmax = cfg->p_q[J - 1];
+    if (in->max_field + 4 * pmax >= ((int64_t)1 << 31))
+        return fail(TDPT_E_RANGE, "local field can reach 2^31");
+    const int64_t quads_per_thread = (in->max_class_quads + tdpt::kBlock - 1) / tdpt::kBlock;
+    if (quads_per_thread * 4 * 2 * (in->max_field + 4 * pmax) >= ((int64_t)1 << 31))
+        return fail(TDPT_E_RANGE, "per-phase energy change can reach 2^31");
+    const int64_t ebound = in->abs_f_bound + pmax * 4 * (int64_t)in->m;
+    if (ebound >= ((int64_t)1 << 51)) return fail(TDPT_E_RANGE, "energy differences can reach 2^52");
+
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    int lds_max = 0;
+    HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev),
+            "hipDeviceGetAttribute");
+    const size_t lds_limit = std::max((size_t)lds_max, (size_t)65536) - 1024;
+    if ((size_t)L.stride > lds_limit)
+        return fail(TDPT_E_INVALID, "a replica (" + std::to_string(in->n_pad) +
+                                        " spins) does not fit the LDS of one workgroup");
+
+    auto *p = new (std::nothrow) tdpt_problem();
+    if (!p) return fail(TDPT_E_NOMEM, "host allocation failed");
+    p->stream = (hipStream_t)stream;
+    p->n = in->n;
+    p->I = I;
+    p->J = J;
+    p->R = R;
+    p->mcs = cfg->mcs_per_swap;
+    p->rank = in->rank;
+    p->ws = (uint8_t *)dev_ws;
+    p->ws_bytes = ws_bytes;
+    p->mut_off = 0;
+    p->mut_bytes = L.mut_end;
+    p->trace_cap = cfg->trace_cap;
+    p->rb = slots_per_block(in, R, L.stride, lds_limit);
+    p->fingerprint = ((uint64_t)in->n_pad << 40) ^ ((uint64_t)R << 20) ^ (uint64_t)L.total;
+
+    tdpt::DevProblem &d = p->dp;
+    uint8_t *ws = p->ws;
+    d.n_pad = in->n_pad;
+    d.stride = L.stride;
+    d.n_colors = in->n_colors;
+    d.wd = in->wd;
+    d.wc = 2;
+    d.narrow = in->narrow;
+    for (int c = 0; c <= in->n_colors; ++c) d.cls_start[c] = in->cls_start[c];
+    for (int c = 0; c < in->n_colors; ++c) d.cls_live[c] = in->cls_live[c];
+    d.nbp = in->narrow ? (const uint32_t *)(ws + L.nbp) : nullptr;
+    d.chp = in->narrow ? (const uint32_t *)(ws + L.chp) : nullptr;
+    d.nb_idx = in->narrow ? nullptr : (const int32_t *)(ws + L.nb_idx);
+    d.nb_J = in->narrow ? nullptr : (const int32_t *)(ws + L.nb_J);
+    d.ch_idx = in->narrow ? nullptr : (const int32_t *)(ws + L.ch_idx);
+    d.bias = (const int32_t *)(ws + L.bias);
+    d.orig = (const int32_t *)(ws + L.orig);
+    d.I = I;
+    d.J = J;
+    d.R = R;
+    d.mcs = cfg->mcs_per_swap;
+    d.key0 = (uint32_t)cfg->seed;
+    d.key1 = (uint32_t)(cfg->seed >> 32);
+    d.flags = cfg->flags;
+    d.has_target = cfg->has_target ? 1 : 0;
+    d.f_target = cfg->f_target_q;
+    d.trace_cap = cfg->trace_cap;
+    d.beta = (const double *)(ws + L.beta);
+    d.p_q = (const int32_t *)(ws + L.p_q);
+    d.hdr = (int64_t *)(ws + L.hdr);
+    d.states = (int8_t *)(ws + L.states);
+    d.f = (int64_t *)(ws + L.f);
+    d.g = (int64_t *)(ws + L.g);
+    d.slot_pos = (int32_t *)(ws + L.slot_pos);
+    d.pos_slot = (int32_t *)(ws + L.pos_slot);
+    d.p_att = (int64_t *)(ws + L.p_att);
+    d.p_acc = (int64_t *)(ws + L.p_acc);
+    d.b_att = (int64_t *)(ws + L.b_att);
+    d.b_acc = (int64_t *)(ws + L.b_acc);
+    d.best_state = (int8_t *)(ws + L.best);
+    d.trace_f = (int64_t *)(ws + L.trace_f);
+    d.trace_g = (int64_t *)(ws + L.trace_g);
+
+    hipStream_t s = p->stream;
+    auto cleanup = [&](int code) {
+        delete p;
+        return code;
+    };
+    // immutable structure
+    std::vector<uint32_t> packed;
+    hipError_t e = hipSuccess;
+#define UP(dst, src, bytes)                                                        \
+    do {                                                                           \
+        e = hipMemcpyAsync((dst), (src), (bytes), hipMemcpyHostToDevice, s);       \
+        if (e == hipSuccess) e = hipStreamSynchronize(s);                          \
+        if (e != hipSuccess) return cleanup(hip_fail(e, "upload"));                \
+    } while (0)
+    UP(ws + L.beta, cfg->beta, (size_t)I * 8);
+    UP(ws + L.p_q, cfg->p_q, (size_t)J * 4);
+    if (in->narrow) {
+        packed.resize((size_t)in->wd * in->n_pad);
+        for (size_t k = 0; k < packed.size(); ++k)
+            packed[k] = ((uint32_t)in->nb_idx[k] & 0xffffu) | ((uint32_t)(in->nb_J[k] & 0xffff) << 16);
+        UP(ws + L.nbp, packed.data(), packed.size() * 4);
+        std::vector<uint32_t> ch((size_t)in->n_pad);
+        for (int32_t r = 0; r < in->n_pad; ++r)
+            ch[r] = ((uint32_t)in->ch_idx[r] & 0xffffu) | ((uint32_t)in->ch_idx[(size_t)in->n_pad + r] << 16);
+        UP(ws + L.chp, ch.data(), ch.size() * 4);
+    } else {
+        UP(ws + L.nb_idx, in->nb_idx.data(), in->nb_idx.size() * 4);
+        UP(ws + L.nb_J, in->nb_J.data(), in->nb_J.size() * 4);
+        UP(ws + L.ch_idx, in->ch_idx.data(), in->ch_idx.size() * 4);
+    }
+    UP(ws + L.bias, in->bias.data(), in->bias.size() * 4);
+    UP(ws + L.orig, in->orig.data(), in->orig.size() * 4);
+    // mutable state
+    {
+        std::vector<uint8_t> zero(L.mut_end, 0);
+        int64_t *hdr = (int64_t *)(zero.data() + L.hdr);
+        hdr[tdpt::kHdrRounds] = 0;
+        hdr[tdpt::kHdrFirstHit] = -1;
+        hdr[tdpt::kHdrBestF] = INT64_MAX;
+        hdr[tdpt::kHdrBestSweep] = -1;
+        int32_t *sp = (int32_t *)(zero.data() + L.slot_pos);
+        int32_t *ps = (int32_t *)(zero.data() + L.pos_slot);
+        for (int32_t r = 0; r < R; ++r) sp[r] = ps[r] = r;
+        if (cfg->s0) {
+            for (int32_t r = 0; r < R; ++r) {
+                int8_t *st = (int8_t *)(zero.data() + L.states + (size_t)r * L.stride);
+                const int8_t *src = cfg->s0 + (size_t)r * in->n;
+                for (int32_t v = 0; v < in->n; ++v) {
+                    if (src[v] != 1 && src[v] != -1) return cleanup(fail(TDPT_E_INVALID, "s0 must be +-1"));
+                    st[in->rank[v]] = src[v];
+                }
+            }
+        }
+        UP(ws, zero.data(), zero.size());
+    }
+#undef UP
+    if (!cfg->s0) {
+        e = tdpt::launch_init_states(d, s);
+        if (e != hipSuccess) return cleanup(hip_fail(e, "init states"));
+    }
+    e = tdpt::launch_energy(d, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "initial energies"));
+    *out = p;
+    return TDPT_OK;
+}
+
+int tdpt_problem_run(tdpt_problem *p, int64_t n_rounds)
+{
+    if (!p) return fail(TDPT_E_INVALID, "problem is NULL");
+    if (n_rounds < 0) return fail(TDPT_E_INVALID, "n_rounds must be >= 0");
+    for (int64_t r = 0; r < n_rounds; ++r) {
+        const bool timed = p->time_every > 0 && p->sweep_launches % p->time_every == 0 &&
+                           p->events.size() < kMaxTimedLaunches;
+        std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+        if (timed) {
+            HIP_TRY(hipEventCreate(&ev.first), "hipEventCreate");
+            HIP_TRY(hipEventCreate(&ev.second), "hipEventCreate");
+            p->events.push_back(ev);
+            HIP_TRY(hipEventRecord(ev.first, p->stream), "hipEventRecord");
+        }
+        hipError_t e = tdpt::launch_sweep(p->dp, p->rb, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "launch sweep");
+        if (timed) HIP_TRY(hipEventRecord(ev.second, p->stream), "hipEventRecord");
+        ++p->sweep_launches;
+        e = tdpt::launch_swap(p->dp, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "launch swap");
+    }
+    return TDPT_OK;
+}
+
+int tdpt_problem_set_timing(tdpt_problem *p, int32_t every)
+{
+    if (!p || every < 0) return fail(TDPT_E_INVALID, "bad argument");
+    HIP_TRY(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+    for (auto &e : p->events) {
+        hipEventDestroy(e.first);
+        hipEventDestroy(e.second);
+    }
+    p->events.clear();
+    p->time_every = every;
+    p->sweep_launches = 0;
+    return TDPT_OK;
+}
+
+int tdpt_problem_read_timing(tdpt_problem *p, double *avg_ms, int64_t *launches)
+{
+    if (!p || !avg_ms || !launches) return fail(TDPT_E_INVALID, "NULL argument");
+    HIP_TRY(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+    double total = 0.0;
+    for (auto &e : p->events) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e.first, e.second), "hipEventElapsedTime");
+        total += ms;
+    }
+    *launches = (int64_t)p->events.size();
+    *avg_ms = p->events.empty() ? 0.0 : total / (double)p->events.size();
+    return TDPT_OK;
+}
+
+static int d2h(tdpt_problem *p, void *dst, const void *src, size_t bytes)
+{
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "readback");
+    return TDPT_OK;
+}
+
+int tdpt_problem_query(tdpt_problem *p, tdpt_status *out)
+{
+    if (!p || !out) return fail(TDPT_E_INVALID, "NULL argument");
+    int64_t h[tdpt::kHdrWords];
+    int rc = d2h(p, h, p->dp.hdr, sizeof(h));
+    if (rc) return rc;
+    out->rounds_done = h[tdpt::kHdrRounds];
+    out->sweeps_done = h[tdpt::kHdrRounds] * p->mcs;
+    out->first_hit_sweep = h[tdpt::kHdrFirstHit];
+    out->best_f_q = h[tdpt::kHdrBestF];
+    out->best_sweep = h[tdpt::kHdrBestSweep];
+    return TDPT_OK;
+}
+
+int tdpt_problem_read_perm(tdpt_problem *p, int32_t *pos_to_slot)
+{
+    if (!p || !pos_to_slot) return fail(TDPT_E_INVALID, "NULL argument");
+    return d2h(p, pos_to_slot, p->dp.pos_slot, (size_t)p->R * 4);
+}
+
+int tdpt_problem_read_energies(tdpt_problem *p, int64_t *f_q, int64_t *g)
+{
+    if (!p) return fail(TDPT_E_INVALID, "NULL argument");
+    std::vector<int32_t> ps(p->R);
+    std::vector<int64_t> fs(p->R), gs(p->R);
+    int rc = d2h(p, ps.data(), p->dp.pos_slot, (size_t)p->R * 4);
+    if (!rc) rc = d2h(p, fs.data(), p->dp.f, (size_t)p->R * 8);
+    if (!rc) rc = d2h(p, gs.data(), p->dp.g, (size_t)p->R * 8);
+    if (rc) return rc;
+    for (int32_t q = 0; q < p->R; ++q) {
+        if (f_q) f_q[q] = fs[ps[q]];
+        if (g) g[q] = gs[ps[q]];
+    }
+    return TDPT_OK;
+}
+
+int tdpt_problem_read_states(tdpt_problem *p, int8_t *s)
+{
+    if (!p || !s) return fail(TDPT_E_INVALID, "NULL argument");
+    const size_t stride = (size_t)p->dp.stride;
+    std::vector<int32_t> ps(p->R);
+    std::vector<int8_t> st((size_t)p->R * stride);
+    int rc = d2h(p, ps.data(), p->dp.pos_slot, (size_t)p->R * 4);
+    if (!rc) rc = d2h(p, st.data(), p->dp.states, st.size());
+    if (rc) return rc;
+    for (int32_t q = 0; q < p->R; ++q) {
+        const int8_t *src = st.data() + (size_t)ps[q] * stride;
+        int8_t *dst = s + (size_t)q * p->n;
+        for (int32_t v = 0; v < p->n; ++v) dst[v] = src[p->rank[v]];
+    }
+    return TDPT_OK;
+}
+
+int tdpt_problem_read_best(tdpt_problem *p, int8_t *s, int64_t *f_q, int64_t *sweep)
+{
+    if (!p) return fail(TDPT_E_INVALID, "NULL argument");
+    int64_t h[tdpt::kHdrWords];
+    int rc = d2h(p, h, p->dp.hdr, sizeof(h));
+    if (rc) return rc;
+    if (f_q) *f_q = h[tdpt::kHdrBestF];
+    if (sweep) *sweep = h[tdpt::kHdrBestSweep];
+    if (s) {
+        std::vector<int8_t> st((size_t)p->dp.stride);
+        rc = d2h(p, st.data(), p->dp.best_state, st.size());
+        if (rc) return rc;
+        for (int32_t v = 0; v < p->n; ++v) s[v] = st[p->rank[v]];
+    }
+    return TDPT_OK;
+}
+
+int tdpt_problem_read_counters(tdpt_problem *p, int64_t *p_att, int64_t *p_acc, int64_t *b_att,
+                               int64_t *b_acc)
+{
+    if (!p) return fail(TDPT_E_INVALID, "NULL argument");
+    const size_t np = (size_t)p->I * (p->J - 1), nb = (size_t)p->J * (p->I - 1);
+    int rc = TDPT_OK;
+    if (p_att && np) rc = d2h(p, p_att, p->dp.p_att, np * 8);
+    if (!rc && p_acc && np) rc = d2h(p, p_acc, p->dp.p_acc, np * 8);
+    if (!rc && b_att && nb) rc = d2h(p, b_att, p->dp.b_att, nb * 8);
+    if (!rc && b_acc && nb) rc = d2h(p, b_acc, p->dp.b_acc, nb * 8);
+    return rc;
+}
+
+int tdpt_problem_read_trace(tdpt_problem *p, int64_t *f_q, int64_t *g, int64_t *count)
+{
+    if (!p || !count) return fail(TDPT_E_INVALID, "NULL argument");
+    int64_t h[tdpt::kHdrWords];
+    int rc = d2h(p, h, p->dp.hdr, sizeof(h));
+    if (rc) return rc;
+    const int64_t c = std::min(h[tdpt::kHdrRounds], p->trace_cap);
+    *count = c;
+    if (c > 0 && f_q) rc = d2h(p, f_q, p->dp.trace_f, (size_t)c * 8);
+    if (!rc && c > 0 && g) rc = d2h(p, g, p->dp.trace_g, (size_t)c * 8);
+    return rc;
+}
+
+static const uint64_t kCkptMagic = 0x3154504454324454ull;  // "TD2TDPT1"
+
+int tdpt_problem_save(tdpt_problem *p, void *host, size_t *bytes)
+{
+    if (!p || !bytes) return fail(TDPT_E_INVALID, "NULL argument");
+    const size_t need = 16 + p->mut_bytes;
+    if (!host) {
+        *bytes = need;
+        return TDPT_OK;
+    }
+    if (*bytes < need) return fail(TDPT_E_NOMEM, "checkpoint buffer too small");
+    uint64_t head[2] = {kCkptMagic, p->fingerprint};
+    memcpy(host, head, 16);
+    *bytes = need;
+    return d2h(p, (uint8_t *)host + 16, p->ws + p->mut_off, p->mut_bytes);
+}
+
+int tdpt_problem_load(tdpt_problem *p, const void *host, size_t bytes)
+{
+    if (!p || !host) return fail(TDPT_E_INVALID, "NULL argument");
+    if (bytes != 16 + p->mut_bytes) return fail(TDPT_E_INVALID, "checkpoint size does not match the problem");
+    uint64_t head[2];
+    memcpy(head, host, 16);
+    if (head[0] != kCkptMagic || head[1] != p->fingerprint)
+        return fail(TDPT_E_INVALID, "checkpoint belongs to a different problem shape");
+    hipError_t e = hipMemcpyAsync(p->ws + p->mut_off, (const uint8_t *)host + 16, p->mut_bytes,
+                                  hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "checkpoint load");
+    return TDPT_OK;
+}
+
+void tdpt_problem_destroy(tdpt_problem *p) { delete p; }
+
+}  // extern "C"

@@ -1,0 +1,289 @@
+"""Python binding of libtdpt.so (the C ABI declared in include/tdpt.h).
+
+Argument marshalling only: every step of 2D parallel tempering runs in the
+library's gfx950 kernels.  PyTorch supplies the device workspace (a uint8
+tensor) and the HIP stream.  There is no fallback: if the library is not
+built, or no GPU is present, the calls that need it raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libtdpt.so")
+
+OK, E_INVALID, E_RANGE, E_NOMEM, E_DEVICE, E_STATE = range(6)
+NO_PSWAP = 1
+
+EXPORTED = [
+    "tdpt_instance_create", "tdpt_instance_info_get", "tdpt_instance_destroy",
+    "tdpt_workspace_bytes", "tdpt_problem_create", "tdpt_problem_run", "tdpt_problem_query",
+    "tdpt_problem_read_energies", "tdpt_problem_read_states", "tdpt_problem_read_perm",
+    "tdpt_problem_read_best", "tdpt_problem_read_counters", "tdpt_problem_read_trace",
+    "tdpt_problem_save", "tdpt_problem_load", "tdpt_problem_destroy", "tdpt_last_error",
+    "tdpt_problem_set_timing", "tdpt_problem_read_timing",
+]
+
+
+class TdptError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"tdpt error {code}: {msg}")
+        self.code = code
+
+
+class _RunCfg(ctypes.Structure):
+    _fields_ = [
+        ("n_beta", ctypes.c_int32), ("beta", ctypes.c_void_p),
+        ("n_p", ctypes.c_int32), ("p_q", ctypes.c_void_p),
+        ("mcs_per_swap", ctypes.c_int32), ("seed", ctypes.c_uint64),
+        ("s0", ctypes.c_void_p), ("has_target", ctypes.c_int32),
+        ("f_target_q", ctypes.c_int64), ("flags", ctypes.c_uint32),
+        ("trace_cap", ctypes.c_int64),
+    ]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("n_pad", ctypes.c_int32), ("n_colors", ctypes.c_int32),
+                ("max_degree", ctypes.c_int32), ("max_copy_degree", ctypes.c_int32),
+                ("narrow", ctypes.c_int32), ("nnz", ctypes.c_int64), ("m", ctypes.c_int32)]
+
+
+class _Status(ctypes.Structure):
+    _fields_ = [("rounds_done", ctypes.c_int64), ("sweeps_done", ctypes.c_int64),
+                ("first_hit_sweep", ctypes.c_int64), ("best_f_q", ctypes.c_int64),
+                ("best_sweep", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libtdpt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2506_14781_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    sig = {
+        "tdpt_instance_create": [I32, P, P, P, P, I32, P, P, P, P],
+        "tdpt_instance_info_get": [P, P],
+        "tdpt_workspace_bytes": [P, P, P],
+        "tdpt_problem_create": [P, P, P, SZ, P, P],
+        "tdpt_problem_run": [P, I64],
+        "tdpt_problem_query": [P, P],
+        "tdpt_problem_read_energies": [P, P, P],
+        "tdpt_problem_read_states": [P, P],
+        "tdpt_problem_read_perm": [P, P],
+        "tdpt_problem_read_best": [P, P, P, P],
+        "tdpt_problem_read_counters": [P, P, P, P, P],
+        "tdpt_problem_read_trace": [P, P, P, P],
+        "tdpt_problem_save": [P, P, P],
+        "tdpt_problem_load": [P, P, SZ],
+        "tdpt_problem_set_timing": [P, I32],
+        "tdpt_problem_read_timing": [P, P, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.tdpt_instance_destroy.argtypes = [P]
+    lib.tdpt_instance_destroy.restype = None
+    lib.tdpt_problem_destroy.argtypes = [P]
+    lib.tdpt_problem_destroy.restype = None
+    lib.tdpt_last_error.argtypes = []
+    lib.tdpt_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise TdptError(rc, load_library().tdpt_last_error().decode())
+
+
+def _ptr(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def _arr(a, dt):
+    return None if a is None else np.ascontiguousarray(a, dtype=dt)
+
+
+class Instance:
+    """A validated, colour-major re-laid-out instance (host memory)."""
+
+    def __init__(self, n, row_ptr, col, J_q, b_q, copy_a, copy_b, color):
+        lib = load_library()
+        self._keep = [_arr(row_ptr, np.int32), _arr(col, np.int32), _arr(J_q, np.int32),
+                      _arr(b_q, np.int32), _arr(copy_a, np.int32), _arr(copy_b, np.int32),
+                      _arr(color, np.int32)]
+        rp, cl, jq, bq, ca, cb, co = self._keep
+        m = 0 if ca is None else int(ca.shape[0])
+        h = ctypes.c_void_p()
+        _check(lib.tdpt_instance_create(int(n), _ptr(rp), _ptr(cl), _ptr(jq), _ptr(bq), m,
+                                        _ptr(ca), _ptr(cb), _ptr(co), ctypes.byref(h)))
+        self._h = h
+        self.n = int(n)
+
+    @classmethod
+    def from_synth(cls, inst):
+        return cls(inst.n, inst.row_ptr, inst.col, inst.J_q, inst.b_q, inst.copy_a,
+                   inst.copy_b, inst.color)
+
+    def info(self) -> dict:
+        out = _Info()
+        _check(load_library().tdpt_instance_info_get(self._h, ctypes.byref(out)))
+        return {k: getattr(out, k) for k, _ in _Info._fields_}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.tdpt_instance_destroy(h)
+            self._h = None
+
+
+class RunConfig:
+    def __init__(self, beta, p_q, *, mcs_per_swap, seed, s0=None, f_target=None, flags=0,
+                 trace_cap=0):
+        self.beta = _arr(beta, np.float64)
+        self.p_q = _arr(p_q, np.int32)
+        self.s0 = None if s0 is None else _arr(s0, np.int8).reshape(-1)
+        self.mcs_per_swap = int(mcs_per_swap)
+        self.seed = int(seed) & (2**64 - 1)
+        self.f_target = f_target
+        self.flags = int(flags)
+        self.trace_cap = int(trace_cap)
+
+    def _c(self):
+        c = _RunCfg()
+        c.n_beta = self.beta.shape[0]
+        c.beta = self.beta.ctypes.data
+        c.n_p = self.p_q.shape[0]
+        c.p_q = self.p_q.ctypes.data
+        c.mcs_per_swap = self.mcs_per_swap
+        c.seed = self.seed
+        c.s0 = None if self.s0 is None else self.s0.ctypes.data
+        c.has_target = 0 if self.f_target is None else 1
+        c.f_target_q = 0 if self.f_target is None else int(self.f_target)
+        c.flags = self.flags
+        c.trace_cap = self.trace_cap
+        return c
+
+    @property
+    def replicas(self):
+        return self.beta.shape[0] * self.p_q.shape[0]
+
+
+def workspace_bytes(instance: Instance, cfg: RunConfig) -> int:
+    out = ctypes.c_size_t()
+    c = cfg._c()
+    _check(load_library().tdpt_workspace_bytes(instance._h, ctypes.byref(c), ctypes.byref(out)))
+    return out.value
+
+
+class Problem:
+    """One 2D-PT run resident on the GPU; outputs are per grid position."""
+
+    def __init__(self, instance: Instance, cfg: RunConfig, device="cuda", stream=None):
+        import torch
+        lib = load_library()
+        self.cfg = cfg
+        self.n = instance.n
+        self.I, self.J = cfg.beta.shape[0], cfg.p_q.shape[0]
+        self.R = self.I * self.J
+        nbytes = workspace_bytes(instance, cfg)
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        c = cfg._c()
+        _check(lib.tdpt_problem_create(instance._h, ctypes.byref(c),
+                                       ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                       ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, n_rounds: int):
+        _check(_lib.tdpt_problem_run(self._h, int(n_rounds)))
+
+    def query(self) -> dict:
+        s = _Status()
+        _check(_lib.tdpt_problem_query(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in _Status._fields_}
+
+    def energies(self):
+        f = np.zeros(self.R, dtype=np.int64)
+        g = np.zeros(self.R, dtype=np.int64)
+        _check(_lib.tdpt_problem_read_energies(self._h, _ptr(f), _ptr(g)))
+        return f, g
+
+    def states(self):
+        s = np.zeros((self.R, self.n), dtype=np.int8)
+        _check(_lib.tdpt_problem_read_states(self._h, _ptr(s)))
+        return s
+
+    def perm(self):
+        p = np.zeros(self.R, dtype=np.int32)
+        _check(_lib.tdpt_problem_read_perm(self._h, _ptr(p)))
+        return p
+
+    def best(self):
+        s = np.zeros(self.n, dtype=np.int8)
+        f = np.zeros(1, dtype=np.int64)
+        w = np.zeros(1, dtype=np.int64)
+        _check(_lib.tdpt_problem_read_best(self._h, _ptr(s), _ptr(f), _ptr(w)))
+        return s, int(f[0]), int(w[0])
+
+    def counters(self):
+        I, J = self.I, self.J
+        pa = np.zeros(max(I * (J - 1), 1), dtype=np.int64)
+        pc = np.zeros_like(pa)
+        ba = np.zeros(max(J * (I - 1), 1), dtype=np.int64)
+        bc = np.zeros_like(ba)
+        _check(_lib.tdpt_problem_read_counters(self._h, _ptr(pa), _ptr(pc), _ptr(ba), _ptr(bc)))
+        return (pa[:I * (J - 1)].reshape(I, J - 1), pc[:I * (J - 1)].reshape(I, J - 1),
+                ba[:J * (I - 1)].reshape(J, I - 1), bc[:J * (I - 1)].reshape(J, I - 1))
+
+    def trace(self):
+        cap = max(self.cfg.trace_cap, 1)
+        f = np.zeros(cap, dtype=np.int64)
+        g = np.zeros(cap, dtype=np.int64)
+        c = np.zeros(1, dtype=np.int64)
+        _check(_lib.tdpt_problem_read_trace(self._h, _ptr(f), _ptr(g), _ptr(c)))
+        k = int(c[0])
+        return f[:k], g[:k]
+
+    def save(self) -> bytes:
+        size = ctypes.c_size_t()
+        _check(_lib.tdpt_problem_save(self._h, None, ctypes.byref(size)))
+        buf = (ctypes.c_uint8 * size.value)()
+        _check(_lib.tdpt_problem_save(self._h, buf, ctypes.byref(size)))
+        return bytes(buf)
+
+    def load(self, blob: bytes):
+        buf = (ctypes.c_uint8 * len(blob)).from_buffer_copy(blob)
+        _check(_lib.tdpt_problem_load(self._h, buf, len(blob)))
+
+    def set_timing(self, every: int):
+        """Time every `every`-th sweep-kernel launch with HIP events (0: off)."""
+        _check(_lib.tdpt_problem_set_timing(self._h, int(every)))
+
+    def timing(self):
+        """(mean ms per timed sweep-kernel launch, number timed)."""
+        ms = ctypes.c_double()
+        k = ctypes.c_int64()
+        _check(_lib.tdpt_problem_read_timing(self._h, ctypes.byref(ms), ctypes.byref(k)))
+        return ms.value, k.value
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.tdpt_problem_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        self.close()

@@ -1,0 +1,126 @@
+"""The C-ABI library loads on any host and validates instances host-side.
+
+No GPU is needed: instance creation, validation and workspace sizing run on
+the host; nothing here launches a kernel.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2506_14781_amd as T
+from paper_2506_14781_amd import tdpt as B
+from synth.configs import wishart_n200, wishart_small
+from tests.tiny import tiny_instance
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "tdpt.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tdpt_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = T.load_library()
+    names = header_functions()
+    assert len(names) >= 17
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(B.EXPORTED)
+
+
+def _mk(inst, **over):
+    d = dict(n=inst.n, row_ptr=inst.row_ptr, col=inst.col, J_q=inst.J_q, b_q=inst.b_q,
+             copy_a=inst.copy_a, copy_b=inst.copy_b, color=inst.color)
+    d.update(over)
+    return T.Instance(**d)
+
+
+def test_info_of_the_workloads():
+    a = T.Instance.from_synth(wishart_small().instance).info()
+    assert (a["n"], a["n_colors"], a["max_degree"], a["narrow"]) == (60, 4, 3, 1)
+    assert a["n_pad"] % 4 == 0 and a["n_pad"] >= 60
+    b = T.Instance.from_synth(wishart_n200().instance).info()
+    assert b["n"] == 6600 and b["max_degree"] == 7 and b["max_copy_degree"] == 2
+    assert b["m"] == 6400 and b["nnz"] == wishart_n200().instance.row_ptr[-1]
+
+
+def test_rejects_asymmetric_couplings():
+    inst = tiny_instance()
+    J = inst.J_q.copy()
+    J[0] += 1
+    with pytest.raises(T.TdptError, match="symmetric"):
+        _mk(inst, J_q=J)
+
+
+def test_rejects_improper_colouring():
+    inst = tiny_instance()
+    color = inst.color.copy()
+    a, b = inst.copy_a[0], inst.copy_b[0]
+    color[b] = color[a]
+    with pytest.raises(T.TdptError, match="proper"):
+        _mk(inst, color=color)
+
+
+def test_rejects_self_loop_and_bad_index():
+    inst = tiny_instance()
+    col = inst.col.copy()
+    col[0] = 0
+    with pytest.raises(T.TdptError, match="self loop|symmetric"):
+        _mk(inst, col=col)
+    col = inst.col.copy()
+    col[0] = inst.n + 3
+    with pytest.raises(T.TdptError, match="range"):
+        _mk(inst, col=col)
+
+
+def test_rejects_copy_edge_that_is_also_a_coupling():
+    inst = tiny_instance()
+    rows = np.repeat(np.arange(inst.n), np.diff(inst.row_ptr))
+    a, b = int(rows[0]), int(inst.col[0])
+    ca = np.concatenate([inst.copy_a, [a]]).astype(np.int32)
+    cb = np.concatenate([inst.copy_b, [b]]).astype(np.int32)
+    with pytest.raises(T.TdptError, match="coupling"):
+        _mk(inst, copy_a=ca, copy_b=cb)
+
+
+def test_rejects_copy_graph_that_is_not_chains():
+    # a star of copy edges around spin 0
+    n = 4
+    rp = np.zeros(n + 1, dtype=np.int32)
+    with pytest.raises(T.TdptError, match="chains"):
+        T.Instance(n, rp, np.zeros(0, np.int32), np.zeros(0, np.int32), None,
+                   np.array([0, 0, 0], np.int32), np.array([1, 2, 3], np.int32),
+                   np.array([0, 1, 1, 1], np.int32))
+
+
+def test_rejects_bad_schedules():
+    inst = T.Instance.from_synth(tiny_instance())
+    for beta, pq, mcs in [([1.0, 0.5], [0], 1), ([0.0, 1.0], [0], 1), ([1.0], [10, 5], 1),
+                          ([1.0], [-1], 1), ([1.0], [0], 0)]:
+        with pytest.raises(T.TdptError):
+            T.workspace_bytes(inst, T.RunConfig(beta, pq, mcs_per_swap=mcs, seed=0))
+
+
+def test_workspace_grows_with_grid_and_trace():
+    inst = T.Instance.from_synth(wishart_small().instance)
+    a = T.workspace_bytes(inst, T.RunConfig([1.0], [0], mcs_per_swap=1, seed=0))
+    b = T.workspace_bytes(inst, T.RunConfig([1.0, 2.0], [0, 1], mcs_per_swap=1, seed=0))
+    c = T.workspace_bytes(inst, T.RunConfig([1.0, 2.0], [0, 1], mcs_per_swap=1, seed=0,
+                                            trace_cap=10000))
+    assert a < b < c
+
+
+def test_error_message_is_thread_local_text():
+    inst = tiny_instance()
+    J = inst.J_q.copy()
+    J[1] += 5
+    try:
+        _mk(inst, J_q=J)
+    except T.TdptError as e:
+        assert "symmetric" in str(e) and e.code == B.E_INVALID
+    assert "symmetric" in T.load_library().tdpt_last_error().decode()

@@ -1,0 +1,246 @@
+"""GPU path vs CPU oracle, bit-exact, through the C ABI.
+
+Every case runs the same seeded inputs through the oracle and through the
+gfx950 library and compares every output element by element: final spins
+of every grid position, f and g per position, swap attempt/accept counters
+of every pair, the bottom-right trace, best state, best energy and
+first-hit sweep.  Integers are compared exactly; the two double-precision
+decisions (heat bath, swap) use the same expression on both sides, so the
+trajectories are identical.
+"""
+from __future__ import annotations
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from synth.configs import batched_member, wishart_n200, wishart_small
+from synth.instances import build_instance, instance_from_logical, q12, random_spins
+from tests.tiny import tiny_instance
+
+pytestmark = pytest.mark.gpu
+
+INT64_MAX = 2**63 - 1
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2506_14781_amd as T
+    return T
+
+
+def run_gpu(T, inst, beta, p_q, *, mcs, rounds, seed, s0=None, f_target=None, flags=0,
+            trace=True, split=None):
+    I = T.Instance.from_synth(inst)
+    cfg = T.RunConfig(beta, p_q, mcs_per_swap=mcs, seed=seed, s0=s0, f_target=f_target,
+                      flags=flags, trace_cap=rounds if trace else 0)
+    P = T.Problem(I, cfg)
+    if split is None:
+        P.run(rounds)
+    else:
+        for part in split:
+            P.run(part)
+    return P
+
+
+def assert_same(o, P, label):
+    st = P.states()
+    if not np.array_equal(st, o["states"]):
+        bad = np.argwhere(st != o["states"])
+        p, v = bad[0]
+        raise AssertionError(f"{label}: states differ at {len(bad)} spins; first: position {p}, "
+                             f"spin {v} (gpu {st[p, v]}, oracle {o['states'][p, v]})")
+    f, g = P.energies()
+    assert np.array_equal(f, o["f"]), f"{label}: f differs"
+    assert np.array_equal(g, o["g"]), f"{label}: g differs"
+    pa, pc, ba, bc = P.counters()
+    assert np.array_equal(pa, o["p_att"]) and np.array_equal(pc, o["p_acc"]), f"{label}: P counters"
+    assert np.array_equal(ba, o["b_att"]) and np.array_equal(bc, o["b_acc"]), f"{label}: beta counters"
+    q = P.query()
+    assert q["first_hit_sweep"] == o["first_hit"], label
+    assert q["best_f_q"] == o["best_f"], label
+    assert q["best_sweep"] == o["best_sweep"], label
+    if o["best_f"] != INT64_MAX:
+        s, bf, bw = P.best()
+        assert np.array_equal(s, o["best_state"]), f"{label}: best state"
+    if len(o["trace_f"]):
+        tf, tg = P.trace()
+        assert np.array_equal(tf, o["trace_f"]) and np.array_equal(tg, o["trace_g"]), label
+
+
+def both(T, inst, beta, p_q, *, mcs, rounds, seed, label, **kw):
+    _say(f"[parity] {label}: n={inst.n} grid={len(beta)}x{len(p_q)} mcs={mcs} rounds={rounds} seed={seed}")
+    o = O.run(inst, beta, p_q, mcs_per_swap=mcs, n_rounds=rounds, seed=seed,
+              s0=kw.get("s0"), f_target=kw.get("f_target"), flags=kw.get("flags", 0),
+              trace=True)
+    P = run_gpu(T, inst, beta, p_q, mcs=mcs, rounds=rounds, seed=seed, **kw)
+    assert_same(o, P, label)
+    return o, P
+
+
+def test_initial_energies_match(T):
+    w = wishart_small()
+    rng = np.random.default_rng(0)
+    s0 = random_spins(rng, w.replicas * w.instance.n)
+    both(T, w.instance, w.beta, w.p_q, mcs=50, rounds=0, seed=0, s0=s0, label="round0-s0")
+    both(T, w.instance, w.beta, w.p_q, mcs=50, rounds=0, seed=9, label="round0-philox-s0")
+
+
+def test_small_wishart_full_run(T):
+    """N=12 planted Wishart, 8x4 grid, 1e4 sweeps: the whole run is bit-exact,
+    including the planted ground-state hit."""
+    w = wishart_small()
+    inst = w.instance
+    f_gs = O.energy(inst, inst.physical_state(inst.planted))[0]
+    for seed in (0, 5):
+        o, P = both(T, inst, w.beta, w.p_q, mcs=w.mcs_per_swap, rounds=w.rounds, seed=seed,
+                    f_target=f_gs, label=f"wishart-N12 seed {seed}")
+    assert o["first_hit"] > 0  # seed 5 reaches the planted ground state
+
+
+@pytest.mark.parametrize("I,J,mcs", [(1, 1, 3), (1, 4, 2), (4, 1, 2), (2, 2, 1), (3, 5, 2)])
+def test_tiny_grids(T, I, J, mcs):
+    inst = tiny_instance()
+    beta = np.geomspace(0.3, 3.0, I)
+    p_q = q12(np.linspace(0.5, 3.0, J))
+    both(T, inst, beta, p_q, mcs=mcs, rounds=40, seed=11, label=f"tiny {I}x{J}")
+
+
+def test_no_pswap_flag(T):
+    w = wishart_small()
+    both(T, w.instance, w.beta, np.full(4, 8192, np.int32), mcs=10, rounds=30, seed=2,
+         flags=O.NO_PSWAP, label="J-column PT")
+
+
+def test_caller_initial_state(T):
+    w = wishart_small()
+    rng = np.random.default_rng(4)
+    s0 = random_spins(rng, w.replicas * w.instance.n)
+    both(T, w.instance, w.beta, w.p_q, mcs=7, rounds=25, seed=3, s0=s0, label="given s0")
+
+
+def test_wide_layout(T):
+    """Couplings beyond 16 bits take the 32-bit structure layout."""
+    rng = np.random.default_rng(8)
+    A = np.triu(rng.normal(0, 10.0, size=(6, 6)), 1)
+    Jq = q12(A + A.T)
+    np.fill_diagonal(Jq, 0)
+    inst = instance_from_logical(Jq, degree_cap=3)
+    assert np.abs(inst.J_q).max() > 32767
+    T_inst = T.Instance.from_synth(inst)
+    assert T_inst.info()["narrow"] == 0
+    both(T, inst, np.array([0.001, 0.003]), q12([0.0, 40.0]), mcs=2, rounds=30, seed=1,
+         label="wide")
+
+
+def test_chains_only_no_couplings(T):
+    inst = instance_from_logical(np.zeros((4, 4), np.int32), copies=3)
+    both(T, inst, np.array([0.5, 1.5]), q12([0.0, 1.0]), mcs=3, rounds=20, seed=6,
+         label="chains only")
+
+
+def test_ragged_colour_classes(T):
+    """Colour classes whose sizes are not multiples of 4 leave dead lanes in
+    the last quad of each class."""
+    inst = build_instance(23, 0.75, 4, degree_cap=5)
+    sizes = np.bincount(inst.color)
+    assert np.any(sizes % 4 != 0)
+    both(T, inst, np.geomspace(0.2, 4, 3), q12([0, 1, 2.5]), mcs=4, rounds=20, seed=7,
+         label="ragged classes")
+
+
+def test_split_runs(T):
+    """run(13) + run(0) + run(27) is the same trajectory as 40 rounds at once."""
+    w = wishart_small()
+    o = O.run(w.instance, w.beta, w.p_q, mcs_per_swap=5, n_rounds=40, seed=12, trace=True)
+    P = run_gpu(T, w.instance, w.beta, w.p_q, mcs=5, rounds=40, seed=12, split=[13, 0, 27])
+    assert_same(o, P, "split 13+0+27")
+
+
+def test_checkpoint_rejects_other_shape(T):
+    w = wishart_small()
+    A = run_gpu(T, w.instance, w.beta, w.p_q, mcs=5, rounds=3, seed=12)
+    other = run_gpu(T, w.instance, w.beta[:4], w.p_q, mcs=5, rounds=0, seed=12)
+    with pytest.raises(T.TdptError):
+        other.load(A.save())
+
+
+def test_checkpoint_resume_is_bit_exact(T):
+    w = wishart_small()
+    I = T.Instance.from_synth(w.instance)
+    cfg = T.RunConfig(w.beta, w.p_q, mcs_per_swap=5, seed=21, trace_cap=40)
+    straight = T.Problem(I, cfg)
+    straight.run(40)
+    first = T.Problem(I, cfg)
+    first.run(17)
+    blob = first.save()
+    resumed = T.Problem(I, cfg)
+    resumed.load(blob)
+    resumed.run(23)
+    assert np.array_equal(straight.states(), resumed.states())
+    assert all(np.array_equal(a, b) for a, b in zip(straight.energies(), resumed.energies()))
+    assert all(np.array_equal(a, b) for a, b in zip(straight.counters(), resumed.counters()))
+    assert all(np.array_equal(a, b) for a, b in zip(straight.trace(), resumed.trace()))
+    assert straight.query() == resumed.query()
+
+
+def test_n200_prefix_bit_exact(T):
+    """N=200 planted Wishart (6600 spins), 32x16 grid, a swap every sweep:
+    the first rounds are bit-exact in the launch configuration the benchmark
+    times."""
+    w = wishart_n200()
+    both(T, w.instance, w.beta, w.p_q, mcs=1, rounds=12, seed=1, label="wishart-N200 prefix")
+
+
+@pytest.mark.parametrize("rb", ["1", "2", "4"])
+def test_slots_per_block_do_not_change_results(T, rb):
+    w = wishart_n200()
+    old = os.environ.get("TDPT_SLOTS_PER_BLOCK")
+    os.environ["TDPT_SLOTS_PER_BLOCK"] = rb
+    try:
+        both(T, w.instance, w.beta[:8], w.p_q[:4], mcs=2, rounds=4, seed=3,
+             label=f"slots per block {rb}")
+    finally:
+        if old is None:
+            del os.environ["TDPT_SLOTS_PER_BLOCK"]
+        else:
+            os.environ["TDPT_SLOTS_PER_BLOCK"] = old
+
+
+def test_batched_family_member(T):
+    w = batched_member(64, 0.5, 3)
+    both(T, w.instance, w.beta, w.p_q, mcs=w.mcs_per_swap, rounds=3, seed=2,
+         label="batched member N=64")
+
+
+def test_n200_long_run_invariants(T):
+    """At full size over many rounds: every spin stays +-1, the energies the
+    library carries equal those of the states it returns (no drift in the
+    incremental bookkeeping), the position permutation stays a permutation
+    and swap counters add up."""
+    w = wishart_n200()
+    _say("[invariants] wishart-N200 2000 rounds")
+    P = run_gpu(T, w.instance, w.beta, w.p_q, mcs=1, rounds=2000, seed=4, trace=False)
+    st = P.states()
+    assert np.all(np.abs(st) == 1)
+    f, g = P.energies()
+    rng = np.random.default_rng(0)
+    for pos in rng.choice(w.replicas, size=24, replace=False):
+        assert O.energy(w.instance, st[pos]) == (f[pos], g[pos])
+    perm = P.perm()
+    assert np.array_equal(np.sort(perm), np.arange(w.replicas))
+    pa, pc, ba, bc = P.counters()
+    assert pa.sum() + ba.sum() == sum(
+        (w.n_beta * ((w.n_p - (r % 2 == 0)) // 2)) if ((r - 1) // 2) % 2 == 0
+        else (w.n_p * ((w.n_beta - (r % 2 == 0)) // 2)) for r in range(1, 2001))
+    assert np.all(pc <= pa) and np.all(bc <= ba)
