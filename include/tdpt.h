@@ -104,6 +104,8 @@ typedef struct tdpt_status {
     int64_t first_hit_sweep; /* -1 if the target was not reached (or no target) */
     int64_t best_f_q;        /* best feasible f_q seen at the bottom-right, INT64_MAX if none */
     int64_t best_sweep;      /* sweep count at which best_f_q was recorded, -1 if none */
+    int32_t driver;          /* 1: one cooperative launch runs many rounds with every
+                                replica resident in LDS; 0: one launch pair per round */
 } tdpt_status;
 
 /* ---------------------------------------------------------------- instance */
@@ -180,12 +182,14 @@ int tdpt_problem_load(tdpt_problem *prob, const void *host, size_t bytes);
 void tdpt_problem_destroy(tdpt_problem *prob);
 
 /* Measurement hook: from now on record a pair of HIP events on the problem's
- * stream around every `every`-th sweep-kernel launch (at most 4096 pairs;
- * 0 switches it off and clears what was recorded). */
+ * stream around every `every`-th launch of the sweep kernel (the per-round
+ * sweep kernel, or the persistent kernel that runs many rounds); at most
+ * 4096 pairs; 0 switches it off and clears what was recorded. */
 int tdpt_problem_set_timing(tdpt_problem *prob, int32_t every);
-/* Wait for the stream and report the mean duration (ms) of the timed
- * sweep-kernel launches and how many were timed. */
-int tdpt_problem_read_timing(tdpt_problem *prob, double *avg_ms, int64_t *launches);
+/* Wait for the stream and report the summed duration (ms) of the timed
+ * launches, how many were timed and how many swap rounds they covered. */
+int tdpt_problem_read_timing(tdpt_problem *prob, double *total_ms, int64_t *launches,
+                             int64_t *rounds);
 
 /* Thread-local message of the last failed call ("" if none). */
 const char *tdpt_last_error(void);

@@ -8,8 +8,9 @@
 namespace tdpt {
 
 constexpr int kMaxColors = 32;
-constexpr int kBlock = 256;       // threads per sweep workgroup (4 wave64)
-constexpr int kMaxSlotsPerBlock = 4;
+constexpr int kMaxBlock = 1024;   // threads per sweep workgroup, at most
+constexpr int kSmallBlock = 256;  // threads of the swap / energy kernels
+constexpr int kRing = 8;          // rounds of partner mailboxes kept per position
 
 // Header words of a problem's device state (int64 each).
 enum HdrWord {
@@ -17,28 +18,41 @@ enum HdrWord {
     kHdrFirstHit = 1,  // first sweep count with a target hit, -1 if none
     kHdrBestF = 2,     // best feasible bottom-right f_q, INT64_MAX if none
     kHdrBestSweep = 3, // sweep count of best_f, -1 if none
+    kHdrError = 4,     // nonzero: a persistent launch gave up waiting for a partner
     kHdrWords = 8
 };
+
+// Best-state keys of the persistent driver: (f_q + 2^30) * 2^32 + sweep,
+// ordered like (f_q, sweep).  Valid while |f_q| < 2^30 and sweeps < 2^32.
+constexpr int64_t kKeyOffset = (int64_t)1 << 30;
 
 // Everything a kernel needs about one problem, passed by value.
 // Spins are numbered colour-major: class c occupies [cls_start[c],
 // cls_live[c]) followed by dead padding up to cls_start[c+1] (a multiple of
 // 4).  Index n_pad is a spin that is always 0; missing neighbours point there.
+//
+// Narrow structure (indices < 2^16, couplings in int16, fields < 2^22):
+//   nbi[k2][n_pad]  neighbour indices 2*k2 and 2*k2+1 packed as 16+16 bits
+//   nbj[k2][n_pad]  their couplings packed as int16 pairs
+//   chp[n_pad]      the two copy neighbours packed as 16+16 bits
+// Wide structure: nb_idx / nb_J [wd][n_pad] int32, ch_idx [2][n_pad] int32.
 struct DevProblem {
     // structure (immutable)
     int32_t n_pad;      // padded spin count
     int32_t stride;     // bytes per replica slot (>= n_pad + 1, multiple of 16)
     int32_t n_colors;
-    int32_t wd;         // problem-neighbour ELL width
-    int32_t wc;         // copy-neighbour ELL width
-    int32_t narrow;     // nbp/chp packed 16+16 bit layout
+    int32_t wd;         // problem-neighbour ELL width (even in the narrow layout)
+    int32_t narrow;
+    int32_t has_bias;   // any nonzero field
+    int32_t block;      // threads per sweep workgroup
     int32_t cls_start[kMaxColors + 1];
     int32_t cls_live[kMaxColors];
-    const uint32_t *nbp;   // narrow: [wd][n_pad] idx | (J << 16)
-    const int32_t *nb_idx; // wide: [wd][n_pad]
-    const int32_t *nb_J;   // wide: [wd][n_pad]
-    const uint32_t *chp;   // narrow (wc <= 2): [n_pad] c0 | (c1 << 16)
-    const int32_t *ch_idx; // wide: [wc][n_pad]
+    const uint32_t *nbi;   // narrow
+    const uint32_t *nbj;   // narrow
+    const uint32_t *chp;   // narrow
+    const int32_t *nb_idx; // wide
+    const int32_t *nb_J;   // wide
+    const int32_t *ch_idx; // wide
     const int32_t *bias;   // [n_pad]
     const int32_t *orig;   // [n_pad] original spin index, -1 for padding
     // run configuration
@@ -62,12 +76,21 @@ struct DevProblem {
     int64_t *b_att, *b_acc; // [J*(I-1)]
     int8_t *best_state;   // [stride]
     int64_t *trace_f, *trace_g; // [trace_cap]
+    // scratch of the persistent driver (not part of checkpoints)
+    uint64_t *mbox;       // [kRing][R][2] tagged (f, g) by grid position
+    int64_t *slot_key;    // [R] best key per slot during a launch
+    int8_t *slot_best;    // [R][stride] state behind slot_key
+    int64_t *hit_min;     // [1] smallest sweep with a target hit during a launch
 };
 
 // Kernel launchers (tdpt_kernels.hip).  Return a hipError_t.
 hipError_t launch_init_states(const DevProblem &p, hipStream_t s);
 hipError_t launch_energy(const DevProblem &p, hipStream_t s);
-hipError_t launch_sweep(const DevProblem &p, int slots_per_block, hipStream_t s);
+hipError_t launch_sweep(const DevProblem &p, hipStream_t s);
 hipError_t launch_swap(const DevProblem &p, hipStream_t s);
+hipError_t persistent_max_blocks(const DevProblem &p, int *max_blocks);
+hipError_t launch_persistent(const DevProblem &p, int64_t n_rounds, hipStream_t s);
+hipError_t launch_scratch_reset(const DevProblem &p, hipStream_t s);
+hipError_t launch_finalize(const DevProblem &p, int64_t n_rounds, hipStream_t s);
 
 }  // namespace tdpt

@@ -6,19 +6,30 @@
 // position labels of two replica slots (pos_slot / slot_pos), which is the
 // same as exchanging the configurations.
 //
-// Sweep layout: one workgroup owns RB replica slots and keeps their int8
-// spins in LDS for the whole round.  Spins are numbered colour-major; a lane
-// takes a quad of 4 consecutive spins of the current colour class, which
-// share one Philox4x32-10 call and one 16-byte load per neighbour slot of
-// the ELL structure.  Same-colour spins have no coupling between them, so
-// updating a whole class in parallel equals updating it one spin at a time
-// (chromatic Gibbs), and the workgroup barrier between classes keeps the
-// sweep order.
+// Sweep layout: one workgroup owns one replica slot and keeps its int8 spins
+// in LDS, starting at LDS address 0, so a neighbour index is its LDS byte
+// address.  Spins are numbered colour-major; a lane takes a quad of 4
+// consecutive spins of the current colour class, which share one
+// Philox4x32-10 call and one 16-byte load per structure row.  Same-colour
+// spins have no coupling between them, so updating a whole class in
+// parallel equals updating it one spin at a time (chromatic Gibbs), and the
+// workgroup barrier between classes keeps the sweep order.
+//
+// Two drivers share the sweep:
+//   k_round_sweep + k_swap_track  one launch pair per round (any grid size);
+//   k_persistent (+ k_finalize)   one cooperative launch for many rounds,
+//                                 every replica resident in LDS; no grid
+//                                 barrier: the two partners of a swap pair
+//                                 exchange (f, g) through per-position
+//                                 mailboxes and take the same decision.
 #include "tdpt_internal.h"
 
 #include <math.h>
 
 namespace tdpt {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef short v2s __attribute__((ext_vector_type(2)));
 
 // ------------------------------------------------------------------ Philox
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
@@ -42,188 +53,6 @@ __device__ __forceinline__ void philox10(uint32_t &x0, uint32_t &x1, uint32_t &x
     }
 }
 
-// ------------------------------------------------------- heat-bath decision
-// The decision is the double-precision expression
-//   +1  iff  (double)u < ldexp(1 / (1 + exp(-ldexp(beta * h, -11))), 32)
-// i.e. P(+1) = sigma(2 beta h) with h in Q12.  The float path below decides
-// exactly the same way whenever u is more than 2^16 away from the threshold
-// (its error is below 2^15 on the 2^32 scale, see DESIGN notes on the
-// margin), and defers to the double expression otherwise (probability about
-// 2^-15 per update).
-__device__ __attribute__((noinline)) int heat_bath_exact(double beta, int h, uint32_t u)
-{
-    const double x = ldexp(beta * (double)h, -11);
-    const double p = 1.0 / (1.0 + exp(-x));
-    return ((double)u < ldexp(p, 32)) ? 1 : -1;
-}
-
-__device__ __forceinline__ int heat_bath(int h, float cb, double beta, uint32_t u)
-{
-    const float y = (float)h * cb;  // x * log2(e), x = 2 beta h / 4096
-    if (y > 46.0f) return 1;        // x > 31.8: threshold above 2^32 - 1
-    if (y < -46.0f) return (u == 0u) ? heat_bath_exact(beta, h, u) : -1;
-    const float e = __builtin_amdgcn_exp2f(-y);
-    const float X = __builtin_amdgcn_rcpf(1.0f + e) * 4294967296.0f;
-    const float uf = (float)u;
-    if (uf < X - 65536.0f) return 1;
-    if (uf >= X + 65536.0f) return -1;
-    return heat_bath_exact(beta, h, u);
-}
-
-// ----------------------------------------------------------- block helpers
-__device__ __forceinline__ int64_t wave_sum64(int64_t v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// ------------------------------------------------------------ sweep kernel
-template <bool NARROW, int WD, int RB>
-__device__ __forceinline__ void sweep_quad(const DevProblem &P, int8_t *lds, int q, int live,
-                                           uint32_t t, const uint32_t (&pos)[RB],
-                                           const double (&beta)[RB], const float (&cb)[RB],
-                                           const int (&twoP)[RB], int ns, int (&dfa)[RB],
-                                           int (&dga)[RB])
-{
-    const int r0 = q * 4;
-    int idx[WD][4];
-    int jv[WD][4];
-    int c0[4], c1[4];
-    if constexpr (NARROW) {
-#pragma unroll
-        for (int k = 0; k < WD; ++k) {
-            const uint4 e = reinterpret_cast<const uint4 *>(P.nbp + (size_t)k * P.n_pad)[q];
-            idx[k][0] = e.x & 0xffff; jv[k][0] = (int)e.x >> 16;
-            idx[k][1] = e.y & 0xffff; jv[k][1] = (int)e.y >> 16;
-            idx[k][2] = e.z & 0xffff; jv[k][2] = (int)e.z >> 16;
-            idx[k][3] = e.w & 0xffff; jv[k][3] = (int)e.w >> 16;
-        }
-        const uint4 c = reinterpret_cast<const uint4 *>(P.chp)[q];
-        c0[0] = c.x & 0xffff; c1[0] = c.x >> 16;
-        c0[1] = c.y & 0xffff; c1[1] = c.y >> 16;
-        c0[2] = c.z & 0xffff; c1[2] = c.z >> 16;
-        c0[3] = c.w & 0xffff; c1[3] = c.w >> 16;
-    } else {
-#pragma unroll
-        for (int k = 0; k < WD; ++k) {
-            const int4 a = reinterpret_cast<const int4 *>(P.nb_idx + (size_t)k * P.n_pad)[q];
-            const int4 b = reinterpret_cast<const int4 *>(P.nb_J + (size_t)k * P.n_pad)[q];
-            idx[k][0] = a.x; idx[k][1] = a.y; idx[k][2] = a.z; idx[k][3] = a.w;
-            jv[k][0] = b.x; jv[k][1] = b.y; jv[k][2] = b.z; jv[k][3] = b.w;
-        }
-        const int4 a = reinterpret_cast<const int4 *>(P.ch_idx)[q];
-        const int4 b = reinterpret_cast<const int4 *>(P.ch_idx + P.n_pad)[q];
-        c0[0] = a.x; c0[1] = a.y; c0[2] = a.z; c0[3] = a.w;
-        c1[0] = b.x; c1[1] = b.y; c1[2] = b.z; c1[3] = b.w;
-    }
-    const int4 bb = reinterpret_cast<const int4 *>(P.bias)[q];
-    const int bias[4] = {bb.x, bb.y, bb.z, bb.w};
-
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-        if (r >= ns) break;
-        int8_t *s = lds + r * P.stride;
-        uint32_t u0 = (uint32_t)q, u1 = t, u2 = pos[r], u3 = 0u;
-        philox10(u0, u1, u2, u3, P.key0, P.key1);
-        const uint32_t u[4] = {u0, u1, u2, u3};
-        const char4 old = *reinterpret_cast<const char4 *>(s + r0);
-        const int so[4] = {old.x, old.y, old.z, old.w};
-        int sn[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (r0 + j < live) {
-                int hp = bias[j];
-#pragma unroll
-                for (int k = 0; k < WD; ++k) hp += jv[k][j] * (int)s[idx[k][j]];
-                const int cs = (int)s[c0[j]] + (int)s[c1[j]];
-                const int h = hp + twoP[r] * cs;
-                sn[j] = heat_bath(h, cb[r], beta[r], u[j]);
-                const int ds = sn[j] - so[j];
-                dfa[r] -= ds * hp;
-                dga[r] -= 2 * ds * cs;
-            } else {
-                sn[j] = so[j];
-            }
-        }
-        *reinterpret_cast<char4 *>(s + r0) =
-            make_char4((char)sn[0], (char)sn[1], (char)sn[2], (char)sn[3]);
-    }
-}
-
-template <bool NARROW, int WD, int RB>
-__global__ __launch_bounds__(kBlock) void k_round_sweep(DevProblem P)
-{
-    extern __shared__ __align__(16) int8_t lds[];
-    __shared__ int64_t red[kBlock / 64][RB][2];
-    const int tid = threadIdx.x;
-    const int slot0 = blockIdx.x * RB;
-    const int ns = min(RB, P.R - slot0);
-
-    const int nvec = P.stride >> 4;
-    for (int r = 0; r < ns; ++r) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(P.states + (size_t)(slot0 + r) * P.stride);
-        uint4 *dst = reinterpret_cast<uint4 *>(lds + r * P.stride);
-        for (int v = tid; v < nvec; v += kBlock) dst[v] = src[v];
-    }
-    const int64_t n_round = P.hdr[kHdrRounds] + 1;
-    uint32_t pos[RB];
-    double beta[RB];
-    float cb[RB];
-    int twoP[RB];
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-        const int p = (r < ns) ? P.slot_pos[slot0 + r] : 0;
-        const int i = p / P.J, j = p - (p / P.J) * P.J;
-        pos[r] = (uint32_t)p;
-        beta[r] = P.beta[i];
-        cb[r] = (float)(beta[r] * (1.4426950408889634 / 2048.0));
-        twoP[r] = 2 * P.p_q[j];
-    }
-    __syncthreads();
-
-    int64_t df[RB], dg[RB];
-#pragma unroll
-    for (int r = 0; r < RB; ++r) { df[r] = 0; dg[r] = 0; }
-
-    for (int k = 0; k < P.mcs; ++k) {
-        const uint32_t t = (uint32_t)((n_round - 1) * P.mcs + k);
-        for (int c = 0; c < P.n_colors; ++c) {
-            const int q0 = P.cls_start[c] >> 2, q1 = P.cls_start[c + 1] >> 2;
-            const int live = P.cls_live[c];
-            int dfa[RB], dga[RB];
-#pragma unroll
-            for (int r = 0; r < RB; ++r) { dfa[r] = 0; dga[r] = 0; }
-            for (int q = q0 + tid; q < q1; q += kBlock)
-                sweep_quad<NARROW, WD, RB>(P, lds, q, live, t, pos, beta, cb, twoP, ns, dfa, dga);
-#pragma unroll
-            for (int r = 0; r < RB; ++r) { df[r] += dfa[r]; dg[r] += dga[r]; }
-            __syncthreads();
-        }
-    }
-
-    const int wave = tid >> 6, lane = tid & 63;
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-        const int64_t a = wave_sum64(df[r]);
-        const int64_t b = wave_sum64(dg[r]);
-        if (lane == 0) { red[wave][r][0] = a; red[wave][r][1] = b; }
-    }
-    __syncthreads();
-    if (tid < ns) {
-        int64_t a = 0, b = 0;
-        for (int w = 0; w < kBlock / 64; ++w) { a += red[w][tid][0]; b += red[w][tid][1]; }
-        P.f[slot0 + tid] += a;
-        P.g[slot0 + tid] += b;
-    }
-    for (int r = 0; r < ns; ++r) {
-        uint4 *dst = reinterpret_cast<uint4 *>(P.states + (size_t)(slot0 + r) * P.stride);
-        const uint4 *src = reinterpret_cast<const uint4 *>(lds + r * P.stride);
-        for (int v = tid; v < nvec; v += kBlock) dst[v] = src[v];
-    }
-}
-
-// -------------------------------------------------------------- swap kernel
 __device__ __forceinline__ double philox_u53(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                              uint32_t k0, uint32_t k1)
 {
@@ -231,57 +60,311 @@ __device__ __forceinline__ double philox_u53(uint32_t c0, uint32_t c1, uint32_t 
     return ((double)(c0 >> 5) * 67108864.0 + (double)(c1 >> 6)) * (1.0 / 9007199254740992.0);
 }
 
+// ------------------------------------------------------- heat-bath decision
+// The decision is the double-precision expression
+//   +1  iff  (double)u < ldexp(1 / (1 + exp(-ldexp(beta * h, -11))), 32)
+// i.e. P(+1) = sigma(2 beta h) with h in Q12.  heat_bath_fast evaluates the
+// threshold X in single precision; its error is below 2^15 on the 2^32
+// scale (and below 2^9 once |x| > 32), so whenever |u - X| >= 2^16 its
+// answer is the exact one; otherwise the lane is flagged and the double
+// expression decides (about 2^-15 of all updates).
+__device__ __attribute__((noinline)) int heat_bath_exact(double beta, int h, uint32_t u)
+{
+    const double x = ldexp(beta * (double)h, -11);
+    const double p = 1.0 / (1.0 + exp(-x));
+    return ((double)u < ldexp(p, 32)) ? 1 : -1;
+}
+
+__device__ __forceinline__ int heat_bath_fast(int h, float cb, uint32_t u, bool &ambiguous)
+{
+    const float y = (float)h * cb;  // x * log2(e), x = 2 beta h / 4096
+    const float e = __builtin_amdgcn_exp2f(-y);
+    const float X = __builtin_amdgcn_rcpf(1.0f + e) * 4294967296.0f;
+    const float uf = (float)u;
+    ambiguous = fabsf(uf - X) < 65536.0f;
+    return (uf < X) ? 1 : -1;
+}
+
+// ------------------------------------------------------ structure access
+constexpr int kRsrcWord3 = 0x00020000;  // raw (untyped) buffer, gfx9 family
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, kRsrcWord3);
+}
+
+struct Rsrc {
+    __amdgpu_buffer_rsrc_t a, b, ch, bias;
+};
+
+__device__ __forceinline__ Rsrc make_rsrc(const DevProblem &P)
+{
+    Rsrc r;
+    if (P.narrow) {
+        const int bytes = (P.wd / 2) * P.n_pad * 4;
+        r.a = rsrc(P.nbi, bytes);
+        r.b = rsrc(P.nbj, bytes);
+        r.ch = rsrc(P.chp, P.n_pad * 4);
+    } else {
+        const int bytes = P.wd * P.n_pad * 4;
+        r.a = rsrc(P.nb_idx, bytes);
+        r.b = rsrc(P.nb_J, bytes);
+        r.ch = rsrc(P.ch_idx, P.n_pad * 8);
+    }
+    r.bias = rsrc(P.bias, P.n_pad * 4);
+    return r;
+}
+
+__device__ __forceinline__ v4i bload(const __amdgpu_buffer_rsrc_t &r, int voff, int soff)
+{
+    return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+}
+
+// Per-slot parameters of the current round.
+struct SlotParams {
+    double beta;
+    float cb;      // beta * log2(e) / 2048, rounded to float
+    int twoP;      // 2 * P_q of the slot's column
+    uint32_t pos;  // grid position (Philox counter word)
+};
+
+__device__ __forceinline__ SlotParams slot_params(const DevProblem &P, int pos)
+{
+    SlotParams sp;
+    const int i = pos / P.J, j = pos - i * P.J;
+    sp.beta = P.beta[i];
+    sp.cb = (float)(sp.beta * (1.4426950408889634 / 2048.0));
+    sp.twoP = 2 * P.p_q[j];
+    sp.pos = (uint32_t)pos;
+    return sp;
+}
+
+// Heat-bath update of the 4 spins of quad q (LDS bytes s).  live: bit j set
+// when spin 4q+j is a real spin (not class padding).  NARROW instances keep
+// every field and energy change below 2^22, so the 16-bit dot products and
+// 24-bit multiplies are exact.
+template <bool NARROW, int WD>
+__device__ __forceinline__ void update_quad(const DevProblem &P, const Rsrc &Rs, int8_t *s, int q,
+                                            unsigned live, uint32_t t, const SlotParams &sp,
+                                            int &dfa, int &dga)
+{
+    const int voff = q * 16;
+    const int row = P.n_pad * 4;
+    int hp[4], cs[4];
+    if (P.has_bias) {
+        const v4i bb = bload(Rs.bias, voff, 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) hp[j] = bb[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) hp[j] = 0;
+    }
+    if constexpr (NARROW) {
+#pragma unroll
+        for (int k2 = 0; k2 < WD / 2; ++k2) {
+            const v4i ia = bload(Rs.a, voff, k2 * row);
+            const v4i jb = bload(Rs.b, voff, k2 * row);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int iw = ia[j], jw = jb[j];  // plain ints: bit-cast a value, not a vector lane
+                v2s sv, jv;
+                sv.x = (short)s[iw & 0xffff];
+                sv.y = (short)s[(unsigned)iw >> 16];
+                jv.x = (short)(jw & 0xffff);
+                jv.y = (short)((unsigned)jw >> 16);
+                hp[j] = __builtin_amdgcn_sdot2(jv, sv, hp[j], false);
+            }
+        }
+        const v4i c = bload(Rs.ch, voff, 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cs[j] = (int)s[c[j] & 0xffff] + (int)s[(unsigned)c[j] >> 16];
+    } else {
+#pragma unroll
+        for (int k = 0; k < WD; ++k) {
+            const v4i ia = bload(Rs.a, voff, k * row);
+            const v4i jb = bload(Rs.b, voff, k * row);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) hp[j] += jb[j] * (int)s[ia[j]];
+        }
+        const v4i c0 = bload(Rs.ch, voff, 0);
+        const v4i c1 = bload(Rs.ch, voff, row);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cs[j] = (int)s[c0[j]] + (int)s[c1[j]];
+    }
+
+    uint32_t u[4] = {(uint32_t)q, t, sp.pos, 0u};
+    philox10(u[0], u[1], u[2], u[3], P.key0, P.key1);
+    const int r0 = q * 4;
+    const char4 old = *reinterpret_cast<const char4 *>(s + r0);
+    const int so[4] = {old.x, old.y, old.z, old.w};
+    int hh[4], sn[4];
+    unsigned amb = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if constexpr (NARROW) hh[j] = __mul24(sp.twoP, cs[j]) + hp[j];
+        else hh[j] = sp.twoP * cs[j] + hp[j];
+        bool a;
+        sn[j] = heat_bath_fast(hh[j], sp.cb, u[j], a);
+        amb |= a ? (1u << j) : 0u;
+    }
+    amb &= live;
+    if (__builtin_expect(amb != 0u, 0)) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (amb & (1u << j)) sn[j] = heat_bath_exact(sp.beta, hh[j], u[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        sn[j] = (live & (1u << j)) ? sn[j] : 0;
+        const int ds = sn[j] - so[j];
+        if constexpr (NARROW) {
+            dfa -= __mul24(ds, hp[j]);
+            dga -= __mul24(ds, cs[j]) * 2;
+        } else {
+            dfa -= ds * hp[j];
+            dga -= 2 * ds * cs[j];
+        }
+    }
+    *reinterpret_cast<char4 *>(s + r0) = make_char4((char)sn[0], (char)sn[1], (char)sn[2], (char)sn[3]);
+}
+
+__device__ __forceinline__ int64_t wave_sum64(int64_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// All sweeps of one round of the slot held at LDS address 0; returns the
+// change of f and g summed over the block into red[0..1] (LDS scratch of
+// 2 * (blockDim / 64) int64).
+template <bool NARROW, int WD>
+__device__ __forceinline__ void sweep_round(const DevProblem &P, const Rsrc &Rs, int8_t *s,
+                                            const SlotParams &sp, int64_t n_round, int64_t *red)
+{
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    int64_t df = 0, dg = 0;
+    for (int k = 0; k < P.mcs; ++k) {
+        const uint32_t t = (uint32_t)((n_round - 1) * P.mcs + k);
+        for (int c = 0; c < P.n_colors; ++c) {
+            const int q0 = P.cls_start[c] >> 2, q1 = P.cls_start[c + 1] >> 2;
+            const int live_end = P.cls_live[c];
+            int dfa = 0, dga = 0;
+            for (int q = q0 + tid; q < q1; q += nthr) {
+                const int rem = live_end - q * 4;
+                const unsigned live = rem >= 4 ? 15u : ((1u << rem) - 1u);
+                update_quad<NARROW, WD>(P, Rs, s, q, live, t, sp, dfa, dga);
+            }
+            df += dfa;
+            dg += dga;
+            __syncthreads();
+        }
+    }
+    const int64_t a = wave_sum64(df), b = wave_sum64(dg);
+    const int wave = tid >> 6, nw = nthr >> 6;
+    if ((tid & 63) == 0) { red[2 + 2 * wave] = a; red[3 + 2 * wave] = b; }
+    __syncthreads();
+    if (tid == 0) {
+        int64_t sa = 0, sb = 0;
+        for (int w = 0; w < nw; ++w) { sa += red[2 + 2 * w]; sb += red[3 + 2 * w]; }
+        red[0] = sa;
+        red[1] = sb;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void copy_bytes16(int8_t *dst, const int8_t *src, int bytes)
+{
+    const uint4 *s = reinterpret_cast<const uint4 *>(src);
+    uint4 *d = reinterpret_cast<uint4 *>(dst);
+    for (int v = threadIdx.x; v < (bytes >> 4); v += blockDim.x) d[v] = s[v];
+}
+
+// LDS of the sweep kernels: [0, stride) spins, then int64 scratch.
+__device__ __forceinline__ int64_t *lds_scratch(int8_t *lds, int stride)
+{
+    return reinterpret_cast<int64_t *>(lds + stride);
+}
+
+// --------------------------------------------------- one launch per round
+template <bool NARROW, int WD>
+__global__ __launch_bounds__(kMaxBlock) void k_round_sweep(DevProblem P)
+{
+    extern __shared__ __align__(16) int8_t lds[];
+    const int slot = blockIdx.x;
+    int64_t *red = lds_scratch(lds, P.stride);
+    copy_bytes16(lds, P.states + (size_t)slot * P.stride, P.stride);
+    const int64_t n_round = P.hdr[kHdrRounds] + 1;
+    const SlotParams sp = slot_params(P, P.slot_pos[slot]);
+    const Rsrc Rs = make_rsrc(P);
+    __syncthreads();
+    sweep_round<NARROW, WD>(P, Rs, lds, sp, n_round, red);
+    if (threadIdx.x == 0) {
+        P.f[slot] += red[0];
+        P.g[slot] += red[1];
+    }
+    copy_bytes16(P.states + (size_t)slot * P.stride, lds, P.stride);
+}
+
 __device__ __forceinline__ bool metropolis(double x, double u)
 {
     return x >= 0.0 || u <= exp(x);
 }
 
+// Swap exponent and acceptance of the pair (left / upper position a,
+// right / lower position b) in round n.  P pairs lie on row `line` with left
+// column k; beta pairs on column `line` with upper row k.
+__device__ __forceinline__ bool pair_accept(const DevProblem &P, bool dir_beta, int k, int line,
+                                            int64_t n, int64_t fa, int64_t ga, int64_t fb, int64_t gb)
+{
+    double x;
+    if (!dir_beta) {
+        const int64_t dpg = ((int64_t)P.p_q[k + 1] - P.p_q[k]) * (gb - ga);
+        x = ldexp(P.beta[line] * (double)dpg, -12);
+    } else {
+        const int64_t ea = fa + (int64_t)P.p_q[line] * ga;
+        const int64_t eb = fb + (int64_t)P.p_q[line] * gb;
+        const double dbeta = P.beta[k + 1] - P.beta[k];
+        x = ldexp(dbeta * (double)(eb - ea), -12);
+    }
+    const double u = philox_u53((uint32_t)k, (uint32_t)n, (uint32_t)line, dir_beta ? 2u : 1u,
+                                P.key0, P.key1);
+    return metropolis(x, u);
+}
+
+__device__ __forceinline__ void round_schedule(const DevProblem &P, int64_t n, bool &dir_beta, int &first)
+{
+    first = (n % 2 == 0) ? 1 : 0;
+    dir_beta = (P.flags & 1u) ? true : (((n - 1) / 2) % 2 == 1);
+}
+
 // One swap step of Algorithm 1 plus bottom-right tracking; one workgroup.
-__global__ __launch_bounds__(kBlock) void k_swap_track(DevProblem P)
+__global__ __launch_bounds__(kSmallBlock) void k_swap_track(DevProblem P)
 {
     __shared__ int improved;
     __shared__ int br_slot;
     const int tid = threadIdx.x;
     const int64_t n = P.hdr[kHdrRounds] + 1;
-    const int first = (n % 2 == 0) ? 1 : 0;
-    const bool dir_beta = (P.flags & 1u) ? true : (((n - 1) / 2) % 2 == 1);
-    if (!dir_beta) {
-        const int per = (P.J - first) / 2;
-        const int total = P.I * per;
-        for (int w = tid; w < total; w += kBlock) {
-            const int i = w / per, k = first + 2 * (w - (w / per) * per);
-            const int a = i * P.J + k, b = a + 1;
-            const int sa = P.pos_slot[a], sb = P.pos_slot[b];
-            const int64_t dpg = ((int64_t)P.p_q[k + 1] - P.p_q[k]) * (P.g[sb] - P.g[sa]);
-            const double x = ldexp(P.beta[i] * (double)dpg, -12);
-            const double u = philox_u53((uint32_t)k, (uint32_t)n, (uint32_t)i, 1u, P.key0, P.key1);
-            const int ci = i * (P.J - 1) + k;
-            P.p_att[ci] += 1;
-            if (metropolis(x, u)) {
-                P.p_acc[ci] += 1;
-                P.pos_slot[a] = sb; P.pos_slot[b] = sa;
-                P.slot_pos[sb] = a; P.slot_pos[sa] = b;
-            }
-        }
-    } else {
-        const int per = (P.I - first) / 2;
-        const int total = P.J * per;
-        for (int w = tid; w < total; w += kBlock) {
-            const int j = w / per, k = first + 2 * (w - (w / per) * per);
-            const int a = k * P.J + j, b = a + P.J;
-            const int sa = P.pos_slot[a], sb = P.pos_slot[b];
-            const int64_t ea = P.f[sa] + (int64_t)P.p_q[j] * P.g[sa];
-            const int64_t eb = P.f[sb] + (int64_t)P.p_q[j] * P.g[sb];
-            const double dbeta = P.beta[k + 1] - P.beta[k];
-            const double x = ldexp(dbeta * (double)(eb - ea), -12);
-            const double u = philox_u53((uint32_t)k, (uint32_t)n, (uint32_t)j, 2u, P.key0, P.key1);
-            const int ci = j * (P.I - 1) + k;
-            P.b_att[ci] += 1;
-            if (metropolis(x, u)) {
-                P.b_acc[ci] += 1;
-                P.pos_slot[a] = sb; P.pos_slot[b] = sa;
-                P.slot_pos[sb] = a; P.slot_pos[sa] = b;
-            }
+    bool dir_beta;
+    int first;
+    round_schedule(P, n, dir_beta, first);
+    const int len = dir_beta ? P.I : P.J;
+    const int lines = dir_beta ? P.J : P.I;
+    const int per = (len - first) / 2;
+    for (int w = tid; w < lines * per; w += blockDim.x) {
+        const int line = w / per, k = first + 2 * (w - (w / per) * per);
+        const int a = dir_beta ? k * P.J + line : line * P.J + k;
+        const int b = dir_beta ? a + P.J : a + 1;
+        const int sa = P.pos_slot[a], sb = P.pos_slot[b];
+        const bool acc = pair_accept(P, dir_beta, k, line, n, P.f[sa], P.g[sa], P.f[sb], P.g[sb]);
+        const int ci = dir_beta ? line * (P.I - 1) + k : line * (P.J - 1) + k;
+        int64_t *att = dir_beta ? P.b_att : P.p_att;
+        int64_t *acp = dir_beta ? P.b_acc : P.p_acc;
+        att[ci] += 1;
+        if (acc) {
+            acp[ci] += 1;
+            P.pos_slot[a] = sb; P.pos_slot[b] = sa;
+            P.slot_pos[sb] = a; P.slot_pos[sa] = b;
         }
     }
     __syncthreads();
@@ -302,13 +385,198 @@ __global__ __launch_bounds__(kBlock) void k_swap_track(DevProblem P)
         }
     }
     __syncthreads();
-    if (improved) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(P.states + (size_t)br_slot * P.stride);
-        uint4 *dst = reinterpret_cast<uint4 *>(P.best_state);
-        for (int v = tid; v < (P.stride >> 4); v += kBlock) dst[v] = src[v];
-    }
+    if (improved) copy_bytes16(P.best_state, P.states + (size_t)br_slot * P.stride, P.stride);
     __syncthreads();
     if (tid == 0) P.hdr[kHdrRounds] = n;
+}
+
+// ------------------------------------------------ persistent (cooperative)
+// Mailbox of grid position p in round n: two 64-bit words written by the
+// slot that sits at p, each carrying the round's tag in its low 16 bits so
+// either word can be checked on its own:
+//   w0 = f << 16 | tag,  w1 = g << 32 | (f >> 48) << 16 | tag.
+// Ring of kRing rounds: positions p and q that pair in round n pair again in
+// round n + 4, and no slot can move into p or q while their occupants have
+// not finished round n, so round n's entry is read before round n + kRing
+// rewrites it.
+__device__ __forceinline__ uint64_t mb_tag(int64_t n) { return (uint64_t)((n & 0x7fff) | 0x8000); }
+
+__device__ __forceinline__ bool mb_wait(const uint64_t *m, uint64_t tag, int64_t &f, int64_t &g, int64_t *hdr)
+{
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    for (;;) {
+        const uint64_t w0 = __hip_atomic_load(const_cast<uint64_t *>(m), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t w1 = __hip_atomic_load(const_cast<uint64_t *>(m + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((w0 & 0xffff) == tag && (w1 & 0xffff) == tag) {
+            f = (int64_t)((w0 >> 16) | (((w1 >> 16) & 0xffff) << 48));
+            g = (int64_t)(w1 >> 32);
+            return true;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        if (__builtin_amdgcn_s_memrealtime() - t0 > 200000000ull) {  // 2 s of the 100 MHz clock
+            __hip_atomic_store(&hdr[kHdrError], (int64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+    }
+}
+
+// One block per replica slot; runs n_rounds rounds.  Per round: sweep in
+// LDS, post (f, g) in the mailbox of the slot's grid position, read the
+// partner position's mailbox, take the pair's decision (both partners draw
+// the same Philox number and reach the same answer), move, and, if the slot
+// now sits bottom-right, record it.  Best states are kept per slot and
+// merged by k_finalize.
+template <bool NARROW, int WD>
+__global__ __launch_bounds__(kMaxBlock, 4) void k_persistent(DevProblem P, int64_t n_rounds)
+{
+    extern __shared__ __align__(16) int8_t lds[];
+    int64_t *red = lds_scratch(lds, P.stride);
+    // per-slot state kept by thread 0 in LDS: [0] f, [1] g, [2] best key
+    int64_t *st = red + 2 + 2 * (kMaxBlock / 64);
+    int *sh = reinterpret_cast<int *>(st + 3);  // [0] position, [1] improved, [2] abort
+    const int slot = blockIdx.x;
+    const int tid = threadIdx.x;
+    copy_bytes16(lds, P.states + (size_t)slot * P.stride, P.stride);
+    if (tid == 0) {
+        st[0] = P.f[slot];
+        st[1] = P.g[slot];
+        st[2] = INT64_MAX;
+        sh[0] = P.slot_pos[slot];
+    }
+    const int64_t n0 = P.hdr[kHdrRounds];
+    const Rsrc Rs = make_rsrc(P);
+    __syncthreads();
+    for (int64_t rr = 1; rr <= n_rounds; ++rr) {
+        const int64_t n = n0 + rr;
+        const int pos = __builtin_amdgcn_readfirstlane(sh[0]);
+        const SlotParams sp = slot_params(P, pos);
+        sweep_round<NARROW, WD>(P, Rs, lds, sp, n, red);
+        if (tid == 0) {
+            const int64_t f = st[0] + red[0];
+            const int64_t g = st[1] + red[1];
+            st[0] = f;
+            st[1] = g;
+            uint64_t *mb = P.mbox + 2 * ((size_t)(n & (kRing - 1)) * P.R);
+            const uint64_t tag = mb_tag(n);
+            __hip_atomic_store(&mb[2 * pos], ((uint64_t)f << 16) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&mb[2 * pos + 1],
+                               ((uint64_t)(uint32_t)g << 32) | ((((uint64_t)f >> 48) & 0xffff) << 16) | tag,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            bool dir_beta;
+            int first;
+            round_schedule(P, n, dir_beta, first);
+            const int i = pos / P.J, j = pos - i * P.J;
+            const int x = dir_beta ? i : j, line = dir_beta ? j : i;
+            const int len = dir_beta ? P.I : P.J;
+            int k = -1;
+            bool left = false;
+            if (x >= first && ((x - first) & 1) == 0 && x + 1 < len) { k = x; left = true; }
+            else if (x >= first + 1 && ((x - first) & 1) == 1) { k = x - 1; }
+            int newpos = pos;
+            int abort = 0;
+            if (k >= 0) {
+                const int a = dir_beta ? k * P.J + line : line * P.J + k;
+                const int b = dir_beta ? a + P.J : a + 1;
+                const int other = left ? b : a;
+                int64_t fo = 0, go = 0;
+                if (!mb_wait(&mb[2 * other], tag, fo, go, P.hdr)) abort = 1;
+                const int64_t fa = left ? f : fo, ga = left ? g : go;
+                const int64_t fb = left ? fo : f, gb = left ? go : g;
+                const bool acc = !abort && pair_accept(P, dir_beta, k, line, n, fa, ga, fb, gb);
+                if (left && !abort) {
+                    const int ci = dir_beta ? line * (P.I - 1) + k : line * (P.J - 1) + k;
+                    __hip_atomic_fetch_add(dir_beta ? &P.b_att[ci] : &P.p_att[ci], (int64_t)1,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (acc)
+                        __hip_atomic_fetch_add(dir_beta ? &P.b_acc[ci] : &P.p_acc[ci], (int64_t)1,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                if (acc) newpos = other;
+            }
+            int improved = 0;
+            if (newpos == P.R - 1 && !abort) {
+                const int64_t sweeps = n * P.mcs;
+                if (n - 1 < P.trace_cap) { P.trace_f[n - 1] = f; P.trace_g[n - 1] = g; }
+                if (g == 0) {
+                    if (P.has_target && f <= P.f_target)
+                        __hip_atomic_fetch_min(P.hit_min, sweeps, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const int64_t key = ((f + kKeyOffset) << 32) | (int64_t)(uint32_t)sweeps;
+                    if (key < st[2]) {
+                        st[2] = key;
+                        improved = 1;
+                    }
+                }
+            }
+            sh[0] = newpos;
+            sh[1] = improved;
+            sh[2] = abort;
+        }
+        __syncthreads();
+        if (sh[2]) break;
+        if (sh[1]) {
+            copy_bytes16(P.slot_best + (size_t)slot * P.stride, lds, P.stride);
+            __syncthreads();
+        }
+    }
+    copy_bytes16(P.states + (size_t)slot * P.stride, lds, P.stride);
+    if (tid == 0) {
+        const int pos = sh[0];
+        P.f[slot] = st[0];
+        P.g[slot] = st[1];
+        P.slot_pos[slot] = pos;
+        P.pos_slot[pos] = slot;
+        P.slot_key[slot] = st[2];
+    }
+}
+
+// Before a persistent launch: clear the per-slot best keys and the hit word.
+__global__ void k_scratch_reset(DevProblem P)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P.R) P.slot_key[i] = INT64_MAX;
+    if (i == 0) P.hit_min[0] = INT64_MAX;
+}
+
+// After a persistent launch: merge the per-slot bests and the first hit into
+// the problem's tracking and advance its round count (one workgroup).
+__global__ __launch_bounds__(kSmallBlock) void k_finalize(DevProblem P, int64_t n_rounds)
+{
+    __shared__ int64_t bk[kSmallBlock];
+    __shared__ int bs[kSmallBlock];
+    const int tid = threadIdx.x;
+    int64_t key = INT64_MAX;
+    int who = -1;
+    for (int r = tid; r < P.R; r += blockDim.x) {
+        const int64_t k = P.slot_key[r];
+        if (k < key) { key = k; who = r; }
+    }
+    bk[tid] = key;
+    bs[tid] = who;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (tid < off && bk[tid + off] < bk[tid]) { bk[tid] = bk[tid + off]; bs[tid] = bs[tid + off]; }
+        __syncthreads();
+    }
+    __shared__ int take;
+    if (tid == 0) {
+        take = -1;
+        const int64_t best = bk[0];
+        if (best != INT64_MAX) {
+            const int64_t bf = (best >> 32) - kKeyOffset;
+            const int64_t bw = best & 0xffffffffll;
+            const int64_t of = P.hdr[kHdrBestF];
+            if (of == INT64_MAX || bf < of) {
+                P.hdr[kHdrBestF] = bf;
+                P.hdr[kHdrBestSweep] = bw;
+                take = bs[0];
+            }
+        }
+        const int64_t hm = P.hit_min[0];
+        if (hm != INT64_MAX && P.hdr[kHdrFirstHit] < 0) P.hdr[kHdrFirstHit] = hm;
+        P.hdr[kHdrRounds] += n_rounds;
+    }
+    __syncthreads();
+    if (take >= 0) copy_bytes16(P.best_state, P.slot_best + (size_t)take * P.stride, P.stride);
 }
 
 // ---------------------------------------------------- initial states, f, g
@@ -335,9 +603,9 @@ __global__ void k_init_states(DevProblem P)
 
 // f = -sum_{i<j} J s_i s_j - sum b s and g = sum_copy (s_a - s_b)^2 of every
 // slot, from scratch (one workgroup per slot).
-__global__ __launch_bounds__(kBlock) void k_energy(DevProblem P)
+__global__ __launch_bounds__(kSmallBlock) void k_energy(DevProblem P)
 {
-    __shared__ int64_t red[kBlock / 64][2];
+    __shared__ int64_t red[kSmallBlock / 64][2];
     const int slot = blockIdx.x;
     const int8_t *s = P.states + (size_t)slot * P.stride;
     int64_t f2 = 0, g2 = 0;
@@ -345,25 +613,24 @@ __global__ __launch_bounds__(kBlock) void k_energy(DevProblem P)
         const int si = s[r];
         if (si == 0) continue;
         int64_t hp = 0;
-        for (int k = 0; k < P.wd; ++k) {
-            int id, jv;
-            if (P.narrow) {
-                const uint32_t e = P.nbp[(size_t)k * P.n_pad + r];
-                id = e & 0xffff; jv = (int)e >> 16;
-            } else {
-                id = P.nb_idx[(size_t)k * P.n_pad + r];
-                jv = P.nb_J[(size_t)k * P.n_pad + r];
-            }
-            hp += (int64_t)jv * s[id];
-        }
-        f2 -= si * hp + 2 * (int64_t)P.bias[r] * si;
         int ca, cb;
         if (P.narrow) {
+            for (int k2 = 0; k2 < P.wd / 2; ++k2) {
+                const uint32_t ia = P.nbi[(size_t)k2 * P.n_pad + r];
+                const uint32_t jb = P.nbj[(size_t)k2 * P.n_pad + r];
+                hp += (int64_t)(int16_t)(jb & 0xffff) * s[ia & 0xffff];
+                hp += (int64_t)(int16_t)(jb >> 16) * s[ia >> 16];
+            }
             const uint32_t c = P.chp[r];
-            ca = c & 0xffff; cb = c >> 16;
+            ca = c & 0xffff;
+            cb = c >> 16;
         } else {
-            ca = P.ch_idx[r]; cb = P.ch_idx[P.n_pad + r];
+            for (int k = 0; k < P.wd; ++k)
+                hp += (int64_t)P.nb_J[(size_t)k * P.n_pad + r] * s[P.nb_idx[(size_t)k * P.n_pad + r]];
+            ca = P.ch_idx[r];
+            cb = P.ch_idx[P.n_pad + r];
         }
+        f2 -= si * hp + 2 * (int64_t)P.bias[r] * si;
         if (ca != P.n_pad) { const int d = si - s[ca]; g2 += d * d; }
         if (cb != P.n_pad) { const int d = si - s[cb]; g2 += d * d; }
     }
@@ -389,56 +656,109 @@ hipError_t launch_init_states(const DevProblem &p, hipStream_t s)
 
 hipError_t launch_energy(const DevProblem &p, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_energy, dim3(p.R), dim3(kBlock), 0, s, p);
+    hipLaunchKernelGGL(k_energy, dim3(p.R), dim3(kSmallBlock), 0, s, p);
     return hipGetLastError();
 }
 
-template <bool NARROW, int WD, int RB>
-static hipError_t launch_sweep_t(const DevProblem &p, hipStream_t s)
+// Dynamic LDS of a sweep workgroup: the spins plus int64 scratch.
+static size_t sweep_lds(const DevProblem &p)
 {
-    const size_t lds = (size_t)RB * p.stride;
-    static bool attr_set = false;
-    if (!attr_set && lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_round_sweep<NARROW, WD, RB>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
-    const int blocks = (p.R + RB - 1) / RB;
-    hipLaunchKernelGGL((k_round_sweep<NARROW, WD, RB>), dim3(blocks), dim3(kBlock), lds, s, p);
+    return (size_t)p.stride + 8 * (2 + 2 * (kMaxBlock / 64) + 3) + 16;
+}
+
+template <typename K>
+static hipError_t allow_lds(K kernel, size_t lds)
+{
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <bool NARROW, int WD>
+static hipError_t round_sweep_t(const DevProblem &p, hipStream_t s)
+{
+    const size_t lds = sweep_lds(p);
+    hipError_t e = allow_lds(k_round_sweep<NARROW, WD>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_round_sweep<NARROW, WD>), dim3(p.R), dim3(p.block), lds, s, p);
     return hipGetLastError();
 }
 
-template <bool NARROW, int RB>
-static hipError_t launch_sweep_w(const DevProblem &p, hipStream_t s)
+template <bool NARROW, int WD>
+static hipError_t persistent_t(const DevProblem &p, int64_t n_rounds, hipStream_t s, bool query_only,
+                               int *max_blocks)
 {
-    switch (p.wd) {
-    case 1: return launch_sweep_t<NARROW, 1, RB>(p, s);
-    case 2: return launch_sweep_t<NARROW, 2, RB>(p, s);
-    case 3: return launch_sweep_t<NARROW, 3, RB>(p, s);
-    case 4: return launch_sweep_t<NARROW, 4, RB>(p, s);
-    case 5: return launch_sweep_t<NARROW, 5, RB>(p, s);
-    case 6: return launch_sweep_t<NARROW, 6, RB>(p, s);
-    case 7: return launch_sweep_t<NARROW, 7, RB>(p, s);
-    case 8: return launch_sweep_t<NARROW, 8, RB>(p, s);
-    case 12: return launch_sweep_t<NARROW, 12, RB>(p, s);
-    case 16: return launch_sweep_t<NARROW, 16, RB>(p, s);
-    default: return hipErrorInvalidValue;
+    const size_t lds = sweep_lds(p);
+    auto kern = k_persistent<NARROW, WD>;
+    hipError_t e = allow_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    if (query_only) {
+        int per_cu = 0, dev = 0, cus = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, p.block, lds);
+        if (e == hipSuccess) e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        *max_blocks = per_cu * cus;
+        return e;
     }
+    DevProblem arg = p;
+    void *args[] = {&arg, &n_rounds};
+    return hipLaunchCooperativeKernel((const void *)kern, dim3(p.R), dim3(p.block), args, lds, s);
 }
 
-hipError_t launch_sweep(const DevProblem &p, int rb, hipStream_t s)
-{
-    if (p.narrow)
-        return (rb == 1) ? launch_sweep_w<true, 1>(p, s)
-             : (rb == 2) ? launch_sweep_w<true, 2>(p, s) : launch_sweep_w<true, 4>(p, s);
-    return (rb == 1) ? launch_sweep_w<false, 1>(p, s)
-         : (rb == 2) ? launch_sweep_w<false, 2>(p, s) : launch_sweep_w<false, 4>(p, s);
-}
+// Narrow ELL widths are even (neighbours go in pairs); wide widths are any
+// of 1..8, 12, 16.
+#define TDPT_DISPATCH(FN, ...)                                              \
+    if (p.narrow) {                                                         \
+        switch (p.wd) {                                                     \
+        case 2: return FN<true, 2>(__VA_ARGS__);                            \
+        case 4: return FN<true, 4>(__VA_ARGS__);                            \
+        case 6: return FN<true, 6>(__VA_ARGS__);                            \
+        case 8: return FN<true, 8>(__VA_ARGS__);                            \
+        case 12: return FN<true, 12>(__VA_ARGS__);                          \
+        case 16: return FN<true, 16>(__VA_ARGS__);                          \
+        default: return hipErrorInvalidValue;                               \
+        }                                                                   \
+    }                                                                       \
+    switch (p.wd) {                                                         \
+    case 1: return FN<false, 1>(__VA_ARGS__);                               \
+    case 2: return FN<false, 2>(__VA_ARGS__);                               \
+    case 3: return FN<false, 3>(__VA_ARGS__);                               \
+    case 4: return FN<false, 4>(__VA_ARGS__);                               \
+    case 5: return FN<false, 5>(__VA_ARGS__);                               \
+    case 6: return FN<false, 6>(__VA_ARGS__);                               \
+    case 7: return FN<false, 7>(__VA_ARGS__);                               \
+    case 8: return FN<false, 8>(__VA_ARGS__);                               \
+    case 12: return FN<false, 12>(__VA_ARGS__);                             \
+    case 16: return FN<false, 16>(__VA_ARGS__);                             \
+    default: return hipErrorInvalidValue;                                   \
+    }
+
+hipError_t launch_sweep(const DevProblem &p, hipStream_t s) { TDPT_DISPATCH(round_sweep_t, p, s) }
 
 hipError_t launch_swap(const DevProblem &p, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_swap_track, dim3(1), dim3(kBlock), 0, s, p);
+    hipLaunchKernelGGL(k_swap_track, dim3(1), dim3(kSmallBlock), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t persistent_max_blocks(const DevProblem &p, int *max_blocks)
+{
+    TDPT_DISPATCH(persistent_t, p, 0, nullptr, true, max_blocks)
+}
+
+hipError_t launch_persistent(const DevProblem &p, int64_t n_rounds, hipStream_t s)
+{
+    TDPT_DISPATCH(persistent_t, p, n_rounds, s, false, nullptr)
+}
+
+hipError_t launch_scratch_reset(const DevProblem &p, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scratch_reset, dim3((p.R + 255) / 256), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const DevProblem &p, int64_t n_rounds, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kSmallBlock), 0, s, p, n_rounds);
     return hipGetLastError();
 }
 

@@ -65,6 +65,7 @@ struct tdpt_instance {
     std::vector<int32_t> nb_idx, nb_J;  // [wd][n_pad]
     std::vector<int32_t> ch_idx;        // [2][n_pad]
     std::vector<int32_t> bias;          // [n_pad]
+    int32_t has_bias = 0;
     int64_t max_field = 0;   // max_i sum_j |J_ij| + |b_i|
     int64_t abs_f_bound = 0; // sum_{i<j} |J_ij| + sum_i |b_i|
     int32_t max_class_quads = 0;
@@ -73,22 +74,24 @@ struct tdpt_instance {
 struct tdpt_problem {
     tdpt::DevProblem dp{};
     hipStream_t stream = nullptr;
-    int rb = 1;
     int32_t n = 0, I = 0, J = 0, R = 0, mcs = 1;
     std::vector<int32_t> rank;
     uint8_t *ws = nullptr;
-    size_t ws_bytes = 0, mut_off = 0, mut_bytes = 0;
+    size_t ws_bytes = 0, mut_off = 0, mut_bytes = 0, mbox_off = 0, mbox_bytes = 0;
     int64_t trace_cap = 0;
     uint64_t fingerprint = 0;
+    bool persistent = false;
+    int64_t rounds_host = 0;  // rounds done, as far as the host has enqueued them
     // optional sweep-kernel timing (HIP events on the problem's stream)
     int32_t time_every = 0;
     int64_t sweep_launches = 0;
+    int64_t timed_rounds = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     ~tdpt_problem()
     {
         for (auto &e : events) {
-            hipEventDestroy(e.first);
-            hipEventDestroy(e.second);
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
         }
     }
 };
@@ -97,16 +100,26 @@ namespace {
 
 struct Layout {
     size_t hdr, states, f, g, slot_pos, pos_slot, p_att, p_acc, b_att, b_acc, best, trace_f,
-        trace_g, mut_end;
-    size_t beta, p_q, nbp, nb_idx, nb_J, chp, ch_idx, bias, orig, total;
-    int32_t stride;
+        trace_g, mut_end, mbox, slot_key, slot_best, hit_min, scratch_end;
+    size_t beta, p_q, nbi, nbj, chp, nb_idx, nb_J, ch_idx, bias, orig, total;
+    int32_t stride, wd;
 };
 
-Layout make_layout(const tdpt_instance *in, int32_t I, int32_t J, int64_t trace_cap)
+// The packed structure (16-bit indices and coupling pairs) and the 16/24-bit
+// arithmetic of the sweep need indices and couplings that fit 16 bits and
+// every local field, penalty term and energy change below 2^22.
+bool use_narrow(const tdpt_instance *in, const tdpt_run_cfg *cfg)
+{
+    const int64_t pmax = cfg->p_q[cfg->n_p - 1];
+    return in->narrow && in->max_field + 4 * pmax < ((int64_t)1 << 22);
+}
+
+Layout make_layout(const tdpt_instance *in, int32_t I, int32_t J, int64_t trace_cap, bool narrow)
 {
     Layout L{};
     const size_t R = (size_t)I * J;
     L.stride = (int32_t)align_up((size_t)in->n_pad + 1, 16);
+    L.wd = narrow ? (in->wd + 1) / 2 * 2 : in->wd;
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t at = o;
@@ -128,18 +141,25 @@ Layout make_layout(const tdpt_instance *in, int32_t I, int32_t J, int64_t trace_
     L.trace_f = take((size_t)trace_cap * 8 + 8);
     L.trace_g = take((size_t)trace_cap * 8 + 8);
     L.mut_end = o;
+    L.mbox = take((size_t)tdpt::kRing * R * 16);
+    L.slot_key = take(R * 8);
+    L.slot_best = take(R * (size_t)L.stride);
+    L.hit_min = take(8);
+    L.scratch_end = o;
     L.beta = take((size_t)I * 8);
     L.p_q = take((size_t)J * 4);
-    const size_t ell = (size_t)in->wd * in->n_pad * 4;
-    if (in->narrow) {
-        L.nbp = take(ell);
+    if (narrow) {
+        const size_t rows = (size_t)(L.wd / 2) * in->n_pad * 4;
+        L.nbi = take(rows);
+        L.nbj = take(rows);
         L.chp = take((size_t)in->n_pad * 4);
         L.nb_idx = L.nb_J = L.ch_idx = 0;
     } else {
+        const size_t ell = (size_t)L.wd * in->n_pad * 4;
         L.nb_idx = take(ell);
         L.nb_J = take(ell);
         L.ch_idx = take((size_t)2 * in->n_pad * 4);
-        L.nbp = L.chp = 0;
+        L.nbi = L.nbj = L.chp = 0;
     }
     L.bias = take((size_t)in->n_pad * 4);
     L.orig = take((size_t)in->n_pad * 4);
@@ -169,16 +189,19 @@ int check_cfg(const tdpt_run_cfg *c)
     return TDPT_OK;
 }
 
-int slots_per_block(const tdpt_instance *in, int32_t R, int32_t stride, size_t lds_max)
+// Threads of a sweep workgroup: one lane per quad of the largest colour
+// class (per-round driver) or one lane per two quads (persistent driver,
+// whose two blocks per compute unit must both stay resident).
+int sweep_block(const tdpt_instance *in, bool persistent)
 {
-    int rb = (R >= 512) ? 2 : 1;
-    if (const char *e = getenv("TDPT_SLOTS_PER_BLOCK")) {
-        int v = atoi(e);
-        if (v == 1 || v == 2 || v == 4) rb = v;
+    const int quads = persistent ? (in->max_class_quads + 1) / 2 : in->max_class_quads;
+    int b = (quads + 63) / 64 * 64;
+    const int cap = persistent ? tdpt::kMaxBlock / 2 : tdpt::kMaxBlock;
+    if (const char *e = getenv("TDPT_BLOCK")) {
+        const int v = atoi(e);
+        if (v >= 64 && v <= cap && v % 64 == 0) b = v;
     }
-    while (rb > 1 && (size_t)rb * stride > lds_max) rb >>= 1;
-    (void)in;
-    return rb;
+    return std::min(std::max(b, 64), cap);
 }
 
 }  // namespace
@@ -319,6 +342,7 @@ int tdpt_instance_create(int32_t n, const int32_t *row_ptr, const int32_t *col, 
         if (b_q) {
             in->bias[r] = b_q[v];
             absf += std::llabs((long long)b_q[v]);
+            if (b_q[v] != 0) in->has_bias = 1;
         }
         in->max_field = std::max(in->max_field, field);
     }
@@ -356,7 +380,7 @@ int tdpt_workspace_bytes(const tdpt_instance *in, const tdpt_run_cfg *cfg, size_
     if (!in || !bytes) return fail(TDPT_E_INVALID, "NULL argument");
     int rc = check_cfg(cfg);
     if (rc) return rc;
-    *bytes = make_layout(in, cfg->n_beta, cfg->n_p, cfg->trace_cap).total;
+    *bytes = make_layout(in, cfg->n_beta, cfg->n_p, cfg->trace_cap, use_narrow(in, cfg)).total;
     return TDPT_OK;
 }
 
@@ -371,7 +395,8 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     if (!dev_ws) return fail(TDPT_E_INVALID, "workspace is NULL");
     if (((uintptr_t)dev_ws) % 256) return fail(TDPT_E_INVALID, "workspace must be 256-byte aligned");
     const int32_t I = cfg->n_beta, J = cfg->n_p, R = I * J;
-    const Layout L = make_layout(in, I, J, cfg->trace_cap);
+    const bool narrow = use_narrow(in, cfg);
+    const Layout L = make_layout(in, I, J, cfg->trace_cap, narrow);
     if (ws_bytes < L.total)
         return fail(TDPT_E_NOMEM, "workspace holds " + std::to_string(ws_bytes) + " bytes, needs " +
                                       std::to_string(L.total));
@@ -379,7 +404,8 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     const int64_t pmax = cfg->p_q[J - 1];
     if (in->max_field + 4 * pmax >= ((int64_t)1 << 31))
         return fail(TDPT_E_RANGE, "local field can reach 2^31");
-    const int64_t quads_per_thread = (in->max_class_quads + tdpt::kBlock - 1) / tdpt::kBlock;
+    const int64_t blk = std::min(sweep_block(in, false), sweep_block(in, true));
+    const int64_t quads_per_thread = (in->max_class_quads + blk - 1) / blk;
     if (quads_per_thread * 4 * 2 * (in->max_field + 4 * pmax) >= ((int64_t)1 << 31))
         return fail(TDPT_E_RANGE, "per-phase energy change can reach 2^31");
     const int64_t ebound = in->abs_f_bound + pmax * 4 * (int64_t)in->m;
@@ -408,8 +434,9 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     p->ws_bytes = ws_bytes;
     p->mut_off = 0;
     p->mut_bytes = L.mut_end;
+    p->mbox_off = L.mbox;
+    p->mbox_bytes = L.slot_key - L.mbox;
     p->trace_cap = cfg->trace_cap;
-    p->rb = slots_per_block(in, R, L.stride, lds_limit);
     p->fingerprint = ((uint64_t)in->n_pad << 40) ^ ((uint64_t)R << 20) ^ (uint64_t)L.total;
 
     tdpt::DevProblem &d = p->dp;
@@ -417,16 +444,18 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     d.n_pad = in->n_pad;
     d.stride = L.stride;
     d.n_colors = in->n_colors;
-    d.wd = in->wd;
-    d.wc = 2;
-    d.narrow = in->narrow;
+    d.wd = L.wd;
+    d.narrow = narrow ? 1 : 0;
+    d.has_bias = in->has_bias;
+    d.block = sweep_block(in, false);
     for (int c = 0; c <= in->n_colors; ++c) d.cls_start[c] = in->cls_start[c];
     for (int c = 0; c < in->n_colors; ++c) d.cls_live[c] = in->cls_live[c];
-    d.nbp = in->narrow ? (const uint32_t *)(ws + L.nbp) : nullptr;
-    d.chp = in->narrow ? (const uint32_t *)(ws + L.chp) : nullptr;
-    d.nb_idx = in->narrow ? nullptr : (const int32_t *)(ws + L.nb_idx);
-    d.nb_J = in->narrow ? nullptr : (const int32_t *)(ws + L.nb_J);
-    d.ch_idx = in->narrow ? nullptr : (const int32_t *)(ws + L.ch_idx);
+    d.nbi = narrow ? (const uint32_t *)(ws + L.nbi) : nullptr;
+    d.nbj = narrow ? (const uint32_t *)(ws + L.nbj) : nullptr;
+    d.chp = narrow ? (const uint32_t *)(ws + L.chp) : nullptr;
+    d.nb_idx = narrow ? nullptr : (const int32_t *)(ws + L.nb_idx);
+    d.nb_J = narrow ? nullptr : (const int32_t *)(ws + L.nb_J);
+    d.ch_idx = narrow ? nullptr : (const int32_t *)(ws + L.ch_idx);
     d.bias = (const int32_t *)(ws + L.bias);
     d.orig = (const int32_t *)(ws + L.orig);
     d.I = I;
@@ -454,6 +483,10 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     d.best_state = (int8_t *)(ws + L.best);
     d.trace_f = (int64_t *)(ws + L.trace_f);
     d.trace_g = (int64_t *)(ws + L.trace_g);
+    d.mbox = (uint64_t *)(ws + L.mbox);
+    d.slot_key = (int64_t *)(ws + L.slot_key);
+    d.slot_best = (int8_t *)(ws + L.slot_best);
+    d.hit_min = (int64_t *)(ws + L.hit_min);
 
     hipStream_t s = p->stream;
     auto cleanup = [&](int code) {
@@ -461,7 +494,6 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
         return code;
     };
     // immutable structure
-    std::vector<uint32_t> packed;
     hipError_t e = hipSuccess;
 #define UP(dst, src, bytes)                                                        \
     do {                                                                           \
@@ -471,14 +503,24 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     } while (0)
     UP(ws + L.beta, cfg->beta, (size_t)I * 8);
     UP(ws + L.p_q, cfg->p_q, (size_t)J * 4);
-    if (in->narrow) {
-        packed.resize((size_t)in->wd * in->n_pad);
-        for (size_t k = 0; k < packed.size(); ++k)
-            packed[k] = ((uint32_t)in->nb_idx[k] & 0xffffu) | ((uint32_t)(in->nb_J[k] & 0xffff) << 16);
-        UP(ws + L.nbp, packed.data(), packed.size() * 4);
-        std::vector<uint32_t> ch((size_t)in->n_pad);
-        for (int32_t r = 0; r < in->n_pad; ++r)
-            ch[r] = ((uint32_t)in->ch_idx[r] & 0xffffu) | ((uint32_t)in->ch_idx[(size_t)in->n_pad + r] << 16);
+    if (narrow) {
+        // neighbour pairs (2k, 2k+1): indices as 16+16 bits, couplings as int16 pairs
+        const int32_t n_pad = in->n_pad, wd = in->wd, pairs = L.wd / 2;
+        auto idx_at = [&](int k, int32_t r) { return k < wd ? in->nb_idx[(size_t)k * n_pad + r] : n_pad; };
+        auto j_at = [&](int k, int32_t r) { return k < wd ? in->nb_J[(size_t)k * n_pad + r] : 0; };
+        std::vector<uint32_t> A((size_t)pairs * n_pad), B((size_t)pairs * n_pad);
+        for (int k2 = 0; k2 < pairs; ++k2)
+            for (int32_t r = 0; r < n_pad; ++r) {
+                A[(size_t)k2 * n_pad + r] = ((uint32_t)idx_at(2 * k2, r) & 0xffffu) |
+                                            ((uint32_t)idx_at(2 * k2 + 1, r) << 16);
+                B[(size_t)k2 * n_pad + r] = ((uint32_t)j_at(2 * k2, r) & 0xffffu) |
+                                            ((uint32_t)(j_at(2 * k2 + 1, r) & 0xffff) << 16);
+            }
+        UP(ws + L.nbi, A.data(), A.size() * 4);
+        UP(ws + L.nbj, B.data(), B.size() * 4);
+        std::vector<uint32_t> ch((size_t)n_pad);
+        for (int32_t r = 0; r < n_pad; ++r)
+            ch[r] = ((uint32_t)in->ch_idx[r] & 0xffffu) | ((uint32_t)in->ch_idx[(size_t)n_pad + r] << 16);
         UP(ws + L.chp, ch.data(), ch.size() * 4);
     } else {
         UP(ws + L.nb_idx, in->nb_idx.data(), in->nb_idx.size() * 4);
@@ -489,7 +531,7 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     UP(ws + L.orig, in->orig.data(), in->orig.size() * 4);
     // mutable state
     {
-        std::vector<uint8_t> zero(L.mut_end, 0);
+        std::vector<uint8_t> zero(L.scratch_end, 0);
         int64_t *hdr = (int64_t *)(zero.data() + L.hdr);
         hdr[tdpt::kHdrRounds] = 0;
         hdr[tdpt::kHdrFirstHit] = -1;
@@ -518,7 +560,34 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     e = tdpt::launch_energy(d, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return cleanup(hip_fail(e, "initial energies"));
+    // the persistent driver needs every slot's block resident at once
+    p->persistent = false;
+    const char *pe = getenv("TDPT_PERSISTENT");
+    if (!(pe && pe[0] == '0') && in->abs_f_bound < tdpt::kKeyOffset) {
+        tdpt::DevProblem dq = d;
+        dq.block = sweep_block(in, true);
+        int max_blocks = 0;
+        e = tdpt::persistent_max_blocks(dq, &max_blocks);
+        if (e != hipSuccess) return cleanup(hip_fail(e, "occupancy query"));
+        if (max_blocks >= R) {
+            p->persistent = true;
+            d.block = dq.block;
+        }
+    }
     *out = p;
+    return TDPT_OK;
+}
+
+// Record a timing event pair around the next launch if it is sampled.
+static int timing_begin(tdpt_problem *p, std::pair<hipEvent_t, hipEvent_t> &ev, bool &timed)
+{
+    timed = p->time_every > 0 && p->sweep_launches % p->time_every == 0 &&
+            p->events.size() < kMaxTimedLaunches;
+    if (!timed) return TDPT_OK;
+    HIP_TRY(hipEventCreate(&ev.first), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&ev.second), "hipEventCreate");
+    p->events.push_back(ev);
+    HIP_TRY(hipEventRecord(ev.first, p->stream), "hipEventRecord");
     return TDPT_OK;
 }
 
@@ -526,23 +595,43 @@ int tdpt_problem_run(tdpt_problem *p, int64_t n_rounds)
 {
     if (!p) return fail(TDPT_E_INVALID, "problem is NULL");
     if (n_rounds < 0) return fail(TDPT_E_INVALID, "n_rounds must be >= 0");
-    for (int64_t r = 0; r < n_rounds; ++r) {
-        const bool timed = p->time_every > 0 && p->sweep_launches % p->time_every == 0 &&
-                           p->events.size() < kMaxTimedLaunches;
+    // the sweep index is a 32-bit Philox counter word
+    if ((p->rounds_host + n_rounds) * (int64_t)p->mcs > ((int64_t)1 << 32))
+        return fail(TDPT_E_RANGE, "a problem runs at most 2^32 sweeps");
+    if (n_rounds == 0) return TDPT_OK;
+    if (p->persistent) {
+        HIP_TRY(tdpt::launch_scratch_reset(p->dp, p->stream), "launch scratch reset");
         std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+        bool timed;
+        int rc = timing_begin(p, ev, timed);
+        if (rc) return rc;
+        hipError_t e = tdpt::launch_persistent(p->dp, n_rounds, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "launch persistent");
         if (timed) {
-            HIP_TRY(hipEventCreate(&ev.first), "hipEventCreate");
-            HIP_TRY(hipEventCreate(&ev.second), "hipEventCreate");
-            p->events.push_back(ev);
-            HIP_TRY(hipEventRecord(ev.first, p->stream), "hipEventRecord");
+            HIP_TRY(hipEventRecord(ev.second, p->stream), "hipEventRecord");
+            p->timed_rounds += n_rounds;
         }
-        hipError_t e = tdpt::launch_sweep(p->dp, p->rb, p->stream);
+        ++p->sweep_launches;
+        HIP_TRY(tdpt::launch_finalize(p->dp, n_rounds, p->stream), "launch finalize");
+        p->rounds_host += n_rounds;
+        return TDPT_OK;
+    }
+    for (int64_t r = 0; r < n_rounds; ++r) {
+        std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+        bool timed;
+        int rc = timing_begin(p, ev, timed);
+        if (rc) return rc;
+        hipError_t e = tdpt::launch_sweep(p->dp, p->stream);
         if (e != hipSuccess) return hip_fail(e, "launch sweep");
-        if (timed) HIP_TRY(hipEventRecord(ev.second, p->stream), "hipEventRecord");
+        if (timed) {
+            HIP_TRY(hipEventRecord(ev.second, p->stream), "hipEventRecord");
+            p->timed_rounds += 1;
+        }
         ++p->sweep_launches;
         e = tdpt::launch_swap(p->dp, p->stream);
         if (e != hipSuccess) return hip_fail(e, "launch swap");
     }
+    p->rounds_host += n_rounds;
     return TDPT_OK;
 }
 
@@ -551,18 +640,19 @@ int tdpt_problem_set_timing(tdpt_problem *p, int32_t every)
     if (!p || every < 0) return fail(TDPT_E_INVALID, "bad argument");
     HIP_TRY(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
     for (auto &e : p->events) {
-        hipEventDestroy(e.first);
-        hipEventDestroy(e.second);
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
     }
     p->events.clear();
     p->time_every = every;
     p->sweep_launches = 0;
+    p->timed_rounds = 0;
     return TDPT_OK;
 }
 
-int tdpt_problem_read_timing(tdpt_problem *p, double *avg_ms, int64_t *launches)
+int tdpt_problem_read_timing(tdpt_problem *p, double *total_ms, int64_t *launches, int64_t *rounds)
 {
-    if (!p || !avg_ms || !launches) return fail(TDPT_E_INVALID, "NULL argument");
+    if (!p || !total_ms || !launches || !rounds) return fail(TDPT_E_INVALID, "NULL argument");
     HIP_TRY(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
     double total = 0.0;
     for (auto &e : p->events) {
@@ -571,7 +661,8 @@ int tdpt_problem_read_timing(tdpt_problem *p, double *avg_ms, int64_t *launches)
         total += ms;
     }
     *launches = (int64_t)p->events.size();
-    *avg_ms = p->events.empty() ? 0.0 : total / (double)p->events.size();
+    *total_ms = total;
+    *rounds = p->timed_rounds;
     return TDPT_OK;
 }
 
@@ -589,7 +680,10 @@ int tdpt_problem_query(tdpt_problem *p, tdpt_status *out)
     int64_t h[tdpt::kHdrWords];
     int rc = d2h(p, h, p->dp.hdr, sizeof(h));
     if (rc) return rc;
+    if (h[tdpt::kHdrError])
+        return fail(TDPT_E_DEVICE, "a persistent launch timed out at a grid barrier (blocks not co-resident)");
     out->rounds_done = h[tdpt::kHdrRounds];
+    out->driver = p->persistent ? 1 : 0;
     out->sweeps_done = h[tdpt::kHdrRounds] * p->mcs;
     out->first_hit_sweep = h[tdpt::kHdrFirstHit];
     out->best_f_q = h[tdpt::kHdrBestF];
@@ -706,8 +800,13 @@ int tdpt_problem_load(tdpt_problem *p, const void *host, size_t bytes)
         return fail(TDPT_E_INVALID, "checkpoint belongs to a different problem shape");
     hipError_t e = hipMemcpyAsync(p->ws + p->mut_off, (const uint8_t *)host + 16, p->mut_bytes,
                                   hipMemcpyHostToDevice, p->stream);
+    // stale partner mailboxes of the rounds being replaced must not match
+    if (e == hipSuccess) e = hipMemsetAsync(p->ws + p->mbox_off, 0, p->mbox_bytes, p->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) return hip_fail(e, "checkpoint load");
+    int64_t rounds = 0;
+    memcpy(&rounds, (const uint8_t *)host + 16 + sizeof(int64_t) * tdpt::kHdrRounds, sizeof(rounds));
+    p->rounds_host = rounds;
     return TDPT_OK;
 }
 

@@ -54,7 +54,7 @@ class _Info(ctypes.Structure):
 class _Status(ctypes.Structure):
     _fields_ = [("rounds_done", ctypes.c_int64), ("sweeps_done", ctypes.c_int64),
                 ("first_hit_sweep", ctypes.c_int64), ("best_f_q", ctypes.c_int64),
-                ("best_sweep", ctypes.c_int64)]
+                ("best_sweep", ctypes.c_int64), ("driver", ctypes.c_int32)]
 
 
 _lib = None
@@ -85,7 +85,7 @@ def load_library():
         "tdpt_problem_save": [P, P, P],
         "tdpt_problem_load": [P, P, SZ],
         "tdpt_problem_set_timing": [P, I32],
-        "tdpt_problem_read_timing": [P, P, P],
+        "tdpt_problem_read_timing": [P, P, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -273,11 +273,13 @@ class Problem:
         _check(_lib.tdpt_problem_set_timing(self._h, int(every)))
 
     def timing(self):
-        """(mean ms per timed sweep-kernel launch, number timed)."""
+        """(total ms of the timed launches, launches timed, rounds they covered)."""
         ms = ctypes.c_double()
         k = ctypes.c_int64()
-        _check(_lib.tdpt_problem_read_timing(self._h, ctypes.byref(ms), ctypes.byref(k)))
-        return ms.value, k.value
+        r = ctypes.c_int64()
+        _check(_lib.tdpt_problem_read_timing(self._h, ctypes.byref(ms), ctypes.byref(k),
+                                             ctypes.byref(r)))
+        return ms.value, k.value, r.value
 
     def close(self):
         h = getattr(self, "_h", None)

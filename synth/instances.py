@@ -108,58 +108,129 @@ def chain_length_for_degree(deg: int, D: int) -> int:
     return L
 
 
+def mirror_chain_length(N: int, D: int) -> int:
+    """Even chain length of the mirror embedding under degree cap D.
+
+    The first half of the chain holds the circular offsets d = 1 .. N/2 (the
+    exact middle offset only for half of the nodes), so it needs
+    (D-1) + (L/2 - 1)(D-2) >= ceil((N-1)/2) + (1 if N is even).
+    """
+    if N - 1 <= D:
+        return 1
+    if D < 3:
+        raise ValueError("degree cap must be >= 3 to build chains")
+    h = (N - 1) // 2 + (1 if N % 2 == 0 else 0)
+    half = 1
+    while (D - 1) + (half - 1) * (D - 2) < h:
+        half += 1
+    return 2 * half
+
+
+def _mirror_holders(N: int, D: int, L: int, i: int):
+    """Copy index of node i that holds circular offset d, for d = 1..N-1.
+
+    Offsets of the first half fill copies 0, 1, .. L/2-1 in increasing d
+    (copy 0 takes D-1, later ones D-2); offset d of the second half goes to
+    copy L-1-c(N-d), the mirror of the copy holding N-d.  For even N the
+    middle offset N/2 belongs to the first half of nodes i < N/2 and to the
+    second half of the others.
+    """
+    half = []
+    for d in range(1, N):
+        if 2 * d < N or (2 * d == N and i < N // 2):
+            half.append(d)
+    first_n = (N - 1) // 2 + (1 if N % 2 == 0 else 0)
+    cap = [D - 1] + [D - 2] * (L // 2 - 1)
+    cfirst = {}
+    c, used = 0, 0
+    for d in range(1, first_n + 1):
+        while used >= cap[c]:
+            c += 1
+            used = 0
+        cfirst[d] = c
+        used += 1
+    out = np.zeros(N, dtype=np.int64)
+    for d in range(1, N):
+        if 2 * d < N or (2 * d == N and i < N // 2):
+            out[d] = cfirst[d]
+        else:
+            out[d] = L - 1 - cfirst[N - d]
+    return out
+
+
 def sparsify(Jq_logical: np.ndarray, *, degree_cap: int | None = None,
-             copies: int | None = None):
+             copies: int | None = None, order: str = "mirror"):
     """Copy-chain sparsification of a dense symmetric logical coupling matrix.
 
-    Exactly one of degree_cap / copies is given.  degree_cap: the chain of
-    each node is the shortest one whose copies hold its neighbours (ascending
-    logical index, filled copy 0 first) without any copy exceeding the cap.
-    copies: every chain has that many copies and the neighbours are split
-    into near-equal contiguous groups.  Returns (row_ptr, col, Jq, copy_a,
-    copy_b, logical_of).
+    Exactly one of degree_cap / copies is given.  The paper leaves open how a
+    node's neighbours are distributed among its copies; three rules exist:
+
+      "mirror" (degree_cap only): even chains; neighbour i+d (circular
+          offset d) of node i sits on copy c(d) and offset N-d on copy
+          L-1-c(d), so every coupling joins copies of opposite parity and
+          the physical graph is bipartite (two colour classes);
+      "circular": neighbours in circular order i+1, i+2, .. fill copy 0,
+          then copy 1, .. (shortest chain under the cap);
+      "ascending": the same with neighbours in index order 0, 1, ..
+
+    copies: every chain has that many copies and the neighbours (circular
+    order) are split into near-equal contiguous groups.  Couplings that are
+    zero are not edges.  Returns (row_ptr, col, Jq, copy_a, copy_b,
+    logical_of, copy_index).
     """
     Jq_logical = np.asarray(Jq_logical)
     N = Jq_logical.shape[0]
-    nbrs = [np.flatnonzero(Jq_logical[i]) for i in range(N)]
-    nbrs = [nb[nb != i] for i, nb in enumerate(nbrs)]
     if (degree_cap is None) == (copies is None):
         raise ValueError("give exactly one of degree_cap / copies")
+    if order == "mirror" and degree_cap is None:
+        order = "circular"
     L = np.zeros(N, dtype=np.int64)
-    holder = []  # holder[i][k] = copy index of node i that holds nbrs[i][k]
+    holder = []  # holder[i][j] = copy index of node i that holds neighbour j (-1: none)
     for i in range(N):
-        d = len(nbrs[i])
-        if degree_cap is not None:
-            Li = chain_length_for_degree(d, degree_cap)
+        nb = np.flatnonzero(Jq_logical[i])
+        nb = nb[nb != i]
+        h = np.full(N, -1, dtype=np.int64)
+        if order == "mirror":
+            Li = mirror_chain_length(N, degree_cap)
             if Li == 1:
-                cap = np.array([degree_cap])
+                h[nb] = 0
             else:
-                cap = np.full(Li, degree_cap - 2)
-                cap[0] = cap[-1] = degree_cap - 1
-            h = np.repeat(np.arange(Li), cap)[:d]
+                cd = _mirror_holders(N, degree_cap, Li, i)
+                h[nb] = cd[(nb - i) % N]
         else:
-            Li = copies
-            h = (np.arange(d) * Li) // max(d, 1)
+            if order == "circular":
+                nb = nb[np.argsort((nb - i - 1) % N, kind="stable")]
+            elif order != "ascending":
+                raise ValueError("order must be 'mirror', 'circular' or 'ascending'")
+            d = len(nb)
+            if degree_cap is not None:
+                Li = chain_length_for_degree(d, degree_cap)
+                if Li == 1:
+                    cap = np.array([degree_cap])
+                else:
+                    cap = np.full(Li, degree_cap - 2)
+                    cap[0] = cap[-1] = degree_cap - 1
+                h[nb] = np.repeat(np.arange(Li), cap)[:d]
+            else:
+                Li = copies
+                h[nb] = (np.arange(d) * Li) // max(d, 1)
         L[i] = Li
         holder.append(h)
     off = np.concatenate([[0], np.cumsum(L)])
     n = int(off[-1])
     logical_of = np.repeat(np.arange(N), L).astype(np.int32)
-    pos = [{int(j): k for k, j in enumerate(nbrs[i])} for i in range(N)]
+    copy_index = (np.arange(n) - off[logical_of]).astype(np.int32)
     rows, cols, vals = [], [], []
     for i in range(N):
-        for k, j in enumerate(nbrs[i]):
-            j = int(j)
-            a = off[i] + holder[i][k]
-            b = off[j] + holder[j][pos[j][i]]
-            rows.append(a)
-            cols.append(b)
+        for j in np.flatnonzero(holder[i] >= 0):
+            rows.append(off[i] + holder[i][j])
+            cols.append(off[j] + holder[j][i])
             vals.append(Jq_logical[i, j])
     rows = np.asarray(rows, dtype=np.int64)
     cols = np.asarray(cols, dtype=np.int64)
     vals = np.asarray(vals, dtype=np.int32)
-    order = np.lexsort((cols, rows))
-    rows, cols, vals = rows[order], cols[order], vals[order]
+    srt = np.lexsort((cols, rows))
+    rows, cols, vals = rows[srt], cols[srt], vals[srt]
     row_ptr = np.zeros(n + 1, dtype=np.int32)
     np.add.at(row_ptr, rows + 1, 1)
     row_ptr = np.cumsum(row_ptr).astype(np.int32)
@@ -169,7 +240,7 @@ def sparsify(Jq_logical: np.ndarray, *, degree_cap: int | None = None,
             ca.append(off[i] + c)
             cb.append(off[i] + c + 1)
     return (row_ptr, cols.astype(np.int32), vals, np.asarray(ca, dtype=np.int32),
-            np.asarray(cb, dtype=np.int32), logical_of)
+            np.asarray(cb, dtype=np.int32), logical_of, copy_index)
 
 
 def _adjacency(n, row_ptr, col, copy_a, copy_b):
@@ -182,6 +253,15 @@ def _adjacency(n, row_ptr, col, copy_a, copy_b):
     ptr = np.zeros(n + 1, dtype=np.int64)
     np.add.at(ptr, a + 1, 1)
     return np.cumsum(ptr), b
+
+
+def parity_coloring_if_proper(n, row_ptr, col, copy_a, copy_b, copy_index):
+    """Colour = copy index mod 2, if that is proper (bipartite embedding)."""
+    color = (np.asarray(copy_index) % 2).astype(np.int32)
+    src = np.repeat(np.arange(n), np.diff(row_ptr))
+    if np.any(color[src] == color[col]) or np.any(color[copy_a] == color[copy_b]):
+        return None
+    return color
 
 
 def balanced_coloring(n, row_ptr, col, copy_a, copy_b, max_colors=None):
@@ -252,15 +332,17 @@ def balanced_coloring(n, row_ptr, col, copy_a, copy_b, max_colors=None):
 
 
 def build_instance(N: int, alpha: float, seed: int, *, degree_cap=None,
-                   copies=None) -> Instance:
+                   copies=None, order: str = "mirror") -> Instance:
     """Planted Wishart instance, Q12-quantised, sparsified and coloured."""
     J, t = planted_wishart(N, alpha, seed)
     Jq = q12(J)
     np.fill_diagonal(Jq, 0)
-    row_ptr, col, vals, ca, cb, logical_of = sparsify(
-        Jq, degree_cap=degree_cap, copies=copies)
+    row_ptr, col, vals, ca, cb, logical_of, cidx = sparsify(
+        Jq, degree_cap=degree_cap, copies=copies, order=order)
     n = int(logical_of.shape[0])
-    color = balanced_coloring(n, row_ptr, col, ca, cb)
+    color = parity_coloring_if_proper(n, row_ptr, col, ca, cb, cidx)
+    if color is None:
+        color = balanced_coloring(n, row_ptr, col, ca, cb)
     return Instance(n=n, row_ptr=row_ptr, col=col, J_q=vals,
                     b_q=np.zeros(n, dtype=np.int32), copy_a=ca, copy_b=cb,
                     color=color, logical_of=logical_of, N=N, planted=t,
@@ -268,19 +350,21 @@ def build_instance(N: int, alpha: float, seed: int, *, degree_cap=None,
 
 
 def instance_from_logical(Jq_logical, *, b_logical_q=None, degree_cap=None,
-                          copies=None, planted=None) -> Instance:
+                          copies=None, planted=None, order: str = "mirror") -> Instance:
     """Sparsify and colour a caller-supplied dense logical Q12 problem."""
     Jq_logical = np.asarray(Jq_logical, dtype=np.int32)
     N = Jq_logical.shape[0]
-    row_ptr, col, vals, ca, cb, logical_of = sparsify(
-        Jq_logical, degree_cap=degree_cap, copies=copies)
+    row_ptr, col, vals, ca, cb, logical_of, cidx = sparsify(
+        Jq_logical, degree_cap=degree_cap, copies=copies, order=order)
     n = int(logical_of.shape[0])
     b = np.zeros(n, dtype=np.int32)
     if b_logical_q is not None:
         # the field of a logical node sits on its first copy
         first = np.concatenate([[0], np.flatnonzero(np.diff(logical_of)) + 1])
         b[first] = np.asarray(b_logical_q, dtype=np.int32)
-    color = balanced_coloring(n, row_ptr, col, ca, cb)
+    color = parity_coloring_if_proper(n, row_ptr, col, ca, cb, cidx)
+    if color is None:
+        color = balanced_coloring(n, row_ptr, col, ca, cb)
     return Instance(n=n, row_ptr=row_ptr, col=col, J_q=vals, b_q=b,
                     copy_a=ca, copy_b=cb, color=color, logical_of=logical_of,
                     N=N, planted=planted, J_logical_q=Jq_logical)

@@ -42,11 +42,11 @@ def _mk(inst, **over):
 
 def test_info_of_the_workloads():
     a = T.Instance.from_synth(wishart_small().instance).info()
-    assert (a["n"], a["n_colors"], a["max_degree"], a["narrow"]) == (60, 4, 3, 1)
-    assert a["n_pad"] % 4 == 0 and a["n_pad"] >= 60
+    assert (a["n"], a["n_colors"], a["max_degree"], a["narrow"]) == (72, 2, 3, 1)
+    assert a["n_pad"] % 4 == 0 and a["n_pad"] >= 72
     b = T.Instance.from_synth(wishart_n200().instance).info()
-    assert b["n"] == 6600 and b["max_degree"] == 7 and b["max_copy_degree"] == 2
-    assert b["m"] == 6400 and b["nnz"] == wishart_n200().instance.row_ptr[-1]
+    assert b["n"] == 6800 and b["max_degree"] == 7 and b["max_copy_degree"] == 2
+    assert b["m"] == 6600 and b["nnz"] == wishart_n200().instance.row_ptr[-1]
 
 
 def test_rejects_asymmetric_couplings():
@@ -109,9 +109,10 @@ def test_rejects_bad_schedules():
 def test_workspace_grows_with_grid_and_trace():
     inst = T.Instance.from_synth(wishart_small().instance)
     a = T.workspace_bytes(inst, T.RunConfig([1.0], [0], mcs_per_swap=1, seed=0))
-    b = T.workspace_bytes(inst, T.RunConfig([1.0, 2.0], [0, 1], mcs_per_swap=1, seed=0))
-    c = T.workspace_bytes(inst, T.RunConfig([1.0, 2.0], [0, 1], mcs_per_swap=1, seed=0,
-                                            trace_cap=10000))
+    b = T.workspace_bytes(inst, T.RunConfig(np.arange(1, 33), np.arange(16), mcs_per_swap=1,
+                                            seed=0))
+    c = T.workspace_bytes(inst, T.RunConfig(np.arange(1, 33), np.arange(16), mcs_per_swap=1,
+                                            seed=0, trace_cap=10000))
     assert a < b < c
 
 

@@ -152,8 +152,9 @@ def test_chains_only_no_couplings(T):
 def test_ragged_colour_classes(T):
     """Colour classes whose sizes are not multiples of 4 leave dead lanes in
     the last quad of each class."""
-    inst = build_instance(23, 0.75, 4, degree_cap=5)
+    inst = build_instance(23, 0.75, 4, degree_cap=5, order="ascending")
     sizes = np.bincount(inst.color)
+    assert inst.n_colors == 5
     assert np.any(sizes % 4 != 0)
     both(T, inst, np.geomspace(0.2, 4, 3), q12([0, 1, 2.5]), mcs=4, rounds=20, seed=7,
          label="ragged classes")
@@ -194,27 +195,62 @@ def test_checkpoint_resume_is_bit_exact(T):
     assert straight.query() == resumed.query()
 
 
+def _with_env(key, value, fn):
+    old = os.environ.get(key)
+    os.environ[key] = value
+    try:
+        return fn()
+    finally:
+        if old is None:
+            del os.environ[key]
+        else:
+            os.environ[key] = old
+
+
 def test_n200_prefix_bit_exact(T):
     """N=200 planted Wishart (6600 spins), 32x16 grid, a swap every sweep:
     the first rounds are bit-exact in the launch configuration the benchmark
-    times."""
+    times (the persistent driver)."""
     w = wishart_n200()
-    both(T, w.instance, w.beta, w.p_q, mcs=1, rounds=12, seed=1, label="wishart-N200 prefix")
+    o, P = both(T, w.instance, w.beta, w.p_q, mcs=1, rounds=40, seed=1,
+                label="wishart-N200 prefix")
+    assert P.query()["driver"] == 1
 
 
-@pytest.mark.parametrize("rb", ["1", "2", "4"])
-def test_slots_per_block_do_not_change_results(T, rb):
+def test_n200_prefix_per_round_driver(T):
+    """The same prefix through the one-launch-pair-per-round driver."""
     w = wishart_n200()
-    old = os.environ.get("TDPT_SLOTS_PER_BLOCK")
-    os.environ["TDPT_SLOTS_PER_BLOCK"] = rb
-    try:
-        both(T, w.instance, w.beta[:8], w.p_q[:4], mcs=2, rounds=4, seed=3,
-             label=f"slots per block {rb}")
-    finally:
-        if old is None:
-            del os.environ["TDPT_SLOTS_PER_BLOCK"]
-        else:
-            os.environ["TDPT_SLOTS_PER_BLOCK"] = old
+    o, P = _with_env("TDPT_PERSISTENT", "0", lambda: both(
+        T, w.instance, w.beta, w.p_q, mcs=1, rounds=12, seed=1, label="wishart-N200 per-round"))
+    assert P.query()["driver"] == 0
+
+
+def test_drivers_agree_on_the_small_workload(T):
+    w = wishart_small()
+    a = run_gpu(T, w.instance, w.beta, w.p_q, mcs=5, rounds=60, seed=8)
+    b = _with_env("TDPT_PERSISTENT", "0", lambda: run_gpu(
+        T, w.instance, w.beta, w.p_q, mcs=5, rounds=60, seed=8))
+    assert a.query()["driver"] == 1 and b.query()["driver"] == 0
+    assert np.array_equal(a.states(), b.states())
+    assert all(np.array_equal(x, y) for x, y in zip(a.counters(), b.counters()))
+    assert all(np.array_equal(x, y) for x, y in zip(a.trace(), b.trace()))
+    qa, qb = a.query(), b.query()
+    qa.pop("driver"), qb.pop("driver")
+    assert qa == qb
+
+
+@pytest.mark.parametrize("driver,block", [("0", "64"), ("0", "256"), ("0", "1024"),
+                                          ("1", "64"), ("1", "192"), ("1", "512")])
+def test_block_size_does_not_change_results(T, driver, block):
+    """Threads per workgroup (so quads per lane) is a launch choice only."""
+    w = wishart_n200()
+
+    def go():
+        return _with_env("TDPT_BLOCK", block, lambda: both(
+            T, w.instance, w.beta[:8], w.p_q[:4], mcs=2, rounds=6, seed=3,
+            label=f"driver {driver} block {block}"))
+    o, P = _with_env("TDPT_PERSISTENT", driver, go)
+    assert P.query()["driver"] == int(driver)
 
 
 def test_batched_family_member(T):

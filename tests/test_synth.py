@@ -3,7 +3,8 @@ import numpy as np
 import pytest
 
 from synth.configs import batched_sizes, serving_grid, wishart_n200, wishart_small
-from synth.instances import _adjacency, build_instance, chain_length_for_degree, q12
+from synth.instances import (_adjacency, build_instance, chain_length_for_degree,
+                             mirror_chain_length, q12)
 
 
 def _check(inst, cap=None):
@@ -40,16 +41,32 @@ def test_chain_lengths_for_the_workload_caps():
     assert chain_length_for_degree(199, 8) == 33
     assert chain_length_for_degree(999, 6) == 250
     assert chain_length_for_degree(3, 3) == 1
+    # mirror embedding: even chains
+    assert mirror_chain_length(12, 4) == 6
+    assert mirror_chain_length(200, 8) == 34
+    assert mirror_chain_length(1000, 6) == 250
+    assert mirror_chain_length(64, 6) == 16
+    assert mirror_chain_length(4, 3) == 1
+
+
+@pytest.mark.parametrize("N,D", [(12, 4), (13, 4), (40, 5), (64, 6), (101, 6), (200, 8)])
+def test_mirror_embedding_is_bipartite(N, D):
+    """Every coupling joins copies of opposite parity, so two colour classes."""
+    inst = build_instance(N, 0.75, 1, degree_cap=D)
+    _check(inst, cap=D)
+    assert inst.n_colors == 2
+    sizes = np.bincount(inst.color)
+    assert abs(int(sizes[0]) - int(sizes[1])) <= N
 
 
 def test_small_and_n200_instances():
     a = wishart_small().instance
-    assert a.n == 60
+    assert a.n == 72
     _check(a, cap=4)
     b = wishart_n200().instance
-    assert b.n == 6600
+    assert b.n == 6800
     _check(b, cap=8)
-    assert b.n_colors <= 9
+    assert b.n_colors == 2
 
 
 def test_batched_member_shapes():
@@ -63,6 +80,12 @@ def test_copies_per_node_mode():
     inst = build_instance(20, 0.75, 1, copies=3)
     assert inst.n == 60 and len(inst.copy_a) == 40
     _check(inst)
+
+
+@pytest.mark.parametrize("order", ["circular", "ascending"])
+def test_other_distribution_orders(order):
+    inst = build_instance(30, 0.75, 2, degree_cap=6, order=order)
+    _check(inst, cap=6)
 
 
 def test_q12_rounding_half_away_from_zero():
