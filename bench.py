@@ -2,7 +2,7 @@
 """Spin-update throughput of 2D parallel tempering on one MI355X.
 
 Workload: planted Wishart N=200 (alpha 0.8) sparsified with copy chains to
-degree 8 (6600 physical spins), a 32 x 16 replica grid (beta geometric
+degree 8 (6800 physical spins), a 32 x 16 replica grid (beta geometric
 0.05..10, P linear 0..8), a swap round after every sweep.  One step is
 `--rounds-per-step` swap rounds (default 1000 sweeps of all 512 replicas,
 each followed by the f/g reduction, the swap step and bottom-right
@@ -26,6 +26,23 @@ if ROOT not in sys.path:
 
 # MI355X: 256 compute units x 4 SIMD x 16 lanes x 2.4 GHz of 32-bit VALU lanes
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
+
+# HBM bytes per swap round of the persistent kernel on this workload, from
+# rocprofv3 FETCH_SIZE (x2.00) and WRITE_SIZE (x1.00) counters scaled against
+# a plain copy of known size; valid for the kernel source with this hash.
+MEASURED_TRAFFIC = {"kernel_sha256": "3e315b895864101a", "bytes_per_round": 213452}
+KERNEL_SRC = os.path.join(ROOT, "paper_2506_14781_amd", "csrc", "tdpt_kernels.hip")
+
+
+def measured_traffic(persistent: bool, rounds_per_launch: int):
+    """HBM bytes per launch from the committed counter run, or None if the
+    kernel source changed since the counters were taken."""
+    import hashlib
+    with open(KERNEL_SRC, "rb") as fh:
+        digest = hashlib.sha256(fh.read()).hexdigest()[:16]
+    if not persistent or digest != MEASURED_TRAFFIC["kernel_sha256"]:
+        return None
+    return MEASURED_TRAFFIC["bytes_per_round"] * rounds_per_launch
 
 
 def alu_ops_per_update(info) -> float:
@@ -124,7 +141,7 @@ def main():
         "peak": round(PEAK_LANE_OPS / 1e12, 3),
         "unit": "Tlane-op/s",
         "frac": round(achieved / PEAK_LANE_OPS, 4),
-        "traffic": None,
+        "traffic": measured_traffic(persistent, timed_rounds // max(timed, 1)),
         "kernel": "k_persistent" if persistent else "k_round_sweep",
         "kernel_avg_ms": round(launch_ms, 5),
         "kernel_launches_timed": timed,
