@@ -20,6 +20,8 @@ import platform
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -74,6 +76,81 @@ def cpu_baseline(w, rounds: int) -> dict:
             "seconds": round(dt, 3)}
 
 
+def _requests(T, members, cap_sweeps, f_target_from_planted=True):
+    """Requests of the batched / serving modes: target = planted energy,
+    computed on the GPU from the planted state itself (zero rounds)."""
+    from paper_2506_14781_amd.serve import Request
+    reqs = []
+    for w in members:
+        inst = T.Instance.from_synth(w.instance)
+        planted = np.tile(w.instance.physical_state(w.instance.planted), w.replicas)
+        probe = T.Problem(inst, T.RunConfig(w.beta, w.p_q, mcs_per_swap=w.mcs_per_swap, seed=w.seed,
+                                            s0=planted))
+        f_gs = int(probe.energies()[0][0])
+        probe.close()
+        cfg = T.RunConfig(w.beta, w.p_q, mcs_per_swap=w.mcs_per_swap, seed=w.seed, f_target=f_gs)
+        reqs.append(Request(name=w.name, instance=inst, cfg=cfg,
+                            max_rounds=cap_sweeps // w.mcs_per_swap))
+    return reqs
+
+
+def bench_batched(args):
+    """Batched family: the same instances run one after another (plain) and
+    all together in one batch; time to the planted ground state."""
+    import copy
+
+    import paper_2506_14781_amd as T
+    from paper_2506_14781_amd.serve import run_batched, run_plain, summarize
+    from synth.configs import batched_member, batched_sizes
+    members = [batched_member(N, a, s) for N, a, s in batched_sizes(args.count)]
+    reqs_b = _requests(T, members, args.cap_sweeps)
+    reqs_p = [copy.copy(r) for r in reqs_b]
+    print(f"[bench] batched family: {len(members)} instances, cap {args.cap_sweeps} sweeps",
+          file=sys.stderr, flush=True)
+    tb = run_batched(reqs_b, chunk=args.chunk)
+    sb = summarize(reqs_b, tb)
+    print(f"[bench] batched done in {tb:.2f} s", file=sys.stderr, flush=True)
+    tp = run_plain(reqs_p, chunk=args.chunk)
+    sp = summarize(reqs_p, tp)
+    for a, b in zip(reqs_b, reqs_p):
+        assert a.hit_sweep == b.hit_sweep, "sweeps to hit differ between modes"
+    out = {"metric": "time-to-planted-GS p50 (batched)", "value": sb["tts_p50_s"], "unit": "s",
+           "higher_is_better": False, "n_gpus": 1,
+           "data": "synthetic (seeded planted Wishart, copy-chain sparsified)",
+           "config": {"workload": f"batched family, {len(members)} instances, 16x8 grids, "
+                                  f"cap {args.cap_sweeps} sweeps"},
+           "batched": sb, "plain": sp}
+    print(json.dumps(out), flush=True)
+
+
+def bench_serving(args):
+    """Poisson arrivals of planted-Wishart solves (N ~ U{64..1024} scaled
+    down by --max-n), continuous batching under an HBM budget."""
+    import paper_2506_14781_amd as T
+    from paper_2506_14781_amd.serve import serve, summarize
+    from synth.configs import serving_member
+    rng = np.random.default_rng(0)
+    members, arrivals, t = [], [], 0.0
+    for k in range(args.count):
+        N = int(rng.integers(64, args.max_n + 1))
+        alpha = float(rng.choice([0.5, 0.8]))
+        members.append(serving_member(N, alpha, k, args.cap_sweeps))
+        t += rng.exponential(1.0 / args.rate)
+        arrivals.append(t)
+    reqs = _requests(T, members, args.cap_sweeps)
+    for r, a in zip(reqs, arrivals):
+        r.arrival = a
+    total = serve(reqs, chunk=args.chunk, budget_bytes=int(args.budget_gb * 2**30))
+    s = summarize(reqs, total)
+    out = {"metric": "time-to-planted-GS p50 (serving)", "value": s["tts_p50_s"], "unit": "s",
+           "higher_is_better": False, "n_gpus": 1,
+           "data": "synthetic (seeded planted Wishart, Poisson arrivals)",
+           "config": {"workload": f"serving, {args.count} requests, rate {args.rate}/s, "
+                                  f"N<= {args.max_n}, cap {args.cap_sweeps} sweeps"},
+           "serving": s}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +160,13 @@ def main():
     ap.add_argument("--cpu-rounds", type=int, default=100,
                     help="rounds of the oracle timed for the CPU baseline (0: skip)")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--workload", choices=["n200", "batched", "serving"], default="n200")
+    ap.add_argument("--count", type=int, default=64, help="instances (batched) / requests (serving)")
+    ap.add_argument("--cap-sweeps", type=int, default=50000)
+    ap.add_argument("--chunk", type=int, default=10, help="rounds between host checks")
+    ap.add_argument("--rate", type=float, default=50.0, help="serving arrivals per second")
+    ap.add_argument("--max-n", type=int, default=1024, help="largest logical size when serving")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serving HBM budget")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -100,6 +184,10 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "serving":
+        return bench_serving(args)
     w = wishart_n200(seed=args.seed)
     inst = T.Instance.from_synth(w.instance)
     info = inst.info()

@@ -191,6 +191,30 @@ int tdpt_problem_set_timing(tdpt_problem *prob, int32_t every);
 int tdpt_problem_read_timing(tdpt_problem *prob, double *total_ms, int64_t *launches,
                              int64_t *rounds);
 
+/* ---------------------------------------------------------------- batches */
+
+/* A batch advances many problems at once: every round is one sweep launch
+ * over all replica slots of all members (grouped by structure layout, the
+ * largest instances first) and one swap-and-track launch over all members,
+ * so problems of uneven size and grid share the GPU.  Results are identical
+ * to running each member alone (random streams are keyed per problem).
+ * Members are ordinary problems; their own streams are ordered after every
+ * batch run, so their read calls see its results.  A problem must not be
+ * run on its own while a batch run that holds it is in flight. */
+
+/* Device bytes of the descriptor table of a batch with up to max_members. */
+int tdpt_batch_workspace_bytes(int32_t max_members, size_t *bytes);
+/* Create a batch in a caller-owned device workspace (256-byte aligned, at
+ * least tdpt_batch_workspace_bytes) bound to `stream`. */
+int tdpt_batch_create(int32_t max_members, void *dev_ws, size_t ws_bytes, void *stream,
+                      tdpt_batch **out);
+/* Replace the member list (count <= max_members, no repeats; count 0 empties
+ * the batch).  Waits for pending work of the members. */
+int tdpt_batch_set_members(tdpt_batch *batch, tdpt_problem *const *probs, int32_t count);
+/* Enqueue n_rounds rounds of every member on the batch's stream. */
+int tdpt_batch_run(tdpt_batch *batch, int64_t n_rounds);
+void tdpt_batch_destroy(tdpt_batch *batch);
+
 /* Thread-local message of the last failed call ("" if none). */
 const char *tdpt_last_error(void);
 

@@ -92,5 +92,10 @@ hipError_t persistent_max_blocks(const DevProblem &p, int *max_blocks);
 hipError_t launch_persistent(const DevProblem &p, int64_t n_rounds, hipStream_t s);
 hipError_t launch_scratch_reset(const DevProblem &p, hipStream_t s);
 hipError_t launch_finalize(const DevProblem &p, int64_t n_rounds, hipStream_t s);
+// Batched rounds over a device table of problems sharing p's layout (p is
+// any member: it selects the kernel instance).
+hipError_t launch_batch_sweep(const DevProblem &p, const DevProblem *table, const int *first_block,
+                              int count, int blocks, int block, size_t max_stride, hipStream_t s);
+hipError_t launch_batch_swap(const DevProblem *table, int count, hipStream_t s);
 
 }  // namespace tdpt

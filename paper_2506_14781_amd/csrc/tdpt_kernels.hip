@@ -287,11 +287,10 @@ __device__ __forceinline__ int64_t *lds_scratch(int8_t *lds, int stride)
 }
 
 // --------------------------------------------------- one launch per round
+// One round of one slot: load its spins into LDS, mcs sweeps, store.
 template <bool NARROW, int WD>
-__global__ __launch_bounds__(kMaxBlock) void k_round_sweep(DevProblem P)
+__device__ __forceinline__ void round_sweep_body(const DevProblem &P, int slot, int8_t *lds)
 {
-    extern __shared__ __align__(16) int8_t lds[];
-    const int slot = blockIdx.x;
     int64_t *red = lds_scratch(lds, P.stride);
     copy_bytes16(lds, P.states + (size_t)slot * P.stride, P.stride);
     const int64_t n_round = P.hdr[kHdrRounds] + 1;
@@ -304,6 +303,30 @@ __global__ __launch_bounds__(kMaxBlock) void k_round_sweep(DevProblem P)
         P.g[slot] += red[1];
     }
     copy_bytes16(P.states + (size_t)slot * P.stride, lds, P.stride);
+}
+
+template <bool NARROW, int WD>
+__global__ __launch_bounds__(kMaxBlock) void k_round_sweep(DevProblem P)
+{
+    extern __shared__ __align__(16) int8_t lds[];
+    round_sweep_body<NARROW, WD>(P, blockIdx.x, lds);
+}
+
+// Batched round: block b serves slot b - first_block[p] of member p, where
+// first_block is the prefix sum of the members' replica counts.
+template <bool NARROW, int WD>
+__global__ __launch_bounds__(kMaxBlock) void k_batch_sweep(const DevProblem *__restrict__ table,
+                                                         const int *__restrict__ first_block, int count)
+{
+    extern __shared__ __align__(16) int8_t lds[];
+    const int b = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first_block[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    round_sweep_body<NARROW, WD>(table[lo], b - first_block[lo], lds);
 }
 
 __device__ __forceinline__ bool metropolis(double x, double u)
@@ -339,7 +362,7 @@ __device__ __forceinline__ void round_schedule(const DevProblem &P, int64_t n, b
 }
 
 // One swap step of Algorithm 1 plus bottom-right tracking; one workgroup.
-__global__ __launch_bounds__(kSmallBlock) void k_swap_track(DevProblem P)
+__device__ __forceinline__ void swap_track_body(const DevProblem &P)
 {
     __shared__ int improved;
     __shared__ int br_slot;
@@ -388,6 +411,13 @@ __global__ __launch_bounds__(kSmallBlock) void k_swap_track(DevProblem P)
     if (improved) copy_bytes16(P.best_state, P.states + (size_t)br_slot * P.stride, P.stride);
     __syncthreads();
     if (tid == 0) P.hdr[kHdrRounds] = n;
+}
+
+__global__ __launch_bounds__(kSmallBlock) void k_swap_track(DevProblem P) { swap_track_body(P); }
+
+__global__ __launch_bounds__(kSmallBlock) void k_batch_swap(const DevProblem *__restrict__ table)
+{
+    swap_track_body(table[blockIdx.x]);
 }
 
 // ------------------------------------------------ persistent (cooperative)
@@ -737,6 +767,31 @@ hipError_t launch_sweep(const DevProblem &p, hipStream_t s) { TDPT_DISPATCH(roun
 hipError_t launch_swap(const DevProblem &p, hipStream_t s)
 {
     hipLaunchKernelGGL(k_swap_track, dim3(1), dim3(kSmallBlock), 0, s, p);
+    return hipGetLastError();
+}
+
+template <bool NARROW, int WD>
+static hipError_t batch_sweep_t(const DevProblem &p, const DevProblem *table, const int *first_block,
+                                int count, int blocks, int block, size_t max_stride, hipStream_t s)
+{
+    (void)p;
+    const size_t lds = max_stride + 8 * (2 + 2 * (kMaxBlock / 64) + 3) + 16;
+    hipError_t e = allow_lds(k_batch_sweep<NARROW, WD>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_batch_sweep<NARROW, WD>), dim3(blocks), dim3(block), lds, s, table,
+                       first_block, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_sweep(const DevProblem &p, const DevProblem *table, const int *first_block,
+                              int count, int blocks, int block, size_t max_stride, hipStream_t s)
+{
+    TDPT_DISPATCH(batch_sweep_t, p, table, first_block, count, blocks, block, max_stride, s)
+}
+
+hipError_t launch_batch_swap(const DevProblem *table, int count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_swap, dim3(count), dim3(kSmallBlock), 0, s, table);
     return hipGetLastError();
 }
 

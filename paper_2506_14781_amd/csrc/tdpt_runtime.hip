@@ -812,4 +812,140 @@ int tdpt_problem_load(tdpt_problem *p, const void *host, size_t bytes)
 
 void tdpt_problem_destroy(tdpt_problem *p) { delete p; }
 
+// ------------------------------------------------------------------ batches
+
+struct tdpt_batch {
+    hipStream_t stream = nullptr;
+    uint8_t *ws = nullptr;
+    int32_t cap = 0;
+    int block = 256;
+    std::vector<tdpt_problem *> members;  // in table order
+    struct Group {
+        int first_member, count, blocks, prefix_off;
+        size_t max_stride;
+    };
+    std::vector<Group> groups;
+    hipEvent_t done = nullptr;
+    ~tdpt_batch()
+    {
+        if (done) (void)hipEventDestroy(done);
+    }
+};
+
+static size_t batch_table_bytes(int32_t cap) { return align_up((size_t)cap * sizeof(tdpt::DevProblem), 256); }
+
+int tdpt_batch_workspace_bytes(int32_t max_members, size_t *bytes)
+{
+    if (max_members < 1 || !bytes) return fail(TDPT_E_INVALID, "need max_members >= 1");
+    *bytes = batch_table_bytes(max_members) + align_up((size_t)(2 * max_members + 1) * 4, 256);
+    return TDPT_OK;
+}
+
+int tdpt_batch_create(int32_t max_members, void *dev_ws, size_t ws_bytes, void *stream, tdpt_batch **out)
+{
+    if (!out) return fail(TDPT_E_INVALID, "out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    int rc = tdpt_batch_workspace_bytes(max_members, &need);
+    if (rc) return rc;
+    if (!dev_ws || ((uintptr_t)dev_ws) % 256) return fail(TDPT_E_INVALID, "workspace must be 256-byte aligned");
+    if (ws_bytes < need) return fail(TDPT_E_NOMEM, "batch workspace too small");
+    auto *b = new (std::nothrow) tdpt_batch();
+    if (!b) return fail(TDPT_E_NOMEM, "host allocation failed");
+    b->stream = (hipStream_t)stream;
+    b->ws = (uint8_t *)dev_ws;
+    b->cap = max_members;
+    if (const char *e = getenv("TDPT_BATCH_BLOCK")) {
+        const int v = atoi(e);
+        if (v >= 64 && v <= tdpt::kMaxBlock && v % 64 == 0) b->block = v;
+    }
+    hipError_t e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e, "hipEventCreate");
+    }
+    *out = b;
+    return TDPT_OK;
+}
+
+int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t count)
+{
+    if (!b) return fail(TDPT_E_INVALID, "batch is NULL");
+    if (count < 0 || count > b->cap || (count > 0 && !probs))
+        return fail(TDPT_E_INVALID, "member count out of range");
+    std::vector<tdpt_problem *> m(probs, probs + count);
+    for (auto *p : m)
+        if (!p) return fail(TDPT_E_INVALID, "NULL member");
+    {
+        std::vector<tdpt_problem *> chk = m;
+        std::sort(chk.begin(), chk.end());
+        if (std::adjacent_find(chk.begin(), chk.end()) != chk.end())
+            return fail(TDPT_E_INVALID, "a problem appears twice in the batch");
+    }
+    for (auto *p : m) HIP_TRY(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+    HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    // group by structure layout (kernel instance), largest replicas first
+    std::stable_sort(m.begin(), m.end(), [](const tdpt_problem *x, const tdpt_problem *y) {
+        if (x->dp.narrow != y->dp.narrow) return x->dp.narrow > y->dp.narrow;
+        if (x->dp.wd != y->dp.wd) return x->dp.wd < y->dp.wd;
+        return x->dp.stride > y->dp.stride;
+    });
+    b->members = m;
+    b->groups.clear();
+    std::vector<tdpt::DevProblem> table(m.size());
+    std::vector<int32_t> prefix;
+    for (size_t i = 0; i < m.size(); ++i) {
+        table[i] = m[i]->dp;
+        const bool start = b->groups.empty() || m[i]->dp.narrow != m[i - 1]->dp.narrow ||
+                           m[i]->dp.wd != m[i - 1]->dp.wd;
+        if (start) {
+            tdpt_batch::Group g{(int)i, 0, 0, (int)prefix.size(), 0};
+            b->groups.push_back(g);
+        }
+        auto &g = b->groups.back();
+        prefix.push_back(g.blocks);
+        g.blocks += m[i]->R;
+        g.count += 1;
+        g.max_stride = std::max(g.max_stride, (size_t)m[i]->dp.stride);
+    }
+    if (!m.empty()) {
+        HIP_TRY(hipMemcpyAsync(b->ws, table.data(), table.size() * sizeof(tdpt::DevProblem),
+                               hipMemcpyHostToDevice, b->stream), "upload batch table");
+        HIP_TRY(hipMemcpyAsync(b->ws + batch_table_bytes(b->cap), prefix.data(), prefix.size() * 4,
+                               hipMemcpyHostToDevice, b->stream), "upload batch table");
+        HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    }
+    return TDPT_OK;
+}
+
+int tdpt_batch_run(tdpt_batch *b, int64_t n_rounds)
+{
+    if (!b) return fail(TDPT_E_INVALID, "batch is NULL");
+    if (n_rounds < 0) return fail(TDPT_E_INVALID, "n_rounds must be >= 0");
+    if (n_rounds == 0 || b->members.empty()) return TDPT_OK;
+    for (auto *p : b->members)
+        if ((p->rounds_host + n_rounds) * (int64_t)p->mcs > ((int64_t)1 << 32))
+            return fail(TDPT_E_RANGE, "a problem runs at most 2^32 sweeps");
+    const tdpt::DevProblem *table = (const tdpt::DevProblem *)b->ws;
+    const int *prefix = (const int *)(b->ws + batch_table_bytes(b->cap));
+    for (int64_t r = 0; r < n_rounds; ++r) {
+        for (const auto &g : b->groups) {
+            hipError_t e = tdpt::launch_batch_sweep(b->members[g.first_member]->dp, table + g.first_member,
+                                                    prefix + g.prefix_off, g.count, g.blocks, b->block,
+                                                    g.max_stride, b->stream);
+            if (e != hipSuccess) return hip_fail(e, "launch batch sweep");
+        }
+        hipError_t e = tdpt::launch_batch_swap(table, (int)b->members.size(), b->stream);
+        if (e != hipSuccess) return hip_fail(e, "launch batch swap");
+    }
+    HIP_TRY(hipEventRecord(b->done, b->stream), "hipEventRecord");
+    for (auto *p : b->members) {
+        HIP_TRY(hipStreamWaitEvent(p->stream, b->done, 0), "hipStreamWaitEvent");
+        p->rounds_host += n_rounds;
+    }
+    return TDPT_OK;
+}
+
+void tdpt_batch_destroy(tdpt_batch *b) { delete b; }
+
 }  // extern "C"

@@ -1,0 +1,198 @@
+"""Host drivers over the C ABI: plain, batched and continuously batched runs.
+
+All sampling work runs in the library's kernels; this module only decides
+which problems run when, and measures wall time to the planted ground state.
+
+* plain   — one problem at a time, each until its target is hit or its sweep
+            cap is reached, the next starting when the previous stops;
+* batched — every problem in one batch from t = 0, solved ones retired;
+* serving — requests arrive over time; a request is admitted into the running
+            batch as soon as its device footprint fits the memory budget,
+            joins at the next round boundary, and retires when it hits its
+            target or reaches its cap.  Requests already on the GPU keep
+            running while new ones are admitted (continuous batching).
+
+A result does not depend on the mode: random streams are keyed per problem.
+Hit times: the hit sweep is exact; its wall time is interpolated inside the
+chunk of rounds in which it happened.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+
+import numpy as np
+
+from . import tdpt as T
+
+
+@dataclasses.dataclass
+class Request:
+    """One solve: an instance, its run configuration, a round cap."""
+    name: str
+    instance: "T.Instance"
+    cfg: "T.RunConfig"
+    max_rounds: int
+    arrival: float = 0.0            # seconds after the start of the job
+    # filled in by the drivers
+    start: float | None = None
+    end: float | None = None
+    hit_time: float | None = None   # seconds after arrival, None if censored
+    hit_sweep: int = -1
+    rounds_done: int = 0
+    best_f: int | None = None
+    problem: "T.Problem | None" = None
+    footprint: int = 0
+
+
+def _advance(req: Request, rounds: int, t0: float, t1: float, elapsed_base: float):
+    """Book a chunk of `rounds` rounds that ran from wall time t0 to t1."""
+    q = req.problem.query()
+    prev = req.rounds_done
+    req.rounds_done = q["rounds_done"]
+    req.best_f = q["best_f_q"]
+    if req.hit_time is None and q["first_hit_sweep"] >= 0:
+        mcs = req.cfg.mcs_per_swap
+        hit_round = q["first_hit_sweep"] // mcs
+        frac = (hit_round - prev) / max(req.rounds_done - prev, 1)
+        req.hit_sweep = q["first_hit_sweep"]
+        req.hit_time = (t0 - elapsed_base) + frac * (t1 - t0) - req.arrival
+
+
+def _done(req: Request) -> bool:
+    return req.hit_time is not None or req.rounds_done >= req.max_rounds
+
+
+def run_plain(requests, chunk: int, device="cuda"):
+    """Each request alone, one after another (all present at t = 0)."""
+    import torch
+    base = time.perf_counter()
+    for req in requests:
+        req.problem = T.Problem(req.instance, req.cfg, device=device)
+        torch.cuda.synchronize()
+        req.start = time.perf_counter() - base
+        while not _done(req):
+            n = min(chunk, req.max_rounds - req.rounds_done)
+            t0 = time.perf_counter()
+            req.problem.run(n)
+            torch.cuda.synchronize()
+            _advance(req, n, t0, time.perf_counter(), base)
+        req.end = time.perf_counter() - base
+        req.problem.close()
+        req.problem = None
+    return time.perf_counter() - base
+
+
+def run_batched(requests, chunk: int, device="cuda"):
+    """All requests in one batch from t = 0; solved or capped ones retire."""
+    import torch
+    batch = T.Batch(len(requests), device=device)
+    for req in requests:
+        req.problem = T.Problem(req.instance, req.cfg, device=device)
+    torch.cuda.synchronize()
+    base = time.perf_counter()
+    active = list(requests)
+    for req in active:
+        req.start = 0.0
+    while active:
+        batch.set_members([r.problem for r in active])
+        n = min(chunk, min(r.max_rounds - r.rounds_done for r in active))
+        t0 = time.perf_counter()
+        batch.run(n)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for r in active:
+            _advance(r, n, t0, t1, base)
+        still = []
+        for r in active:
+            if _done(r):
+                r.end = t1 - base
+            else:
+                still.append(r)
+        active = still
+    total = time.perf_counter() - base
+    batch.close()
+    for req in requests:
+        req.problem.close()
+        req.problem = None
+    return total
+
+
+def serve(requests, chunk: int, budget_bytes: int, max_members: int = 4096, device="cuda"):
+    """Continuous batching: requests (sorted by arrival) join the running
+    batch at round boundaries when their workspace fits the budget."""
+    import torch
+    pending = sorted(requests, key=lambda r: r.arrival)
+    for r in pending:
+        r.footprint = T.workspace_bytes(r.instance, r.cfg)
+        if r.footprint > budget_bytes:
+            raise ValueError(f"request {r.name} needs {r.footprint} bytes, budget {budget_bytes}")
+    batch = T.Batch(max_members, device=device)
+    active = []
+    used = 0
+    base = time.perf_counter()
+    while pending or active:
+        now = time.perf_counter() - base
+        changed = False
+        while (pending and pending[0].arrival <= now and used + pending[0].footprint <= budget_bytes
+               and len(active) < max_members):
+            r = pending.pop(0)
+            r.problem = T.Problem(r.instance, r.cfg, device=device)
+            r.start = time.perf_counter() - base
+            used += r.footprint
+            active.append(r)
+            changed = True
+        if not active:
+            # idle until the next arrival
+            time.sleep(max(0.0, min(pending[0].arrival - now, 0.01)))
+            continue
+        if changed:
+            batch.set_members([r.problem for r in active])
+        n = min(chunk, min(r.max_rounds - r.rounds_done for r in active))
+        t0 = time.perf_counter()
+        batch.run(n)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for r in active:
+            _advance(r, n, t0, t1, base)
+        still = []
+        for r in active:
+            if _done(r):
+                r.end = t1 - base
+                used -= r.footprint
+                r.problem.close()
+                r.problem = None
+            else:
+                still.append(r)
+        if len(still) != len(active):
+            active = still
+            batch.set_members([r.problem for r in active])
+    total = time.perf_counter() - base
+    batch.close()
+    return total
+
+
+def summarize(requests, total_seconds: float):
+    """p50/p99 of time to the target (censored requests count as not hit),
+    sweeps to hit, success fraction and spin updates."""
+    hit = [r for r in requests if r.hit_time is not None]
+    times = np.array([r.hit_time for r in hit]) if hit else np.array([])
+    sweeps = np.array([r.hit_sweep for r in hit]) if hit else np.array([])
+    updates = sum(r.rounds_done * r.cfg.mcs_per_swap * r.cfg.replicas * r.instance.n
+                  for r in requests)
+    out = {
+        "requests": len(requests),
+        "hit_fraction": len(hit) / max(len(requests), 1),
+        "tts_p50_s": float(np.percentile(times, 50)) if len(times) else None,
+        "tts_p99_s": float(np.percentile(times, 99)) if len(times) else None,
+        "sweeps_to_hit_p50": float(np.percentile(sweeps, 50)) if len(sweeps) else None,
+        "sweeps_to_hit_p99": float(np.percentile(sweeps, 99)) if len(sweeps) else None,
+        "makespan_s": total_seconds,
+        "spin_updates": int(updates),
+        "spin_updates_per_s": updates / total_seconds if total_seconds > 0 else None,
+    }
+    lat = [r.end - r.arrival for r in requests if r.end is not None]
+    if lat:
+        out["latency_p50_s"] = float(np.percentile(lat, 50))
+        out["latency_p99_s"] = float(np.percentile(lat, 99))
+    return out

@@ -25,6 +25,8 @@ EXPORTED = [
     "tdpt_problem_read_best", "tdpt_problem_read_counters", "tdpt_problem_read_trace",
     "tdpt_problem_save", "tdpt_problem_load", "tdpt_problem_destroy", "tdpt_last_error",
     "tdpt_problem_set_timing", "tdpt_problem_read_timing",
+    "tdpt_batch_workspace_bytes", "tdpt_batch_create", "tdpt_batch_set_members",
+    "tdpt_batch_run", "tdpt_batch_destroy",
 ]
 
 
@@ -86,6 +88,10 @@ def load_library():
         "tdpt_problem_load": [P, P, SZ],
         "tdpt_problem_set_timing": [P, I32],
         "tdpt_problem_read_timing": [P, P, P, P],
+        "tdpt_batch_workspace_bytes": [I32, P],
+        "tdpt_batch_create": [I32, P, SZ, P, P],
+        "tdpt_batch_set_members": [P, P, I32],
+        "tdpt_batch_run": [P, I64],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -95,6 +101,8 @@ def load_library():
     lib.tdpt_instance_destroy.restype = None
     lib.tdpt_problem_destroy.argtypes = [P]
     lib.tdpt_problem_destroy.restype = None
+    lib.tdpt_batch_destroy.argtypes = [P]
+    lib.tdpt_batch_destroy.restype = None
     lib.tdpt_last_error.argtypes = []
     lib.tdpt_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -285,6 +293,43 @@ class Problem:
         h = getattr(self, "_h", None)
         if h is not None and h.value and _lib is not None:
             _lib.tdpt_problem_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Batch:
+    """Advance many problems together: one sweep launch and one swap launch
+    per round for all members."""
+
+    def __init__(self, max_members: int, device="cuda", stream=None):
+        import torch
+        lib = load_library()
+        size = ctypes.c_size_t()
+        _check(lib.tdpt_batch_workspace_bytes(int(max_members), ctypes.byref(size)))
+        self.device = torch.device(device)
+        self.workspace = torch.empty(size.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(lib.tdpt_batch_create(int(max_members), ctypes.c_void_p(self.workspace.data_ptr()),
+                                     size.value, ctypes.c_void_p(self.stream.cuda_stream),
+                                     ctypes.byref(h)))
+        self._h = h
+        self.members = []
+
+    def set_members(self, problems):
+        self.members = list(problems)
+        arr = (ctypes.c_void_p * max(len(self.members), 1))(*[p._h.value for p in self.members])
+        _check(_lib.tdpt_batch_set_members(self._h, arr, len(self.members)))
+
+    def run(self, n_rounds: int):
+        _check(_lib.tdpt_batch_run(self._h, int(n_rounds)))
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.tdpt_batch_destroy(h)
         self._h = None
 
     def __del__(self):

@@ -1,0 +1,127 @@
+"""Batched and continuously batched runs give each problem exactly the
+results it gets alone (and the oracle's)."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from synth.configs import batched_member, wishart_small
+from synth.instances import instance_from_logical, q12
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2506_14781_amd as T
+    return T
+
+
+def _members():
+    """Problems of different sizes, grids, sweep ratios and layouts."""
+    out = []
+    w = wishart_small()
+    out.append(("wishart-N12", w.instance, w.beta, w.p_q, 5, 11))
+    for N, seed in [(64, 3), (100, 5)]:
+        m = batched_member(N, 0.8, seed)
+        out.append((m.name, m.instance, m.beta[:8], m.p_q[:4], 3, seed))
+    rng = np.random.default_rng(8)
+    A = np.triu(rng.normal(0, 10.0, size=(6, 6)), 1)
+    Jq = q12(A + A.T)
+    np.fill_diagonal(Jq, 0)
+    wide = instance_from_logical(Jq, degree_cap=3)
+    out.append(("wide", wide, np.array([0.001, 0.003]), q12([0.0, 40.0]), 2, 1))
+    return out
+
+
+def _outputs(P):
+    f, g = P.energies()
+    return (P.states(), f, g) + tuple(P.counters()) + tuple(P.trace()) + (P.best()[0],
+                                                                          tuple(P.query().values())[:5])
+
+
+def _same(a, b):
+    assert len(a) == len(b)
+    for x, y in zip(a, b):
+        if isinstance(x, tuple):
+            assert x == y
+        else:
+            assert np.array_equal(x, y)
+
+
+def test_batch_equals_alone_and_oracle(T):
+    rounds = 24
+    specs = _members()
+    alone, probs = [], []
+    for name, inst, beta, p_q, mcs, seed in specs:
+        _say(f"[batch] alone {name}")
+        cfg = T.RunConfig(beta, p_q, mcs_per_swap=mcs, seed=seed, trace_cap=rounds)
+        P = T.Problem(T.Instance.from_synth(inst), cfg)
+        P.run(rounds)
+        alone.append(_outputs(P))
+        probs.append(T.Problem(T.Instance.from_synth(inst), cfg))
+    _say("[batch] batched run with a membership change")
+    B = T.Batch(8)
+    B.set_members(probs)
+    B.run(10)
+    # the last member sits out 4 rounds, then rejoins
+    B.set_members(probs[:-1])
+    B.run(4)
+    B.set_members(probs)
+    B.run(10)
+    B.set_members([probs[-1]])
+    B.run(4)
+    for (name, *_), a, P in zip(specs, alone, probs):
+        _say(f"[batch] compare {name}")
+        _same(a, _outputs(P))
+    # one member against the oracle directly
+    name, inst, beta, p_q, mcs, seed = specs[1]
+    o = O.run(inst, beta, p_q, mcs_per_swap=mcs, n_rounds=rounds, seed=seed, trace=True)
+    assert np.array_equal(probs[1].states(), o["states"])
+    f, g = probs[1].energies()
+    assert np.array_equal(f, o["f"]) and np.array_equal(g, o["g"])
+
+
+def test_serving_results_equal_alone(T):
+    """Requests arriving over time, admitted under a memory budget, retired
+    at their caps: every request's final state is the one it reaches alone."""
+    from paper_2506_14781_amd.serve import Request, serve
+    specs = _members()[:3]
+    reqs, alone = [], []
+    for k, (name, inst, beta, p_q, mcs, seed) in enumerate(specs):
+        cfg = T.RunConfig(beta, p_q, mcs_per_swap=mcs, seed=seed)
+        inst_t = T.Instance.from_synth(inst)
+        cap = 6 + 5 * k
+        P = T.Problem(inst_t, cfg)
+        P.run(cap)
+        alone.append(P.states())
+        reqs.append(Request(name=name, instance=inst_t, cfg=cfg, max_rounds=cap,
+                            arrival=0.002 * k))
+    budget = max(T.workspace_bytes(r.instance, r.cfg) for r in reqs) * 2
+    keep = {}
+
+    orig_close = T.Problem.close
+
+    def grab(self):
+        for r in reqs:
+            if r.problem is self and r.name not in keep:
+                keep[r.name] = self.states()
+        orig_close(self)
+    T.Problem.close = grab
+    try:
+        serve(reqs, chunk=4, budget_bytes=budget)
+    finally:
+        T.Problem.close = orig_close
+    for r, a in zip(reqs, alone):
+        assert r.rounds_done == r.max_rounds
+        assert np.array_equal(keep[r.name], a), r.name
