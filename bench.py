@@ -76,9 +76,12 @@ def cpu_baseline(w, rounds: int) -> dict:
             "seconds": round(dt, 3)}
 
 
-def _requests(T, members, cap_sweeps, f_target_from_planted=True):
-    """Requests of the batched / serving modes: target = planted energy,
-    computed on the GPU from the planted state itself (zero rounds)."""
+def _requests(T, members, cap_sweeps, rho0=0.0):
+    """Requests of the batched / serving modes.  Target: the planted
+    ground-state energy (computed on the GPU from the planted state itself,
+    zero rounds) plus rho0 * N in energy units, i.e. residual energy per
+    logical spin rho_E = (E - E_gs) / N <= rho0 at the bottom-right replica
+    (rho0 = 0: the planted ground state itself)."""
     from paper_2506_14781_amd.serve import Request
     reqs = []
     for w in members:
@@ -88,7 +91,8 @@ def _requests(T, members, cap_sweeps, f_target_from_planted=True):
                                             s0=planted))
         f_gs = int(probe.energies()[0][0])
         probe.close()
-        cfg = T.RunConfig(w.beta, w.p_q, mcs_per_swap=w.mcs_per_swap, seed=w.seed, f_target=f_gs)
+        target = f_gs + int(round(rho0 * w.instance.N * 4096))
+        cfg = T.RunConfig(w.beta, w.p_q, mcs_per_swap=w.mcs_per_swap, seed=w.seed, f_target=target)
         reqs.append(Request(name=w.name, instance=inst, cfg=cfg,
                             max_rounds=cap_sweeps // w.mcs_per_swap))
     return reqs
@@ -103,7 +107,7 @@ def bench_batched(args):
     from paper_2506_14781_amd.serve import run_batched, run_plain, summarize
     from synth.configs import batched_member, batched_sizes
     members = [batched_member(N, a, s) for N, a, s in batched_sizes(args.count)]
-    reqs_b = _requests(T, members, args.cap_sweeps)
+    reqs_b = _requests(T, members, args.cap_sweeps, args.rho0)
     reqs_p = [copy.copy(r) for r in reqs_b]
     print(f"[bench] batched family: {len(members)} instances, cap {args.cap_sweeps} sweeps",
           file=sys.stderr, flush=True)
@@ -114,7 +118,8 @@ def bench_batched(args):
     sp = summarize(reqs_p, tp)
     for a, b in zip(reqs_b, reqs_p):
         assert a.hit_sweep == b.hit_sweep, "sweeps to hit differ between modes"
-    out = {"metric": "time-to-planted-GS p50 (batched)", "value": sb["tts_p50_s"], "unit": "s",
+    tgt = "planted-GS" if args.rho0 == 0 else f"rho_E<={args.rho0}"
+    out = {"metric": f"time-to-{tgt} p50 (batched)", "value": sb["tts_p50_s"], "unit": "s",
            "higher_is_better": False, "n_gpus": 1,
            "data": "synthetic (seeded planted Wishart, copy-chain sparsified)",
            "config": {"workload": f"batched family, {len(members)} instances, 16x8 grids, "
@@ -137,12 +142,13 @@ def bench_serving(args):
         members.append(serving_member(N, alpha, k, args.cap_sweeps))
         t += rng.exponential(1.0 / args.rate)
         arrivals.append(t)
-    reqs = _requests(T, members, args.cap_sweeps)
+    reqs = _requests(T, members, args.cap_sweeps, args.rho0)
     for r, a in zip(reqs, arrivals):
         r.arrival = a
     total = serve(reqs, chunk=args.chunk, budget_bytes=int(args.budget_gb * 2**30))
     s = summarize(reqs, total)
-    out = {"metric": "time-to-planted-GS p50 (serving)", "value": s["tts_p50_s"], "unit": "s",
+    tgt = "planted-GS" if args.rho0 == 0 else f"rho_E<={args.rho0}"
+    out = {"metric": f"time-to-{tgt} p50 (serving)", "value": s["tts_p50_s"], "unit": "s",
            "higher_is_better": False, "n_gpus": 1,
            "data": "synthetic (seeded planted Wishart, Poisson arrivals)",
            "config": {"workload": f"serving, {args.count} requests, rate {args.rate}/s, "
@@ -167,6 +173,8 @@ def main():
     ap.add_argument("--rate", type=float, default=50.0, help="serving arrivals per second")
     ap.add_argument("--max-n", type=int, default=1024, help="largest logical size when serving")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving HBM budget")
+    ap.add_argument("--rho0", type=float, default=0.0,
+                    help="target residual energy per logical spin (0: the planted ground state)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -11,6 +11,7 @@ constexpr int kMaxColors = 32;
 constexpr int kMaxBlock = 1024;   // threads per sweep workgroup, at most
 constexpr int kSmallBlock = 256;  // threads of the swap / energy kernels
 constexpr int kRing = 8;          // rounds of partner mailboxes kept per position
+constexpr int kBitSlots = 4;      // replicas per workgroup in the bit-packed layout
 
 // Header words of a problem's device state (int64 each).
 enum HdrWord {
@@ -36,6 +37,13 @@ constexpr int64_t kKeyOffset = (int64_t)1 << 30;
 //   nbj[k2][n_pad]  their couplings packed as int16 pairs
 //   chp[n_pad]      the two copy neighbours packed as 16+16 bits
 // Wide structure: nb_idx / nb_J [wd][n_pad] int32, ch_idx [2][n_pad] int32.
+// Bit-packed layout (replicas too large for an int8 copy in LDS): spins are
+// bits (1 = +1) in LDS, kBitSlots replicas interleaved by 32-bit word (word w
+// of replica r at byte 16 w + 4 r); each colour class starts on a 32-bit
+// boundary of the bit numbering (bit_start[c]), so spin rho of class c sits
+// at bit rho - cls_start[c] + bit_start[c].  Structure in bit positions:
+//   nb_pos / nb_J [wd][n_pad] (missing neighbours: position 0, coupling 0),
+//   ch_pos [2][n_pad] (-1: no copy neighbour), h0 [n_pad] = b - sum_k J_k.
 struct DevProblem {
     // structure (immutable)
     int32_t n_pad;      // padded spin count
@@ -45,6 +53,12 @@ struct DevProblem {
     int32_t narrow;
     int32_t has_bias;   // any nonzero field
     int32_t block;      // threads per sweep workgroup
+    int32_t bits;       // bit-packed layout
+    int32_t n_words;    // 32-bit words per replica in the bit-packed layout
+    int32_t bit_start[kMaxColors + 1];
+    const int32_t *nb_pos; // bit-packed
+    const int32_t *ch_pos; // bit-packed
+    const int32_t *h0;     // bit-packed
     int32_t cls_start[kMaxColors + 1];
     int32_t cls_live[kMaxColors];
     const uint32_t *nbi;   // narrow
@@ -97,5 +111,9 @@ hipError_t launch_finalize(const DevProblem &p, int64_t n_rounds, hipStream_t s)
 hipError_t launch_batch_sweep(const DevProblem &p, const DevProblem *table, const int *first_block,
                               int count, int blocks, int block, size_t max_stride, hipStream_t s);
 hipError_t launch_batch_swap(const DevProblem *table, int count, hipStream_t s);
+// Bit-packed layout: one round of every slot (ceil(R / kBitSlots) blocks).
+hipError_t launch_sweep_bits(const DevProblem &p, hipStream_t s);
+hipError_t launch_batch_sweep_bits(const DevProblem &p, const DevProblem *table, const int *first_block,
+                                   int count, int blocks, int block, int max_words, hipStream_t s);
 
 }  // namespace tdpt

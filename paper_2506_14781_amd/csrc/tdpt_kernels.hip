@@ -100,6 +100,14 @@ struct Rsrc {
 __device__ __forceinline__ Rsrc make_rsrc(const DevProblem &P)
 {
     Rsrc r;
+    if (P.bits) {
+        const int bytes = P.wd * P.n_pad * 4;
+        r.a = rsrc(P.nb_pos, bytes);
+        r.b = rsrc(P.nb_J, bytes);
+        r.ch = rsrc(P.ch_pos, P.n_pad * 8);
+        r.bias = rsrc(P.h0, P.n_pad * 4);
+        return r;
+    }
     if (P.narrow) {
         const int bytes = (P.wd / 2) * P.n_pad * 4;
         r.a = rsrc(P.nbi, bytes);
@@ -139,20 +147,42 @@ __device__ __forceinline__ SlotParams slot_params(const DevProblem &P, int pos)
     return sp;
 }
 
+// Structure of one quad (4 consecutive colour-major spins).  Never changes,
+// so a copy loaded ahead of time is valid whenever its quad index matches.
+template <bool NARROW, int WD>
+struct QuadS {
+    static constexpr int K = NARROW ? WD / 2 : WD;
+    v4i a[K];    // narrow: index pairs; wide: indices
+    v4i b[K];    // narrow: coupling pairs; wide: couplings
+    v4i c0, c1;  // narrow: copy pairs in c0; wide: two copy rows
+};
+
+template <bool NARROW, int WD>
+__device__ __forceinline__ void load_quad(const DevProblem &P, const Rsrc &Rs, int q, QuadS<NARROW, WD> &Q)
+{
+    const int voff = q * 16;
+    const int row = P.n_pad * 4;
+#pragma unroll
+    for (int k = 0; k < QuadS<NARROW, WD>::K; ++k) {
+        Q.a[k] = bload(Rs.a, voff, k * row);
+        Q.b[k] = bload(Rs.b, voff, k * row);
+    }
+    Q.c0 = bload(Rs.ch, voff, 0);
+    if constexpr (!NARROW) Q.c1 = bload(Rs.ch, voff, row);
+}
+
 // Heat-bath update of the 4 spins of quad q (LDS bytes s).  live: bit j set
 // when spin 4q+j is a real spin (not class padding).  NARROW instances keep
 // every field and energy change below 2^22, so the 16-bit dot products and
 // 24-bit multiplies are exact.
 template <bool NARROW, int WD>
-__device__ __forceinline__ void update_quad(const DevProblem &P, const Rsrc &Rs, int8_t *s, int q,
-                                            unsigned live, uint32_t t, const SlotParams &sp,
-                                            int &dfa, int &dga)
+__device__ __forceinline__ void compute_quad(const DevProblem &P, const Rsrc &Rs, int8_t *s, int q,
+                                             const QuadS<NARROW, WD> &Q, unsigned live, uint32_t t,
+                                             const SlotParams &sp, int &dfa, int &dga)
 {
-    const int voff = q * 16;
-    const int row = P.n_pad * 4;
     int hp[4], cs[4];
     if (P.has_bias) {
-        const v4i bb = bload(Rs.bias, voff, 0);
+        const v4i bb = bload(Rs.bias, q * 16, 0);
 #pragma unroll
         for (int j = 0; j < 4; ++j) hp[j] = bb[j];
     } else {
@@ -162,11 +192,9 @@ __device__ __forceinline__ void update_quad(const DevProblem &P, const Rsrc &Rs,
     if constexpr (NARROW) {
 #pragma unroll
         for (int k2 = 0; k2 < WD / 2; ++k2) {
-            const v4i ia = bload(Rs.a, voff, k2 * row);
-            const v4i jb = bload(Rs.b, voff, k2 * row);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int iw = ia[j], jw = jb[j];  // plain ints: bit-cast a value, not a vector lane
+                const int iw = Q.a[k2][j], jw = Q.b[k2][j];  // plain ints: bit-cast a value, not a vector lane
                 v2s sv, jv;
                 sv.x = (short)s[iw & 0xffff];
                 sv.y = (short)s[(unsigned)iw >> 16];
@@ -175,21 +203,18 @@ __device__ __forceinline__ void update_quad(const DevProblem &P, const Rsrc &Rs,
                 hp[j] = __builtin_amdgcn_sdot2(jv, sv, hp[j], false);
             }
         }
-        const v4i c = bload(Rs.ch, voff, 0);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) cs[j] = (int)s[c[j] & 0xffff] + (int)s[(unsigned)c[j] >> 16];
+        for (int j = 0; j < 4; ++j) {
+            const int c = Q.c0[j];
+            cs[j] = (int)s[c & 0xffff] + (int)s[(unsigned)c >> 16];
+        }
     } else {
 #pragma unroll
-        for (int k = 0; k < WD; ++k) {
-            const v4i ia = bload(Rs.a, voff, k * row);
-            const v4i jb = bload(Rs.b, voff, k * row);
+        for (int k = 0; k < WD; ++k)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) hp[j] += jb[j] * (int)s[ia[j]];
-        }
-        const v4i c0 = bload(Rs.ch, voff, 0);
-        const v4i c1 = bload(Rs.ch, voff, row);
+            for (int j = 0; j < 4; ++j) hp[j] += Q.b[k][j] * (int)s[Q.a[k][j]];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) cs[j] = (int)s[c0[j]] + (int)s[c1[j]];
+        for (int j = 0; j < 4; ++j) cs[j] = (int)s[Q.c0[j]] + (int)s[Q.c1[j]];
     }
 
     uint32_t u[4] = {(uint32_t)q, t, sp.pos, 0u};
@@ -237,13 +262,18 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v)
 
 // All sweeps of one round of the slot held at LDS address 0; returns the
 // change of f and g summed over the block into red[0..1] (LDS scratch of
-// 2 * (blockDim / 64) int64).
+// 2 * (blockDim / 64) int64).  A lane walks its quads q0 + tid, q0 + tid +
+// blockDim, .. of every class; while it updates one quad the structure of
+// its next quad (possibly in the next class, across the barrier) is already
+// on its way.
 template <bool NARROW, int WD>
 __device__ __forceinline__ void sweep_round(const DevProblem &P, const Rsrc &Rs, int8_t *s,
                                             const SlotParams &sp, int64_t n_round, int64_t *red)
 {
     const int tid = threadIdx.x, nthr = blockDim.x;
     int64_t df = 0, dg = 0;
+    QuadS<NARROW, WD> pre;
+    int pre_q = -1;
     for (int k = 0; k < P.mcs; ++k) {
         const uint32_t t = (uint32_t)((n_round - 1) * P.mcs + k);
         for (int c = 0; c < P.n_colors; ++c) {
@@ -251,9 +281,21 @@ __device__ __forceinline__ void sweep_round(const DevProblem &P, const Rsrc &Rs,
             const int live_end = P.cls_live[c];
             int dfa = 0, dga = 0;
             for (int q = q0 + tid; q < q1; q += nthr) {
+                QuadS<NARROW, WD> cur;
+                if (pre_q == q) cur = pre;
+                else load_quad<NARROW, WD>(P, Rs, q, cur);
+                int qn = q + nthr;
+                if (qn >= q1) {
+                    const bool last = (c + 1 == P.n_colors) && (k + 1 == P.mcs);
+                    const int cn = (c + 1 < P.n_colors) ? c + 1 : 0;
+                    qn = (P.cls_start[cn] >> 2) + tid;
+                    if (last || qn >= (P.cls_start[cn + 1] >> 2)) qn = -1;
+                }
+                if (qn >= 0) load_quad<NARROW, WD>(P, Rs, qn, pre);
+                pre_q = qn;
                 const int rem = live_end - q * 4;
                 const unsigned live = rem >= 4 ? 15u : ((1u << rem) - 1u);
-                update_quad<NARROW, WD>(P, Rs, s, q, live, t, sp, dfa, dga);
+                compute_quad<NARROW, WD>(P, Rs, s, q, cur, live, t, sp, dfa, dga);
             }
             df += dfa;
             dg += dga;
@@ -609,6 +651,195 @@ __global__ __launch_bounds__(kSmallBlock) void k_finalize(DevProblem P, int64_t 
     if (take >= 0) copy_bytes16(P.best_state, P.slot_best + (size_t)take * P.stride, P.stride);
 }
 
+// ------------------------------------------------------ bit-packed layout
+// For replicas too large for an int8 copy in LDS.  A workgroup holds
+// kBitSlots replicas as bits, interleaved by word (uint32 4 w + r is word w
+// of replica r), so one 16-byte LDS read returns a neighbour's word of all
+// of them and every structure load serves kBitSlots updates.  With t the
+// spin's bit as 0 / -1, sum_k J_k s_k = (sum_k J_k (2 b_k - 1)) =
+// -sum_k J_k + 2 sum_k (J_k & t_k); h0 = b - sum_k J_k is precomputed.
+__device__ __forceinline__ int bit_sign(uint32_t w, int pos)  // +1 / -1 of bit pos & 31
+{
+    return ((w >> (pos & 31)) & 1u) ? 1 : -1;
+}
+
+template <int WD>
+__device__ __forceinline__ void bits_update_quad(const DevProblem &P, const Rsrc &Rs, uint32_t *W, int q,
+                                                 int c, unsigned live, uint32_t t,
+                                                 const SlotParams (&sp)[kBitSlots], int ns,
+                                                 int (&dfa)[kBitSlots], int (&dga)[kBitSlots])
+{
+    const int voff = q * 16;
+    const int row = P.n_pad * 4;
+    int acc[4][kBitSlots], cs[4][kBitSlots];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < kBitSlots; ++r) { acc[j][r] = 0; cs[j][r] = 0; }
+#pragma unroll
+    for (int k = 0; k < WD; ++k) {
+        const v4i pk = bload(Rs.a, voff, k * row);
+        const v4i jk = bload(Rs.b, voff, k * row);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int pos = pk[j];
+            const uint4 nw = *reinterpret_cast<const uint4 *>(W + 4 * (pos >> 5));
+            const uint32_t w4[4] = {nw.x, nw.y, nw.z, nw.w};
+#pragma unroll
+            for (int r = 0; r < kBitSlots; ++r)
+                acc[j][r] += jk[j] & __builtin_amdgcn_sbfe(w4[r], pos & 31, 1);
+        }
+    }
+    const v4i c0 = bload(Rs.ch, voff, 0);
+    const v4i c1 = bload(Rs.ch, voff, row);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (c0[j] >= 0) {
+            const uint4 nw = *reinterpret_cast<const uint4 *>(W + 4 * (c0[j] >> 5));
+            const uint32_t w4[4] = {nw.x, nw.y, nw.z, nw.w};
+#pragma unroll
+            for (int r = 0; r < kBitSlots; ++r) cs[j][r] += bit_sign(w4[r], c0[j]);
+        }
+        if (c1[j] >= 0) {
+            const uint4 nw = *reinterpret_cast<const uint4 *>(W + 4 * (c1[j] >> 5));
+            const uint32_t w4[4] = {nw.x, nw.y, nw.z, nw.w};
+#pragma unroll
+            for (int r = 0; r < kBitSlots; ++r) cs[j][r] += bit_sign(w4[r], c1[j]);
+        }
+    }
+    const v4i h0 = bload(Rs.bias, voff, 0);
+    const int bpos = q * 4 - P.cls_start[c] + P.bit_start[c];
+    const int wq = bpos >> 5, off = bpos & 31;
+    const uint4 ow = *reinterpret_cast<const uint4 *>(W + 4 * wq);
+    const uint32_t o4[4] = {ow.x, ow.y, ow.z, ow.w};
+#pragma unroll
+    for (int r = 0; r < kBitSlots; ++r) {
+        if (r >= ns) break;
+        uint32_t u[4] = {(uint32_t)q, t, sp[r].pos, 0u};
+        philox10(u[0], u[1], u[2], u[3], P.key0, P.key1);
+        uint32_t nbits = (o4[r] >> off) & 15u;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (!(live & (1u << j))) continue;
+            const int hp = h0[j] + 2 * acc[j][r];
+            const int h = sp[r].twoP * cs[j][r] + hp;
+            bool a;
+            int sn = heat_bath_fast(h, sp[r].cb, u[j], a);
+            if (__builtin_expect(a, 0)) sn = heat_bath_exact(sp[r].beta, h, u[j]);
+            const int so = ((o4[r] >> (off + j)) & 1u) ? 1 : -1;
+            const int ds = sn - so;
+            dfa[r] -= ds * hp;
+            dga[r] -= 2 * ds * cs[j][r];
+            nbits = sn > 0 ? (nbits | (1u << j)) : (nbits & ~(1u << j));
+        }
+        atomicAnd(&W[4 * wq + r], ~(15u << off));
+        atomicOr(&W[4 * wq + r], nbits << off);
+    }
+}
+
+// One round of up to kBitSlots slots (slot0 ..): unpack the int8 states into
+// LDS bits, mcs sweeps, pack them back.
+template <int WD>
+__device__ __forceinline__ void round_sweep_bits_body(const DevProblem &P, int slot0, int8_t *lds)
+{
+    uint32_t *W = reinterpret_cast<uint32_t *>(lds);
+    int64_t *red = reinterpret_cast<int64_t *>(lds + (size_t)P.n_words * 16);
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int ns = min(kBitSlots, P.R - slot0);
+    // unpack: word w of slot r from the spins whose bit positions it holds
+    for (int i = tid; i < P.n_words * kBitSlots; i += nthr) {
+        const int w = i >> 2, r = i & 3;
+        uint32_t bits = 0;
+        if (r < ns) {
+            int c = 0;
+            while (c + 1 < P.n_colors && P.bit_start[c + 1] <= 32 * w) ++c;
+            const int8_t *st = P.states + (size_t)(slot0 + r) * P.stride;
+            const int live = P.cls_live[c] - P.cls_start[c];
+            for (int b = 0; b < 32; ++b) {
+                const int k = 32 * w + b - P.bit_start[c];
+                if (k >= 0 && k < live && st[P.cls_start[c] + k] > 0) bits |= 1u << b;
+            }
+        }
+        W[i] = bits;
+    }
+    SlotParams sp[kBitSlots];
+#pragma unroll
+    for (int r = 0; r < kBitSlots; ++r) sp[r] = slot_params(P, r < ns ? P.slot_pos[slot0 + r] : 0);
+    const Rsrc Rs = make_rsrc(P);
+    const int64_t n_round = P.hdr[kHdrRounds] + 1;
+    __syncthreads();
+    int64_t df[kBitSlots], dg[kBitSlots];
+#pragma unroll
+    for (int r = 0; r < kBitSlots; ++r) { df[r] = 0; dg[r] = 0; }
+    for (int k = 0; k < P.mcs; ++k) {
+        const uint32_t t = (uint32_t)((n_round - 1) * P.mcs + k);
+        for (int c = 0; c < P.n_colors; ++c) {
+            const int q0 = P.cls_start[c] >> 2, q1 = P.cls_start[c + 1] >> 2;
+            const int live_end = P.cls_live[c];
+            int dfa[kBitSlots], dga[kBitSlots];
+#pragma unroll
+            for (int r = 0; r < kBitSlots; ++r) { dfa[r] = 0; dga[r] = 0; }
+            for (int q = q0 + tid; q < q1; q += nthr) {
+                const int rem = live_end - q * 4;
+                const unsigned live = rem >= 4 ? 15u : ((1u << rem) - 1u);
+                bits_update_quad<WD>(P, Rs, W, q, c, live, t, sp, ns, dfa, dga);
+            }
+#pragma unroll
+            for (int r = 0; r < kBitSlots; ++r) { df[r] += dfa[r]; dg[r] += dga[r]; }
+            __syncthreads();
+        }
+    }
+    const int wave = tid >> 6, nw = nthr >> 6;
+#pragma unroll
+    for (int r = 0; r < kBitSlots; ++r) {
+        const int64_t a = wave_sum64(df[r]), b = wave_sum64(dg[r]);
+        if ((tid & 63) == 0) { red[2 * (wave * kBitSlots + r)] = a; red[2 * (wave * kBitSlots + r) + 1] = b; }
+    }
+    __syncthreads();
+    if (tid < ns) {
+        int64_t a = 0, b = 0;
+        for (int w = 0; w < nw; ++w) { a += red[2 * (w * kBitSlots + tid)]; b += red[2 * (w * kBitSlots + tid) + 1]; }
+        P.f[slot0 + tid] += a;
+        P.g[slot0 + tid] += b;
+    }
+    // pack back: live spins only (class padding stays 0 in the int8 copy)
+    for (int i = tid; i < P.n_words * kBitSlots; i += nthr) {
+        const int w = i >> 2, r = i & 3;
+        if (r >= ns) continue;
+        int c = 0;
+        while (c + 1 < P.n_colors && P.bit_start[c + 1] <= 32 * w) ++c;
+        int8_t *st = P.states + (size_t)(slot0 + r) * P.stride;
+        const int live = P.cls_live[c] - P.cls_start[c];
+        const uint32_t bits = W[i];
+        for (int b = 0; b < 32; ++b) {
+            const int k = 32 * w + b - P.bit_start[c];
+            if (k >= 0 && k < live) st[P.cls_start[c] + k] = ((bits >> b) & 1u) ? 1 : -1;
+        }
+    }
+}
+
+template <int WD>
+__global__ __launch_bounds__(kMaxBlock) void k_round_sweep_bits(DevProblem P)
+{
+    extern __shared__ __align__(16) int8_t lds[];
+    round_sweep_bits_body<WD>(P, blockIdx.x * kBitSlots, lds);
+}
+
+template <int WD>
+__global__ __launch_bounds__(kMaxBlock) void k_batch_sweep_bits(const DevProblem *__restrict__ table,
+                                                              const int *__restrict__ first_block, int count)
+{
+    extern __shared__ __align__(16) int8_t lds[];
+    const int b = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first_block[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    round_sweep_bits_body<WD>(table[lo], (b - first_block[lo]) * kBitSlots, lds);
+}
+
 // ---------------------------------------------------- initial states, f, g
 // Initial spin v at position p when the caller gives none: Philox counter
 // (v >> 2, 0, p, 3), output word v & 3, +1 iff its top bit is set.
@@ -787,6 +1018,55 @@ hipError_t launch_batch_sweep(const DevProblem &p, const DevProblem *table, cons
                               int count, int blocks, int block, size_t max_stride, hipStream_t s)
 {
     TDPT_DISPATCH(batch_sweep_t, p, table, first_block, count, blocks, block, max_stride, s)
+}
+
+static size_t bits_lds(int n_words)
+{
+    return (size_t)n_words * 16 + 8 * 2 * kBitSlots * (kMaxBlock / 64) + 16;
+}
+
+template <bool NARROW, int WD>
+static hipError_t sweep_bits_t(const DevProblem &p, hipStream_t s)
+{
+    const size_t lds = bits_lds(p.n_words);
+    hipError_t e = allow_lds(k_round_sweep_bits<WD>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_round_sweep_bits<WD>), dim3((p.R + kBitSlots - 1) / kBitSlots), dim3(p.block), lds,
+                       s, p);
+    return hipGetLastError();
+}
+
+template <bool NARROW, int WD>
+static hipError_t batch_sweep_bits_t(const DevProblem &p, const DevProblem *table, const int *first_block,
+                                     int count, int blocks, int block, int max_words, hipStream_t s)
+{
+    (void)p;
+    const size_t lds = bits_lds(max_words);
+    hipError_t e = allow_lds(k_batch_sweep_bits<WD>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_batch_sweep_bits<WD>), dim3(blocks), dim3(block), lds, s, table, first_block, count);
+    return hipGetLastError();
+}
+
+#define TDPT_DISPATCH_BITS(FN, ...)                 \
+    switch (p.wd) {                                  \
+    case 1: return FN<false, 1>(__VA_ARGS__);        \
+    case 2: return FN<false, 2>(__VA_ARGS__);        \
+    case 3: return FN<false, 3>(__VA_ARGS__);        \
+    case 4: return FN<false, 4>(__VA_ARGS__);        \
+    case 5: return FN<false, 5>(__VA_ARGS__);        \
+    case 6: return FN<false, 6>(__VA_ARGS__);        \
+    case 7: return FN<false, 7>(__VA_ARGS__);        \
+    case 8: return FN<false, 8>(__VA_ARGS__);        \
+    default: return hipErrorInvalidValue;            \
+    }
+
+hipError_t launch_sweep_bits(const DevProblem &p, hipStream_t s) { TDPT_DISPATCH_BITS(sweep_bits_t, p, s) }
+
+hipError_t launch_batch_sweep_bits(const DevProblem &p, const DevProblem *table, const int *first_block,
+                                   int count, int blocks, int block, int max_words, hipStream_t s)
+{
+    TDPT_DISPATCH_BITS(batch_sweep_bits_t, p, table, first_block, count, blocks, block, max_words, s)
 }
 
 hipError_t launch_batch_swap(const DevProblem *table, int count, hipStream_t s)

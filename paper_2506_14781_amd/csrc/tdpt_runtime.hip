@@ -101,9 +101,22 @@ namespace {
 struct Layout {
     size_t hdr, states, f, g, slot_pos, pos_slot, p_att, p_acc, b_att, b_acc, best, trace_f,
         trace_g, mut_end, mbox, slot_key, slot_best, hit_min, scratch_end;
-    size_t beta, p_q, nbi, nbj, chp, nb_idx, nb_J, ch_idx, bias, orig, total;
+    size_t beta, p_q, nbi, nbj, chp, nb_idx, nb_J, ch_idx, bias, orig, nb_pos, ch_pos, h0, total;
     int32_t stride, wd;
 };
+
+// Replicas whose int8 copy exceeds this many bytes of LDS use the bit-packed
+// layout (kBitSlots replicas per workgroup as bits).
+constexpr size_t kInt8StrideMax = 48 * 1024;
+
+bool use_bits(const tdpt_instance *in)
+{
+    if (const char *e = getenv("TDPT_LAYOUT")) {
+        if (!strcmp(e, "bits")) return true;
+        if (!strcmp(e, "bytes")) return false;
+    }
+    return align_up((size_t)in->n_pad + 1, 16) > kInt8StrideMax;
+}
 
 // The packed structure (16-bit indices and coupling pairs) and the 16/24-bit
 // arithmetic of the sweep need indices and couplings that fit 16 bits and
@@ -111,7 +124,7 @@ struct Layout {
 bool use_narrow(const tdpt_instance *in, const tdpt_run_cfg *cfg)
 {
     const int64_t pmax = cfg->p_q[cfg->n_p - 1];
-    return in->narrow && in->max_field + 4 * pmax < ((int64_t)1 << 22);
+    return !use_bits(in) && in->narrow && in->max_field + 4 * pmax < ((int64_t)1 << 22);
 }
 
 Layout make_layout(const tdpt_instance *in, int32_t I, int32_t J, int64_t trace_cap, bool narrow)
@@ -160,6 +173,11 @@ Layout make_layout(const tdpt_instance *in, int32_t I, int32_t J, int64_t trace_
         L.nb_J = take(ell);
         L.ch_idx = take((size_t)2 * in->n_pad * 4);
         L.nbi = L.nbj = L.chp = 0;
+        if (use_bits(in)) {
+            L.nb_pos = take(ell);
+            L.ch_pos = take((size_t)2 * in->n_pad * 4);
+            L.h0 = take((size_t)in->n_pad * 4);
+        }
     }
     L.bias = take((size_t)in->n_pad * 4);
     L.orig = take((size_t)in->n_pad * 4);
@@ -417,7 +435,15 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev),
             "hipDeviceGetAttribute");
     const size_t lds_limit = std::max((size_t)lds_max, (size_t)65536) - 1024;
-    if ((size_t)L.stride > lds_limit)
+    const bool bits = use_bits(in);
+    int32_t bit_start[tdpt::kMaxColors + 1];
+    bit_start[0] = 0;
+    for (int c = 0; c < in->n_colors; ++c)
+        bit_start[c + 1] = (int32_t)align_up((size_t)bit_start[c] + (in->cls_live[c] - in->cls_start[c]), 32);
+    const int32_t n_words = bit_start[in->n_colors] / 32;
+    if (bits && in->max_deg > 8)
+        return fail(TDPT_E_INVALID, "the bit-packed layout takes at most 8 problem neighbours per spin");
+    if (bits ? (size_t)n_words * 16 + 4096 > lds_limit : (size_t)L.stride > lds_limit)
         return fail(TDPT_E_INVALID, "a replica (" + std::to_string(in->n_pad) +
                                         " spins) does not fit the LDS of one workgroup");
 
@@ -448,6 +474,12 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     d.narrow = narrow ? 1 : 0;
     d.has_bias = in->has_bias;
     d.block = sweep_block(in, false);
+    d.bits = bits ? 1 : 0;
+    d.n_words = n_words;
+    for (int c = 0; c <= in->n_colors; ++c) d.bit_start[c] = bit_start[c];
+    d.nb_pos = bits ? (const int32_t *)(ws + L.nb_pos) : nullptr;
+    d.ch_pos = bits ? (const int32_t *)(ws + L.ch_pos) : nullptr;
+    d.h0 = bits ? (const int32_t *)(ws + L.h0) : nullptr;
     for (int c = 0; c <= in->n_colors; ++c) d.cls_start[c] = in->cls_start[c];
     for (int c = 0; c < in->n_colors; ++c) d.cls_live[c] = in->cls_live[c];
     d.nbi = narrow ? (const uint32_t *)(ws + L.nbi) : nullptr;
@@ -526,6 +558,28 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
         UP(ws + L.nb_idx, in->nb_idx.data(), in->nb_idx.size() * 4);
         UP(ws + L.nb_J, in->nb_J.data(), in->nb_J.size() * 4);
         UP(ws + L.ch_idx, in->ch_idx.data(), in->ch_idx.size() * 4);
+        if (bits) {
+            // structure in bit positions: spin rho of class c sits at
+            // rho - cls_start[c] + bit_start[c]
+            const int32_t n_pad = in->n_pad;
+            std::vector<int32_t> cls_of(n_pad, 0);
+            for (int c = 0; c < in->n_colors; ++c)
+                for (int32_t r = in->cls_start[c]; r < in->cls_start[c + 1]; ++r) cls_of[r] = c;
+            auto bitpos = [&](int32_t r) { return r - in->cls_start[cls_of[r]] + bit_start[cls_of[r]]; };
+            std::vector<int32_t> pos(in->nb_idx.size()), chp(in->ch_idx.size()), h0(n_pad, 0);
+            for (int k = 0; k < in->wd; ++k)
+                for (int32_t r = 0; r < n_pad; ++r) {
+                    const int32_t nb = in->nb_idx[(size_t)k * n_pad + r];
+                    pos[(size_t)k * n_pad + r] = (nb == n_pad) ? 0 : bitpos(nb);
+                    h0[r] -= in->nb_J[(size_t)k * n_pad + r];
+                }
+            for (int32_t r = 0; r < n_pad; ++r) h0[r] += in->bias[r];
+            for (size_t i = 0; i < chp.size(); ++i)
+                chp[i] = (in->ch_idx[i] == n_pad) ? -1 : bitpos(in->ch_idx[i]);
+            UP(ws + L.nb_pos, pos.data(), pos.size() * 4);
+            UP(ws + L.ch_pos, chp.data(), chp.size() * 4);
+            UP(ws + L.h0, h0.data(), h0.size() * 4);
+        }
     }
     UP(ws + L.bias, in->bias.data(), in->bias.size() * 4);
     UP(ws + L.orig, in->orig.data(), in->orig.size() * 4);
@@ -563,7 +617,7 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     // the persistent driver needs every slot's block resident at once
     p->persistent = false;
     const char *pe = getenv("TDPT_PERSISTENT");
-    if (!(pe && pe[0] == '0') && in->abs_f_bound < tdpt::kKeyOffset) {
+    if (!(pe && pe[0] == '0') && !bits && in->abs_f_bound < tdpt::kKeyOffset) {
         tdpt::DevProblem dq = d;
         dq.block = sweep_block(in, true);
         int max_blocks = 0;
@@ -621,7 +675,8 @@ int tdpt_problem_run(tdpt_problem *p, int64_t n_rounds)
         bool timed;
         int rc = timing_begin(p, ev, timed);
         if (rc) return rc;
-        hipError_t e = tdpt::launch_sweep(p->dp, p->stream);
+        hipError_t e = p->dp.bits ? tdpt::launch_sweep_bits(p->dp, p->stream)
+                                  : tdpt::launch_sweep(p->dp, p->stream);
         if (e != hipSuccess) return hip_fail(e, "launch sweep");
         if (timed) {
             HIP_TRY(hipEventRecord(ev.second, p->stream), "hipEventRecord");
@@ -823,6 +878,7 @@ struct tdpt_batch {
     struct Group {
         int first_member, count, blocks, prefix_off;
         size_t max_stride;
+        int max_words;
     };
     std::vector<Group> groups;
     hipEvent_t done = nullptr;
@@ -886,6 +942,7 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
     HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
     // group by structure layout (kernel instance), largest replicas first
     std::stable_sort(m.begin(), m.end(), [](const tdpt_problem *x, const tdpt_problem *y) {
+        if (x->dp.bits != y->dp.bits) return x->dp.bits < y->dp.bits;
         if (x->dp.narrow != y->dp.narrow) return x->dp.narrow > y->dp.narrow;
         if (x->dp.wd != y->dp.wd) return x->dp.wd < y->dp.wd;
         return x->dp.stride > y->dp.stride;
@@ -896,17 +953,18 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
     std::vector<int32_t> prefix;
     for (size_t i = 0; i < m.size(); ++i) {
         table[i] = m[i]->dp;
-        const bool start = b->groups.empty() || m[i]->dp.narrow != m[i - 1]->dp.narrow ||
-                           m[i]->dp.wd != m[i - 1]->dp.wd;
+        const bool start = b->groups.empty() || m[i]->dp.bits != m[i - 1]->dp.bits ||
+                           m[i]->dp.narrow != m[i - 1]->dp.narrow || m[i]->dp.wd != m[i - 1]->dp.wd;
         if (start) {
-            tdpt_batch::Group g{(int)i, 0, 0, (int)prefix.size(), 0};
+            tdpt_batch::Group g{(int)i, 0, 0, (int)prefix.size(), 0, 0};
             b->groups.push_back(g);
         }
         auto &g = b->groups.back();
         prefix.push_back(g.blocks);
-        g.blocks += m[i]->R;
+        g.blocks += m[i]->dp.bits ? (m[i]->R + tdpt::kBitSlots - 1) / tdpt::kBitSlots : m[i]->R;
         g.count += 1;
         g.max_stride = std::max(g.max_stride, (size_t)m[i]->dp.stride);
+        g.max_words = std::max(g.max_words, m[i]->dp.n_words);
     }
     if (!m.empty()) {
         HIP_TRY(hipMemcpyAsync(b->ws, table.data(), table.size() * sizeof(tdpt::DevProblem),
@@ -930,9 +988,13 @@ int tdpt_batch_run(tdpt_batch *b, int64_t n_rounds)
     const int *prefix = (const int *)(b->ws + batch_table_bytes(b->cap));
     for (int64_t r = 0; r < n_rounds; ++r) {
         for (const auto &g : b->groups) {
-            hipError_t e = tdpt::launch_batch_sweep(b->members[g.first_member]->dp, table + g.first_member,
-                                                    prefix + g.prefix_off, g.count, g.blocks, b->block,
-                                                    g.max_stride, b->stream);
+            const tdpt::DevProblem &d0 = b->members[g.first_member]->dp;
+            hipError_t e = d0.bits ? tdpt::launch_batch_sweep_bits(d0, table + g.first_member,
+                                                                   prefix + g.prefix_off, g.count, g.blocks,
+                                                                   b->block, g.max_words, b->stream)
+                                   : tdpt::launch_batch_sweep(d0, table + g.first_member,
+                                                              prefix + g.prefix_off, g.count, g.blocks,
+                                                              b->block, g.max_stride, b->stream);
             if (e != hipSuccess) return hip_fail(e, "launch batch sweep");
         }
         hipError_t e = tdpt::launch_batch_swap(table, (int)b->members.size(), b->stream);

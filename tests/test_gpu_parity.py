@@ -280,3 +280,64 @@ def test_n200_long_run_invariants(T):
         (w.n_beta * ((w.n_p - (r % 2 == 0)) // 2)) if ((r - 1) // 2) % 2 == 0
         else (w.n_p * ((w.n_beta - (r % 2 == 0)) // 2)) for r in range(1, 2001))
     assert np.all(pc <= pa) and np.all(bc <= ba)
+
+
+# ------------------------------------------------------ bit-packed layout
+
+@pytest.mark.parametrize("I,J,mcs", [(8, 4, 5), (3, 5, 2), (1, 1, 3)])
+def test_bit_packed_layout_small(T, I, J, mcs):
+    """The bit-packed layout (4 replicas per workgroup as bits), forced on
+    small instances: grids whose replica count is not a multiple of 4, the
+    instance with fields, the N=12 workload."""
+    for inst, name in [(tiny_instance(), "tiny+fields"), (wishart_small().instance, "wishart-N12")]:
+        beta = np.geomspace(0.3, 3.0, I)
+        p_q = q12(np.linspace(0.5, 3.0, J))
+        _with_env("TDPT_LAYOUT", "bits", lambda: both(
+            T, inst, beta, p_q, mcs=mcs, rounds=30, seed=13, label=f"bits {name} {I}x{J}"))
+
+
+def test_bit_packed_ragged_and_batched(T):
+    inst = build_instance(23, 0.75, 4, degree_cap=5, order="ascending")
+    _with_env("TDPT_LAYOUT", "bits", lambda: both(
+        T, inst, np.geomspace(0.2, 4, 3), q12([0, 1, 2.5]), mcs=4, rounds=20, seed=7,
+        label="bits ragged classes"))
+    w = wishart_small()
+    o = O.run(w.instance, w.beta, w.p_q, mcs_per_swap=5, n_rounds=12, seed=2, trace=True)
+    P = _with_env("TDPT_LAYOUT", "bits", lambda: run_gpu(
+        T, w.instance, w.beta, w.p_q, mcs=5, rounds=0, seed=2, trace=False))
+    B = T.Batch(2)
+    B.set_members([P])
+    B.run(12)
+    st = P.states()
+    assert np.array_equal(st, o["states"])
+
+
+def test_n1000_instance_bit_exact_on_a_sub_grid(T):
+    """The N=1000 planted-Wishart instance (250,000 spins per replica, bit-packed
+    layout chosen automatically) on a 2x2 sub-grid: one round of 50 sweeps is
+    bit-exact against the oracle."""
+    from synth.configs import wishart_n1000
+    w = wishart_n1000()
+    P0 = T.Instance.from_synth(w.instance)
+    assert P0.info()["n"] == 250000
+    beta = w.beta[[0, -1]]
+    p_q = w.p_q[[0, -1]]
+    both(T, w.instance, beta, p_q, mcs=50, rounds=1, seed=4, label="wishart-N1000 2x2")
+
+
+def test_n1000_full_grid_invariants(T):
+    """Full 64x32 grid of the N=1000 instance, two rounds of 50 sweeps: every
+    spin +-1, f and g of sampled positions equal their recomputation, the
+    permutation is a permutation."""
+    from synth.configs import wishart_n1000
+    w = wishart_n1000()
+    _say("[invariants] wishart-N1000 64x32, 2 rounds x 50 sweeps")
+    P = run_gpu(T, w.instance, w.beta, w.p_q, mcs=50, rounds=2, seed=0, trace=False)
+    assert P.query()["driver"] == 0
+    st = P.states()
+    assert np.all(np.abs(st) == 1)
+    f, g = P.energies()
+    rng = np.random.default_rng(1)
+    for pos in rng.choice(w.replicas, size=6, replace=False):
+        assert O.energy(w.instance, st[pos]) == (f[pos], g[pos])
+    assert np.array_equal(np.sort(P.perm()), np.arange(w.replicas))
