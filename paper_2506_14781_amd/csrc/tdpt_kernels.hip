@@ -42,8 +42,17 @@ __device__ __forceinline__ void philox10(uint32_t &x0, uint32_t &x1, uint32_t &x
     for (int rnd = 0; rnd < 10; ++rnd) {
         const uint64_t m0 = (uint64_t)0xD2511F53u * x0;
         const uint64_t m1 = (uint64_t)0xCD9E8D57u * x2;
-        const uint32_t y0 = (uint32_t)(m1 >> 32) ^ x1 ^ k0;
-        const uint32_t y2 = (uint32_t)(m0 >> 32) ^ x3 ^ k1;
+        uint32_t y0, y2;
+        if (rnd < 2) {
+            // the first rounds mix in words that are often uniform: plain
+            // xors let the compiler keep those parts scalar
+            y0 = (uint32_t)(m1 >> 32) ^ x1 ^ k0;
+            y2 = (uint32_t)(m0 >> 32) ^ x3 ^ k1;
+        } else {
+            // three-input xor in one gfx950 bitop3 (truth table 0x96)
+            y0 = (uint32_t)__builtin_amdgcn_bitop3_b32((int)(m1 >> 32), (int)x1, (int)k0, 0x96);
+            y2 = (uint32_t)__builtin_amdgcn_bitop3_b32((int)(m0 >> 32), (int)x3, (int)k1, 0x96);
+        }
         x1 = (uint32_t)m1;
         x3 = (uint32_t)m0;
         x0 = y0;
@@ -63,11 +72,21 @@ __device__ __forceinline__ double philox_u53(uint32_t c0, uint32_t c1, uint32_t 
 // ------------------------------------------------------- heat-bath decision
 // The decision is the double-precision expression
 //   +1  iff  (double)u < ldexp(1 / (1 + exp(-ldexp(beta * h, -11))), 32)
-// i.e. P(+1) = sigma(2 beta h) with h in Q12.  heat_bath_fast evaluates the
-// threshold X in single precision; its error is below 2^15 on the 2^32
-// scale (and below 2^9 once |x| > 32), so whenever |u - X| >= 2^16 its
-// answer is the exact one; otherwise the lane is flagged and the double
-// expression decides (about 2^-15 of all updates).
+// i.e. P(+1) = sigma(2 beta h) with h in Q12.
+//
+// heat_bath_up pre-tests it in single precision in product form: with
+// e = exp(-x) the spin goes up iff t = u (1 + e) < 2^32 (no reciprocal).
+// Error of the float t near t = 2^32: e is exp2 of y = h * cb, whose
+// relative error is at most 3 * 2^-24 (rounding of cb, of h, of the
+// product), so e carries a relative error below 2.1 |y| 2^-24 + 2^-23
+// (v_exp_f32 is good to 1 ulp).  Near the boundary u e <= 2^32, so for
+// y in [-32, 0] that term is below 2^14.1, and for y > 0 below
+// 2^32 (1.1 * 2^-24 + 2^-23) < 2^9.7; rounding u and the fma add
+// 2^8 each.  Whenever |t - 2^32| >= 2^16 the float answer is therefore the
+// exact one; otherwise the lane is flagged and the double expression
+// decides (about 2^-15 of all updates).  u = 0 with e = inf gives a NaN
+// t, which fails the margin test and is flagged too; e = inf with u > 0
+// gives t = inf, down, which is also the exact answer (p < 2^-96).
 __device__ __attribute__((noinline)) int heat_bath_exact(double beta, int h, uint32_t u)
 {
     const double x = ldexp(beta * (double)h, -11);
@@ -75,14 +94,18 @@ __device__ __attribute__((noinline)) int heat_bath_exact(double beta, int h, uin
     return ((double)u < ldexp(p, 32)) ? 1 : -1;
 }
 
+__device__ __forceinline__ bool heat_bath_up(int h, float cb, uint32_t u, bool &ambiguous)
+{
+    const float e = __builtin_amdgcn_exp2f(-((float)h * cb));  // cb = beta log2(e) / 2048
+    const float uf = (float)u;
+    const float t = __builtin_fmaf(uf, e, uf);
+    ambiguous = !(fabsf(t - 4294967296.0f) >= 65536.0f);
+    return t < 4294967296.0f;
+}
+
 __device__ __forceinline__ int heat_bath_fast(int h, float cb, uint32_t u, bool &ambiguous)
 {
-    const float y = (float)h * cb;  // x * log2(e), x = 2 beta h / 4096
-    const float e = __builtin_amdgcn_exp2f(-y);
-    const float X = __builtin_amdgcn_rcpf(1.0f + e) * 4294967296.0f;
-    const float uf = (float)u;
-    ambiguous = fabsf(uf - X) < 65536.0f;
-    return (uf < X) ? 1 : -1;
+    return heat_bath_up(h, cb, u, ambiguous) ? 1 : -1;
 }
 
 // ------------------------------------------------------ structure access
@@ -147,14 +170,15 @@ __device__ __forceinline__ SlotParams slot_params(const DevProblem &P, int pos)
     return sp;
 }
 
-// Structure of one quad (4 consecutive colour-major spins).  Never changes,
-// so a copy loaded ahead of time is valid whenever its quad index matches.
+// Structure of one quad (4 consecutive colour-major spins): one 16-byte
+// load per structure row.
 template <bool NARROW, int WD>
 struct QuadS {
     static constexpr int K = NARROW ? WD / 2 : WD;
     v4i a[K];    // narrow: index pairs; wide: indices
     v4i b[K];    // narrow: coupling pairs; wide: couplings
     v4i c0, c1;  // narrow: copy pairs in c0; wide: two copy rows
+    v4i bias;    // fields (zero when the instance has none)
 };
 
 template <bool NARROW, int WD>
@@ -169,45 +193,56 @@ __device__ __forceinline__ void load_quad(const DevProblem &P, const Rsrc &Rs, i
     }
     Q.c0 = bload(Rs.ch, voff, 0);
     if constexpr (!NARROW) Q.c1 = bload(Rs.ch, voff, row);
+    if (P.has_bias) Q.bias = bload(Rs.bias, voff, 0);
+    else Q.bias = v4i{0, 0, 0, 0};
 }
 
-// Heat-bath update of the 4 spins of quad q (LDS bytes s).  live: bit j set
-// when spin 4q+j is a real spin (not class padding).  NARROW instances keep
-// every field and energy change below 2^22, so the 16-bit dot products and
-// 24-bit multiplies are exact.
-template <bool NARROW, int WD>
-__device__ __forceinline__ void compute_quad(const DevProblem &P, const Rsrc &Rs, int8_t *s, int q,
-                                             const QuadS<NARROW, WD> &Q, unsigned live, uint32_t t,
-                                             const SlotParams &sp, int &dfa, int &dga)
+__device__ __forceinline__ int sbyte(uint32_t w, int j)
 {
-    int hp[4], cs[4];
-    if (P.has_bias) {
-        const v4i bb = bload(Rs.bias, q * 16, 0);
+    return (int)(int8_t)(w >> (8 * j));
+}
+
+// Local fields of the 4 spins of a quad from the LDS spins s: hp = problem
+// part (couplings and field), cs = sum of the copy neighbours.  NARROW
+// instances keep every field below 2^22, so the 16-bit dot products are
+// exact.
+template <bool NARROW, int WD>
+__device__ __forceinline__ void quad_fields(const int8_t *s, const QuadS<NARROW, WD> &Q, int hp[4], int cs[4])
+{
 #pragma unroll
-        for (int j = 0; j < 4; ++j) hp[j] = bb[j];
-    } else {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) hp[j] = 0;
-    }
+    for (int j = 0; j < 4; ++j) hp[j] = Q.bias[j];
     if constexpr (NARROW) {
+        // every LDS read of the quad is issued before the first product, so
+        // their latencies overlap
+        int8_t lo[WD / 2][4], hi[WD / 2][4], ca[4], cb[4];
 #pragma unroll
-        for (int k2 = 0; k2 < WD / 2; ++k2) {
+        for (int k2 = 0; k2 < WD / 2; ++k2)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int iw = Q.a[k2][j], jw = Q.b[k2][j];  // plain ints: bit-cast a value, not a vector lane
+                const int iw = Q.a[k2][j];  // plain int: bit-cast a value, not a vector lane
+                lo[k2][j] = s[iw & 0xffff];
+                hi[k2][j] = s[(unsigned)iw >> 16];
+            }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = Q.c0[j];
+            ca[j] = s[c & 0xffff];
+            cb[j] = s[(unsigned)c >> 16];
+        }
+#pragma unroll
+        for (int k2 = 0; k2 < WD / 2; ++k2)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int jw = Q.b[k2][j];
                 v2s sv, jv;
-                sv.x = (short)s[iw & 0xffff];
-                sv.y = (short)s[(unsigned)iw >> 16];
+                sv.x = lo[k2][j];
+                sv.y = hi[k2][j];
                 jv.x = (short)(jw & 0xffff);
                 jv.y = (short)((unsigned)jw >> 16);
                 hp[j] = __builtin_amdgcn_sdot2(jv, sv, hp[j], false);
             }
-        }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int c = Q.c0[j];
-            cs[j] = (int)s[c & 0xffff] + (int)s[(unsigned)c >> 16];
-        }
+        for (int j = 0; j < 4; ++j) cs[j] = (int)ca[j] + (int)cb[j];
     } else {
 #pragma unroll
         for (int k = 0; k < WD; ++k)
@@ -216,41 +251,60 @@ __device__ __forceinline__ void compute_quad(const DevProblem &P, const Rsrc &Rs
 #pragma unroll
         for (int j = 0; j < 4; ++j) cs[j] = (int)s[Q.c0[j]] + (int)s[Q.c1[j]];
     }
+}
 
+// Heat-bath update of the 4 spins of quad q (LDS bytes s) given their
+// fields.  live_bytes has 0xff in byte j when spin 4q+j is a real spin (not
+// class padding); padding spins stay 0.  Padding rows have zero couplings,
+// field and copies, so their h and copy sums are 0 and they add nothing to
+// the energy changes.  dfa accumulates the change of f, dga half the change
+// of g (24-bit multiplies are exact for NARROW instances, whose fields and
+// energy changes stay below 2^22).
+template <bool NARROW>
+__device__ __forceinline__ void quad_update(const DevProblem &P, int8_t *s, int q, const int hp[4], const int cs[4],
+                                            uint32_t live_bytes, uint32_t t, const SlotParams &sp,
+                                            int &dfa, int &dga)
+{
     uint32_t u[4] = {(uint32_t)q, t, sp.pos, 0u};
     philox10(u[0], u[1], u[2], u[3], P.key0, P.key1);
-    const int r0 = q * 4;
-    const char4 old = *reinterpret_cast<const char4 *>(s + r0);
-    const int so[4] = {old.x, old.y, old.z, old.w};
-    int hh[4], sn[4];
-    unsigned amb = 0;
+    uint32_t *wp = reinterpret_cast<uint32_t *>(s + q * 4);
+    const uint32_t ow = *wp;
+    int hh[4];
+    uint32_t up = 0;  // byte j = 1 when spin j goes up
+    bool amb_any = false;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         if constexpr (NARROW) hh[j] = __mul24(sp.twoP, cs[j]) + hp[j];
         else hh[j] = sp.twoP * cs[j] + hp[j];
         bool a;
-        sn[j] = heat_bath_fast(hh[j], sp.cb, u[j], a);
-        amb |= a ? (1u << j) : 0u;
+        up |= heat_bath_up(hh[j], sp.cb, u[j], a) ? (1u << (8 * j)) : 0u;
+        amb_any |= a && ((live_bytes >> (8 * j)) & 1u);
     }
-    amb &= live;
-    if (__builtin_expect(amb != 0u, 0)) {
+    if (__builtin_expect(amb_any, 0)) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (amb & (1u << j)) sn[j] = heat_bath_exact(sp.beta, hh[j], u[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        sn[j] = (live & (1u << j)) ? sn[j] : 0;
-        const int ds = sn[j] - so[j];
-        if constexpr (NARROW) {
-            dfa -= __mul24(ds, hp[j]);
-            dga -= __mul24(ds, cs[j]) * 2;
-        } else {
-            dfa -= ds * hp[j];
-            dga -= 2 * ds * cs[j];
+        for (int j = 0; j < 4; ++j) {
+            bool a;
+            heat_bath_up(hh[j], sp.cb, u[j], a);
+            if (a && ((live_bytes >> (8 * j)) & 1u)) {
+                const uint32_t bit = heat_bath_exact(sp.beta, hh[j], u[j]) > 0 ? 1u : 0u;
+                up = (up & ~(1u << (8 * j))) | (bit << (8 * j));
+            }
         }
     }
-    *reinterpret_cast<char4 *>(s + r0) = make_char4((char)sn[0], (char)sn[1], (char)sn[2], (char)sn[3]);
+    // byte j: +1 (0x01) when up, -1 (0xff) otherwise, 0 for padding
+    const uint32_t nw = (0xffffffffu ^ (up * 0xfeu)) & live_bytes;
+    *wp = nw;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int ds = sbyte(nw, j) - sbyte(ow, j);
+        if constexpr (NARROW) {
+            dfa -= __mul24(ds, hp[j]);
+            dga -= __mul24(ds, cs[j]);
+        } else {
+            dfa -= ds * hp[j];
+            dga -= ds * cs[j];
+        }
+    }
 }
 
 __device__ __forceinline__ int64_t wave_sum64(int64_t v)
@@ -263,17 +317,13 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v)
 // All sweeps of one round of the slot held at LDS address 0; returns the
 // change of f and g summed over the block into red[0..1] (LDS scratch of
 // 2 * (blockDim / 64) int64).  A lane walks its quads q0 + tid, q0 + tid +
-// blockDim, .. of every class; while it updates one quad the structure of
-// its next quad (possibly in the next class, across the barrier) is already
-// on its way.
+// blockDim, .. of every class.
 template <bool NARROW, int WD>
 __device__ __forceinline__ void sweep_round(const DevProblem &P, const Rsrc &Rs, int8_t *s,
                                             const SlotParams &sp, int64_t n_round, int64_t *red)
 {
     const int tid = threadIdx.x, nthr = blockDim.x;
     int64_t df = 0, dg = 0;
-    QuadS<NARROW, WD> pre;
-    int pre_q = -1;
     for (int k = 0; k < P.mcs; ++k) {
         const uint32_t t = (uint32_t)((n_round - 1) * P.mcs + k);
         for (int c = 0; c < P.n_colors; ++c) {
@@ -281,24 +331,16 @@ __device__ __forceinline__ void sweep_round(const DevProblem &P, const Rsrc &Rs,
             const int live_end = P.cls_live[c];
             int dfa = 0, dga = 0;
             for (int q = q0 + tid; q < q1; q += nthr) {
-                QuadS<NARROW, WD> cur;
-                if (pre_q == q) cur = pre;
-                else load_quad<NARROW, WD>(P, Rs, q, cur);
-                int qn = q + nthr;
-                if (qn >= q1) {
-                    const bool last = (c + 1 == P.n_colors) && (k + 1 == P.mcs);
-                    const int cn = (c + 1 < P.n_colors) ? c + 1 : 0;
-                    qn = (P.cls_start[cn] >> 2) + tid;
-                    if (last || qn >= (P.cls_start[cn + 1] >> 2)) qn = -1;
-                }
-                if (qn >= 0) load_quad<NARROW, WD>(P, Rs, qn, pre);
-                pre_q = qn;
+                QuadS<NARROW, WD> Q;
+                load_quad<NARROW, WD>(P, Rs, q, Q);
+                int hp[4], cs[4];
+                quad_fields<NARROW, WD>(s, Q, hp, cs);
                 const int rem = live_end - q * 4;
-                const unsigned live = rem >= 4 ? 15u : ((1u << rem) - 1u);
-                compute_quad<NARROW, WD>(P, Rs, s, q, cur, live, t, sp, dfa, dga);
+                const uint32_t live_bytes = rem >= 4 ? 0xffffffffu : rem <= 0 ? 0u : ((1u << (8 * rem)) - 1u);
+                quad_update<NARROW>(P, s, q, hp, cs, live_bytes, t, sp, dfa, dga);
             }
             df += dfa;
-            dg += dga;
+            dg += 2 * (int64_t)dga;
             __syncthreads();
         }
     }
