@@ -159,13 +159,15 @@ struct SlotParams {
     uint32_t pos;  // grid position (Philox counter word)
 };
 
-__device__ __forceinline__ SlotParams slot_params(const DevProblem &P, int pos)
+// beta / p_q: the problem's ladders, or copies of them in LDS.
+__device__ __forceinline__ SlotParams slot_params(const DevProblem &P, int pos, const double *beta,
+                                                  const int32_t *p_q)
 {
     SlotParams sp;
     const int i = pos / P.J, j = pos - i * P.J;
-    sp.beta = P.beta[i];
+    sp.beta = beta[i];
     sp.cb = (float)(sp.beta * (1.4426950408889634 / 2048.0));
-    sp.twoP = 2 * P.p_q[j];
+    sp.twoP = 2 * p_q[j];
     sp.pos = (uint32_t)pos;
     return sp;
 }
@@ -378,7 +380,7 @@ __device__ __forceinline__ void round_sweep_body(const DevProblem &P, int slot, 
     int64_t *red = lds_scratch(lds, P.stride);
     copy_bytes16(lds, P.states + (size_t)slot * P.stride, P.stride);
     const int64_t n_round = P.hdr[kHdrRounds] + 1;
-    const SlotParams sp = slot_params(P, P.slot_pos[slot]);
+    const SlotParams sp = slot_params(P, P.slot_pos[slot], P.beta, P.p_q);
     const Rsrc Rs = make_rsrc(P);
     __syncthreads();
     sweep_round<NARROW, WD>(P, Rs, lds, sp, n_round, red);
@@ -421,17 +423,18 @@ __device__ __forceinline__ bool metropolis(double x, double u)
 // Swap exponent and acceptance of the pair (left / upper position a,
 // right / lower position b) in round n.  P pairs lie on row `line` with left
 // column k; beta pairs on column `line` with upper row k.
-__device__ __forceinline__ bool pair_accept(const DevProblem &P, bool dir_beta, int k, int line,
-                                            int64_t n, int64_t fa, int64_t ga, int64_t fb, int64_t gb)
+__device__ __forceinline__ bool pair_accept(const DevProblem &P, const double *beta, const int32_t *p_q,
+                                            bool dir_beta, int k, int line, int64_t n, int64_t fa, int64_t ga,
+                                            int64_t fb, int64_t gb)
 {
     double x;
     if (!dir_beta) {
-        const int64_t dpg = ((int64_t)P.p_q[k + 1] - P.p_q[k]) * (gb - ga);
-        x = ldexp(P.beta[line] * (double)dpg, -12);
+        const int64_t dpg = ((int64_t)p_q[k + 1] - p_q[k]) * (gb - ga);
+        x = ldexp(beta[line] * (double)dpg, -12);
     } else {
-        const int64_t ea = fa + (int64_t)P.p_q[line] * ga;
-        const int64_t eb = fb + (int64_t)P.p_q[line] * gb;
-        const double dbeta = P.beta[k + 1] - P.beta[k];
+        const int64_t ea = fa + (int64_t)p_q[line] * ga;
+        const int64_t eb = fb + (int64_t)p_q[line] * gb;
+        const double dbeta = beta[k + 1] - beta[k];
         x = ldexp(dbeta * (double)(eb - ea), -12);
     }
     const double u = philox_u53((uint32_t)k, (uint32_t)n, (uint32_t)line, dir_beta ? 2u : 1u,
@@ -463,7 +466,7 @@ __device__ __forceinline__ void swap_track_body(const DevProblem &P)
         const int a = dir_beta ? k * P.J + line : line * P.J + k;
         const int b = dir_beta ? a + P.J : a + 1;
         const int sa = P.pos_slot[a], sb = P.pos_slot[b];
-        const bool acc = pair_accept(P, dir_beta, k, line, n, P.f[sa], P.g[sa], P.f[sb], P.g[sb]);
+        const bool acc = pair_accept(P, P.beta, P.p_q, dir_beta, k, line, n, P.f[sa], P.g[sa], P.f[sb], P.g[sb]);
         const int ci = dir_beta ? line * (P.I - 1) + k : line * (P.J - 1) + k;
         int64_t *att = dir_beta ? P.b_att : P.p_att;
         int64_t *acp = dir_beta ? P.b_acc : P.p_acc;
@@ -548,8 +551,13 @@ __global__ __launch_bounds__(kMaxBlock, 4) void k_persistent(DevProblem P, int64
     // per-slot state kept by thread 0 in LDS: [0] f, [1] g, [2] best key
     int64_t *st = red + 2 + 2 * (kMaxBlock / 64);
     int *sh = reinterpret_cast<int *>(st + 3);  // [0] position, [1] improved, [2] abort
+    // copies of the beta and penalty ladders, read every round
+    double *lbeta = reinterpret_cast<double *>(sh + 4);
+    int32_t *lpq = reinterpret_cast<int32_t *>(lbeta + P.I);
     const int slot = blockIdx.x;
     const int tid = threadIdx.x;
+    for (int i = tid; i < P.I; i += blockDim.x) lbeta[i] = P.beta[i];
+    for (int j = tid; j < P.J; j += blockDim.x) lpq[j] = P.p_q[j];
     copy_bytes16(lds, P.states + (size_t)slot * P.stride, P.stride);
     if (tid == 0) {
         st[0] = P.f[slot];
@@ -563,7 +571,7 @@ __global__ __launch_bounds__(kMaxBlock, 4) void k_persistent(DevProblem P, int64
     for (int64_t rr = 1; rr <= n_rounds; ++rr) {
         const int64_t n = n0 + rr;
         const int pos = __builtin_amdgcn_readfirstlane(sh[0]);
-        const SlotParams sp = slot_params(P, pos);
+        const SlotParams sp = slot_params(P, pos, lbeta, lpq);
         sweep_round<NARROW, WD>(P, Rs, lds, sp, n, red);
         if (tid == 0) {
             const int64_t f = st[0] + red[0];
@@ -596,7 +604,7 @@ __global__ __launch_bounds__(kMaxBlock, 4) void k_persistent(DevProblem P, int64
                 if (!mb_wait(&mb[2 * other], tag, fo, go, P.hdr)) abort = 1;
                 const int64_t fa = left ? f : fo, ga = left ? g : go;
                 const int64_t fb = left ? fo : f, gb = left ? go : g;
-                const bool acc = !abort && pair_accept(P, dir_beta, k, line, n, fa, ga, fb, gb);
+                const bool acc = !abort && pair_accept(P, lbeta, lpq, dir_beta, k, line, n, fa, ga, fb, gb);
                 if (left && !abort) {
                     const int ci = dir_beta ? line * (P.I - 1) + k : line * (P.J - 1) + k;
                     __hip_atomic_fetch_add(dir_beta ? &P.b_att[ci] : &P.p_att[ci], (int64_t)1,
@@ -806,7 +814,7 @@ __device__ __forceinline__ void round_sweep_bits_body(const DevProblem &P, int s
     }
     SlotParams sp[kBitSlots];
 #pragma unroll
-    for (int r = 0; r < kBitSlots; ++r) sp[r] = slot_params(P, r < ns ? P.slot_pos[slot0 + r] : 0);
+    for (int r = 0; r < kBitSlots; ++r) sp[r] = slot_params(P, r < ns ? P.slot_pos[slot0 + r] : 0, P.beta, P.p_q);
     const Rsrc Rs = make_rsrc(P);
     const int64_t n_round = P.hdr[kHdrRounds] + 1;
     __syncthreads();
@@ -969,6 +977,12 @@ static size_t sweep_lds(const DevProblem &p)
     return (size_t)p.stride + 8 * (2 + 2 * (kMaxBlock / 64) + 3) + 16;
 }
 
+// The persistent workgroup adds its copies of the ladders.
+static size_t persistent_lds(const DevProblem &p)
+{
+    return sweep_lds(p) + 8 * (size_t)p.I + 4 * (size_t)p.J + 8;
+}
+
 template <typename K>
 static hipError_t allow_lds(K kernel, size_t lds)
 {
@@ -990,8 +1004,19 @@ template <bool NARROW, int WD>
 static hipError_t persistent_t(const DevProblem &p, int64_t n_rounds, hipStream_t s, bool query_only,
                                int *max_blocks)
 {
-    const size_t lds = sweep_lds(p);
+    const size_t lds = persistent_lds(p);
     auto kern = k_persistent<NARROW, WD>;
+    if (query_only) {
+        // a workgroup that does not fit the LDS cannot be resident at all
+        int dev = 0, lds_max = 0;
+        hipError_t q = hipGetDevice(&dev);
+        if (q == hipSuccess) q = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (q != hipSuccess) return q;
+        if (lds > (size_t)lds_max) {
+            *max_blocks = 0;
+            return hipSuccess;
+        }
+    }
     hipError_t e = allow_lds(kern, lds);
     if (e != hipSuccess) return e;
     if (query_only) {
