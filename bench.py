@@ -1,12 +1,17 @@
 #!/usr/bin/env python3
 """Spin-update throughput of 2D parallel tempering on one MI355X.
 
-Workload: planted Wishart N=200 (alpha 0.8) sparsified with copy chains to
-degree 8 (6800 physical spins), a 32 x 16 replica grid (beta geometric
-0.05..10, P linear 0..8), a swap round after every sweep.  One step is
-`--rounds-per-step` swap rounds (default 1000 sweeps of all 512 replicas,
-each followed by the f/g reduction, the swap step and bottom-right
-tracking).  The default 100 steps are the workload's full 1e5 sweeps.
+Default workload (n200): planted Wishart N=200 (alpha 0.8) sparsified with
+copy chains to degree 8 (6800 physical spins), a 32 x 16 replica grid (beta
+geometric 0.05..10, P linear 0..8), a swap round after every sweep.  One
+step is `--rounds-per-step` swap rounds (default 1000 sweeps of all 512
+replicas, each followed by the f/g reduction, the swap step and
+bottom-right tracking).  The default 100 steps are the workload's full 1e5
+sweeps.
+
+n1000: planted Wishart N=1000 (alpha 0.6), degree 6 (250,000 physical
+spins), a 64 x 32 grid, 50 sweeps per swap round; one step is 4 rounds
+(200 sweeps), 5 steps by default (1000 sweeps, 5.1e11 spin updates).
 
 Prints one JSON line.  `value` is spin-updates/s over the timed steps with
 the problem already resident in HBM.
@@ -28,23 +33,25 @@ if ROOT not in sys.path:
 
 # MI355X: 256 compute units x 4 SIMD x 16 lanes x 2.4 GHz of 32-bit VALU lanes
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
+PEAK_HBM = 8.0e12  # bytes/s
 
-# HBM bytes per swap round of the persistent kernel on this workload, from
-# rocprofv3 FETCH_SIZE (x2.00) and WRITE_SIZE (x1.00) counters scaled against
-# a plain copy of known size; valid for the kernel source with this hash.
-MEASURED_TRAFFIC = {"kernel_sha256": "3e315b895864101a", "bytes_per_round": 213452}
+# HBM bytes per swap round of each workload's dominant kernel, from rocprofv3
+# FETCH_SIZE (x2.00) and WRITE_SIZE (x1.00) counters scaled against a plain
+# copy of known size; valid for the kernel source with this hash.
+MEASURED_TRAFFIC = {}
 KERNEL_SRC = os.path.join(ROOT, "paper_2506_14781_amd", "csrc", "tdpt_kernels.hip")
 
 
-def measured_traffic(persistent: bool, rounds_per_launch: int):
+def measured_traffic(kernel: str, rounds_per_launch: int):
     """HBM bytes per launch from the committed counter run, or None if the
     kernel source changed since the counters were taken."""
     import hashlib
     with open(KERNEL_SRC, "rb") as fh:
         digest = hashlib.sha256(fh.read()).hexdigest()[:16]
-    if not persistent or digest != MEASURED_TRAFFIC["kernel_sha256"]:
+    m = MEASURED_TRAFFIC.get(kernel)
+    if m is None or digest != m["kernel_sha256"]:
         return None
-    return MEASURED_TRAFFIC["bytes_per_round"] * rounds_per_launch
+    return m["bytes_per_round"] * rounds_per_launch
 
 
 def alu_ops_per_update(info) -> float:
@@ -63,17 +70,32 @@ def alu_ops_per_update(info) -> float:
     return field + philox + decision + bookkeeping
 
 
-def cpu_baseline(w, rounds: int) -> dict:
+def cpu_baseline(w, rounds: int, sub_grid: int = 0) -> dict:
+    """The oracle timed on a bounded sample of the workload: its first
+    `rounds` rounds, on the full grid or (sub_grid > 0) on the top-left
+    sub_grid x sub_grid corner of the grid."""
     from oracle import oracle as O
-    n, R = w.instance.n, w.replicas
+    beta, p_q = w.beta, w.p_q
+    if sub_grid:
+        beta, p_q = beta[:sub_grid], p_q[:sub_grid]
+    n, R = w.instance.n, len(beta) * len(p_q)
     t0 = time.perf_counter()
-    O.run(w.instance, w.beta, w.p_q, mcs_per_swap=w.mcs_per_swap, n_rounds=rounds, seed=0)
+    O.run(w.instance, beta, p_q, mcs_per_swap=w.mcs_per_swap, n_rounds=rounds, seed=0)
     dt = time.perf_counter() - t0
     updates = rounds * w.mcs_per_swap * R * n
+    grid = f"{len(beta)}x{len(p_q)} corner of the grid" if sub_grid else f"all {R} replicas"
     return {"value": updates / dt, "unit": "spin-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{w.name}: first {rounds} rounds x {w.mcs_per_swap} sweep(s) of all "
-                      f"{R} replicas, seed 0, single-threaded plain C ({platform.processor() or platform.machine()})",
+            "sample": f"{w.name}: first {rounds} rounds x {w.mcs_per_swap} sweep(s) of {grid}, "
+                      f"seed 0, single-threaded plain C ({platform.processor() or platform.machine()})",
             "seconds": round(dt, 3)}
+
+
+def bits_bytes_per_update(info, wd: int) -> float:
+    """Bit-packed layout: every workgroup streams the structure once per
+    sweep (neighbour bit positions and couplings, 8 bytes per ELL entry;
+    copy positions, 8; field, 4 — per padded spin) for its 4 replicas, whose
+    spins stay in LDS; the int8 states are read and written once per round."""
+    return (8 * wd + 12) * info["n_pad"] / info["n"] / 4
 
 
 def _requests(T, members, cap_sweeps, rho0=0.0):
@@ -94,7 +116,8 @@ def _requests(T, members, cap_sweeps, rho0=0.0):
         target = f_gs + int(round(rho0 * w.instance.N * 4096))
         cfg = T.RunConfig(w.beta, w.p_q, mcs_per_swap=w.mcs_per_swap, seed=w.seed, f_target=target)
         reqs.append(Request(name=w.name, instance=inst, cfg=cfg,
-                            max_rounds=cap_sweeps // w.mcs_per_swap))
+                            max_rounds=cap_sweeps // w.mcs_per_swap, f_ref=f_gs,
+                            n_logical=w.instance.N))
     return reqs
 
 
@@ -129,48 +152,62 @@ def bench_batched(args):
 
 
 def bench_serving(args):
-    """Poisson arrivals of planted-Wishart solves (N ~ U{64..1024} scaled
-    down by --max-n), continuous batching under an HBM budget."""
+    """Poisson arrivals of planted-Wishart solves (N ~ U{64..max_n}),
+    continuous batching under an HBM budget, at each rate of --rates: the
+    same requests (and arrival draws, rescaled to the rate) at every rate."""
+    import dataclasses
+
     import paper_2506_14781_amd as T
     from paper_2506_14781_amd.serve import serve, summarize
     from synth.configs import serving_member
     rng = np.random.default_rng(0)
-    members, arrivals, t = [], [], 0.0
+    members, gaps = [], []
     for k in range(args.count):
         N = int(rng.integers(64, args.max_n + 1))
         alpha = float(rng.choice([0.5, 0.8]))
         members.append(serving_member(N, alpha, k, args.cap_sweeps))
-        t += rng.exponential(1.0 / args.rate)
-        arrivals.append(t)
-    reqs = _requests(T, members, args.cap_sweeps, args.rho0)
-    for r, a in zip(reqs, arrivals):
-        r.arrival = a
-    total = serve(reqs, chunk=args.chunk, budget_bytes=int(args.budget_gb * 2**30))
-    s = summarize(reqs, total)
+        gaps.append(rng.exponential(1.0))
+    print(f"[bench] serving: {args.count} requests generated", file=sys.stderr, flush=True)
+    template = _requests(T, members, args.cap_sweeps, args.rho0)
+    rates = [float(x) for x in args.rates.split(",")] if args.rates else [args.rate]
+    per_rate = {}
+    for rate in rates:
+        reqs = [dataclasses.replace(r) for r in template]
+        t = 0.0
+        for r, gap in zip(reqs, gaps):
+            t += gap / rate
+            r.arrival = t
+        total = serve(reqs, chunk=args.chunk, budget_bytes=int(args.budget_gb * 2**30))
+        per_rate[str(rate)] = s = summarize(reqs, total)
+        print(f"[bench] rate {rate}/s: makespan {total:.2f} s, latency p50 {s.get('latency_p50_s')}",
+              file=sys.stderr, flush=True)
     tgt = "planted-GS" if args.rho0 == 0 else f"rho_E<={args.rho0}"
-    out = {"metric": f"time-to-{tgt} p50 (serving)", "value": s["tts_p50_s"], "unit": "s",
+    first = per_rate[str(rates[0])]
+    out = {"metric": f"time-to-{tgt} p50 (serving)", "value": first["tts_p50_s"], "unit": "s",
            "higher_is_better": False, "n_gpus": 1,
            "data": "synthetic (seeded planted Wishart, Poisson arrivals)",
-           "config": {"workload": f"serving, {args.count} requests, rate {args.rate}/s, "
-                                  f"N<= {args.max_n}, cap {args.cap_sweeps} sweeps"},
-           "serving": s}
+           "config": {"workload": f"serving, {args.count} requests, N<= {args.max_n}, "
+                                  f"cap {args.cap_sweeps} sweeps, budget {args.budget_gb} GiB",
+                      "sizes": [m.instance.N for m in members]},
+           "serving": per_rate}
     print(json.dumps(out), flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--rounds-per-step", type=int, default=1000)
-    ap.add_argument("--cpu-rounds", type=int, default=100,
-                    help="rounds of the oracle timed for the CPU baseline (0: skip)")
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (n200: 100, n1000: 5)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (n200: 5, n1000: 1)")
+    ap.add_argument("--rounds-per-step", type=int, default=None, help="rounds per step (n200: 1000, n1000: 4)")
+    ap.add_argument("--cpu-rounds", type=int, default=None,
+                    help="rounds of the oracle timed for the CPU baseline (0: skip; n200: 100, n1000: 1)")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", choices=["n200", "batched", "serving"], default="n200")
+    ap.add_argument("--workload", choices=["n200", "n1000", "batched", "serving"], default="n200")
     ap.add_argument("--count", type=int, default=64, help="instances (batched) / requests (serving)")
     ap.add_argument("--cap-sweeps", type=int, default=50000)
     ap.add_argument("--chunk", type=int, default=10, help="rounds between host checks")
     ap.add_argument("--rate", type=float, default=50.0, help="serving arrivals per second")
+    ap.add_argument("--rates", type=str, default="", help="comma-separated serving rates (overrides --rate)")
     ap.add_argument("--max-n", type=int, default=1024, help="largest logical size when serving")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving HBM budget")
     ap.add_argument("--rho0", type=float, default=0.0,
@@ -183,10 +220,16 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    big = args.workload == "n1000"
+    for name, small, large in [("steps", 100, 5), ("warmup", 5, 1), ("rounds_per_step", 1000, 4),
+                               ("cpu_rounds", 100, 1)]:
+        if getattr(args, name) is None:
+            setattr(args, name, large if big else small)
+
     import torch
 
     import paper_2506_14781_amd as T
-    from synth.configs import wishart_n200
+    from synth.configs import wishart_n200, wishart_n1000
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -196,7 +239,7 @@ def main():
         return bench_batched(args)
     if args.workload == "serving":
         return bench_serving(args)
-    w = wishart_n200(seed=args.seed)
+    w = wishart_n1000(seed=args.seed) if big else wishart_n200(seed=args.seed)
     inst = T.Instance.from_synth(w.instance)
     info = inst.info()
     cfg = T.RunConfig(w.beta, w.p_q, mcs_per_swap=w.mcs_per_swap, seed=args.seed)
@@ -227,23 +270,30 @@ def main():
     updates_per_round = w.mcs_per_swap * w.replicas * w.instance.n
     updates = total_rounds * updates_per_round
     value = updates / (ms / 1e3)
-    ops = alu_ops_per_update(info)
     launch_ms = kern_ms / max(timed, 1)
     updates_per_launch = updates_per_round * timed_rounds // max(timed, 1)
-    achieved = ops * updates_per_launch / (launch_ms / 1e3)
-    roofline = {
-        "bound": "alu",
-        "achieved": round(achieved / 1e12, 3),
-        "peak": round(PEAK_LANE_OPS / 1e12, 3),
-        "unit": "Tlane-op/s",
-        "frac": round(achieved / PEAK_LANE_OPS, 4),
-        "traffic": measured_traffic(persistent, timed_rounds // max(timed, 1)),
-        "kernel": "k_persistent" if persistent else "k_round_sweep",
-        "kernel_avg_ms": round(launch_ms, 5),
-        "kernel_launches_timed": timed,
-        "ops_per_update": round(ops, 2),
-        "updates_per_launch": updates_per_launch,
-    }
+    # the library keeps a replica as int8 in LDS up to 48 KiB, as bits beyond
+    bits = os.environ.get("TDPT_LAYOUT") == "bits" or (info["n_pad"] + 1 + 15) // 16 * 16 > 48 * 1024
+    kernel = "k_persistent" if persistent else ("k_round_sweep_bits" if bits else "k_round_sweep")
+    if bits:
+        # structure streamed from L2 / MALL / HBM: bound by memory bandwidth
+        wd = max(1, info["max_degree"]) if info["max_degree"] <= 8 else 16
+        bpu = bits_bytes_per_update(info, wd)
+        achieved = bpu * updates_per_launch / (launch_ms / 1e3)
+        roofline = {"bound": "hbm", "achieved": round(achieved / 1e9, 1), "peak": PEAK_HBM / 1e9,
+                    "unit": "GB/s", "frac": round(achieved / PEAK_HBM, 4),
+                    "traffic": measured_traffic(kernel, timed_rounds // max(timed, 1)),
+                    "bytes_per_update": round(bpu, 3)}
+    else:
+        ops = alu_ops_per_update(info)
+        achieved = ops * updates_per_launch / (launch_ms / 1e3)
+        roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 3),
+                    "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "Tlane-op/s",
+                    "frac": round(achieved / PEAK_LANE_OPS, 4),
+                    "traffic": measured_traffic(kernel, timed_rounds // max(timed, 1)),
+                    "ops_per_update": round(ops, 2)}
+    roofline.update({"kernel": kernel, "kernel_avg_ms": round(launch_ms, 5),
+                     "kernel_launches_timed": timed, "updates_per_launch": updates_per_launch})
     q = prob.query()
     out = {
         "metric": "spin-updates/s",
@@ -272,7 +322,7 @@ def main():
         "roofline": roofline,
     }
     if args.cpu_rounds > 0:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_rounds)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_rounds, sub_grid=2 if big else 0)
     print(json.dumps(out), flush=True)
 
 

@@ -705,21 +705,38 @@ __global__ __launch_bounds__(kSmallBlock) void k_finalize(DevProblem P, int64_t 
 // For replicas too large for an int8 copy in LDS.  A workgroup holds
 // kBitSlots replicas as bits, interleaved by word (uint32 4 w + r is word w
 // of replica r), so one 16-byte LDS read returns a neighbour's word of all
-// of them and every structure load serves kBitSlots updates.  With t the
-// spin's bit as 0 / -1, sum_k J_k s_k = (sum_k J_k (2 b_k - 1)) =
-// -sum_k J_k + 2 sum_k (J_k & t_k); h0 = b - sum_k J_k is precomputed.
-__device__ __forceinline__ int bit_sign(uint32_t w, int pos)  // +1 / -1 of bit pos & 31
+// of them and every structure load serves kBitSlots updates.  With b_k the
+// neighbour's bit (s_k = 2 b_k - 1), sum_k J_k s_k = -sum_k J_k +
+// 2 sum_k J_k b_k; h0 = b - sum_k J_k is precomputed, and J_k b_k is one
+// 24-bit multiply-add (couplings of this layout stay below 2^23).
+//
+// A class starts on a 32-bit boundary of the bit numbering and lane l of a
+// wave takes quad l (+ multiples of the block size) of the class, so the 8
+// quads of one word belong to 8 consecutive lanes of one wave: they OR
+// their new nibbles together across lanes and one of them stores the word.
+// Every lane of a wave that has any quad left runs the update (lanes past
+// the class end with no live spin), so the lanes of a word are converged.
+
+// OR of x over the aligned group of 8 lanes containing this lane, in the
+// group's last lane (DPP: quad_perm swaps, then a shift by 4 within a row).
+__device__ __forceinline__ uint32_t or8_last(uint32_t x)
 {
-    return ((w >> (pos & 31)) & 1u) ? 1 : -1;
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);  // row_shr:4
+    return x;
 }
 
+// q: the lane's quad, which may lie past the class end (q1); its structure
+// and spins are read at min(q, q1 - 1) and then it has no live spin.
 template <int WD>
 __device__ __forceinline__ void bits_update_quad(const DevProblem &P, const Rsrc &Rs, uint32_t *W, int q,
-                                                 int c, unsigned live, uint32_t t,
-                                                 const SlotParams (&sp)[kBitSlots], int ns,
+                                                 int q1, int c, unsigned live, uint32_t t,
+                                                 const SlotParams (&sp)[kBitSlots],
                                                  int (&dfa)[kBitSlots], int (&dga)[kBitSlots])
 {
-    const int voff = q * 16;
+    const int qs = min(q, q1 - 1);
+    const int voff = qs * 16;
     const int row = P.n_pad * 4;
     int acc[4][kBitSlots], cs[4][kBitSlots];
 #pragma unroll
@@ -737,53 +754,78 @@ __device__ __forceinline__ void bits_update_quad(const DevProblem &P, const Rsrc
             const uint32_t w4[4] = {nw.x, nw.y, nw.z, nw.w};
 #pragma unroll
             for (int r = 0; r < kBitSlots; ++r)
-                acc[j][r] += jk[j] & __builtin_amdgcn_sbfe(w4[r], pos & 31, 1);
+                acc[j][r] += __mul24((int)__builtin_amdgcn_ubfe(w4[r], pos & 31, 1), jk[j]);
         }
     }
     const v4i c0 = bload(Rs.ch, voff, 0);
     const v4i c1 = bload(Rs.ch, voff, row);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        if (c0[j] >= 0) {
-            const uint4 nw = *reinterpret_cast<const uint4 *>(W + 4 * (c0[j] >> 5));
-            const uint32_t w4[4] = {nw.x, nw.y, nw.z, nw.w};
+        // a missing copy neighbour (-1) reads word 0 and counts 0
+        const int p0 = c0[j], p1 = c1[j];
+        const uint4 n0 = *reinterpret_cast<const uint4 *>(W + 4 * (max(p0, 0) >> 5));
+        const uint4 n1 = *reinterpret_cast<const uint4 *>(W + 4 * (max(p1, 0) >> 5));
+        const uint32_t a4[4] = {n0.x, n0.y, n0.z, n0.w}, b4[4] = {n1.x, n1.y, n1.z, n1.w};
+        const int k0 = p0 >= 0 ? 1 : 0, k1 = p1 >= 0 ? 1 : 0;
 #pragma unroll
-            for (int r = 0; r < kBitSlots; ++r) cs[j][r] += bit_sign(w4[r], c0[j]);
-        }
-        if (c1[j] >= 0) {
-            const uint4 nw = *reinterpret_cast<const uint4 *>(W + 4 * (c1[j] >> 5));
-            const uint32_t w4[4] = {nw.x, nw.y, nw.z, nw.w};
-#pragma unroll
-            for (int r = 0; r < kBitSlots; ++r) cs[j][r] += bit_sign(w4[r], c1[j]);
+        for (int r = 0; r < kBitSlots; ++r) {
+            const int b0 = (int)__builtin_amdgcn_ubfe(a4[r], p0 & 31, 1) & k0;
+            const int b1 = (int)__builtin_amdgcn_ubfe(b4[r], p1 & 31, 1) & k1;
+            cs[j][r] = 2 * (b0 + b1) - k0 - k1;
         }
     }
     const v4i h0 = bload(Rs.bias, voff, 0);
-    const int bpos = q * 4 - P.cls_start[c] + P.bit_start[c];
+    const int bpos = qs * 4 - P.cls_start[c] + P.bit_start[c];
     const int wq = bpos >> 5, off = bpos & 31;
     const uint4 ow = *reinterpret_cast<const uint4 *>(W + 4 * wq);
     const uint32_t o4[4] = {ow.x, ow.y, ow.z, ow.w};
+    uint32_t nw4[kBitSlots];
 #pragma unroll
     for (int r = 0; r < kBitSlots; ++r) {
-        if (r >= ns) break;
         uint32_t u[4] = {(uint32_t)q, t, sp[r].pos, 0u};
         philox10(u[0], u[1], u[2], u[3], P.key0, P.key1);
-        uint32_t nbits = (o4[r] >> off) & 15u;
+        int hp[4], hh[4];
+        uint32_t up = 0;
+        bool amb_any = false;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            if (!(live & (1u << j))) continue;
-            const int hp = h0[j] + 2 * acc[j][r];
-            const int h = sp[r].twoP * cs[j][r] + hp;
+            hp[j] = h0[j] + 2 * acc[j][r];
+            hh[j] = sp[r].twoP * cs[j][r] + hp[j];
             bool a;
-            int sn = heat_bath_fast(h, sp[r].cb, u[j], a);
-            if (__builtin_expect(a, 0)) sn = heat_bath_exact(sp[r].beta, h, u[j]);
-            const int so = ((o4[r] >> (off + j)) & 1u) ? 1 : -1;
-            const int ds = sn - so;
-            dfa[r] -= ds * hp;
-            dga[r] -= 2 * ds * cs[j][r];
-            nbits = sn > 0 ? (nbits | (1u << j)) : (nbits & ~(1u << j));
+            up |= heat_bath_up(hh[j], sp[r].cb, u[j], a) ? (1u << j) : 0u;
+            amb_any |= a && ((live >> j) & 1u);
         }
-        atomicAnd(&W[4 * wq + r], ~(15u << off));
-        atomicOr(&W[4 * wq + r], nbits << off);
+        if (__builtin_expect(amb_any, 0)) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                bool a;
+                heat_bath_up(hh[j], sp[r].cb, u[j], a);
+                if (a && ((live >> j) & 1u)) {
+                    const uint32_t bit = heat_bath_exact(sp[r].beta, hh[j], u[j]) > 0 ? 1u : 0u;
+                    up = (up & ~(1u << j)) | (bit << j);
+                }
+            }
+        }
+        up &= live;
+        const uint32_t old = (o4[r] >> off) & 15u;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            // s_new - s_old = 2 (bit_new - bit_old); dead spins change nothing.
+            // df = -(s_new - s_old) hp, dg = -2 (s_new - s_old) cs
+            const int db = (((live >> j) & 1u) ? ((int)((up >> j) & 1u) - (int)((old >> j) & 1u)) : 0);
+            dfa[r] -= 2 * db * hp[j];
+            dga[r] -= 4 * db * cs[j][r];
+        }
+        nw4[r] = up << off;  // 0 for a lane past the class end
+    }
+    // the group's word, from its first quad; a group wholly past the class
+    // end owns no word and stores nothing
+    const int qg = q - (int)(threadIdx.x & 7);
+    const int wg = (qg * 4 - P.cls_start[c] + P.bit_start[c]) >> 5;
+#pragma unroll
+    for (int r = 0; r < kBitSlots; ++r) {
+        const uint32_t word = or8_last(nw4[r]);
+        if ((threadIdx.x & 7) == 7 && qg < q1) W[4 * wg + r] = word;
     }
 }
 
@@ -829,10 +871,14 @@ __device__ __forceinline__ void round_sweep_bits_body(const DevProblem &P, int s
             int dfa[kBitSlots], dga[kBitSlots];
 #pragma unroll
             for (int r = 0; r < kBitSlots; ++r) { dfa[r] = 0; dga[r] = 0; }
-            for (int q = q0 + tid; q < q1; q += nthr) {
-                const int rem = live_end - q * 4;
-                const unsigned live = rem >= 4 ? 15u : ((1u << rem) - 1u);
-                bits_update_quad<WD>(P, Rs, W, q, c, live, t, sp, ns, dfa, dga);
+            // a wave runs while any of its lanes has a quad; lanes past the
+            // class end update their (clamped) quad with no live spin
+            const int wave0 = tid & ~63;
+            for (int base = q0; base + wave0 < q1; base += nthr) {
+                const int q = base + tid;
+                const int rem = q < q1 ? live_end - q * 4 : 0;
+                const unsigned live = rem >= 4 ? 15u : rem <= 0 ? 0u : ((1u << rem) - 1u);
+                bits_update_quad<WD>(P, Rs, W, q, q1, c, live, t, sp, dfa, dga);
             }
 #pragma unroll
             for (int r = 0; r < kBitSlots; ++r) { df[r] += dfa[r]; dg[r] += dga[r]; }
@@ -869,14 +915,14 @@ __device__ __forceinline__ void round_sweep_bits_body(const DevProblem &P, int s
 }
 
 template <int WD>
-__global__ __launch_bounds__(kMaxBlock) void k_round_sweep_bits(DevProblem P)
+__global__ __launch_bounds__(kBitsBlock) void k_round_sweep_bits(DevProblem P)
 {
     extern __shared__ __align__(16) int8_t lds[];
     round_sweep_bits_body<WD>(P, blockIdx.x * kBitSlots, lds);
 }
 
 template <int WD>
-__global__ __launch_bounds__(kMaxBlock) void k_batch_sweep_bits(const DevProblem *__restrict__ table,
+__global__ __launch_bounds__(kBitsBlock) void k_batch_sweep_bits(const DevProblem *__restrict__ table,
                                                               const int *__restrict__ first_block, int count)
 {
     extern __shared__ __align__(16) int8_t lds[];
@@ -1098,8 +1144,8 @@ static hipError_t sweep_bits_t(const DevProblem &p, hipStream_t s)
     const size_t lds = bits_lds(p.n_words);
     hipError_t e = allow_lds(k_round_sweep_bits<WD>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_round_sweep_bits<WD>), dim3((p.R + kBitSlots - 1) / kBitSlots), dim3(p.block), lds,
-                       s, p);
+    hipLaunchKernelGGL((k_round_sweep_bits<WD>), dim3((p.R + kBitSlots - 1) / kBitSlots),
+                       dim3(min(p.block, kBitsBlock)), lds, s, p);
     return hipGetLastError();
 }
 
@@ -1111,7 +1157,8 @@ static hipError_t batch_sweep_bits_t(const DevProblem &p, const DevProblem *tabl
     const size_t lds = bits_lds(max_words);
     hipError_t e = allow_lds(k_batch_sweep_bits<WD>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_batch_sweep_bits<WD>), dim3(blocks), dim3(block), lds, s, table, first_block, count);
+    hipLaunchKernelGGL((k_batch_sweep_bits<WD>), dim3(blocks), dim3(min(block, kBitsBlock)), lds, s, table,
+                       first_block, count);
     return hipGetLastError();
 }
 

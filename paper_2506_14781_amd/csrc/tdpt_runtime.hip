@@ -67,6 +67,7 @@ struct tdpt_instance {
     std::vector<int32_t> bias;          // [n_pad]
     int32_t has_bias = 0;
     int64_t max_field = 0;   // max_i sum_j |J_ij| + |b_i|
+    int64_t max_abs_J = 0;   // max |J_ij|
     int64_t abs_f_bound = 0; // sum_{i<j} |J_ij| + sum_i |b_i|
     int32_t max_class_quads = 0;
 };
@@ -354,6 +355,7 @@ int tdpt_instance_create(int32_t n, const int32_t *row_ptr, const int32_t *col, 
             in->nb_idx[(size_t)k * n_pad + r] = in->rank[col[e]];
             in->nb_J[(size_t)k * n_pad + r] = J_q[e];
             field += std::llabs((long long)J_q[e]);
+            in->max_abs_J = std::max(in->max_abs_J, (int64_t)std::llabs((long long)J_q[e]));
             if (J_q[e] < -32768 || J_q[e] > 32767) narrow = false;
             if (col[e] > v) absf += std::llabs((long long)J_q[e]);
         }
@@ -422,7 +424,9 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     const int64_t pmax = cfg->p_q[J - 1];
     if (in->max_field + 4 * pmax >= ((int64_t)1 << 31))
         return fail(TDPT_E_RANGE, "local field can reach 2^31");
-    const int64_t blk = std::min(sweep_block(in, false), sweep_block(in, true));
+    const bool bits = use_bits(in);
+    const int64_t blk = bits ? std::min(sweep_block(in, false), tdpt::kBitsBlock)
+                             : std::min(sweep_block(in, false), sweep_block(in, true));
     const int64_t quads_per_thread = (in->max_class_quads + blk - 1) / blk;
     if (quads_per_thread * 4 * 2 * (in->max_field + 4 * pmax) >= ((int64_t)1 << 31))
         return fail(TDPT_E_RANGE, "per-phase energy change can reach 2^31");
@@ -435,7 +439,6 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev),
             "hipDeviceGetAttribute");
     const size_t lds_limit = std::max((size_t)lds_max, (size_t)65536) - 1024;
-    const bool bits = use_bits(in);
     int32_t bit_start[tdpt::kMaxColors + 1];
     bit_start[0] = 0;
     for (int c = 0; c < in->n_colors; ++c)
@@ -443,6 +446,8 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     const int32_t n_words = bit_start[in->n_colors] / 32;
     if (bits && in->max_deg > 8)
         return fail(TDPT_E_INVALID, "the bit-packed layout takes at most 8 problem neighbours per spin");
+    if (bits && in->max_abs_J >= ((int64_t)1 << 23))
+        return fail(TDPT_E_RANGE, "the bit-packed layout takes couplings |J_q| < 2^23");
     if (bits ? (size_t)n_words * 16 + 4096 > lds_limit : (size_t)L.stride > lds_limit)
         return fail(TDPT_E_INVALID, "a replica (" + std::to_string(in->n_pad) +
                                         " spins) does not fit the LDS of one workgroup");
@@ -473,7 +478,7 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     d.wd = L.wd;
     d.narrow = narrow ? 1 : 0;
     d.has_bias = in->has_bias;
-    d.block = sweep_block(in, false);
+    d.block = bits ? std::min(sweep_block(in, false), tdpt::kBitsBlock) : sweep_block(in, false);
     d.bits = bits ? 1 : 0;
     d.n_words = n_words;
     for (int c = 0; c <= in->n_colors; ++c) d.bit_start[c] = bit_start[c];

@@ -43,6 +43,9 @@ class Request:
     best_f: int | None = None
     problem: "T.Problem | None" = None
     footprint: int = 0
+    # optional reference for reporting: ground-state f_q and logical size
+    f_ref: int | None = None
+    n_logical: int = 0
 
 
 def _advance(req: Request, rounds: int, t0: float, t1: float, elapsed_base: float):
@@ -195,4 +198,13 @@ def summarize(requests, total_seconds: float):
     if lat:
         out["latency_p50_s"] = float(np.percentile(lat, 50))
         out["latency_p99_s"] = float(np.percentile(lat, 99))
+    # best feasible bottom-right energy reached, as residual energy per
+    # logical spin above the reference (rho_E), where a reference is known
+    feasible = [r for r in requests if r.best_f is not None and r.best_f < (1 << 62)]
+    out["feasible_fraction"] = len(feasible) / max(len(requests), 1)
+    rho = [(r.best_f - r.f_ref) / (4096.0 * r.n_logical) for r in feasible
+           if r.f_ref is not None and r.n_logical > 0]
+    if rho:
+        out["best_rho_E_p50"] = float(np.percentile(rho, 50))
+        out["best_rho_E_max"] = float(np.max(rho))
     return out
