@@ -159,7 +159,7 @@ def _mirror_holders(N: int, D: int, L: int, i: int):
 
 
 def sparsify(Jq_logical: np.ndarray, *, degree_cap: int | None = None,
-             copies: int | None = None, order: str = "mirror"):
+             copies: int | None = None, order: str = "mirror", numbering: str = "copy"):
     """Copy-chain sparsification of a dense symmetric logical coupling matrix.
 
     Exactly one of degree_cap / copies is given.  The paper leaves open how a
@@ -175,9 +175,18 @@ def sparsify(Jq_logical: np.ndarray, *, degree_cap: int | None = None,
 
     copies: every chain has that many copies and the neighbours (circular
     order) are split into near-equal contiguous groups.  Couplings that are
-    zero are not edges.  Returns (row_ptr, col, Jq, copy_a, copy_b,
-    logical_of, copy_index).
+    zero are not edges.
+
+    numbering: how physical spins are numbered.  "copy" (copy-major): all
+    copies 0 in logical order, then all copies 1, ..; with the mirror
+    embedding the k-th neighbour of copy c of node i is then node i + d_k
+    on one fixed copy, so spins with consecutive numbers have neighbours
+    with consecutive numbers.  "logical": the copies of node 0, then of
+    node 1, ..  Returns (row_ptr, col, Jq, copy_a, copy_b, logical_of,
+    copy_index).
     """
+    if numbering not in ("copy", "logical"):
+        raise ValueError("numbering must be 'copy' or 'logical'")
     Jq_logical = np.asarray(Jq_logical)
     N = Jq_logical.shape[0]
     if (degree_cap is None) == (copies is None):
@@ -220,16 +229,28 @@ def sparsify(Jq_logical: np.ndarray, *, degree_cap: int | None = None,
     n = int(off[-1])
     logical_of = np.repeat(np.arange(N), L).astype(np.int32)
     copy_index = (np.arange(n) - off[logical_of]).astype(np.int32)
+    # number of each (node, copy) spin: logical-major first, then renumbered
+    if numbering == "copy":
+        old_of_new = np.lexsort((logical_of, copy_index))
+    else:
+        old_of_new = np.arange(n)
+    new_of_old = np.empty(n, dtype=np.int64)
+    new_of_old[old_of_new] = np.arange(n)
     rows, cols, vals = [], [], []
     for i in range(N):
         for j in np.flatnonzero(holder[i] >= 0):
             rows.append(off[i] + holder[i][j])
             cols.append(off[j] + holder[j][i])
             vals.append(Jq_logical[i, j])
-    rows = np.asarray(rows, dtype=np.int64)
-    cols = np.asarray(cols, dtype=np.int64)
+    rows = new_of_old[np.asarray(rows, dtype=np.int64)]
+    cols = new_of_old[np.asarray(cols, dtype=np.int64)]
     vals = np.asarray(vals, dtype=np.int32)
-    srt = np.lexsort((cols, rows))
+    # within a row, neighbours in increasing circular offset of their node
+    # (for the mirror embedding the k-th neighbour of every copy c spin then
+    # has the same offset), then by number
+    lnew = logical_of[old_of_new]
+    offset = (lnew[cols] - lnew[rows]) % N
+    srt = np.lexsort((cols, offset, rows))
     rows, cols, vals = rows[srt], cols[srt], vals[srt]
     row_ptr = np.zeros(n + 1, dtype=np.int32)
     np.add.at(row_ptr, rows + 1, 1)
@@ -239,8 +260,10 @@ def sparsify(Jq_logical: np.ndarray, *, degree_cap: int | None = None,
         for c in range(int(L[i]) - 1):
             ca.append(off[i] + c)
             cb.append(off[i] + c + 1)
-    return (row_ptr, cols.astype(np.int32), vals, np.asarray(ca, dtype=np.int32),
-            np.asarray(cb, dtype=np.int32), logical_of, copy_index)
+    ca = new_of_old[np.asarray(ca, dtype=np.int64)]
+    cb = new_of_old[np.asarray(cb, dtype=np.int64)]
+    return (row_ptr, cols.astype(np.int32), vals, ca.astype(np.int32), cb.astype(np.int32),
+            logical_of[old_of_new].astype(np.int32), copy_index[old_of_new].astype(np.int32))
 
 
 def _adjacency(n, row_ptr, col, copy_a, copy_b):
@@ -359,8 +382,9 @@ def instance_from_logical(Jq_logical, *, b_logical_q=None, degree_cap=None,
     n = int(logical_of.shape[0])
     b = np.zeros(n, dtype=np.int32)
     if b_logical_q is not None:
-        # the field of a logical node sits on its first copy
-        first = np.concatenate([[0], np.flatnonzero(np.diff(logical_of)) + 1])
+        # the field of a logical node sits on its copy 0
+        first = np.flatnonzero(cidx == 0)
+        first = first[np.argsort(logical_of[first], kind="stable")]
         b[first] = np.asarray(b_logical_q, dtype=np.int32)
     color = parity_coloring_if_proper(n, row_ptr, col, ca, cb, cidx)
     if color is None:
