@@ -33,12 +33,16 @@ if ROOT not in sys.path:
 
 # MI355X: 256 compute units x 4 SIMD x 16 lanes x 2.4 GHz of 32-bit VALU lanes
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
-PEAK_HBM = 8.0e12  # bytes/s
 
 # HBM bytes per swap round of each workload's dominant kernel, from rocprofv3
 # FETCH_SIZE (x2.00) and WRITE_SIZE (x1.00) counters scaled against a plain
 # copy of known size; valid for the kernel source with this hash.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    # one 200-round launch on the N=200 workload: FETCH 15,221.1 KiB, WRITE 11,957.0 KiB
+    "k_persistent": {"kernel_sha256": "f66b4ad612f321da", "bytes_per_round": 217084},
+    # one 50-sweep round on the N=1000 workload: FETCH 5,328,645.9 KiB, WRITE 505,859.8 KiB
+    "k_round_sweep_bits": {"kernel_sha256": "f66b4ad612f321da", "bytes_per_round": 11431067238},
+}
 KERNEL_SRC = os.path.join(ROOT, "paper_2506_14781_amd", "csrc", "tdpt_kernels.hip")
 
 
@@ -59,7 +63,8 @@ def alu_ops_per_update(info) -> float:
     one multiply-add per problem neighbour, the copy term (two adds, one
     multiply, one add), the bias add, a quarter of a Philox4x32-10 call
     (ten rounds of two 32x32->64 products = 4 ops, four xors, two key adds),
-    the logistic decision (convert, scale, exp2, add, reciprocal, compare)
+    the logistic decision (convert, scale, exp2, convert the uniform,
+    multiply-add, compare)
     and the bookkeeping of the exact f and g (spin difference, two
     multiply-adds, store)."""
     d_problem = info["nnz"] / info["n"]
@@ -193,6 +198,21 @@ def bench_serving(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_copy():
+    """One plain device copy of 256 MiB (the runtime's copy kernel): the
+    FETCH_SIZE / WRITE_SIZE counters of this dispatch give the factors by
+    which the counters of the sweep kernels are scaled to bytes."""
+    import torch
+    n = 256 << 20
+    x = torch.empty(n, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": "copy", "bytes_read": n, "bytes_written": n}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,7 +222,9 @@ def main():
     ap.add_argument("--cpu-rounds", type=int, default=None,
                     help="rounds of the oracle timed for the CPU baseline (0: skip; n200: 100, n1000: 1)")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", choices=["n200", "n1000", "batched", "serving"], default="n200")
+    ap.add_argument("--workload", choices=["n200", "n1000", "batched", "serving", "copy"], default="n200",
+                    help="copy: one plain 256 MiB device-to-device copy, the reference the HBM "
+                         "traffic counters are scaled against")
     ap.add_argument("--count", type=int, default=64, help="instances (batched) / requests (serving)")
     ap.add_argument("--cap-sweeps", type=int, default=50000)
     ap.add_argument("--chunk", type=int, default=10, help="rounds between host checks")
@@ -235,6 +257,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.workload == "copy":
+        return bench_copy()
     if args.workload == "batched":
         return bench_batched(args)
     if args.workload == "serving":
@@ -275,23 +299,21 @@ def main():
     # the library keeps a replica as int8 in LDS up to 48 KiB, as bits beyond
     bits = os.environ.get("TDPT_LAYOUT") == "bits" or (info["n_pad"] + 1 + 15) // 16 * 16 > 48 * 1024
     kernel = "k_persistent" if persistent else ("k_round_sweep_bits" if bits else "k_round_sweep")
+    # Both layouts are bound by VALU arithmetic: the replica spins stay in
+    # LDS and the structure is served from L2 (the measured HBM traffic is
+    # a small fraction of the structure bytes the sweeps read).
+    ops = alu_ops_per_update(info)
+    achieved = ops * updates_per_launch / (launch_ms / 1e3)
+    roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 3),
+                "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "Tlane-op/s",
+                "frac": round(achieved / PEAK_LANE_OPS, 4),
+                "traffic": measured_traffic(kernel, timed_rounds // max(timed, 1)),
+                "ops_per_update": round(ops, 2)}
     if bits:
-        # structure streamed from L2 / MALL / HBM: bound by memory bandwidth
         wd = max(1, info["max_degree"]) if info["max_degree"] <= 8 else 16
         bpu = bits_bytes_per_update(info, wd)
-        achieved = bpu * updates_per_launch / (launch_ms / 1e3)
-        roofline = {"bound": "hbm", "achieved": round(achieved / 1e9, 1), "peak": PEAK_HBM / 1e9,
-                    "unit": "GB/s", "frac": round(achieved / PEAK_HBM, 4),
-                    "traffic": measured_traffic(kernel, timed_rounds // max(timed, 1)),
-                    "bytes_per_update": round(bpu, 3)}
-    else:
-        ops = alu_ops_per_update(info)
-        achieved = ops * updates_per_launch / (launch_ms / 1e3)
-        roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 3),
-                    "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "Tlane-op/s",
-                    "frac": round(achieved / PEAK_LANE_OPS, 4),
-                    "traffic": measured_traffic(kernel, timed_rounds // max(timed, 1)),
-                    "ops_per_update": round(ops, 2)}
+        roofline["structure_bytes_per_update"] = round(bpu, 3)
+        roofline["structure_GBps"] = round(bpu * updates_per_launch / (launch_ms / 1e3) / 1e9, 1)
     roofline.update({"kernel": kernel, "kernel_avg_ms": round(launch_ms, 5),
                      "kernel_launches_timed": timed, "updates_per_launch": updates_per_launch})
     q = prob.query()
