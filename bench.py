@@ -91,8 +91,19 @@ def cpu_baseline(w, rounds: int, sub_grid: int = 0) -> dict:
     grid = f"{len(beta)}x{len(p_q)} corner of the grid" if sub_grid else f"all {R} replicas"
     return {"value": updates / dt, "unit": "spin-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{w.name}: first {rounds} rounds x {w.mcs_per_swap} sweep(s) of {grid}, "
-                      f"seed 0, single-threaded plain C ({platform.processor() or platform.machine()})",
+                      f"seed 0, single-threaded plain C ({_cpu_model()})",
             "seconds": round(dt, 3)}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
 
 
 def bits_bytes_per_update(info, wd: int) -> float:
@@ -244,7 +255,7 @@ def main():
 
     big = args.workload == "n1000"
     for name, small, large in [("steps", 100, 5), ("warmup", 5, 1), ("rounds_per_step", 1000, 4),
-                               ("cpu_rounds", 100, 1)]:
+                               ("cpu_rounds", 100, 2)]:
         if getattr(args, name) is None:
             setattr(args, name, large if big else small)
 
@@ -344,7 +355,7 @@ def main():
         "roofline": roofline,
     }
     if args.cpu_rounds > 0:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_rounds, sub_grid=2 if big else 0)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_rounds, sub_grid=4 if big else 0)
     print(json.dumps(out), flush=True)
 
 
