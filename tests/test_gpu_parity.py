@@ -208,7 +208,7 @@ def _with_env(key, value, fn):
 
 
 def test_n200_prefix_bit_exact(T):
-    """N=200 planted Wishart (6600 spins), 32x16 grid, a swap every sweep:
+    """N=200 planted Wishart (6800 spins), 32x16 grid, a swap every sweep:
     the first rounds are bit-exact in the launch configuration the benchmark
     times (the persistent driver)."""
     w = wishart_n200()
@@ -237,6 +237,7 @@ def test_drivers_agree_on_the_small_workload(T):
     qa, qb = a.query(), b.query()
     qa.pop("driver"), qb.pop("driver")
     assert qa == qb
+    assert np.array_equal(a.best()[0], b.best()[0])
 
 
 @pytest.mark.parametrize("driver,block", [("0", "64"), ("0", "256"), ("0", "1024"),
