@@ -209,6 +209,97 @@ def bench_serving(args):
     print(json.dumps(out), flush=True)
 
 
+def _planted_f(T, w) -> int:
+    """f_q of the planted state (the ground state), computed on the GPU."""
+    inst = T.Instance.from_synth(w.instance)
+    planted = np.tile(w.instance.physical_state(w.instance.planted), w.replicas)
+    probe = T.Problem(inst, T.RunConfig(w.beta, w.p_q, mcs_per_swap=w.mcs_per_swap, seed=0, s0=planted))
+    f = int(probe.energies()[0][0])
+    probe.close()
+    return f
+
+
+def bench_jcolumn(args):
+    """2D-PT against J-column PT (the same beta ladder repeated over J
+    columns at the mean penalty, best feasible picked afterwards) on planted
+    Wishart instances with three copies per node, equal replicas and
+    sweeps.  Per logical size: residual energy rho_E = (E - E_gs) / N of the
+    best feasible bottom-right state so far at log-spaced sweep counts
+    (median over instances), time to the planted ground state, and how often
+    the coldest replica is feasible."""
+    import paper_2506_14781_amd as T
+    from paper_2506_14781_amd import jcolumn as JC
+    from synth.configs import jcolumn_member
+    sizes = [int(x) for x in args.sizes.split(",")]
+    cap_rounds = args.cap_sweeps // 50
+    checkpoints = sorted({max(1, int(round(c / 50))) for c in
+                          np.geomspace(100, args.cap_sweeps, 9)} | {cap_rounds})
+    out_sizes = {}
+    t_start = time.perf_counter()
+    for N in sizes:
+        members = [jcolumn_member(N, 20000 + k) for k in range(args.count)]
+        two_d, cols = [], []
+        for k, w in enumerate(members):
+            f_gs = _planted_f(T, w)
+            inst = T.Instance.from_synth(w.instance)
+            cfg = T.RunConfig(w.beta, w.p_q, mcs_per_swap=50, seed=k, f_target=f_gs, trace_cap=cap_rounds)
+            two_d.append((w, f_gs, T.Problem(inst, cfg)))
+            cols.append([T.Problem(inst, c) for c in
+                         JC.column_configs(w.beta, w.p_q, mcs_per_swap=50, seed=k, f_target=f_gs,
+                                           trace_cap=cap_rounds)])
+        everything = [p for _, _, p in two_d] + [p for cs in cols for p in cs]
+        batch = T.Batch(len(everything))
+        batch.set_members(everything)
+        done = 0
+        rho2, rhoj = {}, {}
+        for c in checkpoints:
+            batch.run(c - done)
+            done = c
+            r2, rj = [], []
+            for (w, f_gs, p2), cs in zip(two_d, cols):
+                b2 = p2.query()["best_f_q"]
+                bj = JC.best_feasible(cs)
+                r2.append((b2 - f_gs) / (4096.0 * N) if b2 < (1 << 62) else np.nan)
+                rj.append((bj - f_gs) / (4096.0 * N) if bj is not None else np.nan)
+            rho2[c * 50] = r2
+            rhoj[c * 50] = rj
+        hit2 = [p2.query()["first_hit_sweep"] for _, _, p2 in two_d]
+        hitj = [JC.first_hit(cs) for cs in cols]
+        feas2 = [float(np.mean(p2.trace()[1] == 0)) for _, _, p2 in two_d]
+        featj = [float(np.mean([np.mean(p.trace()[1] == 0) for p in cs])) for cs in cols]
+
+        def med(v):
+            v = np.asarray(v, dtype=np.float64)
+            return None if np.all(np.isnan(v)) else round(float(np.nanmedian(v)), 5)
+
+        def hits(h):
+            h = [x for x in h if x >= 0]
+            return {"fraction": len(h) / len(members),
+                    "sweeps_p50": float(np.percentile(h, 50)) if h else None}
+        out_sizes[str(N)] = {
+            "n_spins": members[0].instance.n, "grid": f"{members[0].n_beta}x{members[0].n_p}",
+            "instances": len(members),
+            "rho_E_2dpt": {str(k): med(v) for k, v in rho2.items()},
+            "rho_E_jcolumn": {str(k): med(v) for k, v in rhoj.items()},
+            "feasible_at_sweep_2dpt": {str(k): float(np.mean(~np.isnan(v))) for k, v in rho2.items()},
+            "feasible_at_sweep_jcolumn": {str(k): float(np.mean(~np.isnan(v))) for k, v in rhoj.items()},
+            "planted_gs_2dpt": hits(hit2), "planted_gs_jcolumn": hits(hitj),
+            "coldest_feasible_fraction_2dpt": round(float(np.mean(feas2)), 4),
+            "coldest_feasible_fraction_jcolumn": round(float(np.mean(featj)), 4),
+        }
+        print(f"[bench] jcolumn N={N}: {out_sizes[str(N)]}", file=sys.stderr, flush=True)
+        batch.close()
+        for p in everything:
+            p.close()
+    out = {"metric": "residual energy vs sweeps, 2D-PT vs J-column PT", "value": None, "unit": "rho_E",
+           "higher_is_better": False, "n_gpus": 1,
+           "data": "synthetic (seeded planted Wishart, alpha 0.75, three copies per node)",
+           "config": {"workload": f"J-column comparison, {args.count} instances per size, "
+                                  f"cap {args.cap_sweeps} sweeps, 50 sweeps per swap"},
+           "seconds": round(time.perf_counter() - t_start, 1), "sizes": out_sizes}
+    print(json.dumps(out), flush=True)
+
+
 def bench_copy():
     """One plain device copy of 256 MiB (the runtime's copy kernel): the
     FETCH_SIZE / WRITE_SIZE counters of this dispatch give the factors by
@@ -233,7 +324,9 @@ def main():
     ap.add_argument("--cpu-rounds", type=int, default=None,
                     help="rounds of the oracle timed for the CPU baseline (0: skip; n200: 100, n1000: 1)")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", choices=["n200", "n1000", "batched", "serving", "copy"], default="n200",
+    ap.add_argument("--sizes", type=str, default="16,24,32,48", help="logical sizes (jcolumn)")
+    ap.add_argument("--workload", choices=["n200", "n1000", "batched", "serving", "jcolumn", "copy"],
+                    default="n200",
                     help="copy: one plain 256 MiB device-to-device copy, the reference the HBM "
                          "traffic counters are scaled against")
     ap.add_argument("--count", type=int, default=64, help="instances (batched) / requests (serving)")
@@ -270,6 +363,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "copy":
         return bench_copy()
+    if args.workload == "jcolumn":
+        return bench_jcolumn(args)
     if args.workload == "batched":
         return bench_batched(args)
     if args.workload == "serving":

@@ -109,3 +109,12 @@ def serving_member(N: int, alpha: float, seed: int, sweeps: int) -> Workload:
     return Workload(f"serve-N{N}-D6-{I}x{J}-s{seed}", _inst(N, alpha, seed, 6),
                     geometric_betas(0.1, 8.0, I), linear_penalties_q(0, 6, J),
                     50, sweeps, seed)
+
+
+def jcolumn_member(N: int, seed: int) -> Workload:
+    """A planted Wishart instance as in the paper's 2D-PT vs J-column PT
+    comparison: alpha 0.75, three copies per node, 50 sweeps per swap; a
+    16 x 8 grid (beta geometric 0.1..8, P linear 0..6)."""
+    inst = build_instance(N, 0.75, seed, copies=3)
+    return Workload(f"wishart-N{N}-c3-16x8-s{seed}", inst, geometric_betas(0.1, 8.0, 16),
+                    linear_penalties_q(0, 6, 8), 50, 0, seed)

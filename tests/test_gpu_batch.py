@@ -125,3 +125,27 @@ def test_serving_results_equal_alone(T):
     for r, a in zip(reqs, alone):
         assert r.rounds_done == r.max_rounds
         assert np.array_equal(keep[r.name], a), r.name
+
+
+def test_jcolumn_columns_equal_the_oracle(T):
+    """J-column PT: every column, run in one batch with a 2D-PT problem, is
+    the oracle's I x 1 run with the mean penalty and the column's seed."""
+    from paper_2506_14781_amd import jcolumn as JC
+    from synth.configs import jcolumn_member
+    w = jcolumn_member(16, 20001)
+    beta, p_q = w.beta[:6], w.p_q[:4]
+    inst = T.Instance.from_synth(w.instance)
+    cfgs = JC.column_configs(beta, p_q, mcs_per_swap=5, seed=7, trace_cap=8)
+    cols = [T.Problem(inst, c) for c in cfgs]
+    two_d = T.Problem(inst, T.RunConfig(beta, p_q, mcs_per_swap=5, seed=7, trace_cap=8))
+    B = T.Batch(8)
+    B.set_members([two_d] + cols)
+    _say("[batch] J-column columns")
+    B.run(8)
+    for j, (c, P) in enumerate(zip(cfgs, cols)):
+        o = O.run(w.instance, beta, c.p_q, mcs_per_swap=5, n_rounds=8, seed=c.seed, trace=True)
+        assert np.array_equal(P.states(), o["states"]), j
+        f, g = P.energies()
+        assert np.array_equal(f, o["f"]) and np.array_equal(g, o["g"]), j
+    o = O.run(w.instance, beta, p_q, mcs_per_swap=5, n_rounds=8, seed=7, trace=True)
+    assert np.array_equal(two_d.states(), o["states"])
