@@ -300,6 +300,48 @@ def bench_jcolumn(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_kl(args):
+    """Fig. 2 on a stand-in instance: KL divergence between the bottom-right
+    replica's logical-state histogram (one sample per round of 500 sweeps)
+    and the exact Boltzmann distribution, with P-swaps and without, against
+    the independent-sample level (2^N - 1) / (2 t)."""
+    import paper_2506_14781_amd as T
+    from paper_2506_14781_amd import sampling as S
+    from synth.configs import fig2_workload
+    w = fig2_workload(rounds=args.kl_rounds)
+    inst = T.Instance.from_synth(w.instance)
+    target = S.boltzmann_logical(w.instance.J_logical_q, w.instance.b_logical_q, float(w.beta[0]))
+    fc = S.first_copies(w.instance.logical_of)
+    checkpoints = sorted({int(c) for c in np.geomspace(10, args.kl_rounds, 12)})
+    runs = {}
+    t0 = time.perf_counter()
+    for label, flags in [("p_swaps", 0), ("no_p_swaps", T.NO_PSWAP)]:
+        kls = []
+        for seed in range(args.kl_seeds):
+            prob = T.Problem(inst, T.RunConfig(w.beta, w.p_q, mcs_per_swap=w.mcs_per_swap, seed=seed,
+                                               flags=flags))
+            _, snaps = S.sample_bottom_right(prob, args.kl_rounds, fc, checkpoints)
+            kls.append([S.kl_divergence(snaps[c], target) for c in checkpoints])
+            prob.close()
+        kls = np.array(kls)
+        first_below_1 = []
+        for row in kls:
+            below = [c for c, k in zip(checkpoints, row) if k < 1.0]
+            first_below_1.append(below[0] * w.mcs_per_swap if below else None)
+        runs[label] = {"kl_mean": {str(c * w.mcs_per_swap): round(float(m), 5)
+                                   for c, m in zip(checkpoints, kls.mean(axis=0))},
+                       "sweeps_to_kl_below_1": first_below_1}
+        print(f"[bench] kl {label}: {runs[label]['kl_mean']}", file=sys.stderr, flush=True)
+    iid = {str(c * w.mcs_per_swap): round((len(target) - 1) / (2.0 * c), 5) for c in checkpoints}
+    out = {"metric": "KL divergence of the last replica vs sweeps", "value": None, "unit": "nats",
+           "higher_is_better": False, "n_gpus": 1,
+           "data": "synthetic (5-node all-to-all stand-in, two copies per node)",
+           "config": {"workload": f"{w.name}, 1x4 grid, P 2..8, 500 sweeps per swap, "
+                                  f"{args.kl_rounds} rounds, {args.kl_seeds} seeds"},
+           "seconds": round(time.perf_counter() - t0, 1), "iid_level": iid, "runs": runs}
+    print(json.dumps(out), flush=True)
+
+
 def bench_copy():
     """One plain device copy of 256 MiB (the runtime's copy kernel): the
     FETCH_SIZE / WRITE_SIZE counters of this dispatch give the factors by
@@ -325,7 +367,9 @@ def main():
                     help="rounds of the oracle timed for the CPU baseline (0: skip; n200: 100, n1000: 1)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--sizes", type=str, default="16,24,32,48", help="logical sizes (jcolumn)")
-    ap.add_argument("--workload", choices=["n200", "n1000", "batched", "serving", "jcolumn", "copy"],
+    ap.add_argument("--kl-rounds", type=int, default=2000, help="rounds of 500 sweeps (kl)")
+    ap.add_argument("--kl-seeds", type=int, default=4, help="independent runs per setting (kl)")
+    ap.add_argument("--workload", choices=["n200", "n1000", "batched", "serving", "jcolumn", "kl", "copy"],
                     default="n200",
                     help="copy: one plain 256 MiB device-to-device copy, the reference the HBM "
                          "traffic counters are scaled against")
@@ -365,6 +409,8 @@ def main():
         return bench_copy()
     if args.workload == "jcolumn":
         return bench_jcolumn(args)
+    if args.workload == "kl":
+        return bench_kl(args)
     if args.workload == "batched":
         return bench_batched(args)
     if args.workload == "serving":

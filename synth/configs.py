@@ -13,8 +13,8 @@ import math
 
 import numpy as np
 
-from .instances import (Instance, build_instance, geometric_betas,
-                        linear_penalties_q)
+from .instances import (Instance, build_instance, geometric_betas, instance_from_logical,
+                        linear_penalties_q, q12)
 
 
 @dataclasses.dataclass
@@ -118,3 +118,19 @@ def jcolumn_member(N: int, seed: int) -> Workload:
     inst = build_instance(N, 0.75, seed, copies=3)
     return Workload(f"wishart-N{N}-c3-16x8-s{seed}", inst, geometric_betas(0.1, 8.0, 16),
                     linear_penalties_q(0, 6, 8), 50, 0, seed)
+
+
+def fig2_workload(seed: int = 0, rounds: int = 2000) -> Workload:
+    """The sampling experiment of Fig. 2 on a stand-in instance: a 5-node
+    all-to-all logical problem (couplings ~ N(0, 1), fields ~ N(0, 0.5^2),
+    Q12; the paper's full-adder couplings are not given), two copies per node
+    under degree cap 3 (10 physical spins), one row at beta = 1, penalties
+    {2, 4, 6, 8}, a P-swap step every 500 sweeps."""
+    rng = np.random.default_rng(1000 + seed)
+    A = np.triu(rng.normal(0.0, 1.0, size=(5, 5)), 1)
+    Jq = q12(A + A.T)
+    np.fill_diagonal(Jq, 0)
+    b = q12(rng.normal(0.0, 0.5, size=5))
+    inst = instance_from_logical(Jq, b_logical_q=b, degree_cap=3)
+    return Workload(f"fig2-standin-N5-s{seed}", inst, np.array([1.0]), q12([2.0, 4.0, 6.0, 8.0]),
+                    500, 500 * rounds, seed)

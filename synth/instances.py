@@ -82,6 +82,7 @@ class Instance:
     N: int
     planted: np.ndarray | None = None
     J_logical_q: np.ndarray | None = None
+    b_logical_q: np.ndarray | None = None
 
     @property
     def n_colors(self) -> int:
@@ -391,7 +392,8 @@ def instance_from_logical(Jq_logical, *, b_logical_q=None, degree_cap=None,
         color = balanced_coloring(n, row_ptr, col, ca, cb)
     return Instance(n=n, row_ptr=row_ptr, col=col, J_q=vals, b_q=b,
                     copy_a=ca, copy_b=cb, color=color, logical_of=logical_of,
-                    N=N, planted=planted, J_logical_q=Jq_logical)
+                    N=N, planted=planted, J_logical_q=Jq_logical,
+                    b_logical_q=None if b_logical_q is None else np.asarray(b_logical_q, dtype=np.int32))
 
 
 def geometric_betas(lo: float, hi: float, count: int) -> np.ndarray:
