@@ -238,6 +238,15 @@ def bench_jcolumn(args):
     t_start = time.perf_counter()
     for N in sizes:
         members = [jcolumn_member(N, 20000 + k) for k in range(args.count)]
+        grids = []
+        if args.schedule == "adaptive":
+            # Algorithm 2 per instance (as the paper does), capped at 20 x 20
+            from paper_2506_14781_amd.adaptive import adaptive_schedule
+            for k, w in enumerate(members):
+                sch = adaptive_schedule(T.Instance.from_synth(w.instance), beta0=0.1, p0=0.0, i_max=20,
+                                        j_max=20, sigma_min=args.sigma_min, n_chain=64, mcs=200, seed=k)
+                w.beta, w.p_q = sch.beta, sch.p_q
+                grids.append(f"{len(sch.beta)}x{len(sch.p_q)}")
         two_d, cols = [], []
         for k, w in enumerate(members):
             f_gs = _planted_f(T, w)
@@ -277,7 +286,8 @@ def bench_jcolumn(args):
             return {"fraction": len(h) / len(members),
                     "sweeps_p50": float(np.percentile(h, 50)) if h else None}
         out_sizes[str(N)] = {
-            "n_spins": members[0].instance.n, "grid": f"{members[0].n_beta}x{members[0].n_p}",
+            "n_spins": members[0].instance.n,
+            "grid": grids if grids else f"{members[0].n_beta}x{members[0].n_p}",
             "instances": len(members),
             "rho_E_2dpt": {str(k): med(v) for k, v in rho2.items()},
             "rho_E_jcolumn": {str(k): med(v) for k, v in rhoj.items()},
@@ -295,7 +305,8 @@ def bench_jcolumn(args):
            "higher_is_better": False, "n_gpus": 1,
            "data": "synthetic (seeded planted Wishart, alpha 0.75, three copies per node)",
            "config": {"workload": f"J-column comparison, {args.count} instances per size, "
-                                  f"cap {args.cap_sweeps} sweeps, 50 sweeps per swap"},
+                                  f"cap {args.cap_sweeps} sweeps, 50 sweeps per swap, "
+                                  f"{args.schedule} schedule"},
            "seconds": round(time.perf_counter() - t_start, 1), "sizes": out_sizes}
     print(json.dumps(out), flush=True)
 
@@ -367,6 +378,9 @@ def main():
                     help="rounds of the oracle timed for the CPU baseline (0: skip; n200: 100, n1000: 1)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--sizes", type=str, default="16,24,32,48", help="logical sizes (jcolumn)")
+    ap.add_argument("--schedule", choices=["fixed", "adaptive"], default="fixed",
+                    help="jcolumn: the workload's beta / P ladders, or Algorithm 2 per instance")
+    ap.add_argument("--sigma-min", type=float, default=0.5, help="Algorithm 2 energy spread threshold")
     ap.add_argument("--kl-rounds", type=int, default=2000, help="rounds of 500 sweeps (kl)")
     ap.add_argument("--kl-seeds", type=int, default=4, help="independent runs per setting (kl)")
     ap.add_argument("--workload", choices=["n200", "n1000", "batched", "serving", "jcolumn", "kl", "copy"],
