@@ -173,14 +173,18 @@ __device__ __forceinline__ SlotParams slot_params(const DevProblem &P, int pos, 
 }
 
 // Structure of one quad (4 consecutive colour-major spins): one 16-byte
-// load per structure row.
+// load per structure row.  Up to 8 neighbours per spin every row is held at
+// once; wider rows are streamed in chunks by quad_fields (kStream), which
+// keeps them out of spill territory.
 template <bool NARROW, int WD>
 struct QuadS {
-    static constexpr int K = NARROW ? WD / 2 : WD;
+    static constexpr bool kStream = WD > 8;
+    static constexpr int K = kStream ? 1 : (NARROW ? WD / 2 : WD);
     v4i a[K];    // narrow: index pairs; wide: indices
     v4i b[K];    // narrow: coupling pairs; wide: couplings
     v4i c0, c1;  // narrow: copy pairs in c0; wide: two copy rows
     v4i bias;    // fields (zero when the instance has none)
+    int voff;    // byte offset of the quad in a structure row
 };
 
 template <bool NARROW, int WD>
@@ -188,10 +192,13 @@ __device__ __forceinline__ void load_quad(const DevProblem &P, const Rsrc &Rs, i
 {
     const int voff = q * 16;
     const int row = P.n_pad * 4;
+    Q.voff = voff;
+    if constexpr (!QuadS<NARROW, WD>::kStream) {
 #pragma unroll
-    for (int k = 0; k < QuadS<NARROW, WD>::K; ++k) {
-        Q.a[k] = bload(Rs.a, voff, k * row);
-        Q.b[k] = bload(Rs.b, voff, k * row);
+        for (int k = 0; k < QuadS<NARROW, WD>::K; ++k) {
+            Q.a[k] = bload(Rs.a, voff, k * row);
+            Q.b[k] = bload(Rs.b, voff, k * row);
+        }
     }
     Q.c0 = bload(Rs.ch, voff, 0);
     if constexpr (!NARROW) Q.c1 = bload(Rs.ch, voff, row);
@@ -209,11 +216,69 @@ __device__ __forceinline__ int sbyte(uint32_t w, int j)
 // instances keep every field below 2^22, so the 16-bit dot products are
 // exact.
 template <bool NARROW, int WD>
-__device__ __forceinline__ void quad_fields(const int8_t *s, const QuadS<NARROW, WD> &Q, int hp[4], int cs[4])
+__device__ __forceinline__ void quad_fields(const DevProblem &P, const Rsrc &Rs, const int8_t *s,
+                                            const QuadS<NARROW, WD> &Q, int hp[4], int cs[4])
 {
 #pragma unroll
     for (int j = 0; j < 4; ++j) hp[j] = Q.bias[j];
-    if constexpr (NARROW) {
+    if constexpr (QuadS<NARROW, WD>::kStream) {
+        // rows streamed in chunks of kChunk (pairs or neighbours)
+        constexpr int K = NARROW ? WD / 2 : WD;
+        constexpr int kChunk = NARROW ? 4 : 8;
+        const int row = P.n_pad * 4;
+#pragma unroll
+        for (int k0 = 0; k0 < K; k0 += kChunk) {
+            v4i a[kChunk], b[kChunk];
+#pragma unroll
+            for (int c = 0; c < kChunk; ++c)
+                if (k0 + c < K) {
+                    a[c] = bload(Rs.a, Q.voff, (k0 + c) * row);
+                    b[c] = bload(Rs.b, Q.voff, (k0 + c) * row);
+                }
+            if constexpr (NARROW) {
+                int8_t lo[kChunk][4], hi[kChunk][4];
+#pragma unroll
+                for (int c = 0; c < kChunk; ++c)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (k0 + c < K) {
+                            const int iw = a[c][j];
+                            lo[c][j] = s[iw & 0xffff];
+                            hi[c][j] = s[(unsigned)iw >> 16];
+                        }
+#pragma unroll
+                for (int c = 0; c < kChunk; ++c)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (k0 + c < K) {
+                            const int jw = b[c][j];
+                            v2s sv, jv;
+                            sv.x = lo[c][j];
+                            sv.y = hi[c][j];
+                            jv.x = (short)(jw & 0xffff);
+                            jv.y = (short)((unsigned)jw >> 16);
+                            hp[j] = __builtin_amdgcn_sdot2(jv, sv, hp[j], false);
+                        }
+            } else {
+#pragma unroll
+                for (int c = 0; c < kChunk; ++c)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (k0 + c < K) hp[j] += b[c][j] * (int)s[a[c][j]];
+            }
+        }
+        if constexpr (NARROW) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c = Q.c0[j];
+                cs[j] = (int)s[c & 0xffff] + (int)s[(unsigned)c >> 16];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) cs[j] = (int)s[Q.c0[j]] + (int)s[Q.c1[j]];
+        }
+        return;
+    } else if constexpr (NARROW) {
         // every LDS read of the quad is issued before the first product, so
         // their latencies overlap
         int8_t lo[WD / 2][4], hi[WD / 2][4], ca[4], cb[4];
@@ -336,7 +401,7 @@ __device__ __forceinline__ void sweep_round(const DevProblem &P, const Rsrc &Rs,
                 QuadS<NARROW, WD> Q;
                 load_quad<NARROW, WD>(P, Rs, q, Q);
                 int hp[4], cs[4];
-                quad_fields<NARROW, WD>(s, Q, hp, cs);
+                quad_fields<NARROW, WD>(P, Rs, s, Q, hp, cs);
                 const int rem = live_end - q * 4;
                 const uint32_t live_bytes = rem >= 4 ? 0xffffffffu : rem <= 0 ? 0u : ((1u << (8 * rem)) - 1u);
                 quad_update<NARROW>(P, s, q, hp, cs, live_bytes, t, sp, dfa, dga);
@@ -1089,6 +1154,10 @@ static hipError_t persistent_t(const DevProblem &p, int64_t n_rounds, hipStream_
         case 8: return FN<true, 8>(__VA_ARGS__);                            \
         case 12: return FN<true, 12>(__VA_ARGS__);                          \
         case 16: return FN<true, 16>(__VA_ARGS__);                          \
+        case 24: return FN<true, 24>(__VA_ARGS__);                          \
+        case 32: return FN<true, 32>(__VA_ARGS__);                          \
+        case 40: return FN<true, 40>(__VA_ARGS__);                          \
+        case 48: return FN<true, 48>(__VA_ARGS__);                          \
         default: return hipErrorInvalidValue;                               \
         }                                                                   \
     }                                                                       \
@@ -1103,6 +1172,10 @@ static hipError_t persistent_t(const DevProblem &p, int64_t n_rounds, hipStream_
     case 8: return FN<false, 8>(__VA_ARGS__);                               \
     case 12: return FN<false, 12>(__VA_ARGS__);                             \
     case 16: return FN<false, 16>(__VA_ARGS__);                             \
+    case 24: return FN<false, 24>(__VA_ARGS__);                             \
+    case 32: return FN<false, 32>(__VA_ARGS__);                             \
+    case 40: return FN<false, 40>(__VA_ARGS__);                             \
+    case 48: return FN<false, 48>(__VA_ARGS__);                             \
     default: return hipErrorInvalidValue;                                   \
     }
 

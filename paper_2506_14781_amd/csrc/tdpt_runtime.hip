@@ -48,7 +48,8 @@ int ell_width(int deg)
 {
     if (deg <= 8) return std::max(deg, 1);
     if (deg <= 12) return 12;
-    if (deg <= 16) return 16;
+    for (int w = 16; w <= 48; w += 8)
+        if (deg <= w) return w;
     return -1;
 }
 
@@ -335,7 +336,7 @@ int tdpt_instance_create(int32_t n, const int32_t *row_ptr, const int32_t *col, 
     in->wd = ell_width(maxdeg);
     if (in->wd < 0) {
         delete in;
-        return fail(TDPT_E_INVALID, "a spin has more than 16 problem neighbours");
+        return fail(TDPT_E_INVALID, "a spin has more than 48 problem neighbours");
     }
     in->max_copy_deg = 0;
     for (int32_t v = 0; v < n; ++v) in->max_copy_deg = std::max(in->max_copy_deg, cdeg[v]);

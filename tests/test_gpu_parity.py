@@ -143,6 +143,30 @@ def test_wide_layout(T):
          label="wide")
 
 
+@pytest.mark.parametrize("N,driver", [(48, "1"), (64, "0"), (64, "1")])
+def test_streamed_structure_rows(T, N, driver):
+    """More than 8 problem neighbours per spin (three copies per node: 16 at
+    N = 48, 24 at N = 64): structure rows streamed in chunks."""
+    from synth.configs import jcolumn_member
+    w = jcolumn_member(N, 20000)
+    o, P = _with_env("TDPT_PERSISTENT", driver, lambda: both(
+        T, w.instance, w.beta[:6], w.p_q[:4], mcs=3, rounds=8, seed=2,
+        label=f"three copies N={N} driver {driver}"))
+    assert P.query()["driver"] == int(driver)
+
+
+def test_streamed_rows_wide_layout(T):
+    """Couplings beyond int16 (32-bit structure) with 12+ neighbours."""
+    rng = np.random.default_rng(21)
+    A = np.triu(rng.normal(0, 12.0, size=(26, 26)), 1)
+    Jq = q12(A + A.T)
+    np.fill_diagonal(Jq, 0)
+    inst = instance_from_logical(Jq, copies=2)
+    assert np.abs(inst.J_q).max() > 32767 and np.diff(inst.row_ptr).max() > 8
+    both(T, inst, np.array([0.0005, 0.002, 0.004]), q12([0.0, 30.0]), mcs=2, rounds=6, seed=4,
+         label="wide, streamed")
+
+
 def test_chains_only_no_couplings(T):
     inst = instance_from_logical(np.zeros((4, 4), np.int32), copies=3)
     both(T, inst, np.array([0.5, 1.5]), q12([0.0, 1.0]), mcs=3, rounds=20, seed=6,
