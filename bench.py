@@ -38,10 +38,10 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # FETCH_SIZE (x2.00) and WRITE_SIZE (x1.00) counters scaled against a plain
 # copy of known size; valid for the kernel source with this hash.
 MEASURED_TRAFFIC = {
-    # one 200-round launch on the N=200 workload: FETCH 15,221.1 KiB, WRITE 11,957.0 KiB
-    "k_persistent": {"kernel_sha256": "f66b4ad612f321da", "bytes_per_round": 217084},
-    # one 50-sweep round on the N=1000 workload: FETCH 5,328,645.9 KiB, WRITE 505,859.8 KiB
-    "k_round_sweep_bits": {"kernel_sha256": "f66b4ad612f321da", "bytes_per_round": 11431067238},
+    # one 200-round launch on the N=200 workload: FETCH 15,236.4 KiB, WRITE 11,957.0 KiB
+    "k_persistent": {"kernel_sha256": "73e33ad3e1a5354c", "bytes_per_round": 217241},
+    # one 50-sweep round on the N=1000 workload: FETCH 5,328,612.3 KiB, WRITE 505,921.7 KiB
+    "k_round_sweep_bits": {"kernel_sha256": "73e33ad3e1a5354c", "bytes_per_round": 11431061709},
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_2506_14781_amd", "csrc", "tdpt_kernels.hip")
 
