@@ -57,6 +57,15 @@ def _load():
              P, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32]
             + [P] * 3 + [P] * 4 + [P] * 4 + [P, P, ctypes.c_int64])
         _lib.oracle_run.restype = ctypes.c_int
+        _lib.oracle_energy_terms.argtypes = [ctypes.c_int32, P, P, P, P, ctypes.c_int32, P, P, P, P,
+                                             P, P, P]
+        _lib.oracle_run_terms.argtypes = (
+            [ctypes.c_int32, P, P, P, P, ctypes.c_int32, P, P, P, P, P,
+             ctypes.c_int32, P, ctypes.c_int32, P,
+             ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+             P, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32]
+            + [P] * 3 + [P] * 4 + [P] * 4 + [P, P, ctypes.c_int64])
+        _lib.oracle_run_terms.restype = ctypes.c_int
     return _lib
 
 
@@ -88,14 +97,30 @@ def color_rank(color):
     return rank, int(n_pad[0])
 
 
+def _terms(inst):
+    """The instance's general constraint terms as contiguous arrays, or None
+    when its constraint is copy edges."""
+    if getattr(inst, "term_ptr", None) is None:
+        return None
+    return (_c(inst.term_ptr, np.int32), _c(inst.term_idx, np.int32),
+            _c(inst.term_coef, np.int32), _c(inst.term_const, np.int32))
+
+
 def energy(inst, s):
-    """(f_q, g) of one physical state under the instance's couplings."""
+    """(f_q, g) of one physical state under the instance's couplings and
+    constraint."""
     lib = _load()
     s = _c(s, np.int8)
     f = np.zeros(1, dtype=np.int64)
     g = np.zeros(1, dtype=np.int64)
     rp, col, J, b = (_c(inst.row_ptr, np.int32), _c(inst.col, np.int32),
                      _c(inst.J_q, np.int32), _c(inst.b_q, np.int32))
+    T = _terms(inst)
+    if T is not None:
+        tp, ti, tc, td = T
+        lib.oracle_energy_terms(inst.n, _p(rp), _p(col), _p(J), _p(b), tp.shape[0] - 1, _p(tp), _p(ti),
+                                _p(tc), _p(td), _p(s), _p(f), _p(g))
+        return int(f[0]), int(g[0])
     ca, cb = _c(inst.copy_a, np.int32), _c(inst.copy_b, np.int32)
     lib.oracle_energy(inst.n, _p(rp), _p(col), _p(J), _p(b), ca.shape[0], _p(ca), _p(cb),
                       _p(s), _p(f), _p(g))
@@ -153,12 +178,18 @@ def run(inst, beta, p_q, *, mcs_per_swap, n_rounds, seed, s0=None, f_target=None
     tf = np.zeros(max(tcap, 1), dtype=np.int64)
     tg = np.zeros(max(tcap, 1), dtype=np.int64)
     sc = [scal[i:i + 1] for i in range(3)]
-    rc = lib.oracle_run(
-        n, _p(rp), _p(col), _p(J), _p(b), ca.shape[0], _p(ca), _p(cb), _p(color),
-        I, _p(beta), Jn, _p(p_q), int(mcs_per_swap), int(n_rounds), int(seed) & (2**64 - 1),
-        _p(s0a), 0 if f_target is None else 1, 0 if f_target is None else int(f_target), flags,
-        _p(states), _p(f), _p(g), _p(best), _p(sc[0]), _p(sc[1]), _p(sc[2]),
-        _p(p_att), _p(p_acc), _p(b_att), _p(b_acc), _p(tf), _p(tg), tcap)
+    tail = (_p(color),
+            I, _p(beta), Jn, _p(p_q), int(mcs_per_swap), int(n_rounds), int(seed) & (2**64 - 1),
+            _p(s0a), 0 if f_target is None else 1, 0 if f_target is None else int(f_target), flags,
+            _p(states), _p(f), _p(g), _p(best), _p(sc[0]), _p(sc[1]), _p(sc[2]),
+            _p(p_att), _p(p_acc), _p(b_att), _p(b_acc), _p(tf), _p(tg), tcap)
+    T = _terms(inst)
+    if T is not None:
+        tp, ti, tc, td = T
+        rc = lib.oracle_run_terms(n, _p(rp), _p(col), _p(J), _p(b), tp.shape[0] - 1, _p(tp), _p(ti),
+                                  _p(tc), _p(td), *tail)
+    else:
+        rc = lib.oracle_run(n, _p(rp), _p(col), _p(J), _p(b), ca.shape[0], _p(ca), _p(cb), *tail)
     if rc:
         raise RuntimeError("oracle_run failed with code %d" % rc)
     return {

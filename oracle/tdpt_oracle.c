@@ -11,15 +11,25 @@
  *
  * What it computes (paper references are by section / equation / algorithm):
  *   - energy of a replica in penalty column j: E_j = f + P_j g   (Eq. 1)
- *     with f = -sum_{i<j} J_ij s_i s_j - sum_i b_i s_i and
+ *     with f = -sum_{i<j} J_ij s_i s_j - sum_i b_i s_i and either
  *     g = sum over copy edges of (s_a - s_b)^2  (section on graph
  *     sparsification with copy constraints; 4 per violated edge in +-1 form)
+ *     or, for general constraints (Eq. 1 only asks g >= 0 with g = 0 exactly
+ *     on feasible states), a sum of squared integer linear forms
+ *     g = sum_t (sum_{i in t} a_ti s_i + d_t)^2: an equality constraint
+ *     sum_i w_i x_i = c on bits x = (1 + s) / 2 is the form a = w,
+ *     d = sum_i w_i - 2 c (g = 4 (w.x - c)^2); one-hot groups and inequality
+ *     constraints with slack spins, which the introduction names, are of
+ *     this kind, and a copy edge is a = (1, -1), d = 0
  *   - Monte Carlo sweeps: heat-bath single-spin updates visiting colour
  *     classes in ascending order, P(s_i = +1) = sigma(2 beta h_i) with
- *     h_i = sum_j J_ij s_j + b_i + 2 P sum_{copies k of i} s_k
+ *     h_i = sum_j J_ij s_j + b_i + P c_i, where -s_i c_i collects the terms
+ *     of g that depend on s_i: c_i = 2 sum_{copies k of i} s_k for copy
+ *     edges (the ferromagnetic coupling 2P that P (s_a - s_b)^2 amounts
+ *     to), and c_i = -2 sum_{t ni i} a_ti (r_t - a_ti s_i) with
+ *     r_t = sum_{j in t} a_tj s_j + d_t for general constraints
  *     (Algorithm 1 only says "perform sweeps"; heat-bath is the reading
- *     adopted, the copy term being the ferromagnetic coupling 2P that
- *     P (s_a - s_b)^2 amounts to)
+ *     adopted)
  *   - P-swaps along a row: accept with min(1, exp(beta dP dg))    (Eq. 2)
  *   - beta-swaps along a column: accept with min(1, exp(dbeta dE)) (Eq. 3)
  *     (both are the axis cases of the two-replica rule of Appendix A)
@@ -155,6 +165,129 @@ void oracle_energy(int32_t n, const int32_t *row_ptr, const int32_t *col,
     *g_out = g;
 }
 
+/* General constraints: g = sum_t r_t^2 with r_t = sum_{k} a_tk s_{i_tk} + d_t,
+ * term t holding entries term_ptr[t] .. term_ptr[t+1]-1 of term_idx /
+ * term_coef. */
+static int64_t term_residual(const int32_t *term_ptr, const int32_t *term_idx,
+                             const int32_t *term_coef, const int32_t *term_const,
+                             int32_t t, const int8_t *s)
+{
+    int64_t r = term_const[t];
+    for (int32_t e = term_ptr[t]; e < term_ptr[t + 1]; ++e)
+        r += (int64_t)term_coef[e] * s[term_idx[e]];
+    return r;
+}
+
+/* f as in oracle_energy, g = sum_t r_t^2 */
+void oracle_energy_terms(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                         const int32_t *J_q, const int32_t *b_q, int32_t n_terms,
+                         const int32_t *term_ptr, const int32_t *term_idx,
+                         const int32_t *term_coef, const int32_t *term_const,
+                         const int8_t *s, int64_t *f_out, int64_t *g_out)
+{
+    int64_t f, g_unused;
+    oracle_energy(n, row_ptr, col, J_q, b_q, 0, NULL, NULL, s, &f, &g_unused);
+    int64_t g = 0;
+    for (int32_t t = 0; t < n_terms; ++t) {
+        int64_t r = term_residual(term_ptr, term_idx, term_coef, term_const, t, s);
+        g += r * r;
+    }
+    *f_out = f;
+    *g_out = g;
+}
+
+/* The constraint of a run: copy edges (n_terms < 0) or general terms, with
+ * the list of (term, entry) incidences of every spin for the latter. */
+typedef struct {
+    int32_t m;
+    const int32_t *copy_a, *copy_b;
+    int32_t *chain_ptr, *chain_nbr;   /* copy neighbours of every spin */
+    int32_t n_terms;                  /* -1: copy edges */
+    const int32_t *term_ptr, *term_idx, *term_coef, *term_const;
+    int32_t *inc_ptr, *inc_entry;     /* entries of term_idx naming each spin */
+    int32_t *entry_term;              /* term of every entry */
+} oracle_constraint;
+
+static int constraint_init(oracle_constraint *c, int32_t n)
+{
+    c->chain_ptr = c->chain_nbr = c->inc_ptr = c->inc_entry = c->entry_term = NULL;
+    if (c->n_terms < 0) {
+        c->chain_ptr = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+        c->chain_nbr = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * c->m + 1));
+        int32_t *fill = (int32_t *)calloc((size_t)n, sizeof(int32_t));
+        if (!c->chain_ptr || !c->chain_nbr || !fill) { free(fill); return ORACLE_ENOMEM; }
+        for (int32_t e = 0; e < c->m; ++e) {
+            c->chain_ptr[c->copy_a[e] + 1]++;
+            c->chain_ptr[c->copy_b[e] + 1]++;
+        }
+        for (int32_t v = 0; v < n; ++v) c->chain_ptr[v + 1] += c->chain_ptr[v];
+        for (int32_t e = 0; e < c->m; ++e) {
+            int32_t a = c->copy_a[e], b = c->copy_b[e];
+            c->chain_nbr[c->chain_ptr[a] + fill[a]++] = b;
+            c->chain_nbr[c->chain_ptr[b] + fill[b]++] = a;
+        }
+        free(fill);
+        return ORACLE_OK;
+    }
+    const int32_t ne = c->term_ptr[c->n_terms];
+    c->inc_ptr = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+    c->inc_entry = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ne + 1));
+    c->entry_term = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ne + 1));
+    int32_t *fill = (int32_t *)calloc((size_t)n, sizeof(int32_t));
+    if (!c->inc_ptr || !c->inc_entry || !c->entry_term || !fill) { free(fill); return ORACLE_ENOMEM; }
+    for (int32_t t = 0; t < c->n_terms; ++t)
+        for (int32_t e = c->term_ptr[t]; e < c->term_ptr[t + 1]; ++e) {
+            c->entry_term[e] = t;
+            c->inc_ptr[c->term_idx[e] + 1]++;
+        }
+    for (int32_t v = 0; v < n; ++v) c->inc_ptr[v + 1] += c->inc_ptr[v];
+    for (int32_t e = 0; e < ne; ++e) {
+        int32_t v = c->term_idx[e];
+        c->inc_entry[c->inc_ptr[v] + fill[v]++] = e;
+    }
+    free(fill);
+    return ORACLE_OK;
+}
+
+static void constraint_free(oracle_constraint *c)
+{
+    free(c->chain_ptr); free(c->chain_nbr);
+    free(c->inc_ptr); free(c->inc_entry); free(c->entry_term);
+}
+
+/* c_v: the factor of P in spin v's local field (E = -s_v (h_v) + terms free
+ * of s_v).  Copy edges: 2 sum of the copies.  Terms: the part of
+ * (a s_v + rest)^2 that depends on s_v is 2 a s_v rest, so
+ * c_v = -2 sum_t a_tv rest_t with rest_t = r_t - a_tv s_v. */
+static int64_t constraint_field(const oracle_constraint *c, const int8_t *s, int32_t v)
+{
+    if (c->n_terms < 0) {
+        int64_t cs = 0;
+        for (int32_t e = c->chain_ptr[v]; e < c->chain_ptr[v + 1]; ++e) cs += s[c->chain_nbr[e]];
+        return 2 * cs;
+    }
+    int64_t acc = 0;
+    for (int32_t k = c->inc_ptr[v]; k < c->inc_ptr[v + 1]; ++k) {
+        const int32_t e = c->inc_entry[k], t = c->entry_term[e];
+        const int64_t a = c->term_coef[e];
+        const int64_t rest = term_residual(c->term_ptr, c->term_idx, c->term_coef, c->term_const, t, s)
+                             - a * s[v];
+        acc += a * rest;
+    }
+    return -2 * acc;
+}
+
+static void constraint_energy(const oracle_constraint *c, int32_t n, const int32_t *row_ptr,
+                              const int32_t *col, const int32_t *J_q, const int32_t *b_q,
+                              const int8_t *s, int64_t *f, int64_t *g)
+{
+    if (c->n_terms < 0)
+        oracle_energy(n, row_ptr, col, J_q, b_q, c->m, c->copy_a, c->copy_b, s, f, g);
+    else
+        oracle_energy_terms(n, row_ptr, col, J_q, b_q, c->n_terms, c->term_ptr, c->term_idx,
+                            c->term_coef, c->term_const, s, f, g);
+}
+
 /* ------------------------------------------------------------ swap rules */
 
 /* Eq. 2: exponent of a P-swap between penalty columns a (left) and b (right)
@@ -217,8 +350,8 @@ typedef struct {
     int64_t trace_cap;
 } oracle_out;
 
-int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *J_q,
-               const int32_t *b_q, int32_t m, const int32_t *copy_a, const int32_t *copy_b,
+static int run_core(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *J_q,
+               const int32_t *b_q, oracle_constraint *cons,
                const int32_t *color,
                int32_t n_beta, const double *beta, int32_t n_p, const int32_t *p_q,
                int32_t mcs_per_swap, int64_t n_rounds, uint64_t seed,
@@ -238,15 +371,15 @@ int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, const int3
     int32_t *rank = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     int32_t *order = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     int32_t *class_start = (int32_t *)calloc((size_t)n_colors + 1, sizeof(int32_t));
-    int32_t *chain_ptr = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
-    int32_t *chain_nbr = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * m + 1));
     int8_t *pool = (int8_t *)malloc((size_t)R * (size_t)n);
     int8_t **state = (int8_t **)malloc(sizeof(int8_t *) * (size_t)R);
     int64_t *f = (int64_t *)malloc(sizeof(int64_t) * (size_t)R);
     int64_t *g = (int64_t *)malloc(sizeof(int64_t) * (size_t)R);
-    if (!rank || !order || !class_start || !chain_ptr || !chain_nbr || !pool || !state || !f || !g) {
-        free(rank); free(order); free(class_start); free(chain_ptr); free(chain_nbr);
+    if (!rank || !order || !class_start || !pool || !state || !f || !g ||
+        constraint_init(cons, n) != ORACLE_OK) {
+        free(rank); free(order); free(class_start);
         free(pool); free(state); free(f); free(g);
+        constraint_free(cons);
         return ORACLE_ENOMEM;
     }
     int32_t n_pad;
@@ -263,22 +396,6 @@ int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, const int3
         }
         class_start[n_colors] = k;
     }
-    /* copy-edge neighbours of every spin */
-    for (int32_t e = 0; e < m; ++e) {
-        chain_ptr[copy_a[e] + 1]++;
-        chain_ptr[copy_b[e] + 1]++;
-    }
-    for (int32_t v = 0; v < n; ++v) chain_ptr[v + 1] += chain_ptr[v];
-    {
-        int32_t *fill = (int32_t *)calloc((size_t)n, sizeof(int32_t));
-        for (int32_t e = 0; e < m; ++e) {
-            int32_t a = copy_a[e], b = copy_b[e];
-            chain_nbr[chain_ptr[a] + fill[a]++] = b;
-            chain_nbr[chain_ptr[b] + fill[b]++] = a;
-        }
-        free(fill);
-    }
-
     /* initial configurations, one per grid position */
     for (int32_t p = 0; p < R; ++p) {
         state[p] = pool + (size_t)p * (size_t)n;
@@ -300,7 +417,7 @@ int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, const int3
     const int32_t br = R - 1;
 
     for (int32_t p = 0; p < R; ++p)
-        oracle_energy(n, row_ptr, col, J_q, b_q, m, copy_a, copy_b, state[p], &f[p], &g[p]);
+        constraint_energy(cons, n, row_ptr, col, J_q, b_q, state[p], &f[p], &g[p]);
 
     for (int64_t rnd = 1; rnd <= n_rounds; ++rnd) {
         /* every replica performs mcs_per_swap sweeps */
@@ -315,10 +432,7 @@ int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, const int3
                         int64_t h = b_q ? b_q[v] : 0;
                         for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e)
                             h += (int64_t)J_q[e] * s[col[e]];
-                        int64_t cs = 0;
-                        for (int32_t e = chain_ptr[v]; e < chain_ptr[v + 1]; ++e)
-                            cs += s[chain_nbr[e]];
-                        h += 2 * (int64_t)p_q[j] * cs;
+                        h += (int64_t)p_q[j] * constraint_field(cons, s, v);
                         uint32_t u = philox_word(seed, (uint32_t)rank[v] >> 2, t, (uint32_t)p,
                                                  0u, rank[v] & 3);
                         s[v] = (int8_t)oracle_heat_bath(beta[i], h, u);
@@ -326,7 +440,7 @@ int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, const int3
                 }
             }
             /* "for final sweep: compute energy E and constraint g" */
-            oracle_energy(n, row_ptr, col, J_q, b_q, m, copy_a, copy_b, s, &f[p], &g[p]);
+            constraint_energy(cons, n, row_ptr, col, J_q, b_q, s, &f[p], &g[p]);
         }
 
         int32_t dir_beta, first;
@@ -390,7 +504,62 @@ int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, const int3
     if (best_sweep) *best_sweep = bsweep;
     if (first_hit) *first_hit = fhit;
 
-    free(rank); free(order); free(class_start); free(chain_ptr); free(chain_nbr);
+    free(rank); free(order); free(class_start);
     free(pool); free(state); free(f); free(g);
+    constraint_free(cons);
     return ORACLE_OK;
+}
+
+#define RUN_TAIL_PARAMS                                                                         \
+    const int32_t *color, int32_t n_beta, const double *beta, int32_t n_p, const int32_t *p_q,  \
+        int32_t mcs_per_swap, int64_t n_rounds, uint64_t seed, const int8_t *s0,                \
+        int32_t has_target, int64_t f_target, uint32_t flags, int8_t *states_out,               \
+        int64_t *f_out, int64_t *g_out, int8_t *best_state, int64_t *best_f,                    \
+        int64_t *best_sweep, int64_t *first_hit, int64_t *p_att, int64_t *p_acc,                \
+        int64_t *b_att, int64_t *b_acc, int64_t *trace_f, int64_t *trace_g, int64_t trace_cap
+#define RUN_TAIL_ARGS                                                                           \
+    color, n_beta, beta, n_p, p_q, mcs_per_swap, n_rounds, seed, s0, has_target, f_target,      \
+        flags, states_out, f_out, g_out, best_state, best_f, best_sweep, first_hit, p_att,      \
+        p_acc, b_att, b_acc, trace_f, trace_g, trace_cap
+
+/* Copy-edge constraints: g = sum (s_a - s_b)^2. */
+int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *J_q,
+               const int32_t *b_q, int32_t m, const int32_t *copy_a, const int32_t *copy_b,
+               RUN_TAIL_PARAMS)
+{
+    oracle_constraint c;
+    memset(&c, 0, sizeof c);
+    c.m = m;
+    c.copy_a = copy_a;
+    c.copy_b = copy_b;
+    c.n_terms = -1;
+    return run_core(n, row_ptr, col, J_q, b_q, &c, RUN_TAIL_ARGS);
+}
+
+/* General constraints: g = sum_t (sum a_ti s_i + d_t)^2. */
+int oracle_run_terms(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *J_q,
+                     const int32_t *b_q, int32_t n_terms, const int32_t *term_ptr,
+                     const int32_t *term_idx, const int32_t *term_coef,
+                     const int32_t *term_const, RUN_TAIL_PARAMS)
+{
+    if (n_terms < 0 || n <= 0) return ORACLE_EINVAL;
+    /* every spin at most once per term */
+    int32_t *seen = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!seen) return ORACLE_ENOMEM;
+    for (int32_t v = 0; v < n; ++v) seen[v] = -1;
+    for (int32_t t = 0; t < n_terms; ++t)
+        for (int32_t e = term_ptr[t]; e < term_ptr[t + 1]; ++e) {
+            const int32_t v = term_idx[e];
+            if (v < 0 || v >= n || seen[v] == t) { free(seen); return ORACLE_EINVAL; }
+            seen[v] = t;
+        }
+    free(seen);
+    oracle_constraint c;
+    memset(&c, 0, sizeof c);
+    c.n_terms = n_terms;
+    c.term_ptr = term_ptr;
+    c.term_idx = term_idx;
+    c.term_coef = term_coef;
+    c.term_const = term_const;
+    return run_core(n, row_ptr, col, J_q, b_q, &c, RUN_TAIL_ARGS);
 }

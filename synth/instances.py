@@ -66,6 +66,7 @@ class Instance:
     the n physical spins, both directions present, rows sorted.
     b_q: Q12 fields (int32[n]).
     copy_a/copy_b: copy-constraint edges (int32[m]); g = sum (s_a - s_b)^2.
+    term_*: general constraints instead (see below), None with copy edges.
     color: proper colouring over problem and copy edges (int32[n]).
     logical_of: logical node of each physical spin (int32[n]).
     N: logical size; planted: planted logical state (int8[N]) or None.
@@ -83,6 +84,13 @@ class Instance:
     planted: np.ndarray | None = None
     J_logical_q: np.ndarray | None = None
     b_logical_q: np.ndarray | None = None
+    # General constraints in place of copy edges (copy_a / copy_b empty):
+    # g = sum_t (sum_{e in t} term_coef[e] s[term_idx[e]] + term_const[t])^2,
+    # term t holding entries term_ptr[t] .. term_ptr[t+1]-1.
+    term_ptr: np.ndarray | None = None
+    term_idx: np.ndarray | None = None
+    term_coef: np.ndarray | None = None
+    term_const: np.ndarray | None = None
 
     @property
     def n_colors(self) -> int:
