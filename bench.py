@@ -13,6 +13,10 @@ n1000: planted Wishart N=1000 (alpha 0.6), degree 6 (250,000 physical
 spins), a 64 x 32 grid, 50 sweeps per swap round; one step is 4 rounds
 (200 sweeps), 5 steps by default (1000 sweeps, 5.1e11 spin updates).
 
+coloring: general constraints -- planted 4-colouring of a 4000-node graph
+(degree <= 6) in one-hot form (16,000 spins, 4000 one-hot terms), a 32 x 16
+grid, 50 sweeps per swap round; one step is 100 rounds, 20 steps by default.
+
 Prints one JSON line.  `value` is spin-updates/s over the timed steps with
 the problem already resident in HBM.
 """
@@ -36,39 +40,46 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
 # HBM bytes per swap round of each workload's dominant kernel, from rocprofv3
 # FETCH_SIZE (x2.00) and WRITE_SIZE (x1.00) counters scaled against a plain
-# copy of known size; valid for the kernel source with this hash.
+# copy of known size; valid for that kernel on that workload and for the
+# kernel source with this hash.
 MEASURED_TRAFFIC = {
     # one 200-round launch on the N=200 workload: FETCH 15,236.4 KiB, WRITE 11,957.0 KiB
-    "k_persistent": {"kernel_sha256": "73e33ad3e1a5354c", "bytes_per_round": 217241},
+    "wishart-N200-D8-32x16": {"kernel": "k_persistent", "kernel_sha256": "73e33ad3e1a5354c",
+                              "bytes_per_round": 217241},
     # one 50-sweep round on the N=1000 workload: FETCH 5,328,612.3 KiB, WRITE 505,921.7 KiB
-    "k_round_sweep_bits": {"kernel_sha256": "73e33ad3e1a5354c", "bytes_per_round": 11431061709},
+    "wishart-N1000-D6-64x32": {"kernel": "k_round_sweep_bits", "kernel_sha256": "73e33ad3e1a5354c",
+                               "bytes_per_round": 11431061709},
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_2506_14781_amd", "csrc", "tdpt_kernels.hip")
 
 
-def measured_traffic(kernel: str, rounds_per_launch: int):
-    """HBM bytes per launch from the committed counter run, or None if the
-    kernel source changed since the counters were taken."""
+def measured_traffic(workload: str, kernel: str, rounds_per_launch: int):
+    """HBM bytes per launch from the committed counter run, or None if there
+    is none for this workload and kernel or the kernel source changed since
+    the counters were taken."""
     import hashlib
     with open(KERNEL_SRC, "rb") as fh:
         digest = hashlib.sha256(fh.read()).hexdigest()[:16]
-    m = MEASURED_TRAFFIC.get(kernel)
-    if m is None or digest != m["kernel_sha256"]:
+    m = MEASURED_TRAFFIC.get(workload)
+    if m is None or m["kernel"] != kernel or digest != m["kernel_sha256"]:
         return None
     return m["bytes_per_round"] * rounds_per_launch
 
 
-def alu_ops_per_update(info) -> float:
+def alu_ops_per_update(info, cons_deg_mean: float = 0.0) -> float:
     """Arithmetic one heat-bath update needs, in 32-bit lane operations:
-    one multiply-add per problem neighbour, the copy term (two adds, one
-    multiply, one add), the bias add, a quarter of a Philox4x32-10 call
+    one multiply-add per problem neighbour, the penalty term (copy edges:
+    two adds, one multiply, one add; general constraints: one multiply-add
+    per constraint neighbour (cons_deg_mean on average), the multiply by 2P
+    and the add), the bias add, a quarter of a Philox4x32-10 call
     (ten rounds of two 32x32->64 products = 4 ops, four xors, two key adds),
     the logistic decision (convert, scale, exp2, convert the uniform,
     multiply-add, compare)
     and the bookkeeping of the exact f and g (spin difference, two
     multiply-adds, store)."""
     d_problem = info["nnz"] / info["n"]
-    field = d_problem + 4 + 1
+    penalty = cons_deg_mean + 2 if info.get("n_terms", 0) else 4
+    field = d_problem + penalty + 1
     philox = 10 * (4 + 4 + 2) / 4
     decision = 6
     bookkeeping = 4
@@ -383,7 +394,8 @@ def main():
     ap.add_argument("--sigma-min", type=float, default=0.5, help="Algorithm 2 energy spread threshold")
     ap.add_argument("--kl-rounds", type=int, default=2000, help="rounds of 500 sweeps (kl)")
     ap.add_argument("--kl-seeds", type=int, default=4, help="independent runs per setting (kl)")
-    ap.add_argument("--workload", choices=["n200", "n1000", "batched", "serving", "jcolumn", "kl", "copy"],
+    ap.add_argument("--workload", choices=["n200", "n1000", "coloring", "batched", "serving", "jcolumn", "kl",
+                                           "copy"],
                     default="n200",
                     help="copy: one plain 256 MiB device-to-device copy, the reference the HBM "
                          "traffic counters are scaled against")
@@ -405,15 +417,17 @@ def main():
         sys.exit(2)
 
     big = args.workload == "n1000"
-    for name, small, large in [("steps", 100, 5), ("warmup", 5, 1), ("rounds_per_step", 1000, 4),
-                               ("cpu_rounds", 100, 2)]:
+    defaults = {"n200": dict(steps=100, warmup=5, rounds_per_step=1000, cpu_rounds=100),
+                "n1000": dict(steps=5, warmup=1, rounds_per_step=4, cpu_rounds=2),
+                "coloring": dict(steps=20, warmup=2, rounds_per_step=100, cpu_rounds=4)}
+    for name, v in defaults.get(args.workload, defaults["n200"]).items():
         if getattr(args, name) is None:
-            setattr(args, name, large if big else small)
+            setattr(args, name, v)
 
     import torch
 
     import paper_2506_14781_amd as T
-    from synth.configs import wishart_n200, wishart_n1000
+    from synth.configs import coloring_workload, wishart_n200, wishart_n1000
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -429,10 +443,18 @@ def main():
         return bench_batched(args)
     if args.workload == "serving":
         return bench_serving(args)
-    w = wishart_n1000(seed=args.seed) if big else wishart_n200(seed=args.seed)
+    gen = args.workload == "coloring"
+    if gen:
+        w = coloring_workload(seed=args.seed)
+    else:
+        w = wishart_n1000(seed=args.seed) if big else wishart_n200(seed=args.seed)
     inst = T.Instance.from_synth(w.instance)
     info = inst.info()
-    cfg = T.RunConfig(w.beta, w.p_q, mcs_per_swap=w.mcs_per_swap, seed=args.seed)
+    cons_deg_mean = 0.0
+    if gen:
+        lens = np.diff(w.instance.term_ptr).astype(np.float64)
+        cons_deg_mean = float((lens * (lens - 1)).sum()) / w.instance.n
+    cfg = T.RunConfig(w.beta, w.p_q, mcs_per_swap=w.mcs_per_swap, seed=args.seed, f_target=w.f_target_q)
     prob = T.Problem(inst, cfg, device="cuda:0")
     rps = args.rounds_per_step
     print(f"[bench] {w.name}: n={w.instance.n} R={w.replicas} warmup {args.warmup} x {rps} rounds",
@@ -463,17 +485,19 @@ def main():
     launch_ms = kern_ms / max(timed, 1)
     updates_per_launch = updates_per_round * timed_rounds // max(timed, 1)
     # the library keeps a replica as int8 in LDS up to 48 KiB, as bits beyond
-    bits = os.environ.get("TDPT_LAYOUT") == "bits" or (info["n_pad"] + 1 + 15) // 16 * 16 > 48 * 1024
+    # (general constraints: always int8)
+    bits = not gen and (os.environ.get("TDPT_LAYOUT") == "bits" or
+                        (info["n_pad"] + 1 + 15) // 16 * 16 > 48 * 1024)
     kernel = "k_persistent" if persistent else ("k_round_sweep_bits" if bits else "k_round_sweep")
     # Both layouts are bound by VALU arithmetic: the replica spins stay in
     # LDS and the structure is served from L2 (the measured HBM traffic is
     # a small fraction of the structure bytes the sweeps read).
-    ops = alu_ops_per_update(info)
+    ops = alu_ops_per_update(info, cons_deg_mean)
     achieved = ops * updates_per_launch / (launch_ms / 1e3)
     roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 3),
                 "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "Tlane-op/s",
                 "frac": round(achieved / PEAK_LANE_OPS, 4),
-                "traffic": measured_traffic(kernel, timed_rounds // max(timed, 1)),
+                "traffic": measured_traffic(w.name, kernel, timed_rounds // max(timed, 1)),
                 "ops_per_update": round(ops, 2)}
     if bits:
         wd = max(1, info["max_degree"]) if info["max_degree"] <= 8 else 16
@@ -495,7 +519,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32",
-        "data": "synthetic (seeded planted Wishart, copy-chain sparsified)",
+        "data": ("synthetic (seeded planted graph colouring, one-hot constraints)" if gen else
+                 "synthetic (seeded planted Wishart, copy-chain sparsified)"),
         "config": {
             "workload": w.name,
             "logical_N": w.instance.N,
@@ -509,8 +534,12 @@ def main():
         },
         "roofline": roofline,
     }
+    if gen:
+        out["config"].update({"constraint": "one-hot terms", "n_terms": info["n_terms"],
+                              "f_target_q": w.f_target_q,
+                              "first_hit_sweep": q["first_hit_sweep"]})
     if args.cpu_rounds > 0:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_rounds, sub_grid=4 if big else 0)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_rounds, sub_grid=4 if big else 8 if gen else 0)
     print(json.dumps(out), flush=True)
 
 

@@ -15,9 +15,12 @@
  *     between odd and even left indices and the direction flips after every
  *     even round; the bottom-right replica (largest beta and P) carries the
  *     answer.
- *   - the constraint handled here is the copy constraint of graph
- *     sparsification: g = sum over copy edges (S_a - S_b)^2 (section on
- *     graph sparsification with copy constraints).
+ *   - the constraint is the copy constraint of graph sparsification,
+ *     g = sum over copy edges (S_a - S_b)^2 (section on graph sparsification
+ *     with copy constraints), or any sum of squared integer linear forms
+ *     g = sum_t (sum_i a_ti S_i + d_t)^2 (tdpt_instance_create_terms), which
+ *     holds equality constraints such as one-hot groups and capacity limits
+ *     with slack spins (the constraint kinds named in the introduction).
  *
  * Conventions fixed by this library (the paper leaves them open):
  *   - Q12 fixed point: couplings J_q, fields b_q and penalties P_q are int32
@@ -26,7 +29,10 @@
  *     f_q = -sum_{i<j} J_q[ij] s_i s_j - sum_i b_q[i] s_i.
  *   - Sweep: heat-bath updates colour class by colour class (ascending),
  *     P(s_i = +1) = 1 / (1 + exp(-2 beta h_i)) with
- *     h_i = sum_j J_ij s_j + b_i + 2 P sum_{copy neighbours k} s_k.
+ *     h_i = sum_j J_ij s_j + b_i + 2 P sum_{copy neighbours k} s_k, or with
+ *     general constraints h_i = sum_j J_ij s_j + b_i + 2 P c_i,
+ *     c_i = -sum_t a_ti (sum_{j != i} a_tj s_j + d_t) (-s_i 2 c_i collects
+ *     the terms of g that depend on s_i).
  *   - Random numbers: Philox4x32-10 keyed by the 64-bit seed; the counter of
  *     every draw is a function of (spin, sweep, grid position) or (pair,
  *     round, line, direction) only, so results do not depend on launch
@@ -96,6 +102,8 @@ typedef struct tdpt_instance_info {
     int32_t narrow;     /* 1 if indices and couplings fit 16 bits (packed layout) */
     int64_t nnz;        /* directed problem couplings */
     int32_t m;          /* copy edges */
+    int32_t n_terms;    /* general constraint terms (0 with copy edges) */
+    int32_t max_constraint_degree; /* most spins one spin shares a term with */
 } tdpt_instance_info;
 
 typedef struct tdpt_status {
@@ -131,6 +139,32 @@ int tdpt_instance_create(int32_t n, const int32_t *row_ptr, const int32_t *col,
                          const int32_t *J_q, const int32_t *b_q, int32_t m,
                          const int32_t *copy_a, const int32_t *copy_b,
                          const int32_t *color, tdpt_instance **out);
+
+/* The same with a general constraint function in place of copy edges (Eq. 1
+ * asks only g >= 0 with g = 0 exactly on feasible states):
+ *   g = sum_{t < n_terms} (sum_{e = term_ptr[t]}^{term_ptr[t+1]-1}
+ *                          term_coef[e] s[term_idx[e]] + term_const[t])^2.
+ * An equality constraint sum_i w_i x_i = c on bits x = (1 + s) / 2 is the
+ * term with coefficients w and constant sum_i w_i - 2c (its square is
+ * 4 (w.x - c)^2); a copy edge is (1, -1) with constant 0, so copy chains
+ * given this way run the same trajectory as through tdpt_instance_create.
+ *   n_terms     >= 0; term_ptr [n_terms+1] offsets, term_ptr[0] == 0
+ *   term_idx    spin of each entry (a spin at most once per term)
+ *   term_coef   integer coefficient of each entry, term_const [n_terms]
+ *   color       must be proper over the couplings and over every pair of
+ *               spins whose expanded weight -sum_t a_ti a_tj is nonzero
+ * Other arguments as tdpt_instance_create.  Such instances always use the
+ * int8 layout with 32-bit structure (no bit-packed replicas), so one replica
+ * must fit the LDS of a workgroup.  Returns TDPT_E_INVALID for malformed
+ * terms or a spin that shares terms with more than 1024 others, and
+ * TDPT_E_RANGE if an expanded weight exceeds int32 or g could reach 2^62.
+ * tdpt_problem_create bounds |h| by sum |J_q| + |b_q| + 2 P_q max_i |c_i|
+ * and |E| by sum |J_q| + |b_q| + P_q max g. */
+int tdpt_instance_create_terms(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                               const int32_t *J_q, const int32_t *b_q, int32_t n_terms,
+                               const int32_t *term_ptr, const int32_t *term_idx,
+                               const int32_t *term_coef, const int32_t *term_const,
+                               const int32_t *color, tdpt_instance **out);
 int tdpt_instance_info_get(const tdpt_instance *inst, tdpt_instance_info *out);
 void tdpt_instance_destroy(tdpt_instance *inst);
 

@@ -68,6 +68,15 @@ struct DevProblem {
     const int32_t *nb_idx; // wide
     const int32_t *nb_J;   // wide
     const int32_t *ch_idx; // wide
+    // General constraints (byte layout only): half the penalty field of spin
+    // i is kh[i] + sum_k cn_w[k][i] s[cn_idx[k][i]] instead of the copy sum;
+    // g = g0 - sum_i s_i (2 kh[i] + sum_k cn_w[k][i] s[cn_idx[k][i]]).
+    int32_t gen;
+    int32_t wcg;           // constraint ELL width, a multiple of 4
+    const int32_t *cn_idx; // [wcg][n_pad] (padding: index n_pad, weight 0)
+    const int32_t *cn_w;   // [wcg][n_pad]
+    const int32_t *kh;     // [n_pad]
+    int64_t g0;
     const int32_t *bias;   // [n_pad]
     const int32_t *orig;   // [n_pad] original spin index, -1 for padding
     // run configuration

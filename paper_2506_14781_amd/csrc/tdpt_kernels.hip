@@ -118,6 +118,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, int bytes)
 
 struct Rsrc {
     __amdgpu_buffer_rsrc_t a, b, ch, bias;
+    __amdgpu_buffer_rsrc_t cw, kh;  // general constraints: weights, linear part (ch: indices)
 };
 
 __device__ __forceinline__ Rsrc make_rsrc(const DevProblem &P)
@@ -140,7 +141,13 @@ __device__ __forceinline__ Rsrc make_rsrc(const DevProblem &P)
         const int bytes = P.wd * P.n_pad * 4;
         r.a = rsrc(P.nb_idx, bytes);
         r.b = rsrc(P.nb_J, bytes);
-        r.ch = rsrc(P.ch_idx, P.n_pad * 8);
+        if (P.gen) {
+            r.ch = rsrc(P.cn_idx, P.wcg * P.n_pad * 4);
+            r.cw = rsrc(P.cn_w, P.wcg * P.n_pad * 4);
+            r.kh = rsrc(P.kh, P.n_pad * 4);
+        } else {
+            r.ch = rsrc(P.ch_idx, P.n_pad * 8);
+        }
     }
     r.bias = rsrc(P.bias, P.n_pad * 4);
     return r;
@@ -200,8 +207,12 @@ __device__ __forceinline__ void load_quad(const DevProblem &P, const Rsrc &Rs, i
             Q.b[k] = bload(Rs.b, voff, k * row);
         }
     }
-    Q.c0 = bload(Rs.ch, voff, 0);
-    if constexpr (!NARROW) Q.c1 = bload(Rs.ch, voff, row);
+    if constexpr (NARROW) {
+        Q.c0 = bload(Rs.ch, voff, 0);
+    } else if (!P.gen) {
+        Q.c0 = bload(Rs.ch, voff, 0);
+        Q.c1 = bload(Rs.ch, voff, row);
+    }
     if (P.has_bias) Q.bias = bload(Rs.bias, voff, 0);
     else Q.bias = v4i{0, 0, 0, 0};
 }
@@ -211,8 +222,38 @@ __device__ __forceinline__ int sbyte(uint32_t w, int j)
     return (int)(int8_t)(w >> (8 * j));
 }
 
+// Half the penalty field of the 4 spins of a quad under general constraints:
+// kh + sum_k w_k s_k over the constraint ELL, streamed 4 rows at a time (the
+// width is a multiple of 4; padding rows name the zero spin with weight 0).
+__device__ __forceinline__ void quad_constraint_sum(const DevProblem &P, const Rsrc &Rs, const int8_t *s,
+                                                    int voff, int cs[4])
+{
+    const v4i k = bload(Rs.kh, voff, 0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) cs[j] = k[j];
+    const int row = P.n_pad * 4;
+    for (int k0 = 0; k0 < P.wcg; k0 += 4) {
+        v4i ci[4], cw[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            ci[c] = bload(Rs.ch, voff, (k0 + c) * row);
+            cw[c] = bload(Rs.cw, voff, (k0 + c) * row);
+        }
+        int sv[4][4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) sv[c][j] = s[ci[c][j]];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) cs[j] += cw[c][j] * sv[c][j];
+    }
+}
+
 // Local fields of the 4 spins of a quad from the LDS spins s: hp = problem
-// part (couplings and field), cs = sum of the copy neighbours.  NARROW
+// part (couplings and field), cs = half the penalty field (the sum of the
+// copy neighbours, or the general-constraint sum).  NARROW
 // instances keep every field below 2^22, so the 16-bit dot products are
 // exact.
 template <bool NARROW, int WD>
@@ -273,6 +314,8 @@ __device__ __forceinline__ void quad_fields(const DevProblem &P, const Rsrc &Rs,
                 const int c = Q.c0[j];
                 cs[j] = (int)s[c & 0xffff] + (int)s[(unsigned)c >> 16];
             }
+        } else if (P.gen) {
+            quad_constraint_sum(P, Rs, s, Q.voff, cs);
         } else {
 #pragma unroll
             for (int j = 0; j < 4; ++j) cs[j] = (int)s[Q.c0[j]] + (int)s[Q.c1[j]];
@@ -315,8 +358,12 @@ __device__ __forceinline__ void quad_fields(const DevProblem &P, const Rsrc &Rs,
         for (int k = 0; k < WD; ++k)
 #pragma unroll
             for (int j = 0; j < 4; ++j) hp[j] += Q.b[k][j] * (int)s[Q.a[k][j]];
+        if (P.gen) {
+            quad_constraint_sum(P, Rs, s, Q.voff, cs);
+        } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) cs[j] = (int)s[Q.c0[j]] + (int)s[Q.c1[j]];
+            for (int j = 0; j < 4; ++j) cs[j] = (int)s[Q.c0[j]] + (int)s[Q.c1[j]];
+        }
     }
 }
 
@@ -1023,7 +1070,8 @@ __global__ void k_init_states(DevProblem P)
     }
 }
 
-// f = -sum_{i<j} J s_i s_j - sum b s and g = sum_copy (s_a - s_b)^2 of every
+// f = -sum_{i<j} J s_i s_j - sum b s and g (sum_copy (s_a - s_b)^2, or the
+// general constraints' g0 - sum_i s_i (2 kh_i + sum_j Kh_ij s_j)) of every
 // slot, from scratch (one workgroup per slot).
 __global__ __launch_bounds__(kSmallBlock) void k_energy(DevProblem P)
 {
@@ -1049,12 +1097,19 @@ __global__ __launch_bounds__(kSmallBlock) void k_energy(DevProblem P)
         } else {
             for (int k = 0; k < P.wd; ++k)
                 hp += (int64_t)P.nb_J[(size_t)k * P.n_pad + r] * s[P.nb_idx[(size_t)k * P.n_pad + r]];
-            ca = P.ch_idx[r];
-            cb = P.ch_idx[P.n_pad + r];
+            ca = P.gen ? P.n_pad : P.ch_idx[r];
+            cb = P.gen ? P.n_pad : P.ch_idx[P.n_pad + r];
         }
         f2 -= si * hp + 2 * (int64_t)P.bias[r] * si;
-        if (ca != P.n_pad) { const int d = si - s[ca]; g2 += d * d; }
-        if (cb != P.n_pad) { const int d = si - s[cb]; g2 += d * d; }
+        if (P.gen) {
+            int64_t c = 2 * (int64_t)P.kh[r];
+            for (int k = 0; k < P.wcg; ++k)
+                c += (int64_t)P.cn_w[(size_t)k * P.n_pad + r] * s[P.cn_idx[(size_t)k * P.n_pad + r]];
+            g2 -= 2 * si * c;
+        } else {
+            if (ca != P.n_pad) { const int d = si - s[ca]; g2 += d * d; }
+            if (cb != P.n_pad) { const int d = si - s[cb]; g2 += d * d; }
+        }
     }
     const int64_t a = wave_sum64(f2), b = wave_sum64(g2);
     const int wave = threadIdx.x >> 6;
@@ -1064,7 +1119,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_energy(DevProblem P)
         int64_t fa = 0, ga = 0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { fa += red[w][0]; ga += red[w][1]; }
         P.f[slot] = fa / 2;
-        P.g[slot] = ga / 2;
+        P.g[slot] = ga / 2 + (P.gen ? P.g0 : 0);
     }
 }
 

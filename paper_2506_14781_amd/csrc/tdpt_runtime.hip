@@ -56,7 +56,7 @@ int ell_width(int deg)
 }  // namespace
 
 struct tdpt_instance {
-    int32_t n = 0, n_pad = 0, n_colors = 0, wd = 0, wc = 2, narrow = 0, m = 0;
+    int32_t n = 0, n_pad = 0, n_colors = 0, wd = 0, narrow = 0, m = 0;
     int32_t max_deg = 0, max_copy_deg = 0;
     int64_t nnz = 0;
     std::vector<int32_t> rank;       // original -> colour-major
@@ -71,6 +71,16 @@ struct tdpt_instance {
     int64_t max_abs_J = 0;   // max |J_ij|
     int64_t abs_f_bound = 0; // sum_{i<j} |J_ij| + sum_i |b_i|
     int32_t max_class_quads = 0;
+    // The penalty field of spin i is 2 P c_i; c_i is the copy sum, or for
+    // general constraints kh_i + sum_j Kh_ij s_j (constraint ELL cn_*).
+    int32_t gen = 0;         // general constraint terms instead of copy edges
+    int32_t n_terms = 0, max_cons_deg = 0;
+    int32_t wcg = 0;         // constraint ELL width (multiple of 4)
+    std::vector<int32_t> cn_idx, cn_w;  // [wcg][n_pad]
+    std::vector<int32_t> kh;            // [n_pad]
+    int64_t g0 = 0;          // constant of g
+    int64_t max_cfield = 0;  // max_i |c_i|
+    int64_t g_bound = 0;     // max |g|
 };
 
 struct tdpt_problem {
@@ -103,7 +113,8 @@ namespace {
 struct Layout {
     size_t hdr, states, f, g, slot_pos, pos_slot, p_att, p_acc, b_att, b_acc, best, trace_f,
         trace_g, mut_end, mbox, slot_key, slot_best, hit_min, scratch_end;
-    size_t beta, p_q, nbi, nbj, chp, nb_idx, nb_J, ch_idx, bias, orig, nb_pos, ch_pos, h0, total;
+    size_t beta, p_q, nbi, nbj, chp, nb_idx, nb_J, ch_idx, bias, orig, nb_pos, ch_pos, h0, cn_idx, cn_w, kh,
+        total;
     int32_t stride, wd;
 };
 
@@ -113,6 +124,7 @@ constexpr size_t kInt8StrideMax = 48 * 1024;
 
 bool use_bits(const tdpt_instance *in)
 {
+    if (in->gen) return false;  // general constraints use the byte layout only
     if (const char *e = getenv("TDPT_LAYOUT")) {
         if (!strcmp(e, "bits")) return true;
         if (!strcmp(e, "bytes")) return false;
@@ -126,7 +138,7 @@ bool use_bits(const tdpt_instance *in)
 bool use_narrow(const tdpt_instance *in, const tdpt_run_cfg *cfg)
 {
     const int64_t pmax = cfg->p_q[cfg->n_p - 1];
-    return !use_bits(in) && in->narrow && in->max_field + 4 * pmax < ((int64_t)1 << 22);
+    return !in->gen && !use_bits(in) && in->narrow && in->max_field + 4 * pmax < ((int64_t)1 << 22);
 }
 
 Layout make_layout(const tdpt_instance *in, int32_t I, int32_t J, int64_t trace_cap, bool narrow)
@@ -173,8 +185,16 @@ Layout make_layout(const tdpt_instance *in, int32_t I, int32_t J, int64_t trace_
         const size_t ell = (size_t)L.wd * in->n_pad * 4;
         L.nb_idx = take(ell);
         L.nb_J = take(ell);
-        L.ch_idx = take((size_t)2 * in->n_pad * 4);
         L.nbi = L.nbj = L.chp = 0;
+        if (in->gen) {
+            const size_t cell = (size_t)in->wcg * in->n_pad * 4;
+            L.cn_idx = take(cell);
+            L.cn_w = take(cell);
+            L.kh = take((size_t)in->n_pad * 4);
+            L.ch_idx = 0;
+        } else {
+            L.ch_idx = take((size_t)2 * in->n_pad * 4);
+        }
         if (use_bits(in)) {
             L.nb_pos = take(ell);
             L.ch_pos = take((size_t)2 * in->n_pad * 4);
@@ -224,28 +244,19 @@ int sweep_block(const tdpt_instance *in, bool persistent)
     return std::min(std::max(b, 64), cap);
 }
 
-}  // namespace
-
-extern "C" {
-
-const char *tdpt_last_error(void) { return g_err.c_str(); }
-
-int tdpt_instance_create(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *J_q,
-                         const int32_t *b_q, int32_t m, const int32_t *copy_a,
-                         const int32_t *copy_b, const int32_t *color, tdpt_instance **out)
+// Problem couplings: CSR shape, symmetry, no self loops or repeats; fills
+// ent with each row's (col, J) sorted by col.
+int check_csr(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *J_q,
+              const int32_t *b_q, const int32_t *color, std::vector<std::pair<int32_t, int32_t>> &ent)
 {
-    if (!out) return fail(TDPT_E_INVALID, "out is NULL");
-    *out = nullptr;
+    (void)b_q;
     if (n <= 0 || !row_ptr || !color) return fail(TDPT_E_INVALID, "need n > 0, row_ptr and color");
     if (row_ptr[0] != 0) return fail(TDPT_E_INVALID, "row_ptr[0] must be 0");
     for (int32_t i = 0; i < n; ++i)
         if (row_ptr[i + 1] < row_ptr[i]) return fail(TDPT_E_INVALID, "row_ptr must be non-decreasing");
     const int64_t nnz = row_ptr[n];
     if (nnz > 0 && (!col || !J_q)) return fail(TDPT_E_INVALID, "col and J_q are required");
-    if (m < 0 || (m > 0 && (!copy_a || !copy_b))) return fail(TDPT_E_INVALID, "bad copy-edge arrays");
-
-    // sorted (col, J) per row for symmetry / duplicate checks
-    std::vector<std::pair<int32_t, int32_t>> ent((size_t)nnz);
+    ent.assign((size_t)nnz, {0, 0});
     for (int32_t i = 0; i < n; ++i) {
         for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
             const int32_t j = col[e];
@@ -258,36 +269,29 @@ int tdpt_instance_create(int32_t n, const int32_t *row_ptr, const int32_t *col, 
             if (ent[e].first == ent[e - 1].first)
                 return fail(TDPT_E_INVALID, "repeated neighbour in row " + std::to_string(i));
     }
-    auto find = [&](int32_t i, int32_t j) -> const std::pair<int32_t, int32_t> * {
-        auto b = ent.begin() + row_ptr[i], e = ent.begin() + row_ptr[i + 1];
-        auto it = std::lower_bound(b, e, std::make_pair(j, INT32_MIN));
-        if (it != e && it->first == j) return &*it;
-        return nullptr;
-    };
     for (int32_t i = 0; i < n; ++i)
         for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-            const auto *rev = find(ent[e].first, i);
-            if (!rev || rev->second != ent[e].second)
+            const int32_t j = ent[e].first;
+            auto b = ent.begin() + row_ptr[j], en = ent.begin() + row_ptr[j + 1];
+            auto it = std::lower_bound(b, en, std::make_pair(i, INT32_MIN));
+            if (it == en || it->first != i || it->second != ent[e].second)
                 return fail(TDPT_E_INVALID, "couplings are not symmetric at (" + std::to_string(i) + "," +
-                                                std::to_string(ent[e].first) + ")");
+                                                std::to_string(j) + ")");
         }
-    // copy edges
-    std::vector<int32_t> cdeg(n, 0);
-    std::vector<std::pair<int32_t, int32_t>> cpairs((size_t)m);
-    for (int32_t e = 0; e < m; ++e) {
-        const int32_t a = copy_a[e], b = copy_b[e];
-        if (a < 0 || a >= n || b < 0 || b >= n || a == b)
-            return fail(TDPT_E_INVALID, "bad copy edge " + std::to_string(e));
-        if (find(a, b)) return fail(TDPT_E_INVALID, "copy edge " + std::to_string(e) + " is also a coupling");
-        cpairs[e] = {std::min(a, b), std::max(a, b)};
-        if (++cdeg[a] > 2 || ++cdeg[b] > 2)
-            return fail(TDPT_E_INVALID, "copy constraints must form chains (at most 2 copy edges per spin)");
-    }
-    std::sort(cpairs.begin(), cpairs.end());
-    for (int32_t e = 1; e < m; ++e)
-        if (cpairs[e] == cpairs[e - 1]) return fail(TDPT_E_INVALID, "repeated copy edge");
-    // colouring
-    int32_t C = 0;
+    return TDPT_OK;
+}
+
+bool csr_has(const int32_t *row_ptr, const std::vector<std::pair<int32_t, int32_t>> &ent, int32_t i, int32_t j)
+{
+    auto b = ent.begin() + row_ptr[i], e = ent.begin() + row_ptr[i + 1];
+    auto it = std::lower_bound(b, e, std::make_pair(j, INT32_MIN));
+    return it != e && it->first == j;
+}
+
+// Colour classes: count (<= kMaxColors) and properness over the couplings.
+int check_colors(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *color, int32_t &C)
+{
+    C = 0;
     for (int32_t v = 0; v < n; ++v) {
         if (color[v] < 0) return fail(TDPT_E_INVALID, "negative colour");
         C = std::max(C, color[v] + 1);
@@ -298,17 +302,17 @@ int tdpt_instance_create(int32_t n, const int32_t *row_ptr, const int32_t *col, 
             if (color[i] == color[col[e]])
                 return fail(TDPT_E_INVALID, "colouring is not proper on coupling (" + std::to_string(i) + "," +
                                                 std::to_string(col[e]) + ")");
-    for (int32_t e = 0; e < m; ++e)
-        if (color[copy_a[e]] == color[copy_b[e]])
-            return fail(TDPT_E_INVALID, "colouring is not proper on copy edge " + std::to_string(e));
+    return TDPT_OK;
+}
 
-    auto *in = new (std::nothrow) tdpt_instance();
-    if (!in) return fail(TDPT_E_NOMEM, "host allocation failed");
+// Colour-major numbering (classes padded to multiples of 4), the problem
+// ELL and the fields of a validated instance.
+int lay_out(tdpt_instance *in, int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *J_q,
+            const int32_t *b_q, const int32_t *color, int32_t C)
+{
     in->n = n;
-    in->nnz = nnz;
-    in->m = m;
+    in->nnz = row_ptr[n];
     in->n_colors = C;
-    // colour-major numbering, classes padded to multiples of 4
     std::vector<int32_t> size(C, 0);
     for (int32_t v = 0; v < n; ++v) size[color[v]]++;
     in->cls_start.assign(C + 1, 0);
@@ -334,16 +338,10 @@ int tdpt_instance_create(int32_t n, const int32_t *row_ptr, const int32_t *col, 
     for (int32_t i = 0; i < n; ++i) maxdeg = std::max(maxdeg, row_ptr[i + 1] - row_ptr[i]);
     in->max_deg = maxdeg;
     in->wd = ell_width(maxdeg);
-    if (in->wd < 0) {
-        delete in;
-        return fail(TDPT_E_INVALID, "a spin has more than 48 problem neighbours");
-    }
-    in->max_copy_deg = 0;
-    for (int32_t v = 0; v < n; ++v) in->max_copy_deg = std::max(in->max_copy_deg, cdeg[v]);
+    if (in->wd < 0) return fail(TDPT_E_INVALID, "a spin has more than 48 problem neighbours");
     const int32_t wd = in->wd;
     in->nb_idx.assign((size_t)wd * n_pad, n_pad);
     in->nb_J.assign((size_t)wd * n_pad, 0);
-    in->ch_idx.assign((size_t)2 * n_pad, n_pad);
     in->bias.assign(n_pad, 0);
     bool narrow = (n_pad + 1 <= 65536);
     int64_t absf = 0;
@@ -367,6 +365,62 @@ int tdpt_instance_create(int32_t n, const int32_t *row_ptr, const int32_t *col, 
         }
         in->max_field = std::max(in->max_field, field);
     }
+    in->abs_f_bound = absf;
+    in->narrow = narrow ? 1 : 0;
+    return TDPT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tdpt_last_error(void) { return g_err.c_str(); }
+
+int tdpt_instance_create(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *J_q,
+                         const int32_t *b_q, int32_t m, const int32_t *copy_a,
+                         const int32_t *copy_b, const int32_t *color, tdpt_instance **out)
+{
+    if (!out) return fail(TDPT_E_INVALID, "out is NULL");
+    *out = nullptr;
+    std::vector<std::pair<int32_t, int32_t>> ent;
+    int rc = check_csr(n, row_ptr, col, J_q, b_q, color, ent);
+    if (rc) return rc;
+    if (m < 0 || (m > 0 && (!copy_a || !copy_b))) return fail(TDPT_E_INVALID, "bad copy-edge arrays");
+    // copy edges
+    std::vector<int32_t> cdeg(n, 0);
+    std::vector<std::pair<int32_t, int32_t>> cpairs((size_t)m);
+    for (int32_t e = 0; e < m; ++e) {
+        const int32_t a = copy_a[e], b = copy_b[e];
+        if (a < 0 || a >= n || b < 0 || b >= n || a == b)
+            return fail(TDPT_E_INVALID, "bad copy edge " + std::to_string(e));
+        if (csr_has(row_ptr, ent, a, b))
+            return fail(TDPT_E_INVALID, "copy edge " + std::to_string(e) + " is also a coupling");
+        cpairs[e] = {std::min(a, b), std::max(a, b)};
+        if (++cdeg[a] > 2 || ++cdeg[b] > 2)
+            return fail(TDPT_E_INVALID, "copy constraints must form chains (at most 2 copy edges per spin)");
+    }
+    std::sort(cpairs.begin(), cpairs.end());
+    for (int32_t e = 1; e < m; ++e)
+        if (cpairs[e] == cpairs[e - 1]) return fail(TDPT_E_INVALID, "repeated copy edge");
+    int32_t C = 0;
+    rc = check_colors(n, row_ptr, col, color, C);
+    if (rc) return rc;
+    for (int32_t e = 0; e < m; ++e)
+        if (color[copy_a[e]] == color[copy_b[e]])
+            return fail(TDPT_E_INVALID, "colouring is not proper on copy edge " + std::to_string(e));
+
+    auto *in = new (std::nothrow) tdpt_instance();
+    if (!in) return fail(TDPT_E_NOMEM, "host allocation failed");
+    rc = lay_out(in, n, row_ptr, col, J_q, b_q, color, C);
+    if (rc) {
+        delete in;
+        return rc;
+    }
+    in->m = m;
+    in->max_copy_deg = 0;
+    for (int32_t v = 0; v < n; ++v) in->max_copy_deg = std::max(in->max_copy_deg, cdeg[v]);
+    const int32_t n_pad = in->n_pad;
+    in->ch_idx.assign((size_t)2 * n_pad, n_pad);
     for (int32_t e = 0; e < m; ++e) {
         const int32_t a = in->rank[copy_a[e]], b = in->rank[copy_b[e]];
         int32_t *sa = (in->ch_idx[a] == n_pad) ? &in->ch_idx[a] : &in->ch_idx[(size_t)n_pad + a];
@@ -374,8 +428,123 @@ int tdpt_instance_create(int32_t n, const int32_t *row_ptr, const int32_t *col, 
         int32_t *sb = (in->ch_idx[b] == n_pad) ? &in->ch_idx[b] : &in->ch_idx[(size_t)n_pad + b];
         *sb = a;
     }
-    in->abs_f_bound = absf;
-    in->narrow = narrow ? 1 : 0;
+    // half the penalty field is the copy sum (|.| <= 2); g <= 4 m
+    in->max_cfield = 2;
+    in->g_bound = 4 * (int64_t)m;
+    *out = in;
+    return TDPT_OK;
+}
+
+int tdpt_instance_create_terms(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                               const int32_t *J_q, const int32_t *b_q, int32_t n_terms,
+                               const int32_t *term_ptr, const int32_t *term_idx,
+                               const int32_t *term_coef, const int32_t *term_const,
+                               const int32_t *color, tdpt_instance **out)
+{
+    if (!out) return fail(TDPT_E_INVALID, "out is NULL");
+    *out = nullptr;
+    std::vector<std::pair<int32_t, int32_t>> ent;
+    int rc = check_csr(n, row_ptr, col, J_q, b_q, color, ent);
+    if (rc) return rc;
+    if (n_terms < 0 || (n_terms > 0 && (!term_ptr || !term_idx || !term_coef || !term_const)))
+        return fail(TDPT_E_INVALID, "bad constraint-term arrays");
+    if (n_terms > 0 && term_ptr[0] != 0) return fail(TDPT_E_INVALID, "term_ptr[0] must be 0");
+    for (int32_t t = 0; t < n_terms; ++t)
+        if (term_ptr[t + 1] < term_ptr[t]) return fail(TDPT_E_INVALID, "term_ptr must be non-decreasing");
+    // g = sum_t (sum_e a_e s_e + d_t)^2 = g0 - 2 sum_i kh_i s_i - 2 sum_{i<j} Kh_ij s_i s_j
+    // with Kh_ij = -sum_t a_ti a_tj, kh_i = -sum_t a_ti d_t, g0 = sum_t (sum_e a_e^2 + d_t^2)
+    std::vector<int32_t> seen(n, -1);
+    std::vector<std::vector<std::pair<int32_t, int64_t>>> kh_pairs(n);
+    std::vector<int64_t> kh(n, 0);
+    __int128 g0 = 0;
+    const __int128 kBig = (__int128)1 << 62;
+    for (int32_t t = 0; t < n_terms; ++t) {
+        const int32_t e0 = term_ptr[t], e1 = term_ptr[t + 1];
+        for (int32_t e = e0; e < e1; ++e) {
+            const int32_t v = term_idx[e];
+            if (v < 0 || v >= n) return fail(TDPT_E_INVALID, "term index out of range in term " + std::to_string(t));
+            if (seen[v] == t) return fail(TDPT_E_INVALID, "spin repeated in term " + std::to_string(t));
+            seen[v] = t;
+            const int64_t a = term_coef[e];
+            kh[v] -= a * (int64_t)term_const[t];
+            g0 += (__int128)a * a;
+            for (int32_t e2 = e0; e2 < e1; ++e2)
+                if (e2 != e) kh_pairs[v].push_back({term_idx[e2], -a * (int64_t)term_coef[e2]});
+            if (std::llabs((long long)kh[v]) >= ((int64_t)1 << 40))
+                return fail(TDPT_E_RANGE, "constraint coefficients too large");
+        }
+        g0 += (__int128)term_const[t] * term_const[t];
+        if (g0 >= kBig) return fail(TDPT_E_RANGE, "constant of g reaches 2^62");
+    }
+    // merge repeated pairs, drop zero weights
+    int64_t max_cfield = 0, g_bound = (int64_t)g0;
+    int32_t wcg = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        auto &L = kh_pairs[v];
+        std::sort(L.begin(), L.end());
+        size_t w = 0;
+        for (size_t i = 0; i < L.size();) {
+            size_t j = i;
+            int64_t sum = 0;
+            while (j < L.size() && L[j].first == L[i].first) sum += L[j++].second;
+            if (sum != 0) L[w++] = {L[i].first, sum};
+            i = j;
+        }
+        L.resize(w);
+        int64_t cf = std::llabs((long long)kh[v]);
+        for (auto &pr : L) {
+            if (pr.second < INT32_MIN || pr.second > INT32_MAX)
+                return fail(TDPT_E_RANGE, "a pair weight of g exceeds int32");
+            cf += std::llabs((long long)pr.second);
+        }
+        if (kh[v] < INT32_MIN || kh[v] > INT32_MAX) return fail(TDPT_E_RANGE, "a linear weight of g exceeds int32");
+        if (cf >= ((int64_t)1 << 31)) return fail(TDPT_E_RANGE, "a penalty field can reach 2^31");
+        max_cfield = std::max(max_cfield, cf);
+        g_bound += 2 * cf;  // 2|kh_v| + sum_j 2|Kh_vj|: every pair counted from both ends
+        if (g_bound >= ((int64_t)1 << 62)) return fail(TDPT_E_RANGE, "g can reach 2^62");
+        wcg = std::max(wcg, (int32_t)L.size());
+    }
+    if (wcg > 1024) return fail(TDPT_E_INVALID, "a spin shares constraint terms with more than 1024 others");
+    int32_t C = 0;
+    rc = check_colors(n, row_ptr, col, color, C);
+    if (rc) return rc;
+    for (int32_t v = 0; v < n; ++v)
+        for (auto &pr : kh_pairs[v])
+            if (color[v] == color[pr.first])
+                return fail(TDPT_E_INVALID, "colouring is not proper on the constraint pair (" + std::to_string(v) +
+                                                "," + std::to_string(pr.first) + ")");
+
+    auto *in = new (std::nothrow) tdpt_instance();
+    if (!in) return fail(TDPT_E_NOMEM, "host allocation failed");
+    rc = lay_out(in, n, row_ptr, col, J_q, b_q, color, C);
+    if (rc) {
+        delete in;
+        return rc;
+    }
+    const int32_t n_pad = in->n_pad;
+    in->gen = 1;
+    in->narrow = 0;
+    in->n_terms = n_terms;
+    in->max_cons_deg = wcg;
+    in->wcg = std::max(4, (wcg + 3) / 4 * 4);
+    in->cn_idx.assign((size_t)in->wcg * n_pad, n_pad);
+    in->cn_w.assign((size_t)in->wcg * n_pad, 0);
+    in->kh.assign(n_pad, 0);
+    for (int32_t r = 0; r < n_pad; ++r) {
+        const int32_t v = in->orig[r];
+        if (v < 0) continue;
+        auto L = kh_pairs[v];
+        for (auto &pr : L) pr.first = in->rank[pr.first];
+        std::sort(L.begin(), L.end());
+        for (size_t k = 0; k < L.size(); ++k) {
+            in->cn_idx[k * n_pad + r] = L[k].first;
+            in->cn_w[k * n_pad + r] = (int32_t)L[k].second;
+        }
+        in->kh[r] = (int32_t)kh[v];
+    }
+    in->g0 = (int64_t)g0;
+    in->max_cfield = max_cfield;
+    in->g_bound = g_bound;
     *out = in;
     return TDPT_OK;
 }
@@ -391,6 +560,8 @@ int tdpt_instance_info_get(const tdpt_instance *in, tdpt_instance_info *out)
     out->narrow = in->narrow;
     out->nnz = in->nnz;
     out->m = in->m;
+    out->n_terms = in->n_terms;
+    out->max_constraint_degree = in->max_cons_deg;
     return TDPT_OK;
 }
 
@@ -423,15 +594,20 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
                                       std::to_string(L.total));
     // fixed-point bounds
     const int64_t pmax = cfg->p_q[J - 1];
-    if (in->max_field + 4 * pmax >= ((int64_t)1 << 31))
+    const int64_t hmax = in->max_field + 2 * pmax * in->max_cfield;  // |h| bound
+    if (in->max_cfield > 0 && 2 * pmax > (((int64_t)1 << 31) / in->max_cfield))
+        return fail(TDPT_E_RANGE, "local field can reach 2^31");
+    if (hmax >= ((int64_t)1 << 31))
         return fail(TDPT_E_RANGE, "local field can reach 2^31");
     const bool bits = use_bits(in);
     const int64_t blk = bits ? std::min(sweep_block(in, false), tdpt::kBitsBlock)
                              : std::min(sweep_block(in, false), sweep_block(in, true));
     const int64_t quads_per_thread = (in->max_class_quads + blk - 1) / blk;
-    if (quads_per_thread * 4 * 2 * (in->max_field + 4 * pmax) >= ((int64_t)1 << 31))
+    if (quads_per_thread * 4 * 2 * hmax >= ((int64_t)1 << 31))
         return fail(TDPT_E_RANGE, "per-phase energy change can reach 2^31");
-    const int64_t ebound = in->abs_f_bound + pmax * 4 * (int64_t)in->m;
+    if (in->g_bound > 0 && pmax > (((int64_t)1 << 51) / in->g_bound))
+        return fail(TDPT_E_RANGE, "energy differences can reach 2^52");
+    const int64_t ebound = in->abs_f_bound + pmax * in->g_bound;
     if (ebound >= ((int64_t)1 << 51)) return fail(TDPT_E_RANGE, "energy differences can reach 2^52");
 
     int dev = 0;
@@ -493,7 +669,13 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     d.chp = narrow ? (const uint32_t *)(ws + L.chp) : nullptr;
     d.nb_idx = narrow ? nullptr : (const int32_t *)(ws + L.nb_idx);
     d.nb_J = narrow ? nullptr : (const int32_t *)(ws + L.nb_J);
-    d.ch_idx = narrow ? nullptr : (const int32_t *)(ws + L.ch_idx);
+    d.ch_idx = (narrow || in->gen) ? nullptr : (const int32_t *)(ws + L.ch_idx);
+    d.gen = in->gen;
+    d.wcg = in->wcg;
+    d.cn_idx = in->gen ? (const int32_t *)(ws + L.cn_idx) : nullptr;
+    d.cn_w = in->gen ? (const int32_t *)(ws + L.cn_w) : nullptr;
+    d.kh = in->gen ? (const int32_t *)(ws + L.kh) : nullptr;
+    d.g0 = in->g0;
     d.bias = (const int32_t *)(ws + L.bias);
     d.orig = (const int32_t *)(ws + L.orig);
     d.I = I;
@@ -563,7 +745,13 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     } else {
         UP(ws + L.nb_idx, in->nb_idx.data(), in->nb_idx.size() * 4);
         UP(ws + L.nb_J, in->nb_J.data(), in->nb_J.size() * 4);
-        UP(ws + L.ch_idx, in->ch_idx.data(), in->ch_idx.size() * 4);
+        if (in->gen) {
+            UP(ws + L.cn_idx, in->cn_idx.data(), in->cn_idx.size() * 4);
+            UP(ws + L.cn_w, in->cn_w.data(), in->cn_w.size() * 4);
+            UP(ws + L.kh, in->kh.data(), in->kh.size() * 4);
+        } else {
+            UP(ws + L.ch_idx, in->ch_idx.data(), in->ch_idx.size() * 4);
+        }
         if (bits) {
             // structure in bit positions: spin rho of class c sits at
             // rho - cls_start[c] + bit_start[c]

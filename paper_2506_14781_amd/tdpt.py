@@ -19,7 +19,8 @@ OK, E_INVALID, E_RANGE, E_NOMEM, E_DEVICE, E_STATE = range(6)
 NO_PSWAP = 1
 
 EXPORTED = [
-    "tdpt_instance_create", "tdpt_instance_info_get", "tdpt_instance_destroy",
+    "tdpt_instance_create", "tdpt_instance_create_terms", "tdpt_instance_info_get",
+    "tdpt_instance_destroy",
     "tdpt_workspace_bytes", "tdpt_problem_create", "tdpt_problem_run", "tdpt_problem_query",
     "tdpt_problem_read_energies", "tdpt_problem_read_states", "tdpt_problem_read_perm",
     "tdpt_problem_read_best", "tdpt_problem_read_counters", "tdpt_problem_read_trace",
@@ -50,7 +51,8 @@ class _RunCfg(ctypes.Structure):
 class _Info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("n_pad", ctypes.c_int32), ("n_colors", ctypes.c_int32),
                 ("max_degree", ctypes.c_int32), ("max_copy_degree", ctypes.c_int32),
-                ("narrow", ctypes.c_int32), ("nnz", ctypes.c_int64), ("m", ctypes.c_int32)]
+                ("narrow", ctypes.c_int32), ("nnz", ctypes.c_int64), ("m", ctypes.c_int32),
+                ("n_terms", ctypes.c_int32), ("max_constraint_degree", ctypes.c_int32)]
 
 
 class _Status(ctypes.Structure):
@@ -73,6 +75,7 @@ def load_library():
     P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     sig = {
         "tdpt_instance_create": [I32, P, P, P, P, I32, P, P, P, P],
+        "tdpt_instance_create_terms": [I32, P, P, P, P, I32, P, P, P, P, P, P],
         "tdpt_instance_info_get": [P, P],
         "tdpt_workspace_bytes": [P, P, P],
         "tdpt_problem_create": [P, P, P, SZ, P, P],
@@ -123,25 +126,39 @@ def _arr(a, dt):
 
 
 class Instance:
-    """A validated, colour-major re-laid-out instance (host memory)."""
+    """A validated, colour-major re-laid-out instance (host memory).
 
-    def __init__(self, n, row_ptr, col, J_q, b_q, copy_a, copy_b, color):
+    The constraint is either copy edges (copy_a, copy_b) or general terms
+    (terms = (term_ptr, term_idx, term_coef, term_const)); see
+    tdpt_instance_create_terms."""
+
+    def __init__(self, n, row_ptr, col, J_q, b_q, copy_a, copy_b, color, terms=None):
         lib = load_library()
         self._keep = [_arr(row_ptr, np.int32), _arr(col, np.int32), _arr(J_q, np.int32),
                       _arr(b_q, np.int32), _arr(copy_a, np.int32), _arr(copy_b, np.int32),
                       _arr(color, np.int32)]
         rp, cl, jq, bq, ca, cb, co = self._keep
-        m = 0 if ca is None else int(ca.shape[0])
         h = ctypes.c_void_p()
-        _check(lib.tdpt_instance_create(int(n), _ptr(rp), _ptr(cl), _ptr(jq), _ptr(bq), m,
-                                        _ptr(ca), _ptr(cb), _ptr(co), ctypes.byref(h)))
+        if terms is not None:
+            tp, ti, tc, td = (_arr(x, np.int32) for x in terms)
+            self._keep += [tp, ti, tc, td]
+            _check(lib.tdpt_instance_create_terms(int(n), _ptr(rp), _ptr(cl), _ptr(jq), _ptr(bq),
+                                                  int(tp.shape[0]) - 1, _ptr(tp), _ptr(ti), _ptr(tc),
+                                                  _ptr(td), _ptr(co), ctypes.byref(h)))
+        else:
+            m = 0 if ca is None else int(ca.shape[0])
+            _check(lib.tdpt_instance_create(int(n), _ptr(rp), _ptr(cl), _ptr(jq), _ptr(bq), m,
+                                            _ptr(ca), _ptr(cb), _ptr(co), ctypes.byref(h)))
         self._h = h
         self.n = int(n)
 
     @classmethod
     def from_synth(cls, inst):
+        terms = None
+        if getattr(inst, "term_ptr", None) is not None:
+            terms = (inst.term_ptr, inst.term_idx, inst.term_coef, inst.term_const)
         return cls(inst.n, inst.row_ptr, inst.col, inst.J_q, inst.b_q, inst.copy_a,
-                   inst.copy_b, inst.color)
+                   inst.copy_b, inst.color, terms=terms)
 
     def info(self) -> dict:
         out = _Info()

@@ -13,6 +13,7 @@ import math
 
 import numpy as np
 
+from .constrained import planted_coloring
 from .instances import (Instance, build_instance, geometric_betas, instance_from_logical,
                         linear_penalties_q, q12)
 
@@ -26,6 +27,7 @@ class Workload:
     mcs_per_swap: int
     sweeps: int
     seed: int
+    f_target_q: int | None = None   # a known optimum's f, when the family plants one
 
     @property
     def n_beta(self) -> int:
@@ -134,3 +136,17 @@ def fig2_workload(seed: int = 0, rounds: int = 2000) -> Workload:
     inst = instance_from_logical(Jq, b_logical_q=b, degree_cap=3)
     return Workload(f"fig2-standin-N5-s{seed}", inst, np.array([1.0]), q12([2.0, 4.0, 6.0, 8.0]),
                     500, 500 * rounds, seed)
+
+
+def coloring_workload(seed: int = 0, V: int = 4000, k: int = 4, degree: int = 6) -> Workload:
+    """General constraints: planted graph k-colouring in one-hot form (V
+    nodes, k spins per node, at most `degree` neighbours per node, one
+    one-hot term per node; 16,000 spins by default), on a 32 x 16 grid
+    (beta geometric 0.2..5, P linear 0..4) with 50 sweeps per swap.  The
+    planted colouring is a feasible optimum (f_target_q)."""
+    key = ("coloring", V, k, degree, seed)
+    if key not in _CACHE:
+        _CACHE[key] = planted_coloring(V, k, degree, seed)
+    pc = _CACHE[key]
+    return Workload(f"coloring-V{V}-k{k}-d{degree}-32x16", pc.instance, geometric_betas(0.2, 5.0, 32),
+                    linear_penalties_q(0, 4, 16), 50, 10_000, seed, f_target_q=pc.f_target_q)

@@ -125,3 +125,68 @@ def test_error_message_is_thread_local_text():
     except T.TdptError as e:
         assert "symmetric" in str(e) and e.code == B.E_INVALID
     assert "symmetric" in T.load_library().tdpt_last_error().decode()
+
+
+# ------------------------------------------------------ general constraints
+
+def _terms(inst):
+    return (inst.term_ptr, inst.term_idx, inst.term_coef, inst.term_const)
+
+
+def test_terms_instance_info():
+    from synth.constrained import planted_coloring
+    pc = planted_coloring(50, 4, degree=5, seed=0)
+    info = T.Instance.from_synth(pc.instance).info()
+    assert info["n"] == 200 and info["n_terms"] == 50 and info["m"] == 0
+    assert info["max_constraint_degree"] == 3 and info["narrow"] == 0
+
+
+def test_terms_rejects_malformed_terms():
+    from synth.constrained import slack_knapsack
+    inst = slack_knapsack(5, seed=2)
+    tp, ti, tc, td = _terms(inst)
+    base = dict(n=inst.n, row_ptr=inst.row_ptr, col=inst.col, J_q=inst.J_q, b_q=inst.b_q,
+                copy_a=None, copy_b=None, color=inst.color)
+    T.Instance(**base, terms=(tp, ti, tc, td))
+    ti2 = ti.copy()
+    ti2[1] = ti2[0]
+    with pytest.raises(T.TdptError, match="repeated"):
+        T.Instance(**base, terms=(tp, ti2, tc, td))
+    ti3 = ti.copy()
+    ti3[0] = inst.n
+    with pytest.raises(T.TdptError, match="range"):
+        T.Instance(**base, terms=(tp, ti3, tc, td))
+    color = inst.color.copy()
+    color[ti[1]] = color[ti[0]]
+    with pytest.raises(T.TdptError, match="constraint pair|coupling"):
+        T.Instance(**{**base, "color": color}, terms=(tp, ti, tc, td))
+    big = tc.copy()
+    big[0] = 1 << 30
+    with pytest.raises(T.TdptError, match="int32|2\\^"):
+        T.Instance(**base, terms=(tp, ti, big, td))
+
+
+def test_terms_pair_with_zero_net_weight_may_share_a_colour():
+    """Two terms whose products a_ti a_tj cancel leave i and j uncoupled:
+    they may share a colour class."""
+    n = 3
+    rp = np.zeros(n + 1, np.int32)
+    # (s0 + s1 + s2)^2 and (s0 - s1)^2: weights 0-1 pair: -(1) - (-1) = 0
+    tp = np.array([0, 3, 5], np.int32)
+    ti = np.array([0, 1, 2, 0, 1], np.int32)
+    tc = np.array([1, 1, 1, 1, -1], np.int32)
+    td = np.array([-1, 0], np.int32)
+    color = np.array([0, 0, 1], np.int32)
+    e = np.zeros(0, np.int32)
+    inst = T.Instance(n, rp, e, e, None, None, None, color, terms=(tp, ti, tc, td))
+    assert inst.info()["max_constraint_degree"] == 2  # spin 2 pairs with 0 and 1
+    with pytest.raises(T.TdptError, match="constraint pair"):
+        T.Instance(n, rp, e, e, None, None, None, np.array([0, 1, 0], np.int32),
+                   terms=(tp, ti, tc, td))
+
+
+def test_terms_workspace_and_range_checks():
+    from synth.constrained import slack_knapsack
+    inst = T.Instance.from_synth(slack_knapsack(5, seed=2))
+    cfg = T.RunConfig([0.5, 1.0], [0, 4096], mcs_per_swap=1, seed=0)
+    assert T.workspace_bytes(inst, cfg) > 0
