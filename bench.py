@@ -17,6 +17,9 @@ coloring: general constraints -- planted 4-colouring of a 4000-node graph
 (degree <= 6) in one-hot form (16,000 spins, 4000 one-hot terms), a 32 x 16
 grid, 50 sweeps per swap round; one step is 100 rounds, 20 steps by default.
 
+Before the warm-up the library's autotuner picks the driver and workgroup
+size on the problem itself (state restored afterwards; not timed).
+
 Prints one JSON line.  `value` is spin-updates/s over the timed steps with
 the problem already resident in HBM.
 """
@@ -391,6 +394,9 @@ def main():
     ap.add_argument("--cpu-rounds", type=int, default=None,
                     help="rounds of the oracle timed for the CPU baseline (0: skip; n200: 100, n1000: 1)")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--autotune", type=int, default=None,
+                    help="rounds per trial of the launch-shape autotuner, run before the warm-up "
+                         "(0: off; n200: 200, n1000: 1, coloring: 10)")
     ap.add_argument("--sizes", type=str, default="16,24,32,48", help="logical sizes (jcolumn)")
     ap.add_argument("--schedule", choices=["fixed", "adaptive"], default="fixed",
                     help="jcolumn: the workload's beta / P ladders, or Algorithm 2 per instance")
@@ -420,9 +426,9 @@ def main():
         sys.exit(2)
 
     big = args.workload == "n1000"
-    defaults = {"n200": dict(steps=100, warmup=5, rounds_per_step=1000, cpu_rounds=100),
-                "n1000": dict(steps=5, warmup=1, rounds_per_step=4, cpu_rounds=2),
-                "coloring": dict(steps=20, warmup=2, rounds_per_step=100, cpu_rounds=4)}
+    defaults = {"n200": dict(steps=100, warmup=5, rounds_per_step=1000, cpu_rounds=100, autotune=200),
+                "n1000": dict(steps=5, warmup=1, rounds_per_step=4, cpu_rounds=2, autotune=1),
+                "coloring": dict(steps=20, warmup=2, rounds_per_step=100, cpu_rounds=4, autotune=10)}
     for name, v in defaults.get(args.workload, defaults["n200"]).items():
         if getattr(args, name) is None:
             setattr(args, name, v)
@@ -460,6 +466,16 @@ def main():
     cfg = T.RunConfig(w.beta, w.p_q, mcs_per_swap=w.mcs_per_swap, seed=args.seed, f_target=w.f_target_q)
     prob = T.Problem(inst, cfg, device="cuda:0")
     rps = args.rounds_per_step
+    tune = None
+    if args.autotune > 0:
+        t0 = time.perf_counter()
+        rep = prob.autotune(args.autotune)
+        tune = {"driver": rep["driver"], "block": rep["block"], "ms_per_round": round(rep["ms_per_round"], 5),
+                "trials": len(rep["trials"]), "rounds_per_trial": args.autotune,
+                "seconds": round(time.perf_counter() - t0, 3)}
+        print(f"[bench] autotune: driver {tune['driver']} block {tune['block']} "
+              f"({tune['ms_per_round']:.4f} ms/round) from {tune['trials']} trials",
+              file=sys.stderr, flush=True)
     print(f"[bench] {w.name}: n={w.instance.n} R={w.replicas} warmup {args.warmup} x {rps} rounds",
           file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -541,6 +557,8 @@ def main():
         out["config"].update({"constraint": "one-hot terms", "n_terms": info["n_terms"],
                               "f_target_q": w.f_target_q,
                               "first_hit_sweep": q["first_hit_sweep"]})
+    if tune is not None:
+        out["autotune"] = tune
     if args.cpu_rounds > 0:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_rounds, sub_grid=4 if big else 8 if gen else 0)
     print(json.dumps(out), flush=True)

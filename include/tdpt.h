@@ -231,6 +231,28 @@ int tdpt_problem_set_timing(tdpt_problem *prob, int32_t every);
 int tdpt_problem_read_timing(tdpt_problem *prob, double *total_ms, int64_t *launches,
                              int64_t *rounds);
 
+/* Launch-shape autotuner.  Times each admissible (driver, threads per sweep
+ * workgroup) pair on the problem itself -- one warm-up round, then
+ * rounds_per_trial rounds between HIP events on the problem's stream -- and
+ * keeps the fastest for later runs.  Candidates: the per-round driver at 64
+ * to 1024 threads (512 for bit-packed replicas) and, where every replica's
+ * workgroup can be resident at once, the persistent driver at 64 to 512,
+ * each no larger than the largest colour class needs and no smaller than the
+ * per-phase 2^31 bounds allow.  The problem's state is saved before and
+ * restored after (the trial rounds leave no trace); since random numbers do
+ * not depend on launch shape, results after tuning equal those without.
+ * Blocks the calling thread until the trials finish. */
+typedef struct tdpt_tune_report {
+    int32_t driver;              /* chosen: 1 persistent, 0 per-round */
+    int32_t block;               /* chosen threads per sweep workgroup */
+    double ms_per_round;         /* its measured time per round */
+    int32_t n_trials;            /* candidates timed (<= 32), in this order: */
+    int32_t trial_driver[32];
+    int32_t trial_block[32];
+    double trial_ms_per_round[32];
+} tdpt_tune_report;
+int tdpt_problem_autotune(tdpt_problem *prob, int32_t rounds_per_trial, tdpt_tune_report *out);
+
 /* ---------------------------------------------------------------- batches */
 
 /* A batch advances many problems at once: every round is one sweep launch
@@ -253,6 +275,21 @@ int tdpt_batch_create(int32_t max_members, void *dev_ws, size_t ws_bytes, void *
 int tdpt_batch_set_members(tdpt_batch *batch, tdpt_problem *const *probs, int32_t count);
 /* Enqueue n_rounds rounds of every member on the batch's stream. */
 int tdpt_batch_run(tdpt_batch *batch, int64_t n_rounds);
+/* Autotune the threads per sweep workgroup of each layout group of the
+ * current members (64 to 1024, 512 for bit-packed groups, no smaller than
+ * the members' per-phase bounds allow), one group after another, timing
+ * whole batch rounds; every member's state is restored afterwards.  The
+ * choice holds until the next tdpt_batch_set_members. */
+typedef struct tdpt_batch_tune_report {
+    int32_t n_groups;                  /* layout groups (<= 32) */
+    int32_t group_block[32];           /* chosen threads per workgroup */
+    double group_ms_per_round[32];     /* batch round time with that choice */
+    int32_t n_trials;                  /* (group, block) pairs timed (<= 128) */
+    int32_t trial_group[128];
+    int32_t trial_block[128];
+    double trial_ms_per_round[128];
+} tdpt_batch_tune_report;
+int tdpt_batch_autotune(tdpt_batch *batch, int32_t rounds_per_trial, tdpt_batch_tune_report *out);
 void tdpt_batch_destroy(tdpt_batch *batch);
 
 /* Thread-local message of the last failed call ("" if none). */

@@ -6,6 +6,7 @@
 #include "tdpt_internal.h"
 
 #include <algorithm>
+#include <functional>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -93,6 +94,9 @@ struct tdpt_problem {
     int64_t trace_cap = 0;
     uint64_t fingerprint = 0;
     bool persistent = false;
+    bool persistent_ok = false;  // the persistent driver may be used (layout, key range)
+    int32_t min_block = 64;      // smallest sweep workgroup the per-phase bounds allow
+    int32_t max_class_quads = 0;
     int64_t rounds_host = 0;  // rounds done, as far as the host has enqueued them
     // optional sweep-kernel timing (HIP events on the problem's stream)
     int32_t time_every = 0;
@@ -370,6 +374,33 @@ int lay_out(tdpt_instance *in, int32_t n, const int32_t *row_ptr, const int32_t 
     return TDPT_OK;
 }
 
+// Wall time (ms) of n rounds enqueued by `enqueue` on `stream`.
+int time_rounds(hipStream_t stream, const std::function<int()> &enqueue, double &ms)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    HIP_TRY(hipEventCreate(&a), "hipEventCreate");
+    hipError_t e = hipEventCreate(&b);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return hip_fail(e, "hipEventCreate");
+    }
+    int rc = TDPT_OK;
+    e = hipEventRecord(a, stream);
+    if (e == hipSuccess) {
+        rc = enqueue();
+        if (rc == TDPT_OK) e = hipEventRecord(b, stream);
+    }
+    if (rc == TDPT_OK && e == hipSuccess) e = hipEventSynchronize(b);
+    float f = 0.f;
+    if (rc == TDPT_OK && e == hipSuccess) e = hipEventElapsedTime(&f, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "autotune timing");
+    ms = f;
+    return TDPT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -605,6 +636,10 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     const int64_t quads_per_thread = (in->max_class_quads + blk - 1) / blk;
     if (quads_per_thread * 4 * 2 * hmax >= ((int64_t)1 << 31))
         return fail(TDPT_E_RANGE, "per-phase energy change can reach 2^31");
+    // smallest workgroup (multiple of 64) keeping every lane's per-phase sums below 2^31
+    const int64_t q_allowed = std::max<int64_t>(1, (((int64_t)1 << 31) - 1) / (8 * std::max<int64_t>(hmax, 1)));
+    const int64_t min_block_q = (in->max_class_quads + q_allowed - 1) / q_allowed;
+    const int32_t min_block = (int32_t)std::max<int64_t>(64, (min_block_q + 63) / 64 * 64);
     if (in->g_bound > 0 && pmax > (((int64_t)1 << 51) / in->g_bound))
         return fail(TDPT_E_RANGE, "energy differences can reach 2^52");
     const int64_t ebound = in->abs_f_bound + pmax * in->g_bound;
@@ -638,6 +673,8 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     p->R = R;
     p->mcs = cfg->mcs_per_swap;
     p->rank = in->rank;
+    p->min_block = min_block;
+    p->max_class_quads = in->max_class_quads;
     p->ws = (uint8_t *)dev_ws;
     p->ws_bytes = ws_bytes;
     p->mut_off = 0;
@@ -811,7 +848,8 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     // the persistent driver needs every slot's block resident at once
     p->persistent = false;
     const char *pe = getenv("TDPT_PERSISTENT");
-    if (!(pe && pe[0] == '0') && !bits && in->abs_f_bound < tdpt::kKeyOffset) {
+    p->persistent_ok = !(pe && pe[0] == '0') && !bits && in->abs_f_bound < tdpt::kKeyOffset;
+    if (p->persistent_ok) {
         tdpt::DevProblem dq = d;
         dq.block = sweep_block(in, true);
         int max_blocks = 0;
@@ -913,6 +951,78 @@ int tdpt_problem_read_timing(tdpt_problem *p, double *total_ms, int64_t *launche
     *total_ms = total;
     *rounds = p->timed_rounds;
     return TDPT_OK;
+}
+
+int tdpt_problem_autotune(tdpt_problem *p, int32_t rounds_per_trial, tdpt_tune_report *out)
+{
+    if (!p || !out) return fail(TDPT_E_INVALID, "NULL argument");
+    if (rounds_per_trial < 1) return fail(TDPT_E_INVALID, "rounds_per_trial must be >= 1");
+    if ((p->rounds_host + 2 * 40 * (int64_t)rounds_per_trial) * (int64_t)p->mcs > ((int64_t)1 << 32))
+        return fail(TDPT_E_RANGE, "a problem runs at most 2^32 sweeps");
+    // candidates: (driver, threads per workgroup)
+    std::vector<std::pair<int, int>> cand;
+    const int cap = p->dp.bits ? tdpt::kBitsBlock : tdpt::kMaxBlock;
+    const int per_round[] = {64, 128, 192, 256, 384, 512, 640, 768, 1024};
+    const int quads = p->max_class_quads;
+    for (int b : per_round)
+        if (b >= p->min_block && b <= cap && b <= std::max(64, (quads + 63) / 64 * 64)) cand.push_back({0, b});
+    if (p->persistent_ok) {
+        for (int b = 64; b <= tdpt::kMaxBlock / 2; b += 64) {
+            if (b < p->min_block || b > std::max(64, (quads + 63) / 64 * 64)) continue;
+            tdpt::DevProblem dq = p->dp;
+            dq.block = b;
+            int max_blocks = 0;
+            HIP_TRY(tdpt::persistent_max_blocks(dq, &max_blocks), "occupancy query");
+            if (max_blocks >= p->R) cand.push_back({1, b});
+        }
+    }
+    if (cand.empty()) return fail(TDPT_E_INVALID, "no launch shape satisfies the problem's bounds");
+    if (cand.size() > 32) cand.resize(32);
+    // keep the state: every trial round is undone afterwards
+    size_t bytes = 0;
+    int rc = tdpt_problem_save(p, nullptr, &bytes);
+    if (rc) return rc;
+    std::vector<uint8_t> saved(bytes);
+    rc = tdpt_problem_save(p, saved.data(), &bytes);
+    if (rc) return rc;
+    const bool old_persistent = p->persistent;
+    const int old_block = p->dp.block;
+    const int32_t old_every = p->time_every;
+    p->time_every = 0;
+    memset(out, 0, sizeof(*out));
+    double best = 1e300;
+    int best_i = -1;
+    for (size_t i = 0; i < cand.size() && rc == TDPT_OK; ++i) {
+        p->persistent = cand[i].first == 1;
+        p->dp.block = cand[i].second;
+        rc = tdpt_problem_run(p, 1);  // warm-up
+        double ms = 0.0;
+        if (rc == TDPT_OK)
+            rc = time_rounds(p->stream, [&] { return tdpt_problem_run(p, rounds_per_trial); }, ms);
+        if (rc) break;
+        const double per = ms / rounds_per_trial;
+        out->trial_driver[i] = cand[i].first;
+        out->trial_block[i] = cand[i].second;
+        out->trial_ms_per_round[i] = per;
+        out->n_trials = (int32_t)i + 1;
+        if (per < best) {
+            best = per;
+            best_i = (int)i;
+        }
+    }
+    p->time_every = old_every;
+    if (rc || best_i < 0) {
+        p->persistent = old_persistent;
+        p->dp.block = old_block;
+        (void)tdpt_problem_load(p, saved.data(), saved.size());
+        return rc ? rc : fail(TDPT_E_DEVICE, "autotune timed nothing");
+    }
+    p->persistent = cand[best_i].first == 1;
+    p->dp.block = cand[best_i].second;
+    out->driver = cand[best_i].first;
+    out->block = cand[best_i].second;
+    out->ms_per_round = best;
+    return tdpt_problem_load(p, saved.data(), saved.size());
 }
 
 static int d2h(tdpt_problem *p, void *dst, const void *src, size_t bytes)
@@ -1073,6 +1183,8 @@ struct tdpt_batch {
         int first_member, count, blocks, prefix_off;
         size_t max_stride;
         int max_words;
+        int block;      // threads per sweep workgroup of this group
+        int min_block;  // smallest the members' per-phase bounds allow
     };
     std::vector<Group> groups;
     hipEvent_t done = nullptr;
@@ -1150,15 +1262,26 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
         const bool start = b->groups.empty() || m[i]->dp.bits != m[i - 1]->dp.bits ||
                            m[i]->dp.narrow != m[i - 1]->dp.narrow || m[i]->dp.wd != m[i - 1]->dp.wd;
         if (start) {
-            tdpt_batch::Group g{(int)i, 0, 0, (int)prefix.size(), 0, 0};
+            tdpt_batch::Group g{(int)i, 0, 0, (int)prefix.size(), 0, 0, 0, 64};
             b->groups.push_back(g);
         }
         auto &g = b->groups.back();
+        g.min_block = std::max(g.min_block, m[i]->min_block);
         prefix.push_back(g.blocks);
         g.blocks += m[i]->dp.bits ? (m[i]->R + tdpt::kBitSlots - 1) / tdpt::kBitSlots : m[i]->R;
         g.count += 1;
         g.max_stride = std::max(g.max_stride, (size_t)m[i]->dp.stride);
         g.max_words = std::max(g.max_words, m[i]->dp.n_words);
+    }
+    for (auto &g : b->groups) {
+        const int cap = b->members[g.first_member]->dp.bits ? tdpt::kBitsBlock : tdpt::kMaxBlock;
+        if (g.min_block > cap) {
+            b->members.clear();
+            b->groups.clear();
+            return fail(TDPT_E_RANGE, "a member's per-phase energy bounds need a larger workgroup than "
+                                      "the batched sweep allows");
+        }
+        g.block = std::min(std::max(b->block, g.min_block), cap);
     }
     if (!m.empty()) {
         HIP_TRY(hipMemcpyAsync(b->ws, table.data(), table.size() * sizeof(tdpt::DevProblem),
@@ -1185,10 +1308,10 @@ int tdpt_batch_run(tdpt_batch *b, int64_t n_rounds)
             const tdpt::DevProblem &d0 = b->members[g.first_member]->dp;
             hipError_t e = d0.bits ? tdpt::launch_batch_sweep_bits(d0, table + g.first_member,
                                                                    prefix + g.prefix_off, g.count, g.blocks,
-                                                                   b->block, g.max_words, b->stream)
+                                                                   g.block, g.max_words, b->stream)
                                    : tdpt::launch_batch_sweep(d0, table + g.first_member,
                                                               prefix + g.prefix_off, g.count, g.blocks,
-                                                              b->block, g.max_stride, b->stream);
+                                                              g.block, g.max_stride, b->stream);
             if (e != hipSuccess) return hip_fail(e, "launch batch sweep");
         }
         hipError_t e = tdpt::launch_batch_swap(table, (int)b->members.size(), b->stream);
@@ -1200,6 +1323,65 @@ int tdpt_batch_run(tdpt_batch *b, int64_t n_rounds)
         p->rounds_host += n_rounds;
     }
     return TDPT_OK;
+}
+
+int tdpt_batch_autotune(tdpt_batch *b, int32_t rounds_per_trial, tdpt_batch_tune_report *out)
+{
+    if (!b || !out) return fail(TDPT_E_INVALID, "NULL argument");
+    if (rounds_per_trial < 1) return fail(TDPT_E_INVALID, "rounds_per_trial must be >= 1");
+    memset(out, 0, sizeof(*out));
+    if (b->members.empty()) return TDPT_OK;
+    if (b->groups.size() > 32) return fail(TDPT_E_INVALID, "more than 32 layout groups");
+    // keep every member's state: the trial rounds are undone afterwards
+    std::vector<std::vector<uint8_t>> saved(b->members.size());
+    for (size_t i = 0; i < b->members.size(); ++i) {
+        size_t bytes = 0;
+        int rc = tdpt_problem_save(b->members[i], nullptr, &bytes);
+        if (rc) return rc;
+        saved[i].resize(bytes);
+        rc = tdpt_problem_save(b->members[i], saved[i].data(), &bytes);
+        if (rc) return rc;
+    }
+    auto restore = [&]() {
+        int rc = TDPT_OK;
+        for (size_t i = 0; i < b->members.size() && rc == TDPT_OK; ++i) {
+            HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+            rc = tdpt_problem_load(b->members[i], saved[i].data(), saved[i].size());
+        }
+        return rc;
+    };
+    const int sizes[] = {64, 128, 256, 512, 1024};
+    int rc = TDPT_OK;
+    out->n_groups = (int32_t)b->groups.size();
+    for (size_t gi = 0; gi < b->groups.size() && rc == TDPT_OK; ++gi) {
+        auto &g = b->groups[gi];
+        const int cap = b->members[g.first_member]->dp.bits ? tdpt::kBitsBlock : tdpt::kMaxBlock;
+        double best = 1e300;
+        int best_block = g.block;
+        for (int sz : sizes) {
+            if (sz < g.min_block || sz > cap || out->n_trials >= 128) continue;
+            g.block = sz;
+            rc = tdpt_batch_run(b, 1);  // warm-up
+            double ms = 0.0;
+            if (rc == TDPT_OK)
+                rc = time_rounds(b->stream, [&] { return tdpt_batch_run(b, rounds_per_trial); }, ms);
+            if (rc) break;
+            const double per = ms / rounds_per_trial;
+            const int t = out->n_trials++;
+            out->trial_group[t] = (int32_t)gi;
+            out->trial_block[t] = sz;
+            out->trial_ms_per_round[t] = per;
+            if (per < best) {
+                best = per;
+                best_block = sz;
+            }
+        }
+        g.block = best_block;
+        out->group_block[gi] = best_block;
+        out->group_ms_per_round[gi] = best;
+    }
+    const int rc2 = restore();
+    return rc ? rc : rc2;
 }
 
 void tdpt_batch_destroy(tdpt_batch *b) { delete b; }

@@ -27,7 +27,7 @@ EXPORTED = [
     "tdpt_problem_save", "tdpt_problem_load", "tdpt_problem_destroy", "tdpt_last_error",
     "tdpt_problem_set_timing", "tdpt_problem_read_timing",
     "tdpt_batch_workspace_bytes", "tdpt_batch_create", "tdpt_batch_set_members",
-    "tdpt_batch_run", "tdpt_batch_destroy",
+    "tdpt_batch_run", "tdpt_batch_destroy", "tdpt_problem_autotune", "tdpt_batch_autotune",
 ]
 
 
@@ -53,6 +53,19 @@ class _Info(ctypes.Structure):
                 ("max_degree", ctypes.c_int32), ("max_copy_degree", ctypes.c_int32),
                 ("narrow", ctypes.c_int32), ("nnz", ctypes.c_int64), ("m", ctypes.c_int32),
                 ("n_terms", ctypes.c_int32), ("max_constraint_degree", ctypes.c_int32)]
+
+
+class _TuneReport(ctypes.Structure):
+    _fields_ = [("driver", ctypes.c_int32), ("block", ctypes.c_int32), ("ms_per_round", ctypes.c_double),
+                ("n_trials", ctypes.c_int32), ("trial_driver", ctypes.c_int32 * 32),
+                ("trial_block", ctypes.c_int32 * 32), ("trial_ms_per_round", ctypes.c_double * 32)]
+
+
+class _BatchTuneReport(ctypes.Structure):
+    _fields_ = [("n_groups", ctypes.c_int32), ("group_block", ctypes.c_int32 * 32),
+                ("group_ms_per_round", ctypes.c_double * 32), ("n_trials", ctypes.c_int32),
+                ("trial_group", ctypes.c_int32 * 128), ("trial_block", ctypes.c_int32 * 128),
+                ("trial_ms_per_round", ctypes.c_double * 128)]
 
 
 class _Status(ctypes.Structure):
@@ -95,6 +108,8 @@ def load_library():
         "tdpt_batch_create": [I32, P, SZ, P, P],
         "tdpt_batch_set_members": [P, P, I32],
         "tdpt_batch_run": [P, I64],
+        "tdpt_problem_autotune": [P, I32, P],
+        "tdpt_batch_autotune": [P, I32, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -293,6 +308,15 @@ class Problem:
         buf = (ctypes.c_uint8 * len(blob)).from_buffer_copy(blob)
         _check(_lib.tdpt_problem_load(self._h, buf, len(blob)))
 
+    def autotune(self, rounds_per_trial: int = 10) -> dict:
+        """Time the admissible (driver, workgroup size) pairs on this problem
+        and keep the fastest; the problem's state is left as it was."""
+        r = _TuneReport()
+        _check(_lib.tdpt_problem_autotune(self._h, int(rounds_per_trial), ctypes.byref(r)))
+        k = r.n_trials
+        return {"driver": r.driver, "block": r.block, "ms_per_round": r.ms_per_round,
+                "trials": [(r.trial_driver[i], r.trial_block[i], r.trial_ms_per_round[i]) for i in range(k)]}
+
     def set_timing(self, every: int):
         """Time every `every`-th sweep-kernel launch with HIP events (0: off)."""
         _check(_lib.tdpt_problem_set_timing(self._h, int(every)))
@@ -342,6 +366,15 @@ class Batch:
 
     def run(self, n_rounds: int):
         _check(_lib.tdpt_batch_run(self._h, int(n_rounds)))
+
+    def autotune(self, rounds_per_trial: int = 3) -> dict:
+        """Pick each layout group's workgroup size by timing batch rounds;
+        every member's state is left as it was."""
+        r = _BatchTuneReport()
+        _check(_lib.tdpt_batch_autotune(self._h, int(rounds_per_trial), ctypes.byref(r)))
+        g, k = r.n_groups, r.n_trials
+        return {"group_block": list(r.group_block[:g]), "group_ms_per_round": list(r.group_ms_per_round[:g]),
+                "trials": [(r.trial_group[i], r.trial_block[i], r.trial_ms_per_round[i]) for i in range(k)]}
 
     def close(self):
         h = getattr(self, "_h", None)

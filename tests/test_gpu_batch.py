@@ -149,3 +149,26 @@ def test_jcolumn_columns_equal_the_oracle(T):
         assert np.array_equal(f, o["f"]) and np.array_equal(g, o["g"]), j
     o = O.run(w.instance, beta, p_q, mcs_per_swap=5, n_rounds=8, seed=7, trace=True)
     assert np.array_equal(two_d.states(), o["states"])
+
+
+def test_batch_autotune_keeps_results(T):
+    """Autotuning a batch restores every member; the tuned batch run equals
+    the members run alone."""
+    rounds = 12
+    specs = _members()
+    alone, probs = [], []
+    for name, inst, beta, p_q, mcs, seed in specs:
+        cfg = T.RunConfig(beta, p_q, mcs_per_swap=mcs, seed=seed, trace_cap=rounds)
+        P = T.Problem(T.Instance.from_synth(inst), cfg)
+        P.run(rounds)
+        alone.append(_outputs(P))
+        probs.append(T.Problem(T.Instance.from_synth(inst), cfg))
+    B = T.Batch(8)
+    B.set_members(probs)
+    B.run(4)
+    rep = B.autotune(2)
+    _say(f"[batch] autotune: {rep['group_block']}")
+    assert len(rep["group_block"]) >= 2 and all(b % 64 == 0 for b in rep["group_block"])
+    B.run(rounds - 4)
+    for (name, *_), a, P in zip(specs, alone, probs):
+        _same(a, _outputs(P))

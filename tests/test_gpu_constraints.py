@@ -134,3 +134,16 @@ def test_coloring_workload_full_grid_invariants(T):
     if q["best_f_q"] < 2**62:
         s, bf, _ = P.best()
         assert O.energy(w.instance, s) == (bf, 0)
+
+
+def test_autotuned_coloring_matches_oracle(T):
+    pc = planted_coloring(200, 4, degree=5, seed=3)
+    beta = np.geomspace(0.3, 4.0, 8)
+    p_q = np.linspace(0, 8192, 4).astype(np.int32)
+    P = T.Problem(T.Instance.from_synth(pc.instance),
+                  T.RunConfig(beta, p_q, mcs_per_swap=5, seed=2, f_target=pc.f_target_q, trace_cap=30))
+    rep = P.autotune(3)
+    _say(f"[constraints] autotune coloring-200x4: driver {rep['driver']} block {rep['block']}")
+    P.run(30)
+    o = O.run(pc.instance, beta, p_q, mcs_per_swap=5, n_rounds=30, seed=2, f_target=pc.f_target_q, trace=True)
+    assert_same(o, P, "tuned coloring")

@@ -366,3 +366,61 @@ def test_n1000_full_grid_invariants(T):
     for pos in rng.choice(w.replicas, size=6, replace=False):
         assert O.energy(w.instance, st[pos]) == (f[pos], g[pos])
     assert np.array_equal(np.sort(P.perm()), np.arange(w.replicas))
+
+
+# ----------------------------------------------------------------- autotuner
+
+def test_autotune_leaves_results_unchanged(T):
+    """The autotuner times launch shapes on the problem itself and restores
+    its state: the state right after tuning equals the state before, and a
+    tuned run is bit-identical to an untuned one (and to the oracle)."""
+    w = wishart_small()
+
+    def make():
+        P = T.Problem(T.Instance.from_synth(w.instance),
+                      T.RunConfig(w.beta, w.p_q, mcs_per_swap=5, seed=8, trace_cap=70))
+        P.run(30)
+        return P
+    a, b = make(), make()
+    before = (b.states(), b.energies(), b.query())
+    rep = b.autotune(3)
+    _say(f"[parity] autotune N12: {rep['driver']} {rep['block']} from {len(rep['trials'])} trials")
+    assert len(rep["trials"]) >= 2
+    assert (rep["driver"], rep["block"]) in {(d, k) for d, k, _ in rep["trials"]}
+    assert np.array_equal(before[0], b.states())
+    assert all(np.array_equal(x, y) for x, y in zip(before[1], b.energies()))
+    assert before[2]["rounds_done"] == b.query()["rounds_done"]
+    a.run(40)
+    b.run(40)
+    assert b.query()["driver"] == rep["driver"]
+    assert np.array_equal(a.states(), b.states())
+    assert all(np.array_equal(x, y) for x, y in zip(a.counters(), b.counters()))
+    o = O.run(w.instance, w.beta, w.p_q, mcs_per_swap=5, n_rounds=70, seed=8, trace=True)
+    assert_same(o, b, "tuned N12")
+
+
+def test_autotune_n200_and_bits(T):
+    """Tuning the N=200 workload and a forced bit-packed problem picks an
+    admissible shape and keeps results bit-exact."""
+    w = wishart_n200()
+    P = T.Problem(T.Instance.from_synth(w.instance),
+                  T.RunConfig(w.beta, w.p_q, mcs_per_swap=1, seed=1, trace_cap=40))
+    rep = P.autotune(20)
+    _say(f"[parity] autotune N200: {rep}")
+    assert rep["block"] % 64 == 0 and 64 <= rep["block"] <= 1024
+    P.run(40)
+    o = O.run(w.instance, w.beta, w.p_q, mcs_per_swap=1, n_rounds=40, seed=1, trace=True)
+    assert_same(o, P, "tuned N200")
+
+    def bits():
+        ws = wishart_small()
+        Q = T.Problem(T.Instance.from_synth(ws.instance),
+                      T.RunConfig(ws.beta, ws.p_q, mcs_per_swap=5, seed=2, trace_cap=20))
+        r = Q.autotune(2)
+        assert all(d == 0 and k <= 512 for d, k, _ in r["trials"])
+        Q.run(20)
+        return Q
+    Q = _with_env("TDPT_LAYOUT", "bits", bits)
+    ws = wishart_small()
+    o = O.run(ws.instance, ws.beta, ws.p_q, mcs_per_swap=5, n_rounds=20, seed=2, trace=True)
+    assert_same(o, Q, "tuned bits")
