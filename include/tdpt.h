@@ -290,6 +290,14 @@ typedef struct tdpt_batch_tune_report {
     double trial_ms_per_round[128];
 } tdpt_batch_tune_report;
 int tdpt_batch_autotune(tdpt_batch *batch, int32_t rounds_per_trial, tdpt_batch_tune_report *out);
+/* Replay rounds from a HIP graph: with rounds_per_graph = k > 0, the launches
+ * of k rounds (every group's sweep, the swap step) are captured once into a
+ * graph -- kernel launches only, on a private non-blocking stream -- and
+ * tdpt_batch_run enqueues floor(n / k) replays of it on the batch's stream,
+ * then the remaining rounds directly.  0 (the default) launches every round
+ * directly.  The graph is rebuilt after tdpt_batch_set_members or
+ * tdpt_batch_autotune; results are the same either way. */
+int tdpt_batch_set_graph(tdpt_batch *batch, int32_t rounds_per_graph);
 void tdpt_batch_destroy(tdpt_batch *batch);
 
 /* Thread-local message of the last failed call ("" if none). */

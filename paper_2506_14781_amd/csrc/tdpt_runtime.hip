@@ -1188,13 +1188,70 @@ struct tdpt_batch {
     };
     std::vector<Group> groups;
     hipEvent_t done = nullptr;
+    // HIP graph of graph_rounds rounds (0: launch every round directly),
+    // captured on cap_stream and replayed on stream; rebuilt after any change
+    // of members or launch shapes.
+    int32_t graph_rounds = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph = nullptr;
+    void drop_graph()
+    {
+        if (graph) (void)hipGraphExecDestroy(graph);
+        graph = nullptr;
+    }
     ~tdpt_batch()
     {
+        drop_graph();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
         if (done) (void)hipEventDestroy(done);
     }
 };
 
 static size_t batch_table_bytes(int32_t cap) { return align_up((size_t)cap * sizeof(tdpt::DevProblem), 256); }
+
+// One round of every member: the sweep launch of each layout group, then the
+// swap-and-track launch.
+static int enqueue_batch_round(tdpt_batch *b, hipStream_t s)
+{
+    const tdpt::DevProblem *table = (const tdpt::DevProblem *)b->ws;
+    const int *prefix = (const int *)(b->ws + batch_table_bytes(b->cap));
+    for (const auto &g : b->groups) {
+        const tdpt::DevProblem &d0 = b->members[g.first_member]->dp;
+        hipError_t e = d0.bits ? tdpt::launch_batch_sweep_bits(d0, table + g.first_member, prefix + g.prefix_off,
+                                                               g.count, g.blocks, g.block, g.max_words, s)
+                               : tdpt::launch_batch_sweep(d0, table + g.first_member, prefix + g.prefix_off,
+                                                          g.count, g.blocks, g.block, g.max_stride, s);
+        if (e != hipSuccess) return hip_fail(e, "launch batch sweep");
+    }
+    hipError_t e = tdpt::launch_batch_swap(table, (int)b->members.size(), s);
+    if (e != hipSuccess) return hip_fail(e, "launch batch swap");
+    return TDPT_OK;
+}
+
+// Capture graph_rounds rounds into b->graph (kernel launches only).
+static int capture_batch_graph(tdpt_batch *b)
+{
+    b->drop_graph();
+    if (!b->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+    HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+    int rc = TDPT_OK;
+    for (int32_t r = 0; r < b->graph_rounds && rc == TDPT_OK; ++r) rc = enqueue_batch_round(b, b->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        b->graph = nullptr;
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    return TDPT_OK;
+}
+
 
 int tdpt_batch_workspace_bytes(int32_t max_members, size_t *bytes)
 {
@@ -1253,6 +1310,7 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
         if (x->dp.wd != y->dp.wd) return x->dp.wd < y->dp.wd;
         return x->dp.stride > y->dp.stride;
     });
+    b->drop_graph();
     b->members = m;
     b->groups.clear();
     std::vector<tdpt::DevProblem> table(m.size());
@@ -1301,21 +1359,18 @@ int tdpt_batch_run(tdpt_batch *b, int64_t n_rounds)
     for (auto *p : b->members)
         if ((p->rounds_host + n_rounds) * (int64_t)p->mcs > ((int64_t)1 << 32))
             return fail(TDPT_E_RANGE, "a problem runs at most 2^32 sweeps");
-    const tdpt::DevProblem *table = (const tdpt::DevProblem *)b->ws;
-    const int *prefix = (const int *)(b->ws + batch_table_bytes(b->cap));
-    for (int64_t r = 0; r < n_rounds; ++r) {
-        for (const auto &g : b->groups) {
-            const tdpt::DevProblem &d0 = b->members[g.first_member]->dp;
-            hipError_t e = d0.bits ? tdpt::launch_batch_sweep_bits(d0, table + g.first_member,
-                                                                   prefix + g.prefix_off, g.count, g.blocks,
-                                                                   g.block, g.max_words, b->stream)
-                                   : tdpt::launch_batch_sweep(d0, table + g.first_member,
-                                                              prefix + g.prefix_off, g.count, g.blocks,
-                                                              g.block, g.max_stride, b->stream);
-            if (e != hipSuccess) return hip_fail(e, "launch batch sweep");
+    int64_t r = 0;
+    if (b->graph_rounds > 0 && n_rounds >= b->graph_rounds) {
+        if (!b->graph) {
+            int rc = capture_batch_graph(b);
+            if (rc) return rc;
         }
-        hipError_t e = tdpt::launch_batch_swap(table, (int)b->members.size(), b->stream);
-        if (e != hipSuccess) return hip_fail(e, "launch batch swap");
+        for (; r + b->graph_rounds <= n_rounds; r += b->graph_rounds)
+            HIP_TRY(hipGraphLaunch(b->graph, b->stream), "hipGraphLaunch");
+    }
+    for (; r < n_rounds; ++r) {
+        int rc = enqueue_batch_round(b, b->stream);
+        if (rc) return rc;
     }
     HIP_TRY(hipEventRecord(b->done, b->stream), "hipEventRecord");
     for (auto *p : b->members) {
@@ -1352,6 +1407,9 @@ int tdpt_batch_autotune(tdpt_batch *b, int32_t rounds_per_trial, tdpt_batch_tune
     };
     const int sizes[] = {64, 128, 256, 512, 1024};
     int rc = TDPT_OK;
+    const int32_t graph_rounds = b->graph_rounds;
+    b->graph_rounds = 0;  // trials launch directly
+    b->drop_graph();
     out->n_groups = (int32_t)b->groups.size();
     for (size_t gi = 0; gi < b->groups.size() && rc == TDPT_OK; ++gi) {
         auto &g = b->groups[gi];
@@ -1380,8 +1438,20 @@ int tdpt_batch_autotune(tdpt_batch *b, int32_t rounds_per_trial, tdpt_batch_tune
         out->group_block[gi] = best_block;
         out->group_ms_per_round[gi] = best;
     }
+    b->graph_rounds = graph_rounds;
     const int rc2 = restore();
     return rc ? rc : rc2;
+}
+
+int tdpt_batch_set_graph(tdpt_batch *b, int32_t rounds_per_graph)
+{
+    if (!b) return fail(TDPT_E_INVALID, "batch is NULL");
+    if (rounds_per_graph < 0 || rounds_per_graph > 4096)
+        return fail(TDPT_E_INVALID, "rounds_per_graph must be in [0, 4096]");
+    HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    b->drop_graph();
+    b->graph_rounds = rounds_per_graph;
+    return TDPT_OK;
 }
 
 void tdpt_batch_destroy(tdpt_batch *b) { delete b; }

@@ -28,6 +28,7 @@ EXPORTED = [
     "tdpt_problem_set_timing", "tdpt_problem_read_timing",
     "tdpt_batch_workspace_bytes", "tdpt_batch_create", "tdpt_batch_set_members",
     "tdpt_batch_run", "tdpt_batch_destroy", "tdpt_problem_autotune", "tdpt_batch_autotune",
+    "tdpt_batch_set_graph",
 ]
 
 
@@ -110,6 +111,7 @@ def load_library():
         "tdpt_batch_run": [P, I64],
         "tdpt_problem_autotune": [P, I32, P],
         "tdpt_batch_autotune": [P, I32, P],
+        "tdpt_batch_set_graph": [P, I32],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -366,6 +368,10 @@ class Batch:
 
     def run(self, n_rounds: int):
         _check(_lib.tdpt_batch_run(self._h, int(n_rounds)))
+
+    def set_graph(self, rounds_per_graph: int):
+        """Replay runs from a HIP graph of this many rounds (0: direct launches)."""
+        _check(_lib.tdpt_batch_set_graph(self._h, int(rounds_per_graph)))
 
     def autotune(self, rounds_per_trial: int = 3) -> dict:
         """Pick each layout group's workgroup size by timing batch rounds;

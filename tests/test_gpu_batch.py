@@ -172,3 +172,40 @@ def test_batch_autotune_keeps_results(T):
     B.run(rounds - 4)
     for (name, *_), a, P in zip(specs, alone, probs):
         _same(a, _outputs(P))
+
+
+def test_graph_replays_equal_direct_launches(T):
+    """Batch rounds replayed from a captured HIP graph equal direct launches
+    after every replay, with host reads and other launches in between, across
+    a membership change (which rebuilds the graph), and against the oracle."""
+    specs = _members()
+
+    def make():
+        return [T.Problem(T.Instance.from_synth(inst),
+                          T.RunConfig(beta, p_q, mcs_per_swap=mcs, seed=seed, trace_cap=64))
+                for name, inst, beta, p_q, mcs, seed in specs]
+    pa, pb = make(), make()
+    A, B = T.Batch(8), T.Batch(8)
+    A.set_members(pa)
+    A.set_graph(4)
+    B.set_members(pb)
+    total = 0
+    for k, n in enumerate([4, 9, 4, 8, 3]):
+        _say(f"[batch] graph replay step {k}: {n} rounds")
+        A.run(n)
+        B.run(n)
+        total += n
+        for x, y in zip(pa, pb):
+            _same(_outputs(x), _outputs(y))
+        pa[0].energies()  # host read between replays
+    A.set_members(pa[1:3])
+    B.set_members(pb[1:3])
+    A.run(8)
+    B.run(8)
+    for x, y in zip(pa, pb):
+        _same(_outputs(x), _outputs(y))
+    name, inst, beta, p_q, mcs, seed = specs[1]
+    o = O.run(inst, beta, p_q, mcs_per_swap=mcs, n_rounds=total + 8, seed=seed, trace=True)
+    assert np.array_equal(pa[1].states(), o["states"])
+    f, g = pa[1].energies()
+    assert np.array_equal(f, o["f"]) and np.array_equal(g, o["g"])
