@@ -133,10 +133,9 @@ __device__ __forceinline__ Rsrc make_rsrc(const DevProblem &P)
         return r;
     }
     if (P.narrow) {
-        const int bytes = (P.wd / 2) * P.n_pad * 4;
-        r.a = rsrc(P.nbi, bytes);
-        r.b = rsrc(P.nbj, bytes);
-        r.ch = rsrc(P.chp, P.n_pad * 4);
+        r.a = rsrc(P.nb_idx, P.wd * P.n_pad * 4);
+        r.b = rsrc(P.nbj, (P.wd / 2) * P.n_pad * 4);
+        r.ch = rsrc(P.ch_idx, P.n_pad * 8);
     } else {
         const int bytes = P.wd * P.n_pad * 4;
         r.a = rsrc(P.nb_idx, bytes);
@@ -157,6 +156,25 @@ __device__ __forceinline__ v4i bload(const __amdgpu_buffer_rsrc_t &r, int voff, 
 {
     return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
 }
+
+// The replica a byte-layout sweep workgroup holds sits at LDS byte 0: the
+// sweep kernels declare no static LDS, so their dynamic LDS starts there.
+// Reading it through an LDS pointer with the constant base 0 lets a
+// neighbour's index serve directly as the gather address (a pointer to the
+// dynamic array would add its link-time base to every index).  The kernels
+// check the assumption once and refuse to run if it does not hold.
+typedef __attribute__((address_space(3))) int8_t lds8_t;
+typedef __attribute__((address_space(3))) uint32_t lds32_t;
+
+__device__ __forceinline__ lds8_t *replica_lds() { return (lds8_t *)(uintptr_t)0u; }
+
+__device__ __forceinline__ bool replica_at_zero(int8_t *lds)
+{
+    return (uint32_t)(uintptr_t)(lds8_t *)lds == 0u;
+}
+
+// Error word value when a sweep kernel finds its dynamic LDS elsewhere.
+constexpr int64_t kErrLdsBase = 2;
 
 // Per-slot parameters of the current round.
 struct SlotParams {
@@ -180,16 +198,19 @@ __device__ __forceinline__ SlotParams slot_params(const DevProblem &P, int pos, 
 }
 
 // Structure of one quad (4 consecutive colour-major spins): one 16-byte
-// load per structure row.  Up to 8 neighbours per spin every row is held at
-// once; wider rows are streamed in chunks by quad_fields (kStream), which
+// load per structure row.  Neighbour rows hold 32-bit LDS byte addresses
+// (read without any address arithmetic); coupling rows hold int16 pairs
+// (narrow) or int32 (wide).  Up to 8 neighbours per spin every row is held
+// at once; wider rows are streamed in chunks by quad_fields (kStream), which
 // keeps them out of spill territory.
 template <bool NARROW, int WD>
 struct QuadS {
     static constexpr bool kStream = WD > 8;
-    static constexpr int K = kStream ? 1 : (NARROW ? WD / 2 : WD);
-    v4i a[K];    // narrow: index pairs; wide: indices
-    v4i b[K];    // narrow: coupling pairs; wide: couplings
-    v4i c0, c1;  // narrow: copy pairs in c0; wide: two copy rows
+    static constexpr int KA = kStream ? 1 : WD;                     // index rows
+    static constexpr int KB = kStream ? 1 : (NARROW ? WD / 2 : WD); // coupling rows
+    v4i a[KA];   // neighbour indices
+    v4i b[KB];   // narrow: coupling pairs (neighbours 2k, 2k+1); wide: couplings
+    v4i c0, c1;  // the two copy-neighbour rows
     v4i bias;    // fields (zero when the instance has none)
     int voff;    // byte offset of the quad in a structure row
 };
@@ -202,14 +223,11 @@ __device__ __forceinline__ void load_quad(const DevProblem &P, const Rsrc &Rs, i
     Q.voff = voff;
     if constexpr (!QuadS<NARROW, WD>::kStream) {
 #pragma unroll
-        for (int k = 0; k < QuadS<NARROW, WD>::K; ++k) {
-            Q.a[k] = bload(Rs.a, voff, k * row);
-            Q.b[k] = bload(Rs.b, voff, k * row);
-        }
+        for (int k = 0; k < QuadS<NARROW, WD>::KA; ++k) Q.a[k] = bload(Rs.a, voff, k * row);
+#pragma unroll
+        for (int k = 0; k < QuadS<NARROW, WD>::KB; ++k) Q.b[k] = bload(Rs.b, voff, k * row);
     }
-    if constexpr (NARROW) {
-        Q.c0 = bload(Rs.ch, voff, 0);
-    } else if (!P.gen) {
+    if (NARROW || !P.gen) {
         Q.c0 = bload(Rs.ch, voff, 0);
         Q.c1 = bload(Rs.ch, voff, row);
     }
@@ -225,7 +243,7 @@ __device__ __forceinline__ int sbyte(uint32_t w, int j)
 // Half the penalty field of the 4 spins of a quad under general constraints:
 // kh + sum_k w_k s_k over the constraint ELL, streamed 4 rows at a time (the
 // width is a multiple of 4; padding rows name the zero spin with weight 0).
-__device__ __forceinline__ void quad_constraint_sum(const DevProblem &P, const Rsrc &Rs, const int8_t *s,
+__device__ __forceinline__ void quad_constraint_sum(const DevProblem &P, const Rsrc &Rs, const lds8_t *s,
                                                     int voff, int cs[4])
 {
     const v4i k = bload(Rs.kh, voff, 0);
@@ -253,117 +271,92 @@ __device__ __forceinline__ void quad_constraint_sum(const DevProblem &P, const R
 
 // Local fields of the 4 spins of a quad from the LDS spins s: hp = problem
 // part (couplings and field), cs = half the penalty field (the sum of the
-// copy neighbours, or the general-constraint sum).  NARROW
-// instances keep every field below 2^22, so the 16-bit dot products are
-// exact.
+// copy neighbours, or the general-constraint sum).  NARROW instances keep
+// every field below 2^22, so the 16-bit dot products are exact.
 template <bool NARROW, int WD>
-__device__ __forceinline__ void quad_fields(const DevProblem &P, const Rsrc &Rs, const int8_t *s,
+__device__ __forceinline__ void quad_fields(const DevProblem &P, const Rsrc &Rs, const lds8_t *s,
                                             const QuadS<NARROW, WD> &Q, int hp[4], int cs[4])
 {
 #pragma unroll
     for (int j = 0; j < 4; ++j) hp[j] = Q.bias[j];
     if constexpr (QuadS<NARROW, WD>::kStream) {
-        // rows streamed in chunks of kChunk (pairs or neighbours)
-        constexpr int K = NARROW ? WD / 2 : WD;
-        constexpr int kChunk = NARROW ? 4 : 8;
+        // rows streamed in chunks of kChunk neighbours
+        constexpr int kChunk = 8;
         const int row = P.n_pad * 4;
 #pragma unroll
-        for (int k0 = 0; k0 < K; k0 += kChunk) {
+        for (int k0 = 0; k0 < WD; k0 += kChunk) {
             v4i a[kChunk], b[kChunk];
 #pragma unroll
             for (int c = 0; c < kChunk; ++c)
-                if (k0 + c < K) {
-                    a[c] = bload(Rs.a, Q.voff, (k0 + c) * row);
-                    b[c] = bload(Rs.b, Q.voff, (k0 + c) * row);
-                }
+                if (k0 + c < WD) a[c] = bload(Rs.a, Q.voff, (k0 + c) * row);
             if constexpr (NARROW) {
-                int8_t lo[kChunk][4], hi[kChunk][4];
+#pragma unroll
+                for (int c = 0; c < kChunk / 2; ++c)
+                    if (k0 + 2 * c < WD) b[c] = bload(Rs.b, Q.voff, ((k0 >> 1) + c) * row);
+            } else {
 #pragma unroll
                 for (int c = 0; c < kChunk; ++c)
+                    if (k0 + c < WD) b[c] = bload(Rs.b, Q.voff, (k0 + c) * row);
+            }
+            int8_t sv[kChunk][4];
+#pragma unroll
+            for (int c = 0; c < kChunk; ++c)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (k0 + c < WD) sv[c][j] = s[a[c][j]];
+            if constexpr (NARROW) {
+#pragma unroll
+                for (int c = 0; c < kChunk / 2; ++c)
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
-                        if (k0 + c < K) {
-                            const int iw = a[c][j];
-                            lo[c][j] = s[iw & 0xffff];
-                            hi[c][j] = s[(unsigned)iw >> 16];
-                        }
-#pragma unroll
-                for (int c = 0; c < kChunk; ++c)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (k0 + c < K) {
-                            const int jw = b[c][j];
-                            v2s sv, jv;
-                            sv.x = lo[c][j];
-                            sv.y = hi[c][j];
-                            jv.x = (short)(jw & 0xffff);
-                            jv.y = (short)((unsigned)jw >> 16);
-                            hp[j] = __builtin_amdgcn_sdot2(jv, sv, hp[j], false);
+                        if (k0 + 2 * c < WD) {
+                            v2s sp;
+                            sp.x = sv[2 * c][j];
+                            sp.y = sv[2 * c + 1][j];
+                            const int jw = b[c][j];  // a value: bit-casting a vector lane reads lane 0
+                            const v2s jv = __builtin_bit_cast(v2s, jw);
+                            hp[j] = __builtin_amdgcn_sdot2(jv, sp, hp[j], false);
                         }
             } else {
 #pragma unroll
                 for (int c = 0; c < kChunk; ++c)
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
-                        if (k0 + c < K) hp[j] += b[c][j] * (int)s[a[c][j]];
+                        if (k0 + c < WD) hp[j] += b[c][j] * (int)sv[c][j];
             }
         }
-        if constexpr (NARROW) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int c = Q.c0[j];
-                cs[j] = (int)s[c & 0xffff] + (int)s[(unsigned)c >> 16];
-            }
-        } else if (P.gen) {
-            quad_constraint_sum(P, Rs, s, Q.voff, cs);
-        } else {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) cs[j] = (int)s[Q.c0[j]] + (int)s[Q.c1[j]];
-        }
-        return;
-    } else if constexpr (NARROW) {
+    } else {
         // every LDS read of the quad is issued before the first product, so
         // their latencies overlap
-        int8_t lo[WD / 2][4], hi[WD / 2][4], ca[4], cb[4];
-#pragma unroll
-        for (int k2 = 0; k2 < WD / 2; ++k2)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int iw = Q.a[k2][j];  // plain int: bit-cast a value, not a vector lane
-                lo[k2][j] = s[iw & 0xffff];
-                hi[k2][j] = s[(unsigned)iw >> 16];
-            }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int c = Q.c0[j];
-            ca[j] = s[c & 0xffff];
-            cb[j] = s[(unsigned)c >> 16];
-        }
-#pragma unroll
-        for (int k2 = 0; k2 < WD / 2; ++k2)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int jw = Q.b[k2][j];
-                v2s sv, jv;
-                sv.x = lo[k2][j];
-                sv.y = hi[k2][j];
-                jv.x = (short)(jw & 0xffff);
-                jv.y = (short)((unsigned)jw >> 16);
-                hp[j] = __builtin_amdgcn_sdot2(jv, sv, hp[j], false);
-            }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) cs[j] = (int)ca[j] + (int)cb[j];
-    } else {
+        int8_t sv[WD][4];
 #pragma unroll
         for (int k = 0; k < WD; ++k)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) hp[j] += Q.b[k][j] * (int)s[Q.a[k][j]];
-        if (P.gen) {
-            quad_constraint_sum(P, Rs, s, Q.voff, cs);
+            for (int j = 0; j < 4; ++j) sv[k][j] = s[Q.a[k][j]];
+        if constexpr (NARROW) {
+#pragma unroll
+            for (int k2 = 0; k2 < WD / 2; ++k2)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    v2s sp;
+                    sp.x = sv[2 * k2][j];
+                    sp.y = sv[2 * k2 + 1][j];
+                    const int jw = Q.b[k2][j];  // a value: bit-casting a vector lane reads lane 0
+                    const v2s jv = __builtin_bit_cast(v2s, jw);
+                    hp[j] = __builtin_amdgcn_sdot2(jv, sp, hp[j], false);
+                }
         } else {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) cs[j] = (int)s[Q.c0[j]] + (int)s[Q.c1[j]];
+            for (int k = 0; k < WD; ++k)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) hp[j] += Q.b[k][j] * (int)sv[k][j];
         }
+    }
+    if (!NARROW && P.gen) {
+        quad_constraint_sum(P, Rs, s, Q.voff, cs);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cs[j] = (int)s[Q.c0[j]] + (int)s[Q.c1[j]];
     }
 }
 
@@ -375,13 +368,13 @@ __device__ __forceinline__ void quad_fields(const DevProblem &P, const Rsrc &Rs,
 // of g (24-bit multiplies are exact for NARROW instances, whose fields and
 // energy changes stay below 2^22).
 template <bool NARROW>
-__device__ __forceinline__ void quad_update(const DevProblem &P, int8_t *s, int q, const int hp[4], const int cs[4],
+__device__ __forceinline__ void quad_update(const DevProblem &P, lds8_t *s, int q, const int hp[4], const int cs[4],
                                             uint32_t live_bytes, uint32_t t, const SlotParams &sp,
                                             int &dfa, int &dga)
 {
     uint32_t u[4] = {(uint32_t)q, t, sp.pos, 0u};
     philox10(u[0], u[1], u[2], u[3], P.key0, P.key1);
-    uint32_t *wp = reinterpret_cast<uint32_t *>(s + q * 4);
+    lds32_t *wp = (lds32_t *)(s + q * 4);
     const uint32_t ow = *wp;
     int hh[4];
     uint32_t up = 0;  // byte j = 1 when spin j goes up
@@ -433,7 +426,7 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v)
 // 2 * (blockDim / 64) int64).  A lane walks its quads q0 + tid, q0 + tid +
 // blockDim, .. of every class.
 template <bool NARROW, int WD>
-__device__ __forceinline__ void sweep_round(const DevProblem &P, const Rsrc &Rs, int8_t *s,
+__device__ __forceinline__ void sweep_round(const DevProblem &P, const Rsrc &Rs, lds8_t *s,
                                             const SlotParams &sp, int64_t n_round, int64_t *red)
 {
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -489,13 +482,18 @@ __device__ __forceinline__ int64_t *lds_scratch(int8_t *lds, int stride)
 template <bool NARROW, int WD>
 __device__ __forceinline__ void round_sweep_body(const DevProblem &P, int slot, int8_t *lds)
 {
+    if (!replica_at_zero(lds)) {
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&P.hdr[kHdrError], kErrLdsBase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
     int64_t *red = lds_scratch(lds, P.stride);
     copy_bytes16(lds, P.states + (size_t)slot * P.stride, P.stride);
     const int64_t n_round = P.hdr[kHdrRounds] + 1;
     const SlotParams sp = slot_params(P, P.slot_pos[slot], P.beta, P.p_q);
     const Rsrc Rs = make_rsrc(P);
     __syncthreads();
-    sweep_round<NARROW, WD>(P, Rs, lds, sp, n_round, red);
+    sweep_round<NARROW, WD>(P, Rs, replica_lds(), sp, n_round, red);
     if (threadIdx.x == 0) {
         P.f[slot] += red[0];
         P.g[slot] += red[1];
@@ -659,6 +657,11 @@ template <bool NARROW, int WD>
 __global__ __launch_bounds__(kMaxBlock, 4) void k_persistent(DevProblem P, int64_t n_rounds)
 {
     extern __shared__ __align__(16) int8_t lds[];
+    if (!replica_at_zero(lds)) {
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&P.hdr[kHdrError], kErrLdsBase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
     int64_t *red = lds_scratch(lds, P.stride);
     // per-slot state kept by thread 0 in LDS: [0] f, [1] g, [2] best key
     int64_t *st = red + 2 + 2 * (kMaxBlock / 64);
@@ -684,7 +687,7 @@ __global__ __launch_bounds__(kMaxBlock, 4) void k_persistent(DevProblem P, int64
         const int64_t n = n0 + rr;
         const int pos = __builtin_amdgcn_readfirstlane(sh[0]);
         const SlotParams sp = slot_params(P, pos, lbeta, lpq);
-        sweep_round<NARROW, WD>(P, Rs, lds, sp, n, red);
+        sweep_round<NARROW, WD>(P, Rs, replica_lds(), sp, n, red);
         if (tid == 0) {
             const int64_t f = st[0] + red[0];
             const int64_t g = st[1] + red[1];
@@ -1086,14 +1089,12 @@ __global__ __launch_bounds__(kSmallBlock) void k_energy(DevProblem P)
         int ca, cb;
         if (P.narrow) {
             for (int k2 = 0; k2 < P.wd / 2; ++k2) {
-                const uint32_t ia = P.nbi[(size_t)k2 * P.n_pad + r];
                 const uint32_t jb = P.nbj[(size_t)k2 * P.n_pad + r];
-                hp += (int64_t)(int16_t)(jb & 0xffff) * s[ia & 0xffff];
-                hp += (int64_t)(int16_t)(jb >> 16) * s[ia >> 16];
+                hp += (int64_t)(int16_t)(jb & 0xffff) * s[P.nb_idx[(size_t)(2 * k2) * P.n_pad + r]];
+                hp += (int64_t)(int16_t)(jb >> 16) * s[P.nb_idx[(size_t)(2 * k2 + 1) * P.n_pad + r]];
             }
-            const uint32_t c = P.chp[r];
-            ca = c & 0xffff;
-            cb = c >> 16;
+            ca = P.ch_idx[r];
+            cb = P.ch_idx[P.n_pad + r];
         } else {
             for (int k = 0; k < P.wd; ++k)
                 hp += (int64_t)P.nb_J[(size_t)k * P.n_pad + r] * s[P.nb_idx[(size_t)k * P.n_pad + r]];
