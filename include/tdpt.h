@@ -281,6 +281,7 @@ int tdpt_batch_run(tdpt_batch *batch, int64_t n_rounds);
  * whole batch rounds; every member's state is restored afterwards.  The
  * choice holds until the next tdpt_batch_set_members. */
 typedef struct tdpt_batch_tune_report {
+    int32_t persistent;                /* 1 if the tuned batch runs the persistent driver */
     int32_t n_groups;                  /* layout groups (<= 32) */
     int32_t group_block[32];           /* chosen threads per workgroup */
     double group_ms_per_round[32];     /* batch round time with that choice */
@@ -290,14 +291,25 @@ typedef struct tdpt_batch_tune_report {
     double trial_ms_per_round[128];
 } tdpt_batch_tune_report;
 int tdpt_batch_autotune(tdpt_batch *batch, int32_t rounds_per_trial, tdpt_batch_tune_report *out);
+/* Driver of a batch.  By default (-1) tdpt_batch_run uses the persistent
+ * driver -- per layout group one cooperative launch that runs all the
+ * rounds, every member's replicas resident at once and exchanging through
+ * their own mailboxes -- whenever every member allows it (int8 layout,
+ * persistent driver not switched off) and each group's workgroups fit the
+ * GPU together; otherwise one sweep launch per group and one swap launch per
+ * round.  0 forces the per-round launches.  Results are the same either
+ * way.  tdpt_batch_query_driver reports the current choice (1 persistent). */
+int tdpt_batch_set_driver(tdpt_batch *batch, int32_t driver);
+int tdpt_batch_query_driver(tdpt_batch *batch, int32_t *driver);
 /* Replay rounds from a HIP graph: with rounds_per_graph = k > 0, the launches
  * of k rounds (every group's sweep, the swap step) are captured once into a
  * graph -- kernel launches only, on a private non-blocking stream -- and
  * tdpt_batch_run enqueues floor(n / k) replays of it on the batch's stream,
  * then the remaining rounds directly.  0 (the default) launches every round
  * directly.  The graph is rebuilt after tdpt_batch_set_members or
- * tdpt_batch_autotune; results are the same either way. */
-int tdpt_batch_set_graph(tdpt_batch *batch, int32_t rounds_per_graph);
+ * tdpt_batch_autotune; results are the same either way.  Graphs apply to the
+ * per-round driver; the persistent driver needs one launch per group anyway. */
+int tdpt_batch_set_graph(tdpt_batch *batch, int32_t rounds_per_graph);  /* per-round driver only */
 void tdpt_batch_destroy(tdpt_batch *batch);
 
 /* Thread-local message of the last failed call ("" if none). */

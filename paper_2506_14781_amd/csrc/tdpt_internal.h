@@ -119,6 +119,16 @@ hipError_t launch_finalize(const DevProblem &p, int64_t n_rounds, hipStream_t s)
 hipError_t launch_batch_sweep(const DevProblem &p, const DevProblem *table, const int *first_block,
                               int count, int blocks, int block, size_t max_stride, hipStream_t s);
 hipError_t launch_batch_swap(const DevProblem *table, int count, hipStream_t s);
+// Batched persistent driver over one layout group of count members whose
+// block ranges (prefix sums in first_block) cover `blocks` workgroups; lds is
+// the group's largest persistent_lds_bytes.  Cooperative: every workgroup
+// must be resident at once (batch_persistent_max_blocks).
+size_t persistent_lds_bytes(int stride, int I, int J);
+hipError_t batch_persistent_max_blocks(const DevProblem &p, int block, size_t lds, int *max_blocks);
+hipError_t launch_batch_persistent(const DevProblem &p, const DevProblem *table, const int *first_block, int count,
+                                   int blocks, int block, size_t lds, int64_t n_rounds, hipStream_t s);
+hipError_t launch_batch_scratch_reset(const DevProblem *table, int count, hipStream_t s);
+hipError_t launch_batch_finalize(const DevProblem *table, int count, int64_t n_rounds, hipStream_t s);
 // Bit-packed layout: one round of every slot (ceil(R / kBitSlots) blocks).
 hipError_t launch_sweep_bits(const DevProblem &p, hipStream_t s);
 hipError_t launch_batch_sweep_bits(const DevProblem &p, const DevProblem *table, const int *first_block,

@@ -654,9 +654,8 @@ __device__ __forceinline__ bool mb_wait(const uint64_t *m, uint64_t tag, int64_t
 // now sits bottom-right, record it.  Best states are kept per slot and
 // merged by k_finalize.
 template <bool NARROW, int WD>
-__global__ __launch_bounds__(kMaxBlock, 4) void k_persistent(DevProblem P, int64_t n_rounds)
+__device__ __forceinline__ void persistent_body(const DevProblem &P, int slot, int64_t n_rounds, int8_t *lds)
 {
-    extern __shared__ __align__(16) int8_t lds[];
     if (!replica_at_zero(lds)) {
         if (threadIdx.x == 0)
             __hip_atomic_store(&P.hdr[kHdrError], kErrLdsBase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -669,7 +668,6 @@ __global__ __launch_bounds__(kMaxBlock, 4) void k_persistent(DevProblem P, int64
     // copies of the beta and penalty ladders, read every round
     double *lbeta = reinterpret_cast<double *>(sh + 4);
     int32_t *lpq = reinterpret_cast<int32_t *>(lbeta + P.I);
-    const int slot = blockIdx.x;
     const int tid = threadIdx.x;
     for (int i = tid; i < P.I; i += blockDim.x) lbeta[i] = P.beta[i];
     for (int j = tid; j < P.J; j += blockDim.x) lpq[j] = P.p_q[j];
@@ -766,17 +764,59 @@ __global__ __launch_bounds__(kMaxBlock, 4) void k_persistent(DevProblem P, int64
     }
 }
 
-// Before a persistent launch: clear the per-slot best keys and the hit word.
-__global__ void k_scratch_reset(DevProblem P)
+template <bool NARROW, int WD>
+__global__ __launch_bounds__(kMaxBlock, 4) void k_persistent(DevProblem P, int64_t n_rounds)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    extern __shared__ __align__(16) int8_t lds[];
+    persistent_body<NARROW, WD>(P, blockIdx.x, n_rounds, lds);
+}
+
+// Index of the table member whose block range holds block b (first_block is
+// the prefix sum of the members' block counts).
+__device__ __forceinline__ int member_of(const int *__restrict__ first_block, int count, int b)
+{
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first_block[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Persistent driver over a batch: one cooperative launch runs n_rounds
+// rounds of every member of a layout group, block b serving slot
+// b - first_block[m] of member m.  Each member's slots exchange through that
+// member's own mailboxes, so members never wait for one another.
+template <bool NARROW, int WD>
+__global__ __launch_bounds__(kMaxBlock, 4) void k_batch_persistent(const DevProblem *__restrict__ table,
+                                                                 const int *__restrict__ first_block, int count,
+                                                                 int64_t n_rounds)
+{
+    extern __shared__ __align__(16) int8_t lds[];
+    const int m = member_of(first_block, count, blockIdx.x);
+    persistent_body<NARROW, WD>(table[m], blockIdx.x - first_block[m], n_rounds, lds);
+}
+
+// Before a persistent launch: clear the per-slot best keys and the hit word.
+__device__ __forceinline__ void scratch_reset_body(const DevProblem &P, int i)
+{
     if (i < P.R) P.slot_key[i] = INT64_MAX;
     if (i == 0) P.hit_min[0] = INT64_MAX;
 }
 
+__global__ void k_scratch_reset(DevProblem P) { scratch_reset_body(P, blockIdx.x * blockDim.x + threadIdx.x); }
+
+// The same for every member of a batch (one workgroup per member).
+__global__ __launch_bounds__(kSmallBlock) void k_batch_scratch_reset(const DevProblem *__restrict__ table)
+{
+    const DevProblem &P = table[blockIdx.x];
+    for (int i = threadIdx.x; i < P.R; i += blockDim.x) scratch_reset_body(P, i);
+}
+
 // After a persistent launch: merge the per-slot bests and the first hit into
 // the problem's tracking and advance its round count (one workgroup).
-__global__ __launch_bounds__(kSmallBlock) void k_finalize(DevProblem P, int64_t n_rounds)
+__device__ __forceinline__ void finalize_body(const DevProblem &P, int64_t n_rounds)
 {
     __shared__ int64_t bk[kSmallBlock];
     __shared__ int bs[kSmallBlock];
@@ -814,6 +854,14 @@ __global__ __launch_bounds__(kSmallBlock) void k_finalize(DevProblem P, int64_t 
     }
     __syncthreads();
     if (take >= 0) copy_bytes16(P.best_state, P.slot_best + (size_t)take * P.stride, P.stride);
+}
+
+__global__ __launch_bounds__(kSmallBlock) void k_finalize(DevProblem P, int64_t n_rounds) { finalize_body(P, n_rounds); }
+
+// The same for every member of a batch (one workgroup per member).
+__global__ __launch_bounds__(kSmallBlock) void k_batch_finalize(const DevProblem *__restrict__ table, int64_t n_rounds)
+{
+    finalize_body(table[blockIdx.x], n_rounds);
 }
 
 // ------------------------------------------------------ bit-packed layout
@@ -1337,6 +1385,66 @@ hipError_t launch_scratch_reset(const DevProblem &p, hipStream_t s)
 hipError_t launch_finalize(const DevProblem &p, int64_t n_rounds, hipStream_t s)
 {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kSmallBlock), 0, s, p, n_rounds);
+    return hipGetLastError();
+}
+
+size_t persistent_lds_bytes(int stride, int I, int J)
+{
+    DevProblem q{};
+    q.stride = stride;
+    q.I = I;
+    q.J = J;
+    return persistent_lds(q);
+}
+
+template <bool NARROW, int WD>
+static hipError_t batch_persistent_t(const DevProblem &p, const DevProblem *table, const int *first_block,
+                                     int count, int blocks, int block, size_t lds, int64_t n_rounds, hipStream_t s,
+                                     int *max_blocks)
+{
+    (void)p;
+    auto kern = k_batch_persistent<NARROW, WD>;
+    if (max_blocks) {
+        int dev = 0, lds_max = 0, per_cu = 0, cus = 0;
+        hipError_t q = hipGetDevice(&dev);
+        if (q == hipSuccess) q = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (q != hipSuccess) return q;
+        if (lds > (size_t)lds_max) {
+            *max_blocks = 0;
+            return hipSuccess;
+        }
+        q = allow_lds(kern, lds);
+        if (q == hipSuccess) q = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds);
+        if (q == hipSuccess) q = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        *max_blocks = per_cu * cus;
+        return q;
+    }
+    hipError_t e = allow_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    void *args[] = {&table, &first_block, &count, &n_rounds};
+    return hipLaunchCooperativeKernel((const void *)kern, dim3(blocks), dim3(block), args, lds, s);
+}
+
+hipError_t batch_persistent_max_blocks(const DevProblem &p, int block, size_t lds, int *max_blocks)
+{
+    TDPT_DISPATCH(batch_persistent_t, p, nullptr, nullptr, 0, 0, block, lds, 0, nullptr, max_blocks)
+}
+
+hipError_t launch_batch_persistent(const DevProblem &p, const DevProblem *table, const int *first_block, int count,
+                                   int blocks, int block, size_t lds, int64_t n_rounds, hipStream_t s)
+{
+    TDPT_DISPATCH(batch_persistent_t, p, table, first_block, count, blocks, block, lds, n_rounds, s, nullptr)
+}
+
+hipError_t launch_batch_scratch_reset(const DevProblem *table, int count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_scratch_reset, dim3(count), dim3(kSmallBlock), 0, s, table);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_finalize(const DevProblem *table, int count, int64_t n_rounds, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_finalize, dim3(count), dim3(kSmallBlock), 0, s, table, n_rounds);
     return hipGetLastError();
 }
 

@@ -98,6 +98,11 @@ struct tdpt_problem {
     int32_t min_block = 64;      // smallest sweep workgroup the per-phase bounds allow
     int32_t max_class_quads = 0;
     int64_t rounds_host = 0;  // rounds done, as far as the host has enqueued them
+    // rounds_host when the partner mailboxes were last valid (after a
+    // persistent run, or cleared); rounds run since by per-round launches
+    // leave them stale, and a stale entry 2^15 rounds old would carry a
+    // matching round tag, so they are cleared before the next persistent run
+    int64_t mbox_round = 0;
     // optional sweep-kernel timing (HIP events on the problem's stream)
     int32_t time_every = 0;
     int64_t sweep_launches = 0;
@@ -880,6 +885,8 @@ int tdpt_problem_run(tdpt_problem *p, int64_t n_rounds)
         return fail(TDPT_E_RANGE, "a problem runs at most 2^32 sweeps");
     if (n_rounds == 0) return TDPT_OK;
     if (p->persistent) {
+        if (p->mbox_round != p->rounds_host)
+            HIP_TRY(hipMemsetAsync(p->ws + p->mbox_off, 0, p->mbox_bytes, p->stream), "clear mailboxes");
         HIP_TRY(tdpt::launch_scratch_reset(p->dp, p->stream), "launch scratch reset");
         std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
         bool timed;
@@ -894,6 +901,7 @@ int tdpt_problem_run(tdpt_problem *p, int64_t n_rounds)
         ++p->sweep_launches;
         HIP_TRY(tdpt::launch_finalize(p->dp, n_rounds, p->stream), "launch finalize");
         p->rounds_host += n_rounds;
+        p->mbox_round = p->rounds_host;
         return TDPT_OK;
     }
     for (int64_t r = 0; r < n_rounds; ++r) {
@@ -1162,6 +1170,7 @@ int tdpt_problem_load(tdpt_problem *p, const void *host, size_t bytes)
     int64_t rounds = 0;
     memcpy(&rounds, (const uint8_t *)host + 16 + sizeof(int64_t) * tdpt::kHdrRounds, sizeof(rounds));
     p->rounds_host = rounds;
+    p->mbox_round = rounds;
     return TDPT_OK;
 }
 
@@ -1181,6 +1190,7 @@ struct tdpt_batch {
         int max_words;
         int block;      // threads per sweep workgroup of this group
         int min_block;  // smallest the members' per-phase bounds allow
+        size_t plds;    // LDS of a persistent workgroup (largest member)
     };
     std::vector<Group> groups;
     hipEvent_t done = nullptr;
@@ -1188,6 +1198,11 @@ struct tdpt_batch {
     // captured on cap_stream and replayed on stream; rebuilt after any change
     // of members or launch shapes.
     int32_t graph_rounds = 0;
+    // persistent driver: one cooperative launch per group runs many rounds
+    // (every member's workgroups resident at once); else one launch pair per
+    // round.  driver_mode -1 picks the persistent driver when it fits.
+    int32_t driver_mode = -1;
+    bool persistent = false;
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph = nullptr;
     void drop_graph()
@@ -1204,6 +1219,45 @@ struct tdpt_batch {
 };
 
 static size_t batch_table_bytes(int32_t cap) { return align_up((size_t)cap * sizeof(tdpt::DevProblem), 256); }
+
+// Whether the persistent driver runs this batch: every member allows it, no
+// group is bit-packed, and each group's workgroups fit the GPU at once.
+static int batch_decide_mode(tdpt_batch *b)
+{
+    b->persistent = false;
+    if (b->members.empty() || b->driver_mode == 0) return TDPT_OK;
+    for (auto *p : b->members)
+        if (!p->persistent_ok) return TDPT_OK;
+    for (auto &g : b->groups) {
+        const tdpt::DevProblem &d0 = b->members[g.first_member]->dp;
+        if (d0.bits || g.block > tdpt::kMaxBlock / 2 || g.block < g.min_block) return TDPT_OK;
+        int max_blocks = 0;
+        HIP_TRY(tdpt::batch_persistent_max_blocks(d0, g.block, g.plds, &max_blocks), "occupancy query");
+        if (max_blocks < g.blocks) return TDPT_OK;
+    }
+    b->persistent = true;
+    return TDPT_OK;
+}
+
+// n_rounds rounds of every member through the persistent driver.
+static int enqueue_batch_persistent(tdpt_batch *b, int64_t n_rounds)
+{
+    const tdpt::DevProblem *table = (const tdpt::DevProblem *)b->ws;
+    const int *prefix = (const int *)(b->ws + batch_table_bytes(b->cap));
+    for (auto *p : b->members)
+        if (p->mbox_round != p->rounds_host)
+            HIP_TRY(hipMemsetAsync(p->ws + p->mbox_off, 0, p->mbox_bytes, b->stream), "clear mailboxes");
+    for (const auto &g : b->groups) {
+        const tdpt::DevProblem &d0 = b->members[g.first_member]->dp;
+        hipError_t e = tdpt::launch_batch_scratch_reset(table + g.first_member, g.count, b->stream);
+        if (e == hipSuccess)
+            e = tdpt::launch_batch_persistent(d0, table + g.first_member, prefix + g.prefix_off, g.count, g.blocks,
+                                              g.block, g.plds, n_rounds, b->stream);
+        if (e == hipSuccess) e = tdpt::launch_batch_finalize(table + g.first_member, g.count, n_rounds, b->stream);
+        if (e != hipSuccess) return hip_fail(e, "launch batch persistent");
+    }
+    return TDPT_OK;
+}
 
 // One round of every member: the sweep launch of each layout group, then the
 // swap-and-track launch.
@@ -1316,7 +1370,7 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
         const bool start = b->groups.empty() || m[i]->dp.bits != m[i - 1]->dp.bits ||
                            m[i]->dp.narrow != m[i - 1]->dp.narrow || m[i]->dp.wd != m[i - 1]->dp.wd;
         if (start) {
-            tdpt_batch::Group g{(int)i, 0, 0, (int)prefix.size(), 0, 0, 0, 64};
+            tdpt_batch::Group g{(int)i, 0, 0, (int)prefix.size(), 0, 0, 0, 64, 0};
             b->groups.push_back(g);
         }
         auto &g = b->groups.back();
@@ -1326,6 +1380,7 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
         g.count += 1;
         g.max_stride = std::max(g.max_stride, (size_t)m[i]->dp.stride);
         g.max_words = std::max(g.max_words, m[i]->dp.n_words);
+        g.plds = std::max(g.plds, tdpt::persistent_lds_bytes(m[i]->dp.stride, m[i]->I, m[i]->J));
     }
     for (auto &g : b->groups) {
         const int cap = b->members[g.first_member]->dp.bits ? tdpt::kBitsBlock : tdpt::kMaxBlock;
@@ -1336,6 +1391,22 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
                                       "the batched sweep allows");
         }
         g.block = std::min(std::max(b->block, g.min_block), cap);
+    }
+    // the persistent driver when every group fits at once (with the members'
+    // own workgroup sizes), else per-round launches with the batch default
+    {
+        std::vector<int> per_round_blocks;
+        for (auto &g : b->groups) {
+            per_round_blocks.push_back(g.block);
+            int want = g.min_block;
+            for (int k = g.first_member; k < g.first_member + g.count; ++k)
+                want = std::max(want, b->members[k]->dp.block);
+            g.block = std::min(want, tdpt::kMaxBlock / 2);
+        }
+        int rc = batch_decide_mode(b);
+        if (rc) return rc;
+        if (!b->persistent)
+            for (size_t gi = 0; gi < b->groups.size(); ++gi) b->groups[gi].block = per_round_blocks[gi];
     }
     if (!m.empty()) {
         HIP_TRY(hipMemcpyAsync(b->ws, table.data(), table.size() * sizeof(tdpt::DevProblem),
@@ -1356,7 +1427,12 @@ int tdpt_batch_run(tdpt_batch *b, int64_t n_rounds)
         if ((p->rounds_host + n_rounds) * (int64_t)p->mcs > ((int64_t)1 << 32))
             return fail(TDPT_E_RANGE, "a problem runs at most 2^32 sweeps");
     int64_t r = 0;
-    if (b->graph_rounds > 0 && n_rounds >= b->graph_rounds) {
+    if (b->persistent) {
+        int rc = enqueue_batch_persistent(b, n_rounds);
+        if (rc) return rc;
+        r = n_rounds;
+    }
+    if (r < n_rounds && b->graph_rounds > 0 && n_rounds >= b->graph_rounds) {
         if (!b->graph) {
             int rc = capture_batch_graph(b);
             if (rc) return rc;
@@ -1372,6 +1448,7 @@ int tdpt_batch_run(tdpt_batch *b, int64_t n_rounds)
     for (auto *p : b->members) {
         HIP_TRY(hipStreamWaitEvent(p->stream, b->done, 0), "hipStreamWaitEvent");
         p->rounds_host += n_rounds;
+        if (b->persistent) p->mbox_round = p->rounds_host;
     }
     return TDPT_OK;
 }
@@ -1415,6 +1492,8 @@ int tdpt_batch_autotune(tdpt_batch *b, int32_t rounds_per_trial, tdpt_batch_tune
         for (int sz : sizes) {
             if (sz < g.min_block || sz > cap || out->n_trials >= 128) continue;
             g.block = sz;
+            rc = batch_decide_mode(b);
+            if (rc) break;
             rc = tdpt_batch_run(b, 1);  // warm-up
             double ms = 0.0;
             if (rc == TDPT_OK)
@@ -1434,9 +1513,27 @@ int tdpt_batch_autotune(tdpt_batch *b, int32_t rounds_per_trial, tdpt_batch_tune
         out->group_block[gi] = best_block;
         out->group_ms_per_round[gi] = best;
     }
+    if (rc == TDPT_OK) rc = batch_decide_mode(b);
+    out->persistent = b->persistent ? 1 : 0;
     b->graph_rounds = graph_rounds;
     const int rc2 = restore();
     return rc ? rc : rc2;
+}
+
+int tdpt_batch_set_driver(tdpt_batch *b, int32_t driver)
+{
+    if (!b) return fail(TDPT_E_INVALID, "batch is NULL");
+    if (driver != -1 && driver != 0) return fail(TDPT_E_INVALID, "driver must be -1 (automatic) or 0 (per round)");
+    HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    b->driver_mode = driver;
+    return batch_decide_mode(b);
+}
+
+int tdpt_batch_query_driver(tdpt_batch *b, int32_t *driver)
+{
+    if (!b || !driver) return fail(TDPT_E_INVALID, "NULL argument");
+    *driver = b->persistent ? 1 : 0;
+    return TDPT_OK;
 }
 
 int tdpt_batch_set_graph(tdpt_batch *b, int32_t rounds_per_graph)

@@ -28,7 +28,7 @@ EXPORTED = [
     "tdpt_problem_set_timing", "tdpt_problem_read_timing",
     "tdpt_batch_workspace_bytes", "tdpt_batch_create", "tdpt_batch_set_members",
     "tdpt_batch_run", "tdpt_batch_destroy", "tdpt_problem_autotune", "tdpt_batch_autotune",
-    "tdpt_batch_set_graph",
+    "tdpt_batch_set_graph", "tdpt_batch_set_driver", "tdpt_batch_query_driver",
 ]
 
 
@@ -63,7 +63,7 @@ class _TuneReport(ctypes.Structure):
 
 
 class _BatchTuneReport(ctypes.Structure):
-    _fields_ = [("n_groups", ctypes.c_int32), ("group_block", ctypes.c_int32 * 32),
+    _fields_ = [("persistent", ctypes.c_int32), ("n_groups", ctypes.c_int32), ("group_block", ctypes.c_int32 * 32),
                 ("group_ms_per_round", ctypes.c_double * 32), ("n_trials", ctypes.c_int32),
                 ("trial_group", ctypes.c_int32 * 128), ("trial_block", ctypes.c_int32 * 128),
                 ("trial_ms_per_round", ctypes.c_double * 128)]
@@ -112,6 +112,8 @@ def load_library():
         "tdpt_problem_autotune": [P, I32, P],
         "tdpt_batch_autotune": [P, I32, P],
         "tdpt_batch_set_graph": [P, I32],
+        "tdpt_batch_set_driver": [P, I32],
+        "tdpt_batch_query_driver": [P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -369,6 +371,16 @@ class Batch:
     def run(self, n_rounds: int):
         _check(_lib.tdpt_batch_run(self._h, int(n_rounds)))
 
+    def set_driver(self, driver: int):
+        """-1: persistent driver when it fits (default); 0: per-round launches."""
+        _check(_lib.tdpt_batch_set_driver(self._h, int(driver)))
+
+    def driver(self) -> int:
+        """1 if runs use the persistent driver, else 0."""
+        d = ctypes.c_int32()
+        _check(_lib.tdpt_batch_query_driver(self._h, ctypes.byref(d)))
+        return d.value
+
     def set_graph(self, rounds_per_graph: int):
         """Replay runs from a HIP graph of this many rounds (0: direct launches)."""
         _check(_lib.tdpt_batch_set_graph(self._h, int(rounds_per_graph)))
@@ -379,7 +391,8 @@ class Batch:
         r = _BatchTuneReport()
         _check(_lib.tdpt_batch_autotune(self._h, int(rounds_per_trial), ctypes.byref(r)))
         g, k = r.n_groups, r.n_trials
-        return {"group_block": list(r.group_block[:g]), "group_ms_per_round": list(r.group_ms_per_round[:g]),
+        return {"persistent": r.persistent, "group_block": list(r.group_block[:g]),
+                "group_ms_per_round": list(r.group_ms_per_round[:g]),
                 "trials": [(r.trial_group[i], r.trial_block[i], r.trial_ms_per_round[i]) for i in range(k)]}
 
     def close(self):

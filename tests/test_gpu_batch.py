@@ -187,8 +187,10 @@ def test_graph_replays_equal_direct_launches(T):
     pa, pb = make(), make()
     A, B = T.Batch(8), T.Batch(8)
     A.set_members(pa)
+    A.set_driver(0)  # graphs replay the per-round launches
     A.set_graph(4)
     B.set_members(pb)
+    B.set_driver(0)
     total = 0
     for k, n in enumerate([4, 9, 4, 8, 3]):
         _say(f"[batch] graph replay step {k}: {n} rounds")
@@ -209,3 +211,48 @@ def test_graph_replays_equal_direct_launches(T):
     assert np.array_equal(pa[1].states(), o["states"])
     f, g = pa[1].energies()
     assert np.array_equal(f, o["f"]) and np.array_equal(g, o["g"])
+
+
+def test_persistent_batch_driver(T):
+    """Small problems that fit the GPU together run as one cooperative launch
+    per layout group: equal to each problem alone (and to the oracle), also
+    when the batch switches to per-round launches and back, and after a
+    membership change."""
+    w = wishart_small()
+    specs = [("wishart-N12", w.instance, w.beta, w.p_q, 5, 11)]
+    for N, seed in [(64, 3), (100, 5)]:
+        m = batched_member(N, 0.8, seed)
+        specs.append((m.name, m.instance, m.beta[:8], m.p_q[:4], 3, seed))
+    from synth.constrained import planted_coloring
+    specs.append(("coloring", planted_coloring(60, 3, degree=4, seed=2).instance, np.geomspace(0.3, 3, 4),
+                  np.array([0, 4096], np.int32), 2, 4))
+    rounds = 30
+    alone, probs = [], []
+    for name, inst, beta, p_q, mcs, seed in specs:
+        cfg = T.RunConfig(beta, p_q, mcs_per_swap=mcs, seed=seed, trace_cap=rounds)
+        P = T.Problem(T.Instance.from_synth(inst), cfg)
+        P.run(rounds)
+        alone.append(_outputs(P))
+        probs.append(T.Problem(T.Instance.from_synth(inst), cfg))
+    B = T.Batch(8)
+    B.set_members(probs)
+    assert B.driver() == 1
+    _say("[batch] persistent driver: 12 rounds")
+    B.run(12)
+    B.set_driver(0)
+    assert B.driver() == 0
+    B.run(5)
+    B.set_driver(-1)
+    assert B.driver() == 1
+    B.set_members(probs[1:])
+    B.run(3)
+    B.set_members(probs)
+    B.run(10)
+    B.set_members([probs[0]])
+    B.run(3)
+    for (name, *_), a, P in zip(specs, alone, probs):
+        _say(f"[batch] persistent compare {name}")
+        _same(a, _outputs(P))
+    name, inst, beta, p_q, mcs, seed = specs[3]
+    o = O.run(inst, beta, p_q, mcs_per_swap=mcs, n_rounds=rounds, seed=seed, trace=True)
+    assert np.array_equal(probs[3].states(), o["states"])
