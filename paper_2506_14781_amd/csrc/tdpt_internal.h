@@ -33,11 +33,11 @@ constexpr int64_t kKeyOffset = (int64_t)1 << 30;
 // cls_live[c]) followed by dead padding up to cls_start[c+1] (a multiple of
 // 4).  Index n_pad is a spin that is always 0; missing neighbours point there.
 //
-// Neighbour indices (both byte layouts): nb_idx [wd][n_pad] int32, copy
-// neighbours ch_idx [2][n_pad] int32 (an index is the neighbour's LDS byte
-// address in a sweep workgroup).  Couplings: narrow (couplings in int16,
-// fields < 2^22, even wd) nbj [wd/2][n_pad], the couplings of neighbours 2k
-// and 2k+1 packed as an int16 pair; wide nb_J [wd][n_pad] int32.
+// Narrow structure (indices < 2^16, couplings in int16, fields < 2^22):
+//   nbi[k2][n_pad]  neighbour indices 2*k2 and 2*k2+1 packed as 16+16 bits
+//   nbj[k2][n_pad]  their couplings packed as int16 pairs
+//   chp[n_pad]      the two copy neighbours packed as 16+16 bits
+// Wide structure: nb_idx / nb_J [wd][n_pad] int32, ch_idx [2][n_pad] int32.
 // Bit-packed layout (replicas too large for an int8 copy in LDS): spins are
 // bits (1 = +1) in LDS, kBitSlots replicas interleaved by 32-bit word (word w
 // of replica r at byte 16 w + 4 r); each colour class starts on a 32-bit
@@ -62,10 +62,12 @@ struct DevProblem {
     const int32_t *h0;     // bit-packed
     int32_t cls_start[kMaxColors + 1];
     int32_t cls_live[kMaxColors];
+    const uint32_t *nbi;   // narrow
     const uint32_t *nbj;   // narrow
-    const int32_t *nb_idx;
+    const uint32_t *chp;   // narrow
+    const int32_t *nb_idx; // wide
     const int32_t *nb_J;   // wide
-    const int32_t *ch_idx; // copy edges
+    const int32_t *ch_idx; // wide
     // General constraints (byte layout only): half the penalty field of spin
     // i is kh[i] + sum_k cn_w[k][i] s[cn_idx[k][i]] instead of the copy sum;
     // g = g0 - sum_i s_i (2 kh[i] + sum_k cn_w[k][i] s[cn_idx[k][i]]).

@@ -133,9 +133,10 @@ __device__ __forceinline__ Rsrc make_rsrc(const DevProblem &P)
         return r;
     }
     if (P.narrow) {
-        r.a = rsrc(P.nb_idx, P.wd * P.n_pad * 4);
-        r.b = rsrc(P.nbj, (P.wd / 2) * P.n_pad * 4);
-        r.ch = rsrc(P.ch_idx, P.n_pad * 8);
+        const int bytes = (P.wd / 2) * P.n_pad * 4;
+        r.a = rsrc(P.nbi, bytes);
+        r.b = rsrc(P.nbj, bytes);
+        r.ch = rsrc(P.chp, P.n_pad * 4);
     } else {
         const int bytes = P.wd * P.n_pad * 4;
         r.a = rsrc(P.nb_idx, bytes);
@@ -198,19 +199,16 @@ __device__ __forceinline__ SlotParams slot_params(const DevProblem &P, int pos, 
 }
 
 // Structure of one quad (4 consecutive colour-major spins): one 16-byte
-// load per structure row.  Neighbour rows hold 32-bit LDS byte addresses
-// (read without any address arithmetic); coupling rows hold int16 pairs
-// (narrow) or int32 (wide).  Up to 8 neighbours per spin every row is held
-// at once; wider rows are streamed in chunks by quad_fields (kStream), which
+// load per structure row.  Up to 8 neighbours per spin every row is held at
+// once; wider rows are streamed in chunks by quad_fields (kStream), which
 // keeps them out of spill territory.
 template <bool NARROW, int WD>
 struct QuadS {
     static constexpr bool kStream = WD > 8;
-    static constexpr int KA = kStream ? 1 : WD;                     // index rows
-    static constexpr int KB = kStream ? 1 : (NARROW ? WD / 2 : WD); // coupling rows
-    v4i a[KA];   // neighbour indices
-    v4i b[KB];   // narrow: coupling pairs (neighbours 2k, 2k+1); wide: couplings
-    v4i c0, c1;  // the two copy-neighbour rows
+    static constexpr int K = kStream ? 1 : (NARROW ? WD / 2 : WD);
+    v4i a[K];    // narrow: index pairs; wide: indices
+    v4i b[K];    // narrow: coupling pairs; wide: couplings
+    v4i c0, c1;  // narrow: copy pairs in c0; wide: two copy rows
     v4i bias;    // fields (zero when the instance has none)
     int voff;    // byte offset of the quad in a structure row
 };
@@ -223,11 +221,14 @@ __device__ __forceinline__ void load_quad(const DevProblem &P, const Rsrc &Rs, i
     Q.voff = voff;
     if constexpr (!QuadS<NARROW, WD>::kStream) {
 #pragma unroll
-        for (int k = 0; k < QuadS<NARROW, WD>::KA; ++k) Q.a[k] = bload(Rs.a, voff, k * row);
-#pragma unroll
-        for (int k = 0; k < QuadS<NARROW, WD>::KB; ++k) Q.b[k] = bload(Rs.b, voff, k * row);
+        for (int k = 0; k < QuadS<NARROW, WD>::K; ++k) {
+            Q.a[k] = bload(Rs.a, voff, k * row);
+            Q.b[k] = bload(Rs.b, voff, k * row);
+        }
     }
-    if (NARROW || !P.gen) {
+    if constexpr (NARROW) {
+        Q.c0 = bload(Rs.ch, voff, 0);
+    } else if (!P.gen) {
         Q.c0 = bload(Rs.ch, voff, 0);
         Q.c1 = bload(Rs.ch, voff, row);
     }
@@ -271,8 +272,9 @@ __device__ __forceinline__ void quad_constraint_sum(const DevProblem &P, const R
 
 // Local fields of the 4 spins of a quad from the LDS spins s: hp = problem
 // part (couplings and field), cs = half the penalty field (the sum of the
-// copy neighbours, or the general-constraint sum).  NARROW instances keep
-// every field below 2^22, so the 16-bit dot products are exact.
+// copy neighbours, or the general-constraint sum).  NARROW
+// instances keep every field below 2^22, so the 16-bit dot products are
+// exact.
 template <bool NARROW, int WD>
 __device__ __forceinline__ void quad_fields(const DevProblem &P, const Rsrc &Rs, const lds8_t *s,
                                             const QuadS<NARROW, WD> &Q, int hp[4], int cs[4])
@@ -280,83 +282,107 @@ __device__ __forceinline__ void quad_fields(const DevProblem &P, const Rsrc &Rs,
 #pragma unroll
     for (int j = 0; j < 4; ++j) hp[j] = Q.bias[j];
     if constexpr (QuadS<NARROW, WD>::kStream) {
-        // rows streamed in chunks of kChunk neighbours
-        constexpr int kChunk = 8;
+        // rows streamed in chunks of kChunk (pairs or neighbours)
+        constexpr int K = NARROW ? WD / 2 : WD;
+        constexpr int kChunk = NARROW ? 4 : 8;
         const int row = P.n_pad * 4;
 #pragma unroll
-        for (int k0 = 0; k0 < WD; k0 += kChunk) {
+        for (int k0 = 0; k0 < K; k0 += kChunk) {
             v4i a[kChunk], b[kChunk];
 #pragma unroll
             for (int c = 0; c < kChunk; ++c)
-                if (k0 + c < WD) a[c] = bload(Rs.a, Q.voff, (k0 + c) * row);
+                if (k0 + c < K) {
+                    a[c] = bload(Rs.a, Q.voff, (k0 + c) * row);
+                    b[c] = bload(Rs.b, Q.voff, (k0 + c) * row);
+                }
             if constexpr (NARROW) {
-#pragma unroll
-                for (int c = 0; c < kChunk / 2; ++c)
-                    if (k0 + 2 * c < WD) b[c] = bload(Rs.b, Q.voff, ((k0 >> 1) + c) * row);
-            } else {
+                int8_t lo[kChunk][4], hi[kChunk][4];
 #pragma unroll
                 for (int c = 0; c < kChunk; ++c)
-                    if (k0 + c < WD) b[c] = bload(Rs.b, Q.voff, (k0 + c) * row);
-            }
-            int8_t sv[kChunk][4];
-#pragma unroll
-            for (int c = 0; c < kChunk; ++c)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (k0 + c < WD) sv[c][j] = s[a[c][j]];
-            if constexpr (NARROW) {
-#pragma unroll
-                for (int c = 0; c < kChunk / 2; ++c)
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
-                        if (k0 + 2 * c < WD) {
-                            v2s sp;
-                            sp.x = sv[2 * c][j];
-                            sp.y = sv[2 * c + 1][j];
-                            const int jw = b[c][j];  // a value: bit-casting a vector lane reads lane 0
-                            const v2s jv = __builtin_bit_cast(v2s, jw);
-                            hp[j] = __builtin_amdgcn_sdot2(jv, sp, hp[j], false);
+                        if (k0 + c < K) {
+                            const int iw = a[c][j];
+                            lo[c][j] = s[iw & 0xffff];
+                            hi[c][j] = s[(unsigned)iw >> 16];
+                        }
+#pragma unroll
+                for (int c = 0; c < kChunk; ++c)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (k0 + c < K) {
+                            const int jw = b[c][j];
+                            v2s sv, jv;
+                            sv.x = lo[c][j];
+                            sv.y = hi[c][j];
+                            jv.x = (short)(jw & 0xffff);
+                            jv.y = (short)((unsigned)jw >> 16);
+                            hp[j] = __builtin_amdgcn_sdot2(jv, sv, hp[j], false);
                         }
             } else {
 #pragma unroll
                 for (int c = 0; c < kChunk; ++c)
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
-                        if (k0 + c < WD) hp[j] += b[c][j] * (int)sv[c][j];
+                        if (k0 + c < K) hp[j] += b[c][j] * (int)s[a[c][j]];
             }
         }
-    } else {
+        if constexpr (NARROW) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c = Q.c0[j];
+                cs[j] = (int)s[c & 0xffff] + (int)s[(unsigned)c >> 16];
+            }
+        } else if (P.gen) {
+            quad_constraint_sum(P, Rs, s, Q.voff, cs);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) cs[j] = (int)s[Q.c0[j]] + (int)s[Q.c1[j]];
+        }
+        return;
+    } else if constexpr (NARROW) {
         // every LDS read of the quad is issued before the first product, so
         // their latencies overlap
-        int8_t sv[WD][4];
+        int8_t lo[WD / 2][4], hi[WD / 2][4], ca[4], cb[4];
+#pragma unroll
+        for (int k2 = 0; k2 < WD / 2; ++k2)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int iw = Q.a[k2][j];  // plain int: bit-cast a value, not a vector lane
+                lo[k2][j] = s[iw & 0xffff];
+                hi[k2][j] = s[(unsigned)iw >> 16];
+            }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = Q.c0[j];
+            ca[j] = s[c & 0xffff];
+            cb[j] = s[(unsigned)c >> 16];
+        }
+#pragma unroll
+        for (int k2 = 0; k2 < WD / 2; ++k2)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int jw = Q.b[k2][j];
+                v2s sv, jv;
+                sv.x = lo[k2][j];
+                sv.y = hi[k2][j];
+                jv.x = (short)(jw & 0xffff);
+                jv.y = (short)((unsigned)jw >> 16);
+                hp[j] = __builtin_amdgcn_sdot2(jv, sv, hp[j], false);
+            }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cs[j] = (int)ca[j] + (int)cb[j];
+    } else {
 #pragma unroll
         for (int k = 0; k < WD; ++k)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) sv[k][j] = s[Q.a[k][j]];
-        if constexpr (NARROW) {
-#pragma unroll
-            for (int k2 = 0; k2 < WD / 2; ++k2)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    v2s sp;
-                    sp.x = sv[2 * k2][j];
-                    sp.y = sv[2 * k2 + 1][j];
-                    const int jw = Q.b[k2][j];  // a value: bit-casting a vector lane reads lane 0
-                    const v2s jv = __builtin_bit_cast(v2s, jw);
-                    hp[j] = __builtin_amdgcn_sdot2(jv, sp, hp[j], false);
-                }
+            for (int j = 0; j < 4; ++j) hp[j] += Q.b[k][j] * (int)s[Q.a[k][j]];
+        if (P.gen) {
+            quad_constraint_sum(P, Rs, s, Q.voff, cs);
         } else {
 #pragma unroll
-            for (int k = 0; k < WD; ++k)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) hp[j] += Q.b[k][j] * (int)sv[k][j];
+            for (int j = 0; j < 4; ++j) cs[j] = (int)s[Q.c0[j]] + (int)s[Q.c1[j]];
         }
-    }
-    if (!NARROW && P.gen) {
-        quad_constraint_sum(P, Rs, s, Q.voff, cs);
-    } else {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) cs[j] = (int)s[Q.c0[j]] + (int)s[Q.c1[j]];
     }
 }
 
@@ -1137,12 +1163,14 @@ __global__ __launch_bounds__(kSmallBlock) void k_energy(DevProblem P)
         int ca, cb;
         if (P.narrow) {
             for (int k2 = 0; k2 < P.wd / 2; ++k2) {
+                const uint32_t ia = P.nbi[(size_t)k2 * P.n_pad + r];
                 const uint32_t jb = P.nbj[(size_t)k2 * P.n_pad + r];
-                hp += (int64_t)(int16_t)(jb & 0xffff) * s[P.nb_idx[(size_t)(2 * k2) * P.n_pad + r]];
-                hp += (int64_t)(int16_t)(jb >> 16) * s[P.nb_idx[(size_t)(2 * k2 + 1) * P.n_pad + r]];
+                hp += (int64_t)(int16_t)(jb & 0xffff) * s[ia & 0xffff];
+                hp += (int64_t)(int16_t)(jb >> 16) * s[ia >> 16];
             }
-            ca = P.ch_idx[r];
-            cb = P.ch_idx[P.n_pad + r];
+            const uint32_t c = P.chp[r];
+            ca = c & 0xffff;
+            cb = c >> 16;
         } else {
             for (int k = 0; k < P.wd; ++k)
                 hp += (int64_t)P.nb_J[(size_t)k * P.n_pad + r] * s[P.nb_idx[(size_t)k * P.n_pad + r]];

@@ -122,7 +122,8 @@ namespace {
 struct Layout {
     size_t hdr, states, f, g, slot_pos, pos_slot, p_att, p_acc, b_att, b_acc, best, trace_f,
         trace_g, mut_end, mbox, slot_key, slot_best, hit_min, scratch_end;
-    size_t beta, p_q, nbj, nb_idx, nb_J, ch_idx, bias, orig, nb_pos, ch_pos, h0, cn_idx, cn_w, kh, total;
+    size_t beta, p_q, nbi, nbj, chp, nb_idx, nb_J, ch_idx, bias, orig, nb_pos, ch_pos, h0, cn_idx, cn_w, kh,
+        total;
     int32_t stride, wd;
 };
 
@@ -140,9 +141,9 @@ bool use_bits(const tdpt_instance *in)
     return align_up((size_t)in->n_pad + 1, 16) > kInt8StrideMax;
 }
 
-// The packed couplings (int16 pairs) and the 16/24-bit arithmetic of the
-// sweep need couplings that fit 16 bits and every local field, penalty term
-// and energy change below 2^22.
+// The packed structure (16-bit indices and coupling pairs) and the 16/24-bit
+// arithmetic of the sweep need indices and couplings that fit 16 bits and
+// every local field, penalty term and energy change below 2^22.
 bool use_narrow(const tdpt_instance *in, const tdpt_run_cfg *cfg)
 {
     const int64_t pmax = cfg->p_q[cfg->n_p - 1];
@@ -184,15 +185,16 @@ Layout make_layout(const tdpt_instance *in, int32_t I, int32_t J, int64_t trace_
     L.beta = take((size_t)I * 8);
     L.p_q = take((size_t)J * 4);
     if (narrow) {
-        L.nb_idx = take((size_t)L.wd * in->n_pad * 4);
-        L.nbj = take((size_t)(L.wd / 2) * in->n_pad * 4);
-        L.ch_idx = take((size_t)2 * in->n_pad * 4);
-        L.nb_J = 0;
+        const size_t rows = (size_t)(L.wd / 2) * in->n_pad * 4;
+        L.nbi = take(rows);
+        L.nbj = take(rows);
+        L.chp = take((size_t)in->n_pad * 4);
+        L.nb_idx = L.nb_J = L.ch_idx = 0;
     } else {
         const size_t ell = (size_t)L.wd * in->n_pad * 4;
         L.nb_idx = take(ell);
         L.nb_J = take(ell);
-        L.nbj = 0;
+        L.nbi = L.nbj = L.chp = 0;
         if (in->gen) {
             const size_t cell = (size_t)in->wcg * in->n_pad * 4;
             L.cn_idx = take(cell);
@@ -350,7 +352,7 @@ int lay_out(tdpt_instance *in, int32_t n, const int32_t *row_ptr, const int32_t 
     in->nb_idx.assign((size_t)wd * n_pad, n_pad);
     in->nb_J.assign((size_t)wd * n_pad, 0);
     in->bias.assign(n_pad, 0);
-    bool narrow = true;
+    bool narrow = (n_pad + 1 <= 65536);
     int64_t absf = 0;
     for (int32_t r = 0; r < n_pad; ++r) {
         const int32_t v = in->orig[r];
@@ -704,10 +706,12 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     d.h0 = bits ? (const int32_t *)(ws + L.h0) : nullptr;
     for (int c = 0; c <= in->n_colors; ++c) d.cls_start[c] = in->cls_start[c];
     for (int c = 0; c < in->n_colors; ++c) d.cls_live[c] = in->cls_live[c];
+    d.nbi = narrow ? (const uint32_t *)(ws + L.nbi) : nullptr;
     d.nbj = narrow ? (const uint32_t *)(ws + L.nbj) : nullptr;
-    d.nb_idx = (const int32_t *)(ws + L.nb_idx);
+    d.chp = narrow ? (const uint32_t *)(ws + L.chp) : nullptr;
+    d.nb_idx = narrow ? nullptr : (const int32_t *)(ws + L.nb_idx);
     d.nb_J = narrow ? nullptr : (const int32_t *)(ws + L.nb_J);
-    d.ch_idx = in->gen ? nullptr : (const int32_t *)(ws + L.ch_idx);
+    d.ch_idx = (narrow || in->gen) ? nullptr : (const int32_t *)(ws + L.ch_idx);
     d.gen = in->gen;
     d.wcg = in->wcg;
     d.cn_idx = in->gen ? (const int32_t *)(ws + L.cn_idx) : nullptr;
@@ -762,22 +766,24 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     UP(ws + L.beta, cfg->beta, (size_t)I * 8);
     UP(ws + L.p_q, cfg->p_q, (size_t)J * 4);
     if (narrow) {
-        // neighbour indices as int32 rows (padded to an even width), couplings
-        // of neighbours (2k, 2k+1) as int16 pairs
+        // neighbour pairs (2k, 2k+1): indices as 16+16 bits, couplings as int16 pairs
         const int32_t n_pad = in->n_pad, wd = in->wd, pairs = L.wd / 2;
         auto idx_at = [&](int k, int32_t r) { return k < wd ? in->nb_idx[(size_t)k * n_pad + r] : n_pad; };
         auto j_at = [&](int k, int32_t r) { return k < wd ? in->nb_J[(size_t)k * n_pad + r] : 0; };
-        std::vector<int32_t> A((size_t)L.wd * n_pad);
-        std::vector<uint32_t> B((size_t)pairs * n_pad);
-        for (int k = 0; k < L.wd; ++k)
-            for (int32_t r = 0; r < n_pad; ++r) A[(size_t)k * n_pad + r] = idx_at(k, r);
+        std::vector<uint32_t> A((size_t)pairs * n_pad), B((size_t)pairs * n_pad);
         for (int k2 = 0; k2 < pairs; ++k2)
-            for (int32_t r = 0; r < n_pad; ++r)
+            for (int32_t r = 0; r < n_pad; ++r) {
+                A[(size_t)k2 * n_pad + r] = ((uint32_t)idx_at(2 * k2, r) & 0xffffu) |
+                                            ((uint32_t)idx_at(2 * k2 + 1, r) << 16);
                 B[(size_t)k2 * n_pad + r] = ((uint32_t)j_at(2 * k2, r) & 0xffffu) |
                                             ((uint32_t)(j_at(2 * k2 + 1, r) & 0xffff) << 16);
-        UP(ws + L.nb_idx, A.data(), A.size() * 4);
+            }
+        UP(ws + L.nbi, A.data(), A.size() * 4);
         UP(ws + L.nbj, B.data(), B.size() * 4);
-        UP(ws + L.ch_idx, in->ch_idx.data(), in->ch_idx.size() * 4);
+        std::vector<uint32_t> ch((size_t)n_pad);
+        for (int32_t r = 0; r < n_pad; ++r)
+            ch[r] = ((uint32_t)in->ch_idx[r] & 0xffffu) | ((uint32_t)in->ch_idx[(size_t)n_pad + r] << 16);
+        UP(ws + L.chp, ch.data(), ch.size() * 4);
     } else {
         UP(ws + L.nb_idx, in->nb_idx.data(), in->nb_idx.size() * 4);
         UP(ws + L.nb_J, in->nb_J.data(), in->nb_J.size() * 4);
