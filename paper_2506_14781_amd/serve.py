@@ -97,8 +97,8 @@ def run_batched(requests, chunk: int, device="cuda"):
     active = list(requests)
     for req in active:
         req.start = 0.0
+    batch.set_members([r.problem for r in active])
     while active:
-        batch.set_members([r.problem for r in active])
         n = min(chunk, min(r.max_rounds - r.rounds_done for r in active))
         t0 = time.perf_counter()
         batch.run(n)
@@ -112,6 +112,8 @@ def run_batched(requests, chunk: int, device="cuda"):
                 r.end = t1 - base
             else:
                 still.append(r)
+        if len(still) != len(active) and still:
+            batch.set_members([r.problem for r in still])
         active = still
     total = time.perf_counter() - base
     batch.close()
