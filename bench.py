@@ -184,6 +184,44 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_tts(args):
+    """Sweeps and time to the planted ground state on the N=12 workload over
+    many run seeds (the same instance, --count seeds, the workload's 1e4
+    sweeps unless --cap-sweeps says otherwise), all runs in one batch and one
+    after another.  TTS99 follows the usual Ising-machine convention
+    t ln(0.01) / ln(1 - p) with p the hit fraction at the cap (it is not a
+    figure of the paper)."""
+    import copy
+    import math
+
+    import paper_2506_14781_amd as T
+    from paper_2506_14781_amd.serve import run_batched, run_plain, summarize
+    from synth.configs import wishart_small
+    members = [wishart_small(seed=k) for k in range(args.count)]
+    reqs_b = _requests(T, members, args.cap_sweeps, 0.0)
+    reqs_p = [copy.copy(r) for r in reqs_b]
+    print(f"[bench] tts: {len(members)} seeds of {members[0].name}, cap {args.cap_sweeps} sweeps",
+          file=sys.stderr, flush=True)
+    tb = run_batched(reqs_b, chunk=args.chunk)
+    sb = summarize(reqs_b, tb)
+    tp = run_plain(reqs_p, chunk=args.chunk)
+    sp = summarize(reqs_p, tp)
+    for a, b in zip(reqs_b, reqs_p):
+        assert a.hit_sweep == b.hit_sweep, "sweeps to hit differ between modes"
+    p = sb["hit_fraction"]
+    tts99 = None
+    if 0 < p < 1:
+        tts99 = args.cap_sweeps * math.log(0.01) / math.log(1.0 - p)
+    elif p == 1:
+        tts99 = sb["sweeps_to_hit_p99"]
+    out = {"metric": "time-to-planted-GS p50 (batched)", "value": sb["tts_p50_s"], "unit": "s",
+           "higher_is_better": False, "n_gpus": 1,
+           "data": "synthetic (seeded planted Wishart N=12, copy-chain sparsified)",
+           "config": {"workload": f"{members[0].name}, {len(members)} run seeds, cap {args.cap_sweeps} sweeps"},
+           "sweeps_tts99": tts99, "batched": sb, "plain": sp}
+    print(json.dumps(out), flush=True)
+
+
 def bench_serving(args):
     """Poisson arrivals of planted-Wishart solves (N ~ U{64..max_n}),
     continuous batching under an HBM budget, at each rate of --rates: the
@@ -403,8 +441,8 @@ def main():
     ap.add_argument("--sigma-min", type=float, default=0.5, help="Algorithm 2 energy spread threshold")
     ap.add_argument("--kl-rounds", type=int, default=2000, help="rounds of 500 sweeps (kl)")
     ap.add_argument("--kl-seeds", type=int, default=4, help="independent runs per setting (kl)")
-    ap.add_argument("--workload", choices=["n200", "n1000", "coloring", "batched", "serving", "jcolumn", "kl",
-                                           "copy"],
+    ap.add_argument("--workload", choices=["n200", "n1000", "coloring", "batched", "tts", "serving", "jcolumn",
+                                           "kl", "copy"],
                     default="n200",
                     help="copy: one plain 256 MiB device-to-device copy, the reference the HBM "
                          "traffic counters are scaled against")
@@ -450,6 +488,8 @@ def main():
         return bench_kl(args)
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "tts":
+        return bench_tts(args)
     if args.workload == "serving":
         return bench_serving(args)
     gen = args.workload == "coloring"
