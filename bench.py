@@ -13,6 +13,12 @@ n1000: planted Wishart N=1000 (alpha 0.6), degree 6 (250,000 physical
 spins), a 64 x 32 grid, 50 sweeps per swap round; one step is 4 rounds
 (200 sweeps), 5 steps by default (1000 sweeps, 5.1e11 spin updates).
 
+Other workloads (one JSON line each, not spin-update throughput): batched
+(64 planted Wishart instances, batched vs plain time to target), tts (the
+N=12 workload over many run seeds: time to the planted ground state), serving
+(Poisson arrivals, continuous batching), jcolumn (2D-PT vs J-column PT), kl
+(the Fig. 2 sampling experiment), copy (counter calibration).
+
 coloring: general constraints -- planted 4-colouring of a 4000-node graph
 (degree <= 6) in one-hot form (16,000 spins, 4000 one-hot terms), a 32 x 16
 grid, 50 sweeps per swap round; one step is 100 rounds, 20 steps by default.
