@@ -147,3 +147,22 @@ def test_autotuned_coloring_matches_oracle(T):
     P.run(30)
     o = O.run(pc.instance, beta, p_q, mcs_per_swap=5, n_rounds=30, seed=2, f_target=pc.f_target_q, trace=True)
     assert_same(o, P, "tuned coloring")
+
+
+def test_degenerate_constraints(T):
+    """No terms (g = 0: plain PT on every column, every P-swap accepted) and a
+    term without spins (g = d^2 everywhere: nothing is ever feasible), each
+    bit-exact against the oracle."""
+    from synth.constrained import with_terms
+    base = slack_knapsack(5, seed=2)
+    beta = np.array([0.1, 0.3])
+    p_q = np.array([512, 2048], np.int32)
+    free = with_terms(base, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32),
+                      np.zeros(0, np.int32))
+    o, P = both(T, free, beta, p_q, mcs=2, rounds=24, seed=3, label="no terms")
+    pa, pc, _, _ = P.counters()
+    assert np.all(o["g"] == 0) and np.array_equal(pa, pc) and pa.sum() > 0
+    const = with_terms(base, np.array([0, 0], np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32),
+                       np.array([3], np.int32))
+    o, P = both(T, const, beta, p_q, mcs=2, rounds=24, seed=3, label="constant term")
+    assert np.all(o["g"] == 9) and P.query()["best_f_q"] == 2**63 - 1
