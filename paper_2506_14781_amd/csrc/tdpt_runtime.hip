@@ -1211,6 +1211,11 @@ struct tdpt_batch {
     bool persistent = false;
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph = nullptr;
+    // per-round driver: the sweeps of different layout groups run side by
+    // side on auxiliary streams (fork and join through events each round)
+    static constexpr int kAux = 7;
+    hipStream_t aux[kAux] = {};
+    hipEvent_t fork = nullptr, join[kAux] = {};
     void drop_graph()
     {
         if (graph) (void)hipGraphExecDestroy(graph);
@@ -1220,6 +1225,11 @@ struct tdpt_batch {
     {
         drop_graph();
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        for (int k = 0; k < kAux; ++k) {
+            if (aux[k]) (void)hipStreamDestroy(aux[k]);
+            if (join[k]) (void)hipEventDestroy(join[k]);
+        }
+        if (fork) (void)hipEventDestroy(fork);
         if (done) (void)hipEventDestroy(done);
     }
 };
@@ -1267,17 +1277,45 @@ static int enqueue_batch_persistent(tdpt_batch *b, int64_t n_rounds)
 
 // One round of every member: the sweep launch of each layout group, then the
 // swap-and-track launch.
+// Auxiliary streams and events for the groups' side-by-side sweeps.
+static int batch_aux_init(tdpt_batch *b)
+{
+    const int n_aux = std::min((int)b->groups.size() - 1, tdpt_batch::kAux);
+    if (n_aux <= 0) return TDPT_OK;
+    if (!b->fork) HIP_TRY(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming), "hipEventCreate");
+    for (int k = 0; k < n_aux; ++k) {
+        if (!b->aux[k]) HIP_TRY(hipStreamCreateWithFlags(&b->aux[k], hipStreamNonBlocking), "hipStreamCreate");
+        if (!b->join[k]) HIP_TRY(hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming), "hipEventCreate");
+    }
+    return TDPT_OK;
+}
+
 static int enqueue_batch_round(tdpt_batch *b, hipStream_t s)
 {
     const tdpt::DevProblem *table = (const tdpt::DevProblem *)b->ws;
     const int *prefix = (const int *)(b->ws + batch_table_bytes(b->cap));
-    for (const auto &g : b->groups) {
+    const int n_groups = (int)b->groups.size();
+    const int n_aux = std::min(n_groups - 1, tdpt_batch::kAux);
+    if (n_aux > 0) {
+        int rc = batch_aux_init(b);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(b->fork, s), "hipEventRecord");
+        for (int k = 0; k < n_aux; ++k) HIP_TRY(hipStreamWaitEvent(b->aux[k], b->fork, 0), "hipStreamWaitEvent");
+    }
+    // group 0 on the batch's stream, group g > 0 on auxiliary stream (g-1) mod kAux
+    for (int gi = 0; gi < n_groups; ++gi) {
+        const auto &g = b->groups[gi];
+        hipStream_t gs = gi == 0 ? s : b->aux[(gi - 1) % tdpt_batch::kAux];
         const tdpt::DevProblem &d0 = b->members[g.first_member]->dp;
         hipError_t e = d0.bits ? tdpt::launch_batch_sweep_bits(d0, table + g.first_member, prefix + g.prefix_off,
-                                                               g.count, g.blocks, g.block, g.max_words, s)
+                                                               g.count, g.blocks, g.block, g.max_words, gs)
                                : tdpt::launch_batch_sweep(d0, table + g.first_member, prefix + g.prefix_off,
-                                                          g.count, g.blocks, g.block, g.max_stride, s);
+                                                          g.count, g.blocks, g.block, g.max_stride, gs);
         if (e != hipSuccess) return hip_fail(e, "launch batch sweep");
+    }
+    for (int k = 0; k < n_aux; ++k) {
+        HIP_TRY(hipEventRecord(b->join[k], b->aux[k]), "hipEventRecord");
+        HIP_TRY(hipStreamWaitEvent(s, b->join[k], 0), "hipStreamWaitEvent");
     }
     hipError_t e = tdpt::launch_batch_swap(table, (int)b->members.size(), s);
     if (e != hipSuccess) return hip_fail(e, "launch batch swap");
@@ -1289,6 +1327,10 @@ static int capture_batch_graph(tdpt_batch *b)
 {
     b->drop_graph();
     if (!b->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+    {
+        int rc = batch_aux_init(b);
+        if (rc) return rc;
+    }
     HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
     int rc = TDPT_OK;
     for (int32_t r = 0; r < b->graph_rounds && rc == TDPT_OK; ++r) rc = enqueue_batch_round(b, b->cap_stream);
@@ -1396,7 +1438,16 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
             return fail(TDPT_E_RANGE, "a member's per-phase energy bounds need a larger workgroup than "
                                       "the batched sweep allows");
         }
-        g.block = std::min(std::max(b->block, g.min_block), cap);
+        // per-round default: the batch's workgroup size for byte layouts; for
+        // bit-packed groups the members' own (their sweep wants every thread
+        // a compute unit can hold next to one 4-replica workgroup)
+        int def = b->block;
+        if (b->members[g.first_member]->dp.bits) {
+            def = 64;
+            for (int k = g.first_member; k < g.first_member + g.count; ++k)
+                def = std::max(def, b->members[k]->dp.block);
+        }
+        g.block = std::min(std::max(def, g.min_block), cap);
     }
     // the persistent driver when every group fits at once (with the members'
     // own workgroup sizes), else per-round launches with the batch default
