@@ -464,9 +464,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build runs the whole replica grid on a "
-              "single MI355X and has no multi-GPU path (see the sharding design notes).",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs each replica grid on a single "
+              "MI355X and has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
     big = args.workload == "n1000"
