@@ -118,6 +118,41 @@ def cpu_baseline(w, rounds: int, sub_grid: int = 0) -> dict:
             "seconds": round(dt, 3)}
 
 
+_ORACLE_CHILD = r"""
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+from oracle import oracle as O
+from synth import configs as C
+w = getattr(C, sys.argv[2])()
+rounds, sub = int(sys.argv[3]), int(sys.argv[4])
+beta, p_q = (w.beta[:sub], w.p_q[:sub]) if sub else (w.beta, w.p_q)
+t0 = time.perf_counter()
+O.run(w.instance, beta, p_q, mcs_per_swap=w.mcs_per_swap, n_rounds=rounds, seed=0)
+print(json.dumps({"seconds": time.perf_counter() - t0}))
+"""
+
+
+def cpu_baseline_all_cores(w, builder: str, rounds: int, sub_grid: int, procs: int) -> dict:
+    """The same oracle sample run by `procs` independent single-threaded
+    processes at once (child interpreters that never touch the GPU): the
+    aggregate rate of the host's cores.  Each child times its own run; the
+    aggregate is procs x updates over the longest of them."""
+    import subprocess
+    kids = [subprocess.Popen([sys.executable, "-c", _ORACLE_CHILD, ROOT, builder, str(rounds), str(sub_grid)],
+                             stdout=subprocess.PIPE, text=True) for _ in range(procs)]
+    secs = []
+    for k in kids:
+        out, _ = k.communicate()
+        if k.returncode != 0:
+            raise RuntimeError("oracle child failed")
+        secs.append(json.loads(out.strip().splitlines()[-1])["seconds"])
+    beta_n = min(sub_grid, w.n_beta) if sub_grid else w.n_beta
+    p_n = min(sub_grid, w.n_p) if sub_grid else w.n_p
+    updates = rounds * w.mcs_per_swap * beta_n * p_n * w.instance.n
+    return {"value": procs * updates / max(secs), "unit": "spin-updates/s", "cores": procs, "kind": "oracle",
+            "sample": f"{procs} concurrent copies of the single-core sample", "seconds": round(max(secs), 3)}
+
+
 def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
@@ -437,6 +472,8 @@ def main():
     ap.add_argument("--rounds-per-step", type=int, default=None, help="rounds per step (n200: 1000, n1000: 4)")
     ap.add_argument("--cpu-rounds", type=int, default=None,
                     help="rounds of the oracle timed for the CPU baseline (0: skip; n200: 100, n1000: 1)")
+    ap.add_argument("--cpu-procs", type=int, default=min(16, os.cpu_count() or 1),
+                    help="concurrent oracle processes for the all-cores CPU figure (1: skip)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--autotune", type=int, default=None,
                     help="rounds per trial of the launch-shape autotuner, run before the warm-up "
@@ -605,7 +642,11 @@ def main():
     if tune is not None:
         out["autotune"] = tune
     if args.cpu_rounds > 0:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_rounds, sub_grid=4 if big else 8 if gen else 0)
+        sub = 4 if big else 8 if gen else 0
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_rounds, sub_grid=sub)
+        if args.cpu_procs > 1:
+            builder = "coloring_workload" if gen else "wishart_n1000" if big else "wishart_n200"
+            out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(w, builder, args.cpu_rounds, sub, args.cpu_procs)
     print(json.dumps(out), flush=True)
 
 
