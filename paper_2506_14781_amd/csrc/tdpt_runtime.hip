@@ -965,7 +965,9 @@ int tdpt_problem_autotune(tdpt_problem *p, int32_t rounds_per_trial, tdpt_tune_r
 {
     if (!p || !out) return fail(TDPT_E_INVALID, "NULL argument");
     if (rounds_per_trial < 1) return fail(TDPT_E_INVALID, "rounds_per_trial must be >= 1");
-    if ((p->rounds_host + 2 * 40 * (int64_t)rounds_per_trial) * (int64_t)p->mcs > ((int64_t)1 << 32))
+    constexpr int kMaxTrials = 32;
+    // the trials run (temporarily) up to kMaxTrials * (1 + rounds_per_trial) rounds
+    if ((p->rounds_host + kMaxTrials * (1 + (int64_t)rounds_per_trial)) * (int64_t)p->mcs > ((int64_t)1 << 32))
         return fail(TDPT_E_RANGE, "a problem runs at most 2^32 sweeps");
     // candidates: (driver, threads per workgroup)
     std::vector<std::pair<int, int>> cand;
@@ -985,7 +987,7 @@ int tdpt_problem_autotune(tdpt_problem *p, int32_t rounds_per_trial, tdpt_tune_r
         }
     }
     if (cand.empty()) return fail(TDPT_E_INVALID, "no launch shape satisfies the problem's bounds");
-    if (cand.size() > 32) cand.resize(32);
+    if (cand.size() > (size_t)kMaxTrials) cand.resize(kMaxTrials);
     // keep the state: every trial round is undone afterwards
     size_t bytes = 0;
     int rc = tdpt_problem_save(p, nullptr, &bytes);
