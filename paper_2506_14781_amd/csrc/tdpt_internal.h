@@ -42,7 +42,9 @@ constexpr int64_t kKeyOffset = (int64_t)1 << 30;
 // bits (1 = +1) in LDS, kBitSlots replicas interleaved by 32-bit word (word w
 // of replica r at byte 16 w + 4 r); each colour class starts on a 32-bit
 // boundary of the bit numbering (bit_start[c]), so spin rho of class c sits
-// at bit rho - cls_start[c] + bit_start[c].  Structure in bit positions:
+// at bit rho - cls_start[c] + bit_start[c].  Structure in bit positions,
+// each stored as 512 (b >> 5) + (b & 31) so that shifted right by 5 it is the
+// LDS byte address of the word's 4-replica group (the low 5 bits are the bit):
 //   nb_pos / nb_J [wd][n_pad] (missing neighbours: position 0, coupling 0),
 //   ch_pos [2][n_pad] (-1: no copy neighbour), h0 [n_pad] = b - sum_k J_k.
 struct DevProblem {

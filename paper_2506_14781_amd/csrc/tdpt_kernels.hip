@@ -166,6 +166,8 @@ __device__ __forceinline__ v4i bload(const __amdgpu_buffer_rsrc_t &r, int voff, 
 // check the assumption once and refuse to run if it does not hold.
 typedef __attribute__((address_space(3))) int8_t lds8_t;
 typedef __attribute__((address_space(3))) uint32_t lds32_t;
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) u4v lds_u4_t;
 
 __device__ __forceinline__ lds8_t *replica_lds() { return (lds8_t *)(uintptr_t)0u; }
 
@@ -919,7 +921,7 @@ __device__ __forceinline__ uint32_t or8_last(uint32_t x)
 // q: the lane's quad, which may lie past the class end (q1); its structure
 // and spins are read at min(q, q1 - 1) and then it has no live spin.
 template <int WD>
-__device__ __forceinline__ void bits_update_quad(const DevProblem &P, const Rsrc &Rs, uint32_t *W, int q,
+__device__ __forceinline__ void bits_update_quad(const DevProblem &P, const Rsrc &Rs, int q,
                                                  int q1, int c, unsigned live, uint32_t t,
                                                  const SlotParams (&sp)[kBitSlots],
                                                  int (&dfa)[kBitSlots], int (&dga)[kBitSlots])
@@ -938,8 +940,9 @@ __device__ __forceinline__ void bits_update_quad(const DevProblem &P, const Rsrc
         const v4i jk = bload(Rs.b, voff, k * row);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
+            // 512 word + bit: the word group's LDS byte address is pos >> 5
             const int pos = pk[j];
-            const uint4 nw = *reinterpret_cast<const uint4 *>(W + 4 * (pos >> 5));
+            const u4v nw = *(const lds_u4_t *)(uintptr_t)(uint32_t)(pos >> 5);
             const uint32_t w4[4] = {nw.x, nw.y, nw.z, nw.w};
 #pragma unroll
             for (int r = 0; r < kBitSlots; ++r)
@@ -952,8 +955,8 @@ __device__ __forceinline__ void bits_update_quad(const DevProblem &P, const Rsrc
     for (int j = 0; j < 4; ++j) {
         // a missing copy neighbour (-1) reads word 0 and counts 0
         const int p0 = c0[j], p1 = c1[j];
-        const uint4 n0 = *reinterpret_cast<const uint4 *>(W + 4 * (max(p0, 0) >> 5));
-        const uint4 n1 = *reinterpret_cast<const uint4 *>(W + 4 * (max(p1, 0) >> 5));
+        const u4v n0 = *(const lds_u4_t *)(uintptr_t)(uint32_t)(max(p0, 0) >> 5);
+        const u4v n1 = *(const lds_u4_t *)(uintptr_t)(uint32_t)(max(p1, 0) >> 5);
         const uint32_t a4[4] = {n0.x, n0.y, n0.z, n0.w}, b4[4] = {n1.x, n1.y, n1.z, n1.w};
         const int k0 = p0 >= 0 ? 1 : 0, k1 = p1 >= 0 ? 1 : 0;
 #pragma unroll
@@ -966,7 +969,7 @@ __device__ __forceinline__ void bits_update_quad(const DevProblem &P, const Rsrc
     const v4i h0 = bload(Rs.bias, voff, 0);
     const int bpos = qs * 4 - P.cls_start[c] + P.bit_start[c];
     const int wq = bpos >> 5, off = bpos & 31;
-    const uint4 ow = *reinterpret_cast<const uint4 *>(W + 4 * wq);
+    const u4v ow = *(const lds_u4_t *)(uintptr_t)(uint32_t)(wq * 16);
     const uint32_t o4[4] = {ow.x, ow.y, ow.z, ow.w};
     uint32_t nw4[kBitSlots];
 #pragma unroll
@@ -1014,7 +1017,7 @@ __device__ __forceinline__ void bits_update_quad(const DevProblem &P, const Rsrc
 #pragma unroll
     for (int r = 0; r < kBitSlots; ++r) {
         const uint32_t word = or8_last(nw4[r]);
-        if ((threadIdx.x & 7) == 7 && qg < q1) W[4 * wg + r] = word;
+        if ((threadIdx.x & 7) == 7 && qg < q1) *(lds32_t *)(uintptr_t)(uint32_t)(16 * wg + 4 * r) = word;
     }
 }
 
@@ -1023,6 +1026,12 @@ __device__ __forceinline__ void bits_update_quad(const DevProblem &P, const Rsrc
 template <int WD>
 __device__ __forceinline__ void round_sweep_bits_body(const DevProblem &P, int slot0, int8_t *lds)
 {
+    // the replicas' words sit at LDS byte 0 (the update addresses them there)
+    if (!replica_at_zero(lds)) {
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&P.hdr[kHdrError], kErrLdsBase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
     uint32_t *W = reinterpret_cast<uint32_t *>(lds);
     int64_t *red = reinterpret_cast<int64_t *>(lds + (size_t)P.n_words * 16);
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -1067,7 +1076,7 @@ __device__ __forceinline__ void round_sweep_bits_body(const DevProblem &P, int s
                 const int q = base + tid;
                 const int rem = q < q1 ? live_end - q * 4 : 0;
                 const unsigned live = rem >= 4 ? 15u : rem <= 0 ? 0u : ((1u << rem) - 1u);
-                bits_update_quad<WD>(P, Rs, W, q, q1, c, live, t, sp, dfa, dga);
+                bits_update_quad<WD>(P, Rs, q, q1, c, live, t, sp, dfa, dga);
             }
 #pragma unroll
             for (int r = 0; r < kBitSlots; ++r) { df[r] += dfa[r]; dg[r] += dga[r]; }

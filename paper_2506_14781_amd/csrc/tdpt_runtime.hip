@@ -801,7 +801,12 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
             std::vector<int32_t> cls_of(n_pad, 0);
             for (int c = 0; c < in->n_colors; ++c)
                 for (int32_t r = in->cls_start[c]; r < in->cls_start[c + 1]; ++r) cls_of[r] = c;
-            auto bitpos = [&](int32_t r) { return r - in->cls_start[cls_of[r]] + bit_start[cls_of[r]]; };
+            // a bit position b is stored as 512 (b >> 5) + (b & 31): shifted
+            // right by 5 it is the LDS byte address of its word group
+            auto bitpos = [&](int32_t r) {
+                const int32_t b = r - in->cls_start[cls_of[r]] + bit_start[cls_of[r]];
+                return ((b >> 5) << 9) | (b & 31);
+            };
             std::vector<int32_t> pos(in->nb_idx.size()), chp(in->ch_idx.size()), h0(n_pad, 0);
             for (int k = 0; k < in->wd; ++k)
                 for (int32_t r = 0; r < n_pad; ++r) {
