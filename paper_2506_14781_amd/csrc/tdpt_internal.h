@@ -46,7 +46,9 @@ constexpr int64_t kKeyOffset = (int64_t)1 << 30;
 // each stored as 512 (b >> 5) + (b & 31) so that shifted right by 5 it is the
 // LDS byte address of the word's 4-replica group (the low 5 bits are the bit):
 //   nb_pos / nb_J [wd][n_pad] (missing neighbours: position 0, coupling 0),
-//   ch_pos [2][n_pad] (-1: no copy neighbour), h0 [n_pad] = b - sum_k J_k.
+//   ch_pos [2][n_pad] (a missing copy neighbour names bit 0 of an always-zero
+//   word group n_words; row 0 also holds in bits 29..30 how many of the two
+//   exist), h0 [n_pad] = b - sum_k J_k.
 struct DevProblem {
     // structure (immutable)
     int32_t n_pad;      // padded spin count

@@ -953,17 +953,19 @@ __device__ __forceinline__ void bits_update_quad(const DevProblem &P, const Rsrc
     const v4i c1 = bload(Rs.ch, voff, row);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        // a missing copy neighbour (-1) reads word 0 and counts 0
+        // a missing copy neighbour reads a bit of the always-zero word group
+        // past the last class; row 0 carries the count kc of present copy
+        // neighbours in bits 29..30, so the copy sum is 2 (b0 + b1) - kc
         const int p0 = c0[j], p1 = c1[j];
-        const u4v n0 = *(const lds_u4_t *)(uintptr_t)(uint32_t)(max(p0, 0) >> 5);
-        const u4v n1 = *(const lds_u4_t *)(uintptr_t)(uint32_t)(max(p1, 0) >> 5);
+        const u4v n0 = *(const lds_u4_t *)(uintptr_t)__builtin_amdgcn_ubfe((uint32_t)p0, 5, 18);
+        const u4v n1 = *(const lds_u4_t *)(uintptr_t)(uint32_t)(p1 >> 5);
         const uint32_t a4[4] = {n0.x, n0.y, n0.z, n0.w}, b4[4] = {n1.x, n1.y, n1.z, n1.w};
-        const int k0 = p0 >= 0 ? 1 : 0, k1 = p1 >= 0 ? 1 : 0;
+        const int nkc = -(int)((uint32_t)p0 >> 29);
 #pragma unroll
         for (int r = 0; r < kBitSlots; ++r) {
-            const int b0 = (int)__builtin_amdgcn_ubfe(a4[r], p0 & 31, 1) & k0;
-            const int b1 = (int)__builtin_amdgcn_ubfe(b4[r], p1 & 31, 1) & k1;
-            cs[j][r] = 2 * (b0 + b1) - k0 - k1;
+            const int b0 = (int)__builtin_amdgcn_ubfe(a4[r], p0 & 31, 1);
+            const int b1 = (int)__builtin_amdgcn_ubfe(b4[r], p1 & 31, 1);
+            cs[j][r] = 2 * (b0 + b1) + nkc;
         }
     }
     const v4i h0 = bload(Rs.bias, voff, 0);
@@ -1033,11 +1035,13 @@ __device__ __forceinline__ void round_sweep_bits_body(const DevProblem &P, int s
         return;
     }
     uint32_t *W = reinterpret_cast<uint32_t *>(lds);
-    int64_t *red = reinterpret_cast<int64_t *>(lds + (size_t)P.n_words * 16);
+    // words of the replicas, one always-zero word group, then int64 scratch
+    int64_t *red = reinterpret_cast<int64_t *>(lds + (size_t)(P.n_words + 1) * 16);
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int ns = min(kBitSlots, P.R - slot0);
     // unpack: word w of slot r from the spins whose bit positions it holds
-    for (int i = tid; i < P.n_words * kBitSlots; i += nthr) {
+    // (the extra word group w = n_words holds no spin and stays zero)
+    for (int i = tid; i < (P.n_words + 1) * kBitSlots; i += nthr) {
         const int w = i >> 2, r = i & 3;
         uint32_t bits = 0;
         if (r < ns) {
@@ -1349,7 +1353,7 @@ hipError_t launch_batch_sweep(const DevProblem &p, const DevProblem *table, cons
 
 static size_t bits_lds(int n_words)
 {
-    return (size_t)n_words * 16 + 8 * 2 * kBitSlots * (kMaxBlock / 64) + 16;
+    return (size_t)(n_words + 1) * 16 + 8 * 2 * kBitSlots * (kMaxBlock / 64) + 16;
 }
 
 template <bool NARROW, int WD>

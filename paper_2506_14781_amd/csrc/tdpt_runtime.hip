@@ -665,7 +665,7 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
         return fail(TDPT_E_INVALID, "the bit-packed layout takes at most 8 problem neighbours per spin");
     if (bits && in->max_abs_J >= ((int64_t)1 << 23))
         return fail(TDPT_E_RANGE, "the bit-packed layout takes couplings |J_q| < 2^23");
-    if (bits ? (size_t)n_words * 16 + 4096 > lds_limit : (size_t)L.stride > lds_limit)
+    if (bits ? (size_t)(n_words + 1) * 16 + 4096 > lds_limit : (size_t)L.stride > lds_limit)
         return fail(TDPT_E_INVALID, "a replica (" + std::to_string(in->n_pad) +
                                         " spins) does not fit the LDS of one workgroup");
 
@@ -815,8 +815,16 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
                     h0[r] -= in->nb_J[(size_t)k * n_pad + r];
                 }
             for (int32_t r = 0; r < n_pad; ++r) h0[r] += in->bias[r];
+            // copy neighbours: a missing one names bit 0 of the always-zero
+            // word group n_words; row 0 also carries, in bits 29..30, how
+            // many of the spin's two copy neighbours exist
+            const int32_t zero_pos = n_words << 9;
             for (size_t i = 0; i < chp.size(); ++i)
-                chp[i] = (in->ch_idx[i] == n_pad) ? -1 : bitpos(in->ch_idx[i]);
+                chp[i] = (in->ch_idx[i] == n_pad) ? zero_pos : bitpos(in->ch_idx[i]);
+            for (int32_t r = 0; r < n_pad; ++r) {
+                const int32_t kc = (in->ch_idx[r] != n_pad) + (in->ch_idx[(size_t)n_pad + r] != n_pad);
+                chp[r] |= kc << 29;
+            }
             UP(ws + L.nb_pos, pos.data(), pos.size() * 4);
             UP(ws + L.ch_pos, chp.data(), chp.size() * 4);
             UP(ws + L.h0, h0.data(), h0.size() * 4);
