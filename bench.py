@@ -52,15 +52,15 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # copy of known size; valid for that kernel on that workload and for the
 # kernel source with this hash.
 MEASURED_TRAFFIC = {
-    # one 200-round launch on the N=200 workload: FETCH 14,618.8 KiB, WRITE 11,957.0 KiB
-    "wishart-N200-D8-32x16": {"kernel": "k_persistent", "kernel_sha256": "4bc4e98ed2a13b44",
-                              "bytes_per_round": 210916},
-    # one 50-sweep round on the N=1000 workload: FETCH 5,329,585.3 KiB, WRITE 505,818.1 KiB
-    "wishart-N1000-D6-64x32": {"kernel": "k_round_sweep_bits", "kernel_sha256": "4bc4e98ed2a13b44",
-                               "bytes_per_round": 11432948531},
-    # one 10-round launch on the colouring workload: FETCH 11,865.8 KiB, WRITE 26,259.2 KiB
-    "coloring-V4000-k4-d6-32x16": {"kernel": "k_persistent", "kernel_sha256": "4bc4e98ed2a13b44",
-                                   "bytes_per_round": 5119058},
+    # one 200-round launch on the N=200 workload: FETCH 14,604.4 KiB, WRITE 11,957.0 KiB
+    "wishart-N200-D8-32x16": {"kernel": "k_persistent", "kernel_sha256": "5592f015c750743a",
+                              "bytes_per_round": 210769},
+    # one 50-sweep round on the N=1000 workload: FETCH 5,328,853.2 KiB, WRITE 505,911.1 KiB
+    "wishart-N1000-D6-64x32": {"kernel": "k_round_sweep_bits", "kernel_sha256": "5592f015c750743a",
+                               "bytes_per_round": 11431544422},
+    # one 10-round launch on the colouring workload: FETCH 11,879.1 KiB, WRITE 26,261.4 KiB
+    "coloring-V4000-k4-d6-32x16": {"kernel": "k_persistent", "kernel_sha256": "5592f015c750743a",
+                                   "bytes_per_round": 5122007},
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_2506_14781_amd", "csrc", "tdpt_kernels.hip")
 
