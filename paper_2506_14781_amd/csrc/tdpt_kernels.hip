@@ -449,13 +449,17 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v)
     return v;
 }
 
-// All sweeps of one round of the slot held at LDS address 0; returns the
-// change of f and g summed over the block into red[0..1] (LDS scratch of
-// 2 * (blockDim / 64) int64).  A lane walks its quads q0 + tid, q0 + tid +
-// blockDim, .. of every class.
-template <bool NARROW, int WD>
+// All sweeps of one round of the slot held at LDS address 0; leaves the
+// change of f and g summed over the block in red[0..1] (LDS scratch of
+// 2 * (blockDim / 64) int64), written and meant to be read by thread 0 only.
+// A lane walks its quads q0 + tid, q0 + tid + blockDim, .. of every class.
+// at_end() runs on every thread after its last quad, before the closing
+// barrier (the reduction's, which also ends the last class); on return the
+// spins are final for the whole block.
+template <bool NARROW, int WD, typename AtEnd>
 __device__ __forceinline__ void sweep_round(const DevProblem &P, const Rsrc &Rs, lds8_t *s,
-                                            const SlotParams &sp, int64_t n_round, int64_t *red)
+                                            const SlotParams &sp, int64_t n_round, int64_t *red,
+                                            AtEnd &&at_end)
 {
     const int tid = threadIdx.x, nthr = blockDim.x;
     int64_t df = 0, dg = 0;
@@ -476,9 +480,10 @@ __device__ __forceinline__ void sweep_round(const DevProblem &P, const Rsrc &Rs,
             }
             df += dfa;
             dg += 2 * (int64_t)dga;
-            __syncthreads();
+            if (k + 1 < P.mcs || c + 1 < P.n_colors) __syncthreads();
         }
     }
+    at_end();
     const int64_t a = wave_sum64(df), b = wave_sum64(dg);
     const int wave = tid >> 6, nw = nthr >> 6;
     if ((tid & 63) == 0) { red[2 + 2 * wave] = a; red[3 + 2 * wave] = b; }
@@ -489,7 +494,6 @@ __device__ __forceinline__ void sweep_round(const DevProblem &P, const Rsrc &Rs,
         red[0] = sa;
         red[1] = sb;
     }
-    __syncthreads();
 }
 
 __device__ __forceinline__ void copy_bytes16(int8_t *dst, const int8_t *src, int bytes)
@@ -521,7 +525,7 @@ __device__ __forceinline__ void round_sweep_body(const DevProblem &P, int slot, 
     const SlotParams sp = slot_params(P, P.slot_pos[slot], P.beta, P.p_q);
     const Rsrc Rs = make_rsrc(P);
     __syncthreads();
-    sweep_round<NARROW, WD>(P, Rs, replica_lds(), sp, n_round, red);
+    sweep_round<NARROW, WD>(P, Rs, replica_lds(), sp, n_round, red, [] {});
     if (threadIdx.x == 0) {
         P.f[slot] += red[0];
         P.g[slot] += red[1];
@@ -558,26 +562,48 @@ __device__ __forceinline__ bool metropolis(double x, double u)
     return x >= 0.0 || u <= exp(x);
 }
 
-// Swap exponent and acceptance of the pair (left / upper position a,
-// right / lower position b) in round n.  P pairs lie on row `line` with left
-// column k; beta pairs on column `line` with upper row k.
+// The same decision with lu = log(u) taken in advance, so that only a
+// comparison remains once x is known.  u is 0 or at least 2^-53, so |ln u|
+// < 37; log and exp are good to a few ulp, hence |lu - ln u| < 2^-40 and
+// exp(x) is within a relative 2^-40 of e^x.  If x exceeds lu by more than
+// 2^-30, e^x > u (1 + 2^-31) and the computed exp(x) is above u: accept;
+// below lu by more than 2^-30 likewise reject; in between the expression
+// itself decides.  u = 0 gives lu = -inf and acceptance, as u <= exp(x).
+__device__ __forceinline__ bool metropolis_pre(double x, double u, double lu)
+{
+    if (x >= 0.0 || x > lu + 0x1p-30) return true;
+    if (x < lu - 0x1p-30) return false;
+    return u <= exp(x);
+}
+
+// Swap exponent of the pair (left / upper position a, right / lower
+// position b): P pairs lie on row `line` with left column k (Eq. 2), beta
+// pairs on column `line` with upper row k (Eq. 3).
+__device__ __forceinline__ double pair_exponent(const double *beta, const int32_t *p_q, bool dir_beta, int k,
+                                                int line, int64_t fa, int64_t ga, int64_t fb, int64_t gb)
+{
+    if (!dir_beta) {
+        const int64_t dpg = ((int64_t)p_q[k + 1] - p_q[k]) * (gb - ga);
+        return ldexp(beta[line] * (double)dpg, -12);
+    }
+    const int64_t ea = fa + (int64_t)p_q[line] * ga;
+    const int64_t eb = fb + (int64_t)p_q[line] * gb;
+    const double dbeta = beta[k + 1] - beta[k];
+    return ldexp(dbeta * (double)(eb - ea), -12);
+}
+
+// Uniform of the pair's decision in round n.
+__device__ __forceinline__ double pair_uniform(const DevProblem &P, bool dir_beta, int k, int line, int64_t n)
+{
+    return philox_u53((uint32_t)k, (uint32_t)n, (uint32_t)line, dir_beta ? 2u : 1u, P.key0, P.key1);
+}
+
 __device__ __forceinline__ bool pair_accept(const DevProblem &P, const double *beta, const int32_t *p_q,
                                             bool dir_beta, int k, int line, int64_t n, int64_t fa, int64_t ga,
                                             int64_t fb, int64_t gb)
 {
-    double x;
-    if (!dir_beta) {
-        const int64_t dpg = ((int64_t)p_q[k + 1] - p_q[k]) * (gb - ga);
-        x = ldexp(beta[line] * (double)dpg, -12);
-    } else {
-        const int64_t ea = fa + (int64_t)p_q[line] * ga;
-        const int64_t eb = fb + (int64_t)p_q[line] * gb;
-        const double dbeta = beta[k + 1] - beta[k];
-        x = ldexp(dbeta * (double)(eb - ea), -12);
-    }
-    const double u = philox_u53((uint32_t)k, (uint32_t)n, (uint32_t)line, dir_beta ? 2u : 1u,
-                                P.key0, P.key1);
-    return metropolis(x, u);
+    return metropolis(pair_exponent(beta, p_q, dir_beta, k, line, fa, ga, fb, gb),
+                      pair_uniform(P, dir_beta, k, line, n));
 }
 
 __device__ __forceinline__ void round_schedule(const DevProblem &P, int64_t n, bool &dir_beta, int &first)
@@ -656,17 +682,24 @@ __global__ __launch_bounds__(kSmallBlock) void k_batch_swap(const DevProblem *__
 // rewrites it.
 __device__ __forceinline__ uint64_t mb_tag(int64_t n) { return (uint64_t)((n & 0x7fff) | 0x8000); }
 
+__device__ __forceinline__ uint64_t mb_load(const uint64_t *m)
+{
+    return __hip_atomic_load(const_cast<uint64_t *>(m), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool mb_take(uint64_t w0, uint64_t w1, uint64_t tag, int64_t &f, int64_t &g)
+{
+    if ((w0 & 0xffff) != tag || (w1 & 0xffff) != tag) return false;
+    f = (int64_t)((w0 >> 16) | (((w1 >> 16) & 0xffff) << 48));
+    g = (int64_t)(w1 >> 32);
+    return true;
+}
+
 __device__ __forceinline__ bool mb_wait(const uint64_t *m, uint64_t tag, int64_t &f, int64_t &g, int64_t *hdr)
 {
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
     for (;;) {
-        const uint64_t w0 = __hip_atomic_load(const_cast<uint64_t *>(m), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint64_t w1 = __hip_atomic_load(const_cast<uint64_t *>(m + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((w0 & 0xffff) == tag && (w1 & 0xffff) == tag) {
-            f = (int64_t)((w0 >> 16) | (((w1 >> 16) & 0xffff) << 48));
-            g = (int64_t)(w1 >> 32);
-            return true;
-        }
+        if (mb_take(mb_load(m), mb_load(m + 1), tag, f, g)) return true;
         __builtin_amdgcn_s_sleep(1);
         if (__builtin_amdgcn_s_memrealtime() - t0 > 200000000ull) {  // 2 s of the 100 MHz clock
             __hip_atomic_store(&hdr[kHdrError], (int64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -675,12 +708,45 @@ __device__ __forceinline__ bool mb_wait(const uint64_t *m, uint64_t tag, int64_t
     }
 }
 
+// The pairing of grid position pos in round n: k >= 0 when it has a partner,
+// then `other` is the partner's position and `left` tells whether pos is the
+// left (P pairs) or upper (beta pairs) one.
+struct RoundPair {
+    bool dir_beta, left;
+    int k, line, other;
+};
+
+__device__ __forceinline__ RoundPair round_pair(const DevProblem &P, int64_t n, int pos)
+{
+    RoundPair r;
+    int first;
+    round_schedule(P, n, r.dir_beta, first);
+    const int i = pos / P.J, j = pos - i * P.J;
+    const int x = r.dir_beta ? i : j;
+    r.line = r.dir_beta ? j : i;
+    const int len = r.dir_beta ? P.I : P.J;
+    r.k = -1;
+    r.left = false;
+    r.other = pos;
+    if (x >= first && ((x - first) & 1) == 0 && x + 1 < len) { r.k = x; r.left = true; }
+    else if (x >= first + 1 && ((x - first) & 1) == 1) { r.k = x - 1; }
+    if (r.k >= 0) {
+        const int a = r.dir_beta ? r.k * P.J + r.line : r.line * P.J + r.k;
+        const int b = r.dir_beta ? a + P.J : a + 1;
+        r.other = r.left ? b : a;
+    }
+    return r;
+}
+
 // One block per replica slot; runs n_rounds rounds.  Per round: sweep in
 // LDS, post (f, g) in the mailbox of the slot's grid position, read the
 // partner position's mailbox, take the pair's decision (both partners draw
 // the same Philox number and reach the same answer), move, and, if the slot
 // now sits bottom-right, record it.  Best states are kept per slot and
-// merged by k_finalize.
+// merged by k_finalize.  The partner's entry is first read while the block
+// reduces its energy change (a partner that finished earlier has posted by
+// then), and the pair's uniform and its logarithm are computed while that
+// read is in flight.
 template <bool NARROW, int WD>
 __device__ __forceinline__ void persistent_body(const DevProblem &P, int slot, int64_t n_rounds, int8_t *lds)
 {
@@ -713,39 +779,40 @@ __device__ __forceinline__ void persistent_body(const DevProblem &P, int slot, i
         const int64_t n = n0 + rr;
         const int pos = __builtin_amdgcn_readfirstlane(sh[0]);
         const SlotParams sp = slot_params(P, pos, lbeta, lpq);
-        sweep_round<NARROW, WD>(P, Rs, replica_lds(), sp, n, red);
+        const RoundPair rp = round_pair(P, n, pos);
+        uint64_t *mb = P.mbox + 2 * ((size_t)(n & (kRing - 1)) * P.R);
+        uint64_t pw0 = 0, pw1 = 0;
+        sweep_round<NARROW, WD>(P, Rs, replica_lds(), sp, n, red, [&] {
+            if (tid == 0 && rp.k >= 0) {
+                pw0 = mb_load(&mb[2 * rp.other]);
+                pw1 = mb_load(&mb[2 * rp.other + 1]);
+            }
+        });
         if (tid == 0) {
             const int64_t f = st[0] + red[0];
             const int64_t g = st[1] + red[1];
             st[0] = f;
             st[1] = g;
-            uint64_t *mb = P.mbox + 2 * ((size_t)(n & (kRing - 1)) * P.R);
             const uint64_t tag = mb_tag(n);
             __hip_atomic_store(&mb[2 * pos], ((uint64_t)f << 16) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&mb[2 * pos + 1],
                                ((uint64_t)(uint32_t)g << 32) | ((((uint64_t)f >> 48) & 0xffff) << 16) | tag,
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            bool dir_beta;
-            int first;
-            round_schedule(P, n, dir_beta, first);
-            const int i = pos / P.J, j = pos - i * P.J;
-            const int x = dir_beta ? i : j, line = dir_beta ? j : i;
-            const int len = dir_beta ? P.I : P.J;
-            int k = -1;
-            bool left = false;
-            if (x >= first && ((x - first) & 1) == 0 && x + 1 < len) { k = x; left = true; }
-            else if (x >= first + 1 && ((x - first) & 1) == 1) { k = x - 1; }
+            const bool dir_beta = rp.dir_beta, left = rp.left;
+            const int k = rp.k, line = rp.line, other = rp.other;
             int newpos = pos;
             int abort = 0;
             if (k >= 0) {
-                const int a = dir_beta ? k * P.J + line : line * P.J + k;
-                const int b = dir_beta ? a + P.J : a + 1;
-                const int other = left ? b : a;
+                const double u = pair_uniform(P, dir_beta, k, line, n);
+                const double lu = log(u);
+                // keep u and lu ahead of the partner's read instead of sunk behind it
+                __asm__ volatile("" ::"v"(u), "v"(lu));
                 int64_t fo = 0, go = 0;
-                if (!mb_wait(&mb[2 * other], tag, fo, go, P.hdr)) abort = 1;
+                if (!mb_take(pw0, pw1, tag, fo, go) && !mb_wait(&mb[2 * other], tag, fo, go, P.hdr)) abort = 1;
                 const int64_t fa = left ? f : fo, ga = left ? g : go;
                 const int64_t fb = left ? fo : f, gb = left ? go : g;
-                const bool acc = !abort && pair_accept(P, lbeta, lpq, dir_beta, k, line, n, fa, ga, fb, gb);
+                const bool acc =
+                    !abort && metropolis_pre(pair_exponent(lbeta, lpq, dir_beta, k, line, fa, ga, fb, gb), u, lu);
                 if (left && !abort) {
                     const int ci = dir_beta ? line * (P.I - 1) + k : line * (P.J - 1) + k;
                     __hip_atomic_fetch_add(dir_beta ? &P.b_att[ci] : &P.p_att[ci], (int64_t)1,
