@@ -249,6 +249,15 @@ def bench_tts(args):
     sp = summarize(reqs_p, tp)
     for a, b in zip(reqs_b, reqs_p):
         assert a.hit_sweep == b.hit_sweep, "sweeps to hit differ between modes"
+    for reqs, s in ((reqs_b, sb), (reqs_p, sp)):
+        # time until 99 % of all runs have hit (None below 99 % success), and
+        # each run's time to hit from its own start (plain runs queue)
+        hits = sorted(r.hit_time for r in reqs if r.hit_time is not None)
+        need = math.ceil(0.99 * len(reqs))
+        s["time_to_99pct_of_runs_s"] = hits[need - 1] if len(hits) >= need else None
+        own = [r.hit_time - r.start for r in reqs if r.hit_time is not None]
+        s["run_time_to_hit_p50_s"] = float(np.percentile(own, 50)) if own else None
+        s["run_time_to_hit_p99_s"] = float(np.percentile(own, 99)) if own else None
     p = sb["hit_fraction"]
     tts99 = None
     if 0 < p < 1:
