@@ -832,28 +832,38 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     }
     UP(ws + L.bias, in->bias.data(), in->bias.size() * 4);
     UP(ws + L.orig, in->orig.data(), in->orig.size() * 4);
-    // mutable state
+    // mutable state: cleared on the device (states and best-state copies
+    // are most of the workspace), then the few words that start non-zero
     {
-        std::vector<uint8_t> zero(L.scratch_end, 0);
-        int64_t *hdr = (int64_t *)(zero.data() + L.hdr);
+        if (cfg->s0)
+            for (size_t i = 0; i < (size_t)R * in->n; ++i)
+                if (cfg->s0[i] != 1 && cfg->s0[i] != -1) return cleanup(fail(TDPT_E_INVALID, "s0 must be +-1"));
+        e = hipMemsetAsync(ws, 0, L.scratch_end, s);
+        if (e != hipSuccess) return cleanup(hip_fail(e, "clear workspace"));
+        std::vector<int64_t> hdr(tdpt::kHdrWords, 0);
         hdr[tdpt::kHdrRounds] = 0;
         hdr[tdpt::kHdrFirstHit] = -1;
         hdr[tdpt::kHdrBestF] = INT64_MAX;
         hdr[tdpt::kHdrBestSweep] = -1;
-        int32_t *sp = (int32_t *)(zero.data() + L.slot_pos);
-        int32_t *ps = (int32_t *)(zero.data() + L.pos_slot);
-        for (int32_t r = 0; r < R; ++r) sp[r] = ps[r] = r;
+        UP(ws + L.hdr, hdr.data(), hdr.size() * 8);
+        std::vector<int32_t> ids(R);
+        for (int32_t r = 0; r < R; ++r) ids[r] = r;
+        UP(ws + L.slot_pos, ids.data(), ids.size() * 4);
+        UP(ws + L.pos_slot, ids.data(), ids.size() * 4);
         if (cfg->s0) {
-            for (int32_t r = 0; r < R; ++r) {
-                int8_t *st = (int8_t *)(zero.data() + L.states + (size_t)r * L.stride);
-                const int8_t *src = cfg->s0 + (size_t)r * in->n;
-                for (int32_t v = 0; v < in->n; ++v) {
-                    if (src[v] != 1 && src[v] != -1) return cleanup(fail(TDPT_E_INVALID, "s0 must be +-1"));
-                    st[in->rank[v]] = src[v];
+            // about 16 MB of replicas per upload (padding bytes stay zero)
+            const int32_t per = (int32_t)std::max<size_t>(1, ((size_t)16 << 20) / (size_t)L.stride);
+            std::vector<int8_t> st((size_t)std::min(per, R) * L.stride, 0);
+            for (int32_t r0 = 0; r0 < R; r0 += per) {
+                const int32_t nr = std::min(per, R - r0);
+                for (int32_t r = 0; r < nr; ++r) {
+                    const int8_t *src = cfg->s0 + (size_t)(r0 + r) * in->n;
+                    int8_t *dst = st.data() + (size_t)r * L.stride;
+                    for (int32_t v = 0; v < in->n; ++v) dst[in->rank[v]] = src[v];
                 }
+                UP(ws + L.states + (size_t)r0 * L.stride, st.data(), (size_t)nr * L.stride);
             }
         }
-        UP(ws, zero.data(), zero.size());
     }
 #undef UP
     if (!cfg->s0) {
