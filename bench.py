@@ -52,15 +52,15 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # copy of known size; valid for that kernel on that workload and for the
 # kernel source with this hash.
 MEASURED_TRAFFIC = {
-    # one 200-round launch on the N=200 workload: FETCH 14,604.4 KiB, WRITE 11,957.0 KiB
-    "wishart-N200-D8-32x16": {"kernel": "k_persistent", "kernel_sha256": "5592f015c750743a",
-                              "bytes_per_round": 210769},
-    # one 50-sweep round on the N=1000 workload: FETCH 5,328,853.2 KiB, WRITE 505,911.1 KiB
-    "wishart-N1000-D6-64x32": {"kernel": "k_round_sweep_bits", "kernel_sha256": "5592f015c750743a",
-                               "bytes_per_round": 11431544422},
-    # one 10-round launch on the colouring workload: FETCH 11,879.1 KiB, WRITE 26,261.4 KiB
-    "coloring-V4000-k4-d6-32x16": {"kernel": "k_persistent", "kernel_sha256": "5592f015c750743a",
-                                   "bytes_per_round": 5122007},
+    # one 200-round launch on the N=200 workload: FETCH 16,951.6 KiB, WRITE 11,957.0 KiB
+    "wishart-N200-D8-32x16": {"kernel": "k_persistent", "kernel_sha256": "2bd01e080ceadfce",
+                              "bytes_per_round": 234804},
+    # one 50-sweep round on the N=1000 workload: FETCH 5,329,768.4 KiB, WRITE 505,865.2 KiB
+    "wishart-N1000-D6-64x32": {"kernel": "k_round_sweep_bits", "kernel_sha256": "2bd01e080ceadfce",
+                               "bytes_per_round": 11433371560},
+    # one 10-round launch on the colouring workload: FETCH 12,271.7 KiB, WRITE 36,245.0 KiB
+    "coloring-V4000-k4-d6-32x16": {"kernel": "k_persistent", "kernel_sha256": "2bd01e080ceadfce",
+                                   "bytes_per_round": 6224726},
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_2506_14781_amd", "csrc", "tdpt_kernels.hip")
 

@@ -350,6 +350,25 @@ def test_n1000_instance_bit_exact_on_a_sub_grid(T):
     both(T, w.instance, beta, p_q, mcs=50, rounds=1, seed=4, label="wishart-N1000 2x2")
 
 
+def test_caller_initial_state_in_several_uploads(T):
+    """A given initial state larger than one upload chunk (80 replicas of
+    250,000 spins, about 20 MB) arrives whole: the states read back equal
+    it, and the initial energies of replicas in the first and the last chunk
+    equal the oracle's."""
+    from synth.configs import wishart_n1000
+    w = wishart_n1000()
+    beta = np.geomspace(0.1, 3.0, 4)
+    p_q = np.linspace(0, 8192, 20).astype(np.int32)
+    R = len(beta) * len(p_q)
+    s0 = random_spins(np.random.default_rng(12), R * w.instance.n).reshape(R, w.instance.n)
+    _say("[s0] wishart-N1000 4x20 given state, 0 rounds")
+    P = T.Problem(T.Instance.from_synth(w.instance), T.RunConfig(beta, p_q, mcs_per_swap=1, seed=0, s0=s0))
+    assert np.array_equal(P.states(), s0)
+    f, g = P.energies()
+    for r in (0, 66, 67, R - 1):
+        assert O.energy(w.instance, s0[r]) == (f[r], g[r])
+
+
 def test_n1000_full_grid_invariants(T):
     """Full 64x32 grid of the N=1000 instance, two rounds of 50 sweeps: every
     spin +-1, f and g of sampled positions equal their recomputation, the
