@@ -176,9 +176,11 @@ void tdpt_instance_destroy(tdpt_instance *inst);
 int tdpt_workspace_bytes(const tdpt_instance *inst, const tdpt_run_cfg *cfg, size_t *bytes);
 
 /* Create a problem in a caller-owned device workspace (>= tdpt_workspace_bytes,
- * 256-byte aligned, on the current HIP device) and enqueue its
- * initialisation on `stream` (a hipStream_t; NULL is the default stream).
- * The instance may be destroyed afterwards.  The workspace must stay
+ * 256-byte aligned, on the current HIP device) and initialise it on `stream`
+ * (a hipStream_t; NULL is the default stream): the workspace is cleared on
+ * the device, the structure, ladders and any caller states are copied in,
+ * and the call returns once the initial energies are computed (it waits for
+ * the stream).  The instance may be destroyed afterwards.  The workspace must stay
  * allocated until tdpt_problem_destroy.  Returns TDPT_E_RANGE if a local
  * field could reach 2^31 in magnitude (sum |J_q| + |b_q| + 2 P_q * copy
  * degree) or an energy difference 2^52, or if an instance whose replica
