@@ -12,7 +12,7 @@ constexpr int kMaxBlock = 1024;   // threads per sweep workgroup, at most
 constexpr int kSmallBlock = 256;  // threads of the swap / energy kernels
 constexpr int kRing = 8;          // rounds of partner mailboxes kept per position
 constexpr int kBitSlots = 4;      // replicas per workgroup in the bit-packed layout
-constexpr int kBitsBlock = 512;   // threads of a bit-packed sweep workgroup, at most
+constexpr int kBitsBlock = 768;   // threads of a bit-packed sweep workgroup, at most
 
 // Header words of a problem's device state (int64 each).
 enum HdrWord {

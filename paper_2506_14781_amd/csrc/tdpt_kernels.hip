@@ -977,6 +977,16 @@ __global__ __launch_bounds__(kSmallBlock) void k_batch_finalize(const DevProblem
 
 // OR of x over the aligned group of 8 lanes containing this lane, in the
 // group's last lane (DPP: quad_perm swaps, then a shift by 4 within a row).
+// a * b + c on 24-bit operands as one instruction (the compiler otherwise
+// pairs the products into three-input adds: three instructions per two
+// products instead of two)
+__device__ __forceinline__ int mad24(int a, int b, int c)
+{
+    int r;
+    __asm__("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
 __device__ __forceinline__ uint32_t or8_last(uint32_t x)
 {
     x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
@@ -1013,7 +1023,7 @@ __device__ __forceinline__ void bits_update_quad(const DevProblem &P, const Rsrc
             const uint32_t w4[4] = {nw.x, nw.y, nw.z, nw.w};
 #pragma unroll
             for (int r = 0; r < kBitSlots; ++r)
-                acc[j][r] += __mul24((int)__builtin_amdgcn_ubfe(w4[r], pos & 31, 1), jk[j]);
+                acc[j][r] = mad24((int)__builtin_amdgcn_ubfe(w4[r], pos & 31, 1), jk[j], acc[j][r]);
         }
     }
     const v4i c0 = bload(Rs.ch, voff, 0);
