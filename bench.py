@@ -52,15 +52,15 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # copy of known size; valid for that kernel on that workload and for the
 # kernel source with this hash.
 MEASURED_TRAFFIC = {
-    # one 200-round launch on the N=200 workload: FETCH 16,951.6 KiB, WRITE 11,957.0 KiB
-    "wishart-N200-D8-32x16": {"kernel": "k_persistent", "kernel_sha256": "2bd01e080ceadfce",
-                              "bytes_per_round": 234804},
-    # one 50-sweep round on the N=1000 workload: FETCH 5,329,768.4 KiB, WRITE 505,865.2 KiB
-    "wishart-N1000-D6-64x32": {"kernel": "k_round_sweep_bits", "kernel_sha256": "2bd01e080ceadfce",
-                               "bytes_per_round": 11433371560},
-    # one 10-round launch on the colouring workload: FETCH 12,271.7 KiB, WRITE 36,245.0 KiB
-    "coloring-V4000-k4-d6-32x16": {"kernel": "k_persistent", "kernel_sha256": "2bd01e080ceadfce",
-                                   "bytes_per_round": 6224726},
+    # one 200-round launch on the N=200 workload: FETCH 16,961.6 KiB, WRITE 11,957.0 KiB
+    "wishart-N200-D8-32x16": {"kernel": "k_persistent", "kernel_sha256": "3d100ff645492d32",
+                              "bytes_per_round": 234907},
+    # one 50-sweep round on the N=1000 workload: FETCH 5,329,819.7 KiB, WRITE 513,519.1 KiB
+    "wishart-N1000-D6-64x32": {"kernel": "k_round_sweep_bits", "kernel_sha256": "3d100ff645492d32",
+                               "bytes_per_round": 11441314288},
+    # one 10-round launch on the colouring workload: FETCH 12,202.6 KiB, WRITE 36,244.6 KiB
+    "coloring-V4000-k4-d6-32x16": {"kernel": "k_persistent", "kernel_sha256": "3d100ff645492d32",
+                                   "bytes_per_round": 6210528},
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_2506_14781_amd", "csrc", "tdpt_kernels.hip")
 
