@@ -237,7 +237,7 @@ int tdpt_problem_read_timing(tdpt_problem *prob, double *total_ms, int64_t *laun
  * workgroup) pair on the problem itself -- one warm-up round, then
  * rounds_per_trial rounds between HIP events on the problem's stream -- and
  * keeps the fastest for later runs.  Candidates: the per-round driver at 64
- * to 1024 threads (512 for bit-packed replicas) and, where every replica's
+ * to 1024 threads (768 for bit-packed replicas) and, where every replica's
  * workgroup can be resident at once, the persistent driver at 64 to 512,
  * each no larger than the largest colour class needs and no smaller than the
  * per-phase 2^31 bounds allow.  The problem's state is saved before and
@@ -278,7 +278,7 @@ int tdpt_batch_set_members(tdpt_batch *batch, tdpt_problem *const *probs, int32_
 /* Enqueue n_rounds rounds of every member on the batch's stream. */
 int tdpt_batch_run(tdpt_batch *batch, int64_t n_rounds);
 /* Autotune the threads per sweep workgroup of each layout group of the
- * current members (64 to 1024, 512 for bit-packed groups, no smaller than
+ * current members (64 to 1024, 768 for bit-packed groups, no smaller than
  * the members' per-phase bounds allow), one group after another, timing
  * whole batch rounds; every member's state is restored afterwards.  The
  * choice holds until the next tdpt_batch_set_members. */
