@@ -314,11 +314,12 @@ def bench_serving(args):
     print(json.dumps(out), flush=True)
 
 
-def _planted_f(T, w) -> int:
-    """f_q of the planted state (the ground state), computed on the GPU."""
-    inst = T.Instance.from_synth(w.instance)
-    planted = np.tile(w.instance.physical_state(w.instance.planted), w.replicas)
-    probe = T.Problem(inst, T.RunConfig(w.beta, w.p_q, mcs_per_swap=w.mcs_per_swap, seed=0, s0=planted))
+def _planted_f(T, w, inst=None) -> int:
+    """f_q of the planted state (the ground state), computed on the GPU on a
+    one-replica grid (f does not depend on beta or P)."""
+    inst = inst if inst is not None else T.Instance.from_synth(w.instance)
+    planted = w.instance.physical_state(w.instance.planted)
+    probe = T.Problem(inst, T.RunConfig(w.beta[:1], w.p_q[:1], mcs_per_swap=1, seed=0, s0=planted))
     f = int(probe.energies()[0][0])
     probe.close()
     return f
@@ -554,7 +555,9 @@ def main():
     if gen:
         lens = np.diff(w.instance.term_ptr).astype(np.float64)
         cons_deg_mean = float((lens * (lens - 1)).sum()) / w.instance.n
-    cfg = T.RunConfig(w.beta, w.p_q, mcs_per_swap=w.mcs_per_swap, seed=args.seed, f_target=w.f_target_q)
+    # target: the planted ground state (Wishart) or the planted colouring
+    f_target = w.f_target_q if gen else _planted_f(T, w, inst)
+    cfg = T.RunConfig(w.beta, w.p_q, mcs_per_swap=w.mcs_per_swap, seed=args.seed, f_target=f_target)
     prob = T.Problem(inst, cfg, device="cuda:0")
     rps = args.rounds_per_step
     tune = None
@@ -644,10 +647,18 @@ def main():
         },
         "roofline": roofline,
     }
+    # time to target of this run (warm-up and autotune rounds included in
+    # the sweep count; censored when first_hit_sweep is -1)
+    hit = q["first_hit_sweep"]
+    per_sweep_s = ms / 1e3 / (total_rounds * w.mcs_per_swap)
+    out["target"] = {"f_target_q": f_target, "best_f_q": q["best_f_q"],
+                     "best_rho_E": ((q["best_f_q"] - f_target) / (4096.0 * w.instance.N)
+                                    if q["best_f_q"] < (1 << 62) else None),
+                     "sweeps_run": q["sweeps_done"],
+                     "first_hit_sweep": hit if hit >= 0 else None,
+                     "time_to_target_s": hit * per_sweep_s if hit >= 0 else None}
     if gen:
-        out["config"].update({"constraint": "one-hot terms", "n_terms": info["n_terms"],
-                              "f_target_q": w.f_target_q,
-                              "first_hit_sweep": q["first_hit_sweep"]})
+        out["config"].update({"constraint": "one-hot terms", "n_terms": info["n_terms"]})
     if tune is not None:
         out["autotune"] = tune
     if args.cpu_rounds > 0:
