@@ -130,7 +130,7 @@ typedef struct tdpt_status {
  *               problem coupling); the constraint is g = sum (s_a - s_b)^2
  *   color       [n] colour class of every spin (>= 0); must be proper over
  *               problem and copy edges (a spin shares no class with any neighbour)
- * At most 48 problem neighbours and 2 copy neighbours per spin, at most 32
+ * At most 256 problem neighbours and 2 copy neighbours per spin, at most 32
  * colour classes.
  * All arrays are read during the call only.  On success *out owns a host
  * object released by tdpt_instance_destroy.  Returns TDPT_E_INVALID with a

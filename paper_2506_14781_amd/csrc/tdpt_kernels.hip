@@ -203,10 +203,11 @@ __device__ __forceinline__ SlotParams slot_params(const DevProblem &P, int pos, 
 // Structure of one quad (4 consecutive colour-major spins): one 16-byte
 // load per structure row.  Up to 8 neighbours per spin every row is held at
 // once; wider rows are streamed in chunks by quad_fields (kStream), which
-// keeps them out of spill territory.
+// keeps them out of spill territory.  WD = 0 stands for a width known only
+// at run time (P.wd, a multiple of 8 above 48), streamed the same way.
 template <bool NARROW, int WD>
 struct QuadS {
-    static constexpr bool kStream = WD > 8;
+    static constexpr bool kStream = WD > 8 || WD == 0;
     static constexpr int K = kStream ? 1 : (NARROW ? WD / 2 : WD);
     v4i a[K];    // narrow: index pairs; wide: indices
     v4i b[K];    // narrow: coupling pairs; wide: couplings
@@ -285,7 +286,7 @@ __device__ __forceinline__ void quad_fields(const DevProblem &P, const Rsrc &Rs,
     for (int j = 0; j < 4; ++j) hp[j] = Q.bias[j];
     if constexpr (QuadS<NARROW, WD>::kStream) {
         // rows streamed in chunks of kChunk (pairs or neighbours)
-        constexpr int K = NARROW ? WD / 2 : WD;
+        const int K = NARROW ? (WD ? WD : P.wd) / 2 : (WD ? WD : P.wd);
         constexpr int kChunk = NARROW ? 4 : 8;
         const int row = P.n_pad * 4;
 #pragma unroll
@@ -1366,7 +1367,8 @@ static hipError_t persistent_t(const DevProblem &p, int64_t n_rounds, hipStream_
 }
 
 // Narrow ELL widths are even (neighbours go in pairs); wide widths are any
-// of 1..8, 12, 16.
+// of 1..8, then 12, 16, 24, .., 48 for both; wider rows (multiples of 8) take
+// the run-time-width instance WD = 0.
 #define TDPT_DISPATCH(FN, ...)                                              \
     if (p.narrow) {                                                         \
         switch (p.wd) {                                                     \
@@ -1380,7 +1382,9 @@ static hipError_t persistent_t(const DevProblem &p, int64_t n_rounds, hipStream_
         case 32: return FN<true, 32>(__VA_ARGS__);                          \
         case 40: return FN<true, 40>(__VA_ARGS__);                          \
         case 48: return FN<true, 48>(__VA_ARGS__);                          \
-        default: return hipErrorInvalidValue;                               \
+        default:                                                            \
+            if (p.wd > 48 && p.wd % 8 == 0) return FN<true, 0>(__VA_ARGS__);  \
+            return hipErrorInvalidValue;                                    \
         }                                                                   \
     }                                                                       \
     switch (p.wd) {                                                         \
@@ -1398,7 +1402,9 @@ static hipError_t persistent_t(const DevProblem &p, int64_t n_rounds, hipStream_
     case 32: return FN<false, 32>(__VA_ARGS__);                             \
     case 40: return FN<false, 40>(__VA_ARGS__);                             \
     case 48: return FN<false, 48>(__VA_ARGS__);                             \
-    default: return hipErrorInvalidValue;                                   \
+    default:                                                                \
+        if (p.wd > 48 && p.wd % 8 == 0) return FN<false, 0>(__VA_ARGS__);   \
+        return hipErrorInvalidValue;                                        \
     }
 
 hipError_t launch_sweep(const DevProblem &p, hipStream_t s) { TDPT_DISPATCH(round_sweep_t, p, s) }

@@ -45,12 +45,15 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 constexpr size_t kMaxTimedLaunches = 4096;
 
 // ELL widths the sweep kernels are instantiated for.
+// ELL width (neighbour slots per spin) for a largest problem degree: the
+// degree itself up to 8, then 12, then multiples of 8 up to kMaxWidth.
+constexpr int kMaxWidth = 256;
+
 int ell_width(int deg)
 {
     if (deg <= 8) return std::max(deg, 1);
     if (deg <= 12) return 12;
-    for (int w = 16; w <= 48; w += 8)
-        if (deg <= w) return w;
+    if (deg <= kMaxWidth) return (deg + 7) / 8 * 8;
     return -1;
 }
 
@@ -347,7 +350,7 @@ int lay_out(tdpt_instance *in, int32_t n, const int32_t *row_ptr, const int32_t 
     for (int32_t i = 0; i < n; ++i) maxdeg = std::max(maxdeg, row_ptr[i + 1] - row_ptr[i]);
     in->max_deg = maxdeg;
     in->wd = ell_width(maxdeg);
-    if (in->wd < 0) return fail(TDPT_E_INVALID, "a spin has more than 48 problem neighbours");
+    if (in->wd < 0) return fail(TDPT_E_INVALID, "a spin has more than 256 problem neighbours");
     const int32_t wd = in->wd;
     in->nb_idx.assign((size_t)wd * n_pad, n_pad);
     in->nb_J.assign((size_t)wd * n_pad, 0);

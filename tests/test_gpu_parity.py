@@ -155,6 +155,20 @@ def test_streamed_structure_rows(T, N, driver):
     assert P.query()["driver"] == int(driver)
 
 
+@pytest.mark.parametrize("N,driver", [(150, "0"), (200, "1")])
+def test_rows_wider_than_48(T, N, driver):
+    """Three copies per node at N = 150 and 200 (50 and 67 problem
+    neighbours per spin, ELL widths 56 and 72): the run-time-width sweep,
+    bit-exact against the oracle."""
+    from synth.configs import jcolumn_member
+    w = jcolumn_member(N, 20000)
+    assert T.Instance.from_synth(w.instance).info()["max_degree"] in (50, 67)
+    o, P = _with_env("TDPT_PERSISTENT", driver, lambda: both(
+        T, w.instance, w.beta[:4], w.p_q[:3], mcs=3, rounds=6, seed=5,
+        label=f"three copies N={N} driver {driver}"))
+    assert P.query()["driver"] == int(driver)
+
+
 def test_streamed_rows_wide_layout(T):
     """Couplings beyond int16 (32-bit structure) with 12+ neighbours."""
     rng = np.random.default_rng(21)
