@@ -298,7 +298,8 @@ def bench_serving(args):
         for r, gap in zip(reqs, gaps):
             t += gap / rate
             r.arrival = t
-        total = serve(reqs, chunk=args.chunk, budget_bytes=int(args.budget_gb * 2**30))
+        total = serve(reqs, chunk=args.chunk, budget_bytes=int(args.budget_gb * 2**30),
+                      max_work=args.max_work if args.max_work > 0 else None)
         per_rate[str(rate)] = s = summarize(reqs, total)
         print(f"[bench] rate {rate}/s: makespan {total:.2f} s, latency p50 {s.get('latency_p50_s')}",
               file=sys.stderr, flush=True)
@@ -308,7 +309,8 @@ def bench_serving(args):
            "higher_is_better": False, "n_gpus": 1,
            "data": "synthetic (seeded planted Wishart, Poisson arrivals)",
            "config": {"workload": f"serving, {args.count} requests, N<= {args.max_n}, "
-                                  f"cap {args.cap_sweeps} sweeps, budget {args.budget_gb} GiB",
+                                  f"cap {args.cap_sweeps} sweeps, budget {args.budget_gb} GiB"
+                                  + (f", running work <= {args.max_work}" if args.max_work > 0 else ""),
                       "sizes": [m.instance.N for m in members]},
            "serving": per_rate}
     print(json.dumps(out), flush=True)
@@ -517,6 +519,8 @@ def main():
     ap.add_argument("--rates", type=str, default="", help="comma-separated serving rates (overrides --rate)")
     ap.add_argument("--max-n", type=int, default=1024, help="largest logical size when serving")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving HBM budget")
+    ap.add_argument("--max-work", type=int, default=600_000_000,
+                    help="serving: cap on the running batch's replicas x spins (0: no cap)")
     ap.add_argument("--rho0", type=float, default=0.0,
                     help="target residual energy per logical spin (0: the planted ground state)")
     args = ap.parse_args()

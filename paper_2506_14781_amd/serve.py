@@ -123,9 +123,14 @@ def run_batched(requests, chunk: int, device="cuda"):
     return total
 
 
-def serve(requests, chunk: int, budget_bytes: int, max_members: int = 4096, device="cuda"):
+def serve(requests, chunk: int, budget_bytes: int, max_members: int = 4096, device="cuda",
+          max_work: int | None = None):
     """Continuous batching: requests (sorted by arrival) join the running
-    batch at round boundaries when their workspace fits the budget."""
+    batch at round boundaries when their workspace fits the budget and, if
+    max_work is given, while the spin updates per sweep of the running batch
+    (replicas x spins, summed) stay within it (a request is always admitted
+    into an empty batch).  Capping the running work lets requests finish in
+    arrival order instead of all sharing the GPU until the end."""
     import torch
     pending = sorted(requests, key=lambda r: r.arrival)
     for r in pending:
@@ -135,16 +140,23 @@ def serve(requests, chunk: int, budget_bytes: int, max_members: int = 4096, devi
     batch = T.Batch(max_members, device=device)
     active = []
     used = 0
+    work = 0
+
+    def work_of(r):
+        return r.cfg.replicas * r.instance.n
+
     base = time.perf_counter()
     while pending or active:
         now = time.perf_counter() - base
         changed = False
         while (pending and pending[0].arrival <= now and used + pending[0].footprint <= budget_bytes
-               and len(active) < max_members):
+               and len(active) < max_members
+               and (max_work is None or not active or work + work_of(pending[0]) <= max_work)):
             r = pending.pop(0)
             r.problem = T.Problem(r.instance, r.cfg, device=device)
             r.start = time.perf_counter() - base
             used += r.footprint
+            work += work_of(r)
             active.append(r)
             changed = True
         if not active:
@@ -165,6 +177,7 @@ def serve(requests, chunk: int, budget_bytes: int, max_members: int = 4096, devi
             if _done(r):
                 r.end = t1 - base
                 used -= r.footprint
+                work -= work_of(r)
                 r.problem.close()
                 r.problem = None
             else:
