@@ -92,9 +92,11 @@ def test_batch_equals_alone_and_oracle(T):
     assert np.array_equal(f, o["f"]) and np.array_equal(g, o["g"])
 
 
-def test_serving_results_equal_alone(T):
+@pytest.mark.parametrize("max_work", [None, 1])
+def test_serving_results_equal_alone(T, max_work):
     """Requests arriving over time, admitted under a memory budget, retired
-    at their caps: every request's final state is the one it reaches alone."""
+    at their caps: every request's final state is the one it reaches alone
+    (also with the running work capped so that requests run one at a time)."""
     from paper_2506_14781_amd.serve import Request, serve
     specs = _members()[:3]
     reqs, alone = [], []
@@ -119,7 +121,7 @@ def test_serving_results_equal_alone(T):
         orig_close(self)
     T.Problem.close = grab
     try:
-        serve(reqs, chunk=4, budget_bytes=budget)
+        serve(reqs, chunk=4, budget_bytes=budget, max_work=max_work)
     finally:
         T.Problem.close = orig_close
     for r, a in zip(reqs, alone):
