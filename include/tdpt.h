@@ -99,7 +99,7 @@ typedef struct tdpt_instance_info {
     int32_t n_colors;
     int32_t max_degree; /* problem neighbours per spin (ELL width) */
     int32_t max_copy_degree;
-    int32_t narrow;     /* 1 if indices and couplings fit 16 bits (packed layout) */
+    int32_t narrow;     /* 1 if problem indices and couplings fit 16 bits (packed layout; general-constraint rows stay 32-bit) */
     int64_t nnz;        /* directed problem couplings */
     int32_t m;          /* copy edges */
     int32_t n_terms;    /* general constraint terms (0 with copy edges) */

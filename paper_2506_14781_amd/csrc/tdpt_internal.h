@@ -14,6 +14,13 @@ constexpr int kRing = 8;          // rounds of partner mailboxes kept per positi
 constexpr int kBitSlots = 4;      // replicas per workgroup in the bit-packed layout
 constexpr int kBitsBlock = 768;   // threads of a bit-packed sweep workgroup, at most
 
+// Structure layouts of the byte-replica sweeps (their NARROW template
+// argument): 32-bit rows; packed 16-bit index and coupling pairs with copy
+// edges; packed problem rows with 32-bit general-constraint rows.
+constexpr int kWide = 0;
+constexpr int kPacked = 1;
+constexpr int kPackedGen = 2;
+
 // Header words of a problem's device state (int64 each).
 enum HdrWord {
     kHdrRounds = 0,    // swap rounds completed

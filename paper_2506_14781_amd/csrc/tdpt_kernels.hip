@@ -124,6 +124,10 @@ struct Rsrc {
 __device__ __forceinline__ Rsrc make_rsrc(const DevProblem &P)
 {
     Rsrc r;
+    // descriptors a layout does not use cover no bytes: a load through one
+    // returns zeros instead of touching memory
+    r.cw = rsrc(nullptr, 0);
+    r.kh = rsrc(nullptr, 0);
     if (P.bits) {
         const int bytes = P.wd * P.n_pad * 4;
         r.a = rsrc(P.nb_pos, bytes);
@@ -136,7 +140,13 @@ __device__ __forceinline__ Rsrc make_rsrc(const DevProblem &P)
         const int bytes = (P.wd / 2) * P.n_pad * 4;
         r.a = rsrc(P.nbi, bytes);
         r.b = rsrc(P.nbj, bytes);
-        r.ch = rsrc(P.chp, P.n_pad * 4);
+        if (P.gen) {
+            r.ch = rsrc(P.cn_idx, P.wcg * P.n_pad * 4);
+            r.cw = rsrc(P.cn_w, P.wcg * P.n_pad * 4);
+            r.kh = rsrc(P.kh, P.n_pad * 4);
+        } else {
+            r.ch = rsrc(P.chp, P.n_pad * 4);
+        }
     } else {
         const int bytes = P.wd * P.n_pad * 4;
         r.a = rsrc(P.nb_idx, bytes);
@@ -205,7 +215,7 @@ __device__ __forceinline__ SlotParams slot_params(const DevProblem &P, int pos, 
 // once; wider rows are streamed in chunks by quad_fields (kStream), which
 // keeps them out of spill territory.  WD = 0 stands for a width known only
 // at run time (P.wd, a multiple of 8 above 48), streamed the same way.
-template <bool NARROW, int WD>
+template <int NARROW, int WD>
 struct QuadS {
     static constexpr bool kStream = WD > 8 || WD == 0;
     static constexpr int K = kStream ? 1 : (NARROW ? WD / 2 : WD);
@@ -216,7 +226,7 @@ struct QuadS {
     int voff;    // byte offset of the quad in a structure row
 };
 
-template <bool NARROW, int WD>
+template <int NARROW, int WD>
 __device__ __forceinline__ void load_quad(const DevProblem &P, const Rsrc &Rs, int q, QuadS<NARROW, WD> &Q)
 {
     const int voff = q * 16;
@@ -229,9 +239,9 @@ __device__ __forceinline__ void load_quad(const DevProblem &P, const Rsrc &Rs, i
             Q.b[k] = bload(Rs.b, voff, k * row);
         }
     }
-    if constexpr (NARROW) {
+    if constexpr (NARROW == kPacked) {
         Q.c0 = bload(Rs.ch, voff, 0);
-    } else if (!P.gen) {
+    } else if (NARROW == kWide && !P.gen) {
         Q.c0 = bload(Rs.ch, voff, 0);
         Q.c1 = bload(Rs.ch, voff, row);
     }
@@ -278,7 +288,7 @@ __device__ __forceinline__ void quad_constraint_sum(const DevProblem &P, const R
 // copy neighbours, or the general-constraint sum).  NARROW
 // instances keep every field below 2^22, so the 16-bit dot products are
 // exact.
-template <bool NARROW, int WD>
+template <int NARROW, int WD>
 __device__ __forceinline__ void quad_fields(const DevProblem &P, const Rsrc &Rs, const lds8_t *s,
                                             const QuadS<NARROW, WD> &Q, int hp[4], int cs[4])
 {
@@ -330,7 +340,9 @@ __device__ __forceinline__ void quad_fields(const DevProblem &P, const Rsrc &Rs,
                         if (k0 + c < K) hp[j] += b[c][j] * (int)s[a[c][j]];
             }
         }
-        if constexpr (NARROW) {
+        if constexpr (NARROW == kPackedGen) {
+            quad_constraint_sum(P, Rs, s, Q.voff, cs);
+        } else if constexpr (NARROW == kPacked) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int c = Q.c0[j];
@@ -355,11 +367,13 @@ __device__ __forceinline__ void quad_fields(const DevProblem &P, const Rsrc &Rs,
                 lo[k2][j] = s[iw & 0xffff];
                 hi[k2][j] = s[(unsigned)iw >> 16];
             }
+        if constexpr (NARROW == kPacked) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int c = Q.c0[j];
-            ca[j] = s[c & 0xffff];
-            cb[j] = s[(unsigned)c >> 16];
+            for (int j = 0; j < 4; ++j) {
+                const int c = Q.c0[j];
+                ca[j] = s[c & 0xffff];
+                cb[j] = s[(unsigned)c >> 16];
+            }
         }
 #pragma unroll
         for (int k2 = 0; k2 < WD / 2; ++k2)
@@ -373,8 +387,12 @@ __device__ __forceinline__ void quad_fields(const DevProblem &P, const Rsrc &Rs,
                 jv.y = (short)((unsigned)jw >> 16);
                 hp[j] = __builtin_amdgcn_sdot2(jv, sv, hp[j], false);
             }
+        if constexpr (NARROW == kPackedGen) {
+            quad_constraint_sum(P, Rs, s, Q.voff, cs);
+        } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) cs[j] = (int)ca[j] + (int)cb[j];
+            for (int j = 0; j < 4; ++j) cs[j] = (int)ca[j] + (int)cb[j];
+        }
     } else {
 #pragma unroll
         for (int k = 0; k < WD; ++k)
@@ -396,7 +414,7 @@ __device__ __forceinline__ void quad_fields(const DevProblem &P, const Rsrc &Rs,
 // the energy changes.  dfa accumulates the change of f, dga half the change
 // of g (24-bit multiplies are exact for NARROW instances, whose fields and
 // energy changes stay below 2^22).
-template <bool NARROW>
+template <int NARROW>
 __device__ __forceinline__ void quad_update(const DevProblem &P, lds8_t *s, int q, const int hp[4], const int cs[4],
                                             uint32_t live_bytes, uint32_t t, const SlotParams &sp,
                                             int &dfa, int &dga)
@@ -457,7 +475,7 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v)
 // at_end() runs on every thread after its last quad, before the closing
 // barrier (the reduction's, which also ends the last class); on return the
 // spins are final for the whole block.
-template <bool NARROW, int WD, typename AtEnd>
+template <int NARROW, int WD, typename AtEnd>
 __device__ __forceinline__ void sweep_round(const DevProblem &P, const Rsrc &Rs, lds8_t *s,
                                             const SlotParams &sp, int64_t n_round, int64_t *red,
                                             AtEnd &&at_end)
@@ -512,7 +530,7 @@ __device__ __forceinline__ int64_t *lds_scratch(int8_t *lds, int stride)
 
 // --------------------------------------------------- one launch per round
 // One round of one slot: load its spins into LDS, mcs sweeps, store.
-template <bool NARROW, int WD>
+template <int NARROW, int WD>
 __device__ __forceinline__ void round_sweep_body(const DevProblem &P, int slot, int8_t *lds)
 {
     if (!replica_at_zero(lds)) {
@@ -534,7 +552,7 @@ __device__ __forceinline__ void round_sweep_body(const DevProblem &P, int slot, 
     copy_bytes16(P.states + (size_t)slot * P.stride, lds, P.stride);
 }
 
-template <bool NARROW, int WD>
+template <int NARROW, int WD>
 __global__ __launch_bounds__(kMaxBlock) void k_round_sweep(DevProblem P)
 {
     extern __shared__ __align__(16) int8_t lds[];
@@ -543,7 +561,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_round_sweep(DevProblem P)
 
 // Batched round: block b serves slot b - first_block[p] of member p, where
 // first_block is the prefix sum of the members' replica counts.
-template <bool NARROW, int WD>
+template <int NARROW, int WD>
 __global__ __launch_bounds__(kMaxBlock) void k_batch_sweep(const DevProblem *__restrict__ table,
                                                          const int *__restrict__ first_block, int count)
 {
@@ -748,7 +766,7 @@ __device__ __forceinline__ RoundPair round_pair(const DevProblem &P, int64_t n, 
 // reduces its energy change (a partner that finished earlier has posted by
 // then), and the pair's uniform and its logarithm are computed while that
 // read is in flight.
-template <bool NARROW, int WD>
+template <int NARROW, int WD>
 __device__ __forceinline__ void persistent_body(const DevProblem &P, int slot, int64_t n_rounds, int8_t *lds)
 {
     if (!replica_at_zero(lds)) {
@@ -860,7 +878,7 @@ __device__ __forceinline__ void persistent_body(const DevProblem &P, int slot, i
     }
 }
 
-template <bool NARROW, int WD>
+template <int NARROW, int WD>
 __global__ __launch_bounds__(kMaxBlock, 4) void k_persistent(DevProblem P, int64_t n_rounds)
 {
     extern __shared__ __align__(16) int8_t lds[];
@@ -884,7 +902,7 @@ __device__ __forceinline__ int member_of(const int *__restrict__ first_block, in
 // rounds of every member of a layout group, block b serving slot
 // b - first_block[m] of member m.  Each member's slots exchange through that
 // member's own mailboxes, so members never wait for one another.
-template <bool NARROW, int WD>
+template <int NARROW, int WD>
 __global__ __launch_bounds__(kMaxBlock, 4) void k_batch_persistent(const DevProblem *__restrict__ table,
                                                                  const int *__restrict__ first_block, int count,
                                                                  int64_t n_rounds)
@@ -1259,9 +1277,9 @@ __global__ __launch_bounds__(kSmallBlock) void k_energy(DevProblem P)
                 hp += (int64_t)(int16_t)(jb & 0xffff) * s[ia & 0xffff];
                 hp += (int64_t)(int16_t)(jb >> 16) * s[ia >> 16];
             }
-            const uint32_t c = P.chp[r];
-            ca = c & 0xffff;
-            cb = c >> 16;
+            const uint32_t c = P.gen ? 0u : P.chp[r];
+            ca = P.gen ? P.n_pad : (int)(c & 0xffff);
+            cb = P.gen ? P.n_pad : (int)(c >> 16);
         } else {
             for (int k = 0; k < P.wd; ++k)
                 hp += (int64_t)P.nb_J[(size_t)k * P.n_pad + r] * s[P.nb_idx[(size_t)k * P.n_pad + r]];
@@ -1324,7 +1342,7 @@ static hipError_t allow_lds(K kernel, size_t lds)
     return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <bool NARROW, int WD>
+template <int NARROW, int WD>
 static hipError_t round_sweep_t(const DevProblem &p, hipStream_t s)
 {
     const size_t lds = sweep_lds(p);
@@ -1334,7 +1352,7 @@ static hipError_t round_sweep_t(const DevProblem &p, hipStream_t s)
     return hipGetLastError();
 }
 
-template <bool NARROW, int WD>
+template <int NARROW, int WD>
 static hipError_t persistent_t(const DevProblem &p, int64_t n_rounds, hipStream_t s, bool query_only,
                                int *max_blocks)
 {
@@ -1368,8 +1386,18 @@ static hipError_t persistent_t(const DevProblem &p, int64_t n_rounds, hipStream_
 
 // Narrow ELL widths are even (neighbours go in pairs); wide widths are any
 // of 1..8, then 12, 16, 24, .., 48 for both; wider rows (multiples of 8) take
-// the run-time-width instance WD = 0.
+// the run-time-width instance WD = 0.  Packed general-constraint problems
+// (NARROW = kPackedGen) have widths 2..8.
 #define TDPT_DISPATCH(FN, ...)                                              \
+    if (p.narrow && p.gen) {                                                \
+        switch (p.wd) {                                                     \
+        case 2: return FN<kPackedGen, 2>(__VA_ARGS__);                      \
+        case 4: return FN<kPackedGen, 4>(__VA_ARGS__);                      \
+        case 6: return FN<kPackedGen, 6>(__VA_ARGS__);                      \
+        case 8: return FN<kPackedGen, 8>(__VA_ARGS__);                      \
+        default: return hipErrorInvalidValue;                               \
+        }                                                                   \
+    }                                                                       \
     if (p.narrow) {                                                         \
         switch (p.wd) {                                                     \
         case 2: return FN<true, 2>(__VA_ARGS__);                            \
@@ -1415,7 +1443,7 @@ hipError_t launch_swap(const DevProblem &p, hipStream_t s)
     return hipGetLastError();
 }
 
-template <bool NARROW, int WD>
+template <int NARROW, int WD>
 static hipError_t batch_sweep_t(const DevProblem &p, const DevProblem *table, const int *first_block,
                                 int count, int blocks, int block, size_t max_stride, hipStream_t s)
 {
@@ -1439,7 +1467,7 @@ static size_t bits_lds(int n_words)
     return (size_t)(n_words + 1) * 16 + 8 * 2 * kBitSlots * (kMaxBlock / 64) + 16;
 }
 
-template <bool NARROW, int WD>
+template <int NARROW, int WD>
 static hipError_t sweep_bits_t(const DevProblem &p, hipStream_t s)
 {
     const size_t lds = bits_lds(p.n_words);
@@ -1450,7 +1478,7 @@ static hipError_t sweep_bits_t(const DevProblem &p, hipStream_t s)
     return hipGetLastError();
 }
 
-template <bool NARROW, int WD>
+template <int NARROW, int WD>
 static hipError_t batch_sweep_bits_t(const DevProblem &p, const DevProblem *table, const int *first_block,
                                      int count, int blocks, int block, int max_words, hipStream_t s)
 {
@@ -1521,7 +1549,7 @@ size_t persistent_lds_bytes(int stride, int I, int J)
     return persistent_lds(q);
 }
 
-template <bool NARROW, int WD>
+template <int NARROW, int WD>
 static hipError_t batch_persistent_t(const DevProblem &p, const DevProblem *table, const int *first_block,
                                      int count, int blocks, int block, size_t lds, int64_t n_rounds, hipStream_t s,
                                      int *max_blocks)

@@ -146,11 +146,14 @@ bool use_bits(const tdpt_instance *in)
 
 // The packed structure (16-bit indices and coupling pairs) and the 16/24-bit
 // arithmetic of the sweep need indices and couplings that fit 16 bits and
-// every local field, penalty term and energy change below 2^22.
+// every local field, penalty term and energy change below 2^22.  General
+// constraints keep their rows 32-bit in either layout (packed only up to 8
+// problem neighbours).
 bool use_narrow(const tdpt_instance *in, const tdpt_run_cfg *cfg)
 {
     const int64_t pmax = cfg->p_q[cfg->n_p - 1];
-    return !in->gen && !use_bits(in) && in->narrow && in->max_field + 4 * pmax < ((int64_t)1 << 22);
+    return !use_bits(in) && in->narrow && (!in->gen || in->wd <= 8) &&
+           in->max_field + 2 * pmax * in->max_cfield < ((int64_t)1 << 22);
 }
 
 Layout make_layout(const tdpt_instance *in, int32_t I, int32_t J, int64_t trace_cap, bool narrow)
@@ -191,8 +194,16 @@ Layout make_layout(const tdpt_instance *in, int32_t I, int32_t J, int64_t trace_
         const size_t rows = (size_t)(L.wd / 2) * in->n_pad * 4;
         L.nbi = take(rows);
         L.nbj = take(rows);
-        L.chp = take((size_t)in->n_pad * 4);
         L.nb_idx = L.nb_J = L.ch_idx = 0;
+        if (in->gen) {
+            const size_t cell = (size_t)in->wcg * in->n_pad * 4;
+            L.cn_idx = take(cell);
+            L.cn_w = take(cell);
+            L.kh = take((size_t)in->n_pad * 4);
+            L.chp = 0;
+        } else {
+            L.chp = take((size_t)in->n_pad * 4);
+        }
     } else {
         const size_t ell = (size_t)L.wd * in->n_pad * 4;
         L.nb_idx = take(ell);
@@ -562,7 +573,6 @@ int tdpt_instance_create_terms(int32_t n, const int32_t *row_ptr, const int32_t 
     }
     const int32_t n_pad = in->n_pad;
     in->gen = 1;
-    in->narrow = 0;
     in->n_terms = n_terms;
     in->max_cons_deg = wcg;
     in->wcg = std::max(4, (wcg + 3) / 4 * 4);
@@ -711,7 +721,7 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     for (int c = 0; c < in->n_colors; ++c) d.cls_live[c] = in->cls_live[c];
     d.nbi = narrow ? (const uint32_t *)(ws + L.nbi) : nullptr;
     d.nbj = narrow ? (const uint32_t *)(ws + L.nbj) : nullptr;
-    d.chp = narrow ? (const uint32_t *)(ws + L.chp) : nullptr;
+    d.chp = (narrow && !in->gen) ? (const uint32_t *)(ws + L.chp) : nullptr;
     d.nb_idx = narrow ? nullptr : (const int32_t *)(ws + L.nb_idx);
     d.nb_J = narrow ? nullptr : (const int32_t *)(ws + L.nb_J);
     d.ch_idx = (narrow || in->gen) ? nullptr : (const int32_t *)(ws + L.ch_idx);
@@ -783,10 +793,16 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
             }
         UP(ws + L.nbi, A.data(), A.size() * 4);
         UP(ws + L.nbj, B.data(), B.size() * 4);
-        std::vector<uint32_t> ch((size_t)n_pad);
-        for (int32_t r = 0; r < n_pad; ++r)
-            ch[r] = ((uint32_t)in->ch_idx[r] & 0xffffu) | ((uint32_t)in->ch_idx[(size_t)n_pad + r] << 16);
-        UP(ws + L.chp, ch.data(), ch.size() * 4);
+        if (in->gen) {
+            UP(ws + L.cn_idx, in->cn_idx.data(), in->cn_idx.size() * 4);
+            UP(ws + L.cn_w, in->cn_w.data(), in->cn_w.size() * 4);
+            UP(ws + L.kh, in->kh.data(), in->kh.size() * 4);
+        } else {
+            std::vector<uint32_t> ch((size_t)n_pad);
+            for (int32_t r = 0; r < n_pad; ++r)
+                ch[r] = ((uint32_t)in->ch_idx[r] & 0xffffu) | ((uint32_t)in->ch_idx[(size_t)n_pad + r] << 16);
+            UP(ws + L.chp, ch.data(), ch.size() * 4);
+        }
     } else {
         UP(ws + L.nb_idx, in->nb_idx.data(), in->nb_idx.size() * 4);
         UP(ws + L.nb_J, in->nb_J.data(), in->nb_J.size() * 4);
@@ -1429,10 +1445,14 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
     }
     for (auto *p : m) HIP_TRY(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
     HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
-    // group by structure layout (kernel instance), largest replicas first
-    std::stable_sort(m.begin(), m.end(), [](const tdpt_problem *x, const tdpt_problem *y) {
+    // group by structure layout (kernel instance: the packed layout has
+    // separate instances for copy edges and general constraints), largest
+    // replicas first
+    auto packed_gen = [](const tdpt_problem *x) { return x->dp.narrow && x->dp.gen; };
+    std::stable_sort(m.begin(), m.end(), [&](const tdpt_problem *x, const tdpt_problem *y) {
         if (x->dp.bits != y->dp.bits) return x->dp.bits < y->dp.bits;
         if (x->dp.narrow != y->dp.narrow) return x->dp.narrow > y->dp.narrow;
+        if (packed_gen(x) != packed_gen(y)) return packed_gen(x) < packed_gen(y);
         if (x->dp.wd != y->dp.wd) return x->dp.wd < y->dp.wd;
         return x->dp.stride > y->dp.stride;
     });
@@ -1444,7 +1464,8 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
     for (size_t i = 0; i < m.size(); ++i) {
         table[i] = m[i]->dp;
         const bool start = b->groups.empty() || m[i]->dp.bits != m[i - 1]->dp.bits ||
-                           m[i]->dp.narrow != m[i - 1]->dp.narrow || m[i]->dp.wd != m[i - 1]->dp.wd;
+                           m[i]->dp.narrow != m[i - 1]->dp.narrow || m[i]->dp.wd != m[i - 1]->dp.wd ||
+                           packed_gen(m[i]) != packed_gen(m[i - 1]);
         if (start) {
             tdpt_batch::Group g{(int)i, 0, 0, (int)prefix.size(), 0, 0, 0, 64, 0};
             b->groups.push_back(g);

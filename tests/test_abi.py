@@ -138,7 +138,9 @@ def test_terms_instance_info():
     pc = planted_coloring(50, 4, degree=5, seed=0)
     info = T.Instance.from_synth(pc.instance).info()
     assert info["n"] == 200 and info["n_terms"] == 50 and info["m"] == 0
-    assert info["max_constraint_degree"] == 3 and info["narrow"] == 0
+    # problem rows (colouring edges, J = -1024) fit the packed layout;
+    # constraint rows stay 32-bit in either layout
+    assert info["max_constraint_degree"] == 3 and info["narrow"] == 1
 
 
 def test_terms_rejects_malformed_terms():
