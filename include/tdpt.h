@@ -153,9 +153,11 @@ int tdpt_instance_create(int32_t n, const int32_t *row_ptr, const int32_t *col,
  *   term_coef   integer coefficient of each entry, term_const [n_terms]
  *   color       must be proper over the couplings and over every pair of
  *               spins whose expanded weight -sum_t a_ti a_tj is nonzero
- * Other arguments as tdpt_instance_create.  Such instances always use the
- * int8 layout with 32-bit structure (no bit-packed replicas), so one replica
- * must fit the LDS of a workgroup.  Returns TDPT_E_INVALID for malformed
+ * Other arguments as tdpt_instance_create.  Such instances always use int8
+ * replicas (no bit-packed replicas), so one replica must fit the LDS of a
+ * workgroup; their constraint rows are 32-bit, their problem rows packed as
+ * 16-bit pairs when indices and couplings allow it and the spin has at most
+ * 8 problem neighbours.  Returns TDPT_E_INVALID for malformed
  * terms or a spin that shares terms with more than 1024 others, and
  * TDPT_E_RANGE if an expanded weight exceeds int32 or g could reach 2^62.
  * tdpt_problem_create bounds |h| by sum |J_q| + |b_q| + 2 P_q max_i |c_i|
