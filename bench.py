@@ -53,13 +53,13 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # kernel source with this hash.
 MEASURED_TRAFFIC = {
     # one 200-round launch on the N=200 workload: FETCH 17,077.9 KiB, WRITE 11,957.0 KiB
-    "wishart-N200-D8-32x16": {"kernel": "k_persistent", "kernel_sha256": "ecde8dbbf5326712",
+    "wishart-N200-D8-32x16": {"kernel": "k_persistent", "kernel_sha256": "20540c1d83ce3149",
                               "bytes_per_round": 236098},
     # one 50-sweep round on the N=1000 workload: FETCH 5,329,078.9 KiB, WRITE 513,511.5 KiB
-    "wishart-N1000-D6-64x32": {"kernel": "k_round_sweep_bits", "kernel_sha256": "ecde8dbbf5326712",
+    "wishart-N1000-D6-64x32": {"kernel": "k_round_sweep_bits", "kernel_sha256": "20540c1d83ce3149",
                                "bytes_per_round": 11439789296},
     # one 10-round launch on the colouring workload: FETCH 8,980.2 KiB, WRITE 17,799.8 KiB
-    "coloring-V4000-k4-d6-32x16": {"kernel": "k_persistent", "kernel_sha256": "ecde8dbbf5326712",
+    "coloring-V4000-k4-d6-32x16": {"kernel": "k_persistent", "kernel_sha256": "20540c1d83ce3149",
                                    "bytes_per_round": 3661856},
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_2506_14781_amd", "csrc", "tdpt_kernels.hip")

@@ -215,6 +215,9 @@ __device__ __forceinline__ SlotParams slot_params(const DevProblem &P, int pos, 
 // once; wider rows are streamed in chunks by quad_fields (kStream), which
 // keeps them out of spill territory.  WD = 0 stands for a width known only
 // at run time (P.wd, a multiple of 8 above 48), streamed the same way.
+// NARROW, here and in the sweep templates below, is the structure layout:
+// kWide (0), kPacked (1) or kPackedGen (2); nonzero means packed problem
+// rows.
 template <int NARROW, int WD>
 struct QuadS {
     static constexpr bool kStream = WD > 8 || WD == 0;
