@@ -235,10 +235,17 @@ def bench_tts(args):
     import copy
     import math
 
+    import dataclasses
+
     import paper_2506_14781_amd as T
     from paper_2506_14781_amd.serve import run_batched, run_plain, summarize
-    from synth.configs import wishart_small
-    members = [wishart_small(seed=k) for k in range(args.count)]
+    from synth.configs import jcolumn_member, wishart_small
+    if args.tts_n == 12:
+        members = [wishart_small(seed=k) for k in range(args.count)]
+    else:
+        # one three-copy instance of the J-column family (16 x 8 grid), many run seeds
+        w = jcolumn_member(args.tts_n, 20000)
+        members = [dataclasses.replace(w, seed=k, sweeps=args.cap_sweeps) for k in range(args.count)]
     reqs_b = _requests(T, members, args.cap_sweeps, 0.0)
     reqs_p = [copy.copy(r) for r in reqs_b]
     print(f"[bench] tts: {len(members)} seeds of {members[0].name}, cap {args.cap_sweeps} sweeps",
@@ -266,7 +273,7 @@ def bench_tts(args):
         tts99 = sb["sweeps_to_hit_p99"]
     out = {"metric": "time-to-planted-GS p50 (batched)", "value": sb["tts_p50_s"], "unit": "s",
            "higher_is_better": False, "n_gpus": 1,
-           "data": "synthetic (seeded planted Wishart N=12, copy-chain sparsified)",
+           "data": f"synthetic (seeded planted Wishart N={args.tts_n}, copy-chain sparsified)",
            "config": {"workload": f"{members[0].name}, {len(members)} run seeds, cap {args.cap_sweeps} sweeps"},
            "sweeps_tts99": tts99, "batched": sb, "plain": sp}
     print(json.dumps(out), flush=True)
@@ -518,6 +525,8 @@ def main():
     ap.add_argument("--rate", type=float, default=50.0, help="serving arrivals per second")
     ap.add_argument("--rates", type=str, default="", help="comma-separated serving rates (overrides --rate)")
     ap.add_argument("--max-n", type=int, default=1024, help="largest logical size when serving")
+    ap.add_argument("--tts-n", type=int, default=12,
+                    help="tts: 12 = the N=12 workload, else one three-copy instance of that size")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving HBM budget")
     ap.add_argument("--max-work", type=int, default=600_000_000,
                     help="serving: cap on the running batch's replicas x spins (0: no cap)")
