@@ -317,6 +317,11 @@ def bench_serving(args):
         total = serve(reqs, chunk=args.chunk, budget_bytes=int(args.budget_gb * 2**30),
                       max_work=args.max_work if args.max_work > 0 else None)
         per_rate[str(rate)] = s = summarize(reqs, total)
+        # whole-job ALU fraction by the per-update model (wall clock, idle
+        # time between arrivals included)
+        ops = sum(r.rounds_done * r.cfg.mcs_per_swap * r.cfg.replicas * r.instance.n *
+                  alu_ops_per_update(r.instance.info()) for r in reqs)
+        s["alu_frac_whole_job"] = round(ops / total / PEAK_LANE_OPS, 4)
         print(f"[bench] rate {rate}/s: makespan {total:.2f} s, latency p50 {s.get('latency_p50_s')}",
               file=sys.stderr, flush=True)
     tgt = "planted-GS" if args.rho0 == 0 else f"rho_E<={args.rho0}"
