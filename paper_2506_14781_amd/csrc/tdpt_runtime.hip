@@ -153,7 +153,7 @@ bool use_narrow(const tdpt_instance *in, const tdpt_run_cfg *cfg)
 {
     const int64_t pmax = cfg->p_q[cfg->n_p - 1];
     return !use_bits(in) && in->narrow && (!in->gen || in->wd <= 8) &&
-           in->max_field + 2 * pmax * in->max_cfield < ((int64_t)1 << 22);
+           in->max_field + 2 * pmax * in->max_cfield < ((int64_t)1 << 22) && in->max_cfield < ((int64_t)1 << 22);
 }
 
 Layout make_layout(const tdpt_instance *in, int32_t I, int32_t J, int64_t trace_cap, bool narrow)
@@ -651,11 +651,14 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     const bool bits = use_bits(in);
     const int64_t blk = bits ? std::min(sweep_block(in, false), tdpt::kBitsBlock)
                              : std::min(sweep_block(in, false), sweep_block(in, true));
+    // a lane's per-phase sums: of 2 |h| (f) and of 2 |c| (g) per spin, c the
+    // half penalty field, which P = 0 leaves out of hmax
+    const int64_t hb = std::max(hmax, in->max_cfield);
     const int64_t quads_per_thread = (in->max_class_quads + blk - 1) / blk;
-    if (quads_per_thread * 4 * 2 * hmax >= ((int64_t)1 << 31))
+    if (quads_per_thread * 4 * 2 * hb >= ((int64_t)1 << 31))
         return fail(TDPT_E_RANGE, "per-phase energy change can reach 2^31");
     // smallest workgroup (multiple of 64) keeping every lane's per-phase sums below 2^31
-    const int64_t q_allowed = std::max<int64_t>(1, (((int64_t)1 << 31) - 1) / (8 * std::max<int64_t>(hmax, 1)));
+    const int64_t q_allowed = std::max<int64_t>(1, (((int64_t)1 << 31) - 1) / (8 * std::max<int64_t>(hb, 1)));
     const int64_t min_block_q = (in->max_class_quads + q_allowed - 1) / q_allowed;
     const int32_t min_block = (int32_t)std::max<int64_t>(64, (min_block_q + 63) / 64 * 64);
     if (in->g_bound > 0 && pmax > (((int64_t)1 << 51) / in->g_bound))

@@ -166,3 +166,21 @@ def test_degenerate_constraints(T):
                        np.array([3], np.int32))
     o, P = both(T, const, beta, p_q, mcs=2, rounds=24, seed=3, label="constant term")
     assert np.all(o["g"] == 9) and P.query()["best_f_q"] == 2**63 - 1
+
+
+def test_large_constraint_field_without_penalty(T):
+    """A term with coefficients of 5000 (pair weights of 2.5e7, above the
+    packed layout's 24-bit products) on a ladder whose penalties are all 0:
+    g does not steer the sampling but is still tracked exactly, so the
+    library must keep such a problem off the packed layout and bound each
+    lane's per-phase g sums by the constraint field."""
+    from synth.constrained import with_terms
+    base = slack_knapsack(5, seed=2)
+    n = base.n
+    idx = np.arange(n, dtype=np.int32)
+    coef = np.full(n, 5000, np.int32)
+    inst = with_terms(base, np.array([0, n], np.int32), idx, coef, np.array([7], np.int32))
+    assert T.Instance.from_synth(inst).info()["narrow"] == 1  # problem rows would fit
+    o, P = both(T, inst, np.array([0.05, 0.2]), np.array([0, 0], np.int32), mcs=3, rounds=12, seed=6,
+                label="large constraint field, P = 0")
+    assert np.abs(o["g"]).max() > (1 << 23)
