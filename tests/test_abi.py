@@ -192,3 +192,16 @@ def test_terms_workspace_and_range_checks():
     inst = T.Instance.from_synth(slack_knapsack(5, seed=2))
     cfg = T.RunConfig([0.5, 1.0], [0, 4096], mcs_per_swap=1, seed=0)
     assert T.workspace_bytes(inst, cfg) > 0
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built library every entry point raises instead of
+    falling back to anything else."""
+    import paper_2506_14781_amd.tdpt as TD
+    monkeypatch.setattr(TD, "_lib", None)
+    monkeypatch.setattr(TD, "LIB_PATH", str(tmp_path / "libtdpt.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        TD.load_library()
+    from synth.configs import wishart_small
+    with pytest.raises(RuntimeError, match="missing"):
+        TD.Instance.from_synth(wishart_small().instance)
