@@ -14,10 +14,13 @@ spins), a 64 x 32 grid, 50 sweeps per swap round; one step is 4 rounds
 (200 sweeps), 5 steps by default (1000 sweeps, 5.1e11 spin updates).
 
 Other workloads (one JSON line each, not spin-update throughput): batched
-(64 planted Wishart instances, batched vs plain time to target), tts (the
-N=12 workload over many run seeds: time to the planted ground state), serving
-(Poisson arrivals, continuous batching), jcolumn (2D-PT vs J-column PT), kl
-(the Fig. 2 sampling experiment), copy (counter calibration).
+(64 planted Wishart instances, batched vs plain time to target, with the
+whole job's ALU fraction), tts (the N=12 workload, or with --tts-n one
+three-copy instance of another size, over many run seeds: time to the
+planted ground state), serving (Poisson arrivals, continuous batching under
+an HBM budget and a cap on the running work), jcolumn (2D-PT vs J-column PT,
+optionally to a residual target --rho0), kl (the Fig. 2 sampling
+experiment), copy (counter calibration).
 
 coloring: general constraints -- planted 4-colouring of a 4000-node graph
 (degree <= 6) in one-hot form (16,000 spins, 4000 one-hot terms), a 32 x 16
@@ -27,7 +30,8 @@ Before the warm-up the library's autotuner picks the driver and workgroup
 size on the problem itself (state restored afterwards; not timed).
 
 Prints one JSON line.  `value` is spin-updates/s over the timed steps with
-the problem already resident in HBM.
+the problem already resident in HBM; `target` follows the run's progress
+toward the planted ground state (or colouring).
 """
 from __future__ import annotations
 
