@@ -58,7 +58,7 @@ class _World:
                 world.live.remove(self)
 
         class Batch:
-            def __init__(self, cap, device="cuda"):
+            def __init__(self, cap, device="cuda", stream=None):
                 self.members = []
 
             def set_members(self, probs):
@@ -82,6 +82,7 @@ class _World:
 def world(monkeypatch):
     import torch
     monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
+    monkeypatch.setattr(torch.cuda, "Stream", lambda *a, **k: None)
     w = _World()
     monkeypatch.setattr(S, "T", w.module())
     return w
@@ -154,3 +155,13 @@ def test_summary_counts_hits_and_updates():
     assert s["hit_fraction"] == 0.5 and s["tts_p50_s"] == 0.5
     assert s["spin_updates"] == (3 + 4) * 1 * 2 * 10
     assert np.isclose(s["spin_updates_per_s"], s["spin_updates"] / 2.0)
+
+
+def test_late_arrival_runs_exactly_its_cap(world):
+    """A request that arrives while others run is set up (possibly during a
+    chunk) and joins at a round boundary: it runs exactly its own rounds."""
+    reqs = [_req("first", 100, 2, rounds=6), _req("late", 100, 2, rounds=2, arrival=0.02)]
+    S.serve(reqs, chunk=2, budget_bytes=10 ** 9)
+    assert [r.rounds_done for r in reqs] == [6, 2]
+    assert reqs[1].start >= reqs[1].arrival
+    assert not world.live
