@@ -70,3 +70,124 @@ def test_rows_stop_at_sigma_min_and_columns_grow_until_feasible():
     assert len(beta) == 6 and np.all(np.diff(beta) > 0)
     assert 2 <= len(P) <= 6 and np.all(np.diff(P) > 0)
     assert k == 6 + 6 * (len(P) - 1)
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2's recurrences against values worked out by hand.
+#
+# The population statistics are scripted (a table in draw order), so every
+# step of the algorithm is visible: the beta step beta + alpha_beta / sigma_E,
+# the penalty proposal P + alpha_P / (beta sigma_g) made with the row's beta
+# before its step, the column medians of the proposals, the sigma_E <=
+# sigma_min stop of the first column only, the mean_g < 0.5 stop of later
+# columns (read at the coldest row), and the final row-by-row median over the
+# columns.  Parameters: beta_0 = 0.5, P_0 = 0.25, I = 4, J = 3,
+# sigma_min = 0.5, alpha_beta = 1.5, alpha_P = 3.
+#
+# First column (P = 0.25):
+#   row 1, beta 0.5:   sigma_E 2,    sigma_g 4   -> beta 0.5 + 1.5/2 = 1.25,
+#                                                   P 0.25 + 3/(0.5*4) = 1.75
+#   row 2, beta 1.25:  sigma_E 1.5,  sigma_g 2   -> beta 2.25, P 0.25 + 3/2.5 = 1.45
+#   row 3, beta 2.25:  sigma_E 0.75, sigma_g 1   -> beta 4.25, P 0.25 + 3/2.25 = 1.583333...
+#   row 4, beta 4.25:  sigma_E 0.4 <= sigma_min  -> stop; I = 4 rows
+#   P(2) = median(1.75, 1.45, 1.58333) = 1.583333...
+# Second column (P = 1.583333, beta ladder rebuilt from 0.5, no sigma_min test):
+#   beta 0.5   -> 0.5 + 1.5/4 = 0.875;   P(2) + 3/(0.5*2)   = P(2) + 3
+#   beta 0.875 -> 0.875 + 1.5/3 = 1.375;  P(2) + 3/(0.875*1.5) = P(2) + 2.285714...
+#   beta 1.375 -> 1.375 + 1.5/1 = 2.875;  P(2) + 3/(1.375*0.8) = P(2) + 2.727272...
+#   beta 2.875 -> 2.875 + 1.5/0.5 = 5.875; P(2) + 3/(2.875*0.6) = P(2) + 1.739130...
+#   mean_g of the coldest row 1.0 >= 0.5, so P(3) = P(2) + median(3, 2.2857, 2.7273, 1.7391)
+#                                               = P(2) + (2.285714 + 2.727273) / 2 = 4.089827...
+# Third column (P = 4.089827): ladder 0.5 -> 1.25 -> 1.85 -> 3.1 -> 4.766..., coldest
+#   mean_g 0.25 < 0.5: stop (J = 3 would stop here anyway).
+# Final beta, row-wise medians over the three columns:
+#   median(0.5, 0.5, 0.5) = 0.5; median(1.25, 0.875, 1.25) = 1.25;
+#   median(2.25, 1.375, 1.85) = 1.85; median(4.25, 2.875, 3.1) = 3.1
+# Penalties in Q12 (round half away from zero): 0.25 -> 1024, 1.583333 -> 6485,
+# 4.089827 -> 16752.
+SCRIPT = [
+    # (beta expected, P expected, sigma_E, sigma_g, mean_g)
+    (0.5, 0.25, 2.0, 4.0, 9.0),
+    (1.25, 0.25, 1.5, 2.0, 7.0),
+    (2.25, 0.25, 0.75, 1.0, 5.0),
+    (4.25, 0.25, 0.4, 0.5, 3.0),
+    (0.5, 1.5833333333333333, 4.0, 2.0, 6.0),
+    (0.875, 1.5833333333333333, 3.0, 1.5, 4.0),
+    (1.375, 1.5833333333333333, 1.0, 0.8, 2.0),
+    (2.875, 1.5833333333333333, 0.5, 0.6, 1.0),
+    (0.5, 4.0898268398268398, 2.0, 1.0, 3.0),
+    (1.25, 4.0898268398268398, 2.5, 1.0, 2.0),
+    (1.85, 4.0898268398268398, 1.2, 1.0, 1.0),
+    (3.1, 4.0898268398268398, 0.9, 0.5, 0.25),
+]
+EXPECT_BETA = [0.5, 1.25, 1.85, 3.1]
+EXPECT_P_Q = [1024, 6485, 16752]
+ARGS = dict(beta0=0.5, P0=0.25, I=4, J=3, sigma_min=0.5, alpha_beta=1.5, alpha_P=3.0)
+
+
+class _Scripted:
+    """Population statistics from SCRIPT in draw order; checks that each
+    population is asked for at the (beta, P) worked out above."""
+
+    def __init__(self, script):
+        self.script = list(script)
+        self.k = 0
+
+    def __call__(self, beta, P):
+        assert self.k < len(self.script), "more populations than the worked example"
+        b, p, se, sg, mg = self.script[self.k]
+        assert beta == pytest.approx(b, rel=1e-12, abs=1e-12), f"population {self.k}: beta"
+        assert P == pytest.approx(p, rel=1e-12, abs=1e-12), f"population {self.k}: P"
+        self.k += 1
+        return se, sg, mg
+
+
+def test_oracle_algorithm_2_worked_example(monkeypatch):
+    s = _Scripted(SCRIPT)
+    monkeypatch.setattr(OA, "population", lambda inst, beta, P, N_chain, MCS, seed: s(beta, P))
+    beta, p_q, k = OA.adaptive_schedule(None, N_chain=8, MCS=1, seed=0, **ARGS)
+    assert k == len(SCRIPT) and s.k == len(SCRIPT)
+    assert np.allclose(beta, EXPECT_BETA, rtol=1e-12, atol=0)
+    assert p_q.tolist() == EXPECT_P_Q
+
+
+def test_library_algorithm_2_worked_example(monkeypatch):
+    """The library's host loop (which samples on the GPU) takes the same steps:
+    its sampler is replaced by the script, so this runs on the CPU."""
+    from paper_2506_14781_amd import adaptive as LA
+    s = _Scripted(SCRIPT)
+    monkeypatch.setattr(LA._Sampler, "stats", lambda self, beta, p: (self.__setattr__("count", self.count + 1),
+                                                                    s(beta, p))[1])
+    sch = LA.adaptive_schedule(None, beta0=0.5, p0=0.25, i_max=4, j_max=3, sigma_min=0.5,
+                               alpha_beta=1.5, alpha_p=3.0, n_chain=8, mcs=1, seed=0, device="cpu")
+    assert sch.populations == len(SCRIPT) and s.k == len(SCRIPT)
+    assert np.allclose(sch.beta, EXPECT_BETA, rtol=1e-12, atol=0)
+    assert sch.p_q.tolist() == EXPECT_P_Q
+
+
+@pytest.mark.parametrize("which", ["oracle", "library"])
+def test_algorithm_2_column_cap_and_first_column_stop(monkeypatch, which):
+    """J = 2 stops after the second column even though its coldest row is
+    still infeasible (mean_g >= 0.5); a first-column row with sigma_E equal to
+    sigma_min ends the rows (the test is sigma_E > sigma_min)."""
+    script = [
+        (0.5, 0.0, 1.0, 2.0, 9.0),      # beta 0.5 + 1/1 = 1.5; P 0 + 1/(0.5*2) = 1
+        (1.5, 0.0, 0.5, 1.0, 9.0),      # sigma_E == sigma_min: stop, 2 rows
+        (0.5, 1.0, 2.0, 1.0, 5.0),      # column 2 at P = median(1) = 1: beta 1.0
+        (1.0, 1.0, 4.0, 1.0, 3.0),      # beta 1.25; coldest mean_g 3 >= 0.5 but J = 2
+    ]
+    s = _Scripted(script)
+    if which == "oracle":
+        monkeypatch.setattr(OA, "population", lambda inst, beta, P, N_chain, MCS, seed: s(beta, P))
+        beta, p_q, k = OA.adaptive_schedule(None, 0.5, 0.0, 5, 2, 0.5, 1.0, 1.0, 8, 1, 0)
+    else:
+        from paper_2506_14781_amd import adaptive as LA
+        monkeypatch.setattr(LA._Sampler, "stats",
+                            lambda self, beta, p: (self.__setattr__("count", self.count + 1), s(beta, p))[1])
+        sch = LA.adaptive_schedule(None, beta0=0.5, p0=0.0, i_max=5, j_max=2, sigma_min=0.5,
+                                   alpha_beta=1.0, alpha_p=1.0, n_chain=8, mcs=1, seed=0, device="cpu")
+        beta, p_q, k = sch.beta, sch.p_q, sch.populations
+    assert s.k == 4 and k == 4
+    # rows: median(0.5, 0.5) = 0.5, median(1.5, 1.0) = 1.25
+    assert np.allclose(beta, [0.5, 1.25], rtol=1e-12, atol=0)
+    assert p_q.tolist() == [0, 4096]
