@@ -1,17 +1,22 @@
 #!/usr/bin/env python3
-"""Spin-update throughput of 2D parallel tempering on one MI355X.
+"""Spin-update throughput and time to the planted ground state of
+two-dimensional parallel tempering on one MI355X.
 
-Default workload (n200): planted Wishart N=200 (alpha 0.8) sparsified with
-copy chains to degree 8 (6800 physical spins), a 32 x 16 replica grid (beta
-geometric 0.05..10, P linear 0..8), a swap round after every sweep.  One
-step is `--rounds-per-step` swap rounds (default 1000 sweeps of all 512
-replicas, each followed by the f/g reduction, the swap step and
-bottom-right tracking).  The default 100 steps are the workload's full 1e5
-sweeps.
+Default workload (n1000): planted Wishart N=1000 (alpha 0.6) sparsified with
+copy chains to degree 6 (250,000 physical spins), a 64 x 32 replica grid
+(beta geometric 0.02..12, P linear 0..10), 50 sweeps per swap round,
+bit-packed replicas.  One step is 4 rounds (200 sweeps of all 2048
+replicas, each round followed by the f/g reduction, the swap step and
+bottom-right tracking); 10 steps by default (2000 sweeps, 1.0e12 spin
+updates).  The same line then carries the metric's second half: the N=12
+workload (8 x 4 grid) over --tts-seeds run seeds with a --tts-cap sweep
+cap, every run in one batch and then one after another (the plain form),
+each until it reaches the planted ground state -- success fraction and p50 /
+p99 time to hit per mode (N=1000 does not reach its planted ground state
+within any cap this job can afford).
 
-n1000: planted Wishart N=1000 (alpha 0.6), degree 6 (250,000 physical
-spins), a 64 x 32 grid, 50 sweeps per swap round; one step is 4 rounds
-(200 sweeps), 5 steps by default (1000 sweeps, 5.1e11 spin updates).
+n200: planted Wishart N=200 (alpha 0.8), degree 8 (6800 physical spins), a
+32 x 16 grid, a swap round after every sweep; one step is 1000 rounds.
 
 Other workloads (one JSON line each, not spin-update throughput): batched
 (64 planted Wishart instances, batched vs plain time to target, with the
@@ -30,8 +35,12 @@ Before the warm-up the library's autotuner picks the driver and workgroup
 size on the problem itself (state restored afterwards; not timed).
 
 Prints one JSON line.  `value` is spin-updates/s over the timed steps with
-the problem already resident in HBM; `target` follows the run's progress
-toward the planted ground state (or colouring).
+the problem already resident in HBM; `roofline` relates the dominant
+kernel's event-timed launches to the ALU roof (and states the byte model);
+`cpu_baseline` is the oracle on one host core, `cpu_baseline_all_cores`
+the oracle with each round's positions split over the host's threads;
+`target` follows the run's progress toward the planted ground state (or
+colouring).
 """
 from __future__ import annotations
 
@@ -122,39 +131,36 @@ def cpu_baseline(w, rounds: int, sub_grid: int = 0) -> dict:
             "seconds": round(dt, 3)}
 
 
-_ORACLE_CHILD = r"""
-import json, sys, time
-sys.path.insert(0, sys.argv[1])
-from oracle import oracle as O
-from synth import configs as C
-w = getattr(C, sys.argv[2])()
-rounds, sub = int(sys.argv[3]), int(sys.argv[4])
-beta, p_q = (w.beta[:sub], w.p_q[:sub]) if sub else (w.beta, w.p_q)
-t0 = time.perf_counter()
-O.run(w.instance, beta, p_q, mcs_per_swap=w.mcs_per_swap, n_rounds=rounds, seed=0)
-print(json.dumps({"seconds": time.perf_counter() - t0}))
-"""
+def host_threads() -> int:
+    """Threads the all-cores CPU baseline uses: the CPUs this process may run
+    on, at most 16 (a one-GPU share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
 
 
-def cpu_baseline_all_cores(w, builder: str, rounds: int, sub_grid: int, procs: int) -> dict:
-    """The same oracle sample run by `procs` independent single-threaded
-    processes at once (child interpreters that never touch the GPU): the
-    aggregate rate of the host's cores.  Each child times its own run; the
-    aggregate is procs x updates over the longest of them."""
-    import subprocess
-    kids = [subprocess.Popen([sys.executable, "-c", _ORACLE_CHILD, ROOT, builder, str(rounds), str(sub_grid)],
-                             stdout=subprocess.PIPE, text=True) for _ in range(procs)]
-    secs = []
-    for k in kids:
-        out, _ = k.communicate()
-        if k.returncode != 0:
-            raise RuntimeError("oracle child failed")
-        secs.append(json.loads(out.strip().splitlines()[-1])["seconds"])
-    beta_n = min(sub_grid, w.n_beta) if sub_grid else w.n_beta
-    p_n = min(sub_grid, w.n_p) if sub_grid else w.n_p
-    updates = rounds * w.mcs_per_swap * beta_n * p_n * w.instance.n
-    return {"value": procs * updates / max(secs), "unit": "spin-updates/s", "cores": procs, "kind": "oracle",
-            "sample": f"{procs} concurrent copies of the single-core sample", "seconds": round(max(secs), 3)}
+def cpu_baseline_threaded(w, rounds: int, sub_grid: int, threads: int) -> dict:
+    """The oracle with each round's sweeps split over `threads` threads by
+    grid position (the swap step and tracking stay sequential; the result is
+    the single-threaded one), timed on its first `rounds` rounds of the full
+    grid or of its top-left sub_grid x sub_grid corner."""
+    from oracle import oracle as O
+    beta, p_q = w.beta, w.p_q
+    if sub_grid:
+        beta, p_q = beta[:sub_grid], p_q[:sub_grid]
+    n, R = w.instance.n, len(beta) * len(p_q)
+    t0 = time.perf_counter()
+    O.run(w.instance, beta, p_q, mcs_per_swap=w.mcs_per_swap, n_rounds=rounds, seed=0, threads=threads)
+    dt = time.perf_counter() - t0
+    updates = rounds * w.mcs_per_swap * R * n
+    grid = f"{len(beta)}x{len(p_q)} corner of the grid" if sub_grid else f"all {R} replicas"
+    return {"value": updates / dt, "unit": "spin-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{w.name}: first {rounds} rounds x {w.mcs_per_swap} sweep(s) of {grid}, seed 0, "
+                      f"{threads} OpenMP threads splitting each round's positions "
+                      f"(host: {os.cpu_count()} CPUs, {_cpu_model()})",
+            "seconds": round(dt, 3)}
 
 
 def _cpu_model() -> str:
@@ -238,40 +244,27 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_tts(args):
-    """Sweeps and time to the planted ground state on the N=12 workload over
-    many run seeds (the same instance, --count seeds, the workload's 1e4
-    sweeps unless --cap-sweeps says otherwise), all runs in one batch and one
-    after another.  TTS99 follows the usual Ising-machine convention
-    t ln(0.01) / ln(1 - p) with p the hit fraction at the cap (it is not a
-    figure of the paper)."""
+def tts_compare(T, members, cap_sweeps: int, chunk: int) -> dict:
+    """Run every member once in one batch and once one after another (the
+    plain form), each until it reaches the planted ground state or the sweep
+    cap.  Sweeps to hit are identical in both modes (random streams are
+    keyed per problem); wall times differ.  Per mode: success fraction,
+    p50/p99 of the time to hit counted from the job's start (plain runs queue
+    behind earlier ones) and from the run's own start, and the time until
+    99 % of the runs have hit (None below 99 % success)."""
     import copy
     import math
 
-    import dataclasses
-
-    import paper_2506_14781_amd as T
     from paper_2506_14781_amd.serve import run_batched, run_plain, summarize
-    from synth.configs import jcolumn_member, wishart_small
-    if args.tts_n == 12:
-        members = [wishart_small(seed=k) for k in range(args.count)]
-    else:
-        # one three-copy instance of the J-column family (16 x 8 grid), many run seeds
-        w = jcolumn_member(args.tts_n, 20000)
-        members = [dataclasses.replace(w, seed=k, sweeps=args.cap_sweeps) for k in range(args.count)]
-    reqs_b = _requests(T, members, args.cap_sweeps, 0.0)
+    reqs_b = _requests(T, members, cap_sweeps, 0.0)
     reqs_p = [copy.copy(r) for r in reqs_b]
-    print(f"[bench] tts: {len(members)} seeds of {members[0].name}, cap {args.cap_sweeps} sweeps",
-          file=sys.stderr, flush=True)
-    tb = run_batched(reqs_b, chunk=args.chunk)
+    tb = run_batched(reqs_b, chunk=chunk)
     sb = summarize(reqs_b, tb)
-    tp = run_plain(reqs_p, chunk=args.chunk)
+    tp = run_plain(reqs_p, chunk=chunk)
     sp = summarize(reqs_p, tp)
     for a, b in zip(reqs_b, reqs_p):
         assert a.hit_sweep == b.hit_sweep, "sweeps to hit differ between modes"
     for reqs, s in ((reqs_b, sb), (reqs_p, sp)):
-        # time until 99 % of all runs have hit (None below 99 % success), and
-        # each run's time to hit from its own start (plain runs queue)
         hits = sorted(r.hit_time for r in reqs if r.hit_time is not None)
         need = math.ceil(0.99 * len(reqs))
         s["time_to_99pct_of_runs_s"] = hits[need - 1] if len(hits) >= need else None
@@ -281,14 +274,41 @@ def bench_tts(args):
     p = sb["hit_fraction"]
     tts99 = None
     if 0 < p < 1:
-        tts99 = args.cap_sweeps * math.log(0.01) / math.log(1.0 - p)
+        tts99 = cap_sweeps * math.log(0.01) / math.log(1.0 - p)
     elif p == 1:
         tts99 = sb["sweeps_to_hit_p99"]
-    out = {"metric": "time-to-planted-GS p50 (batched)", "value": sb["tts_p50_s"], "unit": "s",
+    out = {"runs": len(members), "cap_sweeps": cap_sweeps, "success": p,
+           "meets_99pct_success": p >= 0.99, "sweeps_tts99": tts99, "batched": sb, "plain": sp}
+    if sb["time_to_99pct_of_runs_s"] and sp["time_to_99pct_of_runs_s"]:
+        out["speedup_time_to_99pct"] = round(sp["time_to_99pct_of_runs_s"] / sb["time_to_99pct_of_runs_s"], 2)
+    return out
+
+
+def bench_tts(args):
+    """Sweeps and time to the planted ground state on the N=12 workload over
+    many run seeds (the same instance, --count seeds, the workload's 1e4
+    sweeps unless --cap-sweeps says otherwise), all runs in one batch and one
+    after another.  TTS99 follows the usual Ising-machine convention
+    t ln(0.01) / ln(1 - p) with p the hit fraction at the cap (it is not a
+    figure of the paper)."""
+    import dataclasses
+
+    import paper_2506_14781_amd as T
+    from synth.configs import jcolumn_member, wishart_small
+    if args.tts_n == 12:
+        members = [wishart_small(seed=k) for k in range(args.count)]
+    else:
+        # one three-copy instance of the J-column family (16 x 8 grid), many run seeds
+        w = jcolumn_member(args.tts_n, 20000)
+        members = [dataclasses.replace(w, seed=k, sweeps=args.cap_sweeps) for k in range(args.count)]
+    print(f"[bench] tts: {len(members)} seeds of {members[0].name}, cap {args.cap_sweeps} sweeps",
+          file=sys.stderr, flush=True)
+    res = tts_compare(T, members, args.cap_sweeps, args.chunk)
+    out = {"metric": "time-to-planted-GS p50 (batched)", "value": res["batched"]["tts_p50_s"], "unit": "s",
            "higher_is_better": False, "n_gpus": 1,
            "data": f"synthetic (seeded planted Wishart N={args.tts_n}, copy-chain sparsified)",
            "config": {"workload": f"{members[0].name}, {len(members)} run seeds, cap {args.cap_sweeps} sweeps"},
-           "sweeps_tts99": tts99, "batched": sb, "plain": sp}
+           "sweeps_tts99": res["sweeps_tts99"], "batched": res["batched"], "plain": res["plain"]}
     print(json.dumps(out), flush=True)
 
 
@@ -515,26 +535,29 @@ def bench_copy():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None, help="timed steps (n200: 100, n1000: 5)")
-    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (n200: 5, n1000: 1)")
-    ap.add_argument("--rounds-per-step", type=int, default=None, help="rounds per step (n200: 1000, n1000: 4)")
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (n1000: 10, n200: 100)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (n1000: 1, n200: 5)")
+    ap.add_argument("--rounds-per-step", type=int, default=None, help="rounds per step (n1000: 4, n200: 1000)")
     ap.add_argument("--cpu-rounds", type=int, default=None,
-                    help="rounds of the oracle timed for the CPU baseline (0: skip; n200: 100, n1000: 1)")
-    ap.add_argument("--cpu-procs", type=int, default=min(16, os.cpu_count() or 1),
-                    help="concurrent oracle processes for the all-cores CPU figure (1: skip)")
+                    help="rounds of the oracle timed for the CPU baseline (0: skip; n1000: 2, n200: 100)")
+    ap.add_argument("--cpu-threads", type=int, default=host_threads(),
+                    help="threads of the all-cores CPU baseline (1: skip)")
+    ap.add_argument("--tts-seeds", type=int, default=200,
+                    help="run seeds of the N=12 time-to-planted-GS comparison in the main line (0: skip)")
+    ap.add_argument("--tts-cap", type=int, default=200000, help="sweep cap of that comparison")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--autotune", type=int, default=None,
                     help="rounds per trial of the launch-shape autotuner, run before the warm-up "
-                         "(0: off; n200: 200, n1000: 1, coloring: 10)")
+                         "(0: off; n1000: 1, n200: 200, coloring: 10)")
     ap.add_argument("--sizes", type=str, default="16,24,32,48", help="logical sizes (jcolumn)")
     ap.add_argument("--schedule", choices=["fixed", "adaptive"], default="fixed",
                     help="jcolumn: the workload's beta / P ladders, or Algorithm 2 per instance")
     ap.add_argument("--sigma-min", type=float, default=0.5, help="Algorithm 2 energy spread threshold")
     ap.add_argument("--kl-rounds", type=int, default=2000, help="rounds of 500 sweeps (kl)")
     ap.add_argument("--kl-seeds", type=int, default=4, help="independent runs per setting (kl)")
-    ap.add_argument("--workload", choices=["n200", "n1000", "coloring", "batched", "tts", "serving", "jcolumn",
+    ap.add_argument("--workload", choices=["n1000", "n200", "coloring", "batched", "tts", "serving", "jcolumn",
                                            "kl", "copy"],
-                    default="n200",
+                    default="n1000",
                     help="copy: one plain 256 MiB device-to-device copy, the reference the HBM "
                          "traffic counters are scaled against")
     ap.add_argument("--count", type=int, default=64, help="instances (batched) / requests (serving)")
@@ -559,16 +582,16 @@ def main():
 
     big = args.workload == "n1000"
     defaults = {"n200": dict(steps=100, warmup=5, rounds_per_step=1000, cpu_rounds=100, autotune=200),
-                "n1000": dict(steps=5, warmup=1, rounds_per_step=4, cpu_rounds=2, autotune=1),
+                "n1000": dict(steps=10, warmup=1, rounds_per_step=4, cpu_rounds=2, autotune=1),
                 "coloring": dict(steps=20, warmup=2, rounds_per_step=100, cpu_rounds=4, autotune=10)}
-    for name, v in defaults.get(args.workload, defaults["n200"]).items():
+    for name, v in defaults.get(args.workload, defaults["n1000"]).items():
         if getattr(args, name) is None:
             setattr(args, name, v)
 
     import torch
 
     import paper_2506_14781_amd as T
-    from synth.configs import coloring_workload, wishart_n200, wishart_n1000
+    from synth.configs import coloring_workload, wishart_n200, wishart_n1000, wishart_small
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -653,12 +676,31 @@ def main():
                 "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "Tlane-op/s",
                 "frac": round(achieved / PEAK_LANE_OPS, 4),
                 "traffic": measured_traffic(w.name, kernel, timed_rounds // max(timed, 1)),
+                "traffic_source": "rocprofv3 FETCH_SIZE + WRITE_SIZE of this kernel on this workload, "
+                                  "scaled by a plain copy's counters (null once the kernel source changed)",
                 "ops_per_update": round(ops, 2)}
+    # the byte model: what one update must move at the level its data live
+    d_bar = info["nnz"] / info["n"]
     if bits:
         wd = max(1, info["max_degree"]) if info["max_degree"] <= 8 else 16
         bpu = bits_bytes_per_update(info, wd)
-        roofline["structure_bytes_per_update"] = round(bpu, 3)
-        roofline["structure_GBps"] = round(bpu * updates_per_launch / (launch_ms / 1e3) / 1e9, 1)
+        roofline["bytes_model"] = {
+            "what": "structure streamed once per sweep per 4-replica workgroup (neighbour bit positions "
+                    "and couplings 8 B per ELL entry, copy positions 8 B, field 4 B per padded spin, / 4); "
+                    "spins are LDS-resident bits",
+            "bytes_per_update": round(bpu, 3),
+            "achieved_GBps": round(bpu * updates_per_launch / (launch_ms / 1e3) / 1e9, 1),
+            "peak_GBps": 8000.0}
+        roofline["bytes_model"]["frac"] = round(roofline["bytes_model"]["achieved_GBps"] / 8000.0, 4)
+    else:
+        r_share = w.n_p
+        bpu = (d_bar + 1) + (8 * d_bar + 4) / r_share
+        roofline["bytes_model"] = {
+            "what": "(d+1) int8 spin reads/writes + (8 d + 4) B of structure shared by the replicas of a row",
+            "bytes_per_update": round(bpu, 3),
+            "achieved_GBps": round(bpu * updates_per_launch / (launch_ms / 1e3) / 1e9, 1),
+            "peak_GBps": 8000.0}
+        roofline["bytes_model"]["frac"] = round(roofline["bytes_model"]["achieved_GBps"] / 8000.0, 4)
     roofline.update({"kernel": kernel, "kernel_avg_ms": round(launch_ms, 5),
                      "kernel_launches_timed": timed, "updates_per_launch": updates_per_launch})
     q = prob.query()
@@ -683,6 +725,8 @@ def main():
             "grid": f"{w.n_beta}x{w.n_p}",
             "replicas": w.replicas,
             "mcs_per_swap": w.mcs_per_swap,
+            "layout": "bit-packed" if bits else "int8",
+            "driver": "persistent" if persistent else "per-round",
             "sweeps_timed": total_rounds * w.mcs_per_swap,
             "rounds_per_step": rps,
             "best_f_q": q["best_f_q"],
@@ -703,12 +747,35 @@ def main():
         out["config"].update({"constraint": "one-hot terms", "n_terms": info["n_terms"]})
     if tune is not None:
         out["autotune"] = tune
+    prob.close()
+    del prob
+    torch.cuda.synchronize()
+    if args.tts_seeds > 0:
+        # the metric's second half: time to the planted ground state, batched
+        # vs plain, where >= 99 % success is reachable (N=12; at N=1000 no run
+        # reaches it within any cap this job can afford)
+        members = [wishart_small(seed=k) for k in range(args.tts_seeds)]
+        print(f"[bench] time to planted GS: {len(members)} seeds of {members[0].name}, "
+              f"cap {args.tts_cap} sweeps, batched then plain", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        res = tts_compare(T, members, args.tts_cap, args.chunk)
+        res["workload"] = f"{members[0].name}, run seeds 0..{len(members) - 1}"
+        res["seconds"] = round(time.perf_counter() - t0, 2)
+        out["time_to_planted_gs"] = res
+        b, pl = res["batched"], res["plain"]
+        print(f"[bench] time to planted GS: success {res['success']:.3f}; p50/p99 batched "
+              f"{b['tts_p50_s']}/{b['tts_p99_s']} s, plain {pl['tts_p50_s']}/{pl['tts_p99_s']} s",
+              file=sys.stderr, flush=True)
     if args.cpu_rounds > 0:
         sub = 4 if big else 8 if gen else 0
+        print(f"[bench] oracle on the host: {args.cpu_rounds} rounds, one thread", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_rounds, sub_grid=sub)
-        if args.cpu_procs > 1:
-            builder = "coloring_workload" if gen else "wishart_n1000" if big else "wishart_n200"
-            out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(w, builder, args.cpu_rounds, sub, args.cpu_procs)
+        if args.cpu_threads > 1:
+            # a grid corner with several positions per thread
+            sub_t = 8 if big else sub
+            print(f"[bench] oracle on the host: {args.cpu_threads} threads", file=sys.stderr, flush=True)
+            out["cpu_baseline_all_cores"] = cpu_baseline_threaded(w, args.cpu_rounds, sub_t, args.cpu_threads)
+    torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 
 

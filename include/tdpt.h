@@ -65,7 +65,10 @@ extern "C" {
 #define TDPT_E_RANGE 2   /* fixed-point bounds exceeded (see tdpt_problem_create) */
 #define TDPT_E_NOMEM 3   /* workspace too small / host allocation failed */
 #define TDPT_E_DEVICE 4  /* HIP runtime error (code in the message) */
-#define TDPT_E_STATE 5   /* call out of order (e.g. a problem inside a batch) */
+#define TDPT_E_STATE 5   /* call out of order: a batch whose member was destroyed or moved
+                            to another batch, a histogram or logical read the problem was
+                            not set up for */
+#define TDPT_E_BUSY 6    /* the problem's batch has a run in flight (run, load, autotune) */
 
 /* Flags of tdpt_run_cfg.flags */
 #define TDPT_NO_PSWAP 1u /* J-column PT: no P-swaps; every round tries beta-swaps,
@@ -91,6 +94,10 @@ typedef struct tdpt_run_cfg {
     uint32_t flags;          /* TDPT_NO_PSWAP */
     int64_t trace_cap;       /* keep (f_q, g) of the bottom-right replica for the
                                 first trace_cap rounds; 0 keeps none */
+    int32_t hist_logical;    /* nonzero: after every round's swap step, count the
+                                bottom-right replica's logical state in a device
+                                histogram (the sampling measurement of Fig. 2; the
+                                instance needs logical_of with at most 20 variables) */
 } tdpt_run_cfg;
 
 typedef struct tdpt_instance_info {
@@ -104,6 +111,7 @@ typedef struct tdpt_instance_info {
     int32_t m;          /* copy edges */
     int32_t n_terms;    /* general constraint terms (0 with copy edges) */
     int32_t max_constraint_degree; /* most spins one spin shares a term with */
+    int32_t n_logical;  /* logical variables named by logical_of, 0 if none was given */
 } tdpt_instance_info;
 
 typedef struct tdpt_status {
@@ -119,7 +127,9 @@ typedef struct tdpt_status {
 /* ---------------------------------------------------------------- instance */
 
 /* Validate an Ising instance with copy constraints and lay it out for the
- * device (host memory only; nothing is allocated on the GPU).
+ * device (host memory only; nothing is allocated on the GPU).  Eq. 1 with
+ * the copy constraint of the section on graph sparsification; the inputs
+ * are Algorithm 1's problem instance.
  *   n           physical spins (> 0)
  *   row_ptr     [n+1] CSR offsets of the problem couplings, row_ptr[0] == 0
  *   col, J_q    [row_ptr[n]] neighbour index and Q12 coupling; the matrix must
@@ -130,6 +140,11 @@ typedef struct tdpt_status {
  *               problem coupling); the constraint is g = sum (s_a - s_b)^2
  *   color       [n] colour class of every spin (>= 0); must be proper over
  *               problem and copy edges (a spin shares no class with any neighbour)
+ *   logical_of  [n] or NULL: the logical variable (0 .. N-1, each used) each
+ *               physical spin is a copy of.  A logical variable is read from
+ *               its lowest-numbered copy (tdpt_problem_read_best_logical, the
+ *               histogram of tdpt_run_cfg.hist_logical); on a state with g = 0
+ *               every copy of a chain agrees.
  * At most 256 problem neighbours and 2 copy neighbours per spin, at most 32
  * colour classes.
  * All arrays are read during the call only.  On success *out owns a host
@@ -138,7 +153,8 @@ typedef struct tdpt_status {
 int tdpt_instance_create(int32_t n, const int32_t *row_ptr, const int32_t *col,
                          const int32_t *J_q, const int32_t *b_q, int32_t m,
                          const int32_t *copy_a, const int32_t *copy_b,
-                         const int32_t *color, tdpt_instance **out);
+                         const int32_t *color, const int32_t *logical_of,
+                         tdpt_instance **out);
 
 /* The same with a general constraint function in place of copy edges (Eq. 1
  * asks only g >= 0 with g = 0 exactly on feasible states):
@@ -166,9 +182,22 @@ int tdpt_instance_create_terms(int32_t n, const int32_t *row_ptr, const int32_t 
                                const int32_t *J_q, const int32_t *b_q, int32_t n_terms,
                                const int32_t *term_ptr, const int32_t *term_idx,
                                const int32_t *term_coef, const int32_t *term_const,
-                               const int32_t *color, tdpt_instance **out);
+                               const int32_t *color, const int32_t *logical_of,
+                               tdpt_instance **out);
 int tdpt_instance_info_get(const tdpt_instance *inst, tdpt_instance_info *out);
 void tdpt_instance_destroy(tdpt_instance *inst);
+
+/* Structure layout a problem of this instance and configuration runs with
+ * (host only).  Problems of one batch whose group_key is equal share one
+ * sweep kernel launch per round; a batch holds one group per key. */
+typedef struct tdpt_layout {
+    int32_t bits;       /* 1: replicas as bits, 4 per workgroup (replicas above 48 KiB as int8) */
+    int32_t narrow;     /* 1: 16-bit packed structure rows */
+    int32_t general;    /* 1: general constraint terms, 0: copy edges */
+    int32_t ell_width;  /* problem-neighbour slots per spin in the device structure */
+    int32_t group_key;  /* bits | narrow << 1 | (narrow && general) << 2 | ell_width << 3 */
+} tdpt_layout;
+int tdpt_layout_get(const tdpt_instance *inst, const tdpt_run_cfg *cfg, tdpt_layout *out);
 
 /* ---------------------------------------------------------------- problem */
 
@@ -193,36 +222,67 @@ int tdpt_workspace_bytes(const tdpt_instance *inst, const tdpt_run_cfg *cfg, siz
 int tdpt_problem_create(const tdpt_instance *inst, const tdpt_run_cfg *cfg, void *dev_ws,
                         size_t ws_bytes, void *stream, tdpt_problem **out);
 
-/* Enqueue n_rounds swap rounds (each: mcs_per_swap sweeps of every replica,
- * f/g of the final states, one swap step, bottom-right tracking).  Resumable:
- * calling it twice with a and b rounds equals one call with a + b. */
+/* Enqueue n_rounds swap rounds of Algorithm 1 (each: mcs_per_swap sweeps of
+ * every replica, f/g of the final states, one swap step by Eq. 2 or Eq. 3,
+ * bottom-right tracking).  Resumable: calling it twice with a and b rounds
+ * equals one call with a + b.  TDPT_E_BUSY if the problem's batch has a run
+ * in flight; TDPT_E_RANGE past 2^32 sweeps. */
 int tdpt_problem_run(tdpt_problem *prob, int64_t n_rounds);
 
-/* Wait for the problem's stream, then report counters and tracking. */
-int tdpt_problem_query(tdpt_problem *prob, tdpt_status *out);
+/* Read calls wait for the problem's stream (and so for any batch run that
+ * holds it) and write host memory the caller owns; the _async variants
+ * enqueue the same data on the problem's stream into device memory the
+ * caller owns (on the problem's device) and return at once. */
 
-/* f_q[R], g[R] per grid position (R = I*J). */
+/* Counters and tracking: rounds and sweeps done; the first sweep at which
+ * the bottom-right replica was feasible (g == 0) with f_q <= f_target_q (the
+ * planted ground state of the Wishart study: the residual energy of Fig. 3
+ * is read at the bottom-right replica); its best feasible f_q and sweep. */
+int tdpt_problem_query(tdpt_problem *prob, tdpt_status *out);
+/* dev_words[4] = rounds_done, first_hit_sweep, best_f_q, best_sweep. */
+int tdpt_problem_query_async(tdpt_problem *prob, int64_t *dev_words);
+
+/* E and g of the final state of every grid position's replica, the values
+ * the swap step compares (Eq. 2, Eq. 3): f_q[R], g[R] per position
+ * (R = I*J, row-major); either pointer may be NULL (not both). */
 int tdpt_problem_read_energies(tdpt_problem *prob, int64_t *f_q, int64_t *g);
+int tdpt_problem_read_energies_async(tdpt_problem *prob, int64_t *dev_f_q, int64_t *dev_g);
 /* s[R*n] per position, original spin order. */
 int tdpt_problem_read_states(tdpt_problem *prob, int8_t *s);
-/* pos_to_slot[R]: which internal replica slot sits at each position. */
+int tdpt_problem_read_states_async(tdpt_problem *prob, int8_t *dev_s);
+/* pos_to_slot[R]: which internal replica slot sits at each position (a swap
+ * exchanges the labels of two positions, never their spins). */
 int tdpt_problem_read_perm(tdpt_problem *prob, int32_t *pos_to_slot);
-/* Best feasible bottom-right state (original order), its f_q and sweep. */
+/* Best feasible bottom-right state (Algorithm 1 stores the last replica's
+ * spins after each swap step), original order, its f_q and sweep.  Any
+ * pointer may be NULL. */
 int tdpt_problem_read_best(tdpt_problem *prob, int8_t *s, int64_t *f_q, int64_t *sweep);
+/* dev_s[n] (may be NULL) and dev_f_sweep[2] = best_f_q, best_sweep (may be NULL). */
+int tdpt_problem_read_best_async(tdpt_problem *prob, int8_t *dev_s, int64_t *dev_f_sweep);
+/* The same state decoded to its logical variables x[N] (+-1, each read from
+ * its lowest-numbered copy); TDPT_E_STATE without logical_of. */
+int tdpt_problem_read_best_logical(tdpt_problem *prob, int8_t *x, int64_t *f_q, int64_t *sweep);
 /* Swap attempts/accepts: P pairs [I*(J-1)] indexed (row, left column), beta
  * pairs [J*(I-1)] indexed (column, upper row).  Any pointer may be NULL. */
 int tdpt_problem_read_counters(tdpt_problem *prob, int64_t *p_att, int64_t *p_acc,
                                int64_t *b_att, int64_t *b_acc);
 /* Bottom-right (f_q, g) of rounds 1..min(rounds_done, trace_cap). */
 int tdpt_problem_read_trace(tdpt_problem *prob, int64_t *f_q, int64_t *g, int64_t *count);
+/* The logical-state histogram of the bottom-right replica (hist_logical):
+ * counts[2^N], bin sum_k [x_k = +1] 2^k, one sample per round done
+ * (*samples, may be NULL).  TDPT_E_STATE if the run did not ask for it. */
+int tdpt_problem_read_histogram(tdpt_problem *prob, uint32_t *counts, int64_t *samples);
 
 /* Checkpoint: copy the whole mutable device state to host memory.  With
  * host == NULL only *bytes is set.  tdpt_problem_load restores it into a
  * problem created from the same instance and configuration; a run resumed
  * from it is bit-identical to an uninterrupted one. */
 int tdpt_problem_save(tdpt_problem *prob, void *host, size_t *bytes);
-int tdpt_problem_load(tdpt_problem *prob, const void *host, size_t bytes);
+int tdpt_problem_load(tdpt_problem *prob, const void *host, size_t bytes);  /* TDPT_E_BUSY as run */
 
+/* Release the handle (the caller frees the workspace afterwards).  A batch
+ * member is first taken out of its batch, after the batch's work in flight;
+ * that batch then needs tdpt_batch_set_members before its next run. */
 void tdpt_problem_destroy(tdpt_problem *prob);
 
 /* Measurement hook: from now on record a pair of HIP events on the problem's
@@ -259,14 +319,24 @@ int tdpt_problem_autotune(tdpt_problem *prob, int32_t rounds_per_trial, tdpt_tun
 
 /* ---------------------------------------------------------------- batches */
 
-/* A batch advances many problems at once: every round is one sweep launch
- * over all replica slots of all members (grouped by structure layout, the
- * largest instances first) and one swap-and-track launch over all members,
- * so problems of uneven size and grid share the GPU.  Results are identical
- * to running each member alone (random streams are keyed per problem).
+/* A batch advances many problems at once (many independent Algorithm 1
+ * runs): every round is one sweep launch over all replica slots of all
+ * members (grouped by structure layout, tdpt_layout.group_key, the largest
+ * instances first) and one swap-and-track launch over all members, so
+ * problems of uneven size and grid share the GPU.  Results are identical to
+ * running each member alone (random streams are keyed per problem).
  * Members are ordinary problems; their own streams are ordered after every
- * batch run, so their read calls see its results.  A problem must not be
- * run on its own while a batch run that holds it is in flight. */
+ * batch run, so their read calls see its results.  While a batch run that
+ * holds a problem is in flight, running, loading or autotuning that problem
+ * returns TDPT_E_BUSY.  A problem belongs to at most one batch: naming it
+ * in another batch's member list takes it out of the first, which then
+ * needs tdpt_batch_set_members before it runs again (TDPT_E_STATE).
+ *
+ * Continuous batching with these calls: admitting a problem or retiring one
+ * is tdpt_batch_set_members with the new list (at a round boundary: the
+ * call waits for the work in flight); launching is tdpt_batch_run (returns
+ * at once); polling is tdpt_problem_query or tdpt_problem_query_async on
+ * each member (first_hit_sweep, rounds_done). */
 
 /* Device bytes of the descriptor table of a batch with up to max_members. */
 int tdpt_batch_workspace_bytes(int32_t max_members, size_t *bytes);
@@ -275,9 +345,11 @@ int tdpt_batch_workspace_bytes(int32_t max_members, size_t *bytes);
 int tdpt_batch_create(int32_t max_members, void *dev_ws, size_t ws_bytes, void *stream,
                       tdpt_batch **out);
 /* Replace the member list (count <= max_members, no repeats; count 0 empties
- * the batch).  Waits for pending work of the members. */
+ * the batch).  Waits for pending work of the members and the batch.  On
+ * failure the batch is left empty (no member). */
 int tdpt_batch_set_members(tdpt_batch *batch, tdpt_problem *const *probs, int32_t count);
-/* Enqueue n_rounds rounds of every member on the batch's stream. */
+/* Enqueue n_rounds rounds of every member on the batch's stream.
+ * TDPT_E_STATE if a member was destroyed or moved since set_members. */
 int tdpt_batch_run(tdpt_batch *batch, int64_t n_rounds);
 /* Autotune the threads per sweep workgroup of each layout group of the
  * current members (64 to 1024, 768 for bit-packed groups, no smaller than

@@ -21,12 +21,14 @@ _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle: plain C, -O2, no FMA contraction, no fast-math."""
+    """Compile the oracle: plain C, -O2, no FMA contraction, no fast-math;
+    OpenMP only to split a round's sweeps over positions when asked
+    (set_threads)."""
     os.makedirs(os.path.dirname(_LIB), exist_ok=True)
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+                               "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -50,6 +52,8 @@ def _load():
         _lib.oracle_swap_accept.argtypes = [ctypes.c_double, ctypes.c_double]
         _lib.oracle_heat_bath.argtypes = [ctypes.c_double, ctypes.c_int64, ctypes.c_uint32]
         _lib.oracle_schedule.argtypes = [ctypes.c_int64, ctypes.c_uint32, P, P]
+        _lib.oracle_set_threads.argtypes = [ctypes.c_int32]
+        _lib.oracle_set_threads.restype = None
         _lib.oracle_run.argtypes = (
             [ctypes.c_int32, P, P, P, P, ctypes.c_int32, P, P, P,
              ctypes.c_int32, P, ctypes.c_int32, P,
@@ -151,8 +155,9 @@ def schedule(n, flags=0):
 
 
 def run(inst, beta, p_q, *, mcs_per_swap, n_rounds, seed, s0=None, f_target=None,
-        flags=0, trace=False):
-    """Run 2D-PT for n_rounds rounds; every output is in grid-position order."""
+        flags=0, trace=False, threads=1):
+    """Run 2D-PT for n_rounds rounds; every output is in grid-position order.
+    threads > 1 splits each round's sweeps over positions (same result)."""
     lib = _load()
     beta = _c(beta, np.float64)
     p_q = _c(p_q, np.int32)
@@ -184,12 +189,16 @@ def run(inst, beta, p_q, *, mcs_per_swap, n_rounds, seed, s0=None, f_target=None
             _p(states), _p(f), _p(g), _p(best), _p(sc[0]), _p(sc[1]), _p(sc[2]),
             _p(p_att), _p(p_acc), _p(b_att), _p(b_acc), _p(tf), _p(tg), tcap)
     T = _terms(inst)
-    if T is not None:
-        tp, ti, tc, td = T
-        rc = lib.oracle_run_terms(n, _p(rp), _p(col), _p(J), _p(b), tp.shape[0] - 1, _p(tp), _p(ti),
-                                  _p(tc), _p(td), *tail)
-    else:
-        rc = lib.oracle_run(n, _p(rp), _p(col), _p(J), _p(b), ca.shape[0], _p(ca), _p(cb), *tail)
+    lib.oracle_set_threads(int(threads))
+    try:
+        if T is not None:
+            tp, ti, tc, td = T
+            rc = lib.oracle_run_terms(n, _p(rp), _p(col), _p(J), _p(b), tp.shape[0] - 1, _p(tp),
+                                      _p(ti), _p(tc), _p(td), *tail)
+        else:
+            rc = lib.oracle_run(n, _p(rp), _p(col), _p(J), _p(b), ca.shape[0], _p(ca), _p(cb), *tail)
+    finally:
+        lib.oracle_set_threads(1)
     if rc:
         raise RuntimeError("oracle_run failed with code %d" % rc)
     return {

@@ -64,6 +64,15 @@
 
 #define ORACLE_NO_PSWAP 1u
 
+/* Threads that share the replicas' sweeps inside a round (1 by default).
+ * Positions are independent during the sweep phase and every random number
+ * is keyed by position, so the result does not depend on this; the swap
+ * step and tracking stay sequential.  Without OpenMP the pragma is ignored
+ * and the run is single-threaded. */
+static int32_t oracle_threads = 1;
+
+void oracle_set_threads(int32_t threads) { oracle_threads = threads > 0 ? threads : 1; }
+
 /* ---------------------------------------------------------------- Philox */
 
 void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
@@ -421,6 +430,7 @@ static int run_core(int32_t n, const int32_t *row_ptr, const int32_t *col, const
 
     for (int64_t rnd = 1; rnd <= n_rounds; ++rnd) {
         /* every replica performs mcs_per_swap sweeps */
+#pragma omp parallel for num_threads(oracle_threads) schedule(dynamic, 1)
         for (int32_t p = 0; p < R; ++p) {
             const int32_t i = p / n_p, j = p % n_p;
             int8_t *s = state[p];

@@ -13,6 +13,7 @@ constexpr int kSmallBlock = 256;  // threads of the swap / energy kernels
 constexpr int kRing = 8;          // rounds of partner mailboxes kept per position
 constexpr int kBitSlots = 4;      // replicas per workgroup in the bit-packed layout
 constexpr int kBitsBlock = 768;   // threads of a bit-packed sweep workgroup, at most
+constexpr int kMaxHistVars = 20;  // logical variables of the per-round state histogram, at most
 
 // Structure layouts of the byte-replica sweeps (their NARROW template
 // argument): 32-bit rows; packed 16-bit index and coupling pairs with copy
@@ -111,6 +112,12 @@ struct DevProblem {
     int64_t *b_att, *b_acc; // [J*(I-1)]
     int8_t *best_state;   // [stride]
     int64_t *trace_f, *trace_g; // [trace_cap]
+    // histogram of the bottom-right replica's logical state, one sample per
+    // round after the swap step (hist_n = 0: off): bin sum_k [s > 0] 2^k over
+    // the spins at colour-major positions hist_rank[0 .. hist_n)
+    int32_t hist_n;
+    const int32_t *hist_rank; // [hist_n]
+    uint32_t *hist;           // [2^hist_n]
     // scratch of the persistent driver (not part of checkpoints)
     uint64_t *mbox;       // [kRing][R][2] tagged (f, g) by grid position
     int64_t *slot_key;    // [R] best key per slot during a launch
@@ -142,6 +149,12 @@ hipError_t launch_batch_persistent(const DevProblem &p, const DevProblem *table,
                                    int blocks, int block, size_t lds, int64_t n_rounds, hipStream_t s);
 hipError_t launch_batch_scratch_reset(const DevProblem *table, int count, hipStream_t s);
 hipError_t launch_batch_finalize(const DevProblem *table, int count, int64_t n_rounds, hipStream_t s);
+// Readback into device buffers, in grid-position order and the caller's
+// spin numbering (n physical spins): f and g [R]; states [R][n]; the best
+// state [n].
+hipError_t launch_gather_energies(const DevProblem &p, int64_t *f, int64_t *g, hipStream_t s);
+hipError_t launch_gather_states(const DevProblem &p, int n, int8_t *out, hipStream_t s);
+hipError_t launch_gather_best(const DevProblem &p, int8_t *out, hipStream_t s);
 // Bit-packed layout: one round of every slot (ceil(R / kBitSlots) blocks).
 hipError_t launch_sweep_bits(const DevProblem &p, hipStream_t s);
 hipError_t launch_batch_sweep_bits(const DevProblem &p, const DevProblem *table, const int *first_block,

@@ -682,6 +682,12 @@ __device__ __forceinline__ void swap_track_body(const DevProblem &P)
     }
     __syncthreads();
     if (improved) copy_bytes16(P.best_state, P.states + (size_t)br_slot * P.stride, P.stride);
+    if (P.hist_n && tid == 0) {
+        const int8_t *st = P.states + (size_t)br_slot * P.stride;
+        uint32_t bin = 0;
+        for (int k = 0; k < P.hist_n; ++k) bin |= (uint32_t)(st[P.hist_rank[k]] > 0) << k;
+        P.hist[bin] += 1u;
+    }
     __syncthreads();
     if (tid == 0) P.hdr[kHdrRounds] = n;
 }
@@ -697,7 +703,9 @@ __global__ __launch_bounds__(kSmallBlock) void k_batch_swap(const DevProblem *__
 // Mailbox of grid position p in round n: two 64-bit words written by the
 // slot that sits at p, each carrying the round's tag in its low 16 bits so
 // either word can be checked on its own:
-//   w0 = f << 16 | tag,  w1 = g << 32 | (f >> 48) << 16 | tag.
+//   w0 = f << 16 | tag  (f as a 48-bit two's-complement number),
+//   w1 = g << 16 | tag  (g as a 48-bit unsigned number).
+// The host runs this driver only where |f| < 2^30 and g < 2^47.
 // Ring of kRing rounds: positions p and q that pair in round n pair again in
 // round n + 4, and no slot can move into p or q while their occupants have
 // not finished round n, so round n's entry is read before round n + kRing
@@ -712,8 +720,8 @@ __device__ __forceinline__ uint64_t mb_load(const uint64_t *m)
 __device__ __forceinline__ bool mb_take(uint64_t w0, uint64_t w1, uint64_t tag, int64_t &f, int64_t &g)
 {
     if ((w0 & 0xffff) != tag || (w1 & 0xffff) != tag) return false;
-    f = (int64_t)((w0 >> 16) | (((w1 >> 16) & 0xffff) << 48));
-    g = (int64_t)(w1 >> 32);
+    f = (int64_t)w0 >> 16;
+    g = (int64_t)(w1 >> 16);
     return true;
 }
 
@@ -817,9 +825,8 @@ __device__ __forceinline__ void persistent_body(const DevProblem &P, int slot, i
             st[1] = g;
             const uint64_t tag = mb_tag(n);
             __hip_atomic_store(&mb[2 * pos], ((uint64_t)f << 16) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&mb[2 * pos + 1],
-                               ((uint64_t)(uint32_t)g << 32) | ((((uint64_t)f >> 48) & 0xffff) << 16) | tag,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&mb[2 * pos + 1], ((uint64_t)g << 16) | tag, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
             const bool dir_beta = rp.dir_beta, left = rp.left;
             const int k = rp.k, line = rp.line, other = rp.other;
             int newpos = pos;
@@ -848,6 +855,12 @@ __device__ __forceinline__ void persistent_body(const DevProblem &P, int slot, i
             int improved = 0;
             if (newpos == P.R - 1 && !abort) {
                 const int64_t sweeps = n * P.mcs;
+                if (P.hist_n) {
+                    const lds8_t *rep = replica_lds();
+                    uint32_t bin = 0;
+                    for (int k = 0; k < P.hist_n; ++k) bin |= (uint32_t)(rep[P.hist_rank[k]] > 0) << k;
+                    __hip_atomic_fetch_add(&P.hist[bin], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
                 if (n - 1 < P.trace_cap) { P.trace_f[n - 1] = f; P.trace_g[n - 1] = g; }
                 if (g == 0) {
                     if (P.has_target && f <= P.f_target)
@@ -1312,7 +1325,55 @@ __global__ __launch_bounds__(kSmallBlock) void k_energy(DevProblem P)
     }
 }
 
+// ------------------------------------------------- readback into device buffers
+__global__ void k_gather_energies(DevProblem P, int64_t *f, int64_t *g)
+{
+    const int pos = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= P.R) return;
+    const int slot = P.pos_slot[pos];
+    if (f) f[pos] = P.f[slot];
+    if (g) g[pos] = P.g[slot];
+}
+
+// out[pos][orig(r)] = spin r of the slot at pos; blockIdx.y strides over positions
+__global__ void k_gather_states(DevProblem P, int n, int8_t *out)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= P.n_pad) return;
+    const int o = P.orig[r];
+    if (o < 0) return;
+    for (int pos = blockIdx.y; pos < P.R; pos += gridDim.y)
+        out[(size_t)pos * n + o] = P.states[(size_t)P.pos_slot[pos] * P.stride + r];
+}
+
+__global__ void k_gather_best(DevProblem P, int8_t *out)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= P.n_pad) return;
+    const int o = P.orig[r];
+    if (o >= 0) out[o] = P.best_state[r];
+}
+
 // ---------------------------------------------------------------- launchers
+hipError_t launch_gather_energies(const DevProblem &p, int64_t *f, int64_t *g, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather_energies, dim3((p.R + 255) / 256), dim3(256), 0, s, p, f, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_states(const DevProblem &p, int n, int8_t *out, hipStream_t s)
+{
+    dim3 grid((p.n_pad + 255) / 256, p.R < 65535 ? p.R : 65535);
+    hipLaunchKernelGGL(k_gather_states, grid, dim3(256), 0, s, p, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_best(const DevProblem &p, int8_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather_best, dim3((p.n_pad + 255) / 256), dim3(256), 0, s, p, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_init_states(const DevProblem &p, hipStream_t s)
 {
     dim3 grid((p.stride + 255) / 256, p.R);

@@ -85,11 +85,18 @@ struct tdpt_instance {
     int64_t g0 = 0;          // constant of g
     int64_t max_cfield = 0;  // max_i |c_i|
     int64_t g_bound = 0;     // max |g|
+    // logical variables (optional): variable k is read from its lowest-
+    // numbered physical spin first_copy[k] (colour-major position first_rank[k])
+    int32_t n_logical = 0;
+    std::vector<int32_t> first_copy, first_rank;
 };
 
 struct tdpt_problem {
     tdpt::DevProblem dp{};
     hipStream_t stream = nullptr;
+    tdpt_batch *batch = nullptr;  // the batch that holds it as a member, if any
+    int32_t n_logical = 0;        // logical variables and their first copies
+    std::vector<int32_t> first_copy;
     int32_t n = 0, I = 0, J = 0, R = 0, mcs = 1;
     std::vector<int32_t> rank;
     uint8_t *ws = nullptr;
@@ -124,9 +131,9 @@ namespace {
 
 struct Layout {
     size_t hdr, states, f, g, slot_pos, pos_slot, p_att, p_acc, b_att, b_acc, best, trace_f,
-        trace_g, mut_end, mbox, slot_key, slot_best, hit_min, scratch_end;
+        trace_g, hist, mut_end, mbox, slot_key, slot_best, hit_min, scratch_end;
     size_t beta, p_q, nbi, nbj, chp, nb_idx, nb_J, ch_idx, bias, orig, nb_pos, ch_pos, h0, cn_idx, cn_w, kh,
-        total;
+        hist_rank, total;
     int32_t stride, wd;
 };
 
@@ -156,7 +163,8 @@ bool use_narrow(const tdpt_instance *in, const tdpt_run_cfg *cfg)
            in->max_field + 2 * pmax * in->max_cfield < ((int64_t)1 << 22) && in->max_cfield < ((int64_t)1 << 22);
 }
 
-Layout make_layout(const tdpt_instance *in, int32_t I, int32_t J, int64_t trace_cap, bool narrow)
+Layout make_layout(const tdpt_instance *in, int32_t I, int32_t J, int64_t trace_cap, bool narrow,
+                   int32_t hist_n)
 {
     Layout L{};
     const size_t R = (size_t)I * J;
@@ -182,6 +190,7 @@ Layout make_layout(const tdpt_instance *in, int32_t I, int32_t J, int64_t trace_
     L.best = take((size_t)L.stride);
     L.trace_f = take((size_t)trace_cap * 8 + 8);
     L.trace_g = take((size_t)trace_cap * 8 + 8);
+    L.hist = take(hist_n ? ((size_t)4 << hist_n) : 8);
     L.mut_end = o;
     L.mbox = take((size_t)tdpt::kRing * R * 16);
     L.slot_key = take(R * 8);
@@ -226,8 +235,23 @@ Layout make_layout(const tdpt_instance *in, int32_t I, int32_t J, int64_t trace_
     }
     L.bias = take((size_t)in->n_pad * 4);
     L.orig = take((size_t)in->n_pad * 4);
+    L.hist_rank = take((size_t)hist_n * 4 + 4);
     L.total = o;
     return L;
+}
+
+// Logical variables of the per-round state histogram a configuration asks
+// for (0: none).
+int hist_vars(const tdpt_instance *in, const tdpt_run_cfg *cfg, int32_t *nv)
+{
+    *nv = 0;
+    if (!cfg->hist_logical) return TDPT_OK;
+    if (in->n_logical < 1)
+        return fail(TDPT_E_INVALID, "a logical-state histogram needs logical_of at instance creation");
+    if (in->n_logical > tdpt::kMaxHistVars)
+        return fail(TDPT_E_INVALID, "a logical-state histogram takes at most 20 logical variables");
+    *nv = in->n_logical;
+    return TDPT_OK;
 }
 
 int check_cfg(const tdpt_run_cfg *c)
@@ -426,9 +450,33 @@ extern "C" {
 
 const char *tdpt_last_error(void) { return g_err.c_str(); }
 
+// The logical variable of every physical spin (values 0 .. N-1, each used):
+// variable k is read from its lowest-numbered spin.
+static int set_logical(tdpt_instance *in, const int32_t *logical_of)
+{
+    if (!logical_of) return TDPT_OK;
+    const int32_t n = in->n;
+    int32_t N = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        if (logical_of[v] < 0 || logical_of[v] >= n)
+            return fail(TDPT_E_INVALID, "logical_of[" + std::to_string(v) + "] out of range");
+        N = std::max(N, logical_of[v] + 1);
+    }
+    in->first_copy.assign(N, -1);
+    for (int32_t v = n - 1; v >= 0; --v) in->first_copy[logical_of[v]] = v;
+    for (int32_t k = 0; k < N; ++k)
+        if (in->first_copy[k] < 0)
+            return fail(TDPT_E_INVALID, "logical variable " + std::to_string(k) + " has no spin");
+    in->first_rank.resize(N);
+    for (int32_t k = 0; k < N; ++k) in->first_rank[k] = in->rank[in->first_copy[k]];
+    in->n_logical = N;
+    return TDPT_OK;
+}
+
 int tdpt_instance_create(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *J_q,
                          const int32_t *b_q, int32_t m, const int32_t *copy_a,
-                         const int32_t *copy_b, const int32_t *color, tdpt_instance **out)
+                         const int32_t *copy_b, const int32_t *color, const int32_t *logical_of,
+                         tdpt_instance **out)
 {
     if (!out) return fail(TDPT_E_INVALID, "out is NULL");
     *out = nullptr;
@@ -481,6 +529,11 @@ int tdpt_instance_create(int32_t n, const int32_t *row_ptr, const int32_t *col, 
     // half the penalty field is the copy sum (|.| <= 2); g <= 4 m
     in->max_cfield = 2;
     in->g_bound = 4 * (int64_t)m;
+    rc = set_logical(in, logical_of);
+    if (rc) {
+        delete in;
+        return rc;
+    }
     *out = in;
     return TDPT_OK;
 }
@@ -489,7 +542,7 @@ int tdpt_instance_create_terms(int32_t n, const int32_t *row_ptr, const int32_t 
                                const int32_t *J_q, const int32_t *b_q, int32_t n_terms,
                                const int32_t *term_ptr, const int32_t *term_idx,
                                const int32_t *term_coef, const int32_t *term_const,
-                               const int32_t *color, tdpt_instance **out)
+                               const int32_t *color, const int32_t *logical_of, tdpt_instance **out)
 {
     if (!out) return fail(TDPT_E_INVALID, "out is NULL");
     *out = nullptr;
@@ -594,6 +647,10 @@ int tdpt_instance_create_terms(int32_t n, const int32_t *row_ptr, const int32_t 
     in->g0 = (int64_t)g0;
     in->max_cfield = max_cfield;
     in->g_bound = g_bound;
+    if (int rc2 = set_logical(in, logical_of)) {
+        delete in;
+        return rc2;
+    }
     *out = in;
     return TDPT_OK;
 }
@@ -611,6 +668,7 @@ int tdpt_instance_info_get(const tdpt_instance *in, tdpt_instance_info *out)
     out->m = in->m;
     out->n_terms = in->n_terms;
     out->max_constraint_degree = in->max_cons_deg;
+    out->n_logical = in->n_logical;
     return TDPT_OK;
 }
 
@@ -621,7 +679,10 @@ int tdpt_workspace_bytes(const tdpt_instance *in, const tdpt_run_cfg *cfg, size_
     if (!in || !bytes) return fail(TDPT_E_INVALID, "NULL argument");
     int rc = check_cfg(cfg);
     if (rc) return rc;
-    *bytes = make_layout(in, cfg->n_beta, cfg->n_p, cfg->trace_cap, use_narrow(in, cfg)).total;
+    int32_t hist_n = 0;
+    rc = hist_vars(in, cfg, &hist_n);
+    if (rc) return rc;
+    *bytes = make_layout(in, cfg->n_beta, cfg->n_p, cfg->trace_cap, use_narrow(in, cfg), hist_n).total;
     return TDPT_OK;
 }
 
@@ -637,7 +698,10 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     if (((uintptr_t)dev_ws) % 256) return fail(TDPT_E_INVALID, "workspace must be 256-byte aligned");
     const int32_t I = cfg->n_beta, J = cfg->n_p, R = I * J;
     const bool narrow = use_narrow(in, cfg);
-    const Layout L = make_layout(in, I, J, cfg->trace_cap, narrow);
+    int32_t hist_n = 0;
+    rc = hist_vars(in, cfg, &hist_n);
+    if (rc) return rc;
+    const Layout L = make_layout(in, I, J, cfg->trace_cap, narrow, hist_n);
     if (ws_bytes < L.total)
         return fail(TDPT_E_NOMEM, "workspace holds " + std::to_string(ws_bytes) + " bytes, needs " +
                                       std::to_string(L.total));
@@ -765,6 +829,11 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     d.slot_key = (int64_t *)(ws + L.slot_key);
     d.slot_best = (int8_t *)(ws + L.slot_best);
     d.hit_min = (int64_t *)(ws + L.hit_min);
+    d.hist_n = hist_n;
+    d.hist_rank = (const int32_t *)(ws + L.hist_rank);
+    d.hist = (uint32_t *)(ws + L.hist);
+    p->n_logical = in->n_logical;
+    p->first_copy = in->first_copy;
 
     hipStream_t s = p->stream;
     auto cleanup = [&](int code) {
@@ -781,6 +850,7 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     } while (0)
     UP(ws + L.beta, cfg->beta, (size_t)I * 8);
     UP(ws + L.p_q, cfg->p_q, (size_t)J * 4);
+    if (hist_n) UP(ws + L.hist_rank, in->first_rank.data(), (size_t)hist_n * 4);
     if (narrow) {
         // neighbour pairs (2k, 2k+1): indices as 16+16 bits, couplings as int16 pairs
         const int32_t n_pad = in->n_pad, wd = in->wd, pairs = L.wd / 2;
@@ -898,7 +968,9 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     // the persistent driver needs every slot's block resident at once
     p->persistent = false;
     const char *pe = getenv("TDPT_PERSISTENT");
-    p->persistent_ok = !(pe && pe[0] == '0') && !bits && in->abs_f_bound < tdpt::kKeyOffset;
+    // its best-state keys need |f| < 2^30, its mailboxes carry f and g in 48 bits
+    p->persistent_ok = !(pe && pe[0] == '0') && !bits && in->abs_f_bound < tdpt::kKeyOffset &&
+                       in->g_bound < ((int64_t)1 << 47);
     if (p->persistent_ok) {
         tdpt::DevProblem dq = d;
         dq.block = sweep_block(in, true);
@@ -913,6 +985,35 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     *out = p;
     return TDPT_OK;
 }
+
+// Structure layout of a problem, which selects its sweep kernel instance:
+// problems of one batch group share it.
+struct GroupKey {
+    int bits, narrow, packed_gen, wd;
+    bool operator==(const GroupKey &o) const
+    {
+        return bits == o.bits && narrow == o.narrow && packed_gen == o.packed_gen && wd == o.wd;
+    }
+    // batch order: int8 before bit-packed, packed before wide, copy edges
+    // before general constraints, narrower rows first
+    bool operator<(const GroupKey &o) const
+    {
+        if (bits != o.bits) return bits < o.bits;
+        if (narrow != o.narrow) return narrow > o.narrow;
+        if (packed_gen != o.packed_gen) return packed_gen < o.packed_gen;
+        return wd < o.wd;
+    }
+    int32_t code() const { return bits | narrow << 1 | packed_gen << 2 | wd << 3; }
+};
+
+static GroupKey group_key(const tdpt::DevProblem &d)
+{
+    return GroupKey{d.bits ? 1 : 0, d.narrow ? 1 : 0, (d.narrow && d.gen) ? 1 : 0, d.wd};
+}
+
+// Membership of problems in batches (defined with the batches below).
+static int member_busy(tdpt_problem *p);
+static void leave_batch(tdpt_problem *p);
 
 // Record a timing event pair around the next launch if it is sampled.
 static int timing_begin(tdpt_problem *p, std::pair<hipEvent_t, hipEvent_t> &ev, bool &timed)
@@ -931,6 +1032,7 @@ int tdpt_problem_run(tdpt_problem *p, int64_t n_rounds)
 {
     if (!p) return fail(TDPT_E_INVALID, "problem is NULL");
     if (n_rounds < 0) return fail(TDPT_E_INVALID, "n_rounds must be >= 0");
+    if (int rc = member_busy(p)) return rc;
     // the sweep index is a 32-bit Philox counter word
     if ((p->rounds_host + n_rounds) * (int64_t)p->mcs > ((int64_t)1 << 32))
         return fail(TDPT_E_RANGE, "a problem runs at most 2^32 sweeps");
@@ -1010,6 +1112,7 @@ int tdpt_problem_autotune(tdpt_problem *p, int32_t rounds_per_trial, tdpt_tune_r
 {
     if (!p || !out) return fail(TDPT_E_INVALID, "NULL argument");
     if (rounds_per_trial < 1) return fail(TDPT_E_INVALID, "rounds_per_trial must be >= 1");
+    if (int rc = member_busy(p)) return rc;
     constexpr int kMaxTrials = 32;
     // the trials run (temporarily) up to kMaxTrials * (1 + rounds_per_trial) rounds
     if ((p->rounds_host + kMaxTrials * (1 + (int64_t)rounds_per_trial)) * (int64_t)p->mcs > ((int64_t)1 << 32))
@@ -1097,7 +1200,8 @@ int tdpt_problem_query(tdpt_problem *p, tdpt_status *out)
     if (h[tdpt::kHdrError] == 2)
         return fail(TDPT_E_DEVICE, "a sweep kernel found its LDS replica away from address 0 and did not run");
     if (h[tdpt::kHdrError])
-        return fail(TDPT_E_DEVICE, "a persistent launch timed out at a grid barrier (blocks not co-resident)");
+        return fail(TDPT_E_DEVICE, "a persistent launch gave up after 2 s waiting for a swap partner's "
+                                   "mailbox (blocks not co-resident, or partners disagreeing on a swap)");
     out->rounds_done = h[tdpt::kHdrRounds];
     out->driver = p->persistent ? 1 : 0;
     out->sweeps_done = h[tdpt::kHdrRounds] * p->mcs;
@@ -1189,6 +1293,79 @@ int tdpt_problem_read_trace(tdpt_problem *p, int64_t *f_q, int64_t *g, int64_t *
     return rc;
 }
 
+int tdpt_problem_read_best_logical(tdpt_problem *p, int8_t *x, int64_t *f_q, int64_t *sweep)
+{
+    if (!p) return fail(TDPT_E_INVALID, "NULL argument");
+    if (x && p->n_logical == 0)
+        return fail(TDPT_E_STATE, "the instance was created without logical_of");
+    std::vector<int8_t> s(x ? (size_t)p->n : 0);
+    int rc = tdpt_problem_read_best(p, x ? s.data() : nullptr, f_q, sweep);
+    if (rc) return rc;
+    if (x)
+        for (int32_t k = 0; k < p->n_logical; ++k) x[k] = s[p->first_copy[k]];
+    return TDPT_OK;
+}
+
+int tdpt_problem_read_histogram(tdpt_problem *p, uint32_t *counts, int64_t *samples)
+{
+    if (!p || !counts) return fail(TDPT_E_INVALID, "NULL argument");
+    if (!p->dp.hist_n) return fail(TDPT_E_STATE, "the run configuration asked for no histogram");
+    int64_t h[tdpt::kHdrWords];
+    int rc = d2h(p, h, p->dp.hdr, sizeof(h));
+    if (!rc) rc = d2h(p, counts, p->dp.hist, (size_t)4 << p->dp.hist_n);
+    if (!rc && samples) *samples = h[tdpt::kHdrRounds];
+    return rc;
+}
+
+int tdpt_problem_read_energies_async(tdpt_problem *p, int64_t *dev_f_q, int64_t *dev_g)
+{
+    if (!p || (!dev_f_q && !dev_g)) return fail(TDPT_E_INVALID, "NULL argument");
+    HIP_TRY(tdpt::launch_gather_energies(p->dp, dev_f_q, dev_g, p->stream), "launch gather");
+    return TDPT_OK;
+}
+
+int tdpt_problem_read_states_async(tdpt_problem *p, int8_t *dev_s)
+{
+    if (!p || !dev_s) return fail(TDPT_E_INVALID, "NULL argument");
+    HIP_TRY(tdpt::launch_gather_states(p->dp, p->n, dev_s, p->stream), "launch gather");
+    return TDPT_OK;
+}
+
+int tdpt_problem_read_best_async(tdpt_problem *p, int8_t *dev_s, int64_t *dev_f_sweep)
+{
+    if (!p || (!dev_s && !dev_f_sweep)) return fail(TDPT_E_INVALID, "NULL argument");
+    if (dev_s) HIP_TRY(tdpt::launch_gather_best(p->dp, dev_s, p->stream), "launch gather");
+    if (dev_f_sweep)
+        HIP_TRY(hipMemcpyAsync(dev_f_sweep, p->dp.hdr + tdpt::kHdrBestF, 2 * sizeof(int64_t),
+                               hipMemcpyDeviceToDevice, p->stream), "copy best");
+    return TDPT_OK;
+}
+
+int tdpt_problem_query_async(tdpt_problem *p, int64_t *dev_words)
+{
+    if (!p || !dev_words) return fail(TDPT_E_INVALID, "NULL argument");
+    static_assert(tdpt::kHdrRounds == 0 && tdpt::kHdrFirstHit == 1 && tdpt::kHdrBestF == 2 &&
+                      tdpt::kHdrBestSweep == 3, "header word order");
+    HIP_TRY(hipMemcpyAsync(dev_words, p->dp.hdr, 4 * sizeof(int64_t), hipMemcpyDeviceToDevice, p->stream),
+            "copy status");
+    return TDPT_OK;
+}
+
+int tdpt_layout_get(const tdpt_instance *in, const tdpt_run_cfg *cfg, tdpt_layout *out)
+{
+    if (!in || !out) return fail(TDPT_E_INVALID, "NULL argument");
+    int rc = check_cfg(cfg);
+    if (rc) return rc;
+    const bool narrow = use_narrow(in, cfg);
+    const Layout L = make_layout(in, cfg->n_beta, cfg->n_p, cfg->trace_cap, narrow, 0);
+    out->bits = use_bits(in) ? 1 : 0;
+    out->narrow = narrow ? 1 : 0;
+    out->general = in->gen ? 1 : 0;
+    out->ell_width = L.wd;
+    out->group_key = GroupKey{out->bits, out->narrow, (narrow && in->gen) ? 1 : 0, L.wd}.code();
+    return TDPT_OK;
+}
+
 static const uint64_t kCkptMagic = 0x3154504454324454ull;  // "TD2TDPT1"
 
 int tdpt_problem_save(tdpt_problem *p, void *host, size_t *bytes)
@@ -1209,6 +1386,7 @@ int tdpt_problem_save(tdpt_problem *p, void *host, size_t *bytes)
 int tdpt_problem_load(tdpt_problem *p, const void *host, size_t bytes)
 {
     if (!p || !host) return fail(TDPT_E_INVALID, "NULL argument");
+    if (int rc = member_busy(p)) return rc;
     if (bytes != 16 + p->mut_bytes) return fail(TDPT_E_INVALID, "checkpoint size does not match the problem");
     uint64_t head[2];
     memcpy(head, host, 16);
@@ -1227,7 +1405,12 @@ int tdpt_problem_load(tdpt_problem *p, const void *host, size_t bytes)
     return TDPT_OK;
 }
 
-void tdpt_problem_destroy(tdpt_problem *p) { delete p; }
+void tdpt_problem_destroy(tdpt_problem *p)
+{
+    if (!p) return;
+    leave_batch(p);
+    delete p;
+}
 
 // ------------------------------------------------------------------ batches
 
@@ -1263,6 +1446,9 @@ struct tdpt_batch {
     static constexpr int kAux = 7;
     hipStream_t aux[kAux] = {};
     hipEvent_t fork = nullptr, join[kAux] = {};
+    // a member was destroyed or moved to another batch: the device table
+    // names it, so runs wait for tdpt_batch_set_members
+    bool stale = false;
     void drop_graph()
     {
         if (graph) (void)hipGraphExecDestroy(graph);
@@ -1270,6 +1456,8 @@ struct tdpt_batch {
     }
     ~tdpt_batch()
     {
+        if (done) (void)hipEventSynchronize(done);
+        for (auto *p : members) p->batch = nullptr;
         drop_graph();
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (int k = 0; k < kAux; ++k) {
@@ -1282,6 +1470,31 @@ struct tdpt_batch {
 };
 
 static size_t batch_table_bytes(int32_t cap) { return align_up((size_t)cap * sizeof(tdpt::DevProblem), 256); }
+
+// TDPT_E_BUSY while the last run of the batch holding p has not finished.
+static int member_busy(tdpt_problem *p)
+{
+    if (!p->batch) return TDPT_OK;
+    const hipError_t e = hipEventQuery(p->batch->done);
+    if (e == hipErrorNotReady)
+        return fail(TDPT_E_BUSY, "the problem's batch has a run in flight (wait with a read or query call)");
+    if (e != hipSuccess) return hip_fail(e, "hipEventQuery");
+    return TDPT_OK;
+}
+
+// Take p out of its batch (after the batch's work in flight): the batch's
+// device table still names p, so the batch needs new members before it runs.
+static void leave_batch(tdpt_problem *p)
+{
+    tdpt_batch *b = p->batch;
+    if (!b) return;
+    (void)hipEventSynchronize(b->done);
+    b->members.erase(std::remove(b->members.begin(), b->members.end(), p), b->members.end());
+    b->stale = true;
+    b->drop_graph();
+    p->batch = nullptr;
+}
+
 
 // Whether the persistent driver runs this batch: every member allows it, no
 // group is bit-packed, and each group's workgroups fit the GPU at once.
@@ -1448,32 +1661,34 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
     }
     for (auto *p : m) HIP_TRY(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
     HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
-    // group by structure layout (kernel instance: the packed layout has
-    // separate instances for copy edges and general constraints), largest
+    // On any failure below the batch is left empty (and its old members
+    // released), never half replaced.
+    auto empty_batch = [&]() {
+        for (auto *p : b->members) p->batch = nullptr;
+        b->members.clear();
+        b->groups.clear();
+        b->persistent = false;
+        b->stale = false;
+    };
+    // group by structure layout (the sweep kernel instance), largest
     // replicas first
-    auto packed_gen = [](const tdpt_problem *x) { return x->dp.narrow && x->dp.gen; };
     std::stable_sort(m.begin(), m.end(), [&](const tdpt_problem *x, const tdpt_problem *y) {
-        if (x->dp.bits != y->dp.bits) return x->dp.bits < y->dp.bits;
-        if (x->dp.narrow != y->dp.narrow) return x->dp.narrow > y->dp.narrow;
-        if (packed_gen(x) != packed_gen(y)) return packed_gen(x) < packed_gen(y);
-        if (x->dp.wd != y->dp.wd) return x->dp.wd < y->dp.wd;
+        const GroupKey kx = group_key(x->dp), ky = group_key(y->dp);
+        if (!(kx == ky)) return kx < ky;
         return x->dp.stride > y->dp.stride;
     });
     b->drop_graph();
-    b->members = m;
-    b->groups.clear();
+    empty_batch();
+    std::vector<tdpt_batch::Group> groups;
     std::vector<tdpt::DevProblem> table(m.size());
     std::vector<int32_t> prefix;
     for (size_t i = 0; i < m.size(); ++i) {
         table[i] = m[i]->dp;
-        const bool start = b->groups.empty() || m[i]->dp.bits != m[i - 1]->dp.bits ||
-                           m[i]->dp.narrow != m[i - 1]->dp.narrow || m[i]->dp.wd != m[i - 1]->dp.wd ||
-                           packed_gen(m[i]) != packed_gen(m[i - 1]);
-        if (start) {
+        if (groups.empty() || !(group_key(m[i]->dp) == group_key(m[i - 1]->dp))) {
             tdpt_batch::Group g{(int)i, 0, 0, (int)prefix.size(), 0, 0, 0, 64, 0};
-            b->groups.push_back(g);
+            groups.push_back(g);
         }
-        auto &g = b->groups.back();
+        auto &g = groups.back();
         g.min_block = std::max(g.min_block, m[i]->min_block);
         prefix.push_back(g.blocks);
         g.blocks += m[i]->dp.bits ? (m[i]->R + tdpt::kBitSlots - 1) / tdpt::kBitSlots : m[i]->R;
@@ -1482,25 +1697,32 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
         g.max_words = std::max(g.max_words, m[i]->dp.n_words);
         g.plds = std::max(g.plds, tdpt::persistent_lds_bytes(m[i]->dp.stride, m[i]->I, m[i]->J));
     }
-    for (auto &g : b->groups) {
-        const int cap = b->members[g.first_member]->dp.bits ? tdpt::kBitsBlock : tdpt::kMaxBlock;
-        if (g.min_block > cap) {
-            b->members.clear();
-            b->groups.clear();
+    // every group runs one kernel instance over its members' descriptors:
+    // refuse a group whose members would need different instances
+    for (auto &g : groups)
+        for (int k = g.first_member + 1; k < g.first_member + g.count; ++k)
+            if (!(group_key(m[k]->dp) == group_key(m[g.first_member]->dp)))
+                return fail(TDPT_E_INVALID, "internal: a batch group mixes structure layouts");
+    for (auto &g : groups) {
+        const int cap = m[g.first_member]->dp.bits ? tdpt::kBitsBlock : tdpt::kMaxBlock;
+        if (g.min_block > cap)
             return fail(TDPT_E_RANGE, "a member's per-phase energy bounds need a larger workgroup than "
                                       "the batched sweep allows");
-        }
         // per-round default: the batch's workgroup size for byte layouts; for
         // bit-packed groups the members' own (their sweep wants every thread
         // a compute unit can hold next to one 4-replica workgroup)
         int def = b->block;
-        if (b->members[g.first_member]->dp.bits) {
+        if (m[g.first_member]->dp.bits) {
             def = 64;
-            for (int k = g.first_member; k < g.first_member + g.count; ++k)
-                def = std::max(def, b->members[k]->dp.block);
+            for (int k = g.first_member; k < g.first_member + g.count; ++k) def = std::max(def, m[k]->dp.block);
         }
         g.block = std::min(std::max(def, g.min_block), cap);
     }
+    // members that move here from another batch leave it first
+    for (auto *p : m)
+        if (p->batch && p->batch != b) leave_batch(p);
+    b->members = m;
+    b->groups = groups;
     // the persistent driver when every group fits at once (with the members'
     // own workgroup sizes), else per-round launches with the batch default
     {
@@ -1513,17 +1735,30 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
             g.block = std::min(want, tdpt::kMaxBlock / 2);
         }
         int rc = batch_decide_mode(b);
-        if (rc) return rc;
+        if (rc) {
+            b->members.clear();
+            b->groups.clear();
+            b->persistent = false;
+            return rc;
+        }
         if (!b->persistent)
             for (size_t gi = 0; gi < b->groups.size(); ++gi) b->groups[gi].block = per_round_blocks[gi];
     }
     if (!m.empty()) {
-        HIP_TRY(hipMemcpyAsync(b->ws, table.data(), table.size() * sizeof(tdpt::DevProblem),
-                               hipMemcpyHostToDevice, b->stream), "upload batch table");
-        HIP_TRY(hipMemcpyAsync(b->ws + batch_table_bytes(b->cap), prefix.data(), prefix.size() * 4,
-                               hipMemcpyHostToDevice, b->stream), "upload batch table");
-        HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+        hipError_t e = hipMemcpyAsync(b->ws, table.data(), table.size() * sizeof(tdpt::DevProblem),
+                                      hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->ws + batch_table_bytes(b->cap), prefix.data(), prefix.size() * 4,
+                               hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) {
+            b->members.clear();
+            b->groups.clear();
+            b->persistent = false;
+            return hip_fail(e, "upload batch table");
+        }
     }
+    for (auto *p : m) p->batch = b;
     return TDPT_OK;
 }
 
@@ -1531,6 +1766,8 @@ int tdpt_batch_run(tdpt_batch *b, int64_t n_rounds)
 {
     if (!b) return fail(TDPT_E_INVALID, "batch is NULL");
     if (n_rounds < 0) return fail(TDPT_E_INVALID, "n_rounds must be >= 0");
+    if (b->stale)
+        return fail(TDPT_E_STATE, "a member was destroyed or joined another batch: set the members again");
     if (n_rounds == 0 || b->members.empty()) return TDPT_OK;
     for (auto *p : b->members)
         if ((p->rounds_host + n_rounds) * (int64_t)p->mcs > ((int64_t)1 << 32))

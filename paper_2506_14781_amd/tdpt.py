@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_build", "libtdpt.so")
 
-OK, E_INVALID, E_RANGE, E_NOMEM, E_DEVICE, E_STATE = range(6)
+OK, E_INVALID, E_RANGE, E_NOMEM, E_DEVICE, E_STATE, E_BUSY = range(7)
 NO_PSWAP = 1
 
 EXPORTED = [
@@ -29,6 +29,9 @@ EXPORTED = [
     "tdpt_batch_workspace_bytes", "tdpt_batch_create", "tdpt_batch_set_members",
     "tdpt_batch_run", "tdpt_batch_destroy", "tdpt_problem_autotune", "tdpt_batch_autotune",
     "tdpt_batch_set_graph", "tdpt_batch_set_driver", "tdpt_batch_query_driver",
+    "tdpt_layout_get", "tdpt_problem_query_async", "tdpt_problem_read_energies_async",
+    "tdpt_problem_read_states_async", "tdpt_problem_read_best_async", "tdpt_problem_read_best_logical",
+    "tdpt_problem_read_histogram",
 ]
 
 
@@ -45,7 +48,7 @@ class _RunCfg(ctypes.Structure):
         ("mcs_per_swap", ctypes.c_int32), ("seed", ctypes.c_uint64),
         ("s0", ctypes.c_void_p), ("has_target", ctypes.c_int32),
         ("f_target_q", ctypes.c_int64), ("flags", ctypes.c_uint32),
-        ("trace_cap", ctypes.c_int64),
+        ("trace_cap", ctypes.c_int64), ("hist_logical", ctypes.c_int32),
     ]
 
 
@@ -53,7 +56,13 @@ class _Info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("n_pad", ctypes.c_int32), ("n_colors", ctypes.c_int32),
                 ("max_degree", ctypes.c_int32), ("max_copy_degree", ctypes.c_int32),
                 ("narrow", ctypes.c_int32), ("nnz", ctypes.c_int64), ("m", ctypes.c_int32),
-                ("n_terms", ctypes.c_int32), ("max_constraint_degree", ctypes.c_int32)]
+                ("n_terms", ctypes.c_int32), ("max_constraint_degree", ctypes.c_int32),
+                ("n_logical", ctypes.c_int32)]
+
+
+class _Layout(ctypes.Structure):
+    _fields_ = [("bits", ctypes.c_int32), ("narrow", ctypes.c_int32), ("general", ctypes.c_int32),
+                ("ell_width", ctypes.c_int32), ("group_key", ctypes.c_int32)]
 
 
 class _TuneReport(ctypes.Structure):
@@ -88,8 +97,15 @@ def load_library():
     lib = ctypes.CDLL(LIB_PATH)
     P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     sig = {
-        "tdpt_instance_create": [I32, P, P, P, P, I32, P, P, P, P],
-        "tdpt_instance_create_terms": [I32, P, P, P, P, I32, P, P, P, P, P, P],
+        "tdpt_instance_create": [I32, P, P, P, P, I32, P, P, P, P, P],
+        "tdpt_instance_create_terms": [I32, P, P, P, P, I32, P, P, P, P, P, P, P],
+        "tdpt_layout_get": [P, P, P],
+        "tdpt_problem_query_async": [P, P],
+        "tdpt_problem_read_energies_async": [P, P, P],
+        "tdpt_problem_read_states_async": [P, P],
+        "tdpt_problem_read_best_async": [P, P, P],
+        "tdpt_problem_read_best_logical": [P, P, P, P],
+        "tdpt_problem_read_histogram": [P, P, P],
         "tdpt_instance_info_get": [P, P],
         "tdpt_workspace_bytes": [P, P, P],
         "tdpt_problem_create": [P, P, P, SZ, P, P],
@@ -140,6 +156,11 @@ def _ptr(a):
     return None if a is None else ctypes.c_void_p(a.ctypes.data)
 
 
+def _dptr(t):
+    """Device address of a torch tensor (None stays NULL)."""
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
 def _arr(a, dt):
     return None if a is None else np.ascontiguousarray(a, dtype=dt)
 
@@ -151,38 +172,47 @@ class Instance:
     (terms = (term_ptr, term_idx, term_coef, term_const)); see
     tdpt_instance_create_terms."""
 
-    def __init__(self, n, row_ptr, col, J_q, b_q, copy_a, copy_b, color, terms=None):
+    def __init__(self, n, row_ptr, col, J_q, b_q, copy_a, copy_b, color, terms=None, logical_of=None):
         lib = load_library()
         self._keep = [_arr(row_ptr, np.int32), _arr(col, np.int32), _arr(J_q, np.int32),
                       _arr(b_q, np.int32), _arr(copy_a, np.int32), _arr(copy_b, np.int32),
-                      _arr(color, np.int32)]
-        rp, cl, jq, bq, ca, cb, co = self._keep
+                      _arr(color, np.int32), _arr(logical_of, np.int32)]
+        rp, cl, jq, bq, ca, cb, co, lo = self._keep
         h = ctypes.c_void_p()
         if terms is not None:
             tp, ti, tc, td = (_arr(x, np.int32) for x in terms)
             self._keep += [tp, ti, tc, td]
             _check(lib.tdpt_instance_create_terms(int(n), _ptr(rp), _ptr(cl), _ptr(jq), _ptr(bq),
                                                   int(tp.shape[0]) - 1, _ptr(tp), _ptr(ti), _ptr(tc),
-                                                  _ptr(td), _ptr(co), ctypes.byref(h)))
+                                                  _ptr(td), _ptr(co), _ptr(lo), ctypes.byref(h)))
         else:
             m = 0 if ca is None else int(ca.shape[0])
             _check(lib.tdpt_instance_create(int(n), _ptr(rp), _ptr(cl), _ptr(jq), _ptr(bq), m,
-                                            _ptr(ca), _ptr(cb), _ptr(co), ctypes.byref(h)))
+                                            _ptr(ca), _ptr(cb), _ptr(co), _ptr(lo), ctypes.byref(h)))
         self._h = h
         self.n = int(n)
 
     @classmethod
-    def from_synth(cls, inst):
+    def from_synth(cls, inst, logical=False):
+        """From a synth Instance; logical=True also passes its logical_of."""
         terms = None
         if getattr(inst, "term_ptr", None) is not None:
             terms = (inst.term_ptr, inst.term_idx, inst.term_coef, inst.term_const)
         return cls(inst.n, inst.row_ptr, inst.col, inst.J_q, inst.b_q, inst.copy_a,
-                   inst.copy_b, inst.color, terms=terms)
+                   inst.copy_b, inst.color, terms=terms,
+                   logical_of=inst.logical_of if logical else None)
 
     def info(self) -> dict:
         out = _Info()
         _check(load_library().tdpt_instance_info_get(self._h, ctypes.byref(out)))
         return {k: getattr(out, k) for k, _ in _Info._fields_}
+
+    def layout(self, cfg: "RunConfig") -> dict:
+        """The structure layout (and batch group key) a problem would run with."""
+        out = _Layout()
+        c = cfg._c()
+        _check(load_library().tdpt_layout_get(self._h, ctypes.byref(c), ctypes.byref(out)))
+        return {k: getattr(out, k) for k, _ in _Layout._fields_}
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -193,7 +223,7 @@ class Instance:
 
 class RunConfig:
     def __init__(self, beta, p_q, *, mcs_per_swap, seed, s0=None, f_target=None, flags=0,
-                 trace_cap=0):
+                 trace_cap=0, hist_logical=False):
         self.beta = _arr(beta, np.float64)
         self.p_q = _arr(p_q, np.int32)
         self.s0 = None if s0 is None else _arr(s0, np.int8).reshape(-1)
@@ -202,6 +232,7 @@ class RunConfig:
         self.f_target = f_target
         self.flags = int(flags)
         self.trace_cap = int(trace_cap)
+        self.hist_logical = bool(hist_logical)
 
     def _c(self):
         c = _RunCfg()
@@ -216,6 +247,7 @@ class RunConfig:
         c.f_target_q = 0 if self.f_target is None else int(self.f_target)
         c.flags = self.flags
         c.trace_cap = self.trace_cap
+        c.hist_logical = 1 if self.hist_logical else 0
         return c
 
     @property
@@ -250,6 +282,7 @@ class Problem:
                                        ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
                                        ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
         self._h = h
+        self.n_logical = instance.info()["n_logical"]
 
     def run(self, n_rounds: int):
         _check(_lib.tdpt_problem_run(self._h, int(n_rounds)))
@@ -281,6 +314,40 @@ class Problem:
         w = np.zeros(1, dtype=np.int64)
         _check(_lib.tdpt_problem_read_best(self._h, _ptr(s), _ptr(f), _ptr(w)))
         return s, int(f[0]), int(w[0])
+
+    def best_logical(self):
+        """The best feasible bottom-right state decoded to its logical
+        variables (each read from its lowest-numbered copy), its f_q, sweep."""
+        x = np.zeros(max(self.n_logical, 1), dtype=np.int8)
+        f = np.zeros(1, dtype=np.int64)
+        w = np.zeros(1, dtype=np.int64)
+        _check(_lib.tdpt_problem_read_best_logical(self._h, _ptr(x), _ptr(f), _ptr(w)))
+        return x[:self.n_logical], int(f[0]), int(w[0])
+
+    def histogram(self):
+        """(counts[2^N], samples) of the bottom-right replica's logical state,
+        one sample per round (RunConfig(hist_logical=True))."""
+        counts = np.zeros(1 << self.n_logical, dtype=np.uint32)
+        k = np.zeros(1, dtype=np.int64)
+        _check(_lib.tdpt_problem_read_histogram(self._h, _ptr(counts), _ptr(k)))
+        return counts, int(k[0])
+
+    def energies_async(self, f, g):
+        """Enqueue f, g per position into device tensors (int64[R]) on the
+        problem's stream."""
+        _check(_lib.tdpt_problem_read_energies_async(self._h, _dptr(f), _dptr(g)))
+
+    def states_async(self, s):
+        """Enqueue the states per position into a device tensor (int8[R, n])."""
+        _check(_lib.tdpt_problem_read_states_async(self._h, _dptr(s)))
+
+    def best_async(self, s, f_sweep):
+        """Enqueue the best state (int8[n]) and (best_f_q, best_sweep) (int64[2])."""
+        _check(_lib.tdpt_problem_read_best_async(self._h, _dptr(s), _dptr(f_sweep)))
+
+    def query_async(self, words):
+        """Enqueue rounds_done, first_hit_sweep, best_f_q, best_sweep (int64[4])."""
+        _check(_lib.tdpt_problem_query_async(self._h, _dptr(words)))
 
     def counters(self):
         I, J = self.I, self.J

@@ -205,3 +205,66 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     from synth.configs import wishart_small
     with pytest.raises(RuntimeError, match="missing"):
         TD.Instance.from_synth(wishart_small().instance)
+
+
+def test_logical_of_is_validated_and_reported():
+    w = wishart_small().instance
+    a = T.Instance.from_synth(w, logical=True).info()
+    assert a["n_logical"] == 12
+    assert T.Instance.from_synth(w).info()["n_logical"] == 0
+    bad = w.logical_of.copy()
+    bad[3] = w.n  # out of range
+    with pytest.raises(T.TdptError, match="logical_of"):
+        _mk(w, logical_of=bad)
+    gap = w.logical_of.copy()
+    gap[gap == 5] = 6  # variable 5 has no spin left
+    with pytest.raises(T.TdptError, match="logical variable 5"):
+        _mk(w, logical_of=gap)
+
+
+def test_histogram_needs_a_small_logical_map():
+    w = wishart_small()
+    cfg = T.RunConfig(w.beta, w.p_q, mcs_per_swap=1, seed=0, hist_logical=True)
+    with pytest.raises(T.TdptError, match="logical_of"):
+        T.workspace_bytes(T.Instance.from_synth(w.instance), cfg)
+    with_map = T.Instance.from_synth(w.instance, logical=True)
+    plain = T.RunConfig(w.beta, w.p_q, mcs_per_swap=1, seed=0)
+    # 2^12 four-byte bins in place of an 8-byte stub (both rounded to 256 bytes)
+    assert T.workspace_bytes(with_map, cfg) == T.workspace_bytes(with_map, plain) + 4 * 4096 - 256
+    big = wishart_n200().instance
+    with pytest.raises(T.TdptError, match="at most 20"):
+        T.workspace_bytes(T.Instance.from_synth(big, logical=True),
+                          T.RunConfig([1.0], [0], mcs_per_swap=1, seed=0, hist_logical=True))
+
+
+def test_layout_group_keys(monkeypatch):
+    """The structure layout that selects a problem's sweep kernel instance,
+    and the batch group key built from it: packed copy-edge problems of one
+    ELL width share a key; general constraints on the packed layout, a wider
+    row, the 32-bit layout and the bit-packed layout each get their own."""
+    from synth.constrained import planted_coloring, slack_knapsack
+    w = wishart_small()
+    cfg = T.RunConfig(w.beta, w.p_q, mcs_per_swap=1, seed=0)
+    a = T.Instance.from_synth(w.instance).layout(cfg)
+    assert (a["bits"], a["narrow"], a["general"]) == (0, 1, 0)
+    assert a["ell_width"] % 2 == 0 and a["ell_width"] >= 3
+    assert a["group_key"] == a["bits"] | a["narrow"] << 1 | a["ell_width"] << 3
+    # the same instance with another seed and grid: same key
+    b = T.Instance.from_synth(w.instance).layout(T.RunConfig([1.0, 2.0], [0, 4096], mcs_per_swap=3, seed=9))
+    assert b["group_key"] == a["group_key"]
+    # general constraints on the packed layout
+    pc = planted_coloring(40, 3, degree=4, seed=1).instance
+    c = T.Instance.from_synth(pc).layout(T.RunConfig([1.0], [0, 4096], mcs_per_swap=1, seed=0))
+    assert (c["narrow"], c["general"]) == (1, 1) and c["group_key"] & 4
+    assert c["group_key"] != a["group_key"]
+    # a penalty large enough to leave the packed layout's 22-bit fields
+    d = T.Instance.from_synth(w.instance).layout(T.RunConfig([1.0], [0, 1 << 21], mcs_per_swap=1, seed=0))
+    assert d["narrow"] == 0 and d["group_key"] != a["group_key"]
+    # wide constraint rows (a knapsack term over 30 spins)
+    k = T.Instance.from_synth(slack_knapsack(24, seed=1)).layout(T.RunConfig([1.0], [64], mcs_per_swap=1, seed=0))
+    assert k["general"] == 1
+    # the bit-packed layout (forced; chosen by itself above 48 KiB per replica)
+    monkeypatch.setenv("TDPT_LAYOUT", "bits")
+    e = T.Instance.from_synth(w.instance).layout(cfg)
+    assert (e["bits"], e["narrow"]) == (1, 0) and e["group_key"] & 1
+    assert len({a["group_key"], c["group_key"], d["group_key"], e["group_key"]}) == 4

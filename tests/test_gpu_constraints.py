@@ -184,3 +184,29 @@ def test_large_constraint_field_without_penalty(T):
     o, P = both(T, inst, np.array([0.05, 0.2]), np.array([0, 0], np.int32), mcs=3, rounds=12, seed=6,
                 label="large constraint field, P = 0")
     assert np.abs(o["g"]).max() > (1 << 23)
+
+
+@pytest.mark.parametrize("driver", ["0", "1"])
+def test_constraint_beyond_32_bits(T, driver):
+    """One term over 30 spins with constant 65539, so g = (sum s + 65539)^2
+    straddles 2^32, and a field that pushes the P_q = 1 column above 2^32
+    and the P_q = 2 column below it: every P-swap (Eq. 2) and beta-swap
+    (Eq. 3, E = f + P g) compares g values on both sides of 2^32.  Both
+    drivers must carry g at full width between swap partners and match the
+    oracle bit for bit."""
+    from synth.constrained import with_terms
+    from synth.instances import Instance
+    n = 30
+    base = Instance(n=n, row_ptr=np.zeros(n + 1, np.int32), col=np.zeros(0, np.int32),
+                    J_q=np.zeros(0, np.int32), b_q=np.full(n, 196608, np.int32),
+                    copy_a=np.zeros(0, np.int32), copy_b=np.zeros(0, np.int32),
+                    color=np.zeros(n, np.int32), logical_of=np.arange(n, dtype=np.int32), N=n)
+    inst = with_terms(base, np.array([0, n], np.int32), np.arange(n, dtype=np.int32),
+                      np.ones(n, np.int32), np.array([65536 + 3], np.int32))
+    beta = np.array([0.002, 0.004, 0.008])
+    p_q = np.array([1, 2], np.int32)
+    o, P = _with_env("TDPT_PERSISTENT", driver, lambda: both(
+        T, inst, beta, p_q, mcs=1, rounds=200, seed=3, label=f"g beyond 2^32, driver {driver}"))
+    assert P.query()["driver"] == int(driver)
+    tg = o["trace_g"]
+    assert (tg >= 2**32).any() and (tg < 2**32).any()

@@ -294,6 +294,21 @@ def test_deterministic_and_seeded():
     assert not np.array_equal(a["states"], c["states"])
 
 
+def test_threaded_oracle_equals_sequential():
+    """Splitting a round's sweeps over threads (the all-cores CPU baseline)
+    leaves every output as the sequential run has it, for copy edges and for
+    general constraints."""
+    from synth.constrained import planted_coloring
+    w = wishart_small()
+    pc = planted_coloring(30, 3, degree=4, seed=1)
+    for inst, beta, p_q in ((w.instance, w.beta, w.p_q),
+                            (pc.instance, np.geomspace(0.3, 3, 3), np.array([0, 2048, 4096], np.int32))):
+        a = O.run(inst, beta, p_q, mcs_per_swap=3, n_rounds=25, seed=7, trace=True)
+        b = O.run(inst, beta, p_q, mcs_per_swap=3, n_rounds=25, seed=7, trace=True, threads=5)
+        for k in a:
+            assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
+
+
 def test_planted_ground_state_is_reached_and_never_undercut():
     """On the N=12 planted Wishart workload (10^4 sweeps) the bottom-right
     replica never reports an energy below the brute-force ground state, and
