@@ -477,14 +477,15 @@ def bench_jcolumn(args):
 
 def bench_kl(args):
     """Fig. 2 on a stand-in instance: KL divergence between the bottom-right
-    replica's logical-state histogram (one sample per round of 500 sweeps)
+    replica's logical-state histogram (one sample per round of 500 sweeps,
+    counted on the device)
     and the exact Boltzmann distribution, with P-swaps and without, against
     the independent-sample level (2^N - 1) / (2 t)."""
     import paper_2506_14781_amd as T
     from paper_2506_14781_amd import sampling as S
     from synth.configs import fig2_workload
     w = fig2_workload(rounds=args.kl_rounds)
-    inst = T.Instance.from_synth(w.instance)
+    inst = T.Instance.from_synth(w.instance, logical=True)
     target = S.boltzmann_logical(w.instance.J_logical_q, w.instance.b_logical_q, float(w.beta[0]))
     fc = S.first_copies(w.instance.logical_of)
     checkpoints = sorted({int(c) for c in np.geomspace(10, args.kl_rounds, 12)})
@@ -494,7 +495,7 @@ def bench_kl(args):
         kls = []
         for seed in range(args.kl_seeds):
             prob = T.Problem(inst, T.RunConfig(w.beta, w.p_q, mcs_per_swap=w.mcs_per_swap, seed=seed,
-                                               flags=flags))
+                                               flags=flags, hist_logical=True))
             _, snaps = S.sample_bottom_right(prob, args.kl_rounds, fc, checkpoints)
             kls.append([S.kl_divergence(snaps[c], target) for c in checkpoints])
             prob.close()

@@ -50,12 +50,30 @@ def kl_divergence(counts, target) -> float:
 
 
 def sample_bottom_right(problem, rounds: int, first_copy: np.ndarray, checkpoints=()):
-    """Run `rounds` rounds one at a time, counting the bottom-right replica's
-    logical state after each.  Returns the counts and, for each checkpoint
-    (a number of samples), the counts at that point."""
-    counts = np.zeros(1 << first_copy.shape[0], dtype=np.int64)
+    """Count the bottom-right replica's logical state after each of `rounds`
+    rounds of a fresh problem.  Returns the counts and, for each checkpoint
+    (a number of samples), the counts at that point.
+
+    A problem created with RunConfig(hist_logical=True) (and an instance
+    with logical_of) counts on the device, in the library's per-round
+    histogram: it runs from checkpoint to checkpoint and the counts are read
+    there.  Otherwise the states are read back and counted on the host after
+    every round."""
+    ck = sorted(set(int(c) for c in checkpoints if 0 < int(c) <= rounds))
     snaps = {}
-    ck = set(int(c) for c in checkpoints)
+    if problem.cfg.hist_logical:
+        done = 0
+        for c in ck + [rounds]:
+            if c > done:
+                problem.run(c - done)
+                done = c
+            if c in ck and c not in snaps:
+                snaps[c] = problem.histogram()[0].astype(np.int64)
+        counts, samples = problem.histogram()
+        if samples != rounds:
+            raise ValueError("the problem had run before sampling started")
+        return counts.astype(np.int64), snaps
+    counts = np.zeros(1 << first_copy.shape[0], dtype=np.int64)
     for t in range(1, rounds + 1):
         problem.run(1)
         s = problem.states()[-1]

@@ -258,3 +258,117 @@ def test_persistent_batch_driver(T):
     name, inst, beta, p_q, mcs, seed = specs[3]
     o = O.run(inst, beta, p_q, mcs_per_swap=mcs, n_rounds=rounds, seed=seed, trace=True)
     assert np.array_equal(probs[3].states(), o["states"])
+
+
+def _with_env(key, value, fn):
+    import os
+    old = os.environ.get(key)
+    os.environ[key] = value
+    try:
+        return fn()
+    finally:
+        if old is None:
+            del os.environ[key]
+        else:
+            os.environ[key] = old
+
+
+def test_mixed_layout_batch_equals_oracle(T):
+    """One batch holding bit-packed members (one forced, one large enough to
+    need it), packed byte-layout members, a 32-bit-row member and a
+    general-constraint member: run directly, replayed from a HIP graph and
+    across a membership change, every member equals the oracle on states,
+    f, g, swap counters, trace, best state, best f and sweep, and first
+    hit."""
+    from synth.constrained import planted_coloring
+    from tests.test_gpu_parity import assert_same
+    w = wishart_small()
+    f_gs = O.energy(w.instance, w.instance.physical_state(w.instance.planted))[0]
+    big = batched_member(500, 0.5, 7)  # 63,000 spins: above 48 KiB per int8 replica
+    m64 = batched_member(64, 0.8, 3)
+    wide = _members()[3]
+    col = planted_coloring(40, 3, degree=4, seed=1)
+    specs = [  # name, instance, beta, p_q, mcs, seed, f_target, layout env
+        ("N12 bits", w.instance, w.beta, w.p_q, 5, 11, f_gs, "bits"),
+        ("N12 bytes", w.instance, w.beta, w.p_q, 5, 12, f_gs, None),
+        ("N64", m64.instance, m64.beta[:8], m64.p_q[:4], 3, 3, None, None),
+        ("wide", wide[1], wide[2], wide[3], 2, 1, None, None),
+        ("coloring", col.instance, np.geomspace(0.3, 3, 4), np.array([0, 4096], np.int32), 3, 8,
+         col.f_target_q, None),
+        ("N500", big.instance, big.beta[:4], big.p_q[:4], 1, 4, None, None),
+    ]
+    probs = []
+    for name, inst, beta, p_q, mcs, seed, tgt, lay in specs:
+        cfg = T.RunConfig(beta, p_q, mcs_per_swap=mcs, seed=seed, f_target=tgt, trace_cap=64)
+        mk = lambda: T.Problem(T.Instance.from_synth(inst), cfg)  # noqa: E731
+        probs.append(_with_env("TDPT_LAYOUT", lay, mk) if lay else mk())
+    bits = [T.Instance.from_synth(s[1]).layout(T.RunConfig(s[2], s[3], mcs_per_swap=1, seed=0))["bits"]
+            for s in specs]
+    assert bits[-1] == 1 and bits[1] == 0
+    B = T.Batch(8)
+    B.set_members(probs)
+    assert B.driver() == 0  # bit-packed members run the per-round launches
+    _say("[batch] mixed layouts: direct, graph replay, membership change")
+    B.run(6)
+    B.set_graph(3)
+    B.run(7)  # two replays and one direct round
+    B.set_members(probs[1:])  # the forced bit-packed member sits out
+    B.run(5)
+    B.set_members(probs)
+    B.run(4)
+    B.close()
+    for k, ((name, inst, beta, p_q, mcs, seed, tgt, lay), P) in enumerate(zip(specs, probs)):
+        rounds = 17 if k == 0 else 22
+        _say(f"[batch] mixed layouts: {name} vs oracle ({rounds} rounds)")
+        o = O.run(inst, beta, p_q, mcs_per_swap=mcs, n_rounds=rounds, seed=seed, f_target=tgt, trace=True)
+        assert_same(o, P, name)
+
+
+@pytest.mark.parametrize("max_work", [None, 1])
+def test_serving_outputs_equal_alone(T, max_work):
+    """Eight requests of different sizes, grids, layouts (one bit-packed by
+    size) and constraint kinds arrive over time and are served by continuous
+    batching under a memory budget: each request's states, f, g, swap
+    counters, trace, best state and tracking equal its run alone."""
+    from paper_2506_14781_amd.serve import Request, serve
+    from synth.constrained import planted_coloring
+    w = wishart_small()
+    f_gs = O.energy(w.instance, w.instance.physical_state(w.instance.planted))[0]
+    specs = [s + (None,) for s in _members()]
+    specs[0] = specs[0][:6] + (f_gs,)
+    for N, seed in [(50, 21), (80, 22)]:
+        m = batched_member(N, 0.5, seed)
+        specs.append((m.name, m.instance, m.beta[:4], m.p_q[:4], 2, seed, None))
+    col = planted_coloring(40, 3, degree=4, seed=1)
+    specs.append(("coloring", col.instance, np.geomspace(0.3, 3, 4), np.array([0, 4096], np.int32), 3, 8,
+                  col.f_target_q))
+    big = batched_member(500, 0.5, 7)
+    specs.append(("N500 bits", big.instance, big.beta[:4], big.p_q[:4], 1, 4, None))
+    reqs = []
+    for k, (name, inst, beta, p_q, mcs, seed, tgt) in enumerate(specs):
+        cfg = T.RunConfig(beta, p_q, mcs_per_swap=mcs, seed=seed, f_target=tgt, trace_cap=40)
+        reqs.append(Request(name=name, instance=T.Instance.from_synth(inst), cfg=cfg, max_rounds=6 + 4 * k,
+                            arrival=0.002 * k))
+    budget = max(T.workspace_bytes(r.instance, r.cfg) for r in reqs) * 2
+    keep = {}
+    orig_close = T.Problem.close
+
+    def grab(self):
+        for r in reqs:
+            if r.problem is self and r.name not in keep:
+                keep[r.name] = _outputs(self)
+        orig_close(self)
+    T.Problem.close = grab
+    try:
+        _say(f"[batch] serving {len(reqs)} requests, max_work {max_work}")
+        serve(reqs, chunk=4, budget_bytes=budget, max_work=max_work)
+    finally:
+        T.Problem.close = orig_close
+    for r in reqs:
+        # a request retires at its cap or at the end of the chunk in which it
+        # reached its target; alone it runs the same number of rounds
+        assert r.rounds_done == r.max_rounds or r.hit_time is not None, r.name
+        P = T.Problem(r.instance, r.cfg)
+        P.run(r.rounds_done)
+        _same(keep[r.name], _outputs(P))
+        P.close()

@@ -25,7 +25,7 @@ def T():
 def test_p_swaps_reach_the_independent_sample_level(T):
     from paper_2506_14781_amd import sampling as S
     w = fig2_workload()
-    inst = T.Instance.from_synth(w.instance)
+    inst = T.Instance.from_synth(w.instance, logical=True)
     target = S.boltzmann_logical(w.instance.J_logical_q, w.instance.b_logical_q, 1.0)
     fc = S.first_copies(w.instance.logical_of)
     t = 400
@@ -35,7 +35,7 @@ def test_p_swaps_reach_the_independent_sample_level(T):
         vals = []
         for seed in range(3):
             P = T.Problem(inst, T.RunConfig(w.beta, w.p_q, mcs_per_swap=w.mcs_per_swap, seed=seed,
-                                            flags=flags))
+                                            flags=flags, hist_logical=True))
             counts, _ = S.sample_bottom_right(P, t, fc)
             vals.append(S.kl_divergence(counts, target))
         kl[label] = float(np.mean(vals))
