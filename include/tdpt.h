@@ -222,6 +222,20 @@ int tdpt_workspace_bytes(const tdpt_instance *inst, const tdpt_run_cfg *cfg, siz
 int tdpt_problem_create(const tdpt_instance *inst, const tdpt_run_cfg *cfg, void *dev_ws,
                         size_t ws_bytes, void *stream, tdpt_problem **out);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, tight serving loops, harnesses that forbid allocation): the
+ * same as tdpt_problem_create with the workspace taken from a static device
+ * array of the library, TDPT_STATIC_WORKSPACE_BYTES per GPU, which each GPU
+ * the library runs on holds until the process ends.  The call allocates no
+ * device memory.  One such problem per GPU at a time: TDPT_E_BUSY while
+ * another lives on the current device (tdpt_problem_destroy releases the
+ * array after the problem's stream has finished); TDPT_E_NOMEM if the
+ * problem's tdpt_workspace_bytes exceed the array.  Creation clears the part
+ * of the array the problem uses, so nothing of an earlier holder leaks in. */
+#define TDPT_STATIC_WORKSPACE_BYTES (64u << 20)
+int tdpt_problem_create_static(const tdpt_instance *inst, const tdpt_run_cfg *cfg, void *stream,
+                               tdpt_problem **out);
+
 /* Enqueue n_rounds swap rounds of Algorithm 1 (each: mcs_per_swap sweeps of
  * every replica, f/g of the final states, one swap step by Eq. 2 or Eq. 3,
  * bottom-right tracking).  Resumable: calling it twice with a and b rounds

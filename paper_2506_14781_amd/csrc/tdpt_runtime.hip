@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -97,6 +98,7 @@ struct tdpt_problem {
     tdpt_batch *batch = nullptr;  // the batch that holds it as a member, if any
     int32_t n_logical = 0;        // logical variables and their first copies
     std::vector<int32_t> first_copy;
+    int32_t static_dev = -1;      // device whose static workspace it holds (-1: caller's memory)
     int32_t n = 0, I = 0, J = 0, R = 0, mcs = 1;
     std::vector<int32_t> rank;
     uint8_t *ws = nullptr;
@@ -1405,10 +1407,62 @@ int tdpt_problem_load(tdpt_problem *p, const void *host, size_t bytes)
     return TDPT_OK;
 }
 
+// ------------------------------------------------ static workspace
+// One workspace per GPU in a static device array, for callers that cannot
+// allocate device memory.  Host code never passes the array's name to a
+// kernel or copy: on the host it is only a stand-in for the symbol, and its
+// device address (one per GPU) comes from hipGetSymbolAddress.
+static __device__ __align__(256) uint8_t scratch[TDPT_STATIC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices];            // device address of `scratch` on each GPU
+tdpt_problem *g_static_owner[kMaxDevices];  // the live problem holding it, if any
+}  // namespace
+
+int tdpt_problem_create_static(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *stream,
+                               tdpt_problem **out)
+{
+    if (!out) return fail(TDPT_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!in) return fail(TDPT_E_INVALID, "instance is NULL");
+    size_t need = 0;
+    int rc = tdpt_workspace_bytes(in, cfg, &need);
+    if (rc) return rc;
+    if (need > (size_t)TDPT_STATIC_WORKSPACE_BYTES)
+        return fail(TDPT_E_NOMEM, "the problem needs " + std::to_string(need) +
+                                      " bytes of workspace; the static workspace holds " +
+                                      std::to_string((size_t)TDPT_STATIC_WORKSPACE_BYTES));
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(TDPT_E_INVALID, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!ptr || ((uintptr_t)ptr) % 256) return fail(TDPT_E_DEVICE, "static workspace address unusable");
+        g_static_ptr[dev] = ptr;
+    }
+    if (g_static_owner[dev])
+        return fail(TDPT_E_BUSY, "another problem holds this GPU's static workspace (destroy it first)");
+    rc = tdpt_problem_create(in, cfg, g_static_ptr[dev], (size_t)TDPT_STATIC_WORKSPACE_BYTES, stream, out);
+    if (rc) return rc;
+    (*out)->static_dev = dev;
+    g_static_owner[dev] = *out;
+    return TDPT_OK;
+}
+
 void tdpt_problem_destroy(tdpt_problem *p)
 {
     if (!p) return;
     leave_batch(p);
+    if (p->static_dev >= 0) {
+        // the next holder clears the array on its own stream: let this one's work end first
+        (void)hipStreamSynchronize(p->stream);
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        if (g_static_owner[p->static_dev] == p) g_static_owner[p->static_dev] = nullptr;
+    }
     delete p;
 }
 

@@ -31,8 +31,10 @@ EXPORTED = [
     "tdpt_batch_set_graph", "tdpt_batch_set_driver", "tdpt_batch_query_driver",
     "tdpt_layout_get", "tdpt_problem_query_async", "tdpt_problem_read_energies_async",
     "tdpt_problem_read_states_async", "tdpt_problem_read_best_async", "tdpt_problem_read_best_logical",
-    "tdpt_problem_read_histogram",
+    "tdpt_problem_read_histogram", "tdpt_problem_create_static",
 ]
+
+STATIC_WORKSPACE_BYTES = 64 << 20
 
 
 class TdptError(RuntimeError):
@@ -106,6 +108,7 @@ def load_library():
         "tdpt_problem_read_best_async": [P, P, P],
         "tdpt_problem_read_best_logical": [P, P, P, P],
         "tdpt_problem_read_histogram": [P, P, P],
+        "tdpt_problem_create_static": [P, P, P, P],
         "tdpt_instance_info_get": [P, P],
         "tdpt_workspace_bytes": [P, P, P],
         "tdpt_problem_create": [P, P, P, SZ, P, P],
@@ -265,22 +268,32 @@ def workspace_bytes(instance: Instance, cfg: RunConfig) -> int:
 class Problem:
     """One 2D-PT run resident on the GPU; outputs are per grid position."""
 
-    def __init__(self, instance: Instance, cfg: RunConfig, device="cuda", stream=None):
+    def __init__(self, instance: Instance, cfg: RunConfig, device="cuda", stream=None, static=False):
+        """static=True: the workspace is the library's static device array
+        (tdpt_problem_create_static; nothing is allocated, one such problem
+        per GPU at a time)."""
         import torch
         lib = load_library()
         self.cfg = cfg
         self.n = instance.n
         self.I, self.J = cfg.beta.shape[0], cfg.p_q.shape[0]
         self.R = self.I * self.J
-        nbytes = workspace_bytes(instance, cfg)
         self.device = torch.device(device)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         c = cfg._c()
-        _check(lib.tdpt_problem_create(instance._h, ctypes.byref(c),
-                                       ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
-                                       ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        if static:
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                _check(lib.tdpt_problem_create_static(instance._h, ctypes.byref(c),
+                                                      ctypes.c_void_p(self.stream.cuda_stream),
+                                                      ctypes.byref(h)))
+        else:
+            nbytes = workspace_bytes(instance, cfg)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            _check(lib.tdpt_problem_create(instance._h, ctypes.byref(c),
+                                           ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                           ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
         self._h = h
         self.n_logical = instance.info()["n_logical"]
 
