@@ -13,7 +13,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "tdpt_oracle.c")
-_LIB = os.path.join(_HERE, "_build", "libtdpt_oracle.so")
+# TDPT_ORACLE_LIB names another build of the same source (the sanitizer test
+# loads an AddressSanitizer / UBSan build this way)
+_LIB = os.environ.get("TDPT_ORACLE_LIB") or os.path.join(_HERE, "_build", "libtdpt_oracle.so")
 
 NO_PSWAP = 1
 
@@ -36,7 +38,8 @@ def build(force: bool = True) -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.environ.get("TDPT_ORACLE_LIB") and (
+                not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
             build(force=True)
         _lib = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p

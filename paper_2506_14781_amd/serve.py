@@ -9,7 +9,8 @@ which problems run when, and measures wall time to the planted ground state.
 * serving — requests arrive over time; a request is admitted into the running
             batch as soon as its device footprint fits the memory budget,
             joins at the next round boundary, and retires when it hits its
-            target or reaches its cap.  Requests already on the GPU keep
+            target or reaches its cap, or is dropped when it is cancelled
+            or its time limit runs out.  Requests already on the GPU keep
             running while new ones are admitted (continuous batching).
 
 A result does not depend on the mode: random streams are keyed per problem.
@@ -46,6 +47,12 @@ class Request:
     # optional reference for reporting: ground-state f_q and logical size
     f_ref: int | None = None
     n_logical: int = 0
+    # serving controls: a time limit in seconds after arrival (None: none),
+    # and a flag the caller may set at any time to cancel the request
+    deadline: float | None = None
+    cancelled: bool = False
+    # how the request ended: "hit", "cap", "timeout" or "cancelled"
+    status: str | None = None
 
 
 def _advance(req: Request, rounds: int, t0: float, t1: float, elapsed_base: float):
@@ -66,6 +73,20 @@ def _done(req: Request) -> bool:
     return req.hit_time is not None or req.rounds_done >= req.max_rounds
 
 
+def _finish_status(req: Request) -> str:
+    return "hit" if req.hit_time is not None else "cap"
+
+
+def _dropped(req: Request, now: float) -> str | None:
+    """"cancelled" or "timeout" if the request is to be dropped at time now
+    (seconds after the job's start), else None."""
+    if req.cancelled:
+        return "cancelled"
+    if req.deadline is not None and now - req.arrival >= req.deadline:
+        return "timeout"
+    return None
+
+
 def run_plain(requests, chunk: int, device="cuda"):
     """Each request alone, one after another (all present at t = 0)."""
     import torch
@@ -81,6 +102,7 @@ def run_plain(requests, chunk: int, device="cuda"):
             torch.cuda.synchronize()
             _advance(req, n, t0, time.perf_counter(), base)
         req.end = time.perf_counter() - base
+        req.status = _finish_status(req)
         req.problem.close()
         req.problem = None
     return time.perf_counter() - base
@@ -110,6 +132,7 @@ def run_batched(requests, chunk: int, device="cuda"):
         for r in active:
             if _done(r):
                 r.end = t1 - base
+                r.status = _finish_status(r)
             else:
                 still.append(r)
         if len(still) != len(active) and still:
@@ -124,13 +147,20 @@ def run_batched(requests, chunk: int, device="cuda"):
 
 
 def serve(requests, chunk: int, budget_bytes: int, max_members: int = 4096, device="cuda",
-          max_work: int | None = None):
+          max_work: int | None = None, on_chunk=None):
     """Continuous batching: requests (sorted by arrival) join the running
     batch at round boundaries when their workspace fits the budget and, if
     max_work is given, while the spin updates per sweep of the running batch
     (replicas x spins, summed) stay within it (a request is always admitted
     into an empty batch).  Capping the running work lets requests finish in
-    arrival order instead of all sharing the GPU until the end."""
+    arrival order instead of all sharing the GPU until the end.
+
+    A request whose `cancelled` flag is set, or whose `deadline` (seconds
+    after its arrival) has passed, is dropped at the next round boundary
+    (or before admission): its problem is released and its status set to
+    "cancelled" or "timeout"; its counters keep the rounds it ran.
+    on_chunk(now, active, pending), if given, is called after every chunk
+    (the caller may set flags there)."""
     import torch
     pending = sorted(requests, key=lambda r: r.arrival)
     for r in pending:
@@ -149,6 +179,34 @@ def serve(requests, chunk: int, budget_bytes: int, max_members: int = 4096, devi
     while pending or active:
         now = time.perf_counter() - base
         changed = False
+        # requests dropped before they ran
+        keep = []
+        for r in pending:
+            why = _dropped(r, now) if r.arrival <= now or r.cancelled else None
+            if why:
+                r.status = why
+                r.end = now
+            else:
+                keep.append(r)
+        pending = keep
+        # requests dropped while running
+        if active:
+            still = []
+            for r in active:
+                why = _dropped(r, now)
+                if why:
+                    r.status = why
+                    r.end = now
+                    used -= r.footprint
+                    work -= work_of(r)
+                    r.problem.close()
+                    r.problem = None
+                    changed = True
+                else:
+                    still.append(r)
+            active = still
+        if not pending and not active:
+            break
         while (pending and pending[0].arrival <= now and used + pending[0].footprint <= budget_bytes
                and len(active) < max_members
                and (max_work is None or not active or work + work_of(pending[0]) <= max_work)):
@@ -160,6 +218,8 @@ def serve(requests, chunk: int, budget_bytes: int, max_members: int = 4096, devi
             active.append(r)
             changed = True
         if not active:
+            if changed:
+                batch.set_members([])
             # idle until the next arrival
             time.sleep(max(0.0, min(pending[0].arrival - now, 0.01)))
             continue
@@ -176,6 +236,7 @@ def serve(requests, chunk: int, budget_bytes: int, max_members: int = 4096, devi
         for r in active:
             if _done(r):
                 r.end = t1 - base
+                r.status = _finish_status(r)
                 used -= r.footprint
                 work -= work_of(r)
                 r.problem.close()
@@ -185,6 +246,8 @@ def serve(requests, chunk: int, budget_bytes: int, max_members: int = 4096, devi
         if len(still) != len(active):
             active = still
             batch.set_members([r.problem for r in active])
+        if on_chunk is not None:
+            on_chunk(t1 - base, list(active), list(pending))
     total = time.perf_counter() - base
     batch.close()
     return total
@@ -201,6 +264,7 @@ def summarize(requests, total_seconds: float):
     out = {
         "requests": len(requests),
         "hit_fraction": len(hit) / max(len(requests), 1),
+        "dropped": {k: sum(1 for r in requests if r.status == k) for k in ("timeout", "cancelled")},
         "tts_p50_s": float(np.percentile(times, 50)) if len(times) else None,
         "tts_p99_s": float(np.percentile(times, 99)) if len(times) else None,
         "sweeps_to_hit_p50": float(np.percentile(sweeps, 50)) if len(sweeps) else None,

@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_build", "libtdpt.so")
+# TDPT_LIB names another build of the same sources (the host-sanitizer test
+# loads an AddressSanitizer / UBSan build of the host code this way)
+LIB_PATH = os.environ.get("TDPT_LIB") or os.path.join(_HERE, "_build", "libtdpt.so")
 
 OK, E_INVALID, E_RANGE, E_NOMEM, E_DEVICE, E_STATE, E_BUSY = range(7)
 NO_PSWAP = 1

@@ -165,3 +165,54 @@ def test_late_arrival_runs_exactly_its_cap(world):
     assert [r.rounds_done for r in reqs] == [6, 2]
     assert reqs[1].start >= reqs[1].arrival
     assert not world.live
+
+
+def test_cancelled_request_is_dropped_at_a_round_boundary(world):
+    """A request cancelled while it runs leaves the batch at the next round
+    boundary with the rounds it ran; the others run to their caps."""
+    reqs = [_req("a", 100, 2, rounds=40), _req("b", 100, 2, rounds=12)]
+
+    def on_chunk(now, active, pending):
+        if reqs[0].rounds_done >= 4:
+            reqs[0].cancelled = True
+    S.serve(reqs, chunk=2, budget_bytes=10 ** 9, on_chunk=on_chunk)
+    a, b = reqs
+    assert a.status == "cancelled" and a.rounds_done == 4 and a.end is not None
+    assert b.status == "cap" and b.rounds_done == 12
+    assert not world.live
+
+
+def test_cancelled_before_admission_never_runs(world):
+    reqs = [_req("a", 100, 2, rounds=6), _req("b", 100, 2, rounds=6, arrival=0.05)]
+    reqs[1].cancelled = True
+    S.serve(reqs, chunk=2, budget_bytes=10 ** 9)
+    assert reqs[1].status == "cancelled" and reqs[1].rounds_done == 0 and reqs[1].problem is None
+    assert reqs[0].status == "cap" and reqs[0].rounds_done == 6
+
+
+def test_deadline_drops_running_and_waiting_requests(world, monkeypatch):
+    """Time limits: a running request past its limit is dropped at a round
+    boundary; a waiting one (held back by the memory budget) never starts."""
+    clock = {"t": 0.0}
+    monkeypatch.setattr(S.time, "perf_counter", lambda: clock["t"])
+    monkeypatch.setattr(S.time, "sleep", lambda dt: clock.__setitem__("t", clock["t"] + max(dt, 1e-3)))
+    reqs = [_req("slow", 1000, 4, rounds=100), _req("waits", 1000, 4, rounds=5)]
+    reqs[0].deadline = 1.0
+    reqs[1].deadline = 0.5
+
+    def on_chunk(now, active, pending):
+        clock["t"] += 0.1  # every chunk takes 0.1 s
+    S.serve(reqs, chunk=2, budget_bytes=4_000, on_chunk=on_chunk)  # room for one at a time
+    slow, waits = reqs
+    assert slow.status == "timeout" and 0 < slow.rounds_done < 100
+    assert waits.status == "timeout" and waits.rounds_done == 0 and waits.start is None
+    assert not world.live
+
+
+def test_status_of_finished_requests(world):
+    reqs = [_req("a", 100, 2, rounds=50), _req("b", 100, 2, rounds=6)]
+    world.hit_round[id(reqs[0].instance)] = 3
+    S.serve(reqs, chunk=2, budget_bytes=10 ** 9)
+    assert [r.status for r in reqs] == ["hit", "cap"]
+    s = S.summarize(reqs, 1.0)
+    assert s["dropped"] == {"timeout": 0, "cancelled": 0}
