@@ -91,7 +91,7 @@ def measured_traffic(workload: str, kernel: str, rounds_per_launch: int):
     return m["bytes_per_round"] * rounds_per_launch
 
 
-def alu_ops_per_update(info, cons_deg_mean: float = 0.0) -> float:
+def alu_ops_per_update(info, cons_deg_mean: float = 0.0, mcs: int = 1) -> float:
     """Arithmetic one heat-bath update needs, in 32-bit lane operations:
     one multiply-add per problem neighbour, the penalty term (copy edges:
     two adds, one multiply, one add; general constraints: one multiply-add
@@ -99,15 +99,17 @@ def alu_ops_per_update(info, cons_deg_mean: float = 0.0) -> float:
     and the add), the bias add, a quarter of a Philox4x32-10 call
     (ten rounds of two 32x32->64 products = 4 ops, four xors, two key adds),
     the logistic decision (convert, scale, exp2, convert the uniform,
-    multiply-add, compare)
-    and the bookkeeping of the exact f and g (spin difference, two
-    multiply-adds, store)."""
+    multiply-add, compare), and the round's exact f and g by the cheaper
+    of two ways: following every update (spin difference, two
+    multiply-adds, store: 4) or evaluating them once from the round's final
+    states (a multiply-add per neighbour, the copy or constraint term and
+    the field: d + 3 per spin, over the mcs sweeps of the round)."""
     d_problem = info["nnz"] / info["n"]
     penalty = cons_deg_mean + 2 if info.get("n_terms", 0) else 4
     field = d_problem + penalty + 1
     philox = 10 * (4 + 4 + 2) / 4
     decision = 6
-    bookkeeping = 4
+    bookkeeping = min(4.0, (d_problem + cons_deg_mean + 3) / max(mcs, 1))
     return field + philox + decision + bookkeeping
 
 
@@ -174,6 +176,30 @@ def _cpu_model() -> str:
     return platform.processor() or platform.machine()
 
 
+def stage_breakdown(torch, prob, rounds: int) -> dict:
+    """Where a persistent round's time goes: `rounds` more rounds (untimed)
+    with every slot's stage timestamps (100 MHz clock): its sweeps, the wait
+    from posting its (f, g) until the swap partner's is in hand, and the
+    decision; means over slots and rounds in microseconds, and the round
+    period (start to start of the next round of the same slot)."""
+    buf = torch.zeros(rounds * prob.R * 4, dtype=torch.int64, device=prob.workspace.device)
+    prob.set_stage_trace(buf, rounds)
+    prob.run(rounds)
+    torch.cuda.synchronize()
+    prob.set_stage_trace(None, 0)
+    t = buf.view(rounds, prob.R, 4).cpu().numpy().astype(np.float64) * 0.01  # ticks of 10 ns -> us
+    sweep = t[:, :, 1] - t[:, :, 0]
+    wait = t[:, :, 2] - t[:, :, 1]
+    decide = t[:, :, 3] - t[:, :, 2]
+    period = t[1:, :, 0] - t[:-1, :, 0]
+    return {"rounds": rounds, "unit": "us", "sweep_mean": round(float(sweep.mean()), 3),
+            "partner_wait_mean": round(float(wait.mean()), 3),
+            "partner_wait_p90": round(float(np.percentile(wait, 90)), 3),
+            "decision_mean": round(float(decide.mean()), 3),
+            "round_period_mean": round(float(period.mean()), 3),
+            "sweep_share_of_period": round(float(sweep.mean() / period.mean()), 4)}
+
+
 def bits_bytes_per_update(info, wd: int) -> float:
     """Bit-packed layout: every workgroup streams the structure once per
     sweep (neighbour bit positions and couplings, 8 bytes per ELL entry;
@@ -229,7 +255,7 @@ def bench_batched(args):
     # ALU work of the whole job by the same per-update model as the main
     # line, weighted by each member's spin updates
     ops = sum(r.rounds_done * r.cfg.mcs_per_swap * r.cfg.replicas * r.instance.n *
-              alu_ops_per_update(r.instance.info()) for r in reqs_b)
+              alu_ops_per_update(r.instance.info(), mcs=r.cfg.mcs_per_swap) for r in reqs_b)
     roof = {"bound": "alu", "unit": "Tlane-op/s", "peak": round(PEAK_LANE_OPS / 1e12, 3)}
     for mode, total in (("batched", tb), ("plain", tp)):
         roof[f"achieved_{mode}"] = round(ops / total / 1e12, 3)
@@ -344,7 +370,7 @@ def bench_serving(args):
         # whole-job ALU fraction by the per-update model (wall clock, idle
         # time between arrivals included)
         ops = sum(r.rounds_done * r.cfg.mcs_per_swap * r.cfg.replicas * r.instance.n *
-                  alu_ops_per_update(r.instance.info()) for r in reqs)
+                  alu_ops_per_update(r.instance.info(), mcs=r.cfg.mcs_per_swap) for r in reqs)
         s["alu_frac_whole_job"] = round(ops / total / PEAK_LANE_OPS, 4)
         print(f"[bench] rate {rate}/s: makespan {total:.2f} s, latency p50 {s.get('latency_p50_s')}",
               file=sys.stderr, flush=True)
@@ -546,6 +572,9 @@ def main():
     ap.add_argument("--tts-seeds", type=int, default=200,
                     help="run seeds of the N=12 time-to-planted-GS comparison in the main line (0: skip)")
     ap.add_argument("--tts-cap", type=int, default=200000, help="sweep cap of that comparison")
+    ap.add_argument("--stage-rounds", type=int, default=200,
+                    help="after the timed steps, rounds with per-slot stage timestamps when the "
+                         "persistent driver runs (0: skip)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--autotune", type=int, default=None,
                     help="rounds per trial of the launch-shape autotuner, run before the warm-up "
@@ -632,6 +661,7 @@ def main():
         rep = prob.autotune(args.autotune)
         tune = {"driver": rep["driver"], "block": rep["block"], "ms_per_round": round(rep["ms_per_round"], 5),
                 "trials": len(rep["trials"]), "rounds_per_trial": args.autotune,
+                "trial_ms_per_round": [[d, b, round(ms, 5)] for d, b, ms in rep["trials"]],
                 "seconds": round(time.perf_counter() - t0, 3)}
         print(f"[bench] autotune: driver {tune['driver']} block {tune['block']} "
               f"({tune['ms_per_round']:.4f} ms/round) from {tune['trials']} trials",
@@ -671,7 +701,7 @@ def main():
     # Both layouts are bound by VALU arithmetic: the replica spins stay in
     # LDS and the structure is served from L2 (the measured HBM traffic is
     # a small fraction of the structure bytes the sweeps read).
-    ops = alu_ops_per_update(info, cons_deg_mean)
+    ops = alu_ops_per_update(info, cons_deg_mean, w.mcs_per_swap)
     achieved = ops * updates_per_launch / (launch_ms / 1e3)
     roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 3),
                 "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "Tlane-op/s",
@@ -748,6 +778,8 @@ def main():
         out["config"].update({"constraint": "one-hot terms", "n_terms": info["n_terms"]})
     if tune is not None:
         out["autotune"] = tune
+    if persistent and args.stage_rounds > 0:
+        out["stages"] = stage_breakdown(torch, prob, args.stage_rounds)
     prob.close()
     del prob
     torch.cuda.synchronize()

@@ -309,11 +309,22 @@ int tdpt_problem_set_timing(tdpt_problem *prob, int32_t every);
 int tdpt_problem_read_timing(tdpt_problem *prob, double *total_ms, int64_t *launches,
                              int64_t *rounds);
 
+/* Measurement hook of the persistent driver: from the next round on, for
+ * `rounds` rounds, every replica slot writes four timestamps of the GPU's
+ * 100 MHz real-time clock into dev_buf[round][slot][0..3] (caller-owned
+ * device memory of rounds * R * 4 uint64, on the problem's device): the
+ * round's start, the end of its sweeps, the moment the swap partner's
+ * (f, g) is in hand (= the end of the sweeps when the slot has no partner
+ * that round), and the end of the swap decision.  0 switches it off.  The
+ * per-round driver records nothing.  Waits for the problem's stream. */
+int tdpt_problem_set_stage_trace(tdpt_problem *prob, uint64_t *dev_buf, int32_t rounds);
+
 /* Launch-shape autotuner.  Times each admissible (driver, threads per sweep
  * workgroup) pair on the problem itself -- one warm-up round, then
  * rounds_per_trial rounds between HIP events on the problem's stream -- and
  * keeps the fastest for later runs.  Candidates: the per-round driver at 64
- * to 1024 threads (768 for bit-packed replicas) and, where every replica's
+ * to 1024 threads (768 for bit-packed replicas with fewer than 4 sweeps per
+ * round, whose sweeps follow f and g per update) and, where every replica's
  * workgroup can be resident at once, the persistent driver at 64 to 512,
  * each no larger than the largest colour class needs and no smaller than the
  * per-phase 2^31 bounds allow.  The problem's state is saved before and
@@ -366,8 +377,9 @@ int tdpt_batch_set_members(tdpt_batch *batch, tdpt_problem *const *probs, int32_
  * TDPT_E_STATE if a member was destroyed or moved since set_members. */
 int tdpt_batch_run(tdpt_batch *batch, int64_t n_rounds);
 /* Autotune the threads per sweep workgroup of each layout group of the
- * current members (64 to 1024, 768 for bit-packed groups, no smaller than
- * the members' per-phase bounds allow), one group after another, timing
+ * current members (64 to 1024; 768 for bit-packed groups with a member of
+ * fewer than 4 sweeps per round; no smaller than the members' per-phase
+ * bounds allow), one group after another, timing
  * whole batch rounds; every member's state is restored afterwards.  The
  * choice holds until the next tdpt_batch_set_members. */
 typedef struct tdpt_batch_tune_report {

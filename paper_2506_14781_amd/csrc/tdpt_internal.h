@@ -12,7 +12,9 @@ constexpr int kMaxBlock = 1024;   // threads per sweep workgroup, at most
 constexpr int kSmallBlock = 256;  // threads of the swap / energy kernels
 constexpr int kRing = 8;          // rounds of partner mailboxes kept per position
 constexpr int kBitSlots = 4;      // replicas per workgroup in the bit-packed layout
-constexpr int kBitsBlock = 768;   // threads of a bit-packed sweep workgroup, at most
+constexpr int kBitsBlock = 768;   // threads of a bit-packed sweep workgroup that follows f and g
+                                  // update by update, at most
+constexpr int kBitsBlockScratch = 1024;  // at most, when f and g are recomputed at the round's end
 constexpr int kMaxHistVars = 20;  // logical variables of the per-round state histogram, at most
 
 // Structure layouts of the byte-replica sweeps (their NARROW template
@@ -118,6 +120,13 @@ struct DevProblem {
     int32_t hist_n;
     const int32_t *hist_rank; // [hist_n]
     uint32_t *hist;           // [2^hist_n]
+    // optional stage timestamps of the persistent driver (stage_cap = 0:
+    // off): for rounds stage_round0 + 1 .. stage_round0 + stage_cap, per slot,
+    // the 100 MHz real-time clock at the round's start, after its sweeps,
+    // once the partner's (f, g) is in hand, and after the swap decision
+    uint64_t *stage;          // [stage_cap][R][4], caller-owned device memory
+    int32_t stage_cap;
+    int64_t stage_round0;
     // scratch of the persistent driver (not part of checkpoints)
     uint64_t *mbox;       // [kRing][R][2] tagged (f, g) by grid position
     int64_t *slot_key;    // [R] best key per slot during a launch
@@ -156,8 +165,15 @@ hipError_t launch_gather_energies(const DevProblem &p, int64_t *f, int64_t *g, h
 hipError_t launch_gather_states(const DevProblem &p, int n, int8_t *out, hipStream_t s);
 hipError_t launch_gather_best(const DevProblem &p, int8_t *out, hipStream_t s);
 // Bit-packed layout: one round of every slot (ceil(R / kBitSlots) blocks).
+// Bit-packed sweeps of fewer than kScratchMcs per round follow f and g update
+// by update; longer rounds recompute them from the round's final states
+// (min_mcs: the fewest sweeps per round among a batch group's members).
+constexpr int kScratchMcs = 4;
+__host__ __device__ inline bool track_updates(int mcs) { return mcs < kScratchMcs; }
+__host__ __device__ inline int bits_block_cap(int mcs) { return track_updates(mcs) ? kBitsBlock : kBitsBlockScratch; }
 hipError_t launch_sweep_bits(const DevProblem &p, hipStream_t s);
 hipError_t launch_batch_sweep_bits(const DevProblem &p, const DevProblem *table, const int *first_block,
-                                   int count, int blocks, int block, int max_words, hipStream_t s);
+                                   int count, int blocks, int block, int max_words, int min_mcs,
+                                   hipStream_t s);
 
 }  // namespace tdpt

@@ -812,6 +812,9 @@ __device__ __forceinline__ void persistent_body(const DevProblem &P, int slot, i
         const RoundPair rp = round_pair(P, n, pos);
         uint64_t *mb = P.mbox + 2 * ((size_t)(n & (kRing - 1)) * P.R);
         uint64_t pw0 = 0, pw1 = 0;
+        const bool stamp = P.stage_cap > 0 && n - 1 - P.stage_round0 >= 0 && n - 1 - P.stage_round0 < P.stage_cap;
+        uint64_t ts[4] = {0, 0, 0, 0};
+        if (stamp && tid == 0) ts[0] = __builtin_amdgcn_s_memrealtime();
         sweep_round<NARROW, WD>(P, Rs, replica_lds(), sp, n, red, [&] {
             if (tid == 0 && rp.k >= 0) {
                 pw0 = mb_load(&mb[2 * rp.other]);
@@ -819,6 +822,7 @@ __device__ __forceinline__ void persistent_body(const DevProblem &P, int slot, i
             }
         });
         if (tid == 0) {
+            if (stamp) ts[1] = __builtin_amdgcn_s_memrealtime();
             const int64_t f = st[0] + red[0];
             const int64_t g = st[1] + red[1];
             st[0] = f;
@@ -838,6 +842,7 @@ __device__ __forceinline__ void persistent_body(const DevProblem &P, int slot, i
                 __asm__ volatile("" ::"v"(u), "v"(lu));
                 int64_t fo = 0, go = 0;
                 if (!mb_take(pw0, pw1, tag, fo, go) && !mb_wait(&mb[2 * other], tag, fo, go, P.hdr)) abort = 1;
+                if (stamp) ts[2] = __builtin_amdgcn_s_memrealtime();
                 const int64_t fa = left ? f : fo, ga = left ? g : go;
                 const int64_t fb = left ? fo : f, gb = left ? go : g;
                 const bool acc =
@@ -875,6 +880,15 @@ __device__ __forceinline__ void persistent_body(const DevProblem &P, int slot, i
             sh[0] = newpos;
             sh[1] = improved;
             sh[2] = abort;
+            if (stamp) {
+                ts[3] = __builtin_amdgcn_s_memrealtime();
+                if (k < 0) ts[2] = ts[1];
+                uint64_t *o = P.stage + ((size_t)(n - 1 - P.stage_round0) * P.R + slot) * 4;
+                o[0] = ts[0];
+                o[1] = ts[1];
+                o[2] = ts[2];
+                o[3] = ts[3];
+            }
         }
         __syncthreads();
         if (sh[2]) break;
@@ -1032,7 +1046,7 @@ __device__ __forceinline__ uint32_t or8_last(uint32_t x)
 
 // q: the lane's quad, which may lie past the class end (q1); its structure
 // and spins are read at min(q, q1 - 1) and then it has no live spin.
-template <int WD>
+template <int WD, bool TRACK>
 __device__ __forceinline__ void bits_update_quad(const DevProblem &P, const Rsrc &Rs, int q,
                                                  int q1, int c, unsigned live, uint32_t t,
                                                  const SlotParams (&sp)[kBitSlots],
@@ -1083,8 +1097,11 @@ __device__ __forceinline__ void bits_update_quad(const DevProblem &P, const Rsrc
     const v4i h0 = bload(Rs.bias, voff, 0);
     const int bpos = qs * 4 - P.cls_start[c] + P.bit_start[c];
     const int wq = bpos >> 5, off = bpos & 31;
-    const u4v ow = *(const lds_u4_t *)(uintptr_t)(uint32_t)(wq * 16);
-    const uint32_t o4[4] = {ow.x, ow.y, ow.z, ow.w};
+    uint32_t o4[4] = {0u, 0u, 0u, 0u};
+    if (TRACK) {
+        const u4v ow = *(const lds_u4_t *)(uintptr_t)(uint32_t)(wq * 16);
+        o4[0] = ow.x; o4[1] = ow.y; o4[2] = ow.z; o4[3] = ow.w;
+    }
     uint32_t nw4[kBitSlots];
 #pragma unroll
     for (int r = 0; r < kBitSlots; ++r) {
@@ -1113,14 +1130,16 @@ __device__ __forceinline__ void bits_update_quad(const DevProblem &P, const Rsrc
             }
         }
         up &= live;
-        const uint32_t old = (o4[r] >> off) & 15u;
+        if (TRACK) {
+            const uint32_t old = (o4[r] >> off) & 15u;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            // s_new - s_old = 2 (bit_new - bit_old); dead spins change nothing.
-            // df = -(s_new - s_old) hp, dg = -2 (s_new - s_old) cs
-            const int db = (((live >> j) & 1u) ? ((int)((up >> j) & 1u) - (int)((old >> j) & 1u)) : 0);
-            dfa[r] -= 2 * db * hp[j];
-            dga[r] -= 4 * db * cs[j][r];
+            for (int j = 0; j < 4; ++j) {
+                // s_new - s_old = 2 (bit_new - bit_old); dead spins change nothing.
+                // df = -(s_new - s_old) hp, dg = -2 (s_new - s_old) cs
+                const int db = (((live >> j) & 1u) ? ((int)((up >> j) & 1u) - (int)((old >> j) & 1u)) : 0);
+                dfa[r] -= 2 * db * hp[j];
+                dga[r] -= 4 * db * cs[j][r];
+            }
         }
         nw4[r] = up << off;  // 0 for a lane past the class end
     }
@@ -1135,9 +1154,71 @@ __device__ __forceinline__ void bits_update_quad(const DevProblem &P, const Rsrc
     }
 }
 
-// One round of up to kBitSlots slots (slot0 ..): unpack the int8 states into
-// LDS bits, mcs sweeps, pack them back.
+// f and g of the kBitSlots replicas from scratch, over the live spins of quad
+// q of class c (ef accumulates 2 f, eg accumulates g / 2).  With b_i the
+// spin's bit and A_i = sum_k J_k b_k over its problem neighbours,
+// sum_k J_k s_k = h0_i + 2 A_i - b_i (h0 = b - sum_k J_k), so
+// 2 f = -sum_i s_i (h0_i + 2 A_i + b_i); a copy edge whose ends differ
+// adds 4 to g, seen from both ends.
 template <int WD>
+__device__ __forceinline__ void bits_energy_quad(const DevProblem &P, const Rsrc &Rs,
+                                                 const __amdgpu_buffer_rsrc_t &rb, int q, int c,
+                                                 unsigned live, int64_t (&ef)[kBitSlots], int (&eg)[kBitSlots])
+{
+    const int voff = q * 16;
+    const int row = P.n_pad * 4;
+    int acc[4][kBitSlots];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < kBitSlots; ++r) acc[j][r] = 0;
+#pragma unroll
+    for (int k = 0; k < WD; ++k) {
+        const v4i pk = bload(Rs.a, voff, k * row);
+        const v4i jk = bload(Rs.b, voff, k * row);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int pos = pk[j];
+            const u4v nw = *(const lds_u4_t *)(uintptr_t)(uint32_t)(pos >> 5);
+            const uint32_t w4[4] = {nw.x, nw.y, nw.z, nw.w};
+#pragma unroll
+            for (int r = 0; r < kBitSlots; ++r)
+                acc[j][r] = mad24((int)__builtin_amdgcn_ubfe(w4[r], pos & 31, 1), jk[j], acc[j][r]);
+        }
+    }
+    const v4i c0 = bload(Rs.ch, voff, 0);
+    const v4i c1 = bload(Rs.ch, voff, row);
+    const v4i h0 = bload(Rs.bias, voff, 0);
+    const v4i bb = bload(rb, voff, 0);
+    const int bpos = q * 4 - P.cls_start[c] + P.bit_start[c];
+    const int wq = bpos >> 5, off = bpos & 31;
+    const u4v ow = *(const lds_u4_t *)(uintptr_t)(uint32_t)(wq * 16);
+    const uint32_t o4[4] = {ow.x, ow.y, ow.z, ow.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (!((live >> j) & 1u)) continue;
+        const int p0 = c0[j], p1 = c1[j];
+        const int kc = (int)((uint32_t)p0 >> 29);  // copy neighbours present: row 0 first
+        const u4v n0 = *(const lds_u4_t *)(uintptr_t)__builtin_amdgcn_ubfe((uint32_t)p0, 5, 18);
+        const u4v n1 = *(const lds_u4_t *)(uintptr_t)(uint32_t)(p1 >> 5);
+        const uint32_t a4[4] = {n0.x, n0.y, n0.z, n0.w}, b4[4] = {n1.x, n1.y, n1.z, n1.w};
+#pragma unroll
+        for (int r = 0; r < kBitSlots; ++r) {
+            const uint32_t bi = (o4[r] >> (off + j)) & 1u;
+            const int64_t t = (int64_t)(h0[j] + 2 * acc[j][r]) + bb[j];
+            ef[r] += bi ? -t : t;
+            const uint32_t d0 = (bi ^ __builtin_amdgcn_ubfe(a4[r], p0 & 31, 1)) & (kc >= 1 ? 1u : 0u);
+            const uint32_t d1 = (bi ^ __builtin_amdgcn_ubfe(b4[r], p1 & 31, 1)) & (kc >= 2 ? 1u : 0u);
+            eg[r] += (int)(d0 + d1);
+        }
+    }
+}
+
+// One round of up to kBitSlots slots (slot0 ..): unpack the int8 states into
+// LDS bits, mcs sweeps, pack them back.  TRACK: f and g follow every update
+// exactly (cheap for few sweeps per round); otherwise they are recomputed
+// from the final states of the round (cheaper from about 4 sweeps on).
+template <int WD, bool TRACK>
 __device__ __forceinline__ void round_sweep_bits_body(const DevProblem &P, int slot0, int8_t *lds)
 {
     // the replicas' words sit at LDS byte 0 (the update addresses them there)
@@ -1192,11 +1273,29 @@ __device__ __forceinline__ void round_sweep_bits_body(const DevProblem &P, int s
                 const int q = base + tid;
                 const int rem = q < q1 ? live_end - q * 4 : 0;
                 const unsigned live = rem >= 4 ? 15u : rem <= 0 ? 0u : ((1u << rem) - 1u);
-                bits_update_quad<WD>(P, Rs, q, q1, c, live, t, sp, dfa, dga);
+                bits_update_quad<WD, TRACK>(P, Rs, q, q1, c, live, t, sp, dfa, dga);
             }
 #pragma unroll
             for (int r = 0; r < kBitSlots; ++r) { df[r] += dfa[r]; dg[r] += dga[r]; }
             __syncthreads();
+        }
+    }
+    if (!TRACK) {
+        // f and g of the final states: 2 f into df, g / 2 into dg
+        const __amdgpu_buffer_rsrc_t rb = rsrc(P.bias, P.n_pad * 4);
+        for (int c = 0; c < P.n_colors; ++c) {
+            const int q0 = P.cls_start[c] >> 2, q1 = P.cls_start[c + 1] >> 2;
+            const int live_end = P.cls_live[c];
+            int eg[kBitSlots];
+#pragma unroll
+            for (int r = 0; r < kBitSlots; ++r) eg[r] = 0;
+            for (int q = q0 + tid; q < q1; q += nthr) {
+                const int rem = live_end - q * 4;
+                const unsigned live = rem >= 4 ? 15u : rem <= 0 ? 0u : ((1u << rem) - 1u);
+                bits_energy_quad<WD>(P, Rs, rb, q, c, live, df, eg);
+            }
+#pragma unroll
+            for (int r = 0; r < kBitSlots; ++r) dg[r] += eg[r];
         }
     }
     const int wave = tid >> 6, nw = nthr >> 6;
@@ -1209,8 +1308,13 @@ __device__ __forceinline__ void round_sweep_bits_body(const DevProblem &P, int s
     if (tid < ns) {
         int64_t a = 0, b = 0;
         for (int w = 0; w < nw; ++w) { a += red[2 * (w * kBitSlots + tid)]; b += red[2 * (w * kBitSlots + tid) + 1]; }
-        P.f[slot0 + tid] += a;
-        P.g[slot0 + tid] += b;
+        if (TRACK) {
+            P.f[slot0 + tid] += a;
+            P.g[slot0 + tid] += b;
+        } else {
+            P.f[slot0 + tid] = a / 2;
+            P.g[slot0 + tid] = 2 * b;
+        }
     }
     // pack back: live spins only (class padding stays 0 in the int8 copy)
     for (int i = tid; i < P.n_words * kBitSlots; i += nthr) {
@@ -1228,15 +1332,16 @@ __device__ __forceinline__ void round_sweep_bits_body(const DevProblem &P, int s
     }
 }
 
-template <int WD>
-__global__ __launch_bounds__(kBitsBlock) void k_round_sweep_bits(DevProblem P)
+template <int WD, bool TRACK>
+__global__ __launch_bounds__(TRACK ? kBitsBlock : kBitsBlockScratch) void k_round_sweep_bits(DevProblem P)
 {
     extern __shared__ __align__(16) int8_t lds[];
-    round_sweep_bits_body<WD>(P, blockIdx.x * kBitSlots, lds);
+    round_sweep_bits_body<WD, TRACK>(P, blockIdx.x * kBitSlots, lds);
 }
 
-template <int WD>
-__global__ __launch_bounds__(kBitsBlock) void k_batch_sweep_bits(const DevProblem *__restrict__ table,
+template <int WD, bool TRACK>
+__global__ __launch_bounds__(TRACK ? kBitsBlock : kBitsBlockScratch) void k_batch_sweep_bits(
+    const DevProblem *__restrict__ table,
                                                               const int *__restrict__ first_block, int count)
 {
     extern __shared__ __align__(16) int8_t lds[];
@@ -1247,7 +1352,7 @@ __global__ __launch_bounds__(kBitsBlock) void k_batch_sweep_bits(const DevProble
         if (first_block[mid] <= b) lo = mid;
         else hi = mid - 1;
     }
-    round_sweep_bits_body<WD>(table[lo], (b - first_block[lo]) * kBitSlots, lds);
+    round_sweep_bits_body<WD, TRACK>(table[lo], (b - first_block[lo]) * kBitSlots, lds);
 }
 
 // ---------------------------------------------------- initial states, f, g
@@ -1531,49 +1636,56 @@ static size_t bits_lds(int n_words)
     return (size_t)(n_words + 1) * 16 + 8 * 2 * kBitSlots * (kMaxBlock / 64) + 16;
 }
 
-template <int NARROW, int WD>
+template <bool TRACK, int WD>
 static hipError_t sweep_bits_t(const DevProblem &p, hipStream_t s)
 {
     const size_t lds = bits_lds(p.n_words);
-    hipError_t e = allow_lds(k_round_sweep_bits<WD>, lds);
+    hipError_t e = allow_lds(k_round_sweep_bits<WD, TRACK>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_round_sweep_bits<WD>), dim3((p.R + kBitSlots - 1) / kBitSlots),
-                       dim3(min(p.block, kBitsBlock)), lds, s, p);
+    hipLaunchKernelGGL((k_round_sweep_bits<WD, TRACK>), dim3((p.R + kBitSlots - 1) / kBitSlots),
+                       dim3(min(p.block, TRACK ? kBitsBlock : kBitsBlockScratch)), lds, s, p);
     return hipGetLastError();
 }
 
-template <int NARROW, int WD>
+template <bool TRACK, int WD>
 static hipError_t batch_sweep_bits_t(const DevProblem &p, const DevProblem *table, const int *first_block,
                                      int count, int blocks, int block, int max_words, hipStream_t s)
 {
     (void)p;
     const size_t lds = bits_lds(max_words);
-    hipError_t e = allow_lds(k_batch_sweep_bits<WD>, lds);
+    hipError_t e = allow_lds(k_batch_sweep_bits<WD, TRACK>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_batch_sweep_bits<WD>), dim3(blocks), dim3(min(block, kBitsBlock)), lds, s, table,
-                       first_block, count);
+    hipLaunchKernelGGL((k_batch_sweep_bits<WD, TRACK>), dim3(blocks),
+                       dim3(min(block, TRACK ? kBitsBlock : kBitsBlockScratch)), lds, s,
+                       table, first_block, count);
     return hipGetLastError();
 }
 
-#define TDPT_DISPATCH_BITS(FN, ...)                 \
+#define TDPT_BITS_CASE(FN, W, TR, ...) \
+    case W: return (TR) ? FN<true, W>(__VA_ARGS__) : FN<false, W>(__VA_ARGS__);
+#define TDPT_DISPATCH_BITS(FN, TR, ...)              \
     switch (p.wd) {                                  \
-    case 1: return FN<false, 1>(__VA_ARGS__);        \
-    case 2: return FN<false, 2>(__VA_ARGS__);        \
-    case 3: return FN<false, 3>(__VA_ARGS__);        \
-    case 4: return FN<false, 4>(__VA_ARGS__);        \
-    case 5: return FN<false, 5>(__VA_ARGS__);        \
-    case 6: return FN<false, 6>(__VA_ARGS__);        \
-    case 7: return FN<false, 7>(__VA_ARGS__);        \
-    case 8: return FN<false, 8>(__VA_ARGS__);        \
+    TDPT_BITS_CASE(FN, 1, TR, __VA_ARGS__)           \
+    TDPT_BITS_CASE(FN, 2, TR, __VA_ARGS__)           \
+    TDPT_BITS_CASE(FN, 3, TR, __VA_ARGS__)           \
+    TDPT_BITS_CASE(FN, 4, TR, __VA_ARGS__)           \
+    TDPT_BITS_CASE(FN, 5, TR, __VA_ARGS__)           \
+    TDPT_BITS_CASE(FN, 6, TR, __VA_ARGS__)           \
+    TDPT_BITS_CASE(FN, 7, TR, __VA_ARGS__)           \
+    TDPT_BITS_CASE(FN, 8, TR, __VA_ARGS__)           \
     default: return hipErrorInvalidValue;            \
     }
 
-hipError_t launch_sweep_bits(const DevProblem &p, hipStream_t s) { TDPT_DISPATCH_BITS(sweep_bits_t, p, s) }
+hipError_t launch_sweep_bits(const DevProblem &p, hipStream_t s)
+{
+    TDPT_DISPATCH_BITS(sweep_bits_t, track_updates(p.mcs), p, s)
+}
 
 hipError_t launch_batch_sweep_bits(const DevProblem &p, const DevProblem *table, const int *first_block,
-                                   int count, int blocks, int block, int max_words, hipStream_t s)
+                                   int count, int blocks, int block, int max_words, int min_mcs, hipStream_t s)
 {
-    TDPT_DISPATCH_BITS(batch_sweep_bits_t, p, table, first_block, count, blocks, block, max_words, s)
+    TDPT_DISPATCH_BITS(batch_sweep_bits_t, track_updates(min_mcs), p, table, first_block, count, blocks, block,
+                       max_words, s)
 }
 
 hipError_t launch_batch_swap(const DevProblem *table, int count, hipStream_t s)

@@ -715,7 +715,7 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     if (hmax >= ((int64_t)1 << 31))
         return fail(TDPT_E_RANGE, "local field can reach 2^31");
     const bool bits = use_bits(in);
-    const int64_t blk = bits ? std::min(sweep_block(in, false), tdpt::kBitsBlock)
+    const int64_t blk = bits ? std::min(sweep_block(in, false), tdpt::bits_block_cap(cfg->mcs_per_swap))
                              : std::min(sweep_block(in, false), sweep_block(in, true));
     // a lane's per-phase sums: of 2 |h| (f) and of 2 |c| (g) per spin, c the
     // half penalty field, which P = 0 leaves out of hmax
@@ -779,7 +779,8 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     d.wd = L.wd;
     d.narrow = narrow ? 1 : 0;
     d.has_bias = in->has_bias;
-    d.block = bits ? std::min(sweep_block(in, false), tdpt::kBitsBlock) : sweep_block(in, false);
+    d.block = bits ? std::min(sweep_block(in, false), tdpt::bits_block_cap(cfg->mcs_per_swap))
+                   : sweep_block(in, false);
     d.bits = bits ? 1 : 0;
     d.n_words = n_words;
     for (int c = 0; c <= in->n_colors; ++c) d.bit_start[c] = bit_start[c];
@@ -1121,7 +1122,7 @@ int tdpt_problem_autotune(tdpt_problem *p, int32_t rounds_per_trial, tdpt_tune_r
         return fail(TDPT_E_RANGE, "a problem runs at most 2^32 sweeps");
     // candidates: (driver, threads per workgroup)
     std::vector<std::pair<int, int>> cand;
-    const int cap = p->dp.bits ? tdpt::kBitsBlock : tdpt::kMaxBlock;
+    const int cap = p->dp.bits ? tdpt::bits_block_cap(p->mcs) : tdpt::kMaxBlock;
     const int per_round[] = {64, 128, 192, 256, 384, 512, 640, 768, 1024};
     const int quads = p->max_class_quads;
     for (int b : per_round)
@@ -1293,6 +1294,18 @@ int tdpt_problem_read_trace(tdpt_problem *p, int64_t *f_q, int64_t *g, int64_t *
     if (c > 0 && f_q) rc = d2h(p, f_q, p->dp.trace_f, (size_t)c * 8);
     if (!rc && c > 0 && g) rc = d2h(p, g, p->dp.trace_g, (size_t)c * 8);
     return rc;
+}
+
+int tdpt_problem_set_stage_trace(tdpt_problem *p, uint64_t *dev_buf, int32_t rounds)
+{
+    if (!p) return fail(TDPT_E_INVALID, "problem is NULL");
+    if (rounds < 0 || (rounds > 0 && !dev_buf)) return fail(TDPT_E_INVALID, "need a buffer for rounds > 0");
+    if (int rc = member_busy(p)) return rc;
+    HIP_TRY(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+    p->dp.stage = rounds ? dev_buf : nullptr;
+    p->dp.stage_cap = rounds;
+    p->dp.stage_round0 = p->rounds_host;
+    return TDPT_OK;
 }
 
 int tdpt_problem_read_best_logical(tdpt_problem *p, int8_t *x, int64_t *f_q, int64_t *sweep)
@@ -1481,6 +1494,7 @@ struct tdpt_batch {
         int block;      // threads per sweep workgroup of this group
         int min_block;  // smallest the members' per-phase bounds allow
         size_t plds;    // LDS of a persistent workgroup (largest member)
+        int min_mcs;    // fewest sweeps per round among the members
     };
     std::vector<Group> groups;
     hipEvent_t done = nullptr;
@@ -1622,7 +1636,7 @@ static int enqueue_batch_round(tdpt_batch *b, hipStream_t s)
         hipStream_t gs = gi == 0 ? s : b->aux[(gi - 1) % tdpt_batch::kAux];
         const tdpt::DevProblem &d0 = b->members[g.first_member]->dp;
         hipError_t e = d0.bits ? tdpt::launch_batch_sweep_bits(d0, table + g.first_member, prefix + g.prefix_off,
-                                                               g.count, g.blocks, g.block, g.max_words, gs)
+                                                               g.count, g.blocks, g.block, g.max_words, g.min_mcs, gs)
                                : tdpt::launch_batch_sweep(d0, table + g.first_member, prefix + g.prefix_off,
                                                           g.count, g.blocks, g.block, g.max_stride, gs);
         if (e != hipSuccess) return hip_fail(e, "launch batch sweep");
@@ -1739,7 +1753,7 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
     for (size_t i = 0; i < m.size(); ++i) {
         table[i] = m[i]->dp;
         if (groups.empty() || !(group_key(m[i]->dp) == group_key(m[i - 1]->dp))) {
-            tdpt_batch::Group g{(int)i, 0, 0, (int)prefix.size(), 0, 0, 0, 64, 0};
+            tdpt_batch::Group g{(int)i, 0, 0, (int)prefix.size(), 0, 0, 0, 64, 0, INT_MAX};
             groups.push_back(g);
         }
         auto &g = groups.back();
@@ -1750,6 +1764,7 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
         g.max_stride = std::max(g.max_stride, (size_t)m[i]->dp.stride);
         g.max_words = std::max(g.max_words, m[i]->dp.n_words);
         g.plds = std::max(g.plds, tdpt::persistent_lds_bytes(m[i]->dp.stride, m[i]->I, m[i]->J));
+        g.min_mcs = std::min(g.min_mcs, m[i]->mcs);
     }
     // every group runs one kernel instance over its members' descriptors:
     // refuse a group whose members would need different instances
@@ -1758,7 +1773,7 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
             if (!(group_key(m[k]->dp) == group_key(m[g.first_member]->dp)))
                 return fail(TDPT_E_INVALID, "internal: a batch group mixes structure layouts");
     for (auto &g : groups) {
-        const int cap = m[g.first_member]->dp.bits ? tdpt::kBitsBlock : tdpt::kMaxBlock;
+        const int cap = m[g.first_member]->dp.bits ? tdpt::bits_block_cap(g.min_mcs) : tdpt::kMaxBlock;
         if (g.min_block > cap)
             return fail(TDPT_E_RANGE, "a member's per-phase energy bounds need a larger workgroup than "
                                       "the batched sweep allows");
@@ -1886,7 +1901,7 @@ int tdpt_batch_autotune(tdpt_batch *b, int32_t rounds_per_trial, tdpt_batch_tune
     out->n_groups = (int32_t)b->groups.size();
     for (size_t gi = 0; gi < b->groups.size() && rc == TDPT_OK; ++gi) {
         auto &g = b->groups[gi];
-        const int cap = b->members[g.first_member]->dp.bits ? tdpt::kBitsBlock : tdpt::kMaxBlock;
+        const int cap = b->members[g.first_member]->dp.bits ? tdpt::bits_block_cap(g.min_mcs) : tdpt::kMaxBlock;
         double best = 1e300;
         int best_block = g.block;
         for (int sz : sizes) {

@@ -33,7 +33,7 @@ EXPORTED = [
     "tdpt_batch_set_graph", "tdpt_batch_set_driver", "tdpt_batch_query_driver",
     "tdpt_layout_get", "tdpt_problem_query_async", "tdpt_problem_read_energies_async",
     "tdpt_problem_read_states_async", "tdpt_problem_read_best_async", "tdpt_problem_read_best_logical",
-    "tdpt_problem_read_histogram", "tdpt_problem_create_static",
+    "tdpt_problem_read_histogram", "tdpt_problem_create_static", "tdpt_problem_set_stage_trace",
 ]
 
 STATIC_WORKSPACE_BYTES = 64 << 20
@@ -111,6 +111,7 @@ def load_library():
         "tdpt_problem_read_best_logical": [P, P, P, P],
         "tdpt_problem_read_histogram": [P, P, P],
         "tdpt_problem_create_static": [P, P, P, P],
+        "tdpt_problem_set_stage_trace": [P, P, I32],
         "tdpt_instance_info_get": [P, P],
         "tdpt_workspace_bytes": [P, P, P],
         "tdpt_problem_create": [P, P, P, SZ, P, P],
@@ -402,6 +403,13 @@ class Problem:
         k = r.n_trials
         return {"driver": r.driver, "block": r.block, "ms_per_round": r.ms_per_round,
                 "trials": [(r.trial_driver[i], r.trial_block[i], r.trial_ms_per_round[i]) for i in range(k)]}
+
+    def set_stage_trace(self, buf, rounds: int):
+        """Persistent driver: per-round, per-slot stage timestamps (100 MHz
+        clock) into a device int64 tensor of rounds * R * 4 (None, 0: off)."""
+        if rounds and (buf is None or buf.numel() < rounds * self.R * 4):
+            raise ValueError("the buffer needs rounds * R * 4 entries")
+        _check(_lib.tdpt_problem_set_stage_trace(self._h, _dptr(buf), int(rounds)))
 
     def set_timing(self, every: int):
         """Time every `every`-th sweep-kernel launch with HIP events (0: off)."""

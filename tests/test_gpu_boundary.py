@@ -214,3 +214,26 @@ def test_batch_membership_rules(T):
     assert probs[1].query()["rounds_done"] == long_run + 22
     B.close()
     C.close()
+
+
+def test_stage_trace_of_the_persistent_driver(T):
+    """Stage timestamps for 12 rounds of a persistent run: every slot's four
+    stamps are ordered within each round, rounds follow one another, rounds
+    past the cap stay unwritten, and the run's results equal the oracle's."""
+    import torch
+    from tests.test_gpu_parity import assert_same
+    w = wishart_small()
+    cfg = T.RunConfig(w.beta, w.p_q, mcs_per_swap=5, seed=4, trace_cap=30)
+    P = _with_env("TDPT_PERSISTENT", "1", lambda: T.Problem(T.Instance.from_synth(w.instance), cfg))
+    assert P.query()["driver"] == 1
+    P.run(6)
+    buf = torch.zeros(16 * P.R * 4, dtype=torch.int64, device="cuda")
+    P.set_stage_trace(buf, 12)
+    P.run(24)
+    P.set_stage_trace(None, 0)
+    t = buf.view(16, P.R, 4).cpu().numpy()
+    assert (t[:12] > 0).all() and (t[12:] == 0).all()
+    assert (np.diff(t[:12], axis=2) >= 0).all()
+    assert (t[1:12, :, 0] >= t[:11, :, 3]).all()
+    o = O.run(w.instance, w.beta, w.p_q, mcs_per_swap=5, n_rounds=30, seed=4, trace=True)
+    assert_same(o, P, "with stage trace")

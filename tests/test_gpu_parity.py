@@ -457,3 +457,18 @@ def test_autotune_n200_and_bits(T):
     ws = wishart_small()
     o = O.run(ws.instance, ws.beta, ws.p_q, mcs_per_swap=5, n_rounds=20, seed=2, trace=True)
     assert_same(o, Q, "tuned bits")
+
+
+@pytest.mark.parametrize("mcs,block", [(5, "1024"), (5, "256"), (2, "1024")])
+def test_bit_packed_block_sizes(T, mcs, block):
+    """Bit-packed replicas at 1024 threads (allowed when f and g are
+    recomputed at the round's end, from 4 sweeps per round), at 256, and
+    capped at 768 when they follow every update (2 sweeps per round): the
+    same results as the oracle."""
+    w = batched_member(100, 0.8, 5)
+
+    def go():
+        return _with_env("TDPT_BLOCK", block, lambda: both(
+            T, w.instance, w.beta[:4], w.p_q[:4], mcs=mcs, rounds=5, seed=7,
+            label=f"bits mcs {mcs} block {block}"))
+    _with_env("TDPT_LAYOUT", "bits", go)
