@@ -65,15 +65,10 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # copy of known size; valid for that kernel on that workload and for the
 # kernel source with this hash.
 MEASURED_TRAFFIC = {
-    # one 200-round launch on the N=200 workload: FETCH 17,077.9 KiB, WRITE 11,957.0 KiB
-    "wishart-N200-D8-32x16": {"kernel": "k_persistent", "kernel_sha256": "20540c1d83ce3149",
-                              "bytes_per_round": 236098},
-    # one 50-sweep round on the N=1000 workload: FETCH 5,329,078.9 KiB, WRITE 513,511.5 KiB
-    "wishart-N1000-D6-64x32": {"kernel": "k_round_sweep_bits", "kernel_sha256": "20540c1d83ce3149",
-                               "bytes_per_round": 11439789296},
-    # one 10-round launch on the colouring workload: FETCH 8,980.2 KiB, WRITE 17,799.8 KiB
-    "coloring-V4000-k4-d6-32x16": {"kernel": "k_persistent", "kernel_sha256": "20540c1d83ce3149",
-                                   "bytes_per_round": 3661856},
+    # one 50-sweep round on the N=1000 workload, 1024-thread workgroups:
+    # FETCH 5,444,210 KiB, WRITE 533,745 KiB (mean of 4 dispatches)
+    "wishart-N1000-D6-64x32": {"kernel": "k_round_sweep_bits", "kernel_sha256": "b3d7a50f872f640a",
+                               "bytes_per_round": 11696296448},
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_2506_14781_amd", "csrc", "tdpt_kernels.hip")
 
@@ -711,27 +706,26 @@ def main():
                                   "scaled by a plain copy's counters (null once the kernel source changed)",
                 "ops_per_update": round(ops, 2)}
     # the byte model: what one update must move at the level its data live
+    # (the structure is served by L2 / Infinity Cache; the measured HBM
+    # traffic, `traffic`, is a small part of it)
     d_bar = info["nnz"] / info["n"]
     if bits:
         wd = max(1, info["max_degree"]) if info["max_degree"] <= 8 else 16
         bpu = bits_bytes_per_update(info, wd)
-        roofline["bytes_model"] = {
-            "what": "structure streamed once per sweep per 4-replica workgroup (neighbour bit positions "
-                    "and couplings 8 B per ELL entry, copy positions 8 B, field 4 B per padded spin, / 4); "
-                    "spins are LDS-resident bits",
-            "bytes_per_update": round(bpu, 3),
-            "achieved_GBps": round(bpu * updates_per_launch / (launch_ms / 1e3) / 1e9, 1),
-            "peak_GBps": 8000.0}
-        roofline["bytes_model"]["frac"] = round(roofline["bytes_model"]["achieved_GBps"] / 8000.0, 4)
+        what = ("structure streamed once per sweep per 4-replica workgroup (neighbour bit positions "
+                "and couplings 8 B per ELL entry, copy positions 8 B, field 4 B per padded spin, / 4); "
+                "spins are LDS-resident bits")
     else:
         r_share = w.n_p
         bpu = (d_bar + 1) + (8 * d_bar + 4) / r_share
-        roofline["bytes_model"] = {
-            "what": "(d+1) int8 spin reads/writes + (8 d + 4) B of structure shared by the replicas of a row",
-            "bytes_per_update": round(bpu, 3),
-            "achieved_GBps": round(bpu * updates_per_launch / (launch_ms / 1e3) / 1e9, 1),
-            "peak_GBps": 8000.0}
-        roofline["bytes_model"]["frac"] = round(roofline["bytes_model"]["achieved_GBps"] / 8000.0, 4)
+        what = "(d+1) int8 spin reads/writes + (8 d + 4) B of structure shared by the replicas of a row"
+    roofline["bytes_model"] = {"what": what, "bytes_per_update": round(bpu, 3),
+                               "achieved_GBps": round(bpu * updates_per_launch / (launch_ms / 1e3) / 1e9, 1)}
+    if roofline["traffic"] is not None:
+        hbm = roofline["traffic"] / (launch_ms / 1e3) / 1e9
+        roofline["hbm_GBps"] = round(hbm, 1)
+        roofline["hbm_frac"] = round(hbm / 8000.0, 4)
+        roofline["hbm_bytes_per_update"] = round(roofline["traffic"] / updates_per_launch, 4)
     roofline.update({"kernel": kernel, "kernel_avg_ms": round(launch_ms, 5),
                      "kernel_launches_timed": timed, "updates_per_launch": updates_per_launch})
     q = prob.query()

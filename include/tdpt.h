@@ -216,7 +216,7 @@ int tdpt_workspace_bytes(const tdpt_instance *inst, const tdpt_run_cfg *cfg, siz
  * field could reach 2^31 in magnitude (sum |J_q| + |b_q| + 2 P_q * copy
  * degree) or an energy difference 2^52, or if an instance whose replica
  * exceeds 48 KiB as int8 (the bit-packed layout) has a coupling with
- * |J_q| >= 2^23.  Returns TDPT_E_INVALID if such an instance has more than
+ * |J_q| >= 2^23 or a penalty P_q >= 2^22.  Returns TDPT_E_INVALID if such an instance has more than
  * 8 problem neighbours on a spin, or if one replica does not fit the LDS of
  * a workgroup. */
 int tdpt_problem_create(const tdpt_instance *inst, const tdpt_run_cfg *cfg, void *dev_ws,

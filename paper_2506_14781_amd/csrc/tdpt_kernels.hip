@@ -1113,7 +1113,7 @@ __device__ __forceinline__ void bits_update_quad(const DevProblem &P, const Rsrc
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             hp[j] = h0[j] + 2 * acc[j][r];
-            hh[j] = sp[r].twoP * cs[j][r] + hp[j];
+            hh[j] = mad24(cs[j][r], sp[r].twoP, hp[j]);  // |2 P_q| < 2^23 in this layout
             bool a;
             up |= heat_bath_up(hh[j], sp[r].cb, u[j], a) ? (1u << j) : 0u;
             amb_any |= a && ((live >> j) & 1u);

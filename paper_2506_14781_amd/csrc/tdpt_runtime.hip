@@ -278,14 +278,31 @@ int check_cfg(const tdpt_run_cfg *c)
     return TDPT_OK;
 }
 
+// The fewest passes of a workgroup of at most `cap` threads over `quads`
+// quads (one per lane per pass), then the fewest threads that keep that
+// number of passes, in whole waves -- whole groups of four waves (one per
+// SIMD of the compute unit) once a pass needs that many, since a compute
+// unit whose SIMDs hold unequal wave counts waits for the fullest at every
+// class barrier (at N=1000, one bit-packed workgroup per compute unit:
+// 960 threads 33.5 ms per round, 1024 threads 31.6 ms).
+int balanced_block(int quads, int cap)
+{
+    const int passes = std::max(1, (quads + cap - 1) / cap);
+    const int need = (quads + passes - 1) / passes;
+    const int g = need > 256 ? 256 : 64;
+    const int b = (need + g - 1) / g * g;
+    return std::min(std::max(b, 64), cap);
+}
+
 // Threads of a sweep workgroup: one lane per quad of the largest colour
-// class (per-round driver) or one lane per two quads (persistent driver,
-// whose two blocks per compute unit must both stay resident).
-int sweep_block(const tdpt_instance *in, bool persistent)
+// class, in balanced passes of at most `cap` threads (per-round driver), or
+// one lane per two quads (persistent driver, whose two blocks per compute
+// unit must both stay resident).
+int sweep_block(const tdpt_instance *in, bool persistent, int cap = tdpt::kMaxBlock)
 {
     const int quads = persistent ? (in->max_class_quads + 1) / 2 : in->max_class_quads;
-    int b = (quads + 63) / 64 * 64;
-    const int cap = persistent ? tdpt::kMaxBlock / 2 : tdpt::kMaxBlock;
+    if (persistent) cap = tdpt::kMaxBlock / 2;
+    int b = persistent ? (quads + 63) / 64 * 64 : balanced_block(quads, cap);
     if (const char *e = getenv("TDPT_BLOCK")) {
         const int v = atoi(e);
         if (v >= 64 && v <= cap && v % 64 == 0) b = v;
@@ -715,7 +732,7 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     if (hmax >= ((int64_t)1 << 31))
         return fail(TDPT_E_RANGE, "local field can reach 2^31");
     const bool bits = use_bits(in);
-    const int64_t blk = bits ? std::min(sweep_block(in, false), tdpt::bits_block_cap(cfg->mcs_per_swap))
+    const int64_t blk = bits ? sweep_block(in, false, tdpt::bits_block_cap(cfg->mcs_per_swap))
                              : std::min(sweep_block(in, false), sweep_block(in, true));
     // a lane's per-phase sums: of 2 |h| (f) and of 2 |c| (g) per spin, c the
     // half penalty field, which P = 0 leaves out of hmax
@@ -747,6 +764,8 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
         return fail(TDPT_E_INVALID, "the bit-packed layout takes at most 8 problem neighbours per spin");
     if (bits && in->max_abs_J >= ((int64_t)1 << 23))
         return fail(TDPT_E_RANGE, "the bit-packed layout takes couplings |J_q| < 2^23");
+    if (bits && pmax >= ((int64_t)1 << 22))
+        return fail(TDPT_E_RANGE, "the bit-packed layout takes penalties P_q < 2^22");
     if (bits ? (size_t)(n_words + 1) * 16 + 4096 > lds_limit : (size_t)L.stride > lds_limit)
         return fail(TDPT_E_INVALID, "a replica (" + std::to_string(in->n_pad) +
                                         " spins) does not fit the LDS of one workgroup");
@@ -779,8 +798,7 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     d.wd = L.wd;
     d.narrow = narrow ? 1 : 0;
     d.has_bias = in->has_bias;
-    d.block = bits ? std::min(sweep_block(in, false), tdpt::bits_block_cap(cfg->mcs_per_swap))
-                   : sweep_block(in, false);
+    d.block = bits ? sweep_block(in, false, tdpt::bits_block_cap(cfg->mcs_per_swap)) : sweep_block(in, false);
     d.bits = bits ? 1 : 0;
     d.n_words = n_words;
     for (int c = 0; c <= in->n_colors; ++c) d.bit_start[c] = bit_start[c];
@@ -1123,8 +1141,13 @@ int tdpt_problem_autotune(tdpt_problem *p, int32_t rounds_per_trial, tdpt_tune_r
     // candidates: (driver, threads per workgroup)
     std::vector<std::pair<int, int>> cand;
     const int cap = p->dp.bits ? tdpt::bits_block_cap(p->mcs) : tdpt::kMaxBlock;
-    const int per_round[] = {64, 128, 192, 256, 384, 512, 640, 768, 1024};
     const int quads = p->max_class_quads;
+    // a spread of sizes plus the balanced one (its last pass over a class
+    // nearly full)
+    std::vector<int> per_round = {64, 128, 192, 256, 384, 512, 640, 768, 1024};
+    const int bal = balanced_block(quads, cap);
+    if (std::find(per_round.begin(), per_round.end(), bal) == per_round.end()) per_round.push_back(bal);
+    std::sort(per_round.begin(), per_round.end());
     for (int b : per_round)
         if (b >= p->min_block && b <= cap && b <= std::max(64, (quads + 63) / 64 * 64)) cand.push_back({0, b});
     if (p->persistent_ok) {
