@@ -202,11 +202,14 @@ int tdpt_layout_get(const tdpt_instance *inst, const tdpt_run_cfg *cfg, tdpt_lay
 /* ---------------------------------------------------------------- problem */
 
 /* Device bytes a problem needs (structure, all replica states, energies,
- * counters, tracking and trace).  The caller allocates them (e.g. a torch
+ * counters, tracking and trace) for an instance and Algorithm 1's run inputs
+ * (the grid of beta and P values, sweeps per swap).  The caller allocates them (e.g. a torch
  * uint8 tensor) and passes the pointer to tdpt_problem_create. */
 int tdpt_workspace_bytes(const tdpt_instance *inst, const tdpt_run_cfg *cfg, size_t *bytes);
 
-/* Create a problem in a caller-owned device workspace (>= tdpt_workspace_bytes,
+/* Create a problem -- one run of Algorithm 1: the instance, the ordered beta
+ * and P ladders, sweeps per swap and the initial spins -- in a caller-owned
+ * device workspace (>= tdpt_workspace_bytes,
  * 256-byte aligned, on the current HIP device) and initialise it on `stream`
  * (a hipStream_t; NULL is the default stream): the workspace is cleared on
  * the device, the structure, ladders and any caller states are copied in,
@@ -287,7 +290,8 @@ int tdpt_problem_read_trace(tdpt_problem *prob, int64_t *f_q, int64_t *g, int64_
  * (*samples, may be NULL).  TDPT_E_STATE if the run did not ask for it. */
 int tdpt_problem_read_histogram(tdpt_problem *prob, uint32_t *counts, int64_t *samples);
 
-/* Checkpoint: copy the whole mutable device state to host memory.  With
+/* Checkpoint (not a step of the paper; it makes long runs resumable): copy
+ * the whole mutable device state to host memory.  With
  * host == NULL only *bytes is set.  tdpt_problem_load restores it into a
  * problem created from the same instance and configuration; a run resumed
  * from it is bit-identical to an uninterrupted one. */
@@ -299,10 +303,11 @@ int tdpt_problem_load(tdpt_problem *prob, const void *host, size_t bytes);  /* T
  * that batch then needs tdpt_batch_set_members before its next run. */
 void tdpt_problem_destroy(tdpt_problem *prob);
 
-/* Measurement hook: from now on record a pair of HIP events on the problem's
- * stream around every `every`-th launch of the sweep kernel (the per-round
- * sweep kernel, or the persistent kernel that runs many rounds); at most
- * 4096 pairs; 0 switches it off and clears what was recorded. */
+/* Measurement hook (not a step of the paper): from now on record a pair of
+ * HIP events on the problem's stream around every `every`-th launch of the
+ * sweep kernel (the per-round sweep kernel, or the persistent kernel that
+ * runs many rounds); at most 4096 pairs; 0 switches it off and clears what
+ * was recorded. */
 int tdpt_problem_set_timing(tdpt_problem *prob, int32_t every);
 /* Wait for the stream and report the summed duration (ms) of the timed
  * launches, how many were timed and how many swap rounds they covered. */
@@ -319,7 +324,8 @@ int tdpt_problem_read_timing(tdpt_problem *prob, double *total_ms, int64_t *laun
  * per-round driver records nothing.  Waits for the problem's stream. */
 int tdpt_problem_set_stage_trace(tdpt_problem *prob, uint64_t *dev_buf, int32_t rounds);
 
-/* Launch-shape autotuner.  Times each admissible (driver, threads per sweep
+/* Launch-shape autotuner (not a step of the paper: launch shapes never
+ * change results).  Times each admissible (driver, threads per sweep
  * workgroup) pair on the problem itself -- one warm-up round, then
  * rounds_per_trial rounds between HIP events on the problem's stream -- and
  * keeps the fastest for later runs.  Candidates: the per-round driver at 64
