@@ -127,6 +127,10 @@ struct DevProblem {
     uint64_t *stage;          // [stage_cap][R][4], caller-owned device memory
     int32_t stage_cap;
     int64_t stage_round0;
+    // persistent driver: workgroup b serves slot (b * slot_mul + slot_add) mod R
+    // (1, 0 normally; gcd(slot_mul, R) = 1), so tests can vary which
+    // workgroup, and so which compute unit and XCD, holds which slot
+    int32_t slot_mul, slot_add;
     // scratch of the persistent driver (not part of checkpoints)
     uint64_t *mbox;       // [kRing][R][2] tagged (f, g) by grid position
     int64_t *slot_key;    // [R] best key per slot during a launch

@@ -908,11 +908,18 @@ __device__ __forceinline__ void persistent_body(const DevProblem &P, int slot, i
     }
 }
 
+// The slot a persistent workgroup serves (the identity unless a test asks
+// for another order).
+__device__ __forceinline__ int persistent_slot(const DevProblem &P, int b)
+{
+    return (int)(((int64_t)b * P.slot_mul + P.slot_add) % P.R);
+}
+
 template <int NARROW, int WD>
 __global__ __launch_bounds__(kMaxBlock, 4) void k_persistent(DevProblem P, int64_t n_rounds)
 {
     extern __shared__ __align__(16) int8_t lds[];
-    persistent_body<NARROW, WD>(P, blockIdx.x, n_rounds, lds);
+    persistent_body<NARROW, WD>(P, persistent_slot(P, blockIdx.x), n_rounds, lds);
 }
 
 // Index of the table member whose block range holds block b (first_block is
@@ -939,7 +946,7 @@ __global__ __launch_bounds__(kMaxBlock, 4) void k_batch_persistent(const DevProb
 {
     extern __shared__ __align__(16) int8_t lds[];
     const int m = member_of(first_block, count, blockIdx.x);
-    persistent_body<NARROW, WD>(table[m], blockIdx.x - first_block[m], n_rounds, lds);
+    persistent_body<NARROW, WD>(table[m], persistent_slot(table[m], blockIdx.x - first_block[m]), n_rounds, lds);
 }
 
 // Before a persistent launch: clear the per-slot best keys and the hit word.

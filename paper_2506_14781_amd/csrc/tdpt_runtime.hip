@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <numeric>
 #include <string>
 #include <utility>
 #include <vector>
@@ -850,6 +851,16 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     d.slot_key = (int64_t *)(ws + L.slot_key);
     d.slot_best = (int8_t *)(ws + L.slot_best);
     d.hit_min = (int64_t *)(ws + L.hit_min);
+    d.slot_mul = 1;
+    d.slot_add = 0;
+    if (const char *e = getenv("TDPT_SLOT_ORDER")) {
+        // test hook "mul,add": another assignment of slots to persistent workgroups
+        long a = 1, b = 0;
+        if (sscanf(e, "%ld,%ld", &a, &b) == 2 && a >= 1 && b >= 0 && b < R && std::gcd((long)R, a) == 1) {
+            d.slot_mul = (int32_t)(a % R == 0 ? 1 : a % R);
+            d.slot_add = (int32_t)b;
+        }
+    }
     d.hist_n = hist_n;
     d.hist_rank = (const int32_t *)(ws + L.hist_rank);
     d.hist = (uint32_t *)(ws + L.hist);

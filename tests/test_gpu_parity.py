@@ -472,3 +472,40 @@ def test_bit_packed_block_sizes(T, mcs, block):
             T, w.instance, w.beta[:4], w.p_q[:4], mcs=mcs, rounds=5, seed=7,
             label=f"bits mcs {mcs} block {block}"))
     _with_env("TDPT_LAYOUT", "bits", go)
+
+
+@pytest.mark.parametrize("order", ["7,3", "31,5", "1,17"])
+def test_persistent_slot_order_does_not_matter(T, order):
+    """The persistent driver's exchange must not depend on which workgroup
+    (so which compute unit and XCD) serves which replica slot: with the
+    slots assigned to workgroups in another order the run equals the
+    oracle, for one problem and inside a persistent batch."""
+    w = wishart_small()
+    f_gs = O.energy(w.instance, w.instance.physical_state(w.instance.planted))[0]
+
+    def go():
+        o, P = both(T, w.instance, w.beta, w.p_q, mcs=5, rounds=60, seed=8, f_target=f_gs,
+                    label=f"slot order {order}")
+        assert P.query()["driver"] == 1
+        m = batched_member(64, 0.8, 3)
+        cfgs = [T.RunConfig(w.beta, w.p_q, mcs_per_swap=5, seed=9, trace_cap=30),
+                T.RunConfig(m.beta[:8], m.p_q[:4], mcs_per_swap=3, seed=4, trace_cap=30)]
+        insts = [w.instance, m.instance]
+        probs = [T.Problem(T.Instance.from_synth(i), c) for i, c in zip(insts, cfgs)]
+        B = T.Batch(2)
+        B.set_members(probs)
+        assert B.driver() == 1
+        B.run(30)
+        B.close()
+        for i, c, P in zip(insts, cfgs, probs):
+            o = O.run(i, c.beta, c.p_q, mcs_per_swap=c.mcs_per_swap, n_rounds=30, seed=c.seed, trace=True)
+            assert_same(o, P, f"batch slot order {order}")
+    _with_env("TDPT_PERSISTENT", "1", lambda: _with_env("TDPT_SLOT_ORDER", order, go))
+
+
+def test_persistent_slot_order_n200(T):
+    """The N=200 workload (512 workgroups over every compute unit) with slots
+    assigned in a scattered order: the first rounds equal the oracle."""
+    w = wishart_n200()
+    _with_env("TDPT_SLOT_ORDER", "251,100", lambda: both(
+        T, w.instance, w.beta, w.p_q, mcs=1, rounds=12, seed=2, label="N200 slot order 251,100"))
