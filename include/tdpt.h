@@ -366,8 +366,8 @@ int tdpt_problem_autotune(tdpt_problem *prob, int32_t rounds_per_trial, tdpt_tun
  * Continuous batching with these calls: admitting a problem or retiring one
  * is tdpt_batch_set_members with the new list (at a round boundary: the
  * call waits for the work in flight); launching is tdpt_batch_run (returns
- * at once); polling is tdpt_problem_query or tdpt_problem_query_async on
- * each member (first_hit_sweep, rounds_done). */
+ * at once); polling is tdpt_batch_query (every member's first_hit_sweep,
+ * rounds_done, best f at once) or tdpt_problem_query per member. */
 
 /* Device bytes of the descriptor table of a batch with up to max_members. */
 int tdpt_batch_workspace_bytes(int32_t max_members, size_t *bytes);
@@ -382,6 +382,13 @@ int tdpt_batch_set_members(tdpt_batch *batch, tdpt_problem *const *probs, int32_
 /* Enqueue n_rounds rounds of every member on the batch's stream.
  * TDPT_E_STATE if a member was destroyed or moved since set_members. */
 int tdpt_batch_run(tdpt_batch *batch, int64_t n_rounds);
+/* Poll every member at once: words[count][4] (in the order of the last
+ * tdpt_batch_set_members) = rounds_done, first_hit_sweep, best_f_q,
+ * best_sweep, as tdpt_problem_query reports them; one kernel and one copy
+ * instead of a read per member.  Waits for the batch's stream.  The _async
+ * form enqueues the same words into caller device memory on that stream. */
+int tdpt_batch_query(tdpt_batch *batch, int64_t *words);
+int tdpt_batch_query_async(tdpt_batch *batch, int64_t *dev_words);
 /* Autotune the threads per sweep workgroup of each layout group of the
  * current members (64 to 1024; 768 for bit-packed groups with a member of
  * fewer than 4 sweeps per round; no smaller than the members' per-phase

@@ -168,6 +168,9 @@ hipError_t launch_batch_finalize(const DevProblem *table, int count, int64_t n_r
 hipError_t launch_gather_energies(const DevProblem &p, int64_t *f, int64_t *g, hipStream_t s);
 hipError_t launch_gather_states(const DevProblem &p, int n, int8_t *out, hipStream_t s);
 hipError_t launch_gather_best(const DevProblem &p, int8_t *out, hipStream_t s);
+// [count][4] status words of a batch's members at out[order[i]] for table entry i.
+hipError_t launch_batch_status(const DevProblem *table, int count, const int32_t *order, int64_t *out,
+                               hipStream_t s);
 // Bit-packed layout: one round of every slot (ceil(R / kBitSlots) blocks).
 // Bit-packed sweeps of fewer than kScratchMcs per round follow f and g update
 // by update; longer rounds recompute them from the round's final states

@@ -1438,6 +1438,21 @@ __global__ __launch_bounds__(kSmallBlock) void k_energy(DevProblem P)
 }
 
 // ------------------------------------------------- readback into device buffers
+// Status words of every batch member (rounds done, first hit, best f, best
+// sweep), in the caller's member order.
+__global__ void k_batch_status(const DevProblem *__restrict__ table, int count, const int32_t *__restrict__ order,
+                               int64_t *out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int64_t *h = table[i].hdr;
+    int64_t *o = out + 4 * (size_t)order[i];
+    o[0] = h[kHdrRounds];
+    o[1] = h[kHdrFirstHit];
+    o[2] = h[kHdrBestF];
+    o[3] = h[kHdrBestSweep];
+}
+
 __global__ void k_gather_energies(DevProblem P, int64_t *f, int64_t *g)
 {
     const int pos = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1467,6 +1482,13 @@ __global__ void k_gather_best(DevProblem P, int8_t *out)
 }
 
 // ---------------------------------------------------------------- launchers
+hipError_t launch_batch_status(const DevProblem *table, int count, const int32_t *order, int64_t *out,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_status, dim3((count + 255) / 256), dim3(256), 0, s, table, count, order, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_gather_energies(const DevProblem &p, int64_t *f, int64_t *g, hipStream_t s)
 {
     hipLaunchKernelGGL(k_gather_energies, dim3((p.R + 255) / 256), dim3(256), 0, s, p, f, g);

@@ -1572,6 +1572,12 @@ struct tdpt_batch {
 };
 
 static size_t batch_table_bytes(int32_t cap) { return align_up((size_t)cap * sizeof(tdpt::DevProblem), 256); }
+// Batch workspace: the descriptor table, the members' block prefix sums, the
+// caller's index of every table entry, and [cap][4] int64 status words.
+static size_t batch_prefix_bytes(int32_t cap) { return align_up((size_t)(2 * cap + 1) * 4, 256); }
+static size_t batch_order_off(int32_t cap) { return batch_table_bytes(cap) + batch_prefix_bytes(cap); }
+static size_t batch_status_off(int32_t cap) { return batch_order_off(cap) + align_up((size_t)cap * 4, 256); }
+static size_t batch_ws_bytes(int32_t cap) { return batch_status_off(cap) + align_up((size_t)cap * 32, 256); }
 
 // TDPT_E_BUSY while the last run of the batch holding p has not finished.
 static int member_busy(tdpt_problem *p)
@@ -1716,7 +1722,7 @@ static int capture_batch_graph(tdpt_batch *b)
 int tdpt_batch_workspace_bytes(int32_t max_members, size_t *bytes)
 {
     if (max_members < 1 || !bytes) return fail(TDPT_E_INVALID, "need max_members >= 1");
-    *bytes = batch_table_bytes(max_members) + align_up((size_t)(2 * max_members + 1) * 4, 256);
+    *bytes = batch_ws_bytes(max_members);
     return TDPT_OK;
 }
 
@@ -1755,6 +1761,7 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
     std::vector<tdpt_problem *> m(probs, probs + count);
     for (auto *p : m)
         if (!p) return fail(TDPT_E_INVALID, "NULL member");
+    std::vector<tdpt_problem *> caller(m);
     {
         std::vector<tdpt_problem *> chk = m;
         std::sort(chk.begin(), chk.end());
@@ -1848,10 +1855,17 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
             for (size_t gi = 0; gi < b->groups.size(); ++gi) b->groups[gi].block = per_round_blocks[gi];
     }
     if (!m.empty()) {
+        // the caller's index of every table entry (for status reads in the caller's order)
+        std::vector<int32_t> order(m.size());
+        for (size_t i = 0; i < m.size(); ++i)
+            order[i] = (int32_t)(std::find(caller.begin(), caller.end(), m[i]) - caller.begin());
         hipError_t e = hipMemcpyAsync(b->ws, table.data(), table.size() * sizeof(tdpt::DevProblem),
                                       hipMemcpyHostToDevice, b->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(b->ws + batch_table_bytes(b->cap), prefix.data(), prefix.size() * 4,
+                               hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->ws + batch_order_off(b->cap), order.data(), order.size() * 4,
                                hipMemcpyHostToDevice, b->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
         if (e != hipSuccess) {
@@ -1967,6 +1981,30 @@ int tdpt_batch_autotune(tdpt_batch *b, int32_t rounds_per_trial, tdpt_batch_tune
     b->graph_rounds = graph_rounds;
     const int rc2 = restore();
     return rc ? rc : rc2;
+}
+
+int tdpt_batch_query_async(tdpt_batch *b, int64_t *dev_words)
+{
+    if (!b || !dev_words) return fail(TDPT_E_INVALID, "NULL argument");
+    if (b->stale)
+        return fail(TDPT_E_STATE, "a member was destroyed or joined another batch: set the members again");
+    if (b->members.empty()) return TDPT_OK;
+    HIP_TRY(tdpt::launch_batch_status((const tdpt::DevProblem *)b->ws, (int)b->members.size(),
+                                      (const int32_t *)(b->ws + batch_order_off(b->cap)), dev_words, b->stream),
+            "launch batch status");
+    return TDPT_OK;
+}
+
+int tdpt_batch_query(tdpt_batch *b, int64_t *words)
+{
+    if (!b || !words) return fail(TDPT_E_INVALID, "NULL argument");
+    if (b->members.empty() && !b->stale) return TDPT_OK;
+    int64_t *dev = (int64_t *)(b->ws + batch_status_off(b->cap));
+    int rc = tdpt_batch_query_async(b, dev);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(words, dev, b->members.size() * 32, hipMemcpyDeviceToHost, b->stream), "readback");
+    HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    return TDPT_OK;
 }
 
 int tdpt_batch_set_driver(tdpt_batch *b, int32_t driver)

@@ -55,18 +55,33 @@ class Request:
     status: str | None = None
 
 
-def _advance(req: Request, rounds: int, t0: float, t1: float, elapsed_base: float):
-    """Book a chunk of `rounds` rounds that ran from wall time t0 to t1."""
-    q = req.problem.query()
+def _book(req: Request, rounds_done: int, first_hit: int, best_f: int, t0: float, t1: float,
+          elapsed_base: float):
+    """Book a chunk of rounds that ran from wall time t0 to t1, given the
+    problem's status after it."""
     prev = req.rounds_done
-    req.rounds_done = q["rounds_done"]
-    req.best_f = q["best_f_q"]
-    if req.hit_time is None and q["first_hit_sweep"] >= 0:
+    req.rounds_done = int(rounds_done)
+    req.best_f = int(best_f)
+    if req.hit_time is None and first_hit >= 0:
         mcs = req.cfg.mcs_per_swap
-        hit_round = q["first_hit_sweep"] // mcs
+        hit_round = int(first_hit) // mcs
         frac = (hit_round - prev) / max(req.rounds_done - prev, 1)
-        req.hit_sweep = q["first_hit_sweep"]
+        req.hit_sweep = int(first_hit)
         req.hit_time = (t0 - elapsed_base) + frac * (t1 - t0) - req.arrival
+
+
+def _advance(req: Request, rounds: int, t0: float, t1: float, elapsed_base: float):
+    """Book a chunk of `rounds` rounds of one problem (its own status read)."""
+    q = req.problem.query()
+    _book(req, q["rounds_done"], q["first_hit_sweep"], q["best_f_q"], t0, t1, elapsed_base)
+
+
+def _advance_all(batch, reqs, t0: float, t1: float, elapsed_base: float):
+    """Book a chunk for every member of the batch from one status poll
+    (members in set_members order)."""
+    words = batch.query()
+    for r, w in zip(reqs, words):
+        _book(r, w[0], w[1], w[2], t0, t1, elapsed_base)
 
 
 def _done(req: Request) -> bool:
@@ -126,8 +141,7 @@ def run_batched(requests, chunk: int, device="cuda"):
         batch.run(n)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        for r in active:
-            _advance(r, n, t0, t1, base)
+        _advance_all(batch, active, t0, t1, base)
         still = []
         for r in active:
             if _done(r):
@@ -230,8 +244,7 @@ def serve(requests, chunk: int, budget_bytes: int, max_members: int = 4096, devi
         batch.run(n)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        for r in active:
-            _advance(r, n, t0, t1, base)
+        _advance_all(batch, active, t0, t1, base)
         still = []
         for r in active:
             if _done(r):

@@ -34,6 +34,7 @@ EXPORTED = [
     "tdpt_layout_get", "tdpt_problem_query_async", "tdpt_problem_read_energies_async",
     "tdpt_problem_read_states_async", "tdpt_problem_read_best_async", "tdpt_problem_read_best_logical",
     "tdpt_problem_read_histogram", "tdpt_problem_create_static", "tdpt_problem_set_stage_trace",
+    "tdpt_batch_query", "tdpt_batch_query_async",
 ]
 
 STATIC_WORKSPACE_BYTES = 64 << 20
@@ -112,6 +113,8 @@ def load_library():
         "tdpt_problem_read_histogram": [P, P, P],
         "tdpt_problem_create_static": [P, P, P, P],
         "tdpt_problem_set_stage_trace": [P, P, I32],
+        "tdpt_batch_query": [P, P],
+        "tdpt_batch_query_async": [P, P],
         "tdpt_instance_info_get": [P, P],
         "tdpt_workspace_bytes": [P, P, P],
         "tdpt_problem_create": [P, P, P, SZ, P, P],
@@ -460,6 +463,17 @@ class Batch:
 
     def run(self, n_rounds: int):
         _check(_lib.tdpt_batch_run(self._h, int(n_rounds)))
+
+    def query(self):
+        """Status of every member at once, in set_members order: int64
+        [count, 4] = rounds_done, first_hit_sweep, best_f_q, best_sweep."""
+        out = np.zeros((max(len(self.members), 1), 4), dtype=np.int64)
+        _check(_lib.tdpt_batch_query(self._h, _ptr(out)))
+        return out[:len(self.members)]
+
+    def query_async(self, words):
+        """Enqueue the same status words into a device int64 tensor [count, 4]."""
+        _check(_lib.tdpt_batch_query_async(self._h, _dptr(words)))
 
     def set_driver(self, driver: int):
         """-1: persistent driver when it fits (default); 0: per-round launches."""

@@ -237,3 +237,36 @@ def test_stage_trace_of_the_persistent_driver(T):
     assert (t[1:12, :, 0] >= t[:11, :, 3]).all()
     o = O.run(w.instance, w.beta, w.p_q, mcs_per_swap=5, n_rounds=30, seed=4, trace=True)
     assert_same(o, P, "with stage trace")
+
+
+def test_batch_poll_equals_member_queries(T):
+    """One batch-wide poll returns every member's rounds, first hit, best f
+    and best sweep in the order the members were given (the batch keeps them
+    sorted by layout internally), synchronously and into a device buffer."""
+    import torch
+    from synth.configs import batched_member
+    w = wishart_small()
+    f_gs = O.energy(w.instance, w.instance.physical_state(w.instance.planted))[0]
+    m = batched_member(100, 0.8, 5)
+    probs = [T.Problem(T.Instance.from_synth(m.instance), T.RunConfig(m.beta[:4], m.p_q[:4], mcs_per_swap=3,
+                                                                       seed=1)),
+             T.Problem(T.Instance.from_synth(w.instance), T.RunConfig(w.beta, w.p_q, mcs_per_swap=50, seed=5,
+                                                                       f_target=f_gs)),
+             T.Problem(T.Instance.from_synth(w.instance), T.RunConfig(w.beta, w.p_q, mcs_per_swap=50, seed=7,
+                                                                       f_target=f_gs))]
+    B = T.Batch(4)
+    B.set_members(probs)
+    B.run(200)
+    words = B.query()
+    dev = torch.zeros((3, 4), dtype=torch.int64, device="cuda")
+    B.query_async(dev)
+    torch.cuda.synchronize()
+    for row, drow, P in zip(words, dev.cpu().numpy(), probs):
+        q = P.query()
+        want = [q["rounds_done"], q["first_hit_sweep"], q["best_f_q"], q["best_sweep"]]
+        assert row.tolist() == want and drow.tolist() == want
+    assert words[1][1] > 0  # seed 5 reaches the planted ground state within 1e4 sweeps
+    B.set_members([probs[2], probs[0]])
+    B.run(2)
+    assert B.query()[:, 0].tolist() == [202, 202]
+    B.close()

@@ -71,6 +71,13 @@ class _World:
                     p.rounds += n
                 world.log.append((n, len(self.members)))
 
+            def query(self):
+                rows = []
+                for p in self.members:
+                    q = p.query()
+                    rows.append([q["rounds_done"], q["first_hit_sweep"], q["best_f_q"], -1])
+                return np.array(rows, dtype=np.int64).reshape(-1, 4)
+
             def close(self):
                 pass
 
