@@ -389,21 +389,30 @@ int tdpt_batch_run(tdpt_batch *batch, int64_t n_rounds);
  * form enqueues the same words into caller device memory on that stream. */
 int tdpt_batch_query(tdpt_batch *batch, int64_t *words);
 int tdpt_batch_query_async(tdpt_batch *batch, int64_t *dev_words);
-/* Autotune the threads per sweep workgroup of each layout group of the
- * current members (64 to 1024; 768 for bit-packed groups with a member of
- * fewer than 4 sweeps per round; no smaller than the members' per-phase
- * bounds allow), one group after another, timing
- * whole batch rounds; every member's state is restored afterwards.  The
- * choice holds until the next tdpt_batch_set_members. */
+/* Autotune the launch shape of each layout group of the current members,
+ * one group after another, timing whole batch rounds; every member's state
+ * is restored afterwards.  Candidates: one replica per workgroup of 64 to
+ * 1024 threads (768 for bit-packed groups with a member of fewer than 4
+ * sweeps per round; no smaller than the members' per-phase bounds allow),
+ * run by the persistent driver where it fits; and, for int8 groups whose
+ * largest colour class is small, several replicas per workgroup of 64, 128
+ * or 256 threads (a power-of-two share of lanes each, one to four passes
+ * over the class), run by per-round launches.  Without tuning, per-round
+ * launches already pack the replicas of int8 groups whose largest class
+ * takes under 64 lanes, one wave of 64 threads per workgroup.  The choice
+ * holds until the next tdpt_batch_set_members; a packed choice keeps the
+ * batch on per-round launches. */
 typedef struct tdpt_batch_tune_report {
     int32_t persistent;                /* 1 if the tuned batch runs the persistent driver */
     int32_t n_groups;                  /* layout groups (<= 32) */
     int32_t group_block[32];           /* chosen threads per workgroup */
     double group_ms_per_round[32];     /* batch round time with that choice */
-    int32_t n_trials;                  /* (group, block) pairs timed (<= 128) */
+    int32_t n_trials;                  /* (group, shape) pairs timed (<= 128) */
     int32_t trial_group[128];
     int32_t trial_block[128];
     double trial_ms_per_round[128];
+    int32_t group_slots[32];           /* chosen replicas per workgroup */
+    int32_t trial_slots[128];
 } tdpt_batch_tune_report;
 int tdpt_batch_autotune(tdpt_batch *batch, int32_t rounds_per_trial, tdpt_batch_tune_report *out);
 /* Driver of a batch.  By default (-1) tdpt_batch_run uses the persistent

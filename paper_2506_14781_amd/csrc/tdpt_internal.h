@@ -148,9 +148,12 @@ hipError_t launch_persistent(const DevProblem &p, int64_t n_rounds, hipStream_t 
 hipError_t launch_scratch_reset(const DevProblem &p, hipStream_t s);
 hipError_t launch_finalize(const DevProblem &p, int64_t n_rounds, hipStream_t s);
 // Batched rounds over a device table of problems sharing p's layout (p is
-// any member: it selects the kernel instance).
+// any member: it selects the kernel instance).  rpb slots per workgroup of
+// `block` threads, 2^lshift lanes each (rpb << lshift == block) when rpb > 1;
+// first_block then counts ceil(R / rpb) workgroups per member.
 hipError_t launch_batch_sweep(const DevProblem &p, const DevProblem *table, const int *first_block,
-                              int count, int blocks, int block, size_t max_stride, hipStream_t s);
+                              int count, int blocks, int block, size_t max_stride, int rpb, int lshift,
+                              hipStream_t s);
 hipError_t launch_batch_swap(const DevProblem *table, int count, hipStream_t s);
 // Batched persistent driver over one layout group of count members whose
 // block ranges (prefix sums in first_block) cover `blocks` workgroups; lds is

@@ -419,11 +419,9 @@ __device__ __forceinline__ void quad_fields(const DevProblem &P, const Rsrc &Rs,
 // energy changes stay below 2^22).
 template <int NARROW>
 __device__ __forceinline__ void quad_update(const DevProblem &P, lds8_t *s, int q, const int hp[4], const int cs[4],
-                                            uint32_t live_bytes, uint32_t t, const SlotParams &sp,
+                                            uint32_t live_bytes, const uint32_t u[4], const SlotParams &sp,
                                             int &dfa, int &dga)
 {
-    uint32_t u[4] = {(uint32_t)q, t, sp.pos, 0u};
-    philox10(u[0], u[1], u[2], u[3], P.key0, P.key1);
     lds32_t *wp = (lds32_t *)(s + q * 4);
     const uint32_t ow = *wp;
     int hh[4];
@@ -478,6 +476,41 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v)
 // at_end() runs on every thread after its last quad, before the closing
 // barrier (the reduction's, which also ends the last class); on return the
 // spins are final for the whole block.
+// The class phases of all sweeps of one round for the replica at s, walked
+// by `lanes` lanes of which this one is number `lane` (quads lane,
+// lane + lanes, .. of every class); adds the changes of f and g that this
+// lane made to df and dg.  Every thread of the block calls it (the phases
+// end in block barriers, the last one excepted).
+template <int NARROW, int WD>
+__device__ __forceinline__ void sweep_phases(const DevProblem &P, const Rsrc &Rs, lds8_t *s, const SlotParams &sp,
+                                             int64_t n_round, int lane, int lanes, int64_t &df, int64_t &dg)
+{
+    for (int k = 0; k < P.mcs; ++k) {
+        const uint32_t t = (uint32_t)((n_round - 1) * P.mcs + k);
+        for (int c = 0; c < P.n_colors; ++c) {
+            const int q0 = P.cls_start[c] >> 2, q1 = P.cls_start[c + 1] >> 2;
+            const int live_end = P.cls_live[c];
+            int dfa = 0, dga = 0;
+            for (int q = q0 + lane; q < q1; q += lanes) {
+                QuadS<NARROW, WD> Q;
+                load_quad<NARROW, WD>(P, Rs, q, Q);
+                // the quad's random words do not depend on the spins: they are
+                // computed while its structure loads are in flight
+                uint32_t u[4] = {(uint32_t)q, t, sp.pos, 0u};
+                philox10(u[0], u[1], u[2], u[3], P.key0, P.key1);
+                int hp[4], cs[4];
+                quad_fields<NARROW, WD>(P, Rs, s, Q, hp, cs);
+                const int rem = live_end - q * 4;
+                const uint32_t live_bytes = rem >= 4 ? 0xffffffffu : rem <= 0 ? 0u : ((1u << (8 * rem)) - 1u);
+                quad_update<NARROW>(P, s, q, hp, cs, live_bytes, u, sp, dfa, dga);
+            }
+            df += dfa;
+            dg += 2 * (int64_t)dga;
+            if (k + 1 < P.mcs || c + 1 < P.n_colors) __syncthreads();
+        }
+    }
+}
+
 template <int NARROW, int WD, typename AtEnd>
 __device__ __forceinline__ void sweep_round(const DevProblem &P, const Rsrc &Rs, lds8_t *s,
                                             const SlotParams &sp, int64_t n_round, int64_t *red,
@@ -485,26 +518,7 @@ __device__ __forceinline__ void sweep_round(const DevProblem &P, const Rsrc &Rs,
 {
     const int tid = threadIdx.x, nthr = blockDim.x;
     int64_t df = 0, dg = 0;
-    for (int k = 0; k < P.mcs; ++k) {
-        const uint32_t t = (uint32_t)((n_round - 1) * P.mcs + k);
-        for (int c = 0; c < P.n_colors; ++c) {
-            const int q0 = P.cls_start[c] >> 2, q1 = P.cls_start[c + 1] >> 2;
-            const int live_end = P.cls_live[c];
-            int dfa = 0, dga = 0;
-            for (int q = q0 + tid; q < q1; q += nthr) {
-                QuadS<NARROW, WD> Q;
-                load_quad<NARROW, WD>(P, Rs, q, Q);
-                int hp[4], cs[4];
-                quad_fields<NARROW, WD>(P, Rs, s, Q, hp, cs);
-                const int rem = live_end - q * 4;
-                const uint32_t live_bytes = rem >= 4 ? 0xffffffffu : rem <= 0 ? 0u : ((1u << (8 * rem)) - 1u);
-                quad_update<NARROW>(P, s, q, hp, cs, live_bytes, t, sp, dfa, dga);
-            }
-            df += dfa;
-            dg += 2 * (int64_t)dga;
-            if (k + 1 < P.mcs || c + 1 < P.n_colors) __syncthreads();
-        }
-    }
+    sweep_phases<NARROW, WD>(P, Rs, s, sp, n_round, tid, nthr, df, dg);
     at_end();
     const int64_t a = wave_sum64(df), b = wave_sum64(dg);
     const int wave = tid >> 6, nw = nthr >> 6;
@@ -577,6 +591,74 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch_sweep(const DevProblem *__r
         else hi = mid - 1;
     }
     round_sweep_body<NARROW, WD>(table[lo], b - first_block[lo], lds);
+}
+
+// One round of `rpb` consecutive slots of one problem in one workgroup: the
+// block's threads split into rpb groups of 2^lshift lanes (lshift <= 6 keeps
+// a group inside one wave; larger groups span whole waves), group k sweeping
+// slot slot0 + k, whose spins sit at LDS offset k * stride.  Replicas of a
+// few dozen quads per class then share a wave instead of each leaving most
+// of one idle.  Slots past the problem's last are skipped; their groups
+// still take every barrier.  The same updates, in the same order per slot,
+// as round_sweep_body.
+template <int NARROW, int WD>
+__device__ __forceinline__ void multi_round_body(const DevProblem &P, int slot0, int rpb, int lshift, int8_t *lds)
+{
+    if (!replica_at_zero(lds)) {
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&P.hdr[kHdrError], kErrLdsBase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    const int tid = threadIdx.x;
+    const int nsub = min(rpb, P.R - slot0);
+    const int sub = tid >> lshift, lane = tid & ((1 << lshift) - 1);
+    const bool live = sub < nsub;
+    int64_t *red = lds_scratch(lds, rpb * P.stride);  // [2k] f, [2k + 1] g of group k
+    copy_bytes16(lds, P.states + (size_t)slot0 * P.stride, nsub * P.stride);
+    for (int i = tid; i < 2 * rpb; i += blockDim.x) red[i] = 0;
+    const int slot = slot0 + min(sub, nsub - 1);
+    const int64_t n_round = P.hdr[kHdrRounds] + 1;
+    const SlotParams sp = slot_params(P, P.slot_pos[slot], P.beta, P.p_q);
+    const Rsrc Rs = make_rsrc(P);
+    __syncthreads();
+    int64_t df = 0, dg = 0;
+    // a skipped group starts past every class, so it takes the barriers only
+    sweep_phases<NARROW, WD>(P, Rs, replica_lds() + sub * P.stride, sp, n_round, live ? lane : (1 << 30),
+                             1 << lshift, df, dg);
+    // sum over each group: within its wave segment, then across its waves
+    const int seg = lshift < 6 ? (1 << lshift) : 64;
+    for (int off = seg >> 1; off > 0; off >>= 1) {
+        df += __shfl_xor(df, off, 64);
+        dg += __shfl_xor(dg, off, 64);
+    }
+    if (live && (tid & (seg - 1)) == 0) {
+        atomicAdd(reinterpret_cast<unsigned long long *>(&red[2 * sub]), (unsigned long long)df);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&red[2 * sub + 1]), (unsigned long long)dg);
+    }
+    __syncthreads();
+    if (live && lane == 0) {
+        P.f[slot] += red[2 * sub];
+        P.g[slot] += red[2 * sub + 1];
+    }
+    copy_bytes16(P.states + (size_t)slot0 * P.stride, lds, nsub * P.stride);
+}
+
+// Batched round with rpb slots per workgroup: first_block is the prefix sum
+// of the members' workgroup counts, ceil(R / rpb) each.
+template <int NARROW, int WD>
+__global__ __launch_bounds__(kMaxBlock) void k_batch_sweep_multi(const DevProblem *__restrict__ table,
+                                                               const int *__restrict__ first_block, int count,
+                                                               int rpb, int lshift)
+{
+    extern __shared__ __align__(16) int8_t lds[];
+    const int b = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first_block[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    multi_round_body<NARROW, WD>(table[lo], (b - first_block[lo]) * rpb, rpb, lshift, lds);
 }
 
 __device__ __forceinline__ bool metropolis(double x, double u)
@@ -1643,9 +1725,18 @@ hipError_t launch_swap(const DevProblem &p, hipStream_t s)
 
 template <int NARROW, int WD>
 static hipError_t batch_sweep_t(const DevProblem &p, const DevProblem *table, const int *first_block,
-                                int count, int blocks, int block, size_t max_stride, hipStream_t s)
+                                int count, int blocks, int block, size_t max_stride, int rpb, int lshift,
+                                hipStream_t s)
 {
     (void)p;
+    if (rpb > 1) {
+        const size_t lds = (size_t)rpb * max_stride + 16 * (size_t)rpb + 16;
+        hipError_t e = allow_lds(k_batch_sweep_multi<NARROW, WD>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_batch_sweep_multi<NARROW, WD>), dim3(blocks), dim3(block), lds, s, table,
+                           first_block, count, rpb, lshift);
+        return hipGetLastError();
+    }
     const size_t lds = max_stride + 8 * (2 + 2 * (kMaxBlock / 64) + 3) + 16;
     hipError_t e = allow_lds(k_batch_sweep<NARROW, WD>, lds);
     if (e != hipSuccess) return e;
@@ -1655,9 +1746,11 @@ static hipError_t batch_sweep_t(const DevProblem &p, const DevProblem *table, co
 }
 
 hipError_t launch_batch_sweep(const DevProblem &p, const DevProblem *table, const int *first_block,
-                              int count, int blocks, int block, size_t max_stride, hipStream_t s)
+                              int count, int blocks, int block, size_t max_stride, int rpb, int lshift,
+                              hipStream_t s)
 {
-    TDPT_DISPATCH(batch_sweep_t, p, table, first_block, count, blocks, block, max_stride, s)
+    if (rpb < 1 || (rpb > 1 && (lshift < 0 || (rpb << lshift) != block))) return hipErrorInvalidValue;
+    TDPT_DISPATCH(batch_sweep_t, p, table, first_block, count, blocks, block, max_stride, rpb, lshift, s)
 }
 
 static size_t bits_lds(int n_words)

@@ -109,6 +109,7 @@ struct tdpt_problem {
     bool persistent = false;
     bool persistent_ok = false;  // the persistent driver may be used (layout, key range)
     int32_t min_block = 64;      // smallest sweep workgroup the per-phase bounds allow
+    int32_t min_lanes = 1;       // fewest lanes per replica the per-phase bounds allow
     int32_t max_class_quads = 0;
     int64_t rounds_host = 0;  // rounds done, as far as the host has enqueued them
     // rounds_host when the partner mailboxes were last valid (after a
@@ -781,6 +782,7 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     p->mcs = cfg->mcs_per_swap;
     p->rank = in->rank;
     p->min_block = min_block;
+    p->min_lanes = (int32_t)std::max<int64_t>(1, min_block_q);
     p->max_class_quads = in->max_class_quads;
     p->ws = (uint8_t *)dev_ws;
     p->ws_bytes = ws_bytes;
@@ -1529,6 +1531,13 @@ struct tdpt_batch {
         int min_block;  // smallest the members' per-phase bounds allow
         size_t plds;    // LDS of a persistent workgroup (largest member)
         int min_mcs;    // fewest sweeps per round among the members
+        // per-round driver, int8 layouts: rpb > 1 packs rpb slots into one
+        // workgroup of rpb << lshift threads (block then applies to the
+        // persistent driver only)
+        int rpb = 1, lshift = 0;
+        int replicas = 0;   // slots of all members (workgroups of the persistent driver)
+        int max_quads = 0;  // largest colour class of any member, in quads
+        int min_lanes = 1;  // fewest lanes per slot the members' per-phase bounds allow
     };
     std::vector<Group> groups;
     hipEvent_t done = nullptr;
@@ -1551,6 +1560,12 @@ struct tdpt_batch {
     // a member was destroyed or moved to another batch: the device table
     // names it, so runs wait for tdpt_batch_set_members
     bool stale = false;
+    // the autotuner chose packed slots for some group: per-round launches
+    // until the next tdpt_batch_set_members
+    bool tuned_per_round = false;
+    // workgroup prefix sums as last uploaded (they depend on the driver and
+    // on the groups' slots per workgroup)
+    std::vector<int32_t> prefix_host;
     void drop_graph()
     {
         if (graph) (void)hipGraphExecDestroy(graph);
@@ -1604,23 +1619,109 @@ static void leave_batch(tdpt_problem *p)
 }
 
 
+// Workgroup prefix sums of every group for the current driver: per member
+// its first workgroup within the group (bit-packed: 4 slots per workgroup;
+// int8: one slot each, or rpb under packed per-round launches).
+static std::vector<int32_t> batch_prefix(tdpt_batch *b)
+{
+    std::vector<int32_t> prefix;
+    for (auto &g : b->groups) {
+        g.prefix_off = (int)prefix.size();
+        const int rpb = b->persistent ? 1 : g.rpb;
+        int blocks = 0;
+        for (int k = g.first_member; k < g.first_member + g.count; ++k) {
+            const tdpt_problem *p = b->members[k];
+            prefix.push_back(blocks);
+            blocks += p->dp.bits ? (p->R + tdpt::kBitSlots - 1) / tdpt::kBitSlots : (p->R + rpb - 1) / rpb;
+        }
+        g.blocks = blocks;
+    }
+    return prefix;
+}
+
+// Recompute the prefix sums and upload them if they changed (after the
+// batch's work in flight); a captured graph names the old launch shapes.
+static int batch_sync_prefix(tdpt_batch *b)
+{
+    std::vector<int32_t> prefix = batch_prefix(b);
+    if (prefix == b->prefix_host || prefix.empty()) {
+        b->prefix_host.swap(prefix);
+        return TDPT_OK;
+    }
+    b->drop_graph();
+    b->prefix_host.clear();
+    HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    HIP_TRY(hipMemcpyAsync(b->ws + batch_table_bytes(b->cap), prefix.data(), prefix.size() * 4,
+                           hipMemcpyHostToDevice, b->stream),
+            "upload batch prefix");
+    HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    b->prefix_host.swap(prefix);
+    return TDPT_OK;
+}
+
 // Whether the persistent driver runs this batch: every member allows it, no
-// group is bit-packed, and each group's workgroups fit the GPU at once.
+// group is bit-packed, the autotuner did not choose packed per-round
+// launches, and each group's workgroups fit the GPU at once.  Then the
+// prefix sums follow the choice.
 static int batch_decide_mode(tdpt_batch *b)
 {
     b->persistent = false;
-    if (b->members.empty() || b->driver_mode == 0) return TDPT_OK;
-    for (auto *p : b->members)
-        if (!p->persistent_ok) return TDPT_OK;
-    for (auto &g : b->groups) {
+    bool fits = !b->members.empty() && b->driver_mode != 0 && !b->tuned_per_round;
+    for (auto *p : b->members) fits = fits && p->persistent_ok;
+    for (size_t gi = 0; fits && gi < b->groups.size(); ++gi) {
+        const auto &g = b->groups[gi];
         const tdpt::DevProblem &d0 = b->members[g.first_member]->dp;
-        if (d0.bits || g.block > tdpt::kMaxBlock / 2 || g.block < g.min_block) return TDPT_OK;
+        if (d0.bits || g.block > tdpt::kMaxBlock / 2 || g.block < g.min_block) {
+            fits = false;
+            break;
+        }
         int max_blocks = 0;
         HIP_TRY(tdpt::batch_persistent_max_blocks(d0, g.block, g.plds, &max_blocks), "occupancy query");
-        if (max_blocks < g.blocks) return TDPT_OK;
+        fits = max_blocks >= g.replicas;
     }
-    b->persistent = true;
-    return TDPT_OK;
+    b->persistent = fits;
+    return batch_sync_prefix(b);
+}
+
+// Default slots per workgroup of an int8 group under per-round launches:
+// when its largest colour class takes under 64 lanes, one wave of 64 holds
+// 64 / L slots, L the power of two covering that class (and the members'
+// per-phase bounds); larger replicas keep one slot per workgroup.
+// Whether rpb slots of the group's largest replica fit the LDS a workgroup
+// takes without giving up occupancy (64 KiB).
+static bool pack_fits(const tdpt_batch::Group &g, int rpb)
+{
+    return (size_t)rpb * (g.max_stride + 16) + 16 <= 65536;
+}
+
+static void batch_default_pack(tdpt_batch::Group &g, bool bits)
+{
+    g.rpb = 1;
+    g.lshift = 0;
+    if (bits) return;
+    int lshift = 0;
+    while ((1 << lshift) < std::max(g.max_quads, g.min_lanes)) ++lshift;
+    if (const char *e = getenv("TDPT_BATCH_LANES")) {
+        // test hook: lanes per slot (a power of two); the workgroup then holds
+        // max(block, lanes) / lanes slots, block from TDPT_BATCH_BLOCK or 64
+        const int v = atoi(e);
+        int ls = 0;
+        while ((1 << ls) < v) ++ls;
+        if (v >= 1 && (1 << ls) == v && v >= g.min_lanes && v <= tdpt::kMaxBlock / 2) {
+            const char *eb = getenv("TDPT_BATCH_BLOCK");
+            const int blk = std::max(eb ? atoi(eb) : 64, v);
+            if (blk % v == 0 && blk / v >= 2 && blk <= tdpt::kMaxBlock && pack_fits(g, blk / v)) {
+                g.rpb = blk / v;
+                g.lshift = ls;
+            }
+        }
+        return;
+    }
+    if (lshift >= 6) return;
+    lshift = std::max(lshift, 2);
+    if (!pack_fits(g, 64 >> lshift)) return;
+    g.lshift = lshift;
+    g.rpb = 64 >> lshift;
 }
 
 // n_rounds rounds of every member through the persistent driver.
@@ -1678,7 +1779,8 @@ static int enqueue_batch_round(tdpt_batch *b, hipStream_t s)
         hipError_t e = d0.bits ? tdpt::launch_batch_sweep_bits(d0, table + g.first_member, prefix + g.prefix_off,
                                                                g.count, g.blocks, g.block, g.max_words, g.min_mcs, gs)
                                : tdpt::launch_batch_sweep(d0, table + g.first_member, prefix + g.prefix_off,
-                                                          g.count, g.blocks, g.block, g.max_stride, gs);
+                                                          g.count, g.blocks, g.rpb > 1 ? g.rpb << g.lshift : g.block,
+                                                          g.max_stride, g.rpb, g.lshift, gs);
         if (e != hipSuccess) return hip_fail(e, "launch batch sweep");
     }
     for (int k = 0; k < n_aux; ++k) {
@@ -1790,17 +1892,17 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
     empty_batch();
     std::vector<tdpt_batch::Group> groups;
     std::vector<tdpt::DevProblem> table(m.size());
-    std::vector<int32_t> prefix;
     for (size_t i = 0; i < m.size(); ++i) {
         table[i] = m[i]->dp;
         if (groups.empty() || !(group_key(m[i]->dp) == group_key(m[i - 1]->dp))) {
-            tdpt_batch::Group g{(int)i, 0, 0, (int)prefix.size(), 0, 0, 0, 64, 0, INT_MAX};
+            tdpt_batch::Group g{(int)i, 0, 0, 0, 0, 0, 0, 64, 0, INT_MAX};
             groups.push_back(g);
         }
         auto &g = groups.back();
         g.min_block = std::max(g.min_block, m[i]->min_block);
-        prefix.push_back(g.blocks);
-        g.blocks += m[i]->dp.bits ? (m[i]->R + tdpt::kBitSlots - 1) / tdpt::kBitSlots : m[i]->R;
+        g.min_lanes = std::max(g.min_lanes, m[i]->min_lanes);
+        g.max_quads = std::max(g.max_quads, m[i]->max_class_quads);
+        g.replicas += m[i]->R;
         g.count += 1;
         g.max_stride = std::max(g.max_stride, (size_t)m[i]->dp.stride);
         g.max_words = std::max(g.max_words, m[i]->dp.n_words);
@@ -1827,12 +1929,15 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
             for (int k = g.first_member; k < g.first_member + g.count; ++k) def = std::max(def, m[k]->dp.block);
         }
         g.block = std::min(std::max(def, g.min_block), cap);
+        batch_default_pack(g, m[g.first_member]->dp.bits != 0);
     }
     // members that move here from another batch leave it first
     for (auto *p : m)
         if (p->batch && p->batch != b) leave_batch(p);
     b->members = m;
     b->groups = groups;
+    b->tuned_per_round = false;
+    b->prefix_host.clear();
     // the persistent driver when every group fits at once (with the members'
     // own workgroup sizes), else per-round launches with the batch default
     {
@@ -1845,14 +1950,15 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
             g.block = std::min(want, tdpt::kMaxBlock / 2);
         }
         int rc = batch_decide_mode(b);
+        if (rc == TDPT_OK && !b->persistent)
+            for (size_t gi = 0; gi < b->groups.size(); ++gi) b->groups[gi].block = per_round_blocks[gi];
         if (rc) {
             b->members.clear();
             b->groups.clear();
             b->persistent = false;
+            b->prefix_host.clear();
             return rc;
         }
-        if (!b->persistent)
-            for (size_t gi = 0; gi < b->groups.size(); ++gi) b->groups[gi].block = per_round_blocks[gi];
     }
     if (!m.empty()) {
         // the caller's index of every table entry (for status reads in the caller's order)
@@ -1862,9 +1968,6 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
         hipError_t e = hipMemcpyAsync(b->ws, table.data(), table.size() * sizeof(tdpt::DevProblem),
                                       hipMemcpyHostToDevice, b->stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(b->ws + batch_table_bytes(b->cap), prefix.data(), prefix.size() * 4,
-                               hipMemcpyHostToDevice, b->stream);
-        if (e == hipSuccess)
             e = hipMemcpyAsync(b->ws + batch_order_off(b->cap), order.data(), order.size() * 4,
                                hipMemcpyHostToDevice, b->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -1872,6 +1975,7 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
             b->members.clear();
             b->groups.clear();
             b->persistent = false;
+            b->prefix_host.clear();
             return hip_fail(e, "upload batch table");
         }
     }
@@ -1947,14 +2051,40 @@ int tdpt_batch_autotune(tdpt_batch *b, int32_t rounds_per_trial, tdpt_batch_tune
     b->graph_rounds = 0;  // trials launch directly
     b->drop_graph();
     out->n_groups = (int32_t)b->groups.size();
+    // candidates: one slot per workgroup of `block` threads (run by the
+    // persistent driver when it fits), or, for int8 groups, rpb slots of
+    // 2^lshift lanes in per-round workgroups of 64, 128 or 256 threads, from
+    // 4 passes over the largest class down to one
+    struct Cand {
+        int block, rpb, lshift;
+    };
+    std::vector<bool> packed(b->groups.size(), false);
+    auto any_packed = [&]() { return std::find(packed.begin(), packed.end(), true) != packed.end(); };
     for (size_t gi = 0; gi < b->groups.size() && rc == TDPT_OK; ++gi) {
         auto &g = b->groups[gi];
-        const int cap = b->members[g.first_member]->dp.bits ? tdpt::bits_block_cap(g.min_mcs) : tdpt::kMaxBlock;
+        const bool bits = b->members[g.first_member]->dp.bits != 0;
+        const int cap = bits ? tdpt::bits_block_cap(g.min_mcs) : tdpt::kMaxBlock;
+        std::vector<Cand> cands;
+        for (int sz : sizes)
+            if (sz >= g.min_block && sz <= cap) cands.push_back({sz, 1, 0});
+        if (!bits)
+            for (int ls = 0; ls <= 5; ++ls) {
+                const int lanes = 1 << ls;
+                if (lanes < g.min_lanes || 4 * lanes < g.max_quads || (ls > 0 && lanes / 2 >= g.max_quads)) continue;
+                for (int blk : {64, 128, 256})
+                    if (pack_fits(g, blk >> ls)) cands.push_back({blk, blk >> ls, ls});
+            }
         double best = 1e300;
-        int best_block = g.block;
-        for (int sz : sizes) {
-            if (sz < g.min_block || sz > cap || out->n_trials >= 128) continue;
-            g.block = sz;
+        Cand best_c{g.block, g.rpb, g.lshift};
+        bool best_packed = packed[gi];
+        const int keep_block = g.block;
+        for (const Cand &c : cands) {
+            if (out->n_trials >= 128) break;
+            g.block = c.rpb > 1 ? keep_block : c.block;
+            g.rpb = c.rpb;
+            g.lshift = c.lshift;
+            packed[gi] = c.rpb > 1;
+            b->tuned_per_round = any_packed();
             rc = batch_decide_mode(b);
             if (rc) break;
             rc = tdpt_batch_run(b, 1);  // warm-up
@@ -1965,18 +2095,28 @@ int tdpt_batch_autotune(tdpt_batch *b, int32_t rounds_per_trial, tdpt_batch_tune
             const double per = ms / rounds_per_trial;
             const int t = out->n_trials++;
             out->trial_group[t] = (int32_t)gi;
-            out->trial_block[t] = sz;
+            out->trial_block[t] = c.block;
+            out->trial_slots[t] = c.rpb;
             out->trial_ms_per_round[t] = per;
             if (per < best) {
                 best = per;
-                best_block = sz;
+                best_c = c;
+                best_packed = c.rpb > 1;
             }
         }
-        g.block = best_block;
-        out->group_block[gi] = best_block;
+        g.block = best_packed ? keep_block : best_c.block;
+        g.rpb = best_c.rpb;
+        g.lshift = best_c.lshift;
+        packed[gi] = best_packed;
+        out->group_block[gi] = best_c.block;
+        out->group_slots[gi] = best_c.rpb;
         out->group_ms_per_round[gi] = best;
     }
-    if (rc == TDPT_OK) rc = batch_decide_mode(b);
+    b->tuned_per_round = any_packed();
+    {
+        const int rc1 = batch_decide_mode(b);
+        if (rc == TDPT_OK) rc = rc1;
+    }
     out->persistent = b->persistent ? 1 : 0;
     b->graph_rounds = graph_rounds;
     const int rc2 = restore();

@@ -80,7 +80,8 @@ class _BatchTuneReport(ctypes.Structure):
     _fields_ = [("persistent", ctypes.c_int32), ("n_groups", ctypes.c_int32), ("group_block", ctypes.c_int32 * 32),
                 ("group_ms_per_round", ctypes.c_double * 32), ("n_trials", ctypes.c_int32),
                 ("trial_group", ctypes.c_int32 * 128), ("trial_block", ctypes.c_int32 * 128),
-                ("trial_ms_per_round", ctypes.c_double * 128)]
+                ("trial_ms_per_round", ctypes.c_double * 128), ("group_slots", ctypes.c_int32 * 32),
+                ("trial_slots", ctypes.c_int32 * 128)]
 
 
 class _Status(ctypes.Structure):
@@ -490,14 +491,17 @@ class Batch:
         _check(_lib.tdpt_batch_set_graph(self._h, int(rounds_per_graph)))
 
     def autotune(self, rounds_per_trial: int = 3) -> dict:
-        """Pick each layout group's workgroup size by timing batch rounds;
-        every member's state is left as it was."""
+        """Pick each layout group's workgroup size and replicas per workgroup
+        by timing batch rounds; every member's state is left as it was.
+        Trials are (group, threads, replicas per workgroup, ms per round)."""
         r = _BatchTuneReport()
         _check(_lib.tdpt_batch_autotune(self._h, int(rounds_per_trial), ctypes.byref(r)))
         g, k = r.n_groups, r.n_trials
         return {"persistent": r.persistent, "group_block": list(r.group_block[:g]),
+                "group_slots": list(r.group_slots[:g]),
                 "group_ms_per_round": list(r.group_ms_per_round[:g]),
-                "trials": [(r.trial_group[i], r.trial_block[i], r.trial_ms_per_round[i]) for i in range(k)]}
+                "trials": [(r.trial_group[i], r.trial_block[i], r.trial_slots[i], r.trial_ms_per_round[i])
+                           for i in range(k)]}
 
     def close(self):
         h = getattr(self, "_h", None)

@@ -215,6 +215,60 @@ def test_graph_replays_equal_direct_launches(T):
     assert np.array_equal(f, o["f"]) and np.array_equal(g, o["g"])
 
 
+@pytest.mark.parametrize("lanes,block", [(None, None), (1, 64), (4, 64), (16, 128), (32, 64), (128, 256)])
+def test_packed_batch_equals_alone(T, monkeypatch, lanes, block):
+    """Per-round launches that hold several replicas per workgroup -- the
+    default for replicas whose largest colour class takes under 64 lanes, and
+    forced shapes: one lane per replica, several lanes in a wave, replicas
+    spanning two waves -- give every member (three structure layouts) its
+    results alone, across membership changes, a switch to the persistent
+    driver and back, and graph replays; one member against the oracle."""
+    if lanes is not None:
+        monkeypatch.setenv("TDPT_BATCH_LANES", str(lanes))
+        monkeypatch.setenv("TDPT_BATCH_BLOCK", str(block))
+    specs = _members()
+    from synth.constrained import planted_coloring
+    specs.append(("coloring", planted_coloring(60, 3, degree=4, seed=2).instance, np.geomspace(0.3, 3, 4),
+                  np.array([0, 4096], np.int32), 2, 4))
+    rounds = 26
+    alone, probs = [], []
+    for name, inst, beta, p_q, mcs, seed in specs:
+        cfg = T.RunConfig(beta, p_q, mcs_per_swap=mcs, seed=seed, trace_cap=rounds)
+        P = T.Problem(T.Instance.from_synth(inst), cfg)
+        P.run(rounds)
+        alone.append(_outputs(P))
+        probs.append(T.Problem(T.Instance.from_synth(inst), cfg))
+    _say(f"[batch] packed lanes={lanes} block={block}")
+    B = T.Batch(8)
+    B.set_members(probs)
+    B.set_driver(0)
+    B.run(7)
+    B.set_members(probs[1:])  # the N=12 member sits out
+    B.set_driver(0)
+    B.run(3)
+    B.set_members(probs)
+    B.set_driver(0)
+    B.set_graph(3)
+    B.run(7)  # two replays, one direct round
+    B.set_graph(0)
+    B.set_members(probs[:1])
+    B.set_driver(0)
+    B.run(3)
+    B.set_members(probs)
+    B.set_driver(-1)
+    B.run(2)
+    B.set_driver(0)
+    B.run(7)
+    for (name, *_), a, P in zip(specs, alone, probs):
+        _say(f"[batch] packed compare {name}")
+        _same(a, _outputs(P))
+    name, inst, beta, p_q, mcs, seed = specs[0]
+    o = O.run(inst, beta, p_q, mcs_per_swap=mcs, n_rounds=rounds, seed=seed, trace=True)
+    assert np.array_equal(probs[0].states(), o["states"])
+    f, g = probs[0].energies()
+    assert np.array_equal(f, o["f"]) and np.array_equal(g, o["g"])
+
+
 def test_persistent_batch_driver(T):
     """Small problems that fit the GPU together run as one cooperative launch
     per layout group: equal to each problem alone (and to the oracle), also
