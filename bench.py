@@ -656,7 +656,7 @@ def main():
         rep = prob.autotune(args.autotune)
         tune = {"driver": rep["driver"], "block": rep["block"], "ms_per_round": round(rep["ms_per_round"], 5),
                 "trials": len(rep["trials"]), "rounds_per_trial": args.autotune,
-                "trial_ms_per_round": [[d, b, round(ms, 5)] for d, b, ms in rep["trials"]],
+                "trial_ms_per_round": [[d, b, k, round(ms, 5)] for d, b, k, ms in rep["trials"]],
                 "seconds": round(time.perf_counter() - t0, 3)}
         print(f"[bench] autotune: driver {tune['driver']} block {tune['block']} "
               f"({tune['ms_per_round']:.4f} ms/round) from {tune['trials']} trials",

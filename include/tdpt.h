@@ -122,6 +122,7 @@ typedef struct tdpt_status {
     int64_t best_sweep;      /* sweep count at which best_f_q was recorded, -1 if none */
     int32_t driver;          /* 1: one cooperative launch runs many rounds with every
                                 replica resident in LDS; 0: one launch pair per round */
+    int32_t slots;           /* per-round launches: replicas per sweep workgroup */
 } tdpt_status;
 
 /* ---------------------------------------------------------------- instance */
@@ -243,7 +244,18 @@ int tdpt_problem_create_static(const tdpt_instance *inst, const tdpt_run_cfg *cf
  * every replica, f/g of the final states, one swap step by Eq. 2 or Eq. 3,
  * bottom-right tracking).  Resumable: calling it twice with a and b rounds
  * equals one call with a + b.  TDPT_E_BUSY if the problem's batch has a run
- * in flight; TDPT_E_RANGE past 2^32 sweeps. */
+ * in flight; TDPT_E_RANGE past 2^32 sweeps.
+ * Driver (tdpt_status.driver; results never depend on it): the persistent
+ * one -- one cooperative launch runs all n_rounds, replicas resident in LDS
+ * and exchanging through mailboxes -- when every replica's workgroup fits
+ * the GPU at once, except for int8 replicas whose largest colour class takes
+ * under 64 lanes, whose structure (packed copy-edge layout, at most 8
+ * problem neighbours) fits an LDS copy and whose rounds hold 16 sweeps or
+ * more: those run per-round launches with several replicas per wave
+ * (tdpt_status.slots) reading the structure from LDS.  Otherwise one sweep
+ * launch and one swap launch per round.  The environment variable
+ * TDPT_PERSISTENT=0 at creation forbids the persistent driver, =1 prefers it
+ * wherever it fits; tdpt_problem_autotune may change the choice. */
 int tdpt_problem_run(tdpt_problem *prob, int64_t n_rounds);
 
 /* Read calls wait for the problem's stream (and so for any batch run that
@@ -326,14 +338,16 @@ int tdpt_problem_set_stage_trace(tdpt_problem *prob, uint64_t *dev_buf, int32_t 
 
 /* Launch-shape autotuner (not a step of the paper: launch shapes never
  * change results).  Times each admissible (driver, threads per sweep
- * workgroup) pair on the problem itself -- one warm-up round, then
- * rounds_per_trial rounds between HIP events on the problem's stream -- and
- * keeps the fastest for later runs.  Candidates: the per-round driver at 64
- * to 1024 threads (768 for bit-packed replicas with fewer than 4 sweeps per
- * round, whose sweeps follow f and g per update) and, where every replica's
- * workgroup can be resident at once, the persistent driver at 64 to 512,
- * each no larger than the largest colour class needs and no smaller than the
- * per-phase 2^31 bounds allow.  The problem's state is saved before and
+ * workgroup, replicas per workgroup) on the problem itself -- one warm-up
+ * round, then rounds_per_trial rounds between HIP events on the problem's
+ * stream -- and keeps the fastest for later runs.  Candidates: the per-round
+ * driver at 64 to 1024 threads (768 for bit-packed replicas with fewer than
+ * 4 sweeps per round, whose sweeps follow f and g per update), for int8
+ * replicas of a small largest colour class also several replicas per
+ * workgroup of 64, 128 or 256 threads (one to four passes over the class),
+ * and, where every replica's workgroup can be resident at once, the
+ * persistent driver at 64 to 512, each no larger than the largest colour
+ * class needs and no smaller than the per-phase 2^31 bounds allow.  The problem's state is saved before and
  * restored after (the trial rounds leave no trace); since random numbers do
  * not depend on launch shape, results after tuning equal those without.
  * Blocks the calling thread until the trials finish. */
@@ -345,6 +359,8 @@ typedef struct tdpt_tune_report {
     int32_t trial_driver[32];
     int32_t trial_block[32];
     double trial_ms_per_round[32];
+    int32_t slots;               /* chosen replicas per workgroup (per-round driver) */
+    int32_t trial_slots[32];
 } tdpt_tune_report;
 int tdpt_problem_autotune(tdpt_problem *prob, int32_t rounds_per_trial, tdpt_tune_report *out);
 
@@ -420,8 +436,10 @@ int tdpt_batch_autotune(tdpt_batch *batch, int32_t rounds_per_trial, tdpt_batch_
  * rounds, every member's replicas resident at once and exchanging through
  * their own mailboxes -- whenever every member allows it (int8 layout,
  * persistent driver not switched off) and each group's workgroups fit the
- * GPU together; otherwise one sweep launch per group and one swap launch per
- * round.  0 forces the per-round launches.  Results are the same either
+ * GPU together, unless every group packs several replicas per workgroup
+ * with its structure in LDS and every member's rounds hold 16 sweeps or
+ * more (as for one such problem, see tdpt_problem_run); otherwise one sweep
+ * launch per group and one swap launch per round.  0 forces the per-round launches.  Results are the same either
  * way.  tdpt_batch_query_driver reports the current choice (1 persistent). */
 int tdpt_batch_set_driver(tdpt_batch *batch, int32_t driver);
 int tdpt_batch_query_driver(tdpt_batch *batch, int32_t *driver);

@@ -10,6 +10,7 @@ namespace tdpt {
 constexpr int kMaxColors = 32;
 constexpr int kMaxBlock = 1024;   // threads per sweep workgroup, at most
 constexpr int kSmallBlock = 256;  // threads of the swap / energy kernels
+constexpr int kMultiBlock = 256;  // threads per workgroup of the packed-slot sweeps, at most
 constexpr int kRing = 8;          // rounds of partner mailboxes kept per position
 constexpr int kBitSlots = 4;      // replicas per workgroup in the bit-packed layout
 constexpr int kBitsBlock = 768;   // threads of a bit-packed sweep workgroup that follows f and g
@@ -68,6 +69,8 @@ struct DevProblem {
     int32_t narrow;
     int32_t has_bias;   // any nonzero field
     int32_t block;      // threads per sweep workgroup
+    int32_t rpb;        // per-round driver, int8: > 1 packs rpb slots per workgroup
+    int32_t lshift;     // of 2^lshift lanes each (rpb << lshift threads)
     int32_t bits;       // bit-packed layout
     int32_t n_words;    // 32-bit words per replica in the bit-packed layout
     int32_t bit_start[kMaxColors + 1];

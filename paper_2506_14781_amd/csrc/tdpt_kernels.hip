@@ -229,6 +229,10 @@ struct QuadS {
     int voff;    // byte offset of the quad in a structure row
 };
 
+// Layouts whose structure the packed-slot sweeps may hold in registers.
+template <int NARROW, int WD>
+constexpr bool kHoistable = NARROW == kPacked && WD <= 4;
+
 template <int NARROW, int WD>
 __device__ __forceinline__ void load_quad(const DevProblem &P, const Rsrc &Rs, int q, QuadS<NARROW, WD> &Q)
 {
@@ -481,12 +485,61 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v)
 // lane + lanes, .. of every class); adds the changes of f and g that this
 // lane made to df and dg.  Every thread of the block calls it (the phases
 // end in block barriers, the last one excepted).
-template <int NARROW, int WD>
+// The class phases of all sweeps of one round for the replica at s, walked
+// by `lanes` lanes of which this one is number `lane` (quads lane,
+// lane + lanes, .. of every class); adds the changes of f and g that this
+// lane made to df and dg.  Every thread of the block calls it (the phases
+// end in block barriers, the last one excepted).
+// HOIST (packed copy-edge layout, at most 4 problem neighbours, no fields):
+// when there are two colour classes of at most `lanes` quads each (small
+// bipartite instances), every lane holds the structure of its (at most) one
+// quad per class in registers for the whole round instead of loading it
+// again in every phase, whose latency then no longer waits on the cache
+// (the classes' loop unrolled, so both quads stay in registers, and the
+// Philox key read once per round).  It costs about 75 registers, so only
+// the packed-slot sweeps, which run such replicas, use it.
+template <int NARROW, int WD, bool HOIST = false>
 __device__ __forceinline__ void sweep_phases(const DevProblem &P, const Rsrc &Rs, lds8_t *s, const SlotParams &sp,
                                              int64_t n_round, int lane, int lanes, int64_t &df, int64_t &dg)
 {
-    for (int k = 0; k < P.mcs; ++k) {
-        const uint32_t t = (uint32_t)((n_round - 1) * P.mcs + k);
+    const int mcs = P.mcs;
+    if constexpr (HOIST && kHoistable<NARROW, WD>) {
+        const uint32_t key0 = P.key0, key1 = P.key1;
+        const int qa = P.cls_start[0] >> 2, qb = P.cls_start[1] >> 2, qc = P.cls_start[2] >> 2;
+        if (P.n_colors == 2 && !P.has_bias && qb - qa <= lanes && qc - qb <= lanes) {
+            QuadS<NARROW, WD> QQ[2];
+            const int qq[2] = {qa + lane, qb + lane};
+            const bool has[2] = {qq[0] < qb, qq[1] < qc};
+            const int live_end[2] = {P.cls_live[0], P.cls_live[1]};
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                if (has[c]) load_quad<NARROW, WD>(P, Rs, qq[c], QQ[c]);
+            for (int k = 0; k < mcs; ++k) {
+                const uint32_t t = (uint32_t)((n_round - 1) * mcs + k);
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    int dfa = 0, dga = 0;
+                    if (has[c]) {
+                        const int q = qq[c];
+                        uint32_t u[4] = {(uint32_t)q, t, sp.pos, 0u};
+                        philox10(u[0], u[1], u[2], u[3], key0, key1);
+                        int hp[4], cs[4];
+                        quad_fields<NARROW, WD>(P, Rs, s, QQ[c], hp, cs);
+                        const int rem = live_end[c] - q * 4;
+                        const uint32_t live_bytes =
+                            rem >= 4 ? 0xffffffffu : rem <= 0 ? 0u : ((1u << (8 * rem)) - 1u);
+                        quad_update<NARROW>(P, s, q, hp, cs, live_bytes, u, sp, dfa, dga);
+                    }
+                    df += dfa;
+                    dg += 2 * (int64_t)dga;
+                    if (k + 1 < mcs || c == 0) __syncthreads();
+                }
+            }
+            return;
+        }
+    }
+    for (int k = 0; k < mcs; ++k) {
+        const uint32_t t = (uint32_t)((n_round - 1) * mcs + k);
         for (int c = 0; c < P.n_colors; ++c) {
             const int q0 = P.cls_start[c] >> 2, q1 = P.cls_start[c + 1] >> 2;
             const int live_end = P.cls_live[c];
@@ -506,7 +559,7 @@ __device__ __forceinline__ void sweep_phases(const DevProblem &P, const Rsrc &Rs
             }
             df += dfa;
             dg += 2 * (int64_t)dga;
-            if (k + 1 < P.mcs || c + 1 < P.n_colors) __syncthreads();
+            if (k + 1 < mcs || c + 1 < P.n_colors) __syncthreads();
         }
     }
 }
@@ -623,8 +676,8 @@ __device__ __forceinline__ void multi_round_body(const DevProblem &P, int slot0,
     __syncthreads();
     int64_t df = 0, dg = 0;
     // a skipped group starts past every class, so it takes the barriers only
-    sweep_phases<NARROW, WD>(P, Rs, replica_lds() + sub * P.stride, sp, n_round, live ? lane : (1 << 30),
-                             1 << lshift, df, dg);
+    sweep_phases<NARROW, WD, true>(P, Rs, replica_lds() + sub * P.stride, sp, n_round, live ? lane : (1 << 30),
+                                   1 << lshift, df, dg);
     // sum over each group: within its wave segment, then across its waves
     const int seg = lshift < 6 ? (1 << lshift) : 64;
     for (int off = seg >> 1; off > 0; off >>= 1) {
@@ -643,10 +696,19 @@ __device__ __forceinline__ void multi_round_body(const DevProblem &P, int slot0,
     copy_bytes16(P.states + (size_t)slot0 * P.stride, lds, nsub * P.stride);
 }
 
+// One round of one problem with rpb slots per workgroup (ceil(R / rpb)
+// workgroups).
+template <int NARROW, int WD>
+__global__ __launch_bounds__(kMultiBlock, 2) void k_round_sweep_multi(DevProblem P)
+{
+    extern __shared__ __align__(16) int8_t lds[];
+    multi_round_body<NARROW, WD>(P, blockIdx.x * P.rpb, P.rpb, P.lshift, lds);
+}
+
 // Batched round with rpb slots per workgroup: first_block is the prefix sum
 // of the members' workgroup counts, ceil(R / rpb) each.
 template <int NARROW, int WD>
-__global__ __launch_bounds__(kMaxBlock) void k_batch_sweep_multi(const DevProblem *__restrict__ table,
+__global__ __launch_bounds__(kMultiBlock, 2) void k_batch_sweep_multi(const DevProblem *__restrict__ table,
                                                                const int *__restrict__ first_block, int count,
                                                                int rpb, int lshift)
 {
@@ -1625,6 +1687,14 @@ static hipError_t allow_lds(K kernel, size_t lds)
 template <int NARROW, int WD>
 static hipError_t round_sweep_t(const DevProblem &p, hipStream_t s)
 {
+    if (p.rpb > 1) {
+        const size_t lds = (size_t)p.rpb * p.stride + 16 * (size_t)p.rpb + 16;
+        hipError_t e = allow_lds(k_round_sweep_multi<NARROW, WD>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_round_sweep_multi<NARROW, WD>), dim3((p.R + p.rpb - 1) / p.rpb),
+                           dim3(p.rpb << p.lshift), lds, s, p);
+        return hipGetLastError();
+    }
     const size_t lds = sweep_lds(p);
     hipError_t e = allow_lds(k_round_sweep<NARROW, WD>, lds);
     if (e != hipSuccess) return e;
@@ -1715,7 +1785,11 @@ static hipError_t persistent_t(const DevProblem &p, int64_t n_rounds, hipStream_
         return hipErrorInvalidValue;                                        \
     }
 
-hipError_t launch_sweep(const DevProblem &p, hipStream_t s) { TDPT_DISPATCH(round_sweep_t, p, s) }
+hipError_t launch_sweep(const DevProblem &p, hipStream_t s)
+{
+    if (p.rpb > 1 && (p.lshift < 0 || (p.rpb << p.lshift) > kMultiBlock)) return hipErrorInvalidValue;
+    TDPT_DISPATCH(round_sweep_t, p, s)
+}
 
 hipError_t launch_swap(const DevProblem &p, hipStream_t s)
 {
@@ -1749,7 +1823,8 @@ hipError_t launch_batch_sweep(const DevProblem &p, const DevProblem *table, cons
                               int count, int blocks, int block, size_t max_stride, int rpb, int lshift,
                               hipStream_t s)
 {
-    if (rpb < 1 || (rpb > 1 && (lshift < 0 || (rpb << lshift) != block))) return hipErrorInvalidValue;
+    if (rpb < 1 || (rpb > 1 && (lshift < 0 || (rpb << lshift) != block || block > kMultiBlock)))
+        return hipErrorInvalidValue;
     TDPT_DISPATCH(batch_sweep_t, p, table, first_block, count, blocks, block, max_stride, rpb, lshift, s)
 }
 

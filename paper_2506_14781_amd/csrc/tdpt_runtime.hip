@@ -110,6 +110,7 @@ struct tdpt_problem {
     bool persistent_ok = false;  // the persistent driver may be used (layout, key range)
     int32_t min_block = 64;      // smallest sweep workgroup the per-phase bounds allow
     int32_t min_lanes = 1;       // fewest lanes per replica the per-phase bounds allow
+    size_t stride_bytes = 0;     // bytes per replica slot
     int32_t max_class_quads = 0;
     int64_t rounds_host = 0;  // rounds done, as far as the host has enqueued them
     // rounds_host when the partner mailboxes were last valid (after a
@@ -295,6 +296,39 @@ int balanced_block(int quads, int cap)
     const int b = (need + g - 1) / g * g;
     return std::min(std::max(b, 64), cap);
 }
+
+// Whether rpb slots of `stride` bytes fit the LDS a workgroup takes without
+// giving up occupancy (64 KiB).
+bool pack_fits(size_t stride, int rpb)
+{
+    return (size_t)rpb * (stride + 16) + 16 <= 65536;
+}
+
+// Default packing of an int8 replica for per-round sweeps: when its largest
+// colour class takes under 64 lanes, one wave of 64 threads holds 64 / L
+// slots, L the power of two (at least 4) covering that class and the lanes
+// the per-phase bounds need; else one slot per workgroup (rpb = 1).
+void default_pack(int max_quads, int min_lanes, size_t stride, int32_t *rpb, int32_t *lshift)
+{
+    *rpb = 1;
+    *lshift = 0;
+    int ls = 2;
+    while ((1 << ls) < std::max(max_quads, min_lanes)) ++ls;
+    if (ls >= 6 || !pack_fits(stride, 64 >> ls)) return;
+    *rpb = 64 >> ls;
+    *lshift = ls;
+}
+
+// Whether the packed sweep keeps a replica's structure in registers for a
+// whole round (packed copy-edge layout, at most 4 problem neighbours, no
+// fields, two colour classes of at most 2^lshift quads).  Then per-round
+// launches beat the persistent driver once a round holds enough sweeps.
+bool pack_hoists(const tdpt::DevProblem &d, int max_quads, int lshift)
+{
+    return d.narrow && !d.gen && !d.bits && !d.has_bias && d.wd <= 4 && d.n_colors == 2 &&
+           max_quads <= (1 << lshift);
+}
+constexpr int kPackRoundMcs = 16;  // sweeps per round from which packed per-round launches are preferred
 
 // Threads of a sweep workgroup: one lane per quad of the largest colour
 // class, in balanced passes of at most `cap` threads (per-round driver), or
@@ -783,6 +817,7 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     p->rank = in->rank;
     p->min_block = min_block;
     p->min_lanes = (int32_t)std::max<int64_t>(1, min_block_q);
+    p->stride_bytes = L.stride;
     p->max_class_quads = in->max_class_quads;
     p->ws = (uint8_t *)dev_ws;
     p->ws_bytes = ws_bytes;
@@ -802,6 +837,9 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     d.narrow = narrow ? 1 : 0;
     d.has_bias = in->has_bias;
     d.block = bits ? sweep_block(in, false, tdpt::bits_block_cap(cfg->mcs_per_swap)) : sweep_block(in, false);
+    d.rpb = 1;
+    d.lshift = 0;
+    if (!bits) default_pack(in->max_class_quads, p->min_lanes, L.stride, &d.rpb, &d.lshift);
     d.bits = bits ? 1 : 0;
     d.n_words = n_words;
     for (int c = 0; c <= in->n_colors; ++c) d.bit_start[c] = bit_start[c];
@@ -1005,7 +1043,12 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     // its best-state keys need |f| < 2^30, its mailboxes carry f and g in 48 bits
     p->persistent_ok = !(pe && pe[0] == '0') && !bits && in->abs_f_bound < tdpt::kKeyOffset &&
                        in->g_bound < ((int64_t)1 << 47);
-    if (p->persistent_ok) {
+    // small bipartite replicas whose structure the packed per-round sweep
+    // holds in registers run that driver when rounds are long enough
+    // (TDPT_PERSISTENT=1 asks for the persistent driver wherever it fits)
+    const bool prefer_round = d.rpb > 1 && pack_hoists(d, in->max_class_quads, d.lshift) &&
+                              cfg->mcs_per_swap >= kPackRoundMcs && !(pe && pe[0] == '1');
+    if (p->persistent_ok && !prefer_round) {
         tdpt::DevProblem dq = d;
         dq.block = sweep_block(in, true);
         int max_blocks = 0;
@@ -1151,8 +1194,12 @@ int tdpt_problem_autotune(tdpt_problem *p, int32_t rounds_per_trial, tdpt_tune_r
     // the trials run (temporarily) up to kMaxTrials * (1 + rounds_per_trial) rounds
     if ((p->rounds_host + kMaxTrials * (1 + (int64_t)rounds_per_trial)) * (int64_t)p->mcs > ((int64_t)1 << 32))
         return fail(TDPT_E_RANGE, "a problem runs at most 2^32 sweeps");
-    // candidates: (driver, threads per workgroup)
-    std::vector<std::pair<int, int>> cand;
+    // candidates: (driver, threads per workgroup, slots per workgroup, log2
+    // of lanes per slot)
+    struct Cand {
+        int first, second, rpb, lshift;
+    };
+    std::vector<Cand> cand;
     const int cap = p->dp.bits ? tdpt::bits_block_cap(p->mcs) : tdpt::kMaxBlock;
     const int quads = p->max_class_quads;
     // a spread of sizes plus the balanced one (its last pass over a class
@@ -1162,7 +1209,16 @@ int tdpt_problem_autotune(tdpt_problem *p, int32_t rounds_per_trial, tdpt_tune_r
     if (std::find(per_round.begin(), per_round.end(), bal) == per_round.end()) per_round.push_back(bal);
     std::sort(per_round.begin(), per_round.end());
     for (int b : per_round)
-        if (b >= p->min_block && b <= cap && b <= std::max(64, (quads + 63) / 64 * 64)) cand.push_back({0, b});
+        if (b >= p->min_block && b <= cap && b <= std::max(64, (quads + 63) / 64 * 64)) cand.push_back({0, b, 1, 0});
+    // int8 replicas of a small largest class: several per workgroup of 64,
+    // 128 or 256 threads, one to four passes over the class
+    if (!p->dp.bits)
+        for (int ls = 0; ls <= 5; ++ls) {
+            const int lanes = 1 << ls;
+            if (lanes < p->min_lanes || 4 * lanes < quads || (ls > 0 && lanes / 2 >= quads)) continue;
+            for (int blk : {64, 128, 256})
+                if (pack_fits(p->stride_bytes, blk >> ls)) cand.push_back({0, blk, blk >> ls, ls});
+        }
     if (p->persistent_ok) {
         for (int b = 64; b <= tdpt::kMaxBlock / 2; b += 64) {
             if (b < p->min_block || b > std::max(64, (quads + 63) / 64 * 64)) continue;
@@ -1170,7 +1226,7 @@ int tdpt_problem_autotune(tdpt_problem *p, int32_t rounds_per_trial, tdpt_tune_r
             dq.block = b;
             int max_blocks = 0;
             HIP_TRY(tdpt::persistent_max_blocks(dq, &max_blocks), "occupancy query");
-            if (max_blocks >= p->R) cand.push_back({1, b});
+            if (max_blocks >= p->R) cand.push_back({1, b, 1, 0});
         }
     }
     if (cand.empty()) return fail(TDPT_E_INVALID, "no launch shape satisfies the problem's bounds");
@@ -1183,7 +1239,7 @@ int tdpt_problem_autotune(tdpt_problem *p, int32_t rounds_per_trial, tdpt_tune_r
     rc = tdpt_problem_save(p, saved.data(), &bytes);
     if (rc) return rc;
     const bool old_persistent = p->persistent;
-    const int old_block = p->dp.block;
+    const int old_block = p->dp.block, old_rpb = p->dp.rpb, old_lshift = p->dp.lshift;
     const int32_t old_every = p->time_every;
     p->time_every = 0;
     memset(out, 0, sizeof(*out));
@@ -1191,7 +1247,9 @@ int tdpt_problem_autotune(tdpt_problem *p, int32_t rounds_per_trial, tdpt_tune_r
     int best_i = -1;
     for (size_t i = 0; i < cand.size() && rc == TDPT_OK; ++i) {
         p->persistent = cand[i].first == 1;
-        p->dp.block = cand[i].second;
+        p->dp.block = cand[i].rpb > 1 ? old_block : cand[i].second;
+        p->dp.rpb = cand[i].rpb;
+        p->dp.lshift = cand[i].lshift;
         rc = tdpt_problem_run(p, 1);  // warm-up
         double ms = 0.0;
         if (rc == TDPT_OK)
@@ -1200,6 +1258,7 @@ int tdpt_problem_autotune(tdpt_problem *p, int32_t rounds_per_trial, tdpt_tune_r
         const double per = ms / rounds_per_trial;
         out->trial_driver[i] = cand[i].first;
         out->trial_block[i] = cand[i].second;
+        out->trial_slots[i] = cand[i].rpb;
         out->trial_ms_per_round[i] = per;
         out->n_trials = (int32_t)i + 1;
         if (per < best) {
@@ -1211,13 +1270,18 @@ int tdpt_problem_autotune(tdpt_problem *p, int32_t rounds_per_trial, tdpt_tune_r
     if (rc || best_i < 0) {
         p->persistent = old_persistent;
         p->dp.block = old_block;
+        p->dp.rpb = old_rpb;
+        p->dp.lshift = old_lshift;
         (void)tdpt_problem_load(p, saved.data(), saved.size());
         return rc ? rc : fail(TDPT_E_DEVICE, "autotune timed nothing");
     }
     p->persistent = cand[best_i].first == 1;
-    p->dp.block = cand[best_i].second;
+    p->dp.block = cand[best_i].rpb > 1 ? old_block : cand[best_i].second;
+    p->dp.rpb = cand[best_i].rpb;
+    p->dp.lshift = cand[best_i].lshift;
     out->driver = cand[best_i].first;
     out->block = cand[best_i].second;
+    out->slots = cand[best_i].rpb;
     out->ms_per_round = best;
     return tdpt_problem_load(p, saved.data(), saved.size());
 }
@@ -1243,6 +1307,7 @@ int tdpt_problem_query(tdpt_problem *p, tdpt_status *out)
                                    "mailbox (blocks not co-resident, or partners disagreeing on a swap)");
     out->rounds_done = h[tdpt::kHdrRounds];
     out->driver = p->persistent ? 1 : 0;
+    out->slots = p->persistent ? 1 : std::max(p->dp.rpb, 1);
     out->sweeps_done = h[tdpt::kHdrRounds] * p->mcs;
     out->first_hit_sweep = h[tdpt::kHdrFirstHit];
     out->best_f_q = h[tdpt::kHdrBestF];
@@ -1666,7 +1731,17 @@ static int batch_sync_prefix(tdpt_batch *b)
 static int batch_decide_mode(tdpt_batch *b)
 {
     b->persistent = false;
-    bool fits = !b->members.empty() && b->driver_mode != 0 && !b->tuned_per_round;
+    // every group packed with its structure in registers, every member's
+    // rounds long enough: per-round launches (as for one such problem)
+    bool prefer_round = !b->groups.empty();
+    for (const auto &g : b->groups) {
+        prefer_round = prefer_round && g.rpb > 1 && g.min_mcs >= kPackRoundMcs;
+        for (int k = g.first_member; prefer_round && k < g.first_member + g.count; ++k)
+            prefer_round = pack_hoists(b->members[k]->dp, b->members[k]->max_class_quads, g.lshift);
+    }
+    const char *pe = getenv("TDPT_PERSISTENT");
+    if (pe && pe[0] == '1') prefer_round = false;
+    bool fits = !b->members.empty() && b->driver_mode != 0 && !b->tuned_per_round && !prefer_round;
     for (auto *p : b->members) fits = fits && p->persistent_ok;
     for (size_t gi = 0; fits && gi < b->groups.size(); ++gi) {
         const auto &g = b->groups[gi];
@@ -1687,20 +1762,11 @@ static int batch_decide_mode(tdpt_batch *b)
 // when its largest colour class takes under 64 lanes, one wave of 64 holds
 // 64 / L slots, L the power of two covering that class (and the members'
 // per-phase bounds); larger replicas keep one slot per workgroup.
-// Whether rpb slots of the group's largest replica fit the LDS a workgroup
-// takes without giving up occupancy (64 KiB).
-static bool pack_fits(const tdpt_batch::Group &g, int rpb)
-{
-    return (size_t)rpb * (g.max_stride + 16) + 16 <= 65536;
-}
-
 static void batch_default_pack(tdpt_batch::Group &g, bool bits)
 {
     g.rpb = 1;
     g.lshift = 0;
     if (bits) return;
-    int lshift = 0;
-    while ((1 << lshift) < std::max(g.max_quads, g.min_lanes)) ++lshift;
     if (const char *e = getenv("TDPT_BATCH_LANES")) {
         // test hook: lanes per slot (a power of two); the workgroup then holds
         // max(block, lanes) / lanes slots, block from TDPT_BATCH_BLOCK or 64
@@ -1710,18 +1776,14 @@ static void batch_default_pack(tdpt_batch::Group &g, bool bits)
         if (v >= 1 && (1 << ls) == v && v >= g.min_lanes && v <= tdpt::kMaxBlock / 2) {
             const char *eb = getenv("TDPT_BATCH_BLOCK");
             const int blk = std::max(eb ? atoi(eb) : 64, v);
-            if (blk % v == 0 && blk / v >= 2 && blk <= tdpt::kMaxBlock && pack_fits(g, blk / v)) {
+            if (blk % v == 0 && blk / v >= 2 && blk <= tdpt::kMultiBlock && pack_fits(g.max_stride, blk / v)) {
                 g.rpb = blk / v;
                 g.lshift = ls;
             }
         }
         return;
     }
-    if (lshift >= 6) return;
-    lshift = std::max(lshift, 2);
-    if (!pack_fits(g, 64 >> lshift)) return;
-    g.lshift = lshift;
-    g.rpb = 64 >> lshift;
+    default_pack(g.max_quads, g.min_lanes, g.max_stride, &g.rpb, &g.lshift);
 }
 
 // n_rounds rounds of every member through the persistent driver.
@@ -2072,7 +2134,7 @@ int tdpt_batch_autotune(tdpt_batch *b, int32_t rounds_per_trial, tdpt_batch_tune
                 const int lanes = 1 << ls;
                 if (lanes < g.min_lanes || 4 * lanes < g.max_quads || (ls > 0 && lanes / 2 >= g.max_quads)) continue;
                 for (int blk : {64, 128, 256})
-                    if (pack_fits(g, blk >> ls)) cands.push_back({blk, blk >> ls, ls});
+                    if (pack_fits(g.max_stride, blk >> ls)) cands.push_back({blk, blk >> ls, ls});
             }
         double best = 1e300;
         Cand best_c{g.block, g.rpb, g.lshift};

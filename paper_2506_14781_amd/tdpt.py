@@ -73,7 +73,8 @@ class _Layout(ctypes.Structure):
 class _TuneReport(ctypes.Structure):
     _fields_ = [("driver", ctypes.c_int32), ("block", ctypes.c_int32), ("ms_per_round", ctypes.c_double),
                 ("n_trials", ctypes.c_int32), ("trial_driver", ctypes.c_int32 * 32),
-                ("trial_block", ctypes.c_int32 * 32), ("trial_ms_per_round", ctypes.c_double * 32)]
+                ("trial_block", ctypes.c_int32 * 32), ("trial_ms_per_round", ctypes.c_double * 32),
+                ("slots", ctypes.c_int32), ("trial_slots", ctypes.c_int32 * 32)]
 
 
 class _BatchTuneReport(ctypes.Structure):
@@ -87,7 +88,7 @@ class _BatchTuneReport(ctypes.Structure):
 class _Status(ctypes.Structure):
     _fields_ = [("rounds_done", ctypes.c_int64), ("sweeps_done", ctypes.c_int64),
                 ("first_hit_sweep", ctypes.c_int64), ("best_f_q", ctypes.c_int64),
-                ("best_sweep", ctypes.c_int64), ("driver", ctypes.c_int32)]
+                ("best_sweep", ctypes.c_int64), ("driver", ctypes.c_int32), ("slots", ctypes.c_int32)]
 
 
 _lib = None
@@ -400,13 +401,16 @@ class Problem:
         _check(_lib.tdpt_problem_load(self._h, buf, len(blob)))
 
     def autotune(self, rounds_per_trial: int = 10) -> dict:
-        """Time the admissible (driver, workgroup size) pairs on this problem
-        and keep the fastest; the problem's state is left as it was."""
+        """Time the admissible launch shapes (driver, workgroup size, replicas
+        per workgroup) on this problem and keep the fastest; the problem's
+        state is left as it was.  Trials are (driver, threads, replicas per
+        workgroup, ms per round)."""
         r = _TuneReport()
         _check(_lib.tdpt_problem_autotune(self._h, int(rounds_per_trial), ctypes.byref(r)))
         k = r.n_trials
-        return {"driver": r.driver, "block": r.block, "ms_per_round": r.ms_per_round,
-                "trials": [(r.trial_driver[i], r.trial_block[i], r.trial_ms_per_round[i]) for i in range(k)]}
+        return {"driver": r.driver, "block": r.block, "slots": r.slots, "ms_per_round": r.ms_per_round,
+                "trials": [(r.trial_driver[i], r.trial_block[i], r.trial_slots[i], r.trial_ms_per_round[i])
+                           for i in range(k)]}
 
     def set_stage_trace(self, buf, rounds: int):
         """Persistent driver: per-round, per-slot stage timestamps (100 MHz

@@ -108,6 +108,27 @@ def test_small_wishart_full_run(T):
     assert o["first_hit"] > 0  # seed 5 reaches the planted ground state
 
 
+def test_packed_per_round_single_problem(T):
+    """Small bipartite replicas with long rounds run packed per-round
+    launches by default (four N=12 replicas per wave, each lane's structure
+    held in registers for the round): bit-exact against the oracle, as is
+    the persistent driver asked for instead.  The 10-spin instance packs 16
+    replicas (4 lanes each) into a wave of the per-round driver."""
+    w = wishart_small()
+    o, P = both(T, w.instance, w.beta, w.p_q, mcs=20, rounds=12, seed=3, label="packed N12")
+    q = P.query()
+    assert q["driver"] == 0 and q["slots"] == 4
+    Q = _with_env("TDPT_PERSISTENT", "1", lambda: run_gpu(T, w.instance, w.beta, w.p_q, mcs=20, rounds=12, seed=3))
+    assert Q.query()["driver"] == 1
+    assert_same(o, Q, "N12 persistent")
+    inst = tiny_instance()
+    beta = np.geomspace(0.3, 3.0, 5)
+    p_q = q12(np.linspace(0.5, 3.0, 7))
+    o, P = _with_env("TDPT_PERSISTENT", "0", lambda: both(T, inst, beta, p_q, mcs=16, rounds=10, seed=4,
+                                                          label="packed tiny 5x7"))
+    assert P.query()["driver"] == 0 and P.query()["slots"] == 16
+
+
 @pytest.mark.parametrize("I,J,mcs", [(1, 1, 3), (1, 4, 2), (4, 1, 2), (2, 2, 1), (3, 5, 2)])
 def test_tiny_grids(T, I, J, mcs):
     inst = tiny_instance()
@@ -273,7 +294,8 @@ def test_drivers_agree_on_the_small_workload(T):
     assert all(np.array_equal(x, y) for x, y in zip(a.counters(), b.counters()))
     assert all(np.array_equal(x, y) for x, y in zip(a.trace(), b.trace()))
     qa, qb = a.query(), b.query()
-    qa.pop("driver"), qb.pop("driver")
+    for k in ("driver", "slots"):  # the launch shape; results must not depend on it
+        qa.pop(k), qb.pop(k)
     assert qa == qb
     assert np.array_equal(a.best()[0], b.best()[0])
 
@@ -419,7 +441,8 @@ def test_autotune_leaves_results_unchanged(T):
     rep = b.autotune(3)
     _say(f"[parity] autotune N12: {rep['driver']} {rep['block']} from {len(rep['trials'])} trials")
     assert len(rep["trials"]) >= 2
-    assert (rep["driver"], rep["block"]) in {(d, k) for d, k, _ in rep["trials"]}
+    assert (rep["driver"], rep["block"], rep["slots"]) in {(d, k, r) for d, k, r, _ in rep["trials"]}
+    assert any(r > 1 for _, _, r, _ in rep["trials"])  # packed shapes are among the candidates
     assert np.array_equal(before[0], b.states())
     assert all(np.array_equal(x, y) for x, y in zip(before[1], b.energies()))
     assert before[2]["rounds_done"] == b.query()["rounds_done"]
@@ -450,7 +473,7 @@ def test_autotune_n200_and_bits(T):
         Q = T.Problem(T.Instance.from_synth(ws.instance),
                       T.RunConfig(ws.beta, ws.p_q, mcs_per_swap=5, seed=2, trace_cap=20))
         r = Q.autotune(2)
-        assert all(d == 0 and k <= 512 for d, k, _ in r["trials"])
+        assert all(d == 0 and k <= 512 and n == 1 for d, k, n, _ in r["trials"])
         Q.run(20)
         return Q
     Q = _with_env("TDPT_LAYOUT", "bits", bits)
