@@ -1187,6 +1187,16 @@ __device__ __forceinline__ int mad24(int a, int b, int c)
     return r;
 }
 
+// Bit (pos mod 32) of w in one instruction: v_bfe_u32 reads only the low 5
+// bits of its offset operand, so positions stored as 512 word + bit need no
+// mask first (the compiler's bit-field extract masks the offset itself).
+__device__ __forceinline__ uint32_t bit_of(uint32_t w, int pos)
+{
+    uint32_t r;
+    __asm__("v_bfe_u32 %0, %1, %2, 1" : "=v"(r) : "v"(w), "v"(pos));
+    return r;
+}
+
 __device__ __forceinline__ uint32_t or8_last(uint32_t x)
 {
     x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
@@ -1223,7 +1233,7 @@ __device__ __forceinline__ void bits_update_quad(const DevProblem &P, const Rsrc
             const uint32_t w4[4] = {nw.x, nw.y, nw.z, nw.w};
 #pragma unroll
             for (int r = 0; r < kBitSlots; ++r)
-                acc[j][r] = mad24((int)__builtin_amdgcn_ubfe(w4[r], pos & 31, 1), jk[j], acc[j][r]);
+                acc[j][r] = mad24((int)bit_of(w4[r], pos), jk[j], acc[j][r]);
         }
     }
     const v4i c0 = bload(Rs.ch, voff, 0);
@@ -1240,8 +1250,8 @@ __device__ __forceinline__ void bits_update_quad(const DevProblem &P, const Rsrc
         const int nkc = -(int)((uint32_t)p0 >> 29);
 #pragma unroll
         for (int r = 0; r < kBitSlots; ++r) {
-            const int b0 = (int)__builtin_amdgcn_ubfe(a4[r], p0 & 31, 1);
-            const int b1 = (int)__builtin_amdgcn_ubfe(b4[r], p1 & 31, 1);
+            const int b0 = (int)bit_of(a4[r], p0);
+            const int b1 = (int)bit_of(b4[r], p1);
             cs[j][r] = 2 * (b0 + b1) + nkc;
         }
     }
@@ -1334,7 +1344,7 @@ __device__ __forceinline__ void bits_energy_quad(const DevProblem &P, const Rsrc
             const uint32_t w4[4] = {nw.x, nw.y, nw.z, nw.w};
 #pragma unroll
             for (int r = 0; r < kBitSlots; ++r)
-                acc[j][r] = mad24((int)__builtin_amdgcn_ubfe(w4[r], pos & 31, 1), jk[j], acc[j][r]);
+                acc[j][r] = mad24((int)bit_of(w4[r], pos), jk[j], acc[j][r]);
         }
     }
     const v4i c0 = bload(Rs.ch, voff, 0);
@@ -1358,8 +1368,8 @@ __device__ __forceinline__ void bits_energy_quad(const DevProblem &P, const Rsrc
             const uint32_t bi = (o4[r] >> (off + j)) & 1u;
             const int64_t t = (int64_t)(h0[j] + 2 * acc[j][r]) + bb[j];
             ef[r] += bi ? -t : t;
-            const uint32_t d0 = (bi ^ __builtin_amdgcn_ubfe(a4[r], p0 & 31, 1)) & (kc >= 1 ? 1u : 0u);
-            const uint32_t d1 = (bi ^ __builtin_amdgcn_ubfe(b4[r], p1 & 31, 1)) & (kc >= 2 ? 1u : 0u);
+            const uint32_t d0 = (bi ^ bit_of(a4[r], p0)) & (kc >= 1 ? 1u : 0u);
+            const uint32_t d1 = (bi ^ bit_of(b4[r], p1)) & (kc >= 2 ? 1u : 0u);
             eg[r] += (int)(d0 + d1);
         }
     }
