@@ -127,6 +127,37 @@ def test_packed_per_round_single_problem(T):
     o, P = _with_env("TDPT_PERSISTENT", "0", lambda: both(T, inst, beta, p_q, mcs=16, rounds=10, seed=4,
                                                           label="packed tiny 5x7"))
     assert P.query()["driver"] == 0 and P.query()["slots"] == 16
+    # classes of unequal size (1 and 3 quads, the last ones partly dead): the
+    # lanes of a replica hold a quad of both classes, of one, or of none
+    inst = _unequal_classes()
+    o, P = both(T, inst, np.geomspace(0.3, 3.0, 4), q12([0.0, 1.0, 2.0]), mcs=20, rounds=12, seed=5,
+                label="packed unequal classes")
+    assert P.query()["driver"] == 0 and P.query()["slots"] == 16
+
+
+def _unequal_classes():
+    """Bipartite instance without fields: 3 centres (colour 0) with 3 leaves
+    each (colour 1), two of the leaves copies of centres; Q12 couplings."""
+    from synth.instances import Instance
+    rng = np.random.default_rng(21)
+    n = 12
+    edges = [(c, 3 + 3 * c + k) for c in range(3) for k in range(3)]
+    J = np.zeros((n, n), np.int32)
+    for a, b in edges:
+        J[a, b] = J[b, a] = int(rng.integers(-3000, 3000))
+    row_ptr = np.zeros(n + 1, np.int32)
+    cols, vals = [], []
+    for i in range(n):
+        nb = np.flatnonzero(J[i])
+        cols += nb.tolist()
+        vals += J[i, nb].tolist()
+        row_ptr[i + 1] = len(cols)
+    copy_a, copy_b = np.array([0, 1], np.int32), np.array([6, 9], np.int32)
+    logical_of = np.array([0, 1, 2, 3, 4, 5, 0, 6, 7, 1, 8, 9], np.int32)
+    color = np.array([0, 0, 0] + [1] * 9, np.int32)
+    return Instance(n=n, row_ptr=row_ptr, col=np.array(cols, np.int32), J_q=np.array(vals, np.int32),
+                    b_q=np.zeros(n, np.int32), copy_a=copy_a, copy_b=copy_b, color=color,
+                    logical_of=logical_of, N=10)
 
 
 @pytest.mark.parametrize("I,J,mcs", [(1, 1, 3), (1, 4, 2), (4, 1, 2), (2, 2, 1), (3, 5, 2)])
