@@ -197,6 +197,16 @@ typedef struct tdpt_layout {
     int32_t general;    /* 1: general constraint terms, 0: copy edges */
     int32_t ell_width;  /* problem-neighbour slots per spin in the device structure */
     int32_t group_key;  /* bits | narrow << 1 | (narrow && general) << 2 | ell_width << 3 */
+    /* default launch shape of the per-round sweep (int8 replicas): */
+    int32_t slots;      /* replicas per workgroup: 64 / lanes when the largest colour class
+                           takes under 64 lanes (and the slots fit 64 KiB of LDS), else 1 */
+    int32_t lanes;      /* lanes per replica, the power of two (>= 4) covering the largest
+                           class and the per-phase bounds; 0 when slots is 1 */
+    int32_t held;       /* 1: the packed sweep holds each lane's structure in registers for a
+                           round (packed copy-edge layout, <= 4 neighbours, no fields, two
+                           colour classes) */
+    int32_t per_round;  /* 1: tdpt_problem_create picks per-round launches over the persistent
+                           driver (held, and mcs_per_swap >= 16) */
 } tdpt_layout;
 int tdpt_layout_get(const tdpt_instance *inst, const tdpt_run_cfg *cfg, tdpt_layout *out);
 

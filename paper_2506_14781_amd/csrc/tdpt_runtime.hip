@@ -323,12 +323,29 @@ void default_pack(int max_quads, int min_lanes, size_t stride, int32_t *rpb, int
 // whole round (packed copy-edge layout, at most 4 problem neighbours, no
 // fields, two colour classes of at most 2^lshift quads).  Then per-round
 // launches beat the persistent driver once a round holds enough sweeps.
+bool pack_hoists(bool narrow, bool gen, bool bits, bool has_bias, int wd, int n_colors, int max_quads,
+                 int lshift)
+{
+    return narrow && !gen && !bits && !has_bias && wd <= 4 && n_colors == 2 && max_quads <= (1 << lshift);
+}
 bool pack_hoists(const tdpt::DevProblem &d, int max_quads, int lshift)
 {
-    return d.narrow && !d.gen && !d.bits && !d.has_bias && d.wd <= 4 && d.n_colors == 2 &&
-           max_quads <= (1 << lshift);
+    return pack_hoists(d.narrow != 0, d.gen != 0, d.bits != 0, d.has_bias != 0, d.wd, d.n_colors, max_quads,
+                       lshift);
 }
 constexpr int kPackRoundMcs = 16;  // sweeps per round from which packed per-round launches are preferred
+
+// Fewest lanes per replica that keep every lane's per-phase sums of 2 |h|
+// (f) and 2 |c| (g) over its quads below 2^31, for the largest penalty of
+// the configuration (c is the half penalty field, which P = 0 leaves out of
+// the field bound).
+int32_t min_lanes_for(const tdpt_instance *in, int64_t pmax)
+{
+    const int64_t hmax = in->max_field + 2 * pmax * in->max_cfield;
+    const int64_t hb = std::max(hmax, in->max_cfield);
+    const int64_t q_allowed = std::max<int64_t>(1, (((int64_t)1 << 31) - 1) / (8 * std::max<int64_t>(hb, 1)));
+    return (int32_t)std::max<int64_t>(1, (in->max_class_quads + q_allowed - 1) / q_allowed);
+}
 
 // Threads of a sweep workgroup: one lane per quad of the largest colour
 // class, in balanced passes of at most `cap` threads (per-round driver), or
@@ -777,9 +794,8 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     if (quads_per_thread * 4 * 2 * hb >= ((int64_t)1 << 31))
         return fail(TDPT_E_RANGE, "per-phase energy change can reach 2^31");
     // smallest workgroup (multiple of 64) keeping every lane's per-phase sums below 2^31
-    const int64_t q_allowed = std::max<int64_t>(1, (((int64_t)1 << 31) - 1) / (8 * std::max<int64_t>(hb, 1)));
-    const int64_t min_block_q = (in->max_class_quads + q_allowed - 1) / q_allowed;
-    const int32_t min_block = (int32_t)std::max<int64_t>(64, (min_block_q + 63) / 64 * 64);
+    const int32_t min_lanes = min_lanes_for(in, pmax);
+    const int32_t min_block = std::max<int32_t>(64, (min_lanes + 63) / 64 * 64);
     if (in->g_bound > 0 && pmax > (((int64_t)1 << 51) / in->g_bound))
         return fail(TDPT_E_RANGE, "energy differences can reach 2^52");
     const int64_t ebound = in->abs_f_bound + pmax * in->g_bound;
@@ -816,7 +832,7 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     p->mcs = cfg->mcs_per_swap;
     p->rank = in->rank;
     p->min_block = min_block;
-    p->min_lanes = (int32_t)std::max<int64_t>(1, min_block_q);
+    p->min_lanes = min_lanes;
     p->stride_bytes = L.stride;
     p->max_class_quads = in->max_class_quads;
     p->ws = (uint8_t *)dev_ws;
@@ -1479,6 +1495,17 @@ int tdpt_layout_get(const tdpt_instance *in, const tdpt_run_cfg *cfg, tdpt_layou
     out->general = in->gen ? 1 : 0;
     out->ell_width = L.wd;
     out->group_key = GroupKey{out->bits, out->narrow, (narrow && in->gen) ? 1 : 0, L.wd}.code();
+    // the per-round sweep's default packing, as tdpt_problem_create sets it
+    int32_t rpb = 1, lshift = 0;
+    if (!out->bits)
+        default_pack(in->max_class_quads, min_lanes_for(in, cfg->p_q[cfg->n_p - 1]), L.stride, &rpb, &lshift);
+    out->slots = rpb;
+    out->lanes = rpb > 1 ? 1 << lshift : 0;
+    out->held = rpb > 1 && pack_hoists(narrow, in->gen != 0, out->bits != 0, in->has_bias != 0, L.wd,
+                                       in->n_colors, in->max_class_quads, lshift)
+                    ? 1
+                    : 0;
+    out->per_round = out->held && cfg->mcs_per_swap >= kPackRoundMcs ? 1 : 0;
     return TDPT_OK;
 }
 

@@ -268,3 +268,33 @@ def test_layout_group_keys(monkeypatch):
     e = T.Instance.from_synth(w.instance).layout(cfg)
     assert (e["bits"], e["narrow"]) == (1, 0) and e["group_key"] & 1
     assert len({a["group_key"], c["group_key"], d["group_key"], e["group_key"]}) == 4
+
+
+def test_layout_default_packing(monkeypatch):
+    """The per-round sweep's default launch shape: replicas whose largest
+    colour class takes under 64 lanes share a 64-thread workgroup, 2^s lanes
+    each (the power of two, at least 4, covering the class); small bipartite
+    copy-chain replicas without fields hold their structure in registers and
+    run per-round launches when rounds hold 16 sweeps or more; large
+    replicas and the bit-packed layout keep one replica per workgroup."""
+    from synth.configs import wishart_n200
+    from tests.test_gpu_parity import _unequal_classes
+    from tests.tiny import tiny_instance
+    w = wishart_small()   # 72 spins, 2 classes of 9 quads, no fields
+    a = T.Instance.from_synth(w.instance).layout(T.RunConfig(w.beta, w.p_q, mcs_per_swap=50, seed=0))
+    assert (a["slots"], a["lanes"], a["held"], a["per_round"]) == (4, 16, 1, 1)
+    b = T.Instance.from_synth(w.instance).layout(T.RunConfig(w.beta, w.p_q, mcs_per_swap=15, seed=0))
+    assert (b["slots"], b["held"], b["per_round"]) == (4, 1, 0)
+    # 10 spins with fields: 3 quads per class, 4 lanes, structure re-read
+    t = T.Instance.from_synth(tiny_instance()).layout(T.RunConfig([1.0], [0, 4096], mcs_per_swap=50, seed=0))
+    assert (t["slots"], t["lanes"], t["held"], t["per_round"]) == (16, 4, 0, 0)
+    # classes of 1 and 3 quads, no fields
+    u = T.Instance.from_synth(_unequal_classes()).layout(T.RunConfig([1.0], [0, 4096], mcs_per_swap=20, seed=0))
+    assert (u["slots"], u["lanes"], u["held"], u["per_round"]) == (16, 4, 1, 1)
+    # 6800 spins, 850 quads per class: one replica per workgroup
+    n2 = wishart_n200()
+    c = T.Instance.from_synth(n2.instance).layout(T.RunConfig(n2.beta, n2.p_q, mcs_per_swap=1, seed=0))
+    assert (c["slots"], c["lanes"], c["held"], c["per_round"]) == (1, 0, 0, 0)
+    monkeypatch.setenv("TDPT_LAYOUT", "bits")
+    e = T.Instance.from_synth(w.instance).layout(T.RunConfig(w.beta, w.p_q, mcs_per_swap=50, seed=0))
+    assert e["bits"] == 1 and (e["slots"], e["lanes"], e["per_round"]) == (1, 0, 0)
