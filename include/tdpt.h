@@ -258,12 +258,14 @@ int tdpt_problem_create_static(const tdpt_instance *inst, const tdpt_run_cfg *cf
  * Driver (tdpt_status.driver; results never depend on it): the persistent
  * one -- one cooperative launch runs all n_rounds, replicas resident in LDS
  * and exchanging through mailboxes -- when every replica's workgroup fits
- * the GPU at once, except for int8 replicas whose largest colour class takes
- * under 64 lanes, whose structure (packed copy-edge layout, at most 8
- * problem neighbours) fits an LDS copy and whose rounds hold 16 sweeps or
- * more: those run per-round launches with several replicas per wave
- * (tdpt_status.slots) reading the structure from LDS.  Otherwise one sweep
- * launch and one swap launch per round.  The environment variable
+ * the GPU at once, except for small bipartite replicas -- packed copy-edge
+ * layout, at most 4 problem neighbours, no fields, two colour classes of
+ * under 64 lanes -- whose rounds hold 16 sweeps or more: those run per-round
+ * launches with several replicas per wave (tdpt_status.slots), each lane
+ * holding its quads' structure in registers for the round
+ * (tdpt_layout.per_round).  Otherwise one sweep launch and one swap launch
+ * per round, int8 replicas of a small largest class still packed several
+ * per workgroup.  The environment variable
  * TDPT_PERSISTENT=0 at creation forbids the persistent driver, =1 prefers it
  * wherever it fits; tdpt_problem_autotune may change the choice. */
 int tdpt_problem_run(tdpt_problem *prob, int64_t n_rounds);
@@ -446,11 +448,11 @@ int tdpt_batch_autotune(tdpt_batch *batch, int32_t rounds_per_trial, tdpt_batch_
  * rounds, every member's replicas resident at once and exchanging through
  * their own mailboxes -- whenever every member allows it (int8 layout,
  * persistent driver not switched off) and each group's workgroups fit the
- * GPU together, unless every group packs several replicas per workgroup
- * with its structure in LDS and every member's rounds hold 16 sweeps or
- * more (as for one such problem, see tdpt_problem_run); otherwise one sweep
- * launch per group and one swap launch per round.  0 forces the per-round launches.  Results are the same either
- * way.  tdpt_batch_query_driver reports the current choice (1 persistent). */
+ * GPU together, unless every member is a replica of the kind that runs
+ * per-round launches on its own (tdpt_problem_run: packed several per
+ * workgroup, structure held in registers, rounds of 16 sweeps or more);
+ * otherwise one sweep launch per group and one swap launch per round.  0
+ * forces the per-round launches.  Results are the same either way.  tdpt_batch_query_driver reports the current choice (1 persistent). */
 int tdpt_batch_set_driver(tdpt_batch *batch, int32_t driver);
 int tdpt_batch_query_driver(tdpt_batch *batch, int32_t *driver);
 /* Replay rounds from a HIP graph: with rounds_per_graph = k > 0, the launches
