@@ -123,6 +123,7 @@ typedef struct tdpt_status {
     int32_t driver;          /* 1: one cooperative launch runs many rounds with every
                                 replica resident in LDS; 0: one launch pair per round */
     int32_t slots;           /* per-round launches: replicas per sweep workgroup */
+    int32_t spin;            /* per-round launches: 1 if one spin per lane (else one quad) */
 } tdpt_status;
 
 /* ---------------------------------------------------------------- instance */
@@ -198,15 +199,21 @@ typedef struct tdpt_layout {
     int32_t ell_width;  /* problem-neighbour slots per spin in the device structure */
     int32_t group_key;  /* bits | narrow << 1 | (narrow && general) << 2 | ell_width << 3 */
     /* default launch shape of the per-round sweep (int8 replicas): */
-    int32_t slots;      /* replicas per workgroup: 64 / lanes when the largest colour class
-                           takes under 64 lanes (and the slots fit 64 KiB of LDS), else 1 */
-    int32_t lanes;      /* lanes per replica, the power of two (>= 4) covering the largest
-                           class and the per-phase bounds; 0 when slots is 1 */
-    int32_t held;       /* 1: the packed sweep holds each lane's structure in registers for a
-                           round (packed copy-edge layout, <= 4 neighbours, no fields, two
-                           colour classes) */
-    int32_t per_round;  /* 1: tdpt_problem_create picks per-round launches over the persistent
-                           driver (held, and mcs_per_swap >= 16) */
+    int32_t slots;      /* replicas per workgroup: 64 / lanes below 64 lanes (slots within
+                           64 KiB of LDS), else 1 */
+    int32_t lanes;      /* lanes per replica (0: one workgroup per replica at one quad per
+                           lane): with spin, the power of two (>= 4) covering the largest
+                           colour class's spins; else, when that class takes under 64
+                           quads, the power of two (>= 4) covering its quads and the
+                           per-phase bounds */
+    int32_t held;       /* 1: the packed sweep holds each lane's structure in registers for
+                           a round (two colour classes; one quad per lane also needs the
+                           packed copy-edge layout with <= 4 neighbours and no fields) */
+    int32_t per_round;  /* 1: tdpt_problem_create picks per-round launches over the
+                           persistent driver (held, and mcs_per_swap >= 16) */
+    int32_t spin;       /* 1: one spin per lane (packed copy-edge layout, <= 8 neighbours,
+                           largest class <= 256 spins, the problem's round within 2048
+                           waves, so latency-bound) */
 } tdpt_layout;
 int tdpt_layout_get(const tdpt_instance *inst, const tdpt_run_cfg *cfg, tdpt_layout *out);
 
@@ -258,14 +265,16 @@ int tdpt_problem_create_static(const tdpt_instance *inst, const tdpt_run_cfg *cf
  * Driver (tdpt_status.driver; results never depend on it): the persistent
  * one -- one cooperative launch runs all n_rounds, replicas resident in LDS
  * and exchanging through mailboxes -- when every replica's workgroup fits
- * the GPU at once, except for small bipartite replicas -- packed copy-edge
- * layout, at most 4 problem neighbours, no fields, two colour classes of
- * under 64 lanes -- whose rounds hold 16 sweeps or more: those run per-round
- * launches with several replicas per wave (tdpt_status.slots), each lane
- * holding its quads' structure in registers for the round
- * (tdpt_layout.per_round).  Otherwise one sweep launch and one swap launch
- * per round, int8 replicas of a small largest class still packed several
- * per workgroup.  The environment variable
+ * the GPU at once, except for small replicas whose lanes hold their
+ * structure in registers for a round (tdpt_layout.held: two colour classes
+ * and one spin per lane, or one quad per lane with at most 4 neighbours and
+ * no fields) and whose rounds hold 16 sweeps or more: those run per-round
+ * launches (tdpt_layout.per_round).  Per-round sweeps of small int8
+ * replicas take one spin per lane while the problem's round is within 2048
+ * waves (latency-bound; tdpt_status.spin), else one quad per lane, several
+ * replicas per workgroup when the largest colour class takes under 64
+ * lanes (tdpt_status.slots).  Otherwise one sweep launch and one swap
+ * launch per round.  The environment variable
  * TDPT_PERSISTENT=0 at creation forbids the persistent driver, =1 prefers it
  * wherever it fits; tdpt_problem_autotune may change the choice. */
 int tdpt_problem_run(tdpt_problem *prob, int64_t n_rounds);
@@ -356,8 +365,9 @@ int tdpt_problem_set_stage_trace(tdpt_problem *prob, uint64_t *dev_buf, int32_t 
  * driver at 64 to 1024 threads (768 for bit-packed replicas with fewer than
  * 4 sweeps per round, whose sweeps follow f and g per update), for int8
  * replicas of a small largest colour class also several replicas per
- * workgroup of 64, 128 or 256 threads (one to four passes over the class),
- * and, where every replica's workgroup can be resident at once, the
+ * workgroup of 64, 128 or 256 threads (one to four passes over the class)
+ * and one spin per lane (one or two passes), and, where every replica's
+ * workgroup can be resident at once, the
  * persistent driver at 64 to 512, each no larger than the largest colour
  * class needs and no smaller than the per-phase 2^31 bounds allow.  The problem's state is saved before and
  * restored after (the trial rounds leave no trace); since random numbers do
@@ -373,6 +383,8 @@ typedef struct tdpt_tune_report {
     double trial_ms_per_round[32];
     int32_t slots;               /* chosen replicas per workgroup (per-round driver) */
     int32_t trial_slots[32];
+    int32_t spin;                /* chosen: 1 one spin per lane, 0 one quad per lane */
+    int32_t trial_spin[32];
 } tdpt_tune_report;
 int tdpt_problem_autotune(tdpt_problem *prob, int32_t rounds_per_trial, tdpt_tune_report *out);
 
@@ -425,9 +437,11 @@ int tdpt_batch_query_async(tdpt_batch *batch, int64_t *dev_words);
  * run by the persistent driver where it fits; and, for int8 groups whose
  * largest colour class is small, several replicas per workgroup of 64, 128
  * or 256 threads (a power-of-two share of lanes each, one to four passes
- * over the class), run by per-round launches.  Without tuning, per-round
- * launches already pack the replicas of int8 groups whose largest class
- * takes under 64 lanes, one wave of 64 threads per workgroup.  The choice
+ * over the class) and one spin per lane (one or two passes), run by
+ * per-round launches.  Without tuning, per-round launches take one spin per
+ * lane while the batch's round is within 2048 waves, else pack the
+ * replicas of int8 groups whose largest class takes under 64 lanes, one
+ * wave of 64 threads per workgroup.  The choice
  * holds until the next tdpt_batch_set_members; a packed choice keeps the
  * batch on per-round launches. */
 typedef struct tdpt_batch_tune_report {
@@ -441,6 +455,8 @@ typedef struct tdpt_batch_tune_report {
     double trial_ms_per_round[128];
     int32_t group_slots[32];           /* chosen replicas per workgroup */
     int32_t trial_slots[128];
+    int32_t group_spin[32];            /* chosen: 1 one spin per lane */
+    int32_t trial_spin[128];
 } tdpt_batch_tune_report;
 int tdpt_batch_autotune(tdpt_batch *batch, int32_t rounds_per_trial, tdpt_batch_tune_report *out);
 /* Driver of a batch.  By default (-1) tdpt_batch_run uses the persistent
@@ -449,8 +465,8 @@ int tdpt_batch_autotune(tdpt_batch *batch, int32_t rounds_per_trial, tdpt_batch_
  * their own mailboxes -- whenever every member allows it (int8 layout,
  * persistent driver not switched off) and each group's workgroups fit the
  * GPU together, unless every member is a replica of the kind that runs
- * per-round launches on its own (tdpt_problem_run: packed several per
- * workgroup, structure held in registers, rounds of 16 sweeps or more);
+ * per-round launches on its own (tdpt_problem_run: structure held in
+ * registers, rounds of 16 sweeps or more);
  * otherwise one sweep launch per group and one swap launch per round.  0
  * forces the per-round launches.  Results are the same either way.  tdpt_batch_query_driver reports the current choice (1 persistent). */
 int tdpt_batch_set_driver(tdpt_batch *batch, int32_t driver);

@@ -71,6 +71,7 @@ struct DevProblem {
     int32_t block;      // threads per sweep workgroup
     int32_t rpb;        // per-round driver, int8: > 1 packs rpb slots per workgroup
     int32_t lshift;     // of 2^lshift lanes each (rpb << lshift threads)
+    int32_t spin;       // packed sweep with one spin per lane (4 lanes per quad)
     int32_t bits;       // bit-packed layout
     int32_t n_words;    // 32-bit words per replica in the bit-packed layout
     int32_t bit_start[kMaxColors + 1];
@@ -152,11 +153,12 @@ hipError_t launch_scratch_reset(const DevProblem &p, hipStream_t s);
 hipError_t launch_finalize(const DevProblem &p, int64_t n_rounds, hipStream_t s);
 // Batched rounds over a device table of problems sharing p's layout (p is
 // any member: it selects the kernel instance).  rpb slots per workgroup of
-// `block` threads, 2^lshift lanes each (rpb << lshift == block) when rpb > 1;
-// first_block then counts ceil(R / rpb) workgroups per member.
+// `block` threads, 2^lshift lanes each (rpb << lshift == block) when rpb > 1
+// or spin (one spin per lane, 2^lshift >= 4); first_block then counts
+// ceil(R / rpb) workgroups per member.
 hipError_t launch_batch_sweep(const DevProblem &p, const DevProblem *table, const int *first_block,
                               int count, int blocks, int block, size_t max_stride, int rpb, int lshift,
-                              hipStream_t s);
+                              int spin, hipStream_t s);
 hipError_t launch_batch_swap(const DevProblem *table, int count, hipStream_t s);
 // Batched persistent driver over one layout group of count members whose
 // block ranges (prefix sums in first_block) cover `blocks` workgroups; lds is

@@ -229,6 +229,10 @@ struct QuadS {
     int voff;    // byte offset of the quad in a structure row
 };
 
+// Layouts the packed-slot sweeps may run with one spin per lane.
+template <int NARROW, int WD>
+constexpr bool kSpinLanes = NARROW == kPacked && WD >= 2 && WD <= 8;
+
 // Layouts whose structure the packed-slot sweeps may hold in registers.
 template <int NARROW, int WD>
 constexpr bool kHoistable = NARROW == kPacked && WD <= 4;
@@ -564,6 +568,130 @@ __device__ __forceinline__ void sweep_phases(const DevProblem &P, const Rsrc &Rs
     }
 }
 
+__device__ __forceinline__ int bload1(const __amdgpu_buffer_rsrc_t &r, int voff, int soff)
+{
+    return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+}
+
+// Structure of one spin in the packed copy-edge layout (K = WD / 2 pairs).
+template <int WD>
+struct SpinS {
+    int a[WD / 2], b[WD / 2], ch, bias;
+};
+
+template <int WD>
+__device__ __forceinline__ void load_spin(const DevProblem &P, const Rsrc &Rs, int i, SpinS<WD> &S)
+{
+    const int voff = i * 4, row = P.n_pad * 4;
+#pragma unroll
+    for (int k = 0; k < WD / 2; ++k) {
+        S.a[k] = bload1(Rs.a, voff, k * row);
+        S.b[k] = bload1(Rs.b, voff, k * row);
+    }
+    S.ch = bload1(Rs.ch, voff, 0);
+    S.bias = P.has_bias ? bload1(Rs.bias, voff, 0) : 0;
+}
+
+// One spin per lane: lanes 4m..4m+3 of a replica's lane group take the 4
+// spins of one quad; each computes the quad's Philox words and uses its own
+// (the same word, field and decision as the quad-per-lane update, so the
+// same trajectory).  A quarter of the fields, heat-bath decisions and
+// gathers per lane shortens each colour phase when the replica's lanes are
+// latency-bound (few replicas on the GPU); the Philox work is repeated 4
+// times, so it loses when the GPU is full.
+template <int WD>
+__device__ __forceinline__ void spin_update(const DevProblem &P, lds8_t *s, int q, int j, const SpinS<WD> &S,
+                                            int live_end, uint32_t t, const SlotParams &sp, uint32_t key0,
+                                            uint32_t key1, int &dfa, int &dga)
+{
+    uint32_t u[4] = {(uint32_t)q, t, sp.pos, 0u};
+    philox10(u[0], u[1], u[2], u[3], key0, key1);
+    const uint32_t uj = j == 0 ? u[0] : j == 1 ? u[1] : j == 2 ? u[2] : u[3];
+    const int i = 4 * q + j;
+    int8_t lo[WD / 2], hi[WD / 2];
+#pragma unroll
+    for (int k = 0; k < WD / 2; ++k) {
+        lo[k] = s[S.a[k] & 0xffff];
+        hi[k] = s[(unsigned)S.a[k] >> 16];
+    }
+    const int8_t c0 = s[S.ch & 0xffff], c1 = s[(unsigned)S.ch >> 16];
+    const int8_t old = s[i];
+    int hp = S.bias;
+#pragma unroll
+    for (int k = 0; k < WD / 2; ++k) {
+        v2s sv, jv;
+        sv.x = lo[k];
+        sv.y = hi[k];
+        jv.x = (short)(S.b[k] & 0xffff);
+        jv.y = (short)((unsigned)S.b[k] >> 16);
+        hp = __builtin_amdgcn_sdot2(jv, sv, hp, false);
+    }
+    const int cs = (int)c0 + (int)c1;
+    const int hh = __mul24(sp.twoP, cs) + hp;
+    bool amb;
+    bool up = heat_bath_up(hh, sp.cb, uj, amb);
+    const bool live = i < live_end;
+    if (__builtin_expect(amb && live, 0)) up = heat_bath_exact(sp.beta, hh, uj) > 0;
+    const int nw = live ? (up ? 1 : -1) : 0;
+    s[i] = (int8_t)nw;
+    const int ds = nw - (int)old;
+    dfa -= __mul24(ds, hp);
+    dga -= __mul24(ds, cs);
+}
+
+// The class phases of a round with one spin per lane (lanes a multiple of
+// 4); with two colour classes of at most lanes / 4 quads, each lane holds its
+// two spins' structure in registers for the round.
+template <int NARROW, int WD>
+__device__ __forceinline__ void sweep_phases_spin(const DevProblem &P, const Rsrc &Rs, lds8_t *s,
+                                                  const SlotParams &sp, int64_t n_round, int lane, int lanes,
+                                                  int64_t &df, int64_t &dg)
+{
+    if constexpr (NARROW == kPacked && WD >= 2 && WD <= 8) {
+        const int mcs = P.mcs, n_colors = P.n_colors;
+        const uint32_t key0 = P.key0, key1 = P.key1;
+        const int j = lane & 3, ql = lane >> 2, qn = lanes >> 2;
+        const int qa = P.cls_start[0] >> 2, qb = P.cls_start[1] >> 2, qc = P.cls_start[2] >> 2;
+        if (n_colors == 2 && qb - qa <= qn && qc - qb <= qn) {
+            SpinS<WD> SS[2];
+            const int qq[2] = {qa + ql, qb + ql};
+            const bool has[2] = {qq[0] < qb, qq[1] < qc};
+            const int live_end[2] = {P.cls_live[0], P.cls_live[1]};
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                if (has[c]) load_spin<WD>(P, Rs, 4 * qq[c] + j, SS[c]);
+            for (int k = 0; k < mcs; ++k) {
+                const uint32_t t = (uint32_t)((n_round - 1) * mcs + k);
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    int dfa = 0, dga = 0;
+                    if (has[c]) spin_update<WD>(P, s, qq[c], j, SS[c], live_end[c], t, sp, key0, key1, dfa, dga);
+                    df += dfa;
+                    dg += 2 * (int64_t)dga;
+                    if (k + 1 < mcs || c == 0) __syncthreads();
+                }
+            }
+            return;
+        }
+        for (int k = 0; k < mcs; ++k) {
+            const uint32_t t = (uint32_t)((n_round - 1) * mcs + k);
+            for (int c = 0; c < n_colors; ++c) {
+                const int q0 = P.cls_start[c] >> 2, q1 = P.cls_start[c + 1] >> 2;
+                const int live_end = P.cls_live[c];
+                int dfa = 0, dga = 0;
+                for (int q = q0 + ql; q < q1; q += qn) {
+                    SpinS<WD> S;
+                    load_spin<WD>(P, Rs, 4 * q + j, S);
+                    spin_update<WD>(P, s, q, j, S, live_end, t, sp, key0, key1, dfa, dga);
+                }
+                df += dfa;
+                dg += 2 * (int64_t)dga;
+                if (k + 1 < mcs || c + 1 < n_colors) __syncthreads();
+            }
+        }
+    }
+}
+
 template <int NARROW, int WD, typename AtEnd>
 __device__ __forceinline__ void sweep_round(const DevProblem &P, const Rsrc &Rs, lds8_t *s,
                                             const SlotParams &sp, int64_t n_round, int64_t *red,
@@ -655,7 +783,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch_sweep(const DevProblem *__r
 // still take every barrier.  The same updates, in the same order per slot,
 // as round_sweep_body.
 template <int NARROW, int WD>
-__device__ __forceinline__ void multi_round_body(const DevProblem &P, int slot0, int rpb, int lshift, int8_t *lds)
+__device__ __forceinline__ void multi_round_body(const DevProblem &P, int slot0, int rpb, int lshift, int spin,
+                                                 int8_t *lds)
 {
     if (!replica_at_zero(lds)) {
         if (threadIdx.x == 0)
@@ -676,8 +805,12 @@ __device__ __forceinline__ void multi_round_body(const DevProblem &P, int slot0,
     __syncthreads();
     int64_t df = 0, dg = 0;
     // a skipped group starts past every class, so it takes the barriers only
-    sweep_phases<NARROW, WD, true>(P, Rs, replica_lds() + sub * P.stride, sp, n_round, live ? lane : (1 << 30),
-                                   1 << lshift, df, dg);
+    if (kSpinLanes<NARROW, WD> && spin)
+        sweep_phases_spin<NARROW, WD>(P, Rs, replica_lds() + sub * P.stride, sp, n_round,
+                                      live ? lane : (1 << 30), 1 << lshift, df, dg);
+    else
+        sweep_phases<NARROW, WD, true>(P, Rs, replica_lds() + sub * P.stride, sp, n_round,
+                                       live ? lane : (1 << 30), 1 << lshift, df, dg);
     // sum over each group: within its wave segment, then across its waves
     const int seg = lshift < 6 ? (1 << lshift) : 64;
     for (int off = seg >> 1; off > 0; off >>= 1) {
@@ -702,7 +835,7 @@ template <int NARROW, int WD>
 __global__ __launch_bounds__(kMultiBlock, 2) void k_round_sweep_multi(DevProblem P)
 {
     extern __shared__ __align__(16) int8_t lds[];
-    multi_round_body<NARROW, WD>(P, blockIdx.x * P.rpb, P.rpb, P.lshift, lds);
+    multi_round_body<NARROW, WD>(P, blockIdx.x * P.rpb, P.rpb, P.lshift, P.spin, lds);
 }
 
 // Batched round with rpb slots per workgroup: first_block is the prefix sum
@@ -710,7 +843,7 @@ __global__ __launch_bounds__(kMultiBlock, 2) void k_round_sweep_multi(DevProblem
 template <int NARROW, int WD>
 __global__ __launch_bounds__(kMultiBlock, 2) void k_batch_sweep_multi(const DevProblem *__restrict__ table,
                                                                const int *__restrict__ first_block, int count,
-                                                               int rpb, int lshift)
+                                                               int rpb, int lshift, int spin)
 {
     extern __shared__ __align__(16) int8_t lds[];
     const int b = blockIdx.x;
@@ -720,7 +853,7 @@ __global__ __launch_bounds__(kMultiBlock, 2) void k_batch_sweep_multi(const DevP
         if (first_block[mid] <= b) lo = mid;
         else hi = mid - 1;
     }
-    multi_round_body<NARROW, WD>(table[lo], (b - first_block[lo]) * rpb, rpb, lshift, lds);
+    multi_round_body<NARROW, WD>(table[lo], (b - first_block[lo]) * rpb, rpb, lshift, spin, lds);
 }
 
 __device__ __forceinline__ bool metropolis(double x, double u)
@@ -1697,7 +1830,7 @@ static hipError_t allow_lds(K kernel, size_t lds)
 template <int NARROW, int WD>
 static hipError_t round_sweep_t(const DevProblem &p, hipStream_t s)
 {
-    if (p.rpb > 1) {
+    if (p.rpb > 1 || p.spin) {
         const size_t lds = (size_t)p.rpb * p.stride + 16 * (size_t)p.rpb + 16;
         hipError_t e = allow_lds(k_round_sweep_multi<NARROW, WD>, lds);
         if (e != hipSuccess) return e;
@@ -1797,7 +1930,9 @@ static hipError_t persistent_t(const DevProblem &p, int64_t n_rounds, hipStream_
 
 hipError_t launch_sweep(const DevProblem &p, hipStream_t s)
 {
-    if (p.rpb > 1 && (p.lshift < 0 || (p.rpb << p.lshift) > kMultiBlock)) return hipErrorInvalidValue;
+    if ((p.rpb > 1 || p.spin) &&
+        (p.rpb < 1 || p.lshift < 0 || (p.rpb << p.lshift) > kMultiBlock || (p.spin && p.lshift < 2)))
+        return hipErrorInvalidValue;
     TDPT_DISPATCH(round_sweep_t, p, s)
 }
 
@@ -1810,15 +1945,15 @@ hipError_t launch_swap(const DevProblem &p, hipStream_t s)
 template <int NARROW, int WD>
 static hipError_t batch_sweep_t(const DevProblem &p, const DevProblem *table, const int *first_block,
                                 int count, int blocks, int block, size_t max_stride, int rpb, int lshift,
-                                hipStream_t s)
+                                int spin, hipStream_t s)
 {
     (void)p;
-    if (rpb > 1) {
+    if (rpb > 1 || spin) {
         const size_t lds = (size_t)rpb * max_stride + 16 * (size_t)rpb + 16;
         hipError_t e = allow_lds(k_batch_sweep_multi<NARROW, WD>, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_batch_sweep_multi<NARROW, WD>), dim3(blocks), dim3(block), lds, s, table,
-                           first_block, count, rpb, lshift);
+                           first_block, count, rpb, lshift, spin);
         return hipGetLastError();
     }
     const size_t lds = max_stride + 8 * (2 + 2 * (kMaxBlock / 64) + 3) + 16;
@@ -1831,11 +1966,12 @@ static hipError_t batch_sweep_t(const DevProblem &p, const DevProblem *table, co
 
 hipError_t launch_batch_sweep(const DevProblem &p, const DevProblem *table, const int *first_block,
                               int count, int blocks, int block, size_t max_stride, int rpb, int lshift,
-                              hipStream_t s)
+                              int spin, hipStream_t s)
 {
-    if (rpb < 1 || (rpb > 1 && (lshift < 0 || (rpb << lshift) != block || block > kMultiBlock)))
+    if (rpb < 1 || ((rpb > 1 || spin) && (lshift < 0 || (rpb << lshift) != block || block > kMultiBlock)) ||
+        (spin && lshift < 2))
         return hipErrorInvalidValue;
-    TDPT_DISPATCH(batch_sweep_t, p, table, first_block, count, blocks, block, max_stride, rpb, lshift, s)
+    TDPT_DISPATCH(batch_sweep_t, p, table, first_block, count, blocks, block, max_stride, rpb, lshift, spin, s)
 }
 
 static size_t bits_lds(int n_words)

@@ -335,6 +335,38 @@ bool pack_hoists(const tdpt::DevProblem &d, int max_quads, int lshift)
 }
 constexpr int kPackRoundMcs = 16;  // sweeps per round from which packed per-round launches are preferred
 
+// Shape of the packed sweep with one spin per lane (packed copy-edge layout,
+// at most 8 problem neighbours): 2^lshift lanes, the power of two (>= 4,
+// <= 256) covering the largest colour class's spins, so a lane takes one
+// spin per phase; 64 / 2^lshift replicas per 64-thread workgroup below 64
+// lanes, else one.  False when the replica does not qualify.
+bool spin_shape(bool narrow, bool gen, bool bits, int wd, int max_quads, size_t stride, int32_t *rpb,
+                int32_t *lshift)
+{
+    if (!narrow || gen || bits || wd > 8 || max_quads < 1 || 4 * max_quads > tdpt::kMultiBlock) return false;
+    int ls = 2;
+    while ((1 << ls) < 4 * max_quads) ++ls;
+    const int r = std::max(1, 64 >> ls);
+    if (!pack_fits(stride, r)) return false;
+    *rpb = r;
+    *lshift = ls;
+    return true;
+}
+
+// Waves of one round of R replicas at rpb replicas per workgroup of
+// rpb << lshift threads.
+int64_t round_waves(int R, int rpb, int lshift)
+{
+    return (int64_t)((R + rpb - 1) / rpb) * std::max(1, (rpb << lshift) / 64);
+}
+
+// Up to this many waves per round (two per SIMD) the replicas' lanes are
+// latency-bound and the spin-per-lane sweep is the default; beyond it the
+// GPU is full and the quad-per-lane sweep, a quarter of the Philox work,
+// is (N=12 batches, 50 sweeps per round: spin / quad 34 / 45 us per round
+// at 32 problems = 1024 waves, 42 / 49 at 64, 53 / 50 at 96).
+constexpr int64_t kSpinWaves = 2048;
+
 // Fewest lanes per replica that keep every lane's per-phase sums of 2 |h|
 // (f) and 2 |c| (g) over its quads below 2^31, for the largest penalty of
 // the configuration (c is the half penalty field, which P = 0 leaves out of
@@ -855,7 +887,20 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     d.block = bits ? sweep_block(in, false, tdpt::bits_block_cap(cfg->mcs_per_swap)) : sweep_block(in, false);
     d.rpb = 1;
     d.lshift = 0;
+    d.spin = 0;
     if (!bits) default_pack(in->max_class_quads, p->min_lanes, L.stride, &d.rpb, &d.lshift);
+    {
+        // a problem alone is latency-bound unless its replicas fill the GPU
+        int32_t r = 1, ls = 0;
+        const char *es = getenv("TDPT_SPIN");
+        if (!(es && es[0] == '0') &&
+            spin_shape(narrow, in->gen != 0, bits, L.wd, in->max_class_quads, L.stride, &r, &ls) &&
+            (round_waves(R, r, ls) <= kSpinWaves || (es && es[0] == '1'))) {
+            d.rpb = r;
+            d.lshift = ls;
+            d.spin = 1;
+        }
+    }
     d.bits = bits ? 1 : 0;
     d.n_words = n_words;
     for (int c = 0; c <= in->n_colors; ++c) d.bit_start[c] = bit_start[c];
@@ -1062,7 +1107,7 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     // small bipartite replicas whose structure the packed per-round sweep
     // holds in registers run that driver when rounds are long enough
     // (TDPT_PERSISTENT=1 asks for the persistent driver wherever it fits)
-    const bool prefer_round = d.rpb > 1 && pack_hoists(d, in->max_class_quads, d.lshift) &&
+    const bool prefer_round = ((d.spin && d.n_colors == 2) || (d.rpb > 1 && pack_hoists(d, in->max_class_quads, d.lshift))) &&
                               cfg->mcs_per_swap >= kPackRoundMcs && !(pe && pe[0] == '1');
     if (p->persistent_ok && !prefer_round) {
         tdpt::DevProblem dq = d;
@@ -1213,7 +1258,7 @@ int tdpt_problem_autotune(tdpt_problem *p, int32_t rounds_per_trial, tdpt_tune_r
     // candidates: (driver, threads per workgroup, slots per workgroup, log2
     // of lanes per slot)
     struct Cand {
-        int first, second, rpb, lshift;
+        int first, second, rpb, lshift, spin;
     };
     std::vector<Cand> cand;
     const int cap = p->dp.bits ? tdpt::bits_block_cap(p->mcs) : tdpt::kMaxBlock;
@@ -1225,7 +1270,7 @@ int tdpt_problem_autotune(tdpt_problem *p, int32_t rounds_per_trial, tdpt_tune_r
     if (std::find(per_round.begin(), per_round.end(), bal) == per_round.end()) per_round.push_back(bal);
     std::sort(per_round.begin(), per_round.end());
     for (int b : per_round)
-        if (b >= p->min_block && b <= cap && b <= std::max(64, (quads + 63) / 64 * 64)) cand.push_back({0, b, 1, 0});
+        if (b >= p->min_block && b <= cap && b <= std::max(64, (quads + 63) / 64 * 64)) cand.push_back({0, b, 1, 0, 0});
     // int8 replicas of a small largest class: several per workgroup of 64,
     // 128 or 256 threads, one to four passes over the class
     if (!p->dp.bits)
@@ -1233,7 +1278,15 @@ int tdpt_problem_autotune(tdpt_problem *p, int32_t rounds_per_trial, tdpt_tune_r
             const int lanes = 1 << ls;
             if (lanes < p->min_lanes || 4 * lanes < quads || (ls > 0 && lanes / 2 >= quads)) continue;
             for (int blk : {64, 128, 256})
-                if (pack_fits(p->stride_bytes, blk >> ls)) cand.push_back({0, blk, blk >> ls, ls});
+                if (pack_fits(p->stride_bytes, blk >> ls)) cand.push_back({0, blk, blk >> ls, ls, 0});
+        }
+    // one spin per lane: one or two passes over the largest class
+    if (p->dp.narrow && !p->dp.gen && !p->dp.bits && p->dp.wd <= 8)
+        for (int ls = 2; ls <= 8; ++ls) {
+            const int lanes = 1 << ls;
+            if (lanes < 2 * quads || (ls > 2 && lanes / 2 >= 4 * quads)) continue;
+            const int blk = std::max(64, lanes);
+            if (blk <= tdpt::kMultiBlock && pack_fits(p->stride_bytes, blk >> ls)) cand.push_back({0, blk, blk >> ls, ls, 1});
         }
     if (p->persistent_ok) {
         for (int b = 64; b <= tdpt::kMaxBlock / 2; b += 64) {
@@ -1242,7 +1295,7 @@ int tdpt_problem_autotune(tdpt_problem *p, int32_t rounds_per_trial, tdpt_tune_r
             dq.block = b;
             int max_blocks = 0;
             HIP_TRY(tdpt::persistent_max_blocks(dq, &max_blocks), "occupancy query");
-            if (max_blocks >= p->R) cand.push_back({1, b, 1, 0});
+            if (max_blocks >= p->R) cand.push_back({1, b, 1, 0, 0});
         }
     }
     if (cand.empty()) return fail(TDPT_E_INVALID, "no launch shape satisfies the problem's bounds");
@@ -1255,7 +1308,7 @@ int tdpt_problem_autotune(tdpt_problem *p, int32_t rounds_per_trial, tdpt_tune_r
     rc = tdpt_problem_save(p, saved.data(), &bytes);
     if (rc) return rc;
     const bool old_persistent = p->persistent;
-    const int old_block = p->dp.block, old_rpb = p->dp.rpb, old_lshift = p->dp.lshift;
+    const int old_block = p->dp.block, old_rpb = p->dp.rpb, old_lshift = p->dp.lshift, old_spin = p->dp.spin;
     const int32_t old_every = p->time_every;
     p->time_every = 0;
     memset(out, 0, sizeof(*out));
@@ -1263,9 +1316,10 @@ int tdpt_problem_autotune(tdpt_problem *p, int32_t rounds_per_trial, tdpt_tune_r
     int best_i = -1;
     for (size_t i = 0; i < cand.size() && rc == TDPT_OK; ++i) {
         p->persistent = cand[i].first == 1;
-        p->dp.block = cand[i].rpb > 1 ? old_block : cand[i].second;
+        p->dp.block = cand[i].rpb > 1 || cand[i].spin ? old_block : cand[i].second;
         p->dp.rpb = cand[i].rpb;
         p->dp.lshift = cand[i].lshift;
+        p->dp.spin = cand[i].spin;
         rc = tdpt_problem_run(p, 1);  // warm-up
         double ms = 0.0;
         if (rc == TDPT_OK)
@@ -1275,6 +1329,7 @@ int tdpt_problem_autotune(tdpt_problem *p, int32_t rounds_per_trial, tdpt_tune_r
         out->trial_driver[i] = cand[i].first;
         out->trial_block[i] = cand[i].second;
         out->trial_slots[i] = cand[i].rpb;
+        out->trial_spin[i] = cand[i].spin;
         out->trial_ms_per_round[i] = per;
         out->n_trials = (int32_t)i + 1;
         if (per < best) {
@@ -1288,16 +1343,19 @@ int tdpt_problem_autotune(tdpt_problem *p, int32_t rounds_per_trial, tdpt_tune_r
         p->dp.block = old_block;
         p->dp.rpb = old_rpb;
         p->dp.lshift = old_lshift;
+        p->dp.spin = old_spin;
         (void)tdpt_problem_load(p, saved.data(), saved.size());
         return rc ? rc : fail(TDPT_E_DEVICE, "autotune timed nothing");
     }
     p->persistent = cand[best_i].first == 1;
-    p->dp.block = cand[best_i].rpb > 1 ? old_block : cand[best_i].second;
+    p->dp.block = cand[best_i].rpb > 1 || cand[best_i].spin ? old_block : cand[best_i].second;
     p->dp.rpb = cand[best_i].rpb;
     p->dp.lshift = cand[best_i].lshift;
+    p->dp.spin = cand[best_i].spin;
     out->driver = cand[best_i].first;
     out->block = cand[best_i].second;
     out->slots = cand[best_i].rpb;
+    out->spin = cand[best_i].spin;
     out->ms_per_round = best;
     return tdpt_problem_load(p, saved.data(), saved.size());
 }
@@ -1324,6 +1382,7 @@ int tdpt_problem_query(tdpt_problem *p, tdpt_status *out)
     out->rounds_done = h[tdpt::kHdrRounds];
     out->driver = p->persistent ? 1 : 0;
     out->slots = p->persistent ? 1 : std::max(p->dp.rpb, 1);
+    out->spin = p->persistent ? 0 : p->dp.spin;
     out->sweeps_done = h[tdpt::kHdrRounds] * p->mcs;
     out->first_hit_sweep = h[tdpt::kHdrFirstHit];
     out->best_f_q = h[tdpt::kHdrBestF];
@@ -1495,14 +1554,26 @@ int tdpt_layout_get(const tdpt_instance *in, const tdpt_run_cfg *cfg, tdpt_layou
     out->general = in->gen ? 1 : 0;
     out->ell_width = L.wd;
     out->group_key = GroupKey{out->bits, out->narrow, (narrow && in->gen) ? 1 : 0, L.wd}.code();
-    // the per-round sweep's default packing, as tdpt_problem_create sets it
-    int32_t rpb = 1, lshift = 0;
+    // the per-round sweep's default shape, as tdpt_problem_create sets it
+    // (without its environment overrides)
+    int32_t rpb = 1, lshift = 0, srpb = 1, sls = 0;
     if (!out->bits)
         default_pack(in->max_class_quads, min_lanes_for(in, cfg->p_q[cfg->n_p - 1]), L.stride, &rpb, &lshift);
+    const int R = cfg->n_beta * cfg->n_p;
+    out->spin = spin_shape(narrow, in->gen != 0, out->bits != 0, L.wd, in->max_class_quads, L.stride, &srpb, &sls) &&
+                        round_waves(R, srpb, sls) <= kSpinWaves
+                    ? 1
+                    : 0;
+    if (out->spin) {
+        rpb = srpb;
+        lshift = sls;
+    }
     out->slots = rpb;
-    out->lanes = rpb > 1 ? 1 << lshift : 0;
-    out->held = rpb > 1 && pack_hoists(narrow, in->gen != 0, out->bits != 0, in->has_bias != 0, L.wd,
-                                       in->n_colors, in->max_class_quads, lshift)
+    out->lanes = rpb > 1 || out->spin ? 1 << lshift : 0;
+    out->held = (out->spin && in->n_colors == 2) ||
+                        (!out->spin && rpb > 1 &&
+                         pack_hoists(narrow, in->gen != 0, out->bits != 0, in->has_bias != 0, L.wd, in->n_colors,
+                                     in->max_class_quads, lshift))
                     ? 1
                     : 0;
     out->per_round = out->held && cfg->mcs_per_swap >= kPackRoundMcs ? 1 : 0;
@@ -1627,6 +1698,7 @@ struct tdpt_batch {
         // workgroup of rpb << lshift threads (block then applies to the
         // persistent driver only)
         int rpb = 1, lshift = 0;
+        int spin = 0;       // packed sweep with one spin per lane (rpb may then be 1)
         int replicas = 0;   // slots of all members (workgroups of the persistent driver)
         int max_quads = 0;  // largest colour class of any member, in quads
         int min_lanes = 1;  // fewest lanes per slot the members' per-phase bounds allow
@@ -1762,9 +1834,10 @@ static int batch_decide_mode(tdpt_batch *b)
     // rounds long enough: per-round launches (as for one such problem)
     bool prefer_round = !b->groups.empty();
     for (const auto &g : b->groups) {
-        prefer_round = prefer_round && g.rpb > 1 && g.min_mcs >= kPackRoundMcs;
+        prefer_round = prefer_round && (g.rpb > 1 || g.spin) && g.min_mcs >= kPackRoundMcs;
         for (int k = g.first_member; prefer_round && k < g.first_member + g.count; ++k)
-            prefer_round = pack_hoists(b->members[k]->dp, b->members[k]->max_class_quads, g.lshift);
+            prefer_round = g.spin ? b->members[k]->dp.n_colors == 2 && 4 * b->members[k]->max_class_quads <= (1 << g.lshift)
+                                  : pack_hoists(b->members[k]->dp, b->members[k]->max_class_quads, g.lshift);
     }
     const char *pe = getenv("TDPT_PERSISTENT");
     if (pe && pe[0] == '1') prefer_round = false;
@@ -1789,28 +1862,50 @@ static int batch_decide_mode(tdpt_batch *b)
 // when its largest colour class takes under 64 lanes, one wave of 64 holds
 // 64 / L slots, L the power of two covering that class (and the members'
 // per-phase bounds); larger replicas keep one slot per workgroup.
-static void batch_default_pack(tdpt_batch::Group &g, bool bits)
+// Default shape of a group's per-round sweep: one spin per lane while the
+// whole batch's round stays within kSpinWaves waves (latency-bound), else
+// several replicas per workgroup at one quad per lane (default_pack).
+static void batch_default_pack(tdpt_batch *b, tdpt_batch::Group &g)
 {
+    const tdpt::DevProblem &d0 = b->members[g.first_member]->dp;
     g.rpb = 1;
     g.lshift = 0;
-    if (bits) return;
+    g.spin = 0;
+    if (d0.bits) return;
+    const char *es = getenv("TDPT_BATCH_SPIN");
+    const bool spin_ok = !(es && es[0] == '0') && d0.narrow && !d0.gen && d0.wd <= 8;
     if (const char *e = getenv("TDPT_BATCH_LANES")) {
         // test hook: lanes per slot (a power of two); the workgroup then holds
-        // max(block, lanes) / lanes slots, block from TDPT_BATCH_BLOCK or 64
+        // max(block, lanes) / lanes slots, block from TDPT_BATCH_BLOCK or 64;
+        // TDPT_BATCH_SPIN=1 makes it one spin per lane (lanes >= 4)
         const int v = atoi(e);
         int ls = 0;
         while ((1 << ls) < v) ++ls;
-        if (v >= 1 && (1 << ls) == v && v >= g.min_lanes && v <= tdpt::kMaxBlock / 2) {
+        const bool spin = es && es[0] == '1' && spin_ok;
+        const int need = spin ? std::max(4, 4 * g.min_lanes) : g.min_lanes;
+        if (v >= 1 && (1 << ls) == v && v >= need && v <= tdpt::kMultiBlock) {
             const char *eb = getenv("TDPT_BATCH_BLOCK");
             const int blk = std::max(eb ? atoi(eb) : 64, v);
-            if (blk % v == 0 && blk / v >= 2 && blk <= tdpt::kMultiBlock && pack_fits(g.max_stride, blk / v)) {
-                g.rpb = blk / v;
+            const int r = blk / v;
+            if (blk % v == 0 && (r >= 2 || spin) && blk <= tdpt::kMultiBlock && pack_fits(g.max_stride, r)) {
+                g.rpb = r;
                 g.lshift = ls;
+                g.spin = spin ? 1 : 0;
             }
         }
         return;
     }
     default_pack(g.max_quads, g.min_lanes, g.max_stride, &g.rpb, &g.lshift);
+    int32_t r = 1, ls = 0;
+    if (spin_ok && spin_shape(true, false, false, d0.wd, g.max_quads, g.max_stride, &r, &ls)) {
+        int64_t waves = 0;
+        for (const auto *m : b->members) waves += round_waves(m->R, r, ls);
+        if (waves <= kSpinWaves) {
+            g.rpb = r;
+            g.lshift = ls;
+            g.spin = 1;
+        }
+    }
 }
 
 // n_rounds rounds of every member through the persistent driver.
@@ -1868,8 +1963,9 @@ static int enqueue_batch_round(tdpt_batch *b, hipStream_t s)
         hipError_t e = d0.bits ? tdpt::launch_batch_sweep_bits(d0, table + g.first_member, prefix + g.prefix_off,
                                                                g.count, g.blocks, g.block, g.max_words, g.min_mcs, gs)
                                : tdpt::launch_batch_sweep(d0, table + g.first_member, prefix + g.prefix_off,
-                                                          g.count, g.blocks, g.rpb > 1 ? g.rpb << g.lshift : g.block,
-                                                          g.max_stride, g.rpb, g.lshift, gs);
+                                                          g.count, g.blocks,
+                                                          g.rpb > 1 || g.spin ? g.rpb << g.lshift : g.block,
+                                                          g.max_stride, g.rpb, g.lshift, g.spin, gs);
         if (e != hipSuccess) return hip_fail(e, "launch batch sweep");
     }
     for (int k = 0; k < n_aux; ++k) {
@@ -2018,7 +2114,6 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
             for (int k = g.first_member; k < g.first_member + g.count; ++k) def = std::max(def, m[k]->dp.block);
         }
         g.block = std::min(std::max(def, g.min_block), cap);
-        batch_default_pack(g, m[g.first_member]->dp.bits != 0);
     }
     // members that move here from another batch leave it first
     for (auto *p : m)
@@ -2027,6 +2122,7 @@ int tdpt_batch_set_members(tdpt_batch *b, tdpt_problem *const *probs, int32_t co
     b->groups = groups;
     b->tuned_per_round = false;
     b->prefix_host.clear();
+    for (auto &g : b->groups) batch_default_pack(b, g);
     // the persistent driver when every group fits at once (with the members'
     // own workgroup sizes), else per-round launches with the batch default
     {
@@ -2145,7 +2241,7 @@ int tdpt_batch_autotune(tdpt_batch *b, int32_t rounds_per_trial, tdpt_batch_tune
     // 2^lshift lanes in per-round workgroups of 64, 128 or 256 threads, from
     // 4 passes over the largest class down to one
     struct Cand {
-        int block, rpb, lshift;
+        int block, rpb, lshift, spin;
     };
     std::vector<bool> packed(b->groups.size(), false);
     auto any_packed = [&]() { return std::find(packed.begin(), packed.end(), true) != packed.end(); };
@@ -2155,24 +2251,35 @@ int tdpt_batch_autotune(tdpt_batch *b, int32_t rounds_per_trial, tdpt_batch_tune
         const int cap = bits ? tdpt::bits_block_cap(g.min_mcs) : tdpt::kMaxBlock;
         std::vector<Cand> cands;
         for (int sz : sizes)
-            if (sz >= g.min_block && sz <= cap) cands.push_back({sz, 1, 0});
+            if (sz >= g.min_block && sz <= cap) cands.push_back({sz, 1, 0, 0});
         if (!bits)
             for (int ls = 0; ls <= 5; ++ls) {
                 const int lanes = 1 << ls;
                 if (lanes < g.min_lanes || 4 * lanes < g.max_quads || (ls > 0 && lanes / 2 >= g.max_quads)) continue;
                 for (int blk : {64, 128, 256})
-                    if (pack_fits(g.max_stride, blk >> ls)) cands.push_back({blk, blk >> ls, ls});
+                    if (pack_fits(g.max_stride, blk >> ls)) cands.push_back({blk, blk >> ls, ls, 0});
+            }
+        // one spin per lane: one or two passes over the largest class
+        const tdpt::DevProblem &d0 = b->members[g.first_member]->dp;
+        if (!bits && d0.narrow && !d0.gen && d0.wd <= 8)
+            for (int ls = 2; ls <= 8; ++ls) {
+                const int lanes = 1 << ls;
+                if (lanes < 2 * g.max_quads || lanes < 4 * g.min_lanes || (ls > 2 && lanes / 2 >= 4 * g.max_quads))
+                    continue;
+                const int blk = std::max(64, lanes);
+                if (blk <= tdpt::kMultiBlock && pack_fits(g.max_stride, blk >> ls)) cands.push_back({blk, blk >> ls, ls, 1});
             }
         double best = 1e300;
-        Cand best_c{g.block, g.rpb, g.lshift};
+        Cand best_c{g.block, g.rpb, g.lshift, g.spin};
         bool best_packed = packed[gi];
         const int keep_block = g.block;
         for (const Cand &c : cands) {
             if (out->n_trials >= 128) break;
-            g.block = c.rpb > 1 ? keep_block : c.block;
+            g.block = c.rpb > 1 || c.spin ? keep_block : c.block;
             g.rpb = c.rpb;
             g.lshift = c.lshift;
-            packed[gi] = c.rpb > 1;
+            g.spin = c.spin;
+            packed[gi] = c.rpb > 1 || c.spin;
             b->tuned_per_round = any_packed();
             rc = batch_decide_mode(b);
             if (rc) break;
@@ -2186,19 +2293,22 @@ int tdpt_batch_autotune(tdpt_batch *b, int32_t rounds_per_trial, tdpt_batch_tune
             out->trial_group[t] = (int32_t)gi;
             out->trial_block[t] = c.block;
             out->trial_slots[t] = c.rpb;
+            out->trial_spin[t] = c.spin;
             out->trial_ms_per_round[t] = per;
             if (per < best) {
                 best = per;
                 best_c = c;
-                best_packed = c.rpb > 1;
+                best_packed = c.rpb > 1 || c.spin;
             }
         }
         g.block = best_packed ? keep_block : best_c.block;
         g.rpb = best_c.rpb;
         g.lshift = best_c.lshift;
+        g.spin = best_c.spin;
         packed[gi] = best_packed;
         out->group_block[gi] = best_c.block;
         out->group_slots[gi] = best_c.rpb;
+        out->group_spin[gi] = best_c.spin;
         out->group_ms_per_round[gi] = best;
     }
     b->tuned_per_round = any_packed();

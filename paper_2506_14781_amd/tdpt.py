@@ -68,14 +68,16 @@ class _Info(ctypes.Structure):
 class _Layout(ctypes.Structure):
     _fields_ = [("bits", ctypes.c_int32), ("narrow", ctypes.c_int32), ("general", ctypes.c_int32),
                 ("ell_width", ctypes.c_int32), ("group_key", ctypes.c_int32), ("slots", ctypes.c_int32),
-                ("lanes", ctypes.c_int32), ("held", ctypes.c_int32), ("per_round", ctypes.c_int32)]
+                ("lanes", ctypes.c_int32), ("held", ctypes.c_int32), ("per_round", ctypes.c_int32),
+                ("spin", ctypes.c_int32)]
 
 
 class _TuneReport(ctypes.Structure):
     _fields_ = [("driver", ctypes.c_int32), ("block", ctypes.c_int32), ("ms_per_round", ctypes.c_double),
                 ("n_trials", ctypes.c_int32), ("trial_driver", ctypes.c_int32 * 32),
                 ("trial_block", ctypes.c_int32 * 32), ("trial_ms_per_round", ctypes.c_double * 32),
-                ("slots", ctypes.c_int32), ("trial_slots", ctypes.c_int32 * 32)]
+                ("slots", ctypes.c_int32), ("trial_slots", ctypes.c_int32 * 32), ("spin", ctypes.c_int32),
+                ("trial_spin", ctypes.c_int32 * 32)]
 
 
 class _BatchTuneReport(ctypes.Structure):
@@ -83,13 +85,15 @@ class _BatchTuneReport(ctypes.Structure):
                 ("group_ms_per_round", ctypes.c_double * 32), ("n_trials", ctypes.c_int32),
                 ("trial_group", ctypes.c_int32 * 128), ("trial_block", ctypes.c_int32 * 128),
                 ("trial_ms_per_round", ctypes.c_double * 128), ("group_slots", ctypes.c_int32 * 32),
-                ("trial_slots", ctypes.c_int32 * 128)]
+                ("trial_slots", ctypes.c_int32 * 128), ("group_spin", ctypes.c_int32 * 32),
+                ("trial_spin", ctypes.c_int32 * 128)]
 
 
 class _Status(ctypes.Structure):
     _fields_ = [("rounds_done", ctypes.c_int64), ("sweeps_done", ctypes.c_int64),
                 ("first_hit_sweep", ctypes.c_int64), ("best_f_q", ctypes.c_int64),
-                ("best_sweep", ctypes.c_int64), ("driver", ctypes.c_int32), ("slots", ctypes.c_int32)]
+                ("best_sweep", ctypes.c_int64), ("driver", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("spin", ctypes.c_int32)]
 
 
 _lib = None
@@ -409,9 +413,11 @@ class Problem:
         r = _TuneReport()
         _check(_lib.tdpt_problem_autotune(self._h, int(rounds_per_trial), ctypes.byref(r)))
         k = r.n_trials
-        return {"driver": r.driver, "block": r.block, "slots": r.slots, "ms_per_round": r.ms_per_round,
+        return {"driver": r.driver, "block": r.block, "slots": r.slots, "spin": r.spin,
+                "ms_per_round": r.ms_per_round,
                 "trials": [(r.trial_driver[i], r.trial_block[i], r.trial_slots[i], r.trial_ms_per_round[i])
-                           for i in range(k)]}
+                           for i in range(k)],
+                "trial_spin": [r.trial_spin[i] for i in range(k)]}
 
     def set_stage_trace(self, buf, rounds: int):
         """Persistent driver: per-round, per-slot stage timestamps (100 MHz
@@ -503,10 +509,11 @@ class Batch:
         _check(_lib.tdpt_batch_autotune(self._h, int(rounds_per_trial), ctypes.byref(r)))
         g, k = r.n_groups, r.n_trials
         return {"persistent": r.persistent, "group_block": list(r.group_block[:g]),
-                "group_slots": list(r.group_slots[:g]),
+                "group_slots": list(r.group_slots[:g]), "group_spin": list(r.group_spin[:g]),
                 "group_ms_per_round": list(r.group_ms_per_round[:g]),
                 "trials": [(r.trial_group[i], r.trial_block[i], r.trial_slots[i], r.trial_ms_per_round[i])
-                           for i in range(k)]}
+                           for i in range(k)],
+                "trial_spin": [r.trial_spin[i] for i in range(k)]}
 
     def close(self):
         h = getattr(self, "_h", None)

@@ -271,30 +271,41 @@ def test_layout_group_keys(monkeypatch):
 
 
 def test_layout_default_packing(monkeypatch):
-    """The per-round sweep's default launch shape: replicas whose largest
-    colour class takes under 64 lanes share a 64-thread workgroup, 2^s lanes
-    each (the power of two, at least 4, covering the class); small bipartite
-    copy-chain replicas without fields hold their structure in registers and
-    run per-round launches when rounds hold 16 sweeps or more; large
-    replicas and the bit-packed layout keep one replica per workgroup."""
+    """The per-round sweep's default launch shape.  While the problem's round
+    fits within 2048 waves (latency-bound), small packed copy-edge replicas
+    take one spin per lane, 2^s lanes covering the largest colour class's
+    spins, 64 / 2^s replicas per 64-thread workgroup below 64 lanes; beyond
+    that, replicas whose largest class takes under 64 quads share a
+    workgroup at one quad per lane.  Two colour classes let the lanes hold
+    their structure in registers, and then rounds of 16 sweeps or more run
+    per-round launches; large replicas and the bit-packed layout keep one
+    replica per workgroup."""
     from synth.configs import wishart_n200
     from tests.test_gpu_parity import _unequal_classes
     from tests.tiny import tiny_instance
-    w = wishart_small()   # 72 spins, 2 classes of 9 quads, no fields
-    a = T.Instance.from_synth(w.instance).layout(T.RunConfig(w.beta, w.p_q, mcs_per_swap=50, seed=0))
-    assert (a["slots"], a["lanes"], a["held"], a["per_round"]) == (4, 16, 1, 1)
-    b = T.Instance.from_synth(w.instance).layout(T.RunConfig(w.beta, w.p_q, mcs_per_swap=15, seed=0))
-    assert (b["slots"], b["held"], b["per_round"]) == (4, 1, 0)
-    # 10 spins with fields: 3 quads per class, 4 lanes, structure re-read
-    t = T.Instance.from_synth(tiny_instance()).layout(T.RunConfig([1.0], [0, 4096], mcs_per_swap=50, seed=0))
-    assert (t["slots"], t["lanes"], t["held"], t["per_round"]) == (16, 4, 0, 0)
+
+    def shape(lay):
+        return lay["spin"], lay["slots"], lay["lanes"], lay["held"], lay["per_round"]
+    w = wishart_small()   # 72 spins, 2 classes of 9 quads, no fields; 8 x 4 grid
+    inst = T.Instance.from_synth(w.instance)
+    assert shape(inst.layout(T.RunConfig(w.beta, w.p_q, mcs_per_swap=50, seed=0))) == (1, 1, 64, 1, 1)
+    assert shape(inst.layout(T.RunConfig(w.beta, w.p_q, mcs_per_swap=15, seed=0))) == (1, 1, 64, 1, 0)
+    # 3072 replicas are 3072 waves: one quad per lane, 4 replicas per wave
+    big = T.RunConfig(np.geomspace(0.1, 5, 64), np.arange(48, dtype=np.int32) * 64, mcs_per_swap=50, seed=0)
+    assert shape(inst.layout(big)) == (0, 4, 16, 1, 1)
+    # 10 spins with fields, 2 quads per class: 8 lanes, 8 replicas per wave
+    tiny = T.Instance.from_synth(tiny_instance())
+    assert shape(tiny.layout(T.RunConfig([1.0], [0, 4096], mcs_per_swap=50, seed=0))) == (1, 8, 8, 1, 1)
+    # 20480 replicas (2560 waves) of it: one quad per lane, structure re-read (fields)
+    many = T.RunConfig(np.geomspace(0.1, 5, 64), np.arange(320, dtype=np.int32) * 16, mcs_per_swap=50, seed=0)
+    assert shape(tiny.layout(many)) == (0, 16, 4, 0, 0)
     # classes of 1 and 3 quads, no fields
     u = T.Instance.from_synth(_unequal_classes()).layout(T.RunConfig([1.0], [0, 4096], mcs_per_swap=20, seed=0))
-    assert (u["slots"], u["lanes"], u["held"], u["per_round"]) == (16, 4, 1, 1)
+    assert shape(u) == (1, 4, 16, 1, 1)
     # 6800 spins, 850 quads per class: one replica per workgroup
     n2 = wishart_n200()
     c = T.Instance.from_synth(n2.instance).layout(T.RunConfig(n2.beta, n2.p_q, mcs_per_swap=1, seed=0))
-    assert (c["slots"], c["lanes"], c["held"], c["per_round"]) == (1, 0, 0, 0)
+    assert shape(c) == (0, 1, 0, 0, 0)
     monkeypatch.setenv("TDPT_LAYOUT", "bits")
-    e = T.Instance.from_synth(w.instance).layout(T.RunConfig(w.beta, w.p_q, mcs_per_swap=50, seed=0))
-    assert e["bits"] == 1 and (e["slots"], e["lanes"], e["per_round"]) == (1, 0, 0)
+    e = inst.layout(T.RunConfig(w.beta, w.p_q, mcs_per_swap=50, seed=0))
+    assert e["bits"] == 1 and shape(e) == (0, 1, 0, 0, 0)

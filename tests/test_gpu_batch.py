@@ -215,17 +215,22 @@ def test_graph_replays_equal_direct_launches(T):
     assert np.array_equal(f, o["f"]) and np.array_equal(g, o["g"])
 
 
-@pytest.mark.parametrize("lanes,block", [(None, None), (1, 64), (4, 64), (16, 128), (32, 64), (128, 256)])
-def test_packed_batch_equals_alone(T, monkeypatch, lanes, block):
+@pytest.mark.parametrize("lanes,block,spin", [(None, None, None), (None, None, 0), (1, 64, 0), (4, 64, 0),
+                                             (16, 128, 0), (32, 64, 0), (128, 256, 0), (16, 64, 1),
+                                             (64, 64, 1), (128, 256, 1), (256, 256, 1)])
+def test_packed_batch_equals_alone(T, monkeypatch, lanes, block, spin):
     """Per-round launches that hold several replicas per workgroup -- the
-    default for replicas whose largest colour class takes under 64 lanes, and
-    forced shapes: one lane per replica, several lanes in a wave, replicas
-    spanning two waves -- give every member (three structure layouts) its
+    defaults (one spin per lane while the batch's round is latency-bound,
+    else one quad per lane) and forced shapes: one lane per replica, several
+    lanes in a wave, replicas spanning two or four waves, one spin per lane
+    in several passes -- give every member (three structure layouts) its
     results alone, across membership changes, a switch to the persistent
     driver and back, and graph replays; one member against the oracle."""
     if lanes is not None:
         monkeypatch.setenv("TDPT_BATCH_LANES", str(lanes))
         monkeypatch.setenv("TDPT_BATCH_BLOCK", str(block))
+    if spin is not None:
+        monkeypatch.setenv("TDPT_BATCH_SPIN", str(spin))
     specs = _members()
     from synth.constrained import planted_coloring
     specs.append(("coloring", planted_coloring(60, 3, degree=4, seed=2).instance, np.geomspace(0.3, 3, 4),
@@ -238,7 +243,7 @@ def test_packed_batch_equals_alone(T, monkeypatch, lanes, block):
         P.run(rounds)
         alone.append(_outputs(P))
         probs.append(T.Problem(T.Instance.from_synth(inst), cfg))
-    _say(f"[batch] packed lanes={lanes} block={block}")
+    _say(f"[batch] packed lanes={lanes} block={block} spin={spin}")
     B = T.Batch(8)
     B.set_members(probs)
     B.set_driver(0)

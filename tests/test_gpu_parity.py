@@ -109,15 +109,20 @@ def test_small_wishart_full_run(T):
 
 
 def test_packed_per_round_single_problem(T):
-    """Small bipartite replicas with long rounds run packed per-round
-    launches by default (four N=12 replicas per wave, each lane's structure
-    held in registers for the round): bit-exact against the oracle, as is
-    the persistent driver asked for instead.  The 10-spin instance packs 16
-    replicas (4 lanes each) into a wave of the per-round driver."""
+    """Small bipartite replicas with long rounds run per-round launches by
+    default: one spin per lane (a lone problem is latency-bound), each
+    lane's structure held in registers for the round; with TDPT_SPIN=0 one
+    quad per lane, four N=12 replicas per wave.  Both are bit-exact against
+    the oracle, as is the persistent driver asked for instead.  The 10-spin
+    instance (fields) and an instance with colour classes of 1 and 3 quads
+    (lanes holding spins of both classes, one or none) run both shapes."""
     w = wishart_small()
-    o, P = both(T, w.instance, w.beta, w.p_q, mcs=20, rounds=12, seed=3, label="packed N12")
+    o, P = both(T, w.instance, w.beta, w.p_q, mcs=20, rounds=12, seed=3, label="spin lanes N12")
     q = P.query()
-    assert q["driver"] == 0 and q["slots"] == 4
+    assert (q["driver"], q["spin"], q["slots"]) == (0, 1, 1)
+    Q = _with_env("TDPT_SPIN", "0", lambda: run_gpu(T, w.instance, w.beta, w.p_q, mcs=20, rounds=12, seed=3))
+    assert (Q.query()["driver"], Q.query()["spin"], Q.query()["slots"]) == (0, 0, 4)
+    assert_same(o, Q, "quad lanes N12")
     Q = _with_env("TDPT_PERSISTENT", "1", lambda: run_gpu(T, w.instance, w.beta, w.p_q, mcs=20, rounds=12, seed=3))
     assert Q.query()["driver"] == 1
     assert_same(o, Q, "N12 persistent")
@@ -125,14 +130,20 @@ def test_packed_per_round_single_problem(T):
     beta = np.geomspace(0.3, 3.0, 5)
     p_q = q12(np.linspace(0.5, 3.0, 7))
     o, P = _with_env("TDPT_PERSISTENT", "0", lambda: both(T, inst, beta, p_q, mcs=16, rounds=10, seed=4,
-                                                          label="packed tiny 5x7"))
-    assert P.query()["driver"] == 0 and P.query()["slots"] == 16
-    # classes of unequal size (1 and 3 quads, the last ones partly dead): the
-    # lanes of a replica hold a quad of both classes, of one, or of none
+                                                          label="spin lanes tiny 5x7"))
+    assert (P.query()["driver"], P.query()["spin"], P.query()["slots"]) == (0, 1, 8)
+    Q = _with_env("TDPT_PERSISTENT", "0", lambda: _with_env("TDPT_SPIN", "0", lambda: run_gpu(
+        T, inst, beta, p_q, mcs=16, rounds=10, seed=4)))
+    assert (Q.query()["spin"], Q.query()["slots"]) == (0, 16)
+    assert_same(o, Q, "quad lanes tiny 5x7")
+    # classes of unequal size (1 and 3 quads, the last ones partly dead)
     inst = _unequal_classes()
-    o, P = both(T, inst, np.geomspace(0.3, 3.0, 4), q12([0.0, 1.0, 2.0]), mcs=20, rounds=12, seed=5,
-                label="packed unequal classes")
-    assert P.query()["driver"] == 0 and P.query()["slots"] == 16
+    beta, p_q = np.geomspace(0.3, 3.0, 4), q12([0.0, 1.0, 2.0])
+    o, P = both(T, inst, beta, p_q, mcs=20, rounds=12, seed=5, label="spin lanes unequal classes")
+    assert (P.query()["driver"], P.query()["spin"], P.query()["slots"]) == (0, 1, 4)
+    Q = _with_env("TDPT_SPIN", "0", lambda: run_gpu(T, inst, beta, p_q, mcs=20, rounds=12, seed=5))
+    assert (Q.query()["driver"], Q.query()["spin"], Q.query()["slots"]) == (0, 0, 16)
+    assert_same(o, Q, "quad lanes unequal classes")
 
 
 def _unequal_classes():
@@ -325,7 +336,7 @@ def test_drivers_agree_on_the_small_workload(T):
     assert all(np.array_equal(x, y) for x, y in zip(a.counters(), b.counters()))
     assert all(np.array_equal(x, y) for x, y in zip(a.trace(), b.trace()))
     qa, qb = a.query(), b.query()
-    for k in ("driver", "slots"):  # the launch shape; results must not depend on it
+    for k in ("driver", "slots", "spin"):  # the launch shape; results must not depend on it
         qa.pop(k), qb.pop(k)
     assert qa == qb
     assert np.array_equal(a.best()[0], b.best()[0])
