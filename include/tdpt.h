@@ -207,8 +207,8 @@ typedef struct tdpt_layout {
                            quads, the power of two (>= 4) covering its quads and the
                            per-phase bounds */
     int32_t held;       /* 1: the packed sweep holds each lane's structure in registers for
-                           a round (two colour classes; one quad per lane also needs the
-                           packed copy-edge layout with <= 4 neighbours and no fields) */
+                           a round (one spin per lane: 2 to 4 colour classes; one quad per
+                           lane: two classes, <= 4 neighbours and no fields) */
     int32_t per_round;  /* 1: tdpt_problem_create picks per-round launches over the
                            persistent driver (held, and mcs_per_swap >= 16) */
     int32_t spin;       /* 1: one spin per lane (packed copy-edge layout, <= 8 neighbours,
@@ -266,9 +266,9 @@ int tdpt_problem_create_static(const tdpt_instance *inst, const tdpt_run_cfg *cf
  * one -- one cooperative launch runs all n_rounds, replicas resident in LDS
  * and exchanging through mailboxes -- when every replica's workgroup fits
  * the GPU at once, except for small replicas whose lanes hold their
- * structure in registers for a round (tdpt_layout.held: two colour classes
- * and one spin per lane, or one quad per lane with at most 4 neighbours and
- * no fields) and whose rounds hold 16 sweeps or more: those run per-round
+ * structure in registers for a round (tdpt_layout.held: one spin per lane
+ * and 2 to 4 colour classes, or one quad per lane, two classes, at most 4
+ * neighbours and no fields) and whose rounds hold 16 sweeps or more: those run per-round
  * launches (tdpt_layout.per_round).  Per-round sweeps of small int8
  * replicas take one spin per lane while the problem's round is within 2048
  * waves (latency-bound; tdpt_status.spin), else one quad per lane, several

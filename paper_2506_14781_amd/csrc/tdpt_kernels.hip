@@ -639,9 +639,41 @@ __device__ __forceinline__ void spin_update(const DevProblem &P, lds8_t *s, int 
     dga -= __mul24(ds, cs);
 }
 
+// The round's phases when each of the NC colour classes has at most one
+// quad per 4 lanes: every lane holds its (at most) one spin per class of
+// structure in registers for the whole round (2 WD / 2 + 2 words a class).
+template <int NC, int WD>
+__device__ __forceinline__ void spin_phases_held(const DevProblem &P, const Rsrc &Rs, lds8_t *s,
+                                                 const SlotParams &sp, int64_t n_round, int j, int ql,
+                                                 uint32_t key0, uint32_t key1, int64_t &df, int64_t &dg)
+{
+    SpinS<WD> SS[NC];
+    int qq[NC], live_end[NC];
+    bool has[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        qq[c] = (P.cls_start[c] >> 2) + ql;
+        has[c] = qq[c] < (P.cls_start[c + 1] >> 2);
+        live_end[c] = P.cls_live[c];
+        if (has[c]) load_spin<WD>(P, Rs, 4 * qq[c] + j, SS[c]);
+    }
+    const int mcs = P.mcs;
+    for (int k = 0; k < mcs; ++k) {
+        const uint32_t t = (uint32_t)((n_round - 1) * mcs + k);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            int dfa = 0, dga = 0;
+            if (has[c]) spin_update<WD>(P, s, qq[c], j, SS[c], live_end[c], t, sp, key0, key1, dfa, dga);
+            df += dfa;
+            dg += 2 * (int64_t)dga;
+            if (k + 1 < mcs || c + 1 < NC) __syncthreads();
+        }
+    }
+}
+
 // The class phases of a round with one spin per lane (lanes a multiple of
-// 4); with two colour classes of at most lanes / 4 quads, each lane holds its
-// two spins' structure in registers for the round.
+// 4); with 2 to 4 colour classes of at most lanes / 4 quads each, the
+// structure is held in registers for the round (spin_phases_held).
 template <int NARROW, int WD>
 __device__ __forceinline__ void sweep_phases_spin(const DevProblem &P, const Rsrc &Rs, lds8_t *s,
                                                   const SlotParams &sp, int64_t n_round, int lane, int lanes,
@@ -651,26 +683,13 @@ __device__ __forceinline__ void sweep_phases_spin(const DevProblem &P, const Rsr
         const int mcs = P.mcs, n_colors = P.n_colors;
         const uint32_t key0 = P.key0, key1 = P.key1;
         const int j = lane & 3, ql = lane >> 2, qn = lanes >> 2;
-        const int qa = P.cls_start[0] >> 2, qb = P.cls_start[1] >> 2, qc = P.cls_start[2] >> 2;
-        if (n_colors == 2 && qb - qa <= qn && qc - qb <= qn) {
-            SpinS<WD> SS[2];
-            const int qq[2] = {qa + ql, qb + ql};
-            const bool has[2] = {qq[0] < qb, qq[1] < qc};
-            const int live_end[2] = {P.cls_live[0], P.cls_live[1]};
-#pragma unroll
-            for (int c = 0; c < 2; ++c)
-                if (has[c]) load_spin<WD>(P, Rs, 4 * qq[c] + j, SS[c]);
-            for (int k = 0; k < mcs; ++k) {
-                const uint32_t t = (uint32_t)((n_round - 1) * mcs + k);
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    int dfa = 0, dga = 0;
-                    if (has[c]) spin_update<WD>(P, s, qq[c], j, SS[c], live_end[c], t, sp, key0, key1, dfa, dga);
-                    df += dfa;
-                    dg += 2 * (int64_t)dga;
-                    if (k + 1 < mcs || c == 0) __syncthreads();
-                }
-            }
+        bool held = n_colors >= 2 && n_colors <= 4;
+        for (int c = 0; held && c < n_colors; ++c)
+            held = (P.cls_start[c + 1] >> 2) - (P.cls_start[c] >> 2) <= qn;
+        if (held) {
+            if (n_colors == 2) spin_phases_held<2, WD>(P, Rs, s, sp, n_round, j, ql, key0, key1, df, dg);
+            else if (n_colors == 3) spin_phases_held<3, WD>(P, Rs, s, sp, n_round, j, ql, key0, key1, df, dg);
+            else spin_phases_held<4, WD>(P, Rs, s, sp, n_round, j, ql, key0, key1, df, dg);
             return;
         }
         for (int k = 0; k < mcs; ++k) {

@@ -1107,7 +1107,7 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
     // small bipartite replicas whose structure the packed per-round sweep
     // holds in registers run that driver when rounds are long enough
     // (TDPT_PERSISTENT=1 asks for the persistent driver wherever it fits)
-    const bool prefer_round = ((d.spin && d.n_colors == 2) || (d.rpb > 1 && pack_hoists(d, in->max_class_quads, d.lshift))) &&
+    const bool prefer_round = ((d.spin && d.n_colors <= 4) || (d.rpb > 1 && pack_hoists(d, in->max_class_quads, d.lshift))) &&
                               cfg->mcs_per_swap >= kPackRoundMcs && !(pe && pe[0] == '1');
     if (p->persistent_ok && !prefer_round) {
         tdpt::DevProblem dq = d;
@@ -1570,7 +1570,7 @@ int tdpt_layout_get(const tdpt_instance *in, const tdpt_run_cfg *cfg, tdpt_layou
     }
     out->slots = rpb;
     out->lanes = rpb > 1 || out->spin ? 1 << lshift : 0;
-    out->held = (out->spin && in->n_colors == 2) ||
+    out->held = (out->spin && in->n_colors <= 4) ||
                         (!out->spin && rpb > 1 &&
                          pack_hoists(narrow, in->gen != 0, out->bits != 0, in->has_bias != 0, L.wd, in->n_colors,
                                      in->max_class_quads, lshift))
@@ -1836,7 +1836,7 @@ static int batch_decide_mode(tdpt_batch *b)
     for (const auto &g : b->groups) {
         prefer_round = prefer_round && (g.rpb > 1 || g.spin) && g.min_mcs >= kPackRoundMcs;
         for (int k = g.first_member; prefer_round && k < g.first_member + g.count; ++k)
-            prefer_round = g.spin ? b->members[k]->dp.n_colors == 2 && 4 * b->members[k]->max_class_quads <= (1 << g.lshift)
+            prefer_round = g.spin ? b->members[k]->dp.n_colors <= 4 && 4 * b->members[k]->max_class_quads <= (1 << g.lshift)
                                   : pack_hoists(b->members[k]->dp, b->members[k]->max_class_quads, g.lshift);
     }
     const char *pe = getenv("TDPT_PERSISTENT");

@@ -302,6 +302,12 @@ def test_layout_default_packing(monkeypatch):
     # classes of 1 and 3 quads, no fields
     u = T.Instance.from_synth(_unequal_classes()).layout(T.RunConfig([1.0], [0, 4096], mcs_per_swap=20, seed=0))
     assert shape(u) == (1, 4, 16, 1, 1)
+    # four colour classes (the three-copy N=16 J-column member, 48 spins,
+    # ELL width 6): held at one spin per lane only
+    from synth.configs import jcolumn_member
+    jc = jcolumn_member(16, 20000)
+    jl = T.Instance.from_synth(jc.instance).layout(T.RunConfig(jc.beta, jc.p_q, mcs_per_swap=20, seed=0))
+    assert shape(jl) == (1, 4, 16, 1, 1)
     # 6800 spins, 850 quads per class: one replica per workgroup
     n2 = wishart_n200()
     c = T.Instance.from_synth(n2.instance).layout(T.RunConfig(n2.beta, n2.p_q, mcs_per_swap=1, seed=0))

@@ -144,6 +144,18 @@ def test_packed_per_round_single_problem(T):
     Q = _with_env("TDPT_SPIN", "0", lambda: run_gpu(T, inst, beta, p_q, mcs=20, rounds=12, seed=5))
     assert (Q.query()["driver"], Q.query()["spin"], Q.query()["slots"]) == (0, 0, 16)
     assert_same(o, Q, "quad lanes unequal classes")
+    # three and four colour classes held in registers at one spin per lane:
+    # a ladder-ordered N=6 instance (18 spins) and the three-copy N=16
+    # J-column member (48 spins, ELL width 6, its own 16 x 8 grid)
+    inst = build_instance(6, 0.5, 1, degree_cap=3, order="ascending")
+    assert inst.n_colors == 3
+    o, P = both(T, inst, np.geomspace(0.3, 3.0, 3), q12([0.0, 1.0, 2.0]), mcs=20, rounds=10, seed=6,
+                label="spin lanes, 3 classes")
+    assert (P.query()["driver"], P.query()["spin"], P.query()["slots"]) == (0, 1, 8)
+    from synth.configs import jcolumn_member
+    jc = jcolumn_member(16, 20000)
+    o, P = both(T, jc.instance, jc.beta, jc.p_q, mcs=20, rounds=8, seed=7, label="spin lanes, 4 classes")
+    assert (P.query()["driver"], P.query()["spin"], P.query()["slots"]) == (0, 1, 4)
 
 
 def _unequal_classes():
