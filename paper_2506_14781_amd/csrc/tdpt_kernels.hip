@@ -94,18 +94,33 @@ __device__ __attribute__((noinline)) int heat_bath_exact(double beta, int h, uin
     return ((double)u < ldexp(p, 32)) ? 1 : -1;
 }
 
-__device__ __forceinline__ bool heat_bath_up(int h, float cb, uint32_t u, bool &ambiguous)
+// The pre-test's margin d = t - 2^32 (computed exactly whenever t < 2^32,
+// where the float spacing is at most 256): the spin goes up iff d < 0, i.e.
+// iff d's sign bit is set (t >= 2^32, and t = inf, give +0 or more), and the
+// lane needs the double expression iff !(|d| >= 2^16), which includes a NaN t.
+__device__ __forceinline__ float heat_bath_margin(int h, float cb, uint32_t u)
 {
     const float e = __builtin_amdgcn_exp2f(-((float)h * cb));  // cb = beta log2(e) / 2048
     const float uf = (float)u;
-    const float t = __builtin_fmaf(uf, e, uf);
-    ambiguous = !(fabsf(t - 4294967296.0f) >= 65536.0f);
-    return t < 4294967296.0f;
+    return __builtin_fmaf(uf, e, uf) - 4294967296.0f;
 }
 
-__device__ __forceinline__ int heat_bath_fast(int h, float cb, uint32_t u, bool &ambiguous)
+__device__ __forceinline__ bool margin_ambiguous(float d) { return !(fabsf(d) >= 65536.0f); }
+
+__device__ __forceinline__ bool heat_bath_up(int h, float cb, uint32_t u, bool &ambiguous)
 {
-    return heat_bath_up(h, cb, u, ambiguous) ? 1 : -1;
+    const float d = heat_bath_margin(h, cb, u);
+    ambiguous = margin_ambiguous(d);
+    return (__float_as_uint(d) >> 31) != 0u;
+}
+
+// Byte j = 0xff when d_j's sign bit is set, else 0: v_perm_b32 selectors 9
+// and 11 replicate the sign bits of the low and the high operand.
+__device__ __forceinline__ uint32_t sign_bytes4(const float d[4])
+{
+    const uint32_t lo = __builtin_amdgcn_perm(__float_as_uint(d[1]), __float_as_uint(d[0]), 0x0c0c0b09u);
+    const uint32_t hi = __builtin_amdgcn_perm(__float_as_uint(d[3]), __float_as_uint(d[2]), 0x0b090c0cu);
+    return lo | hi;
 }
 
 // ------------------------------------------------------ structure access
@@ -433,29 +448,27 @@ __device__ __forceinline__ void quad_update(const DevProblem &P, lds8_t *s, int 
     lds32_t *wp = (lds32_t *)(s + q * 4);
     const uint32_t ow = *wp;
     int hh[4];
-    uint32_t up = 0;  // byte j = 1 when spin j goes up
-    bool amb_any = false;
+    float d[4];
+    bool amb_any = false;  // padding lanes may set it too: the exact path skips them
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         if constexpr (NARROW) hh[j] = __mul24(sp.twoP, cs[j]) + hp[j];
         else hh[j] = sp.twoP * cs[j] + hp[j];
-        bool a;
-        up |= heat_bath_up(hh[j], sp.cb, u[j], a) ? (1u << (8 * j)) : 0u;
-        amb_any |= a && ((live_bytes >> (8 * j)) & 1u);
+        d[j] = heat_bath_margin(hh[j], sp.cb, u[j]);
+        amb_any |= margin_ambiguous(d[j]);
     }
+    uint32_t up = sign_bytes4(d);  // byte j = 0xff when spin j goes up
     if (__builtin_expect(amb_any, 0)) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            bool a;
-            heat_bath_up(hh[j], sp.cb, u[j], a);
-            if (a && ((live_bytes >> (8 * j)) & 1u)) {
-                const uint32_t bit = heat_bath_exact(sp.beta, hh[j], u[j]) > 0 ? 1u : 0u;
-                up = (up & ~(1u << (8 * j))) | (bit << (8 * j));
+            if (margin_ambiguous(d[j]) && ((live_bytes >> (8 * j)) & 1u)) {
+                const uint32_t byte = heat_bath_exact(sp.beta, hh[j], u[j]) > 0 ? 0xffu : 0u;
+                up = (up & ~(0xffu << (8 * j))) | (byte << (8 * j));
             }
         }
     }
     // byte j: +1 (0x01) when up, -1 (0xff) otherwise, 0 for padding
-    const uint32_t nw = (0xffffffffu ^ (up * 0xfeu)) & live_bytes;
+    const uint32_t nw = (0xffffffffu ^ (up & 0xfefefefeu)) & live_bytes;
     *wp = nw;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -1421,22 +1434,22 @@ __device__ __forceinline__ void bits_update_quad(const DevProblem &P, const Rsrc
         uint32_t u[4] = {(uint32_t)q, t, sp[r].pos, 0u};
         philox10(u[0], u[1], u[2], u[3], P.key0, P.key1);
         int hp[4], hh[4];
-        uint32_t up = 0;
-        bool amb_any = false;
+        float d[4];
+        bool amb_any = false;  // dead lanes may set it too: the exact path skips them
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             hp[j] = h0[j] + 2 * acc[j][r];
             hh[j] = mad24(cs[j][r], sp[r].twoP, hp[j]);  // |2 P_q| < 2^23 in this layout
-            bool a;
-            up |= heat_bath_up(hh[j], sp[r].cb, u[j], a) ? (1u << j) : 0u;
-            amb_any |= a && ((live >> j) & 1u);
+            d[j] = heat_bath_margin(hh[j], sp[r].cb, u[j]);
+            amb_any |= margin_ambiguous(d[j]);
         }
+        // bit j set when spin j goes up: the sign bytes masked to 1, 2, 4, 8
+        // and summed
+        uint32_t up = __builtin_amdgcn_sad_u8(sign_bytes4(d) & 0x08040201u, 0u, 0u);
         if (__builtin_expect(amb_any, 0)) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                bool a;
-                heat_bath_up(hh[j], sp[r].cb, u[j], a);
-                if (a && ((live >> j) & 1u)) {
+                if (margin_ambiguous(d[j]) && ((live >> j) & 1u)) {
                     const uint32_t bit = heat_bath_exact(sp[r].beta, hh[j], u[j]) > 0 ? 1u : 0u;
                     up = (up & ~(1u << j)) | (bit << j);
                 }
