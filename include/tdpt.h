@@ -197,7 +197,8 @@ typedef struct tdpt_layout {
     int32_t narrow;     /* 1: 16-bit packed structure rows */
     int32_t general;    /* 1: general constraint terms, 0: copy edges */
     int32_t ell_width;  /* problem-neighbour slots per spin in the device structure */
-    int32_t group_key;  /* bits | narrow << 1 | (narrow && general) << 2 | ell_width << 3 */
+    int32_t group_key;  /* bits | narrow << 1 | (narrow && general) << 2 | ell_width << 3 |
+                           pair16 << 12 */
     /* default launch shape of the per-round sweep (int8 replicas): */
     int32_t slots;      /* replicas per workgroup: 64 / lanes below 64 lanes (slots within
                            64 KiB of LDS), else 1 */
@@ -214,6 +215,10 @@ typedef struct tdpt_layout {
     int32_t spin;       /* 1: one spin per lane (packed copy-edge layout, <= 8 neighbours,
                            largest class <= 256 spins, the problem's round within 2048
                            waves, so latency-bound) */
+    int32_t pair16;     /* 1: bit-packed replicas in pair form (two replicas per 32-bit word,
+                           their coupling sums in 16-bit halves): every spin's sum of
+                           2 |J_q| over its problem neighbours below 2^15 (environment
+                           TDPT_PAIR16=0 turns it off) */
 } tdpt_layout;
 int tdpt_layout_get(const tdpt_instance *inst, const tdpt_run_cfg *cfg, tdpt_layout *out);
 

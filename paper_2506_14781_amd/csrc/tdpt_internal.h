@@ -50,16 +50,27 @@ constexpr int64_t kKeyOffset = (int64_t)1 << 30;
 //   chp[n_pad]      the two copy neighbours packed as 16+16 bits
 // Wide structure: nb_idx / nb_J [wd][n_pad] int32, ch_idx [2][n_pad] int32.
 // Bit-packed layout (replicas too large for an int8 copy in LDS): spins are
-// bits (1 = +1) in LDS, kBitSlots replicas interleaved by 32-bit word (word w
-// of replica r at byte 16 w + 4 r); each colour class starts on a 32-bit
-// boundary of the bit numbering (bit_start[c]), so spin rho of class c sits
-// at bit rho - cls_start[c] + bit_start[c].  Structure in bit positions,
-// each stored as 512 (b >> 5) + (b & 31) so that shifted right by 5 it is the
-// LDS byte address of the word's 4-replica group (the low 5 bits are the bit):
+// bits (1 = +1) in LDS; each colour class starts on a 32-bit boundary of the
+// bit numbering (bit_start[c]), so spin rho of class c sits at bit
+// b = rho - cls_start[c] + bit_start[c], and the kBitSlots replicas' bits
+// b = 32 G .. 32 G + 31 fill the 16-byte word group G.  Within a group:
+//   plain form: word r (byte 16 G + 4 r) holds bit b & 31 of replica r;
+//     a position is stored as (G << 9) | (b & 31);
+//   pair form (pair16): word 2 h + p (h = (b >> 4) & 1) holds bit b & 15 of
+//     replica 2 p and, 16 places up, of replica 2 p + 1; a position is stored
+//     as (G << 9) | (h << 8) | (b & 15).
+// Either way a position shifted right by 5 is the LDS byte address of the
+// words that hold the bit (the plain form's group, the pair form's word
+// pair) and its low 5 bits are the bit's place in the word (of the replica
+// pair's lower replica).  Structure:
 //   nb_pos / nb_J [wd][n_pad] (missing neighbours: position 0, coupling 0),
+//   nb_J2 [wd][n_pad] (pair form: 2 J as a 16-bit number in both halves),
 //   ch_pos [2][n_pad] (a missing copy neighbour names bit 0 of an always-zero
 //   word group n_words; row 0 also holds in bits 29..30 how many of the two
 //   exist), h0 [n_pad] = b - sum_k J_k.
+// The pair form sums the couplings of two replicas at once in 16-bit
+// halves; the host chooses it when every spin's sum of 2 |J| over its
+// problem neighbours is below 2^15, so the halves never overflow.
 struct DevProblem {
     // structure (immutable)
     int32_t n_pad;      // padded spin count
@@ -73,11 +84,13 @@ struct DevProblem {
     int32_t lshift;     // of 2^lshift lanes each (rpb << lshift threads)
     int32_t spin;       // packed sweep with one spin per lane (4 lanes per quad)
     int32_t bits;       // bit-packed layout
+    int32_t pair16;     // its pair form
     int32_t n_words;    // 32-bit words per replica in the bit-packed layout
     int32_t bit_start[kMaxColors + 1];
     const int32_t *nb_pos; // bit-packed
     const int32_t *ch_pos; // bit-packed
     const int32_t *h0;     // bit-packed
+    const uint32_t *nb_J2; // bit-packed, pair form
     int32_t cls_start[kMaxColors + 1];
     int32_t cls_live[kMaxColors];
     const uint32_t *nbi;   // narrow

@@ -146,7 +146,7 @@ __device__ __forceinline__ Rsrc make_rsrc(const DevProblem &P)
     if (P.bits) {
         const int bytes = P.wd * P.n_pad * 4;
         r.a = rsrc(P.nb_pos, bytes);
-        r.b = rsrc(P.nb_J, bytes);
+        r.b = P.pair16 ? rsrc(P.nb_J2, bytes) : rsrc(P.nb_J, bytes);
         r.ch = rsrc(P.ch_pos, P.n_pad * 8);
         r.bias = rsrc(P.h0, P.n_pad * 4);
         return r;
@@ -193,6 +193,8 @@ typedef __attribute__((address_space(3))) int8_t lds8_t;
 typedef __attribute__((address_space(3))) uint32_t lds32_t;
 typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) u4v lds_u4_t;
+typedef unsigned int u2v __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) u2v lds_u2_t;
 
 __device__ __forceinline__ lds8_t *replica_lds() { return (lds8_t *)(uintptr_t)0u; }
 
@@ -203,6 +205,9 @@ __device__ __forceinline__ bool replica_at_zero(int8_t *lds)
 
 // Error word value when a sweep kernel finds its dynamic LDS elsewhere.
 constexpr int64_t kErrLdsBase = 2;
+// Error word value when a bit-packed sweep kernel of one form is launched on
+// a problem laid out in the other.
+constexpr int64_t kErrBitsForm = 3;
 
 // Per-slot parameters of the current round.
 struct SlotParams {
@@ -1540,11 +1545,202 @@ __device__ __forceinline__ void bits_energy_quad(const DevProblem &P, const Rsrc
     }
 }
 
+// ------------------------------------------- bit-packed layout, pair form
+// Each 32-bit word holds the same 16 spins of two replicas, one per 16-bit
+// half, so one shift and mask read a neighbour's spin in both and one packed
+// 16-bit multiply-add (v_pk_mad_u16) adds its coupling to both replicas'
+// sums.  The sums 2 sum_k J_k b_k stay below 2^15 in magnitude (the host's
+// condition for this form), so the halves' arithmetic modulo 2^16 is exact
+// once each half is read back sign-extended.
+
+// acc + j2 * s in each 16-bit half, as one instruction (written as a vector
+// of two 16-bit numbers the compiler pairs the words of a replica group into
+// 64-bit values and spills them)
+__device__ __forceinline__ uint32_t pair_mad(uint32_t j2, uint32_t s, uint32_t acc)
+{
+    uint32_t r;
+    __asm__("v_pk_mad_u16 %0, %1, %2, %3" : "=v"(r) : "v"(j2), "v"(s), "v"(acc));
+    return r;
+}
+
+// The spin at position pos in both replicas of word w, one bit per half (the
+// shift reads only the low 5 bits of pos, which the compiler drops the mask
+// for).
+__device__ __forceinline__ uint32_t pair_bits(uint32_t w, int pos) { return (w >> (pos & 31)) & 0x00010001u; }
+
+// Half h (0: low) of a pair of 16-bit sums, sign-extended.
+__device__ __forceinline__ int pair_half(uint32_t acc, int h)
+{
+    return h ? ((int)acc >> 16) : (int)(short)(acc & 0xffffu);
+}
+
+// OR of x over the aligned group of 4 lanes containing this lane, in all 4.
+__device__ __forceinline__ uint32_t or4_all(uint32_t x)
+{
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    return x;
+}
+
+// bits_update_quad for the pair form.  The 4 lanes of a half word (16 spins)
+// are an aligned lane quad; they OR their nibbles across lanes and the last
+// of them stores the half's two words (one per replica pair) as one 8-byte
+// write.
+template <int WD, bool TRACK>
+__device__ __forceinline__ void pair_update_quad(const DevProblem &P, const Rsrc &Rs, int q,
+                                                 int q1, int c, unsigned live, uint32_t t,
+                                                 const SlotParams (&sp)[kBitSlots],
+                                                 int (&dfa)[kBitSlots], int (&dga)[kBitSlots])
+{
+    const int qs = min(q, q1 - 1);
+    const int voff = qs * 16;
+    const int row = P.n_pad * 4;
+    uint32_t acc[4][2];  // [spin][replica pair]: 2 sum_k J_k b_k, one replica per half
+#pragma unroll
+    for (int j = 0; j < 4; ++j) { acc[j][0] = 0u; acc[j][1] = 0u; }
+#pragma unroll
+    for (int k = 0; k < WD; ++k) {
+        const v4i pk = bload(Rs.a, voff, k * row);
+        const v4i jk = bload(Rs.b, voff, k * row);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int pos = pk[j];
+            const u2v nw = *(const lds_u2_t *)(uintptr_t)(uint32_t)(pos >> 5);
+            acc[j][0] = pair_mad((uint32_t)jk[j], pair_bits(nw.x, pos), acc[j][0]);
+            acc[j][1] = pair_mad((uint32_t)jk[j], pair_bits(nw.y, pos), acc[j][1]);
+        }
+    }
+    const v4i c0 = bload(Rs.ch, voff, 0);
+    const v4i c1 = bload(Rs.ch, voff, row);
+    int cs[4][kBitSlots];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        // as in the plain form: the copy sum is 2 (b0 + b1) - kc, the two
+        // present-neighbour bits counted per half (at most 2 each)
+        const int p0 = c0[j], p1 = c1[j];
+        const u2v n0 = *(const lds_u2_t *)(uintptr_t)__builtin_amdgcn_ubfe((uint32_t)p0, 5, 18);
+        const u2v n1 = *(const lds_u2_t *)(uintptr_t)(uint32_t)(p1 >> 5);
+        const int nkc = -(int)((uint32_t)p0 >> 29);
+        const uint32_t ca = pair_bits(n0.x, p0) + pair_bits(n1.x, p1);
+        const uint32_t cb = pair_bits(n0.y, p0) + pair_bits(n1.y, p1);
+        cs[j][0] = 2 * (int)(ca & 0xffffu) + nkc;
+        cs[j][1] = 2 * (int)(ca >> 16) + nkc;
+        cs[j][2] = 2 * (int)(cb & 0xffffu) + nkc;
+        cs[j][3] = 2 * (int)(cb >> 16) + nkc;
+    }
+    const v4i h0 = bload(Rs.bias, voff, 0);
+    const int bpos = qs * 4 - P.cls_start[c] + P.bit_start[c];
+    const int b15 = bpos & 15;
+    uint32_t o2[2] = {0u, 0u};
+    if (TRACK) {
+        const u2v ow = *(const lds_u2_t *)(uintptr_t)(uint32_t)(bpos >> 1 & ~7);
+        o2[0] = ow.x;
+        o2[1] = ow.y;
+    }
+    uint32_t nw2[2] = {0u, 0u};
+#pragma unroll
+    for (int r = 0; r < kBitSlots; ++r) {
+        uint32_t u[4] = {(uint32_t)q, t, sp[r].pos, 0u};
+        philox10(u[0], u[1], u[2], u[3], P.key0, P.key1);
+        int hp[4], hh[4];
+        float d[4];
+        bool amb_any = false;  // dead lanes may set it too: the exact path skips them
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            hp[j] = h0[j] + pair_half(acc[j][r >> 1], r & 1);
+            hh[j] = mad24(cs[j][r], sp[r].twoP, hp[j]);  // |2 P_q| < 2^23 in this layout
+            d[j] = heat_bath_margin(hh[j], sp[r].cb, u[j]);
+            amb_any |= margin_ambiguous(d[j]);
+        }
+        uint32_t up = __builtin_amdgcn_sad_u8(sign_bytes4(d) & 0x08040201u, 0u, 0u);
+        if (__builtin_expect(amb_any, 0)) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (margin_ambiguous(d[j]) && ((live >> j) & 1u)) {
+                    const uint32_t bit = heat_bath_exact(sp[r].beta, hh[j], u[j]) > 0 ? 1u : 0u;
+                    up = (up & ~(1u << j)) | (bit << j);
+                }
+            }
+        }
+        up &= live;
+        const int sh = b15 + 16 * (r & 1);
+        if (TRACK) {
+            const uint32_t old = (o2[r >> 1] >> sh) & 15u;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int db = (((live >> j) & 1u) ? ((int)((up >> j) & 1u) - (int)((old >> j) & 1u)) : 0);
+                dfa[r] -= 2 * db * hp[j];
+                dga[r] -= 4 * db * cs[j][r];
+            }
+        }
+        nw2[r >> 1] |= up << sh;  // 0 for a lane past the class end
+    }
+    // the half's two words, from its first quad; a half wholly past the class
+    // end stores nothing (its words are class padding and stay zero)
+    const int qh = q - (int)(threadIdx.x & 3);
+    const uint32_t w0 = or4_all(nw2[0]), w1 = or4_all(nw2[1]);
+    if ((threadIdx.x & 3) == 3 && qh < q1) {
+        const int bh = qh * 4 - P.cls_start[c] + P.bit_start[c];  // a multiple of 16
+        *(lds_u2_t *)(uintptr_t)(uint32_t)(bh >> 1) = u2v{w0, w1};
+    }
+}
+
+// bits_energy_quad for the pair form (acc holds 2 A_i per half).
+template <int WD>
+__device__ __forceinline__ void pair_energy_quad(const DevProblem &P, const Rsrc &Rs,
+                                                 const __amdgpu_buffer_rsrc_t &rb, int q, int c,
+                                                 unsigned live, int64_t (&ef)[kBitSlots], int (&eg)[kBitSlots])
+{
+    const int voff = q * 16;
+    const int row = P.n_pad * 4;
+    uint32_t acc[4][2];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) { acc[j][0] = 0u; acc[j][1] = 0u; }
+#pragma unroll
+    for (int k = 0; k < WD; ++k) {
+        const v4i pk = bload(Rs.a, voff, k * row);
+        const v4i jk = bload(Rs.b, voff, k * row);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int pos = pk[j];
+            const u2v nw = *(const lds_u2_t *)(uintptr_t)(uint32_t)(pos >> 5);
+            acc[j][0] = pair_mad((uint32_t)jk[j], pair_bits(nw.x, pos), acc[j][0]);
+            acc[j][1] = pair_mad((uint32_t)jk[j], pair_bits(nw.y, pos), acc[j][1]);
+        }
+    }
+    const v4i c0 = bload(Rs.ch, voff, 0);
+    const v4i c1 = bload(Rs.ch, voff, row);
+    const v4i h0 = bload(Rs.bias, voff, 0);
+    const v4i bb = bload(rb, voff, 0);
+    const int bpos = q * 4 - P.cls_start[c] + P.bit_start[c];
+    const u2v ow = *(const lds_u2_t *)(uintptr_t)(uint32_t)(bpos >> 1 & ~7);
+    const uint32_t o2[2] = {ow.x, ow.y};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (!((live >> j) & 1u)) continue;
+        const int p0 = c0[j], p1 = c1[j];
+        const int kc = (int)((uint32_t)p0 >> 29);  // copy neighbours present: row 0 first
+        const u2v n0 = *(const lds_u2_t *)(uintptr_t)__builtin_amdgcn_ubfe((uint32_t)p0, 5, 18);
+        const u2v n1 = *(const lds_u2_t *)(uintptr_t)(uint32_t)(p1 >> 5);
+        const uint32_t a2[2] = {n0.x, n0.y}, b2[2] = {n1.x, n1.y};
+#pragma unroll
+        for (int r = 0; r < kBitSlots; ++r) {
+            const int up16 = 16 * (r & 1);
+            const uint32_t bi = (o2[r >> 1] >> ((bpos & 15) + up16 + j)) & 1u;
+            const int64_t t = (int64_t)(h0[j] + pair_half(acc[j][r >> 1], r & 1)) + bb[j];
+            ef[r] += bi ? -t : t;
+            const uint32_t d0 = (bi ^ bit_of(a2[r >> 1], p0 + up16)) & (kc >= 1 ? 1u : 0u);
+            const uint32_t d1 = (bi ^ bit_of(b2[r >> 1], p1 + up16)) & (kc >= 2 ? 1u : 0u);
+            eg[r] += (int)(d0 + d1);
+        }
+    }
+}
+
 // One round of up to kBitSlots slots (slot0 ..): unpack the int8 states into
 // LDS bits, mcs sweeps, pack them back.  TRACK: f and g follow every update
 // exactly (cheap for few sweeps per round); otherwise they are recomputed
 // from the final states of the round (cheaper from about 4 sweeps on).
-template <int WD, bool TRACK>
+template <int WD, bool TRACK, bool PAIR>
 __device__ __forceinline__ void round_sweep_bits_body(const DevProblem &P, int slot0, int8_t *lds)
 {
     // the replicas' words sit at LDS byte 0 (the update addresses them there)
@@ -1553,25 +1749,37 @@ __device__ __forceinline__ void round_sweep_bits_body(const DevProblem &P, int s
             __hip_atomic_store(&P.hdr[kHdrError], kErrLdsBase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return;
     }
+    // the form is a template argument (one sweep loop per kernel schedules
+    // far better than both behind a branch); the host launches the one that
+    // matches the problem's structure
+    if (P.pair16 != (PAIR ? 1 : 0)) {
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&P.hdr[kHdrError], kErrBitsForm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
     uint32_t *W = reinterpret_cast<uint32_t *>(lds);
     // words of the replicas, one always-zero word group, then int64 scratch
     int64_t *red = reinterpret_cast<int64_t *>(lds + (size_t)(P.n_words + 1) * 16);
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int ns = min(kBitSlots, P.R - slot0);
-    // unpack: word w of slot r from the spins whose bit positions it holds
-    // (the extra word group w = n_words holds no spin and stays zero)
+    // unpack: word i of group w from the spins whose bits it holds (the extra
+    // word group w = n_words holds no spin and stays zero); bit x of the word
+    // is spin bit 32 w + x of replica i & 3 (plain form) or spin bit
+    // 32 w + 16 ((i >> 1) & 1) + (x & 15) of replica 2 (i & 1) + (x >> 4)
+    // (pair form)
+    constexpr int pair = PAIR ? 1 : 0;
     for (int i = tid; i < (P.n_words + 1) * kBitSlots; i += nthr) {
-        const int w = i >> 2, r = i & 3;
+        const int w = i >> 2;
         uint32_t bits = 0;
-        if (r < ns) {
-            int c = 0;
-            while (c + 1 < P.n_colors && P.bit_start[c + 1] <= 32 * w) ++c;
-            const int8_t *st = P.states + (size_t)(slot0 + r) * P.stride;
-            const int live = P.cls_live[c] - P.cls_start[c];
-            for (int b = 0; b < 32; ++b) {
-                const int k = 32 * w + b - P.bit_start[c];
-                if (k >= 0 && k < live && st[P.cls_start[c] + k] > 0) bits |= 1u << b;
-            }
+        int c = 0;
+        while (c + 1 < P.n_colors && P.bit_start[c + 1] <= 32 * w) ++c;
+        const int live = P.cls_live[c] - P.cls_start[c];
+        for (int x = 0; x < 32; ++x) {
+            const int r = pair ? 2 * (i & 1) + (x >> 4) : (i & 3);
+            const int k = (pair ? 32 * w + 16 * ((i >> 1) & 1) + (x & 15) : 32 * w + x) - P.bit_start[c];
+            if (r < ns && k >= 0 && k < live &&
+                P.states[(size_t)(slot0 + r) * P.stride + P.cls_start[c] + k] > 0)
+                bits |= 1u << x;
         }
         W[i] = bits;
     }
@@ -1599,7 +1807,8 @@ __device__ __forceinline__ void round_sweep_bits_body(const DevProblem &P, int s
                 const int q = base + tid;
                 const int rem = q < q1 ? live_end - q * 4 : 0;
                 const unsigned live = rem >= 4 ? 15u : rem <= 0 ? 0u : ((1u << rem) - 1u);
-                bits_update_quad<WD, TRACK>(P, Rs, q, q1, c, live, t, sp, dfa, dga);
+                if constexpr (PAIR) pair_update_quad<WD, TRACK>(P, Rs, q, q1, c, live, t, sp, dfa, dga);
+                else bits_update_quad<WD, TRACK>(P, Rs, q, q1, c, live, t, sp, dfa, dga);
             }
 #pragma unroll
             for (int r = 0; r < kBitSlots; ++r) { df[r] += dfa[r]; dg[r] += dga[r]; }
@@ -1618,7 +1827,8 @@ __device__ __forceinline__ void round_sweep_bits_body(const DevProblem &P, int s
             for (int q = q0 + tid; q < q1; q += nthr) {
                 const int rem = live_end - q * 4;
                 const unsigned live = rem >= 4 ? 15u : rem <= 0 ? 0u : ((1u << rem) - 1u);
-                bits_energy_quad<WD>(P, Rs, rb, q, c, live, df, eg);
+                if constexpr (PAIR) pair_energy_quad<WD>(P, Rs, rb, q, c, live, df, eg);
+                else bits_energy_quad<WD>(P, Rs, rb, q, c, live, df, eg);
             }
 #pragma unroll
             for (int r = 0; r < kBitSlots; ++r) dg[r] += eg[r];
@@ -1644,28 +1854,28 @@ __device__ __forceinline__ void round_sweep_bits_body(const DevProblem &P, int s
     }
     // pack back: live spins only (class padding stays 0 in the int8 copy)
     for (int i = tid; i < P.n_words * kBitSlots; i += nthr) {
-        const int w = i >> 2, r = i & 3;
-        if (r >= ns) continue;
+        const int w = i >> 2;
         int c = 0;
         while (c + 1 < P.n_colors && P.bit_start[c + 1] <= 32 * w) ++c;
-        int8_t *st = P.states + (size_t)(slot0 + r) * P.stride;
         const int live = P.cls_live[c] - P.cls_start[c];
         const uint32_t bits = W[i];
-        for (int b = 0; b < 32; ++b) {
-            const int k = 32 * w + b - P.bit_start[c];
-            if (k >= 0 && k < live) st[P.cls_start[c] + k] = ((bits >> b) & 1u) ? 1 : -1;
+        for (int x = 0; x < 32; ++x) {
+            const int r = pair ? 2 * (i & 1) + (x >> 4) : (i & 3);
+            const int k = (pair ? 32 * w + 16 * ((i >> 1) & 1) + (x & 15) : 32 * w + x) - P.bit_start[c];
+            if (r < ns && k >= 0 && k < live)
+                P.states[(size_t)(slot0 + r) * P.stride + P.cls_start[c] + k] = ((bits >> x) & 1u) ? 1 : -1;
         }
     }
 }
 
-template <int WD, bool TRACK>
+template <int WD, bool TRACK, bool PAIR>
 __global__ __launch_bounds__(TRACK ? kBitsBlock : kBitsBlockScratch) void k_round_sweep_bits(DevProblem P)
 {
     extern __shared__ __align__(16) int8_t lds[];
-    round_sweep_bits_body<WD, TRACK>(P, blockIdx.x * kBitSlots, lds);
+    round_sweep_bits_body<WD, TRACK, PAIR>(P, blockIdx.x * kBitSlots, lds);
 }
 
-template <int WD, bool TRACK>
+template <int WD, bool TRACK, bool PAIR>
 __global__ __launch_bounds__(TRACK ? kBitsBlock : kBitsBlockScratch) void k_batch_sweep_bits(
     const DevProblem *__restrict__ table,
                                                               const int *__restrict__ first_block, int count)
@@ -1678,7 +1888,7 @@ __global__ __launch_bounds__(TRACK ? kBitsBlock : kBitsBlockScratch) void k_batc
         if (first_block[mid] <= b) lo = mid;
         else hi = mid - 1;
     }
-    round_sweep_bits_body<WD, TRACK>(table[lo], (b - first_block[lo]) * kBitSlots, lds);
+    round_sweep_bits_body<WD, TRACK, PAIR>(table[lo], (b - first_block[lo]) * kBitSlots, lds);
 }
 
 // ---------------------------------------------------- initial states, f, g
@@ -2011,55 +2221,58 @@ static size_t bits_lds(int n_words)
     return (size_t)(n_words + 1) * 16 + 8 * 2 * kBitSlots * (kMaxBlock / 64) + 16;
 }
 
-template <bool TRACK, int WD>
+template <bool TRACK, int WD, bool PAIR>
 static hipError_t sweep_bits_t(const DevProblem &p, hipStream_t s)
 {
     const size_t lds = bits_lds(p.n_words);
-    hipError_t e = allow_lds(k_round_sweep_bits<WD, TRACK>, lds);
+    hipError_t e = allow_lds(k_round_sweep_bits<WD, TRACK, PAIR>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_round_sweep_bits<WD, TRACK>), dim3((p.R + kBitSlots - 1) / kBitSlots),
+    hipLaunchKernelGGL((k_round_sweep_bits<WD, TRACK, PAIR>), dim3((p.R + kBitSlots - 1) / kBitSlots),
                        dim3(min(p.block, TRACK ? kBitsBlock : kBitsBlockScratch)), lds, s, p);
     return hipGetLastError();
 }
 
-template <bool TRACK, int WD>
+template <bool TRACK, int WD, bool PAIR>
 static hipError_t batch_sweep_bits_t(const DevProblem &p, const DevProblem *table, const int *first_block,
                                      int count, int blocks, int block, int max_words, hipStream_t s)
 {
     (void)p;
     const size_t lds = bits_lds(max_words);
-    hipError_t e = allow_lds(k_batch_sweep_bits<WD, TRACK>, lds);
+    hipError_t e = allow_lds(k_batch_sweep_bits<WD, TRACK, PAIR>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_batch_sweep_bits<WD, TRACK>), dim3(blocks),
+    hipLaunchKernelGGL((k_batch_sweep_bits<WD, TRACK, PAIR>), dim3(blocks),
                        dim3(min(block, TRACK ? kBitsBlock : kBitsBlockScratch)), lds, s,
                        table, first_block, count);
     return hipGetLastError();
 }
 
-#define TDPT_BITS_CASE(FN, W, TR, ...) \
-    case W: return (TR) ? FN<true, W>(__VA_ARGS__) : FN<false, W>(__VA_ARGS__);
-#define TDPT_DISPATCH_BITS(FN, TR, ...)              \
-    switch (p.wd) {                                  \
-    TDPT_BITS_CASE(FN, 1, TR, __VA_ARGS__)           \
-    TDPT_BITS_CASE(FN, 2, TR, __VA_ARGS__)           \
-    TDPT_BITS_CASE(FN, 3, TR, __VA_ARGS__)           \
-    TDPT_BITS_CASE(FN, 4, TR, __VA_ARGS__)           \
-    TDPT_BITS_CASE(FN, 5, TR, __VA_ARGS__)           \
-    TDPT_BITS_CASE(FN, 6, TR, __VA_ARGS__)           \
-    TDPT_BITS_CASE(FN, 7, TR, __VA_ARGS__)           \
-    TDPT_BITS_CASE(FN, 8, TR, __VA_ARGS__)           \
-    default: return hipErrorInvalidValue;            \
+#define TDPT_BITS_CASE(FN, W, TR, PR, ...)                                              \
+    case W:                                                                             \
+        return (TR) ? ((PR) ? FN<true, W, true>(__VA_ARGS__) : FN<true, W, false>(__VA_ARGS__)) \
+                    : ((PR) ? FN<false, W, true>(__VA_ARGS__) : FN<false, W, false>(__VA_ARGS__));
+#define TDPT_DISPATCH_BITS(FN, TR, PR, ...)              \
+    switch (p.wd) {                                      \
+    TDPT_BITS_CASE(FN, 1, TR, PR, __VA_ARGS__)           \
+    TDPT_BITS_CASE(FN, 2, TR, PR, __VA_ARGS__)           \
+    TDPT_BITS_CASE(FN, 3, TR, PR, __VA_ARGS__)           \
+    TDPT_BITS_CASE(FN, 4, TR, PR, __VA_ARGS__)           \
+    TDPT_BITS_CASE(FN, 5, TR, PR, __VA_ARGS__)           \
+    TDPT_BITS_CASE(FN, 6, TR, PR, __VA_ARGS__)           \
+    TDPT_BITS_CASE(FN, 7, TR, PR, __VA_ARGS__)           \
+    TDPT_BITS_CASE(FN, 8, TR, PR, __VA_ARGS__)           \
+    default: return hipErrorInvalidValue;                \
     }
 
 hipError_t launch_sweep_bits(const DevProblem &p, hipStream_t s)
 {
-    TDPT_DISPATCH_BITS(sweep_bits_t, track_updates(p.mcs), p, s)
+    TDPT_DISPATCH_BITS(sweep_bits_t, track_updates(p.mcs), p.pair16 != 0, p, s)
 }
 
 hipError_t launch_batch_sweep_bits(const DevProblem &p, const DevProblem *table, const int *first_block,
                                    int count, int blocks, int block, int max_words, int min_mcs, hipStream_t s)
 {
-    TDPT_DISPATCH_BITS(batch_sweep_bits_t, track_updates(min_mcs), p, table, first_block, count, blocks, block,
+    TDPT_DISPATCH_BITS(batch_sweep_bits_t, track_updates(min_mcs), p.pair16 != 0, p, table, first_block, count,
+                       blocks, block,
                        max_words, s)
 }
 

@@ -75,6 +75,7 @@ struct tdpt_instance {
     int32_t has_bias = 0;
     int64_t max_field = 0;   // max_i sum_j |J_ij| + |b_i|
     int64_t max_abs_J = 0;   // max |J_ij|
+    int64_t max_row_J = 0;   // max_i sum_j |J_ij|
     int64_t abs_f_bound = 0; // sum_{i<j} |J_ij| + sum_i |b_i|
     int32_t max_class_quads = 0;
     // The penalty field of spin i is 2 P c_i; c_i is the copy sum, or for
@@ -137,7 +138,7 @@ namespace {
 struct Layout {
     size_t hdr, states, f, g, slot_pos, pos_slot, p_att, p_acc, b_att, b_acc, best, trace_f,
         trace_g, hist, mut_end, mbox, slot_key, slot_best, hit_min, scratch_end;
-    size_t beta, p_q, nbi, nbj, chp, nb_idx, nb_J, ch_idx, bias, orig, nb_pos, ch_pos, h0, cn_idx, cn_w, kh,
+    size_t beta, p_q, nbi, nbj, chp, nb_idx, nb_J, ch_idx, bias, orig, nb_pos, ch_pos, h0, nb_J2, cn_idx, cn_w, kh,
         hist_rank, total;
     int32_t stride, wd;
 };
@@ -154,6 +155,16 @@ bool use_bits(const tdpt_instance *in)
         if (!strcmp(e, "bytes")) return false;
     }
     return align_up((size_t)in->n_pad + 1, 16) > kInt8StrideMax;
+}
+
+// The bit-packed layout's pair form sums 2 J_k b_k of two replicas in the
+// 16-bit halves of one word: every spin's sum of 2 |J| must stay below 2^15.
+bool use_pair16(const tdpt_instance *in)
+{
+    if (!use_bits(in)) return false;
+    if (const char *e = getenv("TDPT_PAIR16"))
+        if (!strcmp(e, "0")) return false;
+    return 2 * in->max_row_J < ((int64_t)1 << 15);
 }
 
 // The packed structure (16-bit indices and coupling pairs) and the 16/24-bit
@@ -236,6 +247,7 @@ Layout make_layout(const tdpt_instance *in, int32_t I, int32_t J, int64_t trace_
             L.nb_pos = take(ell);
             L.ch_pos = take((size_t)2 * in->n_pad * 4);
             L.h0 = take((size_t)in->n_pad * 4);
+            L.nb_J2 = take(ell);
         }
     }
     L.bias = take((size_t)in->n_pad * 4);
@@ -499,12 +511,13 @@ int lay_out(tdpt_instance *in, int32_t n, const int32_t *row_ptr, const int32_t 
     for (int32_t r = 0; r < n_pad; ++r) {
         const int32_t v = in->orig[r];
         if (v < 0) continue;
-        int64_t field = b_q ? std::llabs((long long)b_q[v]) : 0;
+        int64_t field = b_q ? std::llabs((long long)b_q[v]) : 0, row_J = 0;
         int k = 0;
         for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e, ++k) {
             in->nb_idx[(size_t)k * n_pad + r] = in->rank[col[e]];
             in->nb_J[(size_t)k * n_pad + r] = J_q[e];
             field += std::llabs((long long)J_q[e]);
+            row_J += std::llabs((long long)J_q[e]);
             in->max_abs_J = std::max(in->max_abs_J, (int64_t)std::llabs((long long)J_q[e]));
             if (J_q[e] < -32768 || J_q[e] > 32767) narrow = false;
             if (col[e] > v) absf += std::llabs((long long)J_q[e]);
@@ -515,6 +528,7 @@ int lay_out(tdpt_instance *in, int32_t n, const int32_t *row_ptr, const int32_t 
             if (b_q[v] != 0) in->has_bias = 1;
         }
         in->max_field = std::max(in->max_field, field);
+        in->max_row_J = std::max(in->max_row_J, row_J);
     }
     in->abs_f_bound = absf;
     in->narrow = narrow ? 1 : 0;
@@ -902,11 +916,13 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
         }
     }
     d.bits = bits ? 1 : 0;
+    d.pair16 = use_pair16(in) ? 1 : 0;
     d.n_words = n_words;
     for (int c = 0; c <= in->n_colors; ++c) d.bit_start[c] = bit_start[c];
     d.nb_pos = bits ? (const int32_t *)(ws + L.nb_pos) : nullptr;
     d.ch_pos = bits ? (const int32_t *)(ws + L.ch_pos) : nullptr;
     d.h0 = bits ? (const int32_t *)(ws + L.h0) : nullptr;
+    d.nb_J2 = bits ? (const uint32_t *)(ws + L.nb_J2) : nullptr;
     for (int c = 0; c <= in->n_colors; ++c) d.cls_start[c] = in->cls_start[c];
     for (int c = 0; c < in->n_colors; ++c) d.cls_live[c] = in->cls_live[c];
     d.nbi = narrow ? (const uint32_t *)(ws + L.nbi) : nullptr;
@@ -1026,11 +1042,14 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
             std::vector<int32_t> cls_of(n_pad, 0);
             for (int c = 0; c < in->n_colors; ++c)
                 for (int32_t r = in->cls_start[c]; r < in->cls_start[c + 1]; ++r) cls_of[r] = c;
-            // a bit position b is stored as 512 (b >> 5) + (b & 31): shifted
-            // right by 5 it is the LDS byte address of its word group
+            // a bit position b is stored as 512 (b >> 5) + (b & 31) (plain
+            // form) or 512 (b >> 5) + 256 ((b >> 4) & 1) + (b & 15) (pair
+            // form): shifted right by 5 it is the LDS byte address of the
+            // word group, or of the word pair, that holds the bit
+            const bool pair = d.pair16 != 0;
             auto bitpos = [&](int32_t r) {
                 const int32_t b = r - in->cls_start[cls_of[r]] + bit_start[cls_of[r]];
-                return ((b >> 5) << 9) | (b & 31);
+                return pair ? ((b >> 5) << 9) | (((b >> 4) & 1) << 8) | (b & 15) : ((b >> 5) << 9) | (b & 31);
             };
             std::vector<int32_t> pos(in->nb_idx.size()), chp(in->ch_idx.size()), h0(n_pad, 0);
             for (int k = 0; k < in->wd; ++k)
@@ -1050,9 +1069,13 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
                 const int32_t kc = (in->ch_idx[r] != n_pad) + (in->ch_idx[(size_t)n_pad + r] != n_pad);
                 chp[r] |= kc << 29;
             }
+            // pair form: 2 J as a 16-bit number in both halves
+            std::vector<uint32_t> j2(in->nb_J.size());
+            for (size_t i = 0; i < j2.size(); ++i) j2[i] = ((uint32_t)(2 * in->nb_J[i]) & 0xffffu) * 0x10001u;
             UP(ws + L.nb_pos, pos.data(), pos.size() * 4);
             UP(ws + L.ch_pos, chp.data(), chp.size() * 4);
             UP(ws + L.h0, h0.data(), h0.size() * 4);
+            UP(ws + L.nb_J2, j2.data(), j2.size() * 4);
         }
     }
     UP(ws + L.bias, in->bias.data(), in->bias.size() * 4);
@@ -1127,10 +1150,11 @@ int tdpt_problem_create(const tdpt_instance *in, const tdpt_run_cfg *cfg, void *
 // Structure layout of a problem, which selects its sweep kernel instance:
 // problems of one batch group share it.
 struct GroupKey {
-    int bits, narrow, packed_gen, wd;
+    int bits, narrow, packed_gen, wd, pair16;
     bool operator==(const GroupKey &o) const
     {
-        return bits == o.bits && narrow == o.narrow && packed_gen == o.packed_gen && wd == o.wd;
+        return bits == o.bits && narrow == o.narrow && packed_gen == o.packed_gen && wd == o.wd &&
+               pair16 == o.pair16;
     }
     // batch order: int8 before bit-packed, packed before wide, copy edges
     // before general constraints, narrower rows first
@@ -1139,14 +1163,15 @@ struct GroupKey {
         if (bits != o.bits) return bits < o.bits;
         if (narrow != o.narrow) return narrow > o.narrow;
         if (packed_gen != o.packed_gen) return packed_gen < o.packed_gen;
-        return wd < o.wd;
+        if (wd != o.wd) return wd < o.wd;
+        return pair16 > o.pair16;
     }
-    int32_t code() const { return bits | narrow << 1 | packed_gen << 2 | wd << 3; }
+    int32_t code() const { return bits | narrow << 1 | packed_gen << 2 | wd << 3 | pair16 << 12; }
 };
 
 static GroupKey group_key(const tdpt::DevProblem &d)
 {
-    return GroupKey{d.bits ? 1 : 0, d.narrow ? 1 : 0, (d.narrow && d.gen) ? 1 : 0, d.wd};
+    return GroupKey{d.bits ? 1 : 0, d.narrow ? 1 : 0, (d.narrow && d.gen) ? 1 : 0, d.wd, d.pair16 ? 1 : 0};
 }
 
 // Membership of problems in batches (defined with the batches below).
@@ -1376,6 +1401,8 @@ int tdpt_problem_query(tdpt_problem *p, tdpt_status *out)
     if (rc) return rc;
     if (h[tdpt::kHdrError] == 2)
         return fail(TDPT_E_DEVICE, "a sweep kernel found its LDS replica away from address 0 and did not run");
+    if (h[tdpt::kHdrError] == 3)
+        return fail(TDPT_E_DEVICE, "a bit-packed sweep kernel of the other form was launched and did not run");
     if (h[tdpt::kHdrError])
         return fail(TDPT_E_DEVICE, "a persistent launch gave up after 2 s waiting for a swap partner's "
                                    "mailbox (blocks not co-resident, or partners disagreeing on a swap)");
@@ -1553,7 +1580,8 @@ int tdpt_layout_get(const tdpt_instance *in, const tdpt_run_cfg *cfg, tdpt_layou
     out->narrow = narrow ? 1 : 0;
     out->general = in->gen ? 1 : 0;
     out->ell_width = L.wd;
-    out->group_key = GroupKey{out->bits, out->narrow, (narrow && in->gen) ? 1 : 0, L.wd}.code();
+    out->pair16 = use_pair16(in) ? 1 : 0;
+    out->group_key = GroupKey{out->bits, out->narrow, (narrow && in->gen) ? 1 : 0, L.wd, out->pair16}.code();
     // the per-round sweep's default shape, as tdpt_problem_create sets it
     // (without its environment overrides)
     int32_t rpb = 1, lshift = 0, srpb = 1, sls = 0;

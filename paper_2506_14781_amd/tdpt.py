@@ -69,7 +69,7 @@ class _Layout(ctypes.Structure):
     _fields_ = [("bits", ctypes.c_int32), ("narrow", ctypes.c_int32), ("general", ctypes.c_int32),
                 ("ell_width", ctypes.c_int32), ("group_key", ctypes.c_int32), ("slots", ctypes.c_int32),
                 ("lanes", ctypes.c_int32), ("held", ctypes.c_int32), ("per_round", ctypes.c_int32),
-                ("spin", ctypes.c_int32)]
+                ("spin", ctypes.c_int32), ("pair16", ctypes.c_int32)]
 
 
 class _TuneReport(ctypes.Structure):

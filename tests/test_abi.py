@@ -268,6 +268,11 @@ def test_layout_group_keys(monkeypatch):
     e = T.Instance.from_synth(w.instance).layout(cfg)
     assert (e["bits"], e["narrow"]) == (1, 0) and e["group_key"] & 1
     assert len({a["group_key"], c["group_key"], d["group_key"], e["group_key"]}) == 4
+    # its two forms run different kernels, so they group apart
+    assert e["pair16"] == 1 and e["group_key"] == 1 | e["ell_width"] << 3 | 1 << 12
+    monkeypatch.setenv("TDPT_PAIR16", "0")
+    f = T.Instance.from_synth(w.instance).layout(cfg)
+    assert f["pair16"] == 0 and f["group_key"] == e["group_key"] & ~(1 << 12)
 
 
 def test_layout_default_packing(monkeypatch):
@@ -315,3 +320,36 @@ def test_layout_default_packing(monkeypatch):
     monkeypatch.setenv("TDPT_LAYOUT", "bits")
     e = inst.layout(T.RunConfig(w.beta, w.p_q, mcs_per_swap=50, seed=0))
     assert e["bits"] == 1 and shape(e) == (0, 1, 0, 0, 0)
+
+
+def test_layout_pair_form(monkeypatch):
+    """The bit-packed layout's pair form (two replicas per word, coupling
+    sums in 16-bit halves) is chosen exactly when every spin's sum of 2 |J|
+    over its problem neighbours is below 2^15: the N=1000 workload (largest
+    row sum 1007) takes it, an instance whose row sum reaches 2^14 does not,
+    one just below does; TDPT_PAIR16=0 turns it off, and byte-layout
+    problems never report it."""
+    from synth.configs import wishart_n1000
+    w = wishart_n1000()
+    cfg = T.RunConfig(w.beta, w.p_q, mcs_per_swap=50, seed=0)
+    lay = T.Instance.from_synth(w.instance).layout(cfg)
+    assert lay["bits"] == 1 and lay["pair16"] == 1
+    small = wishart_small()
+    assert T.Instance.from_synth(small.instance).layout(
+        T.RunConfig(small.beta, small.p_q, mcs_per_swap=5, seed=0))["pair16"] == 0
+
+    def ring(j):
+        # 8 spins on a ring, each with two neighbours of coupling j (row sum 2 j)
+        n = 8
+        rows = [sorted(((i - 1) % n, (i + 1) % n)) for i in range(n)]
+        row_ptr = np.arange(0, 2 * n + 1, 2, dtype=np.int32)
+        col = np.array([c for r in rows for c in r], dtype=np.int32)
+        Jq = np.full(2 * n, j, dtype=np.int32)
+        return T.Instance(n, row_ptr, col, Jq, np.zeros(n, np.int32),
+                          np.zeros(0, np.int32), np.zeros(0, np.int32), (np.arange(n) % 2).astype(np.int32))
+    rc = T.RunConfig([1.0], [0], mcs_per_swap=5, seed=0)
+    monkeypatch.setenv("TDPT_LAYOUT", "bits")
+    assert ring(8191).layout(rc)["pair16"] == 1     # 2 * 16382 < 2^15
+    assert ring(8192).layout(rc)["pair16"] == 0     # 2 * 16384 = 2^15
+    monkeypatch.setenv("TDPT_PAIR16", "0")
+    assert ring(8191).layout(rc)["pair16"] == 0

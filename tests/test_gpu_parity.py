@@ -10,6 +10,7 @@ trajectories are identical.
 """
 from __future__ import annotations
 
+import dataclasses
 import os
 import sys
 
@@ -399,16 +400,46 @@ def test_n200_long_run_invariants(T):
 
 # ------------------------------------------------------ bit-packed layout
 
+def _bits_form(T, inst, cfg, form, fn):
+    """fn() with the bit-packed layout forced in the given form ("pair": two
+    replicas per word, 16-bit coupling sums; "plain": one replica per word),
+    after checking that the library reports that form for the problem."""
+    def go():
+        lay = T.Instance.from_synth(inst).layout(cfg)
+        assert lay["bits"] == 1 and lay["pair16"] == (1 if form == "pair" else 0)
+        return fn()
+    return _with_env("TDPT_LAYOUT", "bits",
+                     lambda: _with_env("TDPT_PAIR16", "1" if form == "pair" else "0", go))
+
+
+@pytest.mark.parametrize("form", ["pair", "plain"])
 @pytest.mark.parametrize("I,J,mcs", [(8, 4, 5), (3, 5, 2), (1, 1, 3)])
-def test_bit_packed_layout_small(T, I, J, mcs):
+def test_bit_packed_layout_small(T, I, J, mcs, form):
     """The bit-packed layout (4 replicas per workgroup as bits), forced on
-    small instances: grids whose replica count is not a multiple of 4, the
-    instance with fields, the N=12 workload."""
+    small instances in both its forms: grids whose replica count is not a
+    multiple of 4 (a pair word then holds one live replica), the instance
+    with fields, the N=12 workload; 2 sweeps per round follow f and g
+    update by update, 3 and 5 recompute them at the round's end."""
     for inst, name in [(tiny_instance(), "tiny+fields"), (wishart_small().instance, "wishart-N12")]:
         beta = np.geomspace(0.3, 3.0, I)
         p_q = q12(np.linspace(0.5, 3.0, J))
-        _with_env("TDPT_LAYOUT", "bits", lambda: both(
-            T, inst, beta, p_q, mcs=mcs, rounds=30, seed=13, label=f"bits {name} {I}x{J}"))
+        _bits_form(T, inst, T.RunConfig(beta, p_q, mcs_per_swap=mcs, seed=13), form, lambda: both(
+            T, inst, beta, p_q, mcs=mcs, rounds=30, seed=13, label=f"bits {form} {name} {I}x{J}"))
+
+
+def test_bit_packed_large_couplings_take_the_plain_form(T):
+    """Couplings whose row sums reach 2^14 cannot be summed in 16-bit halves:
+    the library keeps such bit-packed problems in the plain form by itself,
+    and the results equal the oracle's."""
+    base = tiny_instance()
+    inst = dataclasses.replace(base, J_q=np.asarray(base.J_q, dtype=np.int32) * 4)
+    beta, p_q = np.geomspace(0.02, 0.3, 3), q12(np.linspace(0.5, 3.0, 2))
+    cfg = T.RunConfig(beta, p_q, mcs_per_swap=5, seed=3)
+
+    def go():
+        assert T.Instance.from_synth(inst).layout(cfg)["pair16"] == 0
+        both(T, inst, beta, p_q, mcs=5, rounds=20, seed=3, label="bits large couplings")
+    _with_env("TDPT_LAYOUT", "bits", go)
 
 
 def test_bit_packed_ragged_and_batched(T):
@@ -425,6 +456,20 @@ def test_bit_packed_ragged_and_batched(T):
     B.run(12)
     st = P.states()
     assert np.array_equal(st, o["states"])
+    # one member in each form (a group, and a kernel, of its own each)
+    o2 = O.run(w.instance, w.beta, w.p_q, mcs_per_swap=5, n_rounds=12, seed=9, trace=True)
+    Pa = _with_env("TDPT_LAYOUT", "bits", lambda: _with_env("TDPT_PAIR16", "0", lambda: run_gpu(
+        T, w.instance, w.beta, w.p_q, mcs=5, rounds=0, seed=2, trace=False)))
+    Pb = _with_env("TDPT_LAYOUT", "bits", lambda: run_gpu(
+        T, w.instance, w.beta, w.p_q, mcs=5, rounds=0, seed=9, trace=False))
+    B2 = T.Batch(2)
+    B2.set_members([Pa, Pb])
+    B2.run(12)
+    assert np.array_equal(Pa.states(), o["states"])
+    assert np.array_equal(Pb.states(), o2["states"])
+    for oo, PP in ((o, Pa), (o2, Pb)):
+        f, g = PP.energies()
+        assert np.array_equal(f, oo["f"]) and np.array_equal(g, oo["g"])
 
 
 def test_n1000_instance_bit_exact_on_a_sub_grid(T):
@@ -536,19 +581,20 @@ def test_autotune_n200_and_bits(T):
     assert_same(o, Q, "tuned bits")
 
 
+@pytest.mark.parametrize("form", ["pair", "plain"])
 @pytest.mark.parametrize("mcs,block", [(5, "1024"), (5, "256"), (2, "1024")])
-def test_bit_packed_block_sizes(T, mcs, block):
+def test_bit_packed_block_sizes(T, mcs, block, form):
     """Bit-packed replicas at 1024 threads (allowed when f and g are
     recomputed at the round's end, from 4 sweeps per round), at 256, and
-    capped at 768 when they follow every update (2 sweeps per round): the
-    same results as the oracle."""
+    capped at 768 when they follow every update (2 sweeps per round), in
+    both forms: the same results as the oracle."""
     w = batched_member(100, 0.8, 5)
 
     def go():
         return _with_env("TDPT_BLOCK", block, lambda: both(
             T, w.instance, w.beta[:4], w.p_q[:4], mcs=mcs, rounds=5, seed=7,
-            label=f"bits mcs {mcs} block {block}"))
-    _with_env("TDPT_LAYOUT", "bits", go)
+            label=f"bits {form} mcs {mcs} block {block}"))
+    _bits_form(T, w.instance, T.RunConfig(w.beta[:4], w.p_q[:4], mcs_per_swap=mcs, seed=7), form, go)
 
 
 @pytest.mark.parametrize("order", ["7,3", "31,5", "1,17"])
