@@ -1736,6 +1736,50 @@ __device__ __forceinline__ void pair_energy_quad(const DevProblem &P, const Rsrc
     }
 }
 
+// The int8 copy of slot's replica from the first spin of class c on (4-byte
+// aligned: rows are 16-byte multiples, classes start on quads).
+__device__ __forceinline__ int8_t *slot_row(const DevProblem &P, int slot, int c)
+{
+    return P.states + (size_t)slot * P.stride + P.cls_start[c];
+}
+
+// Bits (1 = spin +1) of the class-local spins k0 .. k0 + N - 1 (k0 and N
+// multiples of 4) of a class's int8 row st, 4 spins per load; a load starts
+// only below live, so it stays within the class's quads, and spins from live
+// on (class padding, 0 in the int8 copy) read as 0.
+template <int N>
+__device__ __forceinline__ uint32_t run_bits(const int8_t *st, int k0, int live)
+{
+    uint32_t d[N / 4];
+#pragma unroll
+    for (int m = 0; m < N / 4; ++m) d[m] = k0 + 4 * m < live ? *(const uint32_t *)(st + k0 + 4 * m) : 0u;
+    uint32_t bits = 0;
+#pragma unroll
+    for (int m = 0; m < N / 4; ++m) {
+        // bit 8 j set where byte j is +1 (0x01; -1 is 0xff, padding 0)
+        const uint32_t one = d[m] & ~(d[m] >> 7) & 0x01010101u;
+        bits |= ((one | one >> 7 | one >> 14 | one >> 21) & 15u) << (4 * m);
+    }
+    return bits;
+}
+
+// The inverse of run_bits: spins below live get +1 (bit set) or -1, the
+// bytes of class padding in the last 4-byte store stay 0.
+template <int N>
+__device__ __forceinline__ void run_store(int8_t *st, int k0, int live, uint32_t bits)
+{
+#pragma unroll
+    for (int m = 0; m < N / 4; ++m) {
+        const int rem = live - (k0 + 4 * m);
+        if (rem <= 0) continue;
+        const uint32_t nib = (bits >> (4 * m)) & 15u;
+        const uint32_t set = (nib & 1u) | (nib & 2u) << 7 | (nib & 4u) << 14 | (nib & 8u) << 21;
+        uint32_t word = 0xffffffffu ^ (set * 0xfeu);  // 0x01 where set, 0xff elsewhere
+        if (rem < 4) word &= (1u << (8 * rem)) - 1u;
+        *(uint32_t *)(st + k0 + 4 * m) = word;
+    }
+}
+
 // One round of up to kBitSlots slots (slot0 ..): unpack the int8 states into
 // LDS bits, mcs sweeps, pack them back.  TRACK: f and g follow every update
 // exactly (cheap for few sweeps per round); otherwise they are recomputed
@@ -1767,19 +1811,22 @@ __device__ __forceinline__ void round_sweep_bits_body(const DevProblem &P, int s
     // is spin bit 32 w + x of replica i & 3 (plain form) or spin bit
     // 32 w + 16 ((i >> 1) & 1) + (x & 15) of replica 2 (i & 1) + (x >> 4)
     // (pair form)
-    constexpr int pair = PAIR ? 1 : 0;
     for (int i = tid; i < (P.n_words + 1) * kBitSlots; i += nthr) {
         const int w = i >> 2;
         uint32_t bits = 0;
-        int c = 0;
-        while (c + 1 < P.n_colors && P.bit_start[c + 1] <= 32 * w) ++c;
-        const int live = P.cls_live[c] - P.cls_start[c];
-        for (int x = 0; x < 32; ++x) {
-            const int r = pair ? 2 * (i & 1) + (x >> 4) : (i & 3);
-            const int k = (pair ? 32 * w + 16 * ((i >> 1) & 1) + (x & 15) : 32 * w + x) - P.bit_start[c];
-            if (r < ns && k >= 0 && k < live &&
-                P.states[(size_t)(slot0 + r) * P.stride + P.cls_start[c] + k] > 0)
-                bits |= 1u << x;
+        if (w < P.n_words) {
+            int c = 0;
+            while (c + 1 < P.n_colors && P.bit_start[c + 1] <= 32 * w) ++c;
+            const int live = P.cls_live[c] - P.cls_start[c];
+            const int k0 = 32 * w - P.bit_start[c];  // class-local spin of bit 0 of the group
+            if constexpr (PAIR) {
+                const int r = 2 * (i & 1), kh = k0 + 16 * ((i >> 1) & 1);
+                if (r < ns) bits = run_bits<16>(slot_row(P, slot0 + r, c), kh, live);
+                if (r + 1 < ns) bits |= run_bits<16>(slot_row(P, slot0 + r + 1, c), kh, live) << 16;
+            } else {
+                const int r = i & 3;
+                if (r < ns) bits = run_bits<32>(slot_row(P, slot0 + r, c), k0, live);
+            }
         }
         W[i] = bits;
     }
@@ -1858,12 +1905,15 @@ __device__ __forceinline__ void round_sweep_bits_body(const DevProblem &P, int s
         int c = 0;
         while (c + 1 < P.n_colors && P.bit_start[c + 1] <= 32 * w) ++c;
         const int live = P.cls_live[c] - P.cls_start[c];
+        const int k0 = 32 * w - P.bit_start[c];
         const uint32_t bits = W[i];
-        for (int x = 0; x < 32; ++x) {
-            const int r = pair ? 2 * (i & 1) + (x >> 4) : (i & 3);
-            const int k = (pair ? 32 * w + 16 * ((i >> 1) & 1) + (x & 15) : 32 * w + x) - P.bit_start[c];
-            if (r < ns && k >= 0 && k < live)
-                P.states[(size_t)(slot0 + r) * P.stride + P.cls_start[c] + k] = ((bits >> x) & 1u) ? 1 : -1;
+        if constexpr (PAIR) {
+            const int r = 2 * (i & 1), kh = k0 + 16 * ((i >> 1) & 1);
+            if (r < ns) run_store<16>(slot_row(P, slot0 + r, c), kh, live, bits & 0xffffu);
+            if (r + 1 < ns) run_store<16>(slot_row(P, slot0 + r + 1, c), kh, live, bits >> 16);
+        } else {
+            const int r = i & 3;
+            if (r < ns) run_store<32>(slot_row(P, slot0 + r, c), k0, live, bits);
         }
     }
 }
