@@ -57,8 +57,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X: 256 compute units x 4 SIMD x 16 lanes x 2.4 GHz of 32-bit VALU lanes
-PEAK_LANE_OPS = 256 * 64 * 2.4e9
+# MI355X 32-bit VALU lane operations per second: the published fp32 vector
+# rate, 157.3 TFLOP/s, counts a fused multiply-add as 2 operations, i.e.
+# 256 compute units x 128 lanes x 2.4 GHz.  Measured on gfx950 (8 independent
+# chains per lane, 32 waves per CU): 32-bit add, logic, shift, bitop3 and fp32
+# add / multiply / fma issue in 2.2-2.6 cycles per 64-lane wave instruction
+# per SIMD (78-91 % of this rate); 24- and 32-bit integer multiplies, bit-field
+# extracts, conversions, compares, dot2 and packed 16-bit multiply-adds in
+# 4.1-4.4 cycles; exp2 in 8.1.
+PEAK_LANE_OPS = 256 * 128 * 2.4e9
 
 # HBM bytes per swap round of each workload's dominant kernel, from rocprofv3
 # FETCH_SIZE (x2.00) and WRITE_SIZE (x1.00) counters scaled against a plain
