@@ -333,12 +333,12 @@ def _with_env(key, value, fn):
 
 
 def test_mixed_layout_batch_equals_oracle(T):
-    """One batch holding bit-packed members (one forced, one large enough to
-    need it), packed byte-layout members, a 32-bit-row member and a
-    general-constraint member: run directly, replayed from a HIP graph and
-    across a membership change, every member equals the oracle on states,
-    f, g, swap counters, trace, best state, best f and sweep, and first
-    hit."""
+    """One batch holding bit-packed members (one forced in each form of the
+    layout, one large enough to need it), packed byte-layout members, a
+    32-bit-row member and a general-constraint member: run directly,
+    replayed from a HIP graph and across a membership change, every member
+    equals the oracle on states, f, g, swap counters, trace, best state, best
+    f and sweep, and first hit."""
     from synth.constrained import planted_coloring
     from tests.test_gpu_parity import assert_same
     w = wishart_small()
@@ -350,6 +350,7 @@ def test_mixed_layout_batch_equals_oracle(T):
     specs = [  # name, instance, beta, p_q, mcs, seed, f_target, layout env
         ("N12 bits", w.instance, w.beta, w.p_q, 5, 11, f_gs, "bits"),
         ("N12 bytes", w.instance, w.beta, w.p_q, 5, 12, f_gs, None),
+        ("N12 bits plain form", w.instance, w.beta, w.p_q, 5, 13, f_gs, "bits-plain"),
         ("N64", m64.instance, m64.beta[:8], m64.p_q[:4], 3, 3, None, None),
         ("wide", wide[1], wide[2], wide[3], 2, 1, None, None),
         ("coloring", col.instance, np.geomspace(0.3, 3, 4), np.array([0, 4096], np.int32), 3, 8,
@@ -360,7 +361,10 @@ def test_mixed_layout_batch_equals_oracle(T):
     for name, inst, beta, p_q, mcs, seed, tgt, lay in specs:
         cfg = T.RunConfig(beta, p_q, mcs_per_swap=mcs, seed=seed, f_target=tgt, trace_cap=64)
         mk = lambda: T.Problem(T.Instance.from_synth(inst), cfg)  # noqa: E731
-        probs.append(_with_env("TDPT_LAYOUT", lay, mk) if lay else mk())
+        if lay == "bits-plain":
+            probs.append(_with_env("TDPT_LAYOUT", "bits", lambda: _with_env("TDPT_PAIR16", "0", mk)))
+        else:
+            probs.append(_with_env("TDPT_LAYOUT", lay, mk) if lay else mk())
     bits = [T.Instance.from_synth(s[1]).layout(T.RunConfig(s[2], s[3], mcs_per_swap=1, seed=0))["bits"]
             for s in specs]
     assert bits[-1] == 1 and bits[1] == 0
