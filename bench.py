@@ -76,6 +76,10 @@ MEASURED_TRAFFIC = {
     # FETCH 5,444,408 KiB (x2.00), WRITE 507,834 KiB (x1.00), mean of 4 dispatches
     "wishart-N1000-D6-64x32": {"kernel": "k_round_sweep_bits", "kernel_sha256": "5eeda99f85758a56",
                                "bytes_per_round": 11670168320},
+    # one 200-round persistent launch on the N=200 workload, 384-thread workgroups:
+    # FETCH 16,927 KiB (x2.00), WRITE 11,957 KiB (x1.00)
+    "wishart-N200-D8-32x16": {"kernel": "k_persistent", "kernel_sha256": "5eeda99f85758a56",
+                              "bytes_per_round": 234553},
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_2506_14781_amd", "csrc", "tdpt_kernels.hip")
 
