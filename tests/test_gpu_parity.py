@@ -472,17 +472,23 @@ def test_bit_packed_ragged_and_batched(T):
         assert np.array_equal(f, oo["f"]) and np.array_equal(g, oo["g"])
 
 
-def test_n1000_instance_bit_exact_on_a_sub_grid(T):
+@pytest.mark.parametrize("form", ["pair", "plain"])
+def test_n1000_instance_bit_exact_on_a_sub_grid(T, form):
     """The N=1000 planted-Wishart instance (250,000 spins per replica, bit-packed
-    layout chosen automatically) on a 2x2 sub-grid: one round of 50 sweeps is
-    bit-exact against the oracle."""
+    layout chosen automatically, in its pair form unless TDPT_PAIR16=0) on a
+    2x2 sub-grid: one round of 50 sweeps is bit-exact against the oracle."""
     from synth.configs import wishart_n1000
     w = wishart_n1000()
     P0 = T.Instance.from_synth(w.instance)
     assert P0.info()["n"] == 250000
     beta = w.beta[[0, -1]]
     p_q = w.p_q[[0, -1]]
-    both(T, w.instance, beta, p_q, mcs=50, rounds=1, seed=4, label="wishart-N1000 2x2")
+
+    def go():
+        lay = P0.layout(T.RunConfig(beta, p_q, mcs_per_swap=50, seed=4))
+        assert lay["bits"] == 1 and lay["pair16"] == (1 if form == "pair" else 0)
+        both(T, w.instance, beta, p_q, mcs=50, rounds=1, seed=4, label=f"wishart-N1000 2x2 {form}")
+    _with_env("TDPT_PAIR16", "1" if form == "pair" else "0", go)
 
 
 def test_caller_initial_state_in_several_uploads(T):
